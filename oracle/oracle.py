@@ -1,0 +1,329 @@
+"""ctypes wrapper over the FP64 oracle library (test infrastructure only).
+
+The oracle follows the paper's model definitions (App. A.1, App. B) and the
+discrete adjoint of semi-implicit Euler (App. A, App. A.2).  Arrays are numpy
+float64, AoS ``[n, 3]``.  Nothing under ``paper_2104_02646_amd`` is imported
+here and this module is never imported by the product path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gsim_oracle.cpp")
+_LIB = os.path.join(_HERE, "libgsim_oracle.so")
+
+# FMA contraction off and no fast-math: every product and sum rounds once.
+CXXFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC"]
+
+
+def library_path() -> str:
+    return _LIB
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (FP64, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["g++", *CXXFLAGS, _SRC, "-o", tmp])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+_up = C.POINTER(C.c_ubyte)
+
+
+class _Params(C.Structure):
+    _fields_ = [("mu", _dp), ("lam", _dp), ("act", _dp), ("ktri", _dp), ("hact", _dp), ("mass", _dp),
+                ("kb", C.c_double), ("ke", C.c_double), ("kd", C.c_double), ("kf", C.c_double),
+                ("muf", C.c_double)]
+
+
+class _Grads(C.Structure):
+    _fields_ = [("mu", _dp), ("lam", _dp), ("act", _dp), ("ktri", _dp), ("hact", _dp), ("mass", _dp),
+                ("kb", C.c_double), ("contact", C.c_double * 4)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = C.CDLL(_LIB)
+        lib.oc_create.restype = C.c_void_p
+        lib.oc_create.argtypes = [C.c_int] * 4 + [_dp, _ip, _ip, _ip, _up, _dp, C.c_int, _dp, C.c_double]
+        lib.oc_status.argtypes = [C.c_void_p]
+        lib.oc_free.argtypes = [C.c_void_p]
+        lib.oc_rest_data.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        P = C.POINTER(_Params)
+        G = C.POINTER(_Grads)
+        lib.oc_forces.argtypes = [C.c_void_p, P, _dp, _dp, _dp]
+        lib.oc_energy.restype = C.c_double
+        lib.oc_energy.argtypes = [C.c_void_p, P, _dp]
+        lib.oc_step.argtypes = [C.c_void_p, P, _dp, _dp, _dp, _dp]
+        lib.oc_rollout.argtypes = [C.c_void_p, P, _dp, _dp, C.c_int, _dp, _dp]
+        lib.oc_rollout_final.argtypes = [C.c_void_p, P, _dp, _dp, C.c_int, _dp, _dp]
+        lib.oc_loss.restype = C.c_double
+        lib.oc_loss.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        lib.oc_force_vjp.argtypes = [C.c_void_p, P, _dp, _dp, _dp, _dp, _dp, G]
+        lib.oc_force_jvp.argtypes = [C.c_void_p, P, P, _dp, _dp, _dp, _dp, _dp]
+        lib.oc_step_vjp.argtypes = [C.c_void_p, P, _dp, _dp, _dp, _dp, _dp, _dp, G]
+        lib.oc_backward.argtypes = [C.c_void_p, P, _dp, _dp, C.c_int, _dp, _dp, _dp, _dp, G]
+        for name in ("oc_tet_force1", "oc_tri_force1"):
+            getattr(lib, name).restype = C.c_double
+        lib.oc_tet_force1.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, _dp]
+        lib.oc_tet_energy1.restype = C.c_double
+        lib.oc_tet_energy1.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double]
+        lib.oc_tri_force1.argtypes = [_dp, _dp, C.c_double, _dp]
+        lib.oc_tri_energy1.restype = C.c_double
+        lib.oc_tri_energy1.argtypes = [_dp, _dp, C.c_double]
+        lib.oc_hinge_angle1.restype = C.c_double
+        lib.oc_hinge_angle1.argtypes = [_dp]
+        lib.oc_hinge_force1.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp]
+        lib.oc_contact_force1.argtypes = [_dp, _dp, _dp] + [C.c_double] * 4 + [_dp]
+        _lib = lib
+    return _lib
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+# ----------------------------------------------------------------------------------
+# single-element entry points
+# ----------------------------------------------------------------------------------
+
+def tet_force(x, X, mu, lam, act=0.0):
+    """Corner forces [4,3] of one stable Neo-Hookean tet; also returns V."""
+    lib = _load()
+    x = _f64(x, (4, 3)); X = _f64(X, (4, 3)); f = np.zeros((4, 3))
+    V = lib.oc_tet_force1(_ptr(x), _ptr(X), mu, lam, act, _ptr(f))
+    return f, V
+
+
+def tet_energy(x, X, mu, lam, act=0.0):
+    lib = _load()
+    x = _f64(x, (4, 3)); X = _f64(X, (4, 3))
+    return lib.oc_tet_energy1(_ptr(x), _ptr(X), mu, lam, act)
+
+
+def tri_force(x, X, k):
+    lib = _load()
+    x = _f64(x, (3, 3)); X = _f64(X, (3, 3)); f = np.zeros((3, 3))
+    A = lib.oc_tri_force1(_ptr(x), _ptr(X), k, _ptr(f))
+    return f, A
+
+
+def tri_energy(x, X, k):
+    lib = _load()
+    x = _f64(x, (3, 3)); X = _f64(X, (3, 3))
+    return lib.oc_tri_energy1(_ptr(x), _ptr(X), k)
+
+
+def hinge_angle(x):
+    lib = _load()
+    x = _f64(x, (4, 3))
+    return lib.oc_hinge_angle1(_ptr(x))
+
+
+def hinge_force(x, phi0, kb, act=0.0):
+    lib = _load()
+    x = _f64(x, (4, 3)); f = np.zeros((4, 3))
+    lib.oc_hinge_force1(_ptr(x), phi0, kb, act, _ptr(f))
+    return f
+
+
+def contact_force(x, v, plane, ke, kd, kf, muf):
+    lib = _load()
+    x = _f64(x, (3,)); v = _f64(v, (3,)); pl = _f64(plane, (4,)); f = np.zeros(3)
+    lib.oc_contact_force1(_ptr(x), _ptr(v), _ptr(pl), ke, kd, kf, muf, _ptr(f))
+    return f
+
+
+# ----------------------------------------------------------------------------------
+# whole-body model
+# ----------------------------------------------------------------------------------
+
+class Oracle:
+    """One body: topology, rest shape, environment.  Parameters are passed per call
+    as a dict with keys mu, lam, act, ktri, hact, mass (arrays) and kb, ke, kd, kf,
+    muf (scalars); missing arrays mean zero actuation / no such elements."""
+
+    def __init__(self, X, tets=None, tris=None, hinges=None, pinned=None, gravity=(0.0, -9.81, 0.0),
+                 ground=False, plane=(0.0, 1.0, 0.0, 0.0), dt=1.0 / 600.0):
+        lib = _load()
+        self.X = _f64(X).reshape(-1, 3)
+        self.np = self.X.shape[0]
+        self.tets = np.ascontiguousarray(np.asarray(tets if tets is not None else np.zeros((0, 4)), np.int32).reshape(-1, 4))
+        self.tris = np.ascontiguousarray(np.asarray(tris if tris is not None else np.zeros((0, 3)), np.int32).reshape(-1, 3))
+        self.hinges = np.ascontiguousarray(np.asarray(hinges if hinges is not None else np.zeros((0, 4)), np.int32).reshape(-1, 4))
+        self.ne, self.nt, self.nh = len(self.tets), len(self.tris), len(self.hinges)
+        self.pinned = np.ascontiguousarray(np.zeros(self.np, np.uint8) if pinned is None else np.asarray(pinned, np.uint8))
+        self.gravity = _f64(gravity, (3,))
+        self.plane = _f64(plane, (4,))
+        self.ground = bool(ground)
+        self.dt = float(dt)
+        self._h = lib.oc_create(self.np, self.ne, self.nt, self.nh, _ptr(self.X),
+                                self.tets.ctypes.data_as(_ip), self.tris.ctypes.data_as(_ip),
+                                self.hinges.ctypes.data_as(_ip), self.pinned.ctypes.data_as(_up),
+                                _ptr(self.gravity), int(self.ground), _ptr(self.plane), self.dt)
+        self.status = lib.oc_status(self._h)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.oc_free(h)
+            self._h = None
+
+    # -- marshalling -------------------------------------------------------------
+    def _params(self, p):
+        keep = []
+
+        def arr(name, n):
+            a = p.get(name)
+            if a is None:
+                return None
+            a = _f64(a, (n,))
+            keep.append(a)
+            return _ptr(a)
+        s = _Params()
+        s.mu = arr("mu", self.ne); s.lam = arr("lam", self.ne); s.act = arr("act", self.ne)
+        s.ktri = arr("ktri", self.nt); s.hact = arr("hact", self.nh); s.mass = arr("mass", self.np)
+        s.kb = float(p.get("kb", 0.0)); s.ke = float(p.get("ke", 0.0)); s.kd = float(p.get("kd", 0.0))
+        s.kf = float(p.get("kf", 0.0)); s.muf = float(p.get("muf", 0.0))
+        return s, keep
+
+    def _grads(self, want):
+        out = {}
+        g = _Grads()
+        sizes = {"mu": self.ne, "lam": self.ne, "act": self.ne, "ktri": self.nt, "hact": self.nh, "mass": self.np}
+        for k, n in sizes.items():
+            if k in want:
+                out[k] = np.zeros(n)
+                setattr(g, k, _ptr(out[k]))
+            else:
+                setattr(g, k, None)
+        return g, out
+
+    @staticmethod
+    def _collect(g, out):
+        out["kb"] = g.kb
+        out["contact"] = np.array(list(g.contact))  # ke, kd, kf, muf
+        return out
+
+    # -- API -------------------------------------------------------------------
+    def rest_data(self):
+        tv, ta, ph = np.zeros(self.ne), np.zeros(self.nt), np.zeros(self.nh)
+        _load().oc_rest_data(self._h, _ptr(tv), _ptr(ta), _ptr(ph))
+        return tv, ta, ph
+
+    def forces(self, p, x, v):
+        s, keep = self._params(p)
+        x = _f64(x, (self.np, 3)); v = _f64(v, (self.np, 3)); f = np.zeros((self.np, 3))
+        rc = _load().oc_forces(self._h, C.byref(s), _ptr(x), _ptr(v), _ptr(f))
+        assert rc == 0, rc
+        return f
+
+    def energy(self, p, x):
+        s, keep = self._params(p)
+        x = _f64(x, (self.np, 3))
+        return _load().oc_energy(self._h, C.byref(s), _ptr(x))
+
+    def step(self, p, x, v):
+        s, keep = self._params(p)
+        x = _f64(x, (self.np, 3)); v = _f64(v, (self.np, 3))
+        xo, vo = np.zeros_like(x), np.zeros_like(v)
+        rc = _load().oc_step(self._h, C.byref(s), _ptr(x), _ptr(v), _ptr(xo), _ptr(vo))
+        assert rc == 0, rc
+        return xo, vo
+
+    def rollout(self, p, x0, v0, T):
+        """All T+1 states: xs, vs of shape [T+1, np, 3]."""
+        s, keep = self._params(p)
+        x0 = _f64(x0, (self.np, 3)); v0 = _f64(v0, (self.np, 3))
+        xs = np.zeros((T + 1, self.np, 3)); vs = np.zeros((T + 1, self.np, 3))
+        rc = _load().oc_rollout(self._h, C.byref(s), _ptr(x0), _ptr(v0), int(T), _ptr(xs), _ptr(vs))
+        assert rc == 0, rc
+        return xs, vs
+
+    def rollout_final(self, p, x0, v0, T):
+        s, keep = self._params(p)
+        x0 = _f64(x0, (self.np, 3)); v0 = _f64(v0, (self.np, 3))
+        xT, vT = np.zeros_like(x0), np.zeros_like(v0)
+        rc = _load().oc_rollout_final(self._h, C.byref(s), _ptr(x0), _ptr(v0), int(T), _ptr(xT), _ptr(vT))
+        assert rc == 0, rc
+        return xT, vT
+
+    def loss(self, x, target, with_grad=False):
+        x = _f64(x, (self.np, 3)); t = _f64(target, (self.np, 3))
+        xb = np.zeros_like(x) if with_grad else None
+        L = _load().oc_loss(self._h, _ptr(x), _ptr(t), _ptr(xb))
+        return (L, xb) if with_grad else L
+
+    def force_vjp(self, p, x, v, fbar, want=("mu", "lam", "act", "ktri", "hact", "mass")):
+        s, keep = self._params(p)
+        g, out = self._grads(want)
+        x = _f64(x, (self.np, 3)); v = _f64(v, (self.np, 3)); fb = _f64(fbar, (self.np, 3))
+        xb, vb = np.zeros_like(x), np.zeros_like(v)
+        rc = _load().oc_force_vjp(self._h, C.byref(s), _ptr(x), _ptr(v), _ptr(fb), _ptr(xb), _ptr(vb), C.byref(g))
+        assert rc == 0, rc
+        return xb, vb, self._collect(g, out)
+
+    def force_jvp(self, p, dp, x, v, dx, dv):
+        s, keep = self._params(p)
+        d, keep2 = self._params(dp)
+        x = _f64(x, (self.np, 3)); v = _f64(v, (self.np, 3))
+        dx = _f64(dx, (self.np, 3)); dv = _f64(dv, (self.np, 3)); df = np.zeros_like(x)
+        rc = _load().oc_force_jvp(self._h, C.byref(s), C.byref(d), _ptr(x), _ptr(v), _ptr(dx), _ptr(dv), _ptr(df))
+        assert rc == 0, rc
+        return df
+
+    def step_vjp(self, p, x, v, xbar_plus, vbar_plus, want=("mu", "lam", "act", "ktri", "hact", "mass")):
+        s, keep = self._params(p)
+        g, out = self._grads(want)
+        x = _f64(x, (self.np, 3)); v = _f64(v, (self.np, 3))
+        xbp = _f64(xbar_plus, (self.np, 3)); vbp = _f64(vbar_plus, (self.np, 3))
+        xbm, vbm = np.zeros_like(x), np.zeros_like(v)
+        rc = _load().oc_step_vjp(self._h, C.byref(s), _ptr(x), _ptr(v), _ptr(xbp), _ptr(vbp), _ptr(xbm), _ptr(vbm),
+                                 C.byref(g))
+        assert rc == 0, rc
+        return xbm, vbm, self._collect(g, out)
+
+    def backward(self, p, xs, vs, xbar_T, vbar_T=None, want=("mu", "lam", "act", "ktri", "hact", "mass")):
+        """Reverse pass over a stored trajectory; returns (xbar0, vbar0, grads)."""
+        s, keep = self._params(p)
+        g, out = self._grads(want)
+        T = xs.shape[0] - 1
+        xs = _f64(xs); vs = _f64(vs)
+        xbT = _f64(xbar_T, (self.np, 3))
+        vbT = np.zeros_like(xbT) if vbar_T is None else _f64(vbar_T, (self.np, 3))
+        xb0, vb0 = np.zeros_like(xbT), np.zeros_like(vbT)
+        rc = _load().oc_backward(self._h, C.byref(s), _ptr(xs), _ptr(vs), int(T), _ptr(xbT), _ptr(vbT), _ptr(xb0),
+                                 _ptr(vb0), C.byref(g))
+        assert rc == 0, rc
+        return xb0, vb0, self._collect(g, out)
+
+    def loss_and_grad(self, p, x0, v0, T, target, want=("mu", "lam", "mass")):
+        """Rollout, loss, and the discrete-adjoint gradient of the loss."""
+        xs, vs = self.rollout(p, x0, v0, T)
+        L, xb = self.loss(xs[-1], target, with_grad=True)
+        xb0, vb0, g = self.backward(p, xs, vs, xb, None, want)
+        g["x0"] = xb0
+        g["v0"] = vb0
+        return L, g, xs, vs

@@ -1,0 +1,256 @@
+"""Pins of the oracle's integrator, rollout and discrete adjoint.
+
+Closed forms of semi-implicit Euler (App. A.2, App. C integration kernel), exact
+conservation laws of that integrator, the contact model's fixed points, an
+adjoint dot test against an independent forward-mode directional derivative, and
+central finite differences of the whole rollout loss per parameter group.
+"""
+import numpy as np
+import pytest
+
+from paper_2104_02646_amd import workloads as W
+
+
+def particles(n, rng, y=1.0):
+    X = rng.uniform(-1, 1, (n, 3))
+    X[:, 1] += y
+    return X
+
+
+def make(o, body, **kw):
+    return o.Oracle(body.X, tets=body.tets, tris=body.tris, hinges=body.hinges, pinned=body.pinned,
+                    gravity=kw.get("gravity", body.gravity), ground=kw.get("ground", body.ground),
+                    plane=body.plane, dt=kw.get("dt", body.dt))
+
+
+# ---------------------------------------------------------------- integrator
+
+def test_free_fall_closed_form(oracle_lib):
+    """No elements, no ground: x_n = x0 + n dt v0 + g dt^2 n(n+1)/2 exactly
+    (velocity is updated first, then position), pinned particles stay put."""
+    o = oracle_lib
+    rng = np.random.default_rng(0)
+    X = particles(5, rng)
+    pinned = np.array([0, 0, 1, 0, 0], np.uint8)
+    dt, T = 1.0 / 600, 50
+    g = np.array([0.0, -9.81, 0.0])
+    orc = o.Oracle(X, pinned=pinned, dt=dt)
+    v0 = rng.normal(size=(5, 3))
+    v0[2] = 0.0
+    xs, vs = orc.rollout({"mass": rng.uniform(0.5, 1.5, 5)}, X, v0, T)
+    n = np.arange(T + 1)[:, None, None]
+    expect = X[None] + n * dt * v0[None] + g * dt * dt * n * (n + 1) / 2
+    expect[:, 2] = X[2]
+    assert np.abs(xs - expect).max() < 1e-12
+    assert np.abs(vs[-1] - (v0 + T * dt * g * (1 - pinned[:, None]))).max() < 1e-12
+
+
+def test_contact_static_fixed_point(oracle_lib):
+    """A particle resting at depth y = -m g / k_e is a fixed point of the step
+    (normal force balances gravity; no sliding velocity, no friction)."""
+    o = oracle_lib
+    m, ke = 0.8, 1e4
+    y = -m * 9.81 / ke
+    orc = o.Oracle(np.array([[0.2, y, -0.3]]), ground=True, dt=1.0 / 600)
+    p = {"mass": [m], "ke": ke, "kd": 0.0, "kf": 100.0, "muf": 0.5}
+    xs, vs = orc.rollout(p, [[0.2, y, -0.3]], [[0, 0, 0]], 20)
+    assert np.abs(xs[-1] - [[0.2, y, -0.3]]).max() < 1e-15
+    assert np.abs(vs).max() < 1e-13
+
+
+def test_contact_slip_deceleration(oracle_lib):
+    """Sliding at the static depth: each step the tangential speed drops by exactly
+    dt mu_f lambda_n / m (slip branch), the normal state is unchanged."""
+    o = oracle_lib
+    m, ke, muf, kf, dt = 1.0, 1e4, 0.5, 100.0, 1.0 / 600
+    y = -m * 9.81 / ke
+    orc = o.Oracle(np.array([[0.0, y, 0.0]]), ground=True, dt=dt)
+    p = {"mass": [m], "ke": ke, "kd": 0.0, "kf": kf, "muf": muf}
+    v0 = 2.0
+    xs, vs = orc.rollout(p, [[0.0, y, 0.0]], [[v0, 0, 0]], 10)
+    lam = ke * (-y)
+    expect = v0 - np.arange(11) * dt * muf * lam / m
+    assert np.abs(vs[:, 0, 0] - expect).max() < 1e-12
+    assert np.abs(vs[:, 0, 1]).max() < 1e-12
+
+
+def test_contact_stick_decay(oracle_lib):
+    """In the stick branch u_t <- u_t (1 - dt k_f / m) per step."""
+    o = oracle_lib
+    m, ke, muf, kf, dt = 1.0, 1e4, 0.5, 100.0, 1.0 / 600
+    y = -m * 9.81 / ke
+    orc = o.Oracle(np.array([[0.0, y, 0.0]]), ground=True, dt=dt)
+    p = {"mass": [m], "ke": ke, "kd": 0.0, "kf": kf, "muf": muf}
+    u0 = np.array([0.03, 0.0, -0.02])  # k_f |u| = 3.6 < mu_f lambda_n = 0.5 * 9.81
+    xs, vs = orc.rollout(p, [[0.0, y, 0.0]], [u0], 10)
+    expect = u0[None] * (1 - dt * kf / m) ** np.arange(11)[:, None]
+    assert np.abs(vs[:, 0, [0, 2]] - expect[:, [0, 2]]).max() < 1e-14
+
+
+def test_momentum_exact_without_gravity_or_contact(oracle_lib):
+    """Internal forces are translation and rotation invariant, so symplectic Euler keeps
+    sum m v and sum m x x v exactly (L+ = L + dt sum x x f = L)."""
+    o = oracle_lib
+    b = W.tiny_cube(0)
+    orc = make(o, b, gravity=(0, 0, 0), ground=False)
+    rng = np.random.default_rng(1)
+    x0 = b.X + rng.normal(0, 0.004, b.X.shape)
+    v0 = rng.normal(0, 0.3, b.X.shape)
+    xs, vs = orc.rollout(b.params(), x0, v0, 60)
+    m = b.mass[None, :, None]
+    P = (m * vs).sum(1)
+    L = (m * np.cross(xs, vs)).sum(1)
+    assert np.abs(P - P[0]).max() < 1e-11 * np.abs(P[0]).max()
+    assert np.abs(L - L[0]).max() < 1e-10 * np.abs(L[0]).max()
+
+
+def test_energy_drift_bounded_and_first_order(oracle_lib):
+    """Without gravity, contact or damping the energy error of symplectic Euler is
+    bounded and shrinks linearly with dt (App. A.2 integrator choice)."""
+    o = oracle_lib
+    b = W.tiny_cube(0)
+    p = b.params()
+    rng = np.random.default_rng(2)
+    x0 = b.X + rng.normal(0, 0.003, b.X.shape)
+    drift = []
+    for dt, T in ((1.0 / 1200, 240), (1.0 / 2400, 480)):
+        orc = make(o, b, gravity=(0, 0, 0), ground=False, dt=dt)
+        xs, vs = orc.rollout(p, x0, np.zeros_like(x0), T)
+        E = np.array([orc.energy(p, xs[t]) + 0.5 * (b.mass[:, None] * vs[t] ** 2).sum() for t in range(T + 1)])
+        drift.append(np.abs(E - E[0]).max() / E[0])
+    assert drift[0] < 0.2
+    assert 1.5 < drift[0] / drift[1] < 2.7
+
+
+# ---------------------------------------------------------------- adjoint
+
+def _mixed_body():
+    """A small tet body in sliding contact plus a cloth patch with bending and pins,
+    so every term of the force carries a nonzero Jacobian."""
+    tet = W.tiny_cube(0)
+    cl = W.cloth(11, n=5, size=0.2, height=0.5)
+    off = tet.np
+    X = np.concatenate([tet.X, cl.X])
+    b = W.Body(X=X, tets=tet.tets, tris=cl.tris + off, hinges=cl.hinges + off,
+               pinned=np.concatenate([tet.pinned, cl.pinned]), mu=tet.mu, lam=tet.lam, ktri=cl.ktri,
+               mass=np.concatenate([tet.mass, np.full(cl.np, 0.1)]), kb=0.05, ke=1e4, kd=3.0, kf=100.0, muf=0.5,
+               ground=True, dt=1.0 / 600)
+    return b
+
+
+def test_force_adjoint_dot_test(oracle_lib):
+    """<fbar, J d> = <J^T fbar, d> with J d from a single forward-mode pass over the
+    whole body and J^T fbar assembled from per-element Jacobian transposes; the
+    directional derivative itself matches central finite differences of the force."""
+    o = oracle_lib
+    b = _mixed_body()
+    orc = make(o, b)
+    rng = np.random.default_rng(3)
+    p = b.params()
+    p["act"] = rng.normal(0, 0.01, b.ne)
+    x = b.X + rng.normal(0, 0.002, b.X.shape)
+    x[:20, 1] -= 0.01  # some particles below the ground
+    v = rng.normal(0, 0.5, b.X.shape)
+    dx = rng.normal(size=x.shape); dv = rng.normal(size=x.shape)
+    dp = {"mu": rng.normal(size=b.ne), "lam": rng.normal(size=b.ne), "act": rng.normal(size=b.ne),
+          "ktri": rng.normal(size=b.nt), "kb": rng.normal(), "ke": rng.normal(), "kd": rng.normal(),
+          "kf": rng.normal(), "muf": rng.normal()}
+    dp_full = dict(dp)
+    for k in ("mass",):
+        dp_full[k] = np.zeros(b.np)
+    jd = orc.force_jvp(p, dp_full, x, v, dx, dv)
+    fbar = rng.normal(size=x.shape)
+    xb, vb, g = orc.force_vjp(p, x, v, fbar, want=("mu", "lam", "act", "ktri"))
+    lhs = (fbar * jd).sum()
+    rhs = (xb * dx).sum() + (vb * dv).sum() + g["mu"] @ dp["mu"] + g["lam"] @ dp["lam"] + g["act"] @ dp["act"] \
+        + g["ktri"] @ dp["ktri"] + g["kb"] * dp["kb"] + g["contact"] @ np.array([dp[k] for k in ("ke", "kd", "kf", "muf")])
+    assert abs(lhs - rhs) < 1e-10 * (abs(lhs) + 1e-30)
+    # FD of the force along the same direction (positions and velocities only)
+    h = 1e-7
+    fp = orc.forces(p, x + h * dx, v + h * dv)
+    fm = orc.forces(p, x - h * dx, v - h * dv)
+    jd_x = orc.force_jvp(p, {"mass": np.zeros(b.np)}, x, v, dx, dv)
+    assert np.linalg.norm((fp - fm) / (2 * h) - jd_x) < 1e-6 * np.linalg.norm(jd_x)
+
+
+def _rollout_loss(orc, p, x0, v0, T, target):
+    xT, _ = orc.rollout_final(p, x0, v0, T)
+    return orc.loss(xT, target)
+
+
+def test_rollout_gradient_central_fd(oracle_lib):
+    """Discrete adjoint (App. A) vs central finite differences of the rollout loss, for
+    every parameter group, along random directions and single coordinates."""
+    o = oracle_lib
+    b = _mixed_body()
+    orc = make(o, b)
+    rng = np.random.default_rng(4)
+    T = 40
+    p = b.params()
+    x0 = b.X.copy()
+    v0 = np.zeros_like(x0)
+    v0[:b.np - 25] = [1.0, -0.5, 0.0]
+    target = b.X + rng.normal(0, 0.02, b.X.shape)
+    L, g, xs, vs = orc.loss_and_grad(p, x0, v0, T, target, want=("mu", "lam", "ktri", "mass"))
+
+    def fd(mod, h):
+        pp, pm = mod(h), mod(-h)
+        return (_rollout_loss(orc, pp[0], pp[1], v0, T, target) - _rollout_loss(orc, pm[0], pm[1], v0, T, target)) / (2 * h)
+
+    def check(name, grad, vec, rel_h, tol=2e-5):
+        d = rng.normal(size=vec.shape) if vec.ndim else np.array(1.0)
+        scale = rel_h * np.abs(vec).max()
+
+        def mod(h):
+            q = dict(p)
+            q[name] = vec + h * scale * d
+            return q, x0
+        num = fd(mod, 1.0) / scale * 1.0
+        ana = float(np.sum(grad * d))
+        assert abs(num - ana) <= tol * (abs(ana) + 1e-12 * abs(L)), (name, num, ana)
+
+    check("mu", g["mu"], p["mu"], 1e-6)
+    check("lam", g["lam"], p["lam"], 1e-6)
+    check("ktri", g["ktri"], p["ktri"], 1e-6)
+    check("mass", g["mass"], p["mass"], 1e-6)
+    for k, name in enumerate(("ke", "kd", "kf", "muf")):
+        check(name, g["contact"][k], np.array(p[name], float), 1e-6)
+    check("kb", g["kb"], np.array(p["kb"], float), 1e-6)
+    # initial position
+    d = rng.normal(size=x0.shape)
+    h = 1e-7
+    num = (_rollout_loss(orc, p, x0 + h * d, v0, T, target) - _rollout_loss(orc, p, x0 - h * d, v0, T, target)) / (2 * h)
+    assert abs(num - (g["x0"] * d).sum()) < 2e-5 * abs(num)
+    # single coordinates of mu
+    for e in rng.choice(b.ne, 3, replace=False):
+        h = 1e-6 * p["mu"][e]
+        q1 = dict(p); q1["mu"] = p["mu"].copy(); q1["mu"][e] += h
+        q2 = dict(p); q2["mu"] = p["mu"].copy(); q2["mu"][e] -= h
+        num = (_rollout_loss(orc, q1, x0, v0, T, target) - _rollout_loss(orc, q2, x0, v0, T, target)) / (2 * h)
+        assert abs(num - g["mu"][e]) <= 1e-4 * abs(g["mu"][e]) + 1e-9 * np.abs(g["mu"]).max()
+
+
+def test_special_case_gradients(oracle_lib):
+    """Free fall: dL/dm = 0 (gravity is an acceleration), dL/dx0 = 2 (x_T - x*)/N and
+    dL/dv0 = T dt dL/dx0.  No contact: dL/dmu_f = 0.  All-stick contact: dL/dmu_f = 0."""
+    o = oracle_lib
+    rng = np.random.default_rng(5)
+    X = particles(4, rng)
+    orc = o.Oracle(X, dt=1.0 / 600)
+    T = 30
+    target = X + rng.normal(0, 0.1, X.shape)
+    p = {"mass": rng.uniform(0.5, 1.5, 4), "ke": 1e4, "kf": 100.0, "muf": 0.5}
+    L, g, xs, vs = orc.loss_and_grad(p, X, rng.normal(size=X.shape), T, target, want=("mass",))
+    assert np.all(g["mass"] == 0)
+    xbT = 2 * (xs[-1] - target) / 4
+    assert np.abs(g["x0"] - xbT).max() < 1e-14
+    assert np.abs(g["v0"] - T * orc.dt * xbT).max() < 1e-14
+    assert np.all(g["contact"] == 0)
+    # all-stick: resting particles with tiny sliding velocity at the static depth
+    m, ke = 1.0, 1e4
+    y = -m * 9.81 / ke
+    orc = o.Oracle(np.array([[0.0, y, 0.0]]), ground=True, dt=1.0 / 600)
+    L, g, xs, vs = orc.loss_and_grad({"mass": [m], "ke": ke, "kf": 100.0, "muf": 0.5}, [[0.0, y, 0.0]],
+                                     [[0.01, 0.0, 0.0]], 20, [[0.1, 0.0, 0.0]], want=("mass",))
+    assert g["contact"][3] == 0.0
+    assert g["contact"][2] != 0.0
