@@ -1,0 +1,208 @@
+/*
+ * gsim.h -- C-ABI of the MI355X differentiable simulation step.
+ *
+ * The library implements one time step of a deformable-body simulator and the
+ * reverse-mode adjoint of that step, as stated in "gradSim: differentiable
+ * simulation for system identification and visuomotor control" (ICLR 2021):
+ *
+ *   state      s = [q, u]: particle positions x and velocities v (Sec. 2.1);
+ *   parameters theta: per-tet Lame parameters mu, lambda (App. A.1, App. B.1),
+ *              per-triangle membrane stiffness k (App. A.1 thin shells),
+ *              per-particle mass m, per-body contact parameters
+ *              [k_e, k_d, k_f, mu_f] (App. A.1 "Contact");
+ *   step       the semi-implicit Euler relation g(s-, s+, theta) = 0 (App. A.2):
+ *              v+ = v- + dt (M^-1 f(s-) + g), x+ = x- + dt v+ ;
+ *   backward   the discrete adjoint (App. A, implicit-function theorem, with the
+ *              App. A.2 step Jacobians): from dl/ds+ it produces dl/ds- and
+ *              accumulates dl/dtheta.
+ *
+ * Forces f(s) are the sum of: stable Neo-Hookean constant-strain tets, with
+ * alpha = 1 + 3 mu/(4 lambda) + actuation; Neo-Hookean constant-strain
+ * membrane triangles with mu = lambda = k and alpha2 = 5/3; dihedral bending
+ * f = -k_b |E|^2/(|N1|+|N2|) sin((phi - phi0)/2 + a) dphi/dx with Bridson's
+ * directions; penalty ground contact lambda_n = k_e C + k_d Cdot along the
+ * plane normal and relaxed-Coulomb friction (isotropic cone, stick when
+ * k_f |u_t| <= mu_f |lambda_n|).  Gravity is an acceleration on particles
+ * that are not pinned.
+ *
+ * Conventions
+ *   - Every call returns an int status: GSIM_OK (0) or a negative GSIM_E_*.
+ *     gsim_last_error() returns a thread-local message for the last failure.
+ *   - Device arrays are caller-owned (the library never allocates device
+ *     memory).  Floating arrays have the model's dtype (float or double).
+ *   - Particle state is SoA: x[3][n_particles] (all x components, then y,
+ *     then z), same for v.  Bodies are contiguous particle ranges.
+ *   - Launches are asynchronous on the given stream (hipStream_t passed as
+ *     void*; NULL = the default stream).  Validation errors return
+ *     synchronously.  Successive calls on one model must be stream-ordered
+ *     (same stream, or synchronised by the caller): the model's workspace is
+ *     reused by every call.
+ *   - Parameter gradients ACCUMULATE into caller buffers (zero them first).
+ *     The mass gradient is with respect to m (not 1/m) and is 0 for pinned
+ *     particles.
+ *   - No C++ exception crosses this ABI.  Distinct models are independent.
+ */
+#ifndef GSIM_H
+#define GSIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GSIM_OK = 0,
+    GSIM_E_INVALID = -1,     /* bad argument (NULL pointer, size, dtype, ...) */
+    GSIM_E_TOPOLOGY = -2,    /* index out of range or element crossing bodies */
+    GSIM_E_DEGENERATE = -3,  /* zero-volume tet / zero-area triangle / zero-length hinge edge */
+    GSIM_E_WORKSPACE = -4,   /* workspace / buffer too small for the request */
+    GSIM_E_HIP = -5,         /* a HIP runtime call failed (message has the HIP error) */
+    GSIM_E_NONFINITE = -6,   /* non-finite input value */
+    GSIM_E_UNSUPPORTED = -7  /* request outside what the library implements */
+};
+
+enum { GSIM_F32 = 32, GSIM_F64 = 64 };
+
+/* Execution strategies for rollouts (gsim_model_set_exec). */
+enum {
+    GSIM_EXEC_PLAIN = 0,   /* two kernel launches per step (element pass, particle pass) */
+    GSIM_EXEC_GRAPH = 1,   /* the same launches captured once into a hipGraph and replayed
+                              (needs a non-default stream) */
+    GSIM_EXEC_FUSED = 2    /* persistent fused launch: whole step segments per launch */
+};
+
+const char* gsim_last_error(void);
+int gsim_version(int* major, int* minor);
+
+/* ------------------------------------------------------------------------ */
+/* MODEL DESCRIPTION (host memory, read only during gsim_plan_create)        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int dtype;                         /* GSIM_F32 or GSIM_F64 */
+    int n_bodies;                      /* >= 1 */
+    int64_t n_particles, n_tets, n_tris, n_hinges;
+    const int64_t* body_particle_off;  /* [n_bodies+1], body b owns particles [off[b], off[b+1]) */
+    const int64_t* body_tet_off;       /* [n_bodies+1] or NULL when n_tets == 0 */
+    const int64_t* body_tri_off;       /* [n_bodies+1] or NULL when n_tris == 0 */
+    const int64_t* body_hinge_off;     /* [n_bodies+1] or NULL when n_hinges == 0 */
+    const double* rest_x;              /* [n_particles][3] rest positions (AoS) */
+    const int32_t* tet_idx;            /* [n_tets][4] particle indices (model-global) */
+    const int32_t* tri_idx;            /* [n_tris][3] */
+    const int32_t* hinge_idx;          /* [n_hinges][4] = wing0, wing1, edge0, edge1 */
+    const uint8_t* pinned;             /* [n_particles] nonzero = kinematic (w = 0), or NULL */
+    const double* gravity;             /* [n_bodies][3] acceleration */
+    const double* dt;                  /* [n_bodies] time step */
+    const double* ground;              /* [n_bodies][4] plane n.x = d as (nx, ny, nz, d), or NULL */
+    const uint8_t* contact_on;         /* [n_bodies] nonzero = ground contact active, or NULL (off) */
+    const double* k_bend;              /* [n_bodies] bending stiffness, or NULL (0) */
+} gsim_model_desc;
+
+typedef struct gsim_plan gsim_plan;    /* host object: validated topology, rest data, tiles */
+typedef struct gsim_model gsim_model;  /* host handle bound to a caller-owned device workspace */
+
+/* Validates the description (indices in range and inside their body, finite
+ * rest positions, dt > 0), orients every tet so det(Dm) > 0 (swapping corners
+ * 1 and 2), precomputes Dm^-1 and rest volume / area and rest dihedral angles,
+ * and builds the deterministic force-gather tables (each particle sums its
+ * element-corner contributions in a fixed order: no atomics).
+ * Errors: GSIM_E_INVALID, GSIM_E_TOPOLOGY, GSIM_E_DEGENERATE, GSIM_E_NONFINITE. */
+int gsim_plan_create(const gsim_model_desc* desc, gsim_plan** out);
+int gsim_plan_destroy(gsim_plan* plan);
+
+/* Exact byte sizes of the caller-owned device buffers for rollouts of up to
+ * max_steps steps with a checkpoint every ckpt_every steps:
+ *   workspace: element records, gather tables, internal state buffers, launch
+ *              tables (pass to gsim_model_init);
+ *   ckpt:      ceil(max_steps/ckpt_every) saved states (x, v);
+ *   segment:   ckpt_every recomputed states used by gsim_rollout_backward.
+ * Any output pointer may be NULL. */
+int gsim_plan_sizes(const gsim_plan* plan, int max_steps, int ckpt_every, size_t* workspace_bytes,
+                    size_t* ckpt_bytes, size_t* segment_bytes);
+
+/* Counts of the planned model: particles, tets, tris, hinges, bodies. */
+int gsim_plan_counts(const gsim_plan* plan, int64_t* n_particles, int64_t* n_tets, int64_t* n_tris,
+                     int64_t* n_hinges, int* n_bodies);
+
+/* Binds a plan to a caller-owned device workspace (>= workspace_bytes of
+ * gsim_plan_sizes for the same max_steps / ckpt_every) and uploads the
+ * element records on `stream`.  The plan may be destroyed afterwards. */
+int gsim_model_init(const gsim_plan* plan, int max_steps, int ckpt_every, void* d_workspace, size_t bytes,
+                    void* stream, gsim_model** out);
+int gsim_model_destroy(gsim_model* model);
+
+/* Selects the rollout execution strategy (GSIM_EXEC_*) and launch shape:
+ * block = threads per workgroup (64..512, multiple of 64), items = elements
+ * (or particles) per thread (1..8).  0 keeps the current value. */
+int gsim_model_set_exec(gsim_model* model, int exec, int block, int items);
+int gsim_model_get_exec(const gsim_model* model, int* exec, int* block, int* items);
+
+/* ------------------------------------------------------------------------ */
+/* STATE, PARAMETERS, GRADIENTS (device pointers, caller-owned)              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    void* x; /* [3][n_particles] */
+    void* v; /* [3][n_particles] */
+} gsim_state;
+
+typedef struct {
+    const void* mu;      /* [n_tets] Lame mu            (required if n_tets)  */
+    const void* lam;     /* [n_tets] Lame lambda        (required if n_tets)  */
+    const void* act;     /* [n_tets] tet actuation, NULL = 0                  */
+    const void* k_tri;   /* [n_tris] membrane stiffness (required if n_tris)  */
+    const void* mass;    /* [n_particles] mass > 0 (pinned particles ignore it) */
+    const void* contact; /* [n_bodies][4] = k_e, k_d, k_f, mu_f (required if any contact) */
+} gsim_params;
+
+typedef struct {         /* any pointer may be NULL = gradient not requested */
+    void* mu;            /* [n_tets]      */
+    void* lam;           /* [n_tets]      */
+    void* k_tri;         /* [n_tris]      */
+    void* mass;          /* [n_particles] */
+    void* contact;       /* [n_bodies][4] */
+} gsim_grads;
+
+/* ------------------------------------------------------------------------ */
+/* STEP, ROLLOUT, BACKWARD, LOSS                                             */
+/* ------------------------------------------------------------------------ */
+
+/* n_steps semi-implicit Euler steps from `in` to `out` (App. A.2).  `in` and
+ * `out` may alias.  1 <= n_steps <= max_steps. */
+int gsim_step(gsim_model* model, const gsim_params* params, gsim_state in, gsim_state out, int n_steps,
+              void* stream);
+
+/* Reverse of ONE step taken at state s_minus: given adj_plus = dl/ds+ it writes
+ * adj_minus = dl/ds- and accumulates dl/dtheta into grad (App. A).
+ * adj_plus and adj_minus must not alias. */
+int gsim_step_backward(gsim_model* model, const gsim_params* params, gsim_state s_minus, gsim_state adj_plus,
+                       gsim_state adj_minus, const gsim_grads* grad, void* stream);
+
+/* Rollout of n_steps steps from s0 into s_final, saving the state at every
+ * step t with t % ckpt_every == 0 into d_ckpt (slot t/ckpt_every; layout
+ * [slot][x|v][3][n_particles]).  d_ckpt may be NULL for a forward-only run.
+ * ckpt_every must equal the value the model was initialised with. */
+int gsim_rollout(gsim_model* model, const gsim_params* params, gsim_state s0, int n_steps, void* d_ckpt,
+                 gsim_state s_final, void* stream);
+
+/* Checkpointed reverse pass of a rollout made by gsim_rollout with the same
+ * params and n_steps: for each checkpoint segment in reverse order it recomputes
+ * the segment's states into d_segment and runs the adjoint steps.  adj_final =
+ * dl/d(final state) (input, not modified), adj_initial = dl/d(s0) (output).
+ * Gradients accumulate into grad. */
+int gsim_rollout_backward(gsim_model* model, const gsim_params* params, const void* d_ckpt, int n_steps,
+                          void* d_segment, gsim_state adj_final, gsim_state adj_initial, const gsim_grads* grad,
+                          void* stream);
+
+/* Per-body mean squared distance to a target: loss[b] = (1/n_b) sum_i
+ * |x_i - x*_i|^2 over the body's particles; seeds adj_out.x = 2 (x - x*)/n_b
+ * and adj_out.v = 0 (either field may be NULL to skip).  d_target is
+ * [3][n_particles]; d_loss is [n_bodies]. */
+int gsim_loss_mse(gsim_model* model, gsim_state s, const void* d_target, void* d_loss, gsim_state adj_out,
+                  void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSIM_H */

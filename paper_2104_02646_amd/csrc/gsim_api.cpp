@@ -1,0 +1,1021 @@
+// Host runtime and C-ABI of libgsim (declared in include/gsim.h).
+//
+// Planning (host, once per model): validation of the description, tet
+// orientation, rest-shape precompute (Dm^-1, volume / area, rest dihedral
+// angle), the deterministic gather table (each particle's element corners in a
+// fixed order), and workgroup tiles.  Device memory is caller-owned: the model
+// carves its records, buffers and launch tables out of one workspace.
+//
+// Every step launches an element pass and a particle pass (forward or adjoint).
+// The per-launch pointers live in StepDev records in the workspace; a call
+// builds its records on the host, uploads only what changed, and replays its
+// launch sequence -- as plain launches or as a captured hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gsim.h"
+#include "gsim_internal.h"
+
+using namespace gsim;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(GSIM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call, what)                         \
+    do {                                            \
+        hipError_t e_ = (call);                     \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+#define LAUNCH_TRY(call, what)                                            \
+    do {                                                                  \
+        int rc_ = (call);                                                 \
+        if (rc_) return hip_fail((hipError_t)rc_, what);                  \
+    } while (0)
+
+struct D3 {
+    double x, y, z;
+};
+D3 sub(D3 a, D3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+D3 crs(D3 a, D3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+double dt3(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+double nrm(D3 a) { return std::sqrt(dt3(a, a)); }
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ plan ---
+struct gsim_plan {
+    int dtype = 32;
+    int nb = 0;
+    int64_t np = 0, ne = 0, nt = 0, nh = 0, nslot = 0;
+    std::vector<int64_t> poff, eoff, toff, hoff;   // per-body ranges
+    std::vector<int32_t> tet_idx, tet_slot;        // SoA [4][ne]
+    std::vector<double> tet_dinv, tet_vol;         // SoA [9][ne], [ne]
+    std::vector<int32_t> tri_idx, tri_slot;        // [3][nt]
+    std::vector<double> tri_dinv, tri_area;        // [4][nt], [nt]
+    std::vector<int32_t> hin_idx, hin_slot;        // [4][nh]
+    std::vector<double> hin_phi0;                  // [nh]
+    std::vector<int32_t> csr;                      // [np+1]
+    std::vector<uint8_t> pinned;                   // [np]
+    std::vector<double> dt, grav, plane, kb;       // per body
+    std::vector<uint8_t> contact_on;               // per body
+};
+
+namespace {
+
+bool finite(double v) { return std::isfinite(v); }
+
+int check_offsets(const int64_t* off, int nb, int64_t total, const char* name) {
+    if (total == 0 && off == nullptr) return GSIM_OK;
+    if (!off) return fail(GSIM_E_INVALID, "%s offsets are NULL but the count is %lld", name, (long long)total);
+    if (off[0] != 0 || off[nb] != total)
+        return fail(GSIM_E_INVALID, "%s offsets must start at 0 and end at %lld", name, (long long)total);
+    for (int b = 0; b < nb; ++b)
+        if (off[b + 1] < off[b]) return fail(GSIM_E_INVALID, "%s offsets decrease at body %d", name, b);
+    return GSIM_OK;
+}
+
+// Rest dihedral angle with the same orientation convention as the kernels.
+double rest_angle(const D3 x[4]) {
+    D3 E = sub(x[3], x[2]);
+    D3 N1 = crs(sub(x[0], x[2]), sub(x[0], x[3]));
+    D3 N2 = crs(sub(x[1], x[3]), sub(x[1], x[2]));
+    double el = nrm(E);
+    return std::atan2(-dt3(crs(N1, N2), E) / el, dt3(N1, N2));
+}
+
+int build_plan(const gsim_model_desc* d, gsim_plan* P) {
+    if (!d) return fail(GSIM_E_INVALID, "NULL description");
+    if (d->dtype != GSIM_F32 && d->dtype != GSIM_F64) return fail(GSIM_E_INVALID, "dtype must be 32 or 64");
+    if (d->n_bodies < 1) return fail(GSIM_E_INVALID, "n_bodies must be >= 1");
+    if (d->n_particles < 1 || d->n_tets < 0 || d->n_tris < 0 || d->n_hinges < 0)
+        return fail(GSIM_E_INVALID, "bad element counts");
+    if (d->n_particles > INT32_MAX || 4 * (d->n_tets + d->n_hinges) + 3 * d->n_tris > INT32_MAX)
+        return fail(GSIM_E_UNSUPPORTED, "model too large for 32-bit indices");
+    if (!d->rest_x || !d->body_particle_off || !d->gravity || !d->dt) return fail(GSIM_E_INVALID, "NULL required array");
+    if (d->n_tets && !d->tet_idx) return fail(GSIM_E_INVALID, "tet_idx is NULL");
+    if (d->n_tris && !d->tri_idx) return fail(GSIM_E_INVALID, "tri_idx is NULL");
+    if (d->n_hinges && !d->hinge_idx) return fail(GSIM_E_INVALID, "hinge_idx is NULL");
+    const int nb = d->n_bodies;
+    int rc;
+    if ((rc = check_offsets(d->body_particle_off, nb, d->n_particles, "particle"))) return rc;
+    if ((rc = check_offsets(d->body_tet_off, nb, d->n_tets, "tet"))) return rc;
+    if ((rc = check_offsets(d->body_tri_off, nb, d->n_tris, "tri"))) return rc;
+    if ((rc = check_offsets(d->body_hinge_off, nb, d->n_hinges, "hinge"))) return rc;
+    P->dtype = d->dtype;
+    P->nb = nb;
+    P->np = d->n_particles;
+    P->ne = d->n_tets;
+    P->nt = d->n_tris;
+    P->nh = d->n_hinges;
+    auto offs = [&](const int64_t* o) {
+        std::vector<int64_t> v(nb + 1, 0);
+        if (o) v.assign(o, o + nb + 1);
+        return v;
+    };
+    P->poff = offs(d->body_particle_off);
+    P->eoff = offs(d->body_tet_off);
+    P->toff = offs(d->body_tri_off);
+    P->hoff = offs(d->body_hinge_off);
+    for (int b = 0; b < nb; ++b)
+        if (P->poff[b + 1] == P->poff[b]) return fail(GSIM_E_INVALID, "body %d has no particles", b);
+
+    std::vector<D3> X(P->np);
+    for (int64_t i = 0; i < P->np; ++i) {
+        X[i] = {d->rest_x[3 * i], d->rest_x[3 * i + 1], d->rest_x[3 * i + 2]};
+        if (!finite(X[i].x) || !finite(X[i].y) || !finite(X[i].z))
+            return fail(GSIM_E_NONFINITE, "rest position %lld is not finite", (long long)i);
+    }
+    P->pinned.assign(P->np, 0);
+    if (d->pinned)
+        for (int64_t i = 0; i < P->np; ++i) P->pinned[i] = d->pinned[i] ? 1 : 0;
+    P->dt.resize(nb);
+    P->grav.resize(3 * nb);
+    P->plane.resize(4 * nb);
+    P->kb.resize(nb);
+    P->contact_on.assign(nb, 0);
+    for (int b = 0; b < nb; ++b) {
+        P->dt[b] = d->dt[b];
+        if (!(d->dt[b] > 0) || !finite(d->dt[b])) return fail(GSIM_E_INVALID, "dt of body %d must be > 0", b);
+        for (int c = 0; c < 3; ++c) {
+            P->grav[3 * b + c] = d->gravity[3 * b + c];
+            if (!finite(d->gravity[3 * b + c])) return fail(GSIM_E_NONFINITE, "gravity of body %d", b);
+        }
+        double pl[4] = {0.0, 1.0, 0.0, 0.0};
+        if (d->ground)
+            for (int c = 0; c < 4; ++c) pl[c] = d->ground[4 * b + c];
+        double nn = std::sqrt(pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2]);
+        if (!(nn > 0) || !finite(nn) || !finite(pl[3])) return fail(GSIM_E_INVALID, "ground plane of body %d", b);
+        for (int c = 0; c < 3; ++c) P->plane[4 * b + c] = pl[c] / nn;
+        P->plane[4 * b + 3] = pl[3] / nn;
+        P->kb[b] = d->k_bend ? d->k_bend[b] : 0.0;
+        P->contact_on[b] = d->contact_on ? (d->contact_on[b] ? 1 : 0) : 0;
+    }
+
+    // element -> body checks
+    auto in_body = [&](int64_t p, int b) { return p >= P->poff[b] && p < P->poff[b + 1]; };
+    const int64_t ne = P->ne, nt = P->nt, nh = P->nh;
+    P->tet_idx.resize(4 * ne);
+    P->tet_dinv.resize(9 * ne);
+    P->tet_vol.resize(ne);
+    for (int b = 0; b < nb; ++b)
+        for (int64_t e = P->eoff[b]; e < P->eoff[b + 1]; ++e) {
+            int32_t id[4];
+            for (int c = 0; c < 4; ++c) {
+                id[c] = d->tet_idx[4 * e + c];
+                if (!in_body(id[c], b)) return fail(GSIM_E_TOPOLOGY, "tet %lld corner %d outside body %d", (long long)e, c, b);
+            }
+            D3 c0 = sub(X[id[1]], X[id[0]]), c1 = sub(X[id[2]], X[id[0]]), c2 = sub(X[id[3]], X[id[0]]);
+            double det = dt3(c0, crs(c1, c2));
+            if (det < 0) {  // orient: swap corners 1 and 2
+                std::swap(id[1], id[2]);
+                std::swap(c0, c1);
+                det = -det;
+            }
+            double h = std::max(std::max(nrm(c0), nrm(c1)), nrm(c2));
+            if (!(det > 1e-12 * h * h * h)) return fail(GSIM_E_DEGENERATE, "tet %lld is degenerate", (long long)e);
+            // Dm columns c0, c1, c2; inverse rows are (c1 x c2, c2 x c0, c0 x c1) / det
+            D3 r[3] = {crs(c1, c2), crs(c2, c0), crs(c0, c1)};
+            for (int i = 0; i < 3; ++i) {
+                P->tet_dinv[(3 * i + 0) * ne + e] = r[i].x / det;
+                P->tet_dinv[(3 * i + 1) * ne + e] = r[i].y / det;
+                P->tet_dinv[(3 * i + 2) * ne + e] = r[i].z / det;
+            }
+            P->tet_vol[e] = det / 6.0;
+            for (int c = 0; c < 4; ++c) P->tet_idx[c * ne + e] = id[c];
+        }
+    P->tri_idx.resize(3 * nt);
+    P->tri_dinv.resize(4 * nt);
+    P->tri_area.resize(nt);
+    for (int b = 0; b < nb; ++b)
+        for (int64_t t = P->toff[b]; t < P->toff[b + 1]; ++t) {
+            int32_t id[3];
+            for (int c = 0; c < 3; ++c) {
+                id[c] = d->tri_idx[3 * t + c];
+                if (!in_body(id[c], b)) return fail(GSIM_E_TOPOLOGY, "tri %lld corner %d outside body %d", (long long)t, c, b);
+            }
+            D3 a = sub(X[id[1]], X[id[0]]), c = sub(X[id[2]], X[id[0]]);
+            D3 n = crs(a, c);
+            double la = nrm(a), ln = nrm(n);
+            if (!(la > 0) || !(ln > 1e-12 * la * nrm(c))) return fail(GSIM_E_DEGENERATE, "tri %lld is degenerate", (long long)t);
+            D3 e1 = {a.x / la, a.y / la, a.z / la};
+            D3 nn = {n.x / ln, n.y / ln, n.z / ln};
+            D3 e2 = crs(nn, e1);
+            // Dm = [[e1.a, e1.c], [e2.a, e2.c]]; e2.a = 0 by construction
+            double m00 = dt3(e1, a), m01 = dt3(e1, c), m10 = dt3(e2, a), m11 = dt3(e2, c);
+            double det = m00 * m11 - m01 * m10;
+            P->tri_dinv[0 * nt + t] = m11 / det;
+            P->tri_dinv[1 * nt + t] = -m01 / det;
+            P->tri_dinv[2 * nt + t] = -m10 / det;
+            P->tri_dinv[3 * nt + t] = m00 / det;
+            P->tri_area[t] = 0.5 * det;
+            for (int k = 0; k < 3; ++k) P->tri_idx[k * nt + t] = id[k];
+        }
+    P->hin_idx.resize(4 * nh);
+    P->hin_phi0.resize(nh);
+    for (int b = 0; b < nb; ++b)
+        for (int64_t h = P->hoff[b]; h < P->hoff[b + 1]; ++h) {
+            int32_t id[4];
+            D3 x[4];
+            for (int c = 0; c < 4; ++c) {
+                id[c] = d->hinge_idx[4 * h + c];
+                if (!in_body(id[c], b))
+                    return fail(GSIM_E_TOPOLOGY, "hinge %lld corner %d outside body %d", (long long)h, c, b);
+                x[c] = X[id[c]];
+            }
+            D3 E = sub(x[3], x[2]);
+            double el = nrm(E);
+            double n1 = nrm(crs(sub(x[0], x[2]), sub(x[0], x[3]))), n2 = nrm(crs(sub(x[1], x[3]), sub(x[1], x[2])));
+            if (!(el > 0) || !(n1 > 1e-12 * el * el) || !(n2 > 1e-12 * el * el))
+                return fail(GSIM_E_DEGENERATE, "hinge %lld is degenerate", (long long)h);
+            P->hin_phi0[h] = rest_angle(x);
+            for (int c = 0; c < 4; ++c) P->hin_idx[c * nh + h] = id[c];
+        }
+
+    // gather table: particle p owns slots csr[p] .. csr[p+1]-1, ordered by
+    // (tets, then triangles, then hinges; element index; corner)
+    std::vector<int32_t> deg(P->np, 0);
+    for (int64_t k = 0; k < 4 * ne; ++k) deg[P->tet_idx[k]]++;
+    for (int64_t k = 0; k < 3 * nt; ++k) deg[P->tri_idx[k]]++;
+    for (int64_t k = 0; k < 4 * nh; ++k) deg[P->hin_idx[k]]++;
+    P->csr.assign(P->np + 1, 0);
+    for (int64_t i = 0; i < P->np; ++i) P->csr[i + 1] = P->csr[i] + deg[i];
+    P->nslot = P->csr[P->np];
+    std::vector<int32_t> cur(P->csr.begin(), P->csr.end() - 1);
+    P->tet_slot.resize(4 * ne);
+    P->tri_slot.resize(3 * nt);
+    P->hin_slot.resize(4 * nh);
+    for (int64_t e = 0; e < ne; ++e)
+        for (int c = 0; c < 4; ++c) P->tet_slot[c * ne + e] = cur[P->tet_idx[c * ne + e]]++;
+    for (int64_t t = 0; t < nt; ++t)
+        for (int c = 0; c < 3; ++c) P->tri_slot[c * nt + t] = cur[P->tri_idx[c * nt + t]]++;
+    for (int64_t h = 0; h < nh; ++h)
+        for (int c = 0; c < 4; ++c) P->hin_slot[c * nh + h] = cur[P->hin_idx[c * nh + h]]++;
+    return GSIM_OK;
+}
+
+// ---------------------------------------------------------------- layout ---
+const int MIN_TILE = 64;  // smallest tile (block 64, 1 item): bounds the tile-list capacity
+const int N_XCD = 8;      // workgroups are dispatched round-robin over 8 XCDs
+
+int64_t tile_capacity(const gsim_plan* P, bool particles) {
+    int64_t n = 0;
+    for (int b = 0; b < P->nb; ++b) {
+        if (particles) {
+            n += (P->poff[b + 1] - P->poff[b] + MIN_TILE - 1) / MIN_TILE;
+        } else {
+            n += (P->eoff[b + 1] - P->eoff[b] + MIN_TILE - 1) / MIN_TILE;
+            n += (P->toff[b + 1] - P->toff[b] + MIN_TILE - 1) / MIN_TILE;
+            n += (P->hoff[b + 1] - P->hoff[b] + MIN_TILE - 1) / MIN_TILE;
+        }
+    }
+    return n + N_XCD;
+}
+
+struct Layout {
+    size_t model, bodies, etiles, ptiles;
+    size_t tet_idx, tet_slot, tet_dinv, tet_vol;
+    size_t tri_idx, tri_slot, tri_dinv, tri_area;
+    size_t hin_idx, hin_slot, hin_phi0;
+    size_t csr, pinned, slots, cpart, lpart;
+    size_t fbuf, abuf;  // forward / adjoint internal ping-pong states
+    size_t table;
+    int64_t table_cap;
+    size_t total;
+};
+
+template <typename T>
+Layout make_layout(const gsim_plan* P, int max_steps) {
+    Layout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        o = align_up(o, 256);
+        size_t at = o;
+        o += bytes;
+        return at;
+    };
+    const int64_t ne = P->ne, nt = P->nt, nh = P->nh, np = P->np;
+    const int64_t cap_p = tile_capacity(P, true), cap_e = tile_capacity(P, false);
+    L.model = take(sizeof(ModelDev<T>));
+    L.bodies = take(sizeof(BodyDev<T>) * P->nb);
+    L.etiles = take(sizeof(Tile) * cap_e);
+    L.ptiles = take(sizeof(Tile) * cap_p);
+    L.tet_idx = take(4 * ne * 4);
+    L.tet_slot = take(4 * ne * 4);
+    L.tet_dinv = take(9 * ne * sizeof(T));
+    L.tet_vol = take(ne * sizeof(T));
+    L.tri_idx = take(3 * nt * 4);
+    L.tri_slot = take(3 * nt * 4);
+    L.tri_dinv = take(4 * nt * sizeof(T));
+    L.tri_area = take(nt * sizeof(T));
+    L.hin_idx = take(4 * nh * 4);
+    L.hin_slot = take(4 * nh * 4);
+    L.hin_phi0 = take(nh * sizeof(T));
+    L.csr = take((np + 1) * 4);
+    L.pinned = take(np);
+    L.slots = take(4 * std::max<int64_t>(P->nslot, 1) * sizeof(T));
+    L.cpart = take(4 * (cap_p + 1) * sizeof(T));
+    L.lpart = take((cap_p + 1) * sizeof(T));
+    L.fbuf = take(2 * 6 * np * sizeof(T));
+    L.abuf = take(2 * 6 * np * sizeof(T));
+    L.table_cap = 4 * (int64_t)max_steps + 8;
+    L.table = take(sizeof(StepDev<T>) * L.table_cap);
+    L.total = align_up(o, 256);
+    return L;
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- model ---
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+};
+
+struct gsim_model {
+    int dtype = 32;
+    int nb = 0;
+    int64_t np = 0, ne = 0, nt = 0, nh = 0;
+    int max_steps = 0, K = 1;
+    char* ws = nullptr;
+    Layout L{};
+    std::vector<int64_t> poff, eoff, toff, hoff;
+    int exec = GSIM_EXEC_PLAIN, block = 256, items = 1;
+    int n_etiles = 0, n_ptiles = 0;   // launched grid sizes (including XCD padding)
+    int n_ptile_rows = 0;             // real particle tiles (contact / loss partial rows)
+    std::vector<char> bodies_host;    // BodyDev<T>[nb] as last uploaded
+    char* stage = nullptr;            // pinned copy of the launch table as last uploaded
+    hipEvent_t stage_evt = nullptr;   // completes when the last table upload has read `stage`
+    std::map<long long, GraphEntry> graphs;
+};
+
+namespace {
+
+// Builds the tile list for one pass: per body, `items`-sized chunks of each
+// kind, then permuted so that consecutive chunks land on the same XCD (block b
+// runs on XCD b % 8): chunk t goes to XCD t / ceil(N/8), at block j*8 + xcd.
+void build_tiles(gsim_model* m, bool particles, int tile, std::vector<Tile>& out, int& grid, int& rows) {
+    std::vector<Tile> nat;
+    rows = 0;
+    for (int b = 0; b < m->nb; ++b) {
+        auto add = [&](int kind, int64_t lo, int64_t hi) {
+            for (int64_t s = lo; s < hi; s += tile) {
+                Tile t{};
+                t.model = 0;
+                t.body = b;
+                t.kind = kind;
+                t.count = (int32_t)std::min<int64_t>(tile, hi - s);
+                t.begin = s;
+                t.id = particles ? rows++ : 0;
+                nat.push_back(t);
+            }
+        };
+        if (particles) {
+            add(TILE_PART, m->poff[b], m->poff[b + 1]);
+        } else {
+            add(TILE_TET, m->eoff[b], m->eoff[b + 1]);
+            add(TILE_TRI, m->toff[b], m->toff[b + 1]);
+            add(TILE_HINGE, m->hoff[b], m->hoff[b + 1]);
+        }
+    }
+    const int64_t N = (int64_t)nat.size();
+    if (N == 0) {
+        out.clear();
+        grid = 0;
+        return;
+    }
+    const int64_t G = (N + N_XCD - 1) / N_XCD;
+    grid = (int)(N < N_XCD ? N : G * N_XCD);
+    Tile empty{};
+    empty.kind = particles ? TILE_PART : TILE_TET;
+    empty.count = 0;
+    empty.id = rows;  // dummy partial row, never reduced
+    out.assign(grid, empty);
+    if (N < N_XCD) {
+        out = nat;
+        return;
+    }
+    for (int64_t t = 0; t < N; ++t) {
+        const int64_t xcd = t / G, j = t % G;
+        out[j * N_XCD + xcd] = nat[t];
+    }
+}
+
+template <typename T>
+int upload_tiles(gsim_model* m, void* stream) {
+    std::vector<Tile> et, pt;
+    int rows_e = 0;
+    build_tiles(m, false, m->block * m->items, et, m->n_etiles, rows_e);
+    build_tiles(m, true, m->block * m->items, pt, m->n_ptiles, m->n_ptile_rows);
+    hipStream_t s = (hipStream_t)stream;
+    if (!et.empty()) HIP_TRY(hipMemcpyAsync(m->ws + m->L.etiles, et.data(), et.size() * sizeof(Tile), hipMemcpyHostToDevice, s), "upload tiles");
+    if (!pt.empty()) HIP_TRY(hipMemcpyAsync(m->ws + m->L.ptiles, pt.data(), pt.size() * sizeof(Tile), hipMemcpyHostToDevice, s), "upload tiles");
+    // body particle-tile ranges (contact / loss partial rows) depend on the tile size
+    BodyDev<T>* bodies = reinterpret_cast<BodyDev<T>*>(m->bodies_host.data());
+    int row = 0;
+    const int tile = m->block * m->items;
+    for (int b = 0; b < m->nb; ++b) {
+        bodies[b].pt0 = row;
+        row += (int)((m->poff[b + 1] - m->poff[b] + tile - 1) / tile);
+        bodies[b].pt1 = row;
+    }
+    HIP_TRY(hipMemcpyAsync(m->ws + m->L.bodies, bodies, sizeof(BodyDev<T>) * m->nb, hipMemcpyHostToDevice, s), "upload bodies");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    for (auto& g : m->graphs)
+        if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+    m->graphs.clear();
+    return GSIM_OK;
+}
+
+template <typename T>
+int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t bytes, void* stream, gsim_model** out) {
+    Layout L = make_layout<T>(P, max_steps);
+    if (bytes < L.total) return fail(GSIM_E_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
+    if (((uintptr_t)d_ws & 255) != 0) return fail(GSIM_E_INVALID, "workspace must be 256-byte aligned");
+    gsim_model* m = new (std::nothrow) gsim_model();
+    if (!m) return fail(GSIM_E_INVALID, "out of host memory");
+    m->dtype = P->dtype;
+    m->nb = P->nb;
+    m->np = P->np;
+    m->ne = P->ne;
+    m->nt = P->nt;
+    m->nh = P->nh;
+    m->max_steps = max_steps;
+    m->K = K;
+    m->ws = (char*)d_ws;
+    m->L = L;
+    m->poff = P->poff;
+    m->eoff = P->eoff;
+    m->toff = P->toff;
+    m->hoff = P->hoff;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = m->ws;
+    auto up = [&](size_t off, const void* src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, s);
+    };
+    auto cvt = [](const std::vector<double>& v) { return std::vector<T>(v.begin(), v.end()); };
+    std::vector<T> tet_dinv = cvt(P->tet_dinv), tet_vol = cvt(P->tet_vol), tri_dinv = cvt(P->tri_dinv),
+                   tri_area = cvt(P->tri_area), hin_phi0 = cvt(P->hin_phi0);
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    chk(up(L.tet_idx, P->tet_idx.data(), P->tet_idx.size() * 4));
+    chk(up(L.tet_slot, P->tet_slot.data(), P->tet_slot.size() * 4));
+    chk(up(L.tet_dinv, tet_dinv.data(), tet_dinv.size() * sizeof(T)));
+    chk(up(L.tet_vol, tet_vol.data(), tet_vol.size() * sizeof(T)));
+    chk(up(L.tri_idx, P->tri_idx.data(), P->tri_idx.size() * 4));
+    chk(up(L.tri_slot, P->tri_slot.data(), P->tri_slot.size() * 4));
+    chk(up(L.tri_dinv, tri_dinv.data(), tri_dinv.size() * sizeof(T)));
+    chk(up(L.tri_area, tri_area.data(), tri_area.size() * sizeof(T)));
+    chk(up(L.hin_idx, P->hin_idx.data(), P->hin_idx.size() * 4));
+    chk(up(L.hin_slot, P->hin_slot.data(), P->hin_slot.size() * 4));
+    chk(up(L.hin_phi0, hin_phi0.data(), hin_phi0.size() * sizeof(T)));
+    chk(up(L.csr, P->csr.data(), P->csr.size() * 4));
+    chk(up(L.pinned, P->pinned.data(), P->pinned.size()));
+    std::vector<BodyDev<T>> bodies(P->nb);
+    for (int b = 0; b < P->nb; ++b) {
+        BodyDev<T>& B = bodies[b];
+        std::memset(&B, 0, sizeof B);
+        B.p0 = P->poff[b];
+        B.np = P->poff[b + 1] - P->poff[b];
+        B.contact_on = P->contact_on[b];
+        B.dt = (T)P->dt[b];
+        for (int c = 0; c < 3; ++c) B.g[c] = (T)P->grav[3 * b + c];
+        for (int c = 0; c < 4; ++c) B.plane[c] = (T)P->plane[4 * b + c];
+        B.kb = (T)P->kb[b];
+    }
+    m->bodies_host.assign(reinterpret_cast<const char*>(bodies.data()),
+                          reinterpret_cast<const char*>(bodies.data() + P->nb));
+    ModelDev<T> M;
+    std::memset(&M, 0, sizeof M);
+    M.np = P->np;
+    M.ne = P->ne;
+    M.nt = P->nt;
+    M.nh = P->nh;
+    M.nslot = P->nslot;
+    M.n_bodies = P->nb;
+    M.tet_idx = (const int32_t*)(ws + L.tet_idx);
+    M.tet_dinv = (const T*)(ws + L.tet_dinv);
+    M.tet_vol = (const T*)(ws + L.tet_vol);
+    M.tet_slot = (const int32_t*)(ws + L.tet_slot);
+    M.tri_idx = (const int32_t*)(ws + L.tri_idx);
+    M.tri_dinv = (const T*)(ws + L.tri_dinv);
+    M.tri_area = (const T*)(ws + L.tri_area);
+    M.tri_slot = (const int32_t*)(ws + L.tri_slot);
+    M.hin_idx = (const int32_t*)(ws + L.hin_idx);
+    M.hin_phi0 = (const T*)(ws + L.hin_phi0);
+    M.hin_slot = (const int32_t*)(ws + L.hin_slot);
+    M.csr = (const int32_t*)(ws + L.csr);
+    M.pinned = (const uint8_t*)(ws + L.pinned);
+    M.bodies = (const BodyDev<T>*)(ws + L.bodies);
+    M.slots = (T*)(ws + L.slots);
+    M.cpart = (T*)(ws + L.cpart);
+    M.lpart = (T*)(ws + L.lpart);
+    chk(up(L.model, &M, sizeof M));
+    chk(hipHostMalloc((void**)&m->stage, sizeof(StepDev<T>) * L.table_cap, hipHostMallocDefault));
+    chk(hipEventCreateWithFlags(&m->stage_evt, hipEventDisableTiming));
+    if (e == hipSuccess) std::memset(m->stage, 0, sizeof(StepDev<T>) * L.table_cap);
+    if (e != hipSuccess) {
+        if (m->stage) (void)hipHostFree(m->stage);
+        if (m->stage_evt) (void)hipEventDestroy(m->stage_evt);
+        delete m;
+        return hip_fail(e, "upload model");
+    }
+    int rc = upload_tiles<T>(m, stream);
+    if (rc) {
+        gsim_model_destroy(m);
+        return rc;
+    }
+    *out = m;
+    return GSIM_OK;
+}
+
+// ------------------------------------------------------------- launching ---
+template <typename T>
+struct Ctx {
+    gsim_model* m;
+    const ModelDev<T>* md;
+    const StepDev<T>* table;
+    const Tile* et;
+    const Tile* pt;
+    T* fbuf;  // [2][6][np]
+    T* abuf;
+    int64_t np;
+};
+
+template <typename T>
+Ctx<T> ctx(gsim_model* m) {
+    Ctx<T> c;
+    c.m = m;
+    c.md = (const ModelDev<T>*)(m->ws + m->L.model);
+    c.table = (const StepDev<T>*)(m->ws + m->L.table);
+    c.et = (const Tile*)(m->ws + m->L.etiles);
+    c.pt = (const Tile*)(m->ws + m->L.ptiles);
+    c.fbuf = (T*)(m->ws + m->L.fbuf);
+    c.abuf = (T*)(m->ws + m->L.abuf);
+    c.np = m->np;
+    return c;
+}
+
+// One launch of the sequence a call replays: pass kind and its table row.
+enum Op : int { OP_FWD = 0, OP_ADJ = 1, OP_FILL_CPART = 2, OP_CONTACT_REDUCE = 3, OP_LOSS = 4 };
+struct Launch {
+    int op;
+    int64_t row;
+};
+
+template <typename T>
+int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
+    Ctx<T> c = ctx<T>(m);
+    const ModelDev<T>* md = c.md;
+    for (const Launch& l : seq) {
+        const StepDev<T>* sd = c.table + l.row;
+        switch (l.op) {
+            case OP_FWD:
+                LAUNCH_TRY(launch_elem_fwd<T>(md, sd, c.et, m->n_etiles, m->block, m->items, stream), "element pass");
+                LAUNCH_TRY(launch_part_fwd<T>(md, sd, c.pt, m->n_ptiles, m->block, m->items, stream), "particle pass");
+                break;
+            case OP_ADJ:
+                LAUNCH_TRY(launch_elem_adj<T>(md, sd, c.et, m->n_etiles, m->block, m->items, stream), "element adjoint");
+                LAUNCH_TRY(launch_part_adj<T>(md, sd, c.pt, m->n_ptiles, m->block, m->items, stream), "particle adjoint");
+                break;
+            case OP_FILL_CPART:
+                LAUNCH_TRY(launch_fill<T>((T*)(m->ws + m->L.cpart), 4 * (int64_t)(m->n_ptile_rows + 1), T(0), stream), "clear");
+                break;
+            case OP_CONTACT_REDUCE:
+                LAUNCH_TRY(launch_contact_reduce<T>(md, sd, m->nb, stream), "contact reduce");
+                break;
+            case OP_LOSS:
+                LAUNCH_TRY(launch_loss<T>(md, sd, c.pt, m->n_ptiles, m->block, m->items, m->nb, stream), "loss");
+                break;
+        }
+    }
+    return GSIM_OK;
+}
+
+// Uploads table rows [row0, row0 + n) if they differ from the last upload.  The
+// pinned stage doubles as the record of what the device holds; before it is
+// rewritten the previous upload must have finished reading it.
+template <typename T>
+int upload_rows(gsim_model* m, int64_t row0, const std::vector<StepDev<T>>& rows, void* stream) {
+    const size_t off = (size_t)row0 * sizeof(StepDev<T>), n = rows.size() * sizeof(StepDev<T>);
+    if (row0 + (int64_t)rows.size() > m->L.table_cap) return fail(GSIM_E_WORKSPACE, "launch table too small");
+    if (n == 0 || std::memcmp(m->stage + off, rows.data(), n) == 0) return GSIM_OK;
+    HIP_TRY(hipEventSynchronize(m->stage_evt), "wait for table upload");
+    std::memcpy(m->stage + off, rows.data(), n);
+    HIP_TRY(hipMemcpyAsync(m->ws + m->L.table + off, m->stage + off, n, hipMemcpyHostToDevice, (hipStream_t)stream),
+            "upload launch table");
+    HIP_TRY(hipEventRecord(m->stage_evt, (hipStream_t)stream), "record table upload");
+    return GSIM_OK;
+}
+
+// Runs a launch sequence, through a cached hipGraph when the model asks for it.
+template <typename T>
+int execute(gsim_model* m, long long key, const std::vector<Launch>& seq, void* stream) {
+    if (m->exec == GSIM_EXEC_GRAPH) {
+        if (stream == nullptr) return fail(GSIM_E_UNSUPPORTED, "graph execution needs a non-default stream");
+        auto it = m->graphs.find(key);
+        if (it == m->graphs.end()) {
+            hipStream_t s = (hipStream_t)stream;
+            HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+            int rc = run_sequence<T>(m, seq, stream);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(s, &g);
+            if (rc) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return hip_fail(e, "end capture");
+            hipGraphExec_t ex = nullptr;
+            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(e, "instantiate graph");
+            it = m->graphs.emplace(key, GraphEntry{ex}).first;
+        }
+        HIP_TRY(hipGraphLaunch(it->second.exec, (hipStream_t)stream), "graph launch");
+        return GSIM_OK;
+    }
+    return run_sequence<T>(m, seq, stream);
+}
+
+template <typename T>
+void fill_params(StepDev<T>& r, const gsim_params* p, const gsim_grads* g) {
+    r.mu = (const T*)p->mu;
+    r.lam = (const T*)p->lam;
+    r.act = (const T*)p->act;
+    r.ktri = (const T*)p->k_tri;
+    r.mass = (const T*)p->mass;
+    r.contact = (const T*)p->contact;
+    if (g) {
+        r.g_mu = (T*)g->mu;
+        r.g_lam = (T*)g->lam;
+        r.g_ktri = (T*)g->k_tri;
+        r.g_mass = (T*)g->mass;
+        r.g_contact = (T*)g->contact;
+    }
+}
+
+int check_params(const gsim_model* m, const gsim_params* p) {
+    if (!p) return fail(GSIM_E_INVALID, "NULL params");
+    if (m->ne && (!p->mu || !p->lam)) return fail(GSIM_E_INVALID, "mu and lam are required for tets");
+    if (m->nt && !p->k_tri) return fail(GSIM_E_INVALID, "k_tri is required for triangles");
+    if (!p->mass) return fail(GSIM_E_INVALID, "mass is required");
+    if (!p->contact) return fail(GSIM_E_INVALID, "contact parameters are required ([n_bodies][4])");
+    return GSIM_OK;
+}
+
+// table regions
+int64_t region_rollout(const gsim_model*) { return 0; }
+int64_t region_backward(const gsim_model* m) { return m->max_steps + 2; }
+int64_t region_step(const gsim_model* m) { return 3 * (int64_t)m->max_steps + 4; }
+int64_t region_misc(const gsim_model* m) { return 4 * (int64_t)m->max_steps + 6; }
+
+template <typename T>
+int do_step(gsim_model* m, const gsim_params* p, gsim_state in, gsim_state out, int n, void* stream) {
+    if (n < 1 || n > m->max_steps) return fail(GSIM_E_INVALID, "n_steps must be in [1, %d]", m->max_steps);
+    if (!in.x || !in.v || !out.x || !out.v) return fail(GSIM_E_INVALID, "NULL state");
+    int rc = check_params(m, p);
+    if (rc) return rc;
+    Ctx<T> c = ctx<T>(m);
+    const int64_t S = 6 * c.np;
+    std::vector<StepDev<T>> rows(n);
+    std::vector<Launch> seq;
+    const int64_t r0 = region_step(m);
+    for (int t = 0; t < n; ++t) {
+        StepDev<T>& r = rows[t];
+        std::memset(&r, 0, sizeof r);
+        fill_params<T>(r, p, nullptr);
+        if (t == 0) {
+            r.x = (const T*)in.x;
+            r.v = (const T*)in.v;
+        } else {
+            r.x = c.fbuf + ((t - 1) & 1) * S;
+            r.v = r.x + 3 * c.np;
+        }
+        if (t == n - 1) {
+            r.xo = (T*)out.x;
+            r.vo = (T*)out.v;
+        } else {
+            r.xo = c.fbuf + (t & 1) * S;
+            r.vo = r.xo + 3 * c.np;
+        }
+        seq.push_back({OP_FWD, r0 + t});
+    }
+    if ((rc = upload_rows<T>(m, r0, rows, stream))) return rc;
+    return execute<T>(m, (1LL << 40) | n, seq, stream);
+}
+
+template <typename T>
+int do_step_backward(gsim_model* m, const gsim_params* p, gsim_state s, gsim_state ap, gsim_state am,
+                     const gsim_grads* g, void* stream) {
+    if (!s.x || !s.v || !ap.x || !ap.v || !am.x || !am.v) return fail(GSIM_E_INVALID, "NULL state");
+    if (ap.x == am.x || ap.v == am.v) return fail(GSIM_E_INVALID, "adj_plus and adj_minus must not alias");
+    int rc = check_params(m, p);
+    if (rc) return rc;
+    std::vector<StepDev<T>> rows(1);
+    std::memset(rows.data(), 0, sizeof(StepDev<T>));
+    StepDev<T>& r = rows[0];
+    fill_params<T>(r, p, g);
+    r.x = (const T*)s.x;
+    r.v = (const T*)s.v;
+    r.xb = (const T*)ap.x;
+    r.vb = (const T*)ap.v;
+    r.xbo = (T*)am.x;
+    r.vbo = (T*)am.v;
+    const int64_t r0 = region_misc(m);
+    if ((rc = upload_rows<T>(m, r0, rows, stream))) return rc;
+    std::vector<Launch> seq;
+    if (g && g->contact) seq.push_back({OP_FILL_CPART, r0});
+    seq.push_back({OP_ADJ, r0});
+    if (g && g->contact) seq.push_back({OP_CONTACT_REDUCE, r0});
+    return execute<T>(m, (2LL << 40) | (g && g->contact ? 1 : 0), seq, stream);
+}
+
+template <typename T>
+int do_rollout(gsim_model* m, const gsim_params* p, gsim_state s0, int n, void* ckpt, gsim_state sf, void* stream) {
+    if (n < 1 || n > m->max_steps) return fail(GSIM_E_INVALID, "n_steps must be in [1, %d]", m->max_steps);
+    if (!s0.x || !s0.v || !sf.x || !sf.v) return fail(GSIM_E_INVALID, "NULL state");
+    int rc = check_params(m, p);
+    if (rc) return rc;
+    Ctx<T> c = ctx<T>(m);
+    const int64_t S = 6 * c.np;
+    std::vector<StepDev<T>> rows(n);
+    std::vector<Launch> seq;
+    for (int t = 0; t < n; ++t) {
+        StepDev<T>& r = rows[t];
+        std::memset(&r, 0, sizeof r);
+        fill_params<T>(r, p, nullptr);
+        if (t == 0) {
+            r.x = (const T*)s0.x;
+            r.v = (const T*)s0.v;
+        } else {
+            r.x = c.fbuf + ((t - 1) & 1) * S;
+            r.v = r.x + 3 * c.np;
+        }
+        if (t == n - 1) {
+            r.xo = (T*)sf.x;
+            r.vo = (T*)sf.v;
+        } else {
+            r.xo = c.fbuf + (t & 1) * S;
+            r.vo = r.xo + 3 * c.np;
+        }
+        if (ckpt && t % m->K == 0) {
+            r.ckx = (T*)ckpt + (int64_t)(t / m->K) * S;
+            r.ckv = r.ckx + 3 * c.np;
+        }
+        seq.push_back({OP_FWD, region_rollout(m) + t});
+    }
+    if ((rc = upload_rows<T>(m, region_rollout(m), rows, stream))) return rc;
+    return execute<T>(m, (3LL << 40) | ((long long)n << 1) | (ckpt ? 1 : 0), seq, stream);
+}
+
+template <typename T>
+int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, int n, void* seg, gsim_state af,
+                        gsim_state ai, const gsim_grads* g, void* stream) {
+    if (n < 1 || n > m->max_steps) return fail(GSIM_E_INVALID, "n_steps must be in [1, %d]", m->max_steps);
+    if (!ckpt || !seg) return fail(GSIM_E_INVALID, "checkpoint and segment buffers are required");
+    if (!af.x || !af.v || !ai.x || !ai.v) return fail(GSIM_E_INVALID, "NULL adjoint state");
+    int rc = check_params(m, p);
+    if (rc) return rc;
+    Ctx<T> c = ctx<T>(m);
+    const int64_t S = 6 * c.np, np = c.np;
+    const int K = m->K;
+    const int nseg = (n + K - 1) / K;
+    std::vector<StepDev<T>> rows;
+    std::vector<Launch> seq;
+    const int64_t r0 = region_backward(m);
+    const bool want_contact = g && g->contact;
+    StepDev<T> base;
+    std::memset(&base, 0, sizeof base);
+    fill_params<T>(base, p, g);
+    if (want_contact) {
+        rows.push_back(base);
+        seq.push_back({OP_FILL_CPART, r0});
+    }
+    T* segT = (T*)seg;
+    const T* ck = (const T*)ckpt;
+    int q = 0;  // adjoint steps done
+    for (int s = nseg - 1; s >= 0; --s) {
+        const int t0 = s * K, t1 = std::min(n, t0 + K), L = t1 - t0;
+        // recompute states t0+1 .. t1-1 into seg[0 .. L-2]
+        for (int j = 0; j + 1 < L; ++j) {
+            StepDev<T> r = base;
+            r.g_mu = r.g_lam = r.g_ktri = r.g_mass = r.g_contact = nullptr;
+            r.x = j == 0 ? ck + s * S : segT + (j - 1) * S;
+            r.v = r.x + 3 * np;
+            r.xo = segT + j * S;
+            r.vo = r.xo + 3 * np;
+            rows.push_back(r);
+            seq.push_back({OP_FWD, r0 + (int64_t)rows.size() - 1});
+        }
+        for (int t = t1 - 1; t >= t0; --t, ++q) {
+            StepDev<T> r = base;
+            r.x = t == t0 ? ck + s * S : segT + (t - t0 - 1) * S;
+            r.v = r.x + 3 * np;
+            if (q == 0) {
+                r.xb = (const T*)af.x;
+                r.vb = (const T*)af.v;
+            } else {
+                r.xb = c.abuf + ((q - 1) & 1) * S;
+                r.vb = r.xb + 3 * np;
+            }
+            if (t == 0) {
+                r.xbo = (T*)ai.x;
+                r.vbo = (T*)ai.v;
+            } else {
+                r.xbo = c.abuf + (q & 1) * S;
+                r.vbo = r.xbo + 3 * np;
+            }
+            rows.push_back(r);
+            seq.push_back({OP_ADJ, r0 + (int64_t)rows.size() - 1});
+        }
+    }
+    if (want_contact) seq.push_back({OP_CONTACT_REDUCE, r0});
+    if ((rc = upload_rows<T>(m, r0, rows, stream))) return rc;
+    return execute<T>(m, (4LL << 40) | ((long long)n << 1) | (want_contact ? 1 : 0), seq, stream);
+}
+
+template <typename T>
+int do_loss(gsim_model* m, gsim_state s, const void* target, void* loss, gsim_state adj, void* stream) {
+    if (!s.x || !target || !loss) return fail(GSIM_E_INVALID, "NULL argument");
+    std::vector<StepDev<T>> rows(1);
+    std::memset(rows.data(), 0, sizeof(StepDev<T>));
+    rows[0].x = (const T*)s.x;
+    rows[0].target = (const T*)target;
+    rows[0].loss = (T*)loss;
+    rows[0].xbo = (T*)adj.x;
+    rows[0].vbo = (T*)adj.v;
+    const int64_t r0 = region_misc(m) + 1;
+    int rc = upload_rows<T>(m, r0, rows, stream);
+    if (rc) return rc;
+    std::vector<Launch> seq{{OP_LOSS, r0}};
+    return execute<T>(m, 5LL << 40, seq, stream);
+}
+
+template <typename T, typename F>
+int guarded(F f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc&) {
+        return fail(GSIM_E_INVALID, "out of host memory");
+    } catch (...) {
+        return fail(GSIM_E_INVALID, "internal error");
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C-ABI ---
+extern "C" {
+
+const char* gsim_last_error(void) { return g_err.c_str(); }
+
+int gsim_version(int* major, int* minor) {
+    if (major) *major = 0;
+    if (minor) *minor = 1;
+    return GSIM_OK;
+}
+
+int gsim_plan_create(const gsim_model_desc* desc, gsim_plan** out) {
+    if (!out) return fail(GSIM_E_INVALID, "NULL output");
+    *out = nullptr;
+    return guarded<double>([&]() {
+        gsim_plan* P = new gsim_plan();
+        int rc = build_plan(desc, P);
+        if (rc) {
+            delete P;
+            return rc;
+        }
+        *out = P;
+        return (int)GSIM_OK;
+    });
+}
+
+int gsim_plan_destroy(gsim_plan* plan) {
+    delete plan;
+    return GSIM_OK;
+}
+
+int gsim_plan_counts(const gsim_plan* P, int64_t* np, int64_t* ne, int64_t* nt, int64_t* nh, int* nb) {
+    if (!P) return fail(GSIM_E_INVALID, "NULL plan");
+    if (np) *np = P->np;
+    if (ne) *ne = P->ne;
+    if (nt) *nt = P->nt;
+    if (nh) *nh = P->nh;
+    if (nb) *nb = P->nb;
+    return GSIM_OK;
+}
+
+int gsim_plan_sizes(const gsim_plan* P, int max_steps, int K, size_t* ws, size_t* ck, size_t* seg) {
+    if (!P) return fail(GSIM_E_INVALID, "NULL plan");
+    if (max_steps < 1 || K < 1) return fail(GSIM_E_INVALID, "max_steps and ckpt_every must be >= 1");
+    const size_t sz = P->dtype == GSIM_F64 ? 8 : 4;
+    const size_t state = 6 * (size_t)P->np * sz;
+    if (ws) *ws = P->dtype == GSIM_F64 ? make_layout<double>(P, max_steps).total : make_layout<float>(P, max_steps).total;
+    if (ck) *ck = (size_t)((max_steps + K - 1) / K) * state;
+    if (seg) *seg = (size_t)K * state;
+    return GSIM_OK;
+}
+
+int gsim_model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t bytes, void* stream, gsim_model** out) {
+    if (!P || !out || !d_ws) return fail(GSIM_E_INVALID, "NULL argument");
+    if (max_steps < 1 || K < 1) return fail(GSIM_E_INVALID, "max_steps and ckpt_every must be >= 1");
+    *out = nullptr;
+    return guarded<double>([&]() {
+        return P->dtype == GSIM_F64 ? model_init<double>(P, max_steps, K, d_ws, bytes, stream, out)
+                                    : model_init<float>(P, max_steps, K, d_ws, bytes, stream, out);
+    });
+}
+
+int gsim_model_destroy(gsim_model* m) {
+    if (!m) return GSIM_OK;
+    for (auto& g : m->graphs)
+        if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+    if (m->stage_evt) {
+        (void)hipEventSynchronize(m->stage_evt);
+        (void)hipEventDestroy(m->stage_evt);
+    }
+    if (m->stage) (void)hipHostFree(m->stage);
+    delete m;
+    return GSIM_OK;
+}
+
+int gsim_model_set_exec(gsim_model* m, int exec, int block, int items) {
+    if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    if (exec != GSIM_EXEC_PLAIN && exec != GSIM_EXEC_GRAPH && exec != GSIM_EXEC_FUSED)
+        return fail(GSIM_E_INVALID, "unknown exec %d", exec);
+    if (exec == GSIM_EXEC_FUSED) return fail(GSIM_E_UNSUPPORTED, "fused execution is not available in this build");
+    if (block && (block < 64 || block > 512 || block % 64)) return fail(GSIM_E_INVALID, "block must be 64..512, multiple of 64");
+    if (items && (items < 1 || items > 8)) return fail(GSIM_E_INVALID, "items must be 1..8");
+    m->exec = exec;
+    if ((block && block != m->block) || (items && items != m->items)) {
+        if (block) m->block = block;
+        if (items) m->items = items;
+        return guarded<double>([&]() { return m->dtype == GSIM_F64 ? upload_tiles<double>(m, nullptr) : upload_tiles<float>(m, nullptr); });
+    }
+    return GSIM_OK;
+}
+
+int gsim_model_get_exec(const gsim_model* m, int* exec, int* block, int* items) {
+    if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    if (exec) *exec = m->exec;
+    if (block) *block = m->block;
+    if (items) *items = m->items;
+    return GSIM_OK;
+}
+
+#define DISPATCH(m, call) ((m)->dtype == GSIM_F64 ? call<double> : call<float>)
+
+int gsim_step(gsim_model* m, const gsim_params* p, gsim_state in, gsim_state out, int n, void* stream) {
+    if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    return guarded<double>([&]() { return DISPATCH(m, do_step)(m, p, in, out, n, stream); });
+}
+
+int gsim_step_backward(gsim_model* m, const gsim_params* p, gsim_state s, gsim_state ap, gsim_state am,
+                       const gsim_grads* g, void* stream) {
+    if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    return guarded<double>([&]() { return DISPATCH(m, do_step_backward)(m, p, s, ap, am, g, stream); });
+}
+
+int gsim_rollout(gsim_model* m, const gsim_params* p, gsim_state s0, int n, void* ckpt, gsim_state sf, void* stream) {
+    if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    return guarded<double>([&]() { return DISPATCH(m, do_rollout)(m, p, s0, n, ckpt, sf, stream); });
+}
+
+int gsim_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, int n, void* seg, gsim_state af,
+                          gsim_state ai, const gsim_grads* g, void* stream) {
+    if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    return guarded<double>([&]() { return DISPATCH(m, do_rollout_backward)(m, p, ckpt, n, seg, af, ai, g, stream); });
+}
+
+int gsim_loss_mse(gsim_model* m, gsim_state s, const void* target, void* loss, gsim_state adj, void* stream) {
+    if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    return guarded<double>([&]() { return DISPATCH(m, do_loss)(m, s, target, loss, adj, stream); });
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// Internal layouts shared by the HIP kernels and the host runtime of libgsim.
+//
+// Device data of one model (all inside the caller-owned workspace):
+//   element records, SoA over elements of each kind:
+//     tets    idx[4][ne] (int32, model-global particle index), dinv[9][ne] (Dm^-1
+//             row-major), vol[ne], slot[4][ne] (corner -> gather slot)
+//     tris    idx[3][nt], dinv[4][nt], area[nt], slot[3][nt]
+//     hinges  idx[4][nh] (wing0, wing1, edge0, edge1), phi0[nh], slot[4][nh]
+//   gather table csr[np+1]: particle p sums slots csr[p] .. csr[p+1]-1 in order;
+//   slots[nslot][4]: one 4-vector per element corner, written once per pass by
+//     the element kernel (forward: the corner force; adjoint: the corner's
+//     position-adjoint contribution and f_corner . fbar for the mass gradient).
+// Each kernel launch reads its per-launch pointers (state in/out, adjoints,
+// parameters, gradients) from a StepDev record in device memory, so a launch
+// sequence can be captured once into a hipGraph and replayed with new buffers.
+#pragma once
+#include <stdint.h>
+
+namespace gsim {
+
+enum TileKind : int32_t { TILE_TET = 0, TILE_TRI = 1, TILE_HINGE = 2, TILE_PART = 3 };
+
+// One workgroup's share of a pass: `count` consecutive items of one kind of one body.
+struct Tile {
+    int32_t model;  // index into the ModelDev / StepDev arrays of the launch
+    int32_t body;   // body index inside the model
+    int32_t kind;   // TileKind
+    int32_t count;  // items in this tile
+    int64_t begin;  // first item (model-global element or particle index)
+    int32_t id;     // particle tiles: row of the contact-gradient partial buffer
+    int32_t pad;
+};
+
+template <typename T>
+struct BodyDev {
+    int64_t p0, np;      // particle range
+    int32_t pt0, pt1;    // particle-tile id range (contact-gradient partials)
+    int32_t contact_on;  // ground contact active
+    int32_t pad;
+    T dt;
+    T g[3];
+    T plane[4];          // n.x = d
+    T kb;                // bending stiffness
+};
+
+template <typename T>
+struct ModelDev {
+    int64_t np, ne, nt, nh, nslot;
+    int32_t n_bodies, n_ptiles;
+    const int32_t* tet_idx;
+    const T* tet_dinv;
+    const T* tet_vol;
+    const int32_t* tet_slot;
+    const int32_t* tri_idx;
+    const T* tri_dinv;
+    const T* tri_area;
+    const int32_t* tri_slot;
+    const int32_t* hin_idx;
+    const T* hin_phi0;
+    const int32_t* hin_slot;
+    const int32_t* csr;
+    const uint8_t* pinned;
+    const BodyDev<T>* bodies;
+    T* slots;   // [nslot][4]
+    T* cpart;   // [n_ptiles][4] contact-gradient partial sums
+    T* lpart;   // [n_ptiles] loss partial sums
+};
+
+template <typename T>
+struct StepDev {
+    const T* x;   // state at the start of the step, SoA [3][np]
+    const T* v;
+    T* xo;        // forward: state at the end of the step
+    T* vo;
+    T* ckx;       // forward: optional copy of the input state (checkpoint)
+    T* ckv;
+    const T* xb;  // adjoint of the step output
+    const T* vb;
+    T* xbo;       // adjoint of the step input
+    T* vbo;
+    const T* mu;
+    const T* lam;
+    const T* act;
+    const T* ktri;
+    const T* mass;
+    const T* contact;  // [n_bodies][4]
+    T* g_mu;
+    T* g_lam;
+    T* g_ktri;
+    T* g_mass;
+    T* g_contact;      // [n_bodies][4]
+    const T* target;   // loss target, SoA [3][np]
+    T* loss;           // [n_bodies]
+};
+
+// Host-side launch helpers (defined in gsim_kernels.hip).  `stream` is a hipStream_t.
+template <typename T>
+int launch_elem_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int items,
+                    void* stream);
+template <typename T>
+int launch_part_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int items,
+                    void* stream);
+template <typename T>
+int launch_elem_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int items,
+                    void* stream);
+template <typename T>
+int launch_part_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int items,
+                    void* stream);
+template <typename T>
+int launch_fill(T* p, int64_t n, T value, void* stream);
+template <typename T>
+int launch_contact_reduce(const ModelDev<T>* md, const StepDev<T>* sd, int n_bodies, void* stream);
+template <typename T>
+int launch_loss(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int items,
+                int n_bodies, void* stream);
+
+}  // namespace gsim

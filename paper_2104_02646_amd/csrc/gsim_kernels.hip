@@ -1,0 +1,769 @@
+// HIP kernels of the differentiable simulation step for CDNA4 (gfx950).
+//
+// One step is two passes (Sec. 2.1 step relation; App. A.2 semi-implicit Euler):
+//   element pass   one thread per element: gathers its corner positions, evaluates
+//                  the element force (tet / membrane / bending, App. A.1) and
+//                  writes each corner's 4-vector into that corner's gather slot;
+//   particle pass  one thread per particle: sums its slots in a fixed order (no
+//                  atomics, bitwise deterministic), adds ground contact and
+//                  friction (App. A.1 "Contact", App. B.2) and integrates.
+// The adjoint step (App. A, App. A.2 Jacobians) has the same two passes in the
+// same layout: the element pass applies the hand-written reverse mode of each
+// element force to the corner adjoint forces fbar = dt w (vbar+ + dt xbar+),
+// the particle pass gathers those contributions, applies the contact adjoint and
+// closes the integrator's adjoint.  Element-owned parameter gradients (mu,
+// lambda, k) are accumulated by their element's thread; per-body contact
+// gradients go through a per-tile partial buffer reduced in fixed order.
+//
+// All state arrays are SoA [3][n]; element records SoA over elements; slots AoS
+// [nslot][4] so one corner is one 16-byte (FP32) access.  The kernels are
+// templated on the scalar type: float for production, double for checking the
+// algorithm against the FP64 oracle independently of FP32 rounding.
+#include <hip/hip_runtime.h>
+
+#include "gsim_internal.h"
+
+namespace gsim {
+namespace {
+
+// ------------------------------------------------------------------ math ---
+template <typename T>
+struct V3 {
+    T x, y, z;
+};
+
+template <typename T> __device__ __forceinline__ V3<T> mk3(T x, T y, T z) { return V3<T>{x, y, z}; }
+template <typename T> __device__ __forceinline__ V3<T> operator+(V3<T> a, V3<T> b) { return mk3(a.x + b.x, a.y + b.y, a.z + b.z); }
+template <typename T> __device__ __forceinline__ V3<T> operator-(V3<T> a, V3<T> b) { return mk3(a.x - b.x, a.y - b.y, a.z - b.z); }
+template <typename T> __device__ __forceinline__ V3<T> operator-(V3<T> a) { return mk3(-a.x, -a.y, -a.z); }
+template <typename T> __device__ __forceinline__ V3<T> operator*(V3<T> a, T s) { return mk3(a.x * s, a.y * s, a.z * s); }
+template <typename T> __device__ __forceinline__ V3<T>& operator+=(V3<T>& a, V3<T> b) { a = a + b; return a; }
+template <typename T> __device__ __forceinline__ V3<T>& operator-=(V3<T>& a, V3<T> b) { a = a - b; return a; }
+template <typename T> __device__ __forceinline__ T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <typename T> __device__ __forceinline__ V3<T> cross(V3<T> a, V3<T> b) {
+    return mk3(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+template <typename T> __device__ __forceinline__ V3<T> zero3() { return mk3(T(0), T(0), T(0)); }
+
+__device__ __forceinline__ float gsqrt(float a) { return sqrtf(a); }
+__device__ __forceinline__ double gsqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ float gsin(float a) { return sinf(a); }
+__device__ __forceinline__ double gsin(double a) { return sin(a); }
+__device__ __forceinline__ float gcos(float a) { return cosf(a); }
+__device__ __forceinline__ double gcos(double a) { return cos(a); }
+__device__ __forceinline__ float gatan2(float y, float x) { return atan2f(y, x); }
+__device__ __forceinline__ double gatan2(double y, double x) { return atan2(y, x); }
+
+template <typename T> __device__ __forceinline__ V3<T> ld3(const T* __restrict__ p, int64_t n, int64_t i) {
+    return mk3(p[i], p[n + i], p[2 * n + i]);
+}
+template <typename T> __device__ __forceinline__ void st3(T* __restrict__ p, int64_t n, int64_t i, V3<T> a) {
+    p[i] = a.x;
+    p[n + i] = a.y;
+    p[2 * n + i] = a.z;
+}
+
+__device__ __forceinline__ void st_slot(float* s, int64_t k, float a, float b, float c, float d) {
+    *reinterpret_cast<float4*>(s + 4 * k) = make_float4(a, b, c, d);
+}
+__device__ __forceinline__ void st_slot(double* s, int64_t k, double a, double b, double c, double d) {
+    double2* p = reinterpret_cast<double2*>(s + 4 * k);
+    p[0] = make_double2(a, b);
+    p[1] = make_double2(c, d);
+}
+__device__ __forceinline__ void ld_slot(const float* s, int64_t k, float& a, float& b, float& c, float& d) {
+    float4 q = *reinterpret_cast<const float4*>(s + 4 * k);
+    a = q.x; b = q.y; c = q.z; d = q.w;
+}
+__device__ __forceinline__ void ld_slot(const double* s, int64_t k, double& a, double& b, double& c, double& d) {
+    const double2* p = reinterpret_cast<const double2*>(s + 4 * k);
+    double2 q0 = p[0], q1 = p[1];
+    a = q0.x; b = q0.y; c = q1.x; d = q1.y;
+}
+
+template <typename T> __device__ __forceinline__ T inv_mass(const ModelDev<T>& M, const StepDev<T>& S, int64_t i) {
+    return M.pinned[i] ? T(0) : T(1) / S.mass[i];
+}
+
+// ---------------------------------------------------------- tet (NH) ---
+// F = Ds Dm^-1; P = mu (1 - 1/(Ic+1)) F + lambda (J - alpha) cof F with
+// alpha = 1 + 3 mu/(4 lambda) + a; corner forces [f1 f2 f3] = -V P Dm^-T,
+// f0 = -(f1 + f2 + f3).
+template <typename T>
+__device__ __forceinline__ void tet_force(const V3<T> x[4], const T D[9], T V, T mu, T lam, T act, V3<T> f[4]) {
+    const V3<T> d0 = x[1] - x[0], d1 = x[2] - x[0], d2 = x[3] - x[0];
+    V3<T> F[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) F[j] = d0 * D[j] + d1 * D[3 + j] + d2 * D[6 + j];
+    const T Ic = dot(F[0], F[0]) + dot(F[1], F[1]) + dot(F[2], F[2]);
+    const V3<T> C[3] = {cross(F[1], F[2]), cross(F[2], F[0]), cross(F[0], F[1])};
+    const T J = dot(F[0], C[0]);
+    const T alpha = T(1) + T(0.75) * mu / lam + act;
+    const T A = mu * (T(1) - T(1) / (Ic + T(1)));
+    const T B = lam * (J - alpha);
+    V3<T> P[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) P[j] = F[j] * A + C[j] * B;
+    f[0] = zero3<T>();
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        f[i + 1] = (P[0] * D[3 * i] + P[1] * D[3 * i + 1] + P[2] * D[3 * i + 2]) * (-V);
+        f[0] -= f[i + 1];
+    }
+}
+
+// Reverse mode of tet_force for corner adjoints fb: position adjoints xb (the
+// transpose of df/dx applied to fb), d/dmu and d/dlambda of <fb, f>; also
+// returns the forces themselves (for the mass gradient).
+template <typename T>
+__device__ __forceinline__ void tet_adjoint(const V3<T> x[4], const T D[9], T V, T mu, T lam, T act, const V3<T> fb[4],
+                                            V3<T> f[4], V3<T> xb[4], T& gmu, T& glam) {
+    const V3<T> d0 = x[1] - x[0], d1 = x[2] - x[0], d2 = x[3] - x[0];
+    V3<T> F[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) F[j] = d0 * D[j] + d1 * D[3 + j] + d2 * D[6 + j];
+    const T Ic = dot(F[0], F[0]) + dot(F[1], F[1]) + dot(F[2], F[2]);
+    const V3<T> C[3] = {cross(F[1], F[2]), cross(F[2], F[0]), cross(F[0], F[1])};
+    const T J = dot(F[0], C[0]);
+    const T alpha = T(1) + T(0.75) * mu / lam + act;
+    const T ip = T(1) / (Ic + T(1));
+    const T A = mu * (T(1) - ip);
+    const T B = lam * (J - alpha);
+    V3<T> P[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) P[j] = F[j] * A + C[j] * B;
+    f[0] = zero3<T>();
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        f[i + 1] = (P[0] * D[3 * i] + P[1] * D[3 * i + 1] + P[2] * D[3 * i + 2]) * (-V);
+        f[0] -= f[i + 1];
+    }
+    // f_{i+1} = H_i, f_0 = -sum H_i  =>  Hbar_i = fb_{i+1} - fb_0
+    const V3<T> Hb[3] = {fb[1] - fb[0], fb[2] - fb[0], fb[3] - fb[0]};
+    V3<T> Pb[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Pb[j] = (Hb[0] * D[j] + Hb[1] * D[3 + j] + Hb[2] * D[6 + j]) * (-V);
+    const T Ab = dot(Pb[0], F[0]) + dot(Pb[1], F[1]) + dot(Pb[2], F[2]);
+    const T Bb = dot(Pb[0], C[0]) + dot(Pb[1], C[1]) + dot(Pb[2], C[2]);
+    gmu = (T(1) - ip) * Ab - T(0.75) * Bb;  // dA/dmu = 1 - 1/(Ic+1), dB/dmu = -3/4
+    glam = (J - T(1) - act) * Bb;          // dB/dlambda = J - alpha + 3mu/(4 lambda)
+    const T Icb = Ab * mu * ip * ip;
+    const T Jb = Bb * lam;
+    V3<T> Fb[3], Cb[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        Fb[j] = Pb[j] * A + C[j] * Jb + F[j] * (T(2) * Icb);
+        Cb[j] = Pb[j] * B;
+    }
+    // C0 = F1 x F2, C1 = F2 x F0, C2 = F0 x F1;  (a x b) adjoint: abar = b x cbar, bbar = cbar x a
+    Fb[1] += cross(F[2], Cb[0]);
+    Fb[2] += cross(Cb[0], F[1]);
+    Fb[2] += cross(F[0], Cb[1]);
+    Fb[0] += cross(Cb[1], F[2]);
+    Fb[0] += cross(F[1], Cb[2]);
+    Fb[1] += cross(Cb[2], F[0]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) xb[k + 1] = Fb[0] * D[3 * k] + Fb[1] * D[3 * k + 1] + Fb[2] * D[3 * k + 2];
+    xb[0] = -(xb[1] + xb[2] + xb[3]);
+}
+
+// --------------------------------------------------- membrane triangle ---
+// F (3x2) = [x1-x0, x2-x0] Dm^-1; Ic = |F0|^2+|F1|^2; J = |F0 x F1|; n = (F0 x F1)/J;
+// dJ/dF = [F1 x n, n x F0]; mu = lambda = k, alpha2 = 5/3;
+// P = k (1 - 1/(Ic+1)) F + k (J - 5/3) dJ/dF; [f1 f2] = -A P Dm^-T; f0 = -(f1+f2).
+template <typename T>
+__device__ __forceinline__ void tri_force(const V3<T> x[3], const T D[4], T area, T k, V3<T> f[3]) {
+    const V3<T> d0 = x[1] - x[0], d1 = x[2] - x[0];
+    const V3<T> F0 = d0 * D[0] + d1 * D[2];
+    const V3<T> F1 = d0 * D[1] + d1 * D[3];
+    const T Ic = dot(F0, F0) + dot(F1, F1);
+    const V3<T> c = cross(F0, F1);
+    const T J = gsqrt(dot(c, c));
+    const V3<T> n = c * (T(1) / J);
+    const V3<T> G0 = cross(F1, n), G1 = cross(n, F0);
+    const T A = k * (T(1) - T(1) / (Ic + T(1)));
+    const T B = k * (J - T(5) / T(3));
+    const V3<T> P0 = F0 * A + G0 * B, P1 = F1 * A + G1 * B;
+    f[1] = (P0 * D[0] + P1 * D[1]) * (-area);
+    f[2] = (P0 * D[2] + P1 * D[3]) * (-area);
+    f[0] = -(f[1] + f[2]);
+}
+
+template <typename T>
+__device__ __forceinline__ void tri_adjoint(const V3<T> x[3], const T D[4], T area, T k, const V3<T> fb[3], V3<T> f[3],
+                                            V3<T> xb[3], T& gk) {
+    const V3<T> d0 = x[1] - x[0], d1 = x[2] - x[0];
+    const V3<T> F0 = d0 * D[0] + d1 * D[2];
+    const V3<T> F1 = d0 * D[1] + d1 * D[3];
+    const T Ic = dot(F0, F0) + dot(F1, F1);
+    const V3<T> c = cross(F0, F1);
+    const T J = gsqrt(dot(c, c));
+    const T iJ = T(1) / J;
+    const V3<T> n = c * iJ;
+    const V3<T> G0 = cross(F1, n), G1 = cross(n, F0);
+    const T ip = T(1) / (Ic + T(1));
+    const T A = k * (T(1) - ip);
+    const T B = k * (J - T(5) / T(3));
+    const V3<T> P0 = F0 * A + G0 * B, P1 = F1 * A + G1 * B;
+    f[1] = (P0 * D[0] + P1 * D[1]) * (-area);
+    f[2] = (P0 * D[2] + P1 * D[3]) * (-area);
+    f[0] = -(f[1] + f[2]);
+    const V3<T> Hb0 = fb[1] - fb[0], Hb1 = fb[2] - fb[0];
+    const V3<T> Pb0 = (Hb0 * D[0] + Hb1 * D[2]) * (-area);
+    const V3<T> Pb1 = (Hb0 * D[1] + Hb1 * D[3]) * (-area);
+    const T Ab = dot(Pb0, F0) + dot(Pb1, F1);
+    const T Bb = dot(Pb0, G0) + dot(Pb1, G1);
+    gk = (T(1) - ip) * Ab + (J - T(5) / T(3)) * Bb;
+    const T Icb = Ab * k * ip * ip;
+    const T Jb = Bb * k;
+    V3<T> Fb0 = Pb0 * A + F0 * (T(2) * Icb);
+    V3<T> Fb1 = Pb1 * A + F1 * (T(2) * Icb);
+    const V3<T> Gb0 = Pb0 * B, Gb1 = Pb1 * B;
+    // G0 = F1 x n, G1 = n x F0
+    Fb1 += cross(n, Gb0);
+    V3<T> nb = cross(Gb0, F1);
+    nb += cross(F0, Gb1);
+    Fb0 += cross(Gb1, n);
+    // n = c / |c|, J = |c|
+    const V3<T> cb = (nb - n * dot(n, nb)) * iJ + n * Jb;
+    // c = F0 x F1
+    Fb0 += cross(F1, cb);
+    Fb1 += cross(cb, F0);
+    xb[1] = Fb0 * D[0] + Fb1 * D[1];
+    xb[2] = Fb0 * D[2] + Fb1 * D[3];
+    xb[0] = -(xb[1] + xb[2]);
+}
+
+// ------------------------------------------------------------- bending ---
+// Wings x0, x1; edge E = x3 - x2; N1 = (x0-x2)x(x0-x3), N2 = (x1-x3)x(x1-x2).
+// Bridson's directions u0 = |E| N1/|N1|^2, u1 = |E| N2/|N2|^2,
+// u2 = s0 N1/|N1|^2 + s1 N2/|N2|^2, u3 = -(s2 N1/|N1|^2 + s3 N2/|N2|^2) with
+// s0 = (x0-x3).E/|E|, s1 = (x1-x3).E/|E|, s2 = (x0-x2).E/|E|, s3 = (x1-x2).E/|E|;
+// they equal d phi/dx_i for phi = atan2(-((N1 x N2).E)/|E|, N1.N2).
+// f_i = -k_b |E|^2/(|N1|+|N2|) sin((phi - phi0)/2) u_i.
+template <typename T>
+struct HingeGeo {
+    V3<T> E, N1, N2, a1, a2, Eh, u[4];
+    T el, n1, n2, s[4], phi;
+};
+
+template <typename T>
+__device__ __forceinline__ void hinge_geo(const V3<T> x[4], HingeGeo<T>& h) {
+    h.E = x[3] - x[2];
+    h.N1 = cross(x[0] - x[2], x[0] - x[3]);
+    h.N2 = cross(x[1] - x[3], x[1] - x[2]);
+    h.el = gsqrt(dot(h.E, h.E));
+    const T n1sq = dot(h.N1, h.N1), n2sq = dot(h.N2, h.N2);
+    h.n1 = gsqrt(n1sq);
+    h.n2 = gsqrt(n2sq);
+    h.a1 = h.N1 * (T(1) / n1sq);
+    h.a2 = h.N2 * (T(1) / n2sq);
+    h.Eh = h.E * (T(1) / h.el);
+    h.s[0] = dot(x[0] - x[3], h.Eh);
+    h.s[1] = dot(x[1] - x[3], h.Eh);
+    h.s[2] = dot(x[0] - x[2], h.Eh);
+    h.s[3] = dot(x[1] - x[2], h.Eh);
+    h.u[0] = h.a1 * h.el;
+    h.u[1] = h.a2 * h.el;
+    h.u[2] = h.a1 * h.s[0] + h.a2 * h.s[1];
+    h.u[3] = -(h.a1 * h.s[2] + h.a2 * h.s[3]);
+    h.phi = gatan2(-dot(cross(h.N1, h.N2), h.Eh), dot(h.N1, h.N2));
+}
+
+template <typename T>
+__device__ __forceinline__ void hinge_force(const V3<T> x[4], T phi0, T kb, V3<T> f[4]) {
+    HingeGeo<T> h;
+    hinge_geo(x, h);
+    const T sc = h.el * h.el / (h.n1 + h.n2);
+    const T mag = -kb * sc * gsin(T(0.5) * (h.phi - phi0));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f[i] = h.u[i] * mag;
+}
+
+template <typename T>
+__device__ __forceinline__ void hinge_adjoint(const V3<T> x[4], T phi0, T kb, const V3<T> fb[4], V3<T> f[4],
+                                              V3<T> xb[4]) {
+    HingeGeo<T> h;
+    hinge_geo(x, h);
+    const T q = h.n1 + h.n2;
+    const T sc = h.el * h.el / q;
+    const T psi = T(0.5) * (h.phi - phi0);
+    const T sn = gsin(psi), cs = gcos(psi);
+    const T mag = -kb * sc * sn;
+    T magb = T(0);
+    V3<T> ub[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        f[i] = h.u[i] * mag;
+        ub[i] = fb[i] * mag;
+        magb += dot(fb[i], h.u[i]);
+    }
+    const T scb = -kb * sn * magb;
+    const T phib = -kb * sc * cs * T(0.5) * magb;
+    // phi: its gradient is u (exact identity of the dihedral angle)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) xb[i] = h.u[i] * phib;
+    // sc = el^2 / (|N1| + |N2|)
+    T elb = scb * T(2) * h.el / q;
+    const T qb = -scb * sc / q;
+    V3<T> N1b = h.N1 * (qb / h.n1);
+    V3<T> N2b = h.N2 * (qb / h.n2);
+    // u0 = el a1, u1 = el a2, u2 = s0 a1 + s1 a2, u3 = -(s2 a1 + s3 a2)
+    elb += dot(ub[0], h.a1) + dot(ub[1], h.a2);
+    V3<T> a1b = ub[0] * h.el + ub[2] * h.s[0] - ub[3] * h.s[2];
+    V3<T> a2b = ub[1] * h.el + ub[2] * h.s[1] - ub[3] * h.s[3];
+    const T sb0 = dot(ub[2], h.a1), sb1 = dot(ub[2], h.a2);
+    const T sb2 = -dot(ub[3], h.a1), sb3 = -dot(ub[3], h.a2);
+    // s0 = (x0-x3).Eh, s1 = (x1-x3).Eh, s2 = (x0-x2).Eh, s3 = (x1-x2).Eh
+    xb[0] += h.Eh * (sb0 + sb2);
+    xb[1] += h.Eh * (sb1 + sb3);
+    xb[2] -= h.Eh * (sb2 + sb3);
+    xb[3] -= h.Eh * (sb0 + sb1);
+    const V3<T> Ehb = (x[0] - x[3]) * sb0 + (x[1] - x[3]) * sb1 + (x[0] - x[2]) * sb2 + (x[1] - x[2]) * sb3;
+    // Eh = E / el, el = |E|
+    const V3<T> Eb = (Ehb - h.Eh * dot(h.Eh, Ehb)) * (T(1) / h.el) + h.Eh * elb;
+    // a = N / |N|^2
+    const T n1sq = h.n1 * h.n1, n2sq = h.n2 * h.n2;
+    N1b += a1b * (T(1) / n1sq) - h.N1 * (T(2) * dot(a1b, h.N1) / (n1sq * n1sq));
+    N2b += a2b * (T(1) / n2sq) - h.N2 * (T(2) * dot(a2b, h.N2) / (n2sq * n2sq));
+    // E = x3 - x2
+    xb[3] += Eb;
+    xb[2] -= Eb;
+    // N1 = p x q with p = x0 - x2, q = x0 - x3
+    {
+        const V3<T> p = x[0] - x[2], qv = x[0] - x[3];
+        const V3<T> pb = cross(qv, N1b), qb2 = cross(N1b, p);
+        xb[0] += pb + qb2;
+        xb[2] -= pb;
+        xb[3] -= qb2;
+    }
+    // N2 = p x q with p = x1 - x3, q = x1 - x2
+    {
+        const V3<T> p = x[1] - x[3], qv = x[1] - x[2];
+        const V3<T> pb = cross(qv, N2b), qb2 = cross(N2b, p);
+        xb[1] += pb + qb2;
+        xb[3] -= pb;
+        xb[2] -= qb2;
+    }
+}
+
+// ------------------------------------------------------------- contact ---
+// gap = n.x - d; C = -gap when gap < 0; lambda_n = k_e C + k_d Cdot, Cdot = -n.v;
+// f_n = lambda_n n; u_t = v - (n.v) n; stick if k_f |u_t| <= mu_f |lambda_n|:
+// f_f = -k_f u_t; otherwise f_f = -mu_f |lambda_n| u_t / |u_t|.
+template <typename T>
+__device__ __forceinline__ V3<T> contact_force(V3<T> x, V3<T> v, const T pl[4], const T c[4]) {
+    const V3<T> n = mk3(pl[0], pl[1], pl[2]);
+    const T gap = dot(n, x) - pl[3];
+    if (!(gap < T(0))) return zero3<T>();
+    const T C = -gap;
+    const T vn = dot(n, v);
+    const T lam = c[0] * C - c[1] * vn;
+    const V3<T> ut = v - n * vn;
+    const T s = gsqrt(dot(ut, ut));
+    const T lim = c[3] * (lam < T(0) ? -lam : lam);
+    V3<T> ff;
+    if (c[2] * s <= lim) ff = ut * (-c[2]);
+    else ff = ut * (-lim / s);
+    return n * lam + ff;
+}
+
+// Adjoint of contact_force for the force adjoint fb: adds to xb, vb and the
+// contact-parameter gradients gc (k_e, k_d, k_f, mu_f); returns the force.
+template <typename T>
+__device__ __forceinline__ V3<T> contact_adjoint(V3<T> x, V3<T> v, const T pl[4], const T c[4], V3<T> fb, V3<T>& xb,
+                                                 V3<T>& vb, T gc[4]) {
+    const V3<T> n = mk3(pl[0], pl[1], pl[2]);
+    const T gap = dot(n, x) - pl[3];
+    if (!(gap < T(0))) return zero3<T>();
+    const T C = -gap;
+    const T vn = dot(n, v);
+    const T lam = c[0] * C - c[1] * vn;
+    const V3<T> ut = v - n * vn;
+    const T s = gsqrt(dot(ut, ut));
+    const T sg = lam < T(0) ? T(-1) : T(1);
+    const T lim = c[3] * lam * sg;
+    T lamb = dot(fb, n);
+    V3<T> utb;
+    V3<T> ff;
+    if (c[2] * s <= lim) {
+        ff = ut * (-c[2]);
+        utb = fb * (-c[2]);
+        gc[2] -= dot(ut, fb);
+    } else {
+        const T is = T(1) / s;
+        const V3<T> th = ut * is;
+        ff = th * (-lim);
+        const T limb = -dot(th, fb);
+        const V3<T> thb = fb * (-lim);
+        utb = (thb - th * dot(th, thb)) * is;
+        gc[3] += lam * sg * limb;
+        lamb += c[3] * sg * limb;
+    }
+    vb += utb - n * dot(n, utb);
+    gc[0] += C * lamb;
+    gc[1] -= vn * lamb;
+    xb -= n * (c[0] * lamb);
+    vb -= n * (c[1] * lamb);
+    return n * lam + ff;
+}
+
+// ------------------------------------------------------ block reduction ---
+template <typename T, int N>
+__device__ __forceinline__ void block_sum(T v[N], T out[N]) {
+    __shared__ T red[16][N];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] += __shfl_down(v[k], off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) red[wid][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int k = 0; k < N; ++k) {
+            T s = T(0);
+            for (int w = 0; w < nw; ++w) s += red[w][k];
+            out[k] = s;
+        }
+    }
+}
+
+// ------------------------------------------------------------- kernels ---
+template <typename T>
+__device__ __forceinline__ void load_corners(const T* __restrict__ x, int64_t np, const int32_t* __restrict__ idx,
+                                             int64_t n, int64_t e, int nc, V3<T>* xe, int32_t* id) {
+    for (int c = 0; c < nc; ++c) {
+        id[c] = idx[c * n + e];
+        xe[c] = ld3(x, np, id[c]);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
+                                                   const Tile* __restrict__ tiles) {
+    const Tile tl = tiles[blockIdx.x];
+    const ModelDev<T>& M = md[tl.model];
+    const StepDev<T>& S = sd[tl.model];
+    const int64_t np = M.np;
+    for (int64_t l = threadIdx.x; l < tl.count; l += blockDim.x) {
+        const int64_t e = tl.begin + l;
+        if (tl.kind == TILE_TET) {
+            V3<T> x[4], f[4];
+            int32_t id[4];
+            load_corners(S.x, np, M.tet_idx, M.ne, e, 4, x, id);
+            T D[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) D[k] = M.tet_dinv[k * M.ne + e];
+            const T act = S.act ? S.act[e] : T(0);
+            tet_force(x, D, M.tet_vol[e], S.mu[e], S.lam[e], act, f);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) st_slot(M.slots, M.tet_slot[c * M.ne + e], f[c].x, f[c].y, f[c].z, T(0));
+        } else if (tl.kind == TILE_TRI) {
+            V3<T> x[3], f[3];
+            int32_t id[3];
+            load_corners(S.x, np, M.tri_idx, M.nt, e, 3, x, id);
+            T D[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) D[k] = M.tri_dinv[k * M.nt + e];
+            tri_force(x, D, M.tri_area[e], S.ktri[e], f);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) st_slot(M.slots, M.tri_slot[c * M.nt + e], f[c].x, f[c].y, f[c].z, T(0));
+        } else {
+            V3<T> x[4], f[4];
+            int32_t id[4];
+            load_corners(S.x, np, M.hin_idx, M.nh, e, 4, x, id);
+            hinge_force(x, M.hin_phi0[e], M.bodies[tl.body].kb, f);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) st_slot(M.slots, M.hin_slot[c * M.nh + e], f[c].x, f[c].y, f[c].z, T(0));
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_part_fwd(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
+                                                   const Tile* __restrict__ tiles) {
+    const Tile tl = tiles[blockIdx.x];
+    const ModelDev<T>& M = md[tl.model];
+    const StepDev<T>& S = sd[tl.model];
+    const BodyDev<T>& B = M.bodies[tl.body];
+    const int64_t np = M.np;
+    const T dt = B.dt;
+    T pl[4], cp[4];
+    const bool contact = B.contact_on != 0;
+    if (contact) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            pl[k] = B.plane[k];
+            cp[k] = S.contact[4 * tl.body + k];
+        }
+    }
+    const V3<T> g = mk3(B.g[0], B.g[1], B.g[2]);
+    for (int64_t l = threadIdx.x; l < tl.count; l += blockDim.x) {
+        const int64_t i = tl.begin + l;
+        V3<T> f = zero3<T>();
+        const int32_t s0 = M.csr[i], s1 = M.csr[i + 1];
+        for (int32_t s = s0; s < s1; ++s) {
+            T a, b, c, d;
+            ld_slot(M.slots, s, a, b, c, d);
+            f += mk3(a, b, c);
+        }
+        const V3<T> x = ld3(S.x, np, i), v = ld3(S.v, np, i);
+        if (S.ckx) {
+            st3(S.ckx, np, i, x);
+            st3(S.ckv, np, i, v);
+        }
+        if (contact) f += contact_force(x, v, pl, cp);
+        const T w = inv_mass(M, S, i);
+        const T gate = w > T(0) ? T(1) : T(0);
+        const V3<T> vn = v + (f * w + g * gate) * dt;
+        st3(S.vo, np, i, vn);
+        st3(S.xo, np, i, x + vn * dt);
+    }
+}
+
+// Corner adjoint force of particle p: fbar = dt w (vbar+ + dt xbar+).
+template <typename T>
+__device__ __forceinline__ V3<T> corner_fbar(const ModelDev<T>& M, const StepDev<T>& S, int64_t p, T dt) {
+    const T w = inv_mass(M, S, p);
+    const V3<T> vt = ld3(S.vb, M.np, p) + ld3(S.xb, M.np, p) * dt;
+    return vt * (dt * w);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
+                                                   const Tile* __restrict__ tiles) {
+    const Tile tl = tiles[blockIdx.x];
+    const ModelDev<T>& M = md[tl.model];
+    const StepDev<T>& S = sd[tl.model];
+    const int64_t np = M.np;
+    const T dt = M.bodies[tl.body].dt;
+    for (int64_t l = threadIdx.x; l < tl.count; l += blockDim.x) {
+        const int64_t e = tl.begin + l;
+        if (tl.kind == TILE_TET) {
+            V3<T> x[4], f[4], fb[4], xb[4];
+            int32_t id[4];
+            load_corners(S.x, np, M.tet_idx, M.ne, e, 4, x, id);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) fb[c] = corner_fbar(M, S, id[c], dt);
+            T D[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) D[k] = M.tet_dinv[k * M.ne + e];
+            const T act = S.act ? S.act[e] : T(0);
+            T gmu, glam;
+            tet_adjoint(x, D, M.tet_vol[e], S.mu[e], S.lam[e], act, fb, f, xb, gmu, glam);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                st_slot(M.slots, M.tet_slot[c * M.ne + e], xb[c].x, xb[c].y, xb[c].z, dot(f[c], fb[c]));
+            if (S.g_mu) S.g_mu[e] += gmu;
+            if (S.g_lam) S.g_lam[e] += glam;
+        } else if (tl.kind == TILE_TRI) {
+            V3<T> x[3], f[3], fb[3], xb[3];
+            int32_t id[3];
+            load_corners(S.x, np, M.tri_idx, M.nt, e, 3, x, id);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) fb[c] = corner_fbar(M, S, id[c], dt);
+            T D[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) D[k] = M.tri_dinv[k * M.nt + e];
+            T gk;
+            tri_adjoint(x, D, M.tri_area[e], S.ktri[e], fb, f, xb, gk);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                st_slot(M.slots, M.tri_slot[c * M.nt + e], xb[c].x, xb[c].y, xb[c].z, dot(f[c], fb[c]));
+            if (S.g_ktri) S.g_ktri[e] += gk;
+        } else {
+            V3<T> x[4], f[4], fb[4], xb[4];
+            int32_t id[4];
+            load_corners(S.x, np, M.hin_idx, M.nh, e, 4, x, id);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) fb[c] = corner_fbar(M, S, id[c], dt);
+            hinge_adjoint(x, M.hin_phi0[e], M.bodies[tl.body].kb, fb, f, xb);
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                st_slot(M.slots, M.hin_slot[c * M.nh + e], xb[c].x, xb[c].y, xb[c].z, dot(f[c], fb[c]));
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_part_adj(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
+                                                   const Tile* __restrict__ tiles) {
+    const Tile tl = tiles[blockIdx.x];
+    const ModelDev<T>& M = md[tl.model];
+    const StepDev<T>& S = sd[tl.model];
+    const BodyDev<T>& B = M.bodies[tl.body];
+    const int64_t np = M.np;
+    const T dt = B.dt;
+    T pl[4], cp[4];
+    const bool contact = B.contact_on != 0;
+    if (contact) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            pl[k] = B.plane[k];
+            cp[k] = S.contact[4 * tl.body + k];
+        }
+    }
+    T gc[4] = {T(0), T(0), T(0), T(0)};
+    for (int64_t l = threadIdx.x; l < tl.count; l += blockDim.x) {
+        const int64_t i = tl.begin + l;
+        const V3<T> xbp = ld3(S.xb, np, i);
+        const V3<T> vt = ld3(S.vb, np, i) + xbp * dt;
+        const T w = inv_mass(M, S, i);
+        const V3<T> fb = vt * (dt * w);
+        V3<T> xs = zero3<T>();
+        T ds = T(0);
+        const int32_t s0 = M.csr[i], s1 = M.csr[i + 1];
+        for (int32_t s = s0; s < s1; ++s) {
+            T a, b, c, d;
+            ld_slot(M.slots, s, a, b, c, d);
+            xs += mk3(a, b, c);
+            ds += d;
+        }
+        V3<T> xcb = zero3<T>(), vcb = zero3<T>();
+        if (contact) {
+            const V3<T> x = ld3(S.x, np, i), v = ld3(S.v, np, i);
+            const V3<T> fc = contact_adjoint(x, v, pl, cp, fb, xcb, vcb, gc);
+            ds += dot(fc, fb);
+        }
+        st3(S.xbo, np, i, xbp + xs + xcb);
+        st3(S.vbo, np, i, vt + vcb);
+        if (S.g_mass && w > T(0)) S.g_mass[i] += -w * ds;  // dm = -w^2 dw, dw = dt f.vt = f.fbar / w
+    }
+    if (contact && S.g_contact) {
+        T tot[4];
+        block_sum<T, 4>(gc, tot);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) M.cpart[4 * tl.id + k] += tot[k];
+    }
+}
+
+template <typename T>
+__global__ void k_contact_reduce(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd) {
+    const ModelDev<T>& M = md[0];
+    const StepDev<T>& S = sd[0];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * M.n_bodies || !S.g_contact) return;
+    const int b = t >> 2, k = t & 3;
+    const BodyDev<T>& B = M.bodies[b];
+    if (!B.contact_on) return;
+    T s = T(0);
+    for (int r = B.pt0; r < B.pt1; ++r) s += M.cpart[4 * r + k];
+    S.g_contact[t] += s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) k_loss_part(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
+                                                    const Tile* __restrict__ tiles) {
+    const Tile tl = tiles[blockIdx.x];
+    const ModelDev<T>& M = md[tl.model];
+    const StepDev<T>& S = sd[tl.model];
+    const BodyDev<T>& B = M.bodies[tl.body];
+    const int64_t np = M.np;
+    const T scale = T(2) / T(B.np);
+    T acc[1] = {T(0)};
+    for (int64_t l = threadIdx.x; l < tl.count; l += blockDim.x) {
+        const int64_t i = tl.begin + l;
+        const V3<T> d = ld3(S.x, np, i) - ld3(S.target, np, i);
+        acc[0] += dot(d, d);
+        if (S.xbo) st3(S.xbo, np, i, d * scale);
+        if (S.vbo) st3(S.vbo, np, i, zero3<T>());
+    }
+    T tot[1];
+    block_sum<T, 1>(acc, tot);
+    if (threadIdx.x == 0) M.lpart[tl.id] = tot[0];
+}
+
+template <typename T>
+__global__ void k_loss_reduce(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd) {
+    const ModelDev<T>& M = md[0];
+    const StepDev<T>& S = sd[0];
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= M.n_bodies) return;
+    const BodyDev<T>& B = M.bodies[b];
+    T s = T(0);
+    for (int r = B.pt0; r < B.pt1; ++r) s += M.lpart[r];
+    S.loss[b] = s / T(B.np);
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, int64_t n, T value) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+int check_launch() {
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? 0 : (int)e;
+}
+
+}  // namespace
+
+template <typename T>
+int launch_elem_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int,
+                    void* stream) {
+    if (ntiles <= 0) return 0;
+    hipLaunchKernelGGL(k_elem_fwd<T>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
+    return check_launch();
+}
+template <typename T>
+int launch_part_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int,
+                    void* stream) {
+    if (ntiles <= 0) return 0;
+    hipLaunchKernelGGL(k_part_fwd<T>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
+    return check_launch();
+}
+template <typename T>
+int launch_elem_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int,
+                    void* stream) {
+    if (ntiles <= 0) return 0;
+    hipLaunchKernelGGL(k_elem_adj<T>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
+    return check_launch();
+}
+template <typename T>
+int launch_part_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int,
+                    void* stream) {
+    if (ntiles <= 0) return 0;
+    hipLaunchKernelGGL(k_part_adj<T>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
+    return check_launch();
+}
+template <typename T>
+int launch_fill(T* p, int64_t n, T value, void* stream) {
+    if (n <= 0) return 0;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, p, n, value);
+    return check_launch();
+}
+template <typename T>
+int launch_contact_reduce(const ModelDev<T>* md, const StepDev<T>* sd, int n_bodies, void* stream) {
+    const int n = 4 * n_bodies;
+    hipLaunchKernelGGL(k_contact_reduce<T>, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, md, sd);
+    return check_launch();
+}
+template <typename T>
+int launch_loss(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int,
+                int n_bodies, void* stream) {
+    hipLaunchKernelGGL(k_loss_part<T>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
+    int rc = check_launch();
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_loss_reduce<T>, dim3((n_bodies + 255) / 256), dim3(256), 0, (hipStream_t)stream, md, sd);
+    return check_launch();
+}
+
+#define GSIM_INSTANTIATE(T)                                                                                          \
+    template int launch_elem_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
+    template int launch_part_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
+    template int launch_elem_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
+    template int launch_part_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
+    template int launch_fill<T>(T*, int64_t, T, void*);                                                             \
+    template int launch_contact_reduce<T>(const ModelDev<T>*, const StepDev<T>*, int, void*);                       \
+    template int launch_loss<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, int, void*);
+
+GSIM_INSTANTIATE(float)
+GSIM_INSTANTIATE(double)
+
+}  // namespace gsim

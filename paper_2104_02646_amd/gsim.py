@@ -1,0 +1,326 @@
+"""Python binding of libgsim (ctypes): argument marshalling only.
+
+Every step of the simulation runs in the HIP kernels of ``libgsim.so``; this
+module packs model descriptions, passes device pointers of torch tensors and the
+current HIP stream, and turns status codes into exceptions.  Names follow the
+C-ABI in ``include/gsim.h`` (``gsim_plan_create`` -> :class:`Plan`,
+``gsim_rollout`` -> :meth:`Model.rollout`, ...).
+
+Layouts: device states are SoA ``[3, n_particles]`` tensors; the helpers
+:func:`soa` / :func:`aos` convert from / to numpy ``[n, 3]`` arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgsim.so")
+
+GSIM_OK, GSIM_E_INVALID, GSIM_E_TOPOLOGY, GSIM_E_DEGENERATE = 0, -1, -2, -3
+GSIM_E_WORKSPACE, GSIM_E_HIP, GSIM_E_NONFINITE, GSIM_E_UNSUPPORTED = -4, -5, -6, -7
+EXEC_PLAIN, EXEC_GRAPH, EXEC_FUSED = 0, 1, 2
+
+ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan_destroy", "gsim_plan_sizes",
+               "gsim_plan_counts", "gsim_model_init", "gsim_model_destroy", "gsim_model_set_exec",
+               "gsim_model_get_exec", "gsim_step", "gsim_step_backward", "gsim_rollout", "gsim_rollout_backward",
+               "gsim_loss_mse")
+
+
+class GsimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("gsim error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _Desc(C.Structure):
+    _fields_ = [("dtype", C.c_int), ("n_bodies", C.c_int),
+                ("n_particles", C.c_int64), ("n_tets", C.c_int64), ("n_tris", C.c_int64), ("n_hinges", C.c_int64),
+                ("body_particle_off", C.c_void_p), ("body_tet_off", C.c_void_p), ("body_tri_off", C.c_void_p),
+                ("body_hinge_off", C.c_void_p), ("rest_x", C.c_void_p), ("tet_idx", C.c_void_p),
+                ("tri_idx", C.c_void_p), ("hinge_idx", C.c_void_p), ("pinned", C.c_void_p),
+                ("gravity", C.c_void_p), ("dt", C.c_void_p), ("ground", C.c_void_p), ("contact_on", C.c_void_p),
+                ("k_bend", C.c_void_p)]
+
+
+class _State(C.Structure):
+    _fields_ = [("x", C.c_void_p), ("v", C.c_void_p)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("mu", C.c_void_p), ("lam", C.c_void_p), ("act", C.c_void_p), ("k_tri", C.c_void_p),
+                ("mass", C.c_void_p), ("contact", C.c_void_p)]
+
+
+class _Grads(C.Structure):
+    _fields_ = [("mu", C.c_void_p), ("lam", C.c_void_p), ("k_tri", C.c_void_p), ("mass", C.c_void_p),
+                ("contact", C.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Loads libgsim.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libgsim.so is not built: run `python -m paper_2104_02646_amd.build`")
+        lib = C.CDLL(LIB_PATH)
+        lib.gsim_last_error.restype = C.c_char_p
+        vp, ip = C.c_void_p, C.c_int
+        lib.gsim_plan_create.argtypes = [C.POINTER(_Desc), C.POINTER(vp)]
+        lib.gsim_plan_destroy.argtypes = [vp]
+        lib.gsim_plan_sizes.argtypes = [vp, ip, ip, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+        lib.gsim_plan_counts.argtypes = [vp] + [C.POINTER(C.c_int64)] * 4 + [C.POINTER(C.c_int)]
+        lib.gsim_model_init.argtypes = [vp, ip, ip, vp, C.c_size_t, vp, C.POINTER(vp)]
+        lib.gsim_model_destroy.argtypes = [vp]
+        lib.gsim_model_set_exec.argtypes = [vp, ip, ip, ip]
+        lib.gsim_model_get_exec.argtypes = [vp, C.POINTER(ip), C.POINTER(ip), C.POINTER(ip)]
+        lib.gsim_step.argtypes = [vp, C.POINTER(_Params), _State, _State, ip, vp]
+        lib.gsim_step_backward.argtypes = [vp, C.POINTER(_Params), _State, _State, _State, C.POINTER(_Grads), vp]
+        lib.gsim_rollout.argtypes = [vp, C.POINTER(_Params), _State, ip, vp, _State, vp]
+        lib.gsim_rollout_backward.argtypes = [vp, C.POINTER(_Params), vp, ip, vp, _State, _State, C.POINTER(_Grads), vp]
+        lib.gsim_loss_mse.argtypes = [vp, _State, vp, vp, _State, vp]
+        _lib = lib
+    return _lib
+
+
+def _check(rc):
+    if rc != GSIM_OK:
+        raise GsimError(rc, load().gsim_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def soa(a, dtype=torch.float32, device="cuda"):
+    """numpy [n, 3] -> device SoA tensor [3, n]."""
+    return torch.as_tensor(np.ascontiguousarray(np.asarray(a, np.float64).T)).to(device=device, dtype=dtype).contiguous()
+
+
+def aos(t):
+    """device SoA tensor [3, n] -> numpy float64 [n, 3]."""
+    return t.detach().double().cpu().numpy().T.copy()
+
+
+# ----------------------------------------------------------------------------------
+# Plan / Model
+# ----------------------------------------------------------------------------------
+
+@dataclass
+class Packed:
+    """Host arrays of a packed multi-body description."""
+    n_bodies: int
+    poff: np.ndarray
+    eoff: np.ndarray
+    toff: np.ndarray
+    hoff: np.ndarray
+    X: np.ndarray
+    tets: np.ndarray
+    tris: np.ndarray
+    hinges: np.ndarray
+    pinned: np.ndarray
+    gravity: np.ndarray
+    dt: np.ndarray
+    ground: np.ndarray
+    contact_on: np.ndarray
+    k_bend: np.ndarray
+
+
+def pack(bodies) -> Packed:
+    """Concatenates bodies (``workloads.Body``-like objects) into one model description;
+    element indices become model-global."""
+    poff = np.zeros(len(bodies) + 1, np.int64)
+    eoff, toff, hoff = poff.copy(), poff.copy(), poff.copy()
+    X, tets, tris, hinges, pinned = [], [], [], [], []
+    for b, body in enumerate(bodies):
+        p0 = poff[b]
+        poff[b + 1] = p0 + body.np
+        eoff[b + 1] = eoff[b] + body.ne
+        toff[b + 1] = toff[b] + body.nt
+        hoff[b + 1] = hoff[b] + body.nh
+        X.append(np.asarray(body.X, np.float64))
+        tets.append(np.asarray(body.tets, np.int64) + p0)
+        tris.append(np.asarray(body.tris, np.int64) + p0)
+        hinges.append(np.asarray(body.hinges, np.int64) + p0)
+        pinned.append(np.asarray(body.pinned, np.uint8))
+    cat = lambda a, shape, dt: np.ascontiguousarray(np.concatenate(a).astype(dt).reshape(shape))
+    return Packed(len(bodies), poff, eoff, toff, hoff, cat(X, (-1, 3), np.float64), cat(tets, (-1, 4), np.int32),
+                  cat(tris, (-1, 3), np.int32), cat(hinges, (-1, 4), np.int32), cat(pinned, (-1,), np.uint8),
+                  np.ascontiguousarray([b.gravity for b in bodies], np.float64),
+                  np.ascontiguousarray([b.dt for b in bodies], np.float64),
+                  np.ascontiguousarray([b.plane for b in bodies], np.float64),
+                  np.ascontiguousarray([1 if b.ground else 0 for b in bodies], np.uint8),
+                  np.ascontiguousarray([b.kb for b in bodies], np.float64))
+
+
+class Plan:
+    """``gsim_plan_create``: validated, oriented, precomputed host plan."""
+
+    def __init__(self, bodies, dtype=torch.float32):
+        lib = load()
+        self.bodies = list(bodies)
+        self.dtype = dtype
+        pk = pack(self.bodies)
+        self.packed = pk
+        d = _Desc()
+        d.dtype = 64 if dtype == torch.float64 else 32
+        d.n_bodies = pk.n_bodies
+        d.n_particles, d.n_tets, d.n_tris, d.n_hinges = len(pk.X), len(pk.tets), len(pk.tris), len(pk.hinges)
+        a = lambda arr: arr.ctypes.data if arr is not None and arr.size else None
+        d.body_particle_off = a(pk.poff)
+        d.body_tet_off = a(pk.eoff) if len(pk.tets) else None
+        d.body_tri_off = a(pk.toff) if len(pk.tris) else None
+        d.body_hinge_off = a(pk.hoff) if len(pk.hinges) else None
+        d.rest_x, d.tet_idx, d.tri_idx, d.hinge_idx = a(pk.X), a(pk.tets), a(pk.tris), a(pk.hinges)
+        d.pinned, d.gravity, d.dt, d.ground = a(pk.pinned), a(pk.gravity), a(pk.dt), a(pk.ground)
+        d.contact_on, d.k_bend = a(pk.contact_on), a(pk.k_bend)
+        h = C.c_void_p()
+        _check(lib.gsim_plan_create(C.byref(d), C.byref(h)))
+        self._h = h
+        self.np, self.ne, self.nt, self.nh, self.nb = d.n_particles, d.n_tets, d.n_tris, d.n_hinges, d.n_bodies
+
+    def sizes(self, max_steps, ckpt_every):
+        w, c, s = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        _check(load().gsim_plan_sizes(self._h, int(max_steps), int(ckpt_every), C.byref(w), C.byref(c), C.byref(s)))
+        return w.value, c.value, s.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.gsim_plan_destroy(h)
+            self._h = None
+
+
+class Model:
+    """``gsim_model_init`` over torch-allocated buffers, plus the per-call entry points."""
+
+    def __init__(self, bodies, dtype=torch.float32, max_steps=100, ckpt_every=10, device="cuda", stream=None):
+        self.plan = Plan(bodies, dtype)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.max_steps, self.ckpt_every = int(max_steps), int(ckpt_every)
+        ws, ck, seg = self.plan.sizes(max_steps, ckpt_every)
+        self.bytes = {"workspace": ws, "ckpt": ck, "segment": seg}
+        self.workspace = torch.empty(ws + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws_ptr = self.workspace.data_ptr() + off
+        esz = 8 if dtype == torch.float64 else 4
+        self.ckpt = torch.empty(max(ck // esz, 1), dtype=dtype, device=self.device)
+        self.segment = torch.empty(max(seg // esz, 1), dtype=dtype, device=self.device)
+        h = C.c_void_p()
+        _check(load().gsim_model_init(self.plan._h, self.max_steps, self.ckpt_every, C.c_void_p(self._ws_ptr),
+                                      ws, _stream(stream), C.byref(h)))
+        self._h = h
+        p = self.plan
+        self.np, self.ne, self.nt, self.nh, self.nb = p.np, p.ne, p.nt, p.nh, p.nb
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.gsim_model_destroy(h)
+            self._h = None
+
+    # -- execution settings ---------------------------------------------------
+    def set_exec(self, exec_mode=None, block=0, items=0):
+        cur = self.get_exec()
+        _check(load().gsim_model_set_exec(self._h, cur[0] if exec_mode is None else int(exec_mode), int(block), int(items)))
+
+    def get_exec(self):
+        e, b, i = C.c_int(), C.c_int(), C.c_int()
+        _check(load().gsim_model_get_exec(self._h, C.byref(e), C.byref(b), C.byref(i)))
+        return e.value, b.value, i.value
+
+    # -- tensors ----------------------------------------------------------------
+    def empty_state(self):
+        return (torch.empty(3, self.np, dtype=self.dtype, device=self.device),
+                torch.empty(3, self.np, dtype=self.dtype, device=self.device))
+
+    def params_from_bodies(self, bodies=None):
+        """Device parameter tensors: mu, lam [ne], ktri [nt], mass [np], contact [nb, 4]."""
+        bodies = self.plan.bodies if bodies is None else bodies
+        t = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64)).to(self.device, self.dtype)
+        p = {"mass": t(np.concatenate([b.mass for b in bodies])),
+             "contact": t([[b.ke, b.kd, b.kf, b.muf] for b in bodies])}
+        if self.ne:
+            p["mu"] = t(np.concatenate([b.mu for b in bodies if b.ne]))
+            p["lam"] = t(np.concatenate([b.lam for b in bodies if b.ne]))
+        if self.nt:
+            p["ktri"] = t(np.concatenate([b.ktri for b in bodies if b.nt]))
+        return p
+
+    def zero_grads(self, which=("mu", "lam", "ktri", "mass", "contact")):
+        n = {"mu": self.ne, "lam": self.ne, "ktri": self.nt, "mass": self.np, "contact": 4 * self.nb}
+        g = {}
+        for k in which:
+            if n[k]:
+                g[k] = torch.zeros(n[k], dtype=self.dtype, device=self.device)
+        if "contact" in g:
+            g["contact"] = g["contact"].view(self.nb, 4)
+        return g
+
+    @staticmethod
+    def _params(p):
+        s = _Params()
+        s.mu, s.lam, s.act = _ptr(p.get("mu")), _ptr(p.get("lam")), _ptr(p.get("act"))
+        s.k_tri, s.mass, s.contact = _ptr(p.get("ktri")), _ptr(p.get("mass")), _ptr(p.get("contact"))
+        return s
+
+    @staticmethod
+    def _grads(g):
+        s = _Grads()
+        if g:
+            s.mu, s.lam, s.k_tri = _ptr(g.get("mu")), _ptr(g.get("lam")), _ptr(g.get("ktri"))
+            s.mass, s.contact = _ptr(g.get("mass")), _ptr(g.get("contact"))
+        return s
+
+    @staticmethod
+    def _state(x, v):
+        s = _State()
+        s.x, s.v = _ptr(x), _ptr(v)
+        return s
+
+    # -- entry points -------------------------------------------------------------
+    def step(self, params, x, v, n_steps=1, out=None, stream=None):
+        xo, vo = self.empty_state() if out is None else out
+        _check(load().gsim_step(self._h, C.byref(self._params(params)), self._state(x, v), self._state(xo, vo),
+                                int(n_steps), _stream(stream)))
+        return xo, vo
+
+    def step_backward(self, params, x, v, xb_plus, vb_plus, grads=None, stream=None):
+        xbm, vbm = self.empty_state()
+        _check(load().gsim_step_backward(self._h, C.byref(self._params(params)), self._state(x, v),
+                                         self._state(xb_plus, vb_plus), self._state(xbm, vbm),
+                                         C.byref(self._grads(grads)), _stream(stream)))
+        return xbm, vbm
+
+    def rollout(self, params, x0, v0, n_steps, checkpoint=True, out=None, stream=None):
+        xo, vo = self.empty_state() if out is None else out
+        _check(load().gsim_rollout(self._h, C.byref(self._params(params)), self._state(x0, v0), int(n_steps),
+                                   _ptr(self.ckpt) if checkpoint else None, self._state(xo, vo), _stream(stream)))
+        return xo, vo
+
+    def rollout_backward(self, params, n_steps, xb_final, vb_final, grads=None, out=None, stream=None):
+        xbi, vbi = self.empty_state() if out is None else out
+        _check(load().gsim_rollout_backward(self._h, C.byref(self._params(params)), _ptr(self.ckpt), int(n_steps),
+                                            _ptr(self.segment), self._state(xb_final, vb_final), self._state(xbi, vbi),
+                                            C.byref(self._grads(grads)), _stream(stream)))
+        return xbi, vbi
+
+    def loss_mse(self, x, target, seed=True, stream=None):
+        loss = torch.empty(self.nb, dtype=self.dtype, device=self.device)
+        xb, vb = self.empty_state() if seed else (None, None)
+        _check(load().gsim_loss_mse(self._h, self._state(x, None), _ptr(target), _ptr(loss), self._state(xb, vb),
+                                    _stream(stream)))
+        return loss, xb, vb
