@@ -1,0 +1,261 @@
+"""Benchmark: batched forward + checkpointed adjoint of the differentiable step.
+
+Workload (default): 256 independent tet bodies, tet counts log-uniform in
+[500, 20000] (box or grid-in-sphere voxelisations), FP32, per-body materials
+mu, lambda ~ U(1e4, 1e5), mass ~ U(0.5, 1.5), ground contact k_e = 1e4,
+mu_f = 0.5; 100 steps of dt = 1/600 forward with a checkpoint every 10 steps,
+then the checkpointed adjoint (segment recompute + adjoint steps) back to
+gradients w.r.t. mu, lambda, mass and the contact parameters.  All bodies are
+stepped together: two launches per simulation step cover every body, and the
+whole launch sequence is replayed from a captured hipGraph.
+
+One bench step = one system-identification gradient evaluation over the batch:
+rollout (with checkpoints) + loss + zeroing of gradients + rollout_backward.
+value = sum_b Ne_b * T / (seconds per bench step), element-steps/s fwd+adjoint.
+
+Also reported: forward-only rate; the plain one-body-per-launch path (each body
+its own model, plain launches, no graph); per-kernel durations from HIP events
+(plain execution, one extra bench step); the roofline of the dominant kernel;
+the FP64 oracle on a bounded sample of the same bodies on the host CPU, and the
+FP32 gradient error of those bodies against the oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "element-steps/s fwd+adjoint (FP32, grad err ≤1e-3); served p50/p99 query latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes(kernel, ne, nt, nh, np_, nslot, K):
+    """Compulsory bytes one launch of `kernel` moves (FP32 / int32), each array touched
+    once: element records, gathered particle data (once per particle), gather slots,
+    outputs, gradient read-modify-writes."""
+    if kernel == "element_fwd":
+        return 144 * ne + 96 * nt + 100 * nh + 12 * np_
+    if kernel == "particle_fwd":
+        return 57 * np_ + 16 * nslot + 24 * np_ // K
+    if kernel == "element_adj":
+        return 160 * ne + 104 * nt + 100 * nh + 41 * np_
+    if kernel == "particle_adj":
+        return 89 * np_ + 16 * nslot
+    raise ValueError(kernel)
+
+
+def step_algorithmic_bytes(ne, np_, K):
+    """Whole-step accounting: B_f = 64 Ne + 52 Np per forward step, B_a = 64 Ne + 84 Np
+    + 16 Ne/K per adjoint step; checkpointed fwd+adj = 2 B_f + B_a per step."""
+    bf = 64 * ne + 52 * np_
+    ba = 64 * ne + 84 * np_ + 16 * ne / K
+    return bf, ba
+
+
+def cpu_baseline(bodies, targets, T, budget_tets):
+    """FP64 oracle fwd + loss + adjoint on the first bodies until budget_tets tets."""
+    import oracle.oracle as orc
+    orc.build(force=False)
+    sample, tot = [], 0
+    for i, b in enumerate(bodies):
+        if tot >= budget_tets:
+            break
+        sample.append(i)
+        tot += b.ne
+    out = {}
+    t0 = time.perf_counter()
+    for i in sample:
+        b = bodies[i]
+        o = orc.Oracle(b.X, tets=b.tets, pinned=b.pinned, gravity=b.gravity, ground=True, plane=b.plane, dt=b.dt)
+        L, g, xs, vs = o.loss_and_grad(b.params(), b.x0, b.v0, T, targets[i], want=("mu", "lam", "mass"))
+        out[i] = (L, g, xs[-1])
+    dt = time.perf_counter() - t0
+    return sample, tot, dt, out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--bodies", type=int, default=256)
+    ap.add_argument("--sim-steps", type=int, default=100)
+    ap.add_argument("--ckpt-every", type=int, default=10)
+    ap.add_argument("--exec", choices=("graph", "plain"), default="graph")
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--items", type=int, default=1)
+    ap.add_argument("--cpu-tets", type=int, default=15000, help="oracle sample size (tets)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device-to-device tensor copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (bodies would shard "
+              "across GPUs with no exchange); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2104_02646_amd import gsim, workloads as W
+
+    if args.calibrate_copy:
+        n = 1 << 28  # 2^28 floats = 1 GiB
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n,
+                          "copies": 3}), flush=True)
+        return
+
+    T, K = args.sim_steps, args.ckpt_every
+    t_gen = time.perf_counter()
+    bodies = [b.round_to(np.float32) for b in W.batch_bodies(20, args.bodies)]
+    targets = [W.synthetic_target(b, 7000 + i).astype(np.float32).astype(np.float64) for i, b in enumerate(bodies)]
+    ne = sum(b.ne for b in bodies)
+    np_ = sum(b.np for b in bodies)
+    t_gen = time.perf_counter() - t_gen
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream()
+    t_plan = time.perf_counter()
+    with torch.cuda.stream(stream):
+        model = gsim.Model(bodies, torch.float32, max_steps=T, ckpt_every=K, device=dev)
+        model.set_exec(gsim.EXEC_GRAPH if args.exec == "graph" else gsim.EXEC_PLAIN, args.block, args.items)
+        p = model.params_from_bodies()
+        x0 = gsim.soa(np.concatenate([b.x0 for b in bodies]))
+        v0 = gsim.soa(np.concatenate([b.v0 for b in bodies]))
+        tgt = gsim.soa(np.concatenate(targets))
+        xT, vT = model.empty_state()
+        xb0, vb0 = model.empty_state()
+        g = model.zero_grads(("mu", "lam", "mass", "contact"))
+    stream.synchronize()
+    t_plan = time.perf_counter() - t_plan
+    nslot = 4 * ne
+
+    def bench_step():
+        model.rollout(p, x0, v0, T, out=(xT, vT), stream=stream)
+        loss, xb, vb = model.loss_mse(xT, tgt, stream=stream)
+        for t in g.values():
+            t.zero_()
+        model.rollout_backward(p, T, xb, vb, g, out=(xb0, vb0), stream=stream)
+        return loss
+
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            bench_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            loss = bench_step()
+        torch.cuda.synchronize()
+        t_total = time.perf_counter() - t0
+        sec = t_total / args.steps
+        # forward-only rate (rollout with checkpoints)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            model.rollout(p, x0, v0, T, out=(xT, vT), stream=stream)
+        torch.cuda.synchronize()
+        sec_fwd = (time.perf_counter() - t0) / args.steps
+        # per-kernel durations: one more bench step in plain execution with event timing
+        model.set_exec(gsim.EXEC_PLAIN)
+        model.set_timing()
+        bench_step()
+        torch.cuda.synchronize()
+        timing = model.read_timing()
+        model.set_timing(())
+        g_np = {k: t.detach().double().cpu().numpy() for k, t in g.items()}
+        xT_np = gsim.aos(xT)
+
+    value = ne * T / sec
+    kern = {}
+    for k, (n, ms) in timing.items():
+        if n:
+            avg = ms / n
+            by = kernel_bytes(k, ne, 0, 0, np_, nslot, K)
+            kern[k] = {"launches": n, "avg_us": avg * 1e3, "total_ms": ms, "bytes_per_launch": by,
+                       "GBps": by / (avg * 1e-3) / 1e9}
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    d = kern[dom]
+    bf, ba = step_algorithmic_bytes(ne, np_, K)
+    step_bw = (2 * bf + ba) * T / sec / 1e9
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "element-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batch of %d tet bodies (log-uniform 500-20000 tets), %d steps fwd + "
+                               "checkpointed adjoint (every %d), ground contact + friction" % (len(bodies), T, K),
+                   "bodies": len(bodies), "tets": ne, "particles": np_, "sim_steps": T, "ckpt_every": K,
+                   "exec": args.exec, "block": args.block, "items": args.items},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": d["avg_us"], "bytes_per_launch": d["bytes_per_launch"]},
+        "kernels": kern,
+        "forward_elem_steps_per_s": ne * T / sec_fwd,
+        "step_algorithmic": {"GBps": step_bw, "frac": step_bw / HBM_PEAK_GBS,
+                             "bytes_per_elem_step": (2 * bf + ba) / ne},
+        "setup_s": {"generate": t_gen, "plan_and_upload": t_plan},
+    }
+
+    # plain one-body-per-launch path on the same GPU
+    if not args.no_plain:
+        models = []
+        for i, b in enumerate(bodies):
+            m1 = gsim.Model([b], torch.float32, max_steps=T, ckpt_every=K, device=dev)
+            p1 = m1.params_from_bodies()
+            models.append((m1, p1, gsim.soa(b.x0), gsim.soa(b.v0), gsim.soa(targets[i]), m1.zero_grads(("mu", "lam", "mass", "contact"))))
+
+        def plain_step():
+            for m1, p1, a0, b0, t1, g1 in models:
+                xa, va = m1.rollout(p1, a0, b0, T)
+                l1, xb1, vb1 = m1.loss_mse(xa, t1)
+                for t in g1.values():
+                    t.zero_()
+                m1.rollout_backward(p1, T, xb1, vb1, g1)
+        plain_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain_step()
+        torch.cuda.synchronize()
+        sp = time.perf_counter() - t0
+        result["plain_one_body_per_launch"] = {"value": ne * T / sp, "ms_per_step": sp * 1e3,
+                                               "speedup_of_batched": sp / sec}
+        del models
+
+    # FP64 oracle on a bounded sample, and the FP32 gradient error of those bodies
+    if not args.no_cpu:
+        sample, tot, dt_cpu, ref = cpu_baseline(bodies, targets, T, args.cpu_tets)
+        errs = {"x": 0.0, "mu": 0.0, "lam": 0.0, "mass": 0.0, "muf": 0.0}
+        poffs = np.cumsum([0] + [b.np for b in bodies])
+        eoffs = np.cumsum([0] + [b.ne for b in bodies])
+        rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        for i in sample:
+            L, gr, x_ref = ref[i]
+            sl = slice(poffs[i], poffs[i + 1])
+            se = slice(eoffs[i], eoffs[i + 1])
+            errs["x"] = max(errs["x"], rel(xT_np[sl], x_ref))
+            errs["mu"] = max(errs["mu"], rel(g_np["mu"][se], gr["mu"]))
+            errs["lam"] = max(errs["lam"], rel(g_np["lam"][se], gr["lam"]))
+            errs["mass"] = max(errs["mass"], rel(g_np["mass"][sl], gr["mass"]))
+            if gr["contact"][3] != 0:
+                errs["muf"] = max(errs["muf"], abs(g_np["contact"][i, 3] - gr["contact"][3]) / abs(gr["contact"][3]))
+        result["cpu_baseline"] = {"value": tot * T / dt_cpu, "unit": "element-steps/s", "cores": 1, "kind": "oracle",
+                                  "sample": "bodies 0..%d of the batch (%d tets), %d steps fwd + loss + adjoint, "
+                                            "FP64, single thread" % (sample[-1], tot, T)}
+        result["parity_sample"] = {"bodies": len(sample), "max_rel_err": errs}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -138,6 +138,15 @@ int gsim_model_destroy(gsim_model* model);
 int gsim_model_set_exec(gsim_model* model, int exec, int block, int items);
 int gsim_model_get_exec(const gsim_model* model, int* exec, int* block, int* items);
 
+/* Kernel timing for measurement: with bit k of `mask` set, every launch of
+ * kernel k is bracketed by HIP events on its stream (k: 0 element pass,
+ * 1 particle pass, 2 element adjoint pass, 3 particle adjoint pass).  Plain
+ * execution only (GSIM_E_UNSUPPORTED under GSIM_EXEC_GRAPH).
+ * gsim_model_read_timing waits for the recorded events and returns (then
+ * clears) kernel k's launch count and summed duration in milliseconds. */
+int gsim_model_set_timing(gsim_model* model, int mask);
+int gsim_model_read_timing(gsim_model* model, int kernel, int64_t* launches, double* total_ms);
+
 /* ------------------------------------------------------------------------ */
 /* STATE, PARAMETERS, GRADIENTS (device pointers, caller-owned)              */
 /* ------------------------------------------------------------------------ */
@@ -200,6 +209,69 @@ int gsim_rollout_backward(gsim_model* model, const gsim_params* params, const vo
  * [3][n_particles]; d_loss is [n_bodies]. */
 int gsim_loss_mse(gsim_model* model, gsim_state s, const void* d_target, void* d_loss, gsim_state adj_out,
                   void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* SERVING ENGINE: continuous batching of rollout-gradient queries           */
+/* ------------------------------------------------------------------------ */
+/* A query is one FP32 body (n_bodies == 1) with parameters, start state and
+ * target; its answer is the loss of its final positions (gsim_loss_mse) and
+ * the gradients of that loss, exactly as gsim_rollout + gsim_loss_mse +
+ * gsim_rollout_backward would compute them on a model of its own (bit for bit:
+ * a query's arithmetic does not depend on the other queries in flight).
+ *
+ * The engine carves every admitted query's device buffers out of one
+ * caller-owned pool (first fit), admits queued queries in FIFO order as pool
+ * space and live slots free up, and advances all live queries by one
+ * micro-step per gsim_engine_tick, running the micro-steps of every live query
+ * in one element pass and one particle pass (forward and adjoint). */
+typedef struct gsim_engine gsim_engine;
+
+typedef struct {
+    const gsim_model_desc* desc; /* one body, dtype GSIM_F32; read during submit */
+    int n_steps;                 /* rollout length T */
+    int ckpt_every;              /* checkpoint interval K */
+    /* host inputs, copied during submit */
+    const float* mu;             /* [n_tets] */
+    const float* lam;            /* [n_tets] */
+    const float* k_tri;          /* [n_tris] */
+    const float* mass;           /* [n_particles] */
+    const float* contact;        /* [4] = k_e, k_d, k_f, mu_f */
+    const float* x0;             /* [3][n_particles] SoA */
+    const float* v0;             /* [3][n_particles] */
+    const float* target;         /* [3][n_particles] */
+    /* host outputs, written when the query completes (NULL = not wanted);
+     * they must stay valid until gsim_engine_poll reports the query */
+    float* out_mu;
+    float* out_lam;
+    float* out_k_tri;
+    float* out_mass;
+    float* out_contact;          /* [4] */
+} gsim_query;
+
+typedef struct {
+    int64_t id;
+    float loss;
+    double t_submit, t_admit, t_done; /* host steady-clock seconds */
+} gsim_result;
+
+/* d_pool: caller-owned device memory (256-byte aligned); max_live: live query
+ * slots; max_tiles: capacity of one tick's tile lists (sum over live queries of
+ * their element and particle tiles at 256 items per tile). */
+int gsim_engine_create(void* d_pool, size_t pool_bytes, int max_live, int64_t max_tiles, void* stream,
+                       gsim_engine** out);
+int gsim_engine_destroy(gsim_engine* engine);
+/* Exact device bytes a query occupies while live (its admission footprint). */
+int gsim_engine_query_bytes(const gsim_query* query, size_t* bytes);
+/* Validates and plans the query (host), copies its inputs, queues it.
+ * GSIM_E_WORKSPACE if it can never fit in the pool. */
+int gsim_engine_submit(gsim_engine* engine, const gsim_query* query, int64_t* id);
+/* Admits what fits, then runs one micro-step of every live query.  Completed
+ * queries have their outputs copied (the call waits for that copy). */
+int gsim_engine_tick(gsim_engine* engine, int* n_live, int* n_queued);
+/* Completed queries since the last poll (at most max). */
+int gsim_engine_poll(gsim_engine* engine, gsim_result* out, int max, int* n);
+int gsim_engine_stats(const gsim_engine* engine, int64_t* ticks, int64_t* admitted, int64_t* completed,
+                      double* mean_live, size_t* pool_free);
 
 #ifdef __cplusplus
 }

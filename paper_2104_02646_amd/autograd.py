@@ -1,0 +1,49 @@
+"""Differentiable rollout as a torch.autograd.Function.
+
+The paper wraps each simulation kernel as a PyTorch autograd operation and lets
+the tape carry the program flow (App. A; App. C).  Here the whole T-step rollout
+is one operation: the forward runs ``gsim_rollout`` (storing a checkpoint every K
+steps in a buffer owned by this call), the backward runs the checkpointed
+adjoint ``gsim_rollout_backward`` (recompute each K-step segment, then its
+adjoint steps), so a long rollout's gradient needs only ceil(T/K) saved states.
+Both passes are HIP kernels in libgsim; this module only moves tensors.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import gsim
+
+_PARAM_KEYS = ("mu", "lam", "ktri", "mass", "contact")
+
+
+class SimRollout(torch.autograd.Function):
+    """(x0, v0, mu, lam, ktri, mass, contact) -> (xT, vT) after n_steps steps.
+
+    States are SoA [3, n_particles]; contact is [n_bodies, 4] = (k_e, k_d, k_f, mu_f).
+    Pass None for parameters the model does not have (mu/lam without tets, ktri
+    without triangles)."""
+
+    @staticmethod
+    def forward(ctx, model, n_steps, x0, v0, mu, lam, ktri, mass, contact):
+        params = {k: v.detach() for k, v in zip(_PARAM_KEYS, (mu, lam, ktri, mass, contact)) if v is not None}
+        ckpt = model.new_checkpoints()
+        xT, vT = model.rollout(params, x0.detach().contiguous(), v0.detach().contiguous(), int(n_steps), ckpt=ckpt)
+        ctx.model, ctx.n_steps, ctx.params, ctx.ckpt = model, int(n_steps), params, ckpt
+        ctx.present = tuple(v is not None for v in (mu, lam, ktri, mass, contact))
+        return xT, vT
+
+    @staticmethod
+    def backward(ctx, gx, gv):
+        m = ctx.model
+        gx = torch.zeros(3, m.np, dtype=m.dtype, device=m.device) if gx is None else gx.contiguous()
+        gv = torch.zeros(3, m.np, dtype=m.dtype, device=m.device) if gv is None else gv.contiguous()
+        grads = m.zero_grads(tuple(k for k, p in zip(_PARAM_KEYS, ctx.present) if p))
+        xb0, vb0 = m.rollout_backward(ctx.params, ctx.n_steps, gx, gv, grads, ckpt=ctx.ckpt)
+        out = [grads.get(k) if p else None for k, p in zip(_PARAM_KEYS, ctx.present)]
+        return (None, None, xb0, vb0, *out)
+
+
+def rollout(model, params, x0, v0, n_steps):
+    """Differentiable rollout: params is a dict of (possibly requires_grad) tensors."""
+    return SimRollout.apply(model, n_steps, x0, v0, *(params.get(k) for k in _PARAM_KEYS))

@@ -22,14 +22,15 @@
 #include <string>
 #include <vector>
 
-#include "../../include/gsim.h"
-#include "gsim_internal.h"
+#include "gsim_host.h"
 
 using namespace gsim;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace gsim {
 
 int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -44,6 +45,27 @@ int fail(int code, const char* fmt, ...) {
 int hip_fail(hipError_t e, const char* what) {
     return fail(GSIM_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+void xcd_order(const std::vector<Tile>& nat, int empty_kind, int dummy_id, std::vector<Tile>& out, int& grid) {
+    const int64_t N = (int64_t)nat.size();
+    if (N < N_XCD) {
+        out = nat;
+        grid = (int)N;
+        return;
+    }
+    const int64_t G = (N + N_XCD - 1) / N_XCD;
+    grid = (int)(G * N_XCD);
+    Tile empty{};
+    empty.kind = empty_kind;
+    empty.count = 0;
+    empty.id = dummy_id;
+    out.assign(grid, empty);
+    for (int64_t t = 0; t < N; ++t) out[(t % G) * N_XCD + t / G] = nat[t];
+}
+
+}  // namespace gsim
+
+namespace {
 
 #define HIP_TRY(call, what)                         \
     do {                                            \
@@ -69,23 +91,6 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
 
-// ------------------------------------------------------------------ plan ---
-struct gsim_plan {
-    int dtype = 32;
-    int nb = 0;
-    int64_t np = 0, ne = 0, nt = 0, nh = 0, nslot = 0;
-    std::vector<int64_t> poff, eoff, toff, hoff;   // per-body ranges
-    std::vector<int32_t> tet_idx, tet_slot;        // SoA [4][ne]
-    std::vector<double> tet_dinv, tet_vol;         // SoA [9][ne], [ne]
-    std::vector<int32_t> tri_idx, tri_slot;        // [3][nt]
-    std::vector<double> tri_dinv, tri_area;        // [4][nt], [nt]
-    std::vector<int32_t> hin_idx, hin_slot;        // [4][nh]
-    std::vector<double> hin_phi0;                  // [nh]
-    std::vector<int32_t> csr;                      // [np+1]
-    std::vector<uint8_t> pinned;                   // [np]
-    std::vector<double> dt, grav, plane, kb;       // per body
-    std::vector<uint8_t> contact_on;               // per body
-};
 
 namespace {
 
@@ -258,31 +263,48 @@ int build_plan(const gsim_model_desc* d, gsim_plan* P) {
             for (int c = 0; c < 4; ++c) P->hin_idx[c * nh + h] = id[c];
         }
 
-    // gather table: particle p owns slots csr[p] .. csr[p+1]-1, ordered by
-    // (tets, then triangles, then hinges; element index; corner)
-    std::vector<int32_t> deg(P->np, 0);
-    for (int64_t k = 0; k < 4 * ne; ++k) deg[P->tet_idx[k]]++;
-    for (int64_t k = 0; k < 3 * nt; ++k) deg[P->tri_idx[k]]++;
-    for (int64_t k = 0; k < 4 * nh; ++k) deg[P->hin_idx[k]]++;
-    P->csr.assign(P->np + 1, 0);
-    for (int64_t i = 0; i < P->np; ++i) P->csr[i + 1] = P->csr[i] + deg[i];
-    P->nslot = P->csr[P->np];
-    std::vector<int32_t> cur(P->csr.begin(), P->csr.end() - 1);
+    // gather table (sliced ELL): each body's particles are cut into slices of 64
+    // from the body's first particle; slice g holds width_g = max degree of its
+    // particles, and corner k of the particle at lane j is slot gbase[g] + 64 k + j.
+    // Corners are numbered per particle in the order (tets, then triangles,
+    // then hinges; element index; corner).
+    P->pdeg.assign(P->np, 0);
+    for (int64_t k = 0; k < 4 * ne; ++k) P->pdeg[P->tet_idx[k]]++;
+    for (int64_t k = 0; k < 3 * nt; ++k) P->pdeg[P->tri_idx[k]]++;
+    for (int64_t k = 0; k < 4 * nh; ++k) P->pdeg[P->hin_idx[k]]++;
+    P->gbase.clear();
+    P->body_g0.assign(nb, 0);
+    std::vector<int64_t> pbase(P->np);  // slot of corner 0 of each particle
+    int64_t total = 0;
+    for (int b = 0; b < nb; ++b) {
+        P->body_g0[b] = (int32_t)P->gbase.size();
+        for (int64_t s0 = P->poff[b]; s0 < P->poff[b + 1]; s0 += 64) {
+            const int64_t s1 = std::min<int64_t>(s0 + 64, P->poff[b + 1]);
+            int32_t w = 0;
+            for (int64_t i = s0; i < s1; ++i) w = std::max(w, P->pdeg[i]);
+            if (total + 64 * (int64_t)w > INT32_MAX) return fail(GSIM_E_UNSUPPORTED, "gather table exceeds 32-bit slots");
+            P->gbase.push_back((int32_t)total);
+            for (int64_t i = s0; i < s1; ++i) pbase[i] = total + (i - s0);
+            total += 64 * (int64_t)w;
+        }
+    }
+    P->nslot = total;
+    std::vector<int32_t> cur(P->np, 0);
+    auto slot_of = [&](int32_t p) { return (int32_t)(pbase[p] + 64 * (int64_t)cur[p]++); };
     P->tet_slot.resize(4 * ne);
     P->tri_slot.resize(3 * nt);
     P->hin_slot.resize(4 * nh);
     for (int64_t e = 0; e < ne; ++e)
-        for (int c = 0; c < 4; ++c) P->tet_slot[c * ne + e] = cur[P->tet_idx[c * ne + e]]++;
+        for (int c = 0; c < 4; ++c) P->tet_slot[c * ne + e] = slot_of(P->tet_idx[c * ne + e]);
     for (int64_t t = 0; t < nt; ++t)
-        for (int c = 0; c < 3; ++c) P->tri_slot[c * nt + t] = cur[P->tri_idx[c * nt + t]]++;
+        for (int c = 0; c < 3; ++c) P->tri_slot[c * nt + t] = slot_of(P->tri_idx[c * nt + t]);
     for (int64_t h = 0; h < nh; ++h)
-        for (int c = 0; c < 4; ++c) P->hin_slot[c * nh + h] = cur[P->hin_idx[c * nh + h]]++;
+        for (int c = 0; c < 4; ++c) P->hin_slot[c * nh + h] = slot_of(P->hin_idx[c * nh + h]);
     return GSIM_OK;
 }
 
 // ---------------------------------------------------------------- layout ---
 const int MIN_TILE = 64;  // smallest tile (block 64, 1 item): bounds the tile-list capacity
-const int N_XCD = 8;      // workgroups are dispatched round-robin over 8 XCDs
 
 int64_t tile_capacity(const gsim_plan* P, bool particles) {
     int64_t n = 0;
@@ -298,17 +320,6 @@ int64_t tile_capacity(const gsim_plan* P, bool particles) {
     return n + N_XCD;
 }
 
-struct Layout {
-    size_t model, bodies, etiles, ptiles;
-    size_t tet_idx, tet_slot, tet_dinv, tet_vol;
-    size_t tri_idx, tri_slot, tri_dinv, tri_area;
-    size_t hin_idx, hin_slot, hin_phi0;
-    size_t csr, pinned, slots, cpart, lpart;
-    size_t fbuf, abuf;  // forward / adjoint internal ping-pong states
-    size_t table;
-    int64_t table_cap;
-    size_t total;
-};
 
 template <typename T>
 Layout make_layout(const gsim_plan* P, int max_steps) {
@@ -337,7 +348,8 @@ Layout make_layout(const gsim_plan* P, int max_steps) {
     L.hin_idx = take(4 * nh * 4);
     L.hin_slot = take(4 * nh * 4);
     L.hin_phi0 = take(nh * sizeof(T));
-    L.csr = take((np + 1) * 4);
+    L.gbase = take(P->gbase.size() * 4 + 4);
+    L.pdeg = take(np * 4);
     L.pinned = take(np);
     L.slots = take(4 * std::max<int64_t>(P->nslot, 1) * sizeof(T));
     L.cpart = take(4 * (cap_p + 1) * sizeof(T));
@@ -352,35 +364,14 @@ Layout make_layout(const gsim_plan* P, int max_steps) {
 
 }  // namespace
 
-// ----------------------------------------------------------------- model ---
-struct GraphEntry {
-    hipGraphExec_t exec = nullptr;
-};
-
-struct gsim_model {
-    int dtype = 32;
-    int nb = 0;
-    int64_t np = 0, ne = 0, nt = 0, nh = 0;
-    int max_steps = 0, K = 1;
-    char* ws = nullptr;
-    Layout L{};
-    std::vector<int64_t> poff, eoff, toff, hoff;
-    int exec = GSIM_EXEC_PLAIN, block = 256, items = 1;
-    int n_etiles = 0, n_ptiles = 0;   // launched grid sizes (including XCD padding)
-    int n_ptile_rows = 0;             // real particle tiles (contact / loss partial rows)
-    std::vector<char> bodies_host;    // BodyDev<T>[nb] as last uploaded
-    char* stage = nullptr;            // pinned copy of the launch table as last uploaded
-    hipEvent_t stage_evt = nullptr;   // completes when the last table upload has read `stage`
-    std::map<long long, GraphEntry> graphs;
-};
 
 namespace {
 
-// Builds the tile list for one pass: per body, `items`-sized chunks of each
-// kind, then permuted so that consecutive chunks land on the same XCD (block b
-// runs on XCD b % 8): chunk t goes to XCD t / ceil(N/8), at block j*8 + xcd.
-void build_tiles(gsim_model* m, bool particles, int tile, std::vector<Tile>& out, int& grid, int& rows) {
-    std::vector<Tile> nat;
+// Natural-order tile list of one pass: per body, `tile`-sized chunks of each
+// element kind (or of particles), starting at the body's first item.  Particle
+// tiles get consecutive partial-buffer rows.
+void natural_tiles(const gsim_model* m, bool particles, int tile, std::vector<Tile>& nat, int& rows) {
+    nat.clear();
     rows = 0;
     for (int b = 0; b < m->nb; ++b) {
         auto add = [&](int kind, int64_t lo, int64_t hi) {
@@ -403,35 +394,16 @@ void build_tiles(gsim_model* m, bool particles, int tile, std::vector<Tile>& out
             add(TILE_HINGE, m->hoff[b], m->hoff[b + 1]);
         }
     }
-    const int64_t N = (int64_t)nat.size();
-    if (N == 0) {
-        out.clear();
-        grid = 0;
-        return;
-    }
-    const int64_t G = (N + N_XCD - 1) / N_XCD;
-    grid = (int)(N < N_XCD ? N : G * N_XCD);
-    Tile empty{};
-    empty.kind = particles ? TILE_PART : TILE_TET;
-    empty.count = 0;
-    empty.id = rows;  // dummy partial row, never reduced
-    out.assign(grid, empty);
-    if (N < N_XCD) {
-        out = nat;
-        return;
-    }
-    for (int64_t t = 0; t < N; ++t) {
-        const int64_t xcd = t / G, j = t % G;
-        out[j * N_XCD + xcd] = nat[t];
-    }
 }
 
 template <typename T>
 int upload_tiles(gsim_model* m, void* stream) {
     std::vector<Tile> et, pt;
     int rows_e = 0;
-    build_tiles(m, false, m->block * m->items, et, m->n_etiles, rows_e);
-    build_tiles(m, true, m->block * m->items, pt, m->n_ptiles, m->n_ptile_rows);
+    natural_tiles(m, false, m->block * m->items, m->etiles_nat, rows_e);
+    natural_tiles(m, true, m->block * m->items, m->ptiles_nat, m->n_ptile_rows);
+    xcd_order(m->etiles_nat, TILE_TET, 0, et, m->n_etiles);
+    xcd_order(m->ptiles_nat, TILE_PART, m->n_ptile_rows, pt, m->n_ptiles);
     hipStream_t s = (hipStream_t)stream;
     if (!et.empty()) HIP_TRY(hipMemcpyAsync(m->ws + m->L.etiles, et.data(), et.size() * sizeof(Tile), hipMemcpyHostToDevice, s), "upload tiles");
     if (!pt.empty()) HIP_TRY(hipMemcpyAsync(m->ws + m->L.ptiles, pt.data(), pt.size() * sizeof(Tile), hipMemcpyHostToDevice, s), "upload tiles");
@@ -452,108 +424,6 @@ int upload_tiles(gsim_model* m, void* stream) {
     return GSIM_OK;
 }
 
-template <typename T>
-int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t bytes, void* stream, gsim_model** out) {
-    Layout L = make_layout<T>(P, max_steps);
-    if (bytes < L.total) return fail(GSIM_E_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
-    if (((uintptr_t)d_ws & 255) != 0) return fail(GSIM_E_INVALID, "workspace must be 256-byte aligned");
-    gsim_model* m = new (std::nothrow) gsim_model();
-    if (!m) return fail(GSIM_E_INVALID, "out of host memory");
-    m->dtype = P->dtype;
-    m->nb = P->nb;
-    m->np = P->np;
-    m->ne = P->ne;
-    m->nt = P->nt;
-    m->nh = P->nh;
-    m->max_steps = max_steps;
-    m->K = K;
-    m->ws = (char*)d_ws;
-    m->L = L;
-    m->poff = P->poff;
-    m->eoff = P->eoff;
-    m->toff = P->toff;
-    m->hoff = P->hoff;
-    hipStream_t s = (hipStream_t)stream;
-    char* ws = m->ws;
-    auto up = [&](size_t off, const void* src, size_t n) -> hipError_t {
-        if (n == 0) return hipSuccess;
-        return hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, s);
-    };
-    auto cvt = [](const std::vector<double>& v) { return std::vector<T>(v.begin(), v.end()); };
-    std::vector<T> tet_dinv = cvt(P->tet_dinv), tet_vol = cvt(P->tet_vol), tri_dinv = cvt(P->tri_dinv),
-                   tri_area = cvt(P->tri_area), hin_phi0 = cvt(P->hin_phi0);
-    hipError_t e = hipSuccess;
-    auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
-    chk(up(L.tet_idx, P->tet_idx.data(), P->tet_idx.size() * 4));
-    chk(up(L.tet_slot, P->tet_slot.data(), P->tet_slot.size() * 4));
-    chk(up(L.tet_dinv, tet_dinv.data(), tet_dinv.size() * sizeof(T)));
-    chk(up(L.tet_vol, tet_vol.data(), tet_vol.size() * sizeof(T)));
-    chk(up(L.tri_idx, P->tri_idx.data(), P->tri_idx.size() * 4));
-    chk(up(L.tri_slot, P->tri_slot.data(), P->tri_slot.size() * 4));
-    chk(up(L.tri_dinv, tri_dinv.data(), tri_dinv.size() * sizeof(T)));
-    chk(up(L.tri_area, tri_area.data(), tri_area.size() * sizeof(T)));
-    chk(up(L.hin_idx, P->hin_idx.data(), P->hin_idx.size() * 4));
-    chk(up(L.hin_slot, P->hin_slot.data(), P->hin_slot.size() * 4));
-    chk(up(L.hin_phi0, hin_phi0.data(), hin_phi0.size() * sizeof(T)));
-    chk(up(L.csr, P->csr.data(), P->csr.size() * 4));
-    chk(up(L.pinned, P->pinned.data(), P->pinned.size()));
-    std::vector<BodyDev<T>> bodies(P->nb);
-    for (int b = 0; b < P->nb; ++b) {
-        BodyDev<T>& B = bodies[b];
-        std::memset(&B, 0, sizeof B);
-        B.p0 = P->poff[b];
-        B.np = P->poff[b + 1] - P->poff[b];
-        B.contact_on = P->contact_on[b];
-        B.dt = (T)P->dt[b];
-        for (int c = 0; c < 3; ++c) B.g[c] = (T)P->grav[3 * b + c];
-        for (int c = 0; c < 4; ++c) B.plane[c] = (T)P->plane[4 * b + c];
-        B.kb = (T)P->kb[b];
-    }
-    m->bodies_host.assign(reinterpret_cast<const char*>(bodies.data()),
-                          reinterpret_cast<const char*>(bodies.data() + P->nb));
-    ModelDev<T> M;
-    std::memset(&M, 0, sizeof M);
-    M.np = P->np;
-    M.ne = P->ne;
-    M.nt = P->nt;
-    M.nh = P->nh;
-    M.nslot = P->nslot;
-    M.n_bodies = P->nb;
-    M.tet_idx = (const int32_t*)(ws + L.tet_idx);
-    M.tet_dinv = (const T*)(ws + L.tet_dinv);
-    M.tet_vol = (const T*)(ws + L.tet_vol);
-    M.tet_slot = (const int32_t*)(ws + L.tet_slot);
-    M.tri_idx = (const int32_t*)(ws + L.tri_idx);
-    M.tri_dinv = (const T*)(ws + L.tri_dinv);
-    M.tri_area = (const T*)(ws + L.tri_area);
-    M.tri_slot = (const int32_t*)(ws + L.tri_slot);
-    M.hin_idx = (const int32_t*)(ws + L.hin_idx);
-    M.hin_phi0 = (const T*)(ws + L.hin_phi0);
-    M.hin_slot = (const int32_t*)(ws + L.hin_slot);
-    M.csr = (const int32_t*)(ws + L.csr);
-    M.pinned = (const uint8_t*)(ws + L.pinned);
-    M.bodies = (const BodyDev<T>*)(ws + L.bodies);
-    M.slots = (T*)(ws + L.slots);
-    M.cpart = (T*)(ws + L.cpart);
-    M.lpart = (T*)(ws + L.lpart);
-    chk(up(L.model, &M, sizeof M));
-    chk(hipHostMalloc((void**)&m->stage, sizeof(StepDev<T>) * L.table_cap, hipHostMallocDefault));
-    chk(hipEventCreateWithFlags(&m->stage_evt, hipEventDisableTiming));
-    if (e == hipSuccess) std::memset(m->stage, 0, sizeof(StepDev<T>) * L.table_cap);
-    if (e != hipSuccess) {
-        if (m->stage) (void)hipHostFree(m->stage);
-        if (m->stage_evt) (void)hipEventDestroy(m->stage_evt);
-        delete m;
-        return hip_fail(e, "upload model");
-    }
-    int rc = upload_tiles<T>(m, stream);
-    if (rc) {
-        gsim_model_destroy(m);
-        return rc;
-    }
-    *out = m;
-    return GSIM_OK;
-}
 
 // ------------------------------------------------------------- launching ---
 template <typename T>
@@ -589,6 +459,29 @@ struct Launch {
     int64_t row;
 };
 
+hipError_t take_event(gsim_model* m, hipEvent_t* e) {
+    if (!m->evt_pool.empty()) {
+        *e = m->evt_pool.back();
+        m->evt_pool.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+// Launches one pass, bracketed by timing events when kernel `k` is selected.
+template <typename F>
+int timed(gsim_model* m, int k, void* stream, F launch) {
+    if (!(m->timing_mask & (1 << k))) return launch();
+    hipEvent_t a, b;
+    HIP_TRY(take_event(m, &a), "timing event");
+    HIP_TRY(take_event(m, &b), "timing event");
+    HIP_TRY(hipEventRecord(a, (hipStream_t)stream), "timing record");
+    int rc = launch();
+    HIP_TRY(hipEventRecord(b, (hipStream_t)stream), "timing record");
+    m->pending.push_back({k, a, b});
+    return rc;
+}
+
 template <typename T>
 int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
     Ctx<T> c = ctx<T>(m);
@@ -597,12 +490,12 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
         const StepDev<T>* sd = c.table + l.row;
         switch (l.op) {
             case OP_FWD:
-                LAUNCH_TRY(launch_elem_fwd<T>(md, sd, c.et, m->n_etiles, m->block, m->items, stream), "element pass");
-                LAUNCH_TRY(launch_part_fwd<T>(md, sd, c.pt, m->n_ptiles, m->block, m->items, stream), "particle pass");
+                LAUNCH_TRY(timed(m, 0, stream, [&] { return launch_elem_fwd<T>(md, sd, c.et, m->n_etiles, m->block, m->items, stream); }), "element pass");
+                LAUNCH_TRY(timed(m, 1, stream, [&] { return launch_part_fwd<T>(md, sd, c.pt, m->n_ptiles, m->block, m->items, stream); }), "particle pass");
                 break;
             case OP_ADJ:
-                LAUNCH_TRY(launch_elem_adj<T>(md, sd, c.et, m->n_etiles, m->block, m->items, stream), "element adjoint");
-                LAUNCH_TRY(launch_part_adj<T>(md, sd, c.pt, m->n_ptiles, m->block, m->items, stream), "particle adjoint");
+                LAUNCH_TRY(timed(m, 2, stream, [&] { return launch_elem_adj<T>(md, sd, c.et, m->n_etiles, m->block, m->items, stream); }), "element adjoint");
+                LAUNCH_TRY(timed(m, 3, stream, [&] { return launch_part_adj<T>(md, sd, c.pt, m->n_ptiles, m->block, m->items, stream); }), "particle adjoint");
                 break;
             case OP_FILL_CPART:
                 LAUNCH_TRY(launch_fill<T>((T*)(m->ws + m->L.cpart), 4 * (int64_t)(m->n_ptile_rows + 1), T(0), stream), "clear");
@@ -638,6 +531,7 @@ int upload_rows(gsim_model* m, int64_t row0, const std::vector<StepDev<T>>& rows
 template <typename T>
 int execute(gsim_model* m, long long key, const std::vector<Launch>& seq, void* stream) {
     if (m->exec == GSIM_EXEC_GRAPH) {
+        if (m->timing_mask) return fail(GSIM_E_UNSUPPORTED, "kernel timing needs plain execution");
         if (stream == nullptr) return fail(GSIM_E_UNSUPPORTED, "graph execution needs a non-default stream");
         auto it = m->graphs.find(key);
         if (it == m->graphs.end()) {
@@ -890,6 +784,120 @@ int guarded(F f) {
 
 }  // namespace
 
+namespace gsim {
+
+template <typename T>
+int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t bytes, void* stream, gsim_model** out) {
+    Layout L = make_layout<T>(P, max_steps);
+    if (bytes < L.total) return fail(GSIM_E_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
+    if (((uintptr_t)d_ws & 255) != 0) return fail(GSIM_E_INVALID, "workspace must be 256-byte aligned");
+    gsim_model* m = new (std::nothrow) gsim_model();
+    if (!m) return fail(GSIM_E_INVALID, "out of host memory");
+    m->dtype = P->dtype;
+    m->nb = P->nb;
+    m->np = P->np;
+    m->ne = P->ne;
+    m->nt = P->nt;
+    m->nh = P->nh;
+    m->max_steps = max_steps;
+    m->K = K;
+    m->ws = (char*)d_ws;
+    m->L = L;
+    m->poff = P->poff;
+    m->eoff = P->eoff;
+    m->toff = P->toff;
+    m->hoff = P->hoff;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = m->ws;
+    auto up = [&](size_t off, const void* src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, s);
+    };
+    auto cvt = [](const std::vector<double>& v) { return std::vector<T>(v.begin(), v.end()); };
+    std::vector<T> tet_dinv = cvt(P->tet_dinv), tet_vol = cvt(P->tet_vol), tri_dinv = cvt(P->tri_dinv),
+                   tri_area = cvt(P->tri_area), hin_phi0 = cvt(P->hin_phi0);
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    chk(up(L.tet_idx, P->tet_idx.data(), P->tet_idx.size() * 4));
+    chk(up(L.tet_slot, P->tet_slot.data(), P->tet_slot.size() * 4));
+    chk(up(L.tet_dinv, tet_dinv.data(), tet_dinv.size() * sizeof(T)));
+    chk(up(L.tet_vol, tet_vol.data(), tet_vol.size() * sizeof(T)));
+    chk(up(L.tri_idx, P->tri_idx.data(), P->tri_idx.size() * 4));
+    chk(up(L.tri_slot, P->tri_slot.data(), P->tri_slot.size() * 4));
+    chk(up(L.tri_dinv, tri_dinv.data(), tri_dinv.size() * sizeof(T)));
+    chk(up(L.tri_area, tri_area.data(), tri_area.size() * sizeof(T)));
+    chk(up(L.hin_idx, P->hin_idx.data(), P->hin_idx.size() * 4));
+    chk(up(L.hin_slot, P->hin_slot.data(), P->hin_slot.size() * 4));
+    chk(up(L.hin_phi0, hin_phi0.data(), hin_phi0.size() * sizeof(T)));
+    chk(up(L.gbase, P->gbase.data(), P->gbase.size() * 4));
+    chk(up(L.pdeg, P->pdeg.data(), P->pdeg.size() * 4));
+    chk(up(L.pinned, P->pinned.data(), P->pinned.size()));
+    std::vector<BodyDev<T>> bodies(P->nb);
+    for (int b = 0; b < P->nb; ++b) {
+        BodyDev<T>& B = bodies[b];
+        std::memset(&B, 0, sizeof B);
+        B.p0 = P->poff[b];
+        B.np = P->poff[b + 1] - P->poff[b];
+        B.contact_on = P->contact_on[b];
+        B.g0 = P->body_g0[b];
+        B.dt = (T)P->dt[b];
+        for (int c = 0; c < 3; ++c) B.g[c] = (T)P->grav[3 * b + c];
+        for (int c = 0; c < 4; ++c) B.plane[c] = (T)P->plane[4 * b + c];
+        B.kb = (T)P->kb[b];
+    }
+    m->bodies_host.assign(reinterpret_cast<const char*>(bodies.data()),
+                          reinterpret_cast<const char*>(bodies.data() + P->nb));
+    ModelDev<T> M;
+    std::memset(&M, 0, sizeof M);
+    M.np = P->np;
+    M.ne = P->ne;
+    M.nt = P->nt;
+    M.nh = P->nh;
+    M.nslot = P->nslot;
+    M.n_bodies = P->nb;
+    M.tet_idx = (const int32_t*)(ws + L.tet_idx);
+    M.tet_dinv = (const T*)(ws + L.tet_dinv);
+    M.tet_vol = (const T*)(ws + L.tet_vol);
+    M.tet_slot = (const int32_t*)(ws + L.tet_slot);
+    M.tri_idx = (const int32_t*)(ws + L.tri_idx);
+    M.tri_dinv = (const T*)(ws + L.tri_dinv);
+    M.tri_area = (const T*)(ws + L.tri_area);
+    M.tri_slot = (const int32_t*)(ws + L.tri_slot);
+    M.hin_idx = (const int32_t*)(ws + L.hin_idx);
+    M.hin_phi0 = (const T*)(ws + L.hin_phi0);
+    M.hin_slot = (const int32_t*)(ws + L.hin_slot);
+    M.gbase = (const int32_t*)(ws + L.gbase);
+    M.pdeg = (const int32_t*)(ws + L.pdeg);
+    M.pinned = (const uint8_t*)(ws + L.pinned);
+    M.bodies = (const BodyDev<T>*)(ws + L.bodies);
+    M.slots = (T*)(ws + L.slots);
+    M.cpart = (T*)(ws + L.cpart);
+    M.lpart = (T*)(ws + L.lpart);
+    chk(up(L.model, &M, sizeof M));
+    m->md_host.assign(reinterpret_cast<const char*>(&M), reinterpret_cast<const char*>(&M) + sizeof M);
+    chk(hipHostMalloc((void**)&m->stage, sizeof(StepDev<T>) * L.table_cap, hipHostMallocDefault));
+    chk(hipEventCreateWithFlags(&m->stage_evt, hipEventDisableTiming));
+    if (e == hipSuccess) std::memset(m->stage, 0, sizeof(StepDev<T>) * L.table_cap);
+    if (e != hipSuccess) {
+        if (m->stage) (void)hipHostFree(m->stage);
+        if (m->stage_evt) (void)hipEventDestroy(m->stage_evt);
+        delete m;
+        return hip_fail(e, "upload model");
+    }
+    int rc = upload_tiles<T>(m, stream);
+    if (rc) {
+        gsim_model_destroy(m);
+        return rc;
+    }
+    *out = m;
+    return GSIM_OK;
+}
+
+template int model_init<float>(const gsim_plan*, int, int, void*, size_t, void*, gsim_model**);
+template int model_init<double>(const gsim_plan*, int, int, void*, size_t, void*, gsim_model**);
+
+}  // namespace gsim
+
 // ------------------------------------------------------------------ C-ABI ---
 extern "C" {
 
@@ -961,6 +969,12 @@ int gsim_model_destroy(gsim_model* m) {
         (void)hipEventDestroy(m->stage_evt);
     }
     if (m->stage) (void)hipHostFree(m->stage);
+    for (auto& p : m->pending) {
+        (void)hipEventSynchronize(p.b);
+        m->evt_pool.push_back(p.a);
+        m->evt_pool.push_back(p.b);
+    }
+    for (hipEvent_t e : m->evt_pool) (void)hipEventDestroy(e);
     delete m;
     return GSIM_OK;
 }
@@ -986,6 +1000,33 @@ int gsim_model_get_exec(const gsim_model* m, int* exec, int* block, int* items) 
     if (exec) *exec = m->exec;
     if (block) *block = m->block;
     if (items) *items = m->items;
+    return GSIM_OK;
+}
+
+int gsim_model_set_timing(gsim_model* m, int mask) {
+    if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    if (mask < 0 || mask > 15) return fail(GSIM_E_INVALID, "timing mask must be in [0, 15]");
+    m->timing_mask = mask;
+    return GSIM_OK;
+}
+
+int gsim_model_read_timing(gsim_model* m, int kernel, int64_t* launches, double* total_ms) {
+    if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    if (kernel < 0 || kernel > 3) return fail(GSIM_E_INVALID, "kernel must be in [0, 3]");
+    for (auto& p : m->pending) {
+        HIP_TRY(hipEventSynchronize(p.b), "timing sync");
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, p.a, p.b), "timing elapsed");
+        m->timing_ms[p.kernel] += ms;
+        m->timing_n[p.kernel] += 1;
+        m->evt_pool.push_back(p.a);
+        m->evt_pool.push_back(p.b);
+    }
+    m->pending.clear();
+    if (launches) *launches = m->timing_n[kernel];
+    if (total_ms) *total_ms = m->timing_ms[kernel];
+    m->timing_n[kernel] = 0;
+    m->timing_ms[kernel] = 0;
     return GSIM_OK;
 }
 

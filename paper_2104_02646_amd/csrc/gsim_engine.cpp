@@ -1,0 +1,601 @@
+// Serving engine: continuous batching of system-identification gradient queries.
+//
+// A query is one body (tet mesh or cloth) with parameters, a start state, a
+// target and a step count; its answer is the loss of the rollout's final
+// positions and the gradients of that loss (App. A adjoint through the App. A.2
+// semi-implicit Euler steps).  The engine
+//   - admits queued queries in FIFO order while their exact device footprint
+//     fits in the caller-owned pool (first-fit allocator over the pool);
+//   - keeps every admitted query's states, checkpoints, segment buffer,
+//     adjoint states, parameters and gradients on the device;
+//   - advances every live query by one micro-step per tick, and runs the
+//     micro-steps of all live queries together: one element pass and one
+//     particle pass over the union of their tiles for the forward micro-steps,
+//     and the same for the adjoint micro-steps.  A query's arithmetic and
+//     reduction order do not depend on who else is in the batch.
+// Per-query micro-steps: T forward steps (checkpoint every K), the loss seed,
+// then for each checkpoint segment in reverse the recomputed forward steps and
+// the adjoint steps, then the contact-gradient reduction and the copy-out.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <new>
+
+#include "gsim_host.h"
+
+using namespace gsim;
+
+namespace {
+
+#define HIP_TRY(call, what)                                  \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, what);     \
+    } while (0)
+
+#define LAUNCH_TRY(call, what)                               \
+    do {                                                     \
+        int rc_ = (call);                                    \
+        if (rc_) return hip_fail((hipError_t)rc_, what);     \
+    } while (0)
+
+size_t aup(size_t v) { return (v + 255) / 256 * 256; }
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Device buffers of one query, as offsets from its pool region.
+struct QLayout {
+    size_t ws, ws_bytes, ckpt, seg, s0, sA, sB, seed, aA, aB, target;
+    size_t mu, lam, ktri, mass, contact, g_mu, g_lam, g_ktri, g_mass, g_contact, loss;
+    size_t total;
+};
+
+QLayout qlayout(const gsim_plan* P, int T, int K) {
+    QLayout L;
+    size_t ws = 0, ck = 0, sg = 0;
+    gsim_plan_sizes(P, T, K, &ws, &ck, &sg);
+    const size_t st = 6 * (size_t)P->np * 4;
+    size_t o = 0;
+    auto take = [&](size_t b) {
+        size_t at = o;
+        o = aup(o + b);
+        return at;
+    };
+    L.ws_bytes = ws;
+    L.ws = take(ws);
+    L.ckpt = take(ck);
+    L.seg = take(sg);
+    L.s0 = take(st);
+    L.sA = take(st);
+    L.sB = take(st);
+    L.seed = take(st);
+    L.aA = take(st);
+    L.aB = take(st);
+    L.target = take(3 * (size_t)P->np * 4);
+    L.mu = take(P->ne * 4);
+    L.lam = take(P->ne * 4);
+    L.ktri = take(P->nt * 4);
+    L.mass = take(P->np * 4);
+    L.contact = take(16);
+    L.g_mu = take(P->ne * 4);
+    L.g_lam = take(P->ne * 4);
+    L.g_ktri = take(P->nt * 4);
+    L.g_mass = take(P->np * 4);
+    L.g_contact = take(16);
+    L.loss = take(4);
+    L.total = o;
+    return L;
+}
+
+enum Phase { PH_FWD = 0, PH_LOSS = 1, PH_BWD = 2, PH_FIN = 3 };
+enum OpKind { OP_NONE = 0, OP_FWD = 1, OP_ADJ = 2, OP_LOSS = 3, OP_FIN = 4 };
+
+struct Query {
+    int64_t id = 0;
+    std::unique_ptr<gsim_plan, int (*)(gsim_plan*)> plan{nullptr, gsim_plan_destroy};
+    int T = 0, K = 1;
+    int64_t np = 0, ne = 0, nt = 0;
+    std::vector<float> mu, lam, ktri, mass, contact, x0v0, target;  // x0v0 = [x0 | v0] SoA
+    float *o_mu = nullptr, *o_lam = nullptr, *o_ktri = nullptr, *o_mass = nullptr, *o_contact = nullptr;
+    QLayout lay{};
+    double t_submit = 0;
+};
+
+struct Live {
+    std::unique_ptr<Query> q;
+    gsim_model* model = nullptr;
+    size_t off = 0;  // pool region
+    char* base = nullptr;
+    int phase = PH_FWD;
+    int t = 0;         // forward step
+    int seg = 0;       // current backward segment
+    int j = 0;         // recompute index inside the segment (j < L-1), then adjoint
+    int ta = 0;        // next adjoint step
+    int qa = 0;        // adjoint steps done
+    double t_admit = 0;
+    float* F(size_t o) const { return reinterpret_cast<float*>(base + o); }
+};
+
+struct Done {
+    int64_t id;
+    float loss;
+    double t_submit, t_admit, t_done;
+};
+
+// First-fit allocator over [0, size) with 256-byte granularity.
+struct Pool {
+    size_t size = 0;
+    std::vector<std::pair<size_t, size_t>> free_list;  // (offset, length), sorted by offset
+    void init(size_t s) {
+        size = s;
+        free_list.assign(1, {0, s});
+    }
+    bool alloc(size_t n, size_t& off) {
+        n = aup(n);
+        for (size_t i = 0; i < free_list.size(); ++i)
+            if (free_list[i].second >= n) {
+                off = free_list[i].first;
+                free_list[i].first += n;
+                free_list[i].second -= n;
+                if (free_list[i].second == 0) free_list.erase(free_list.begin() + i);
+                return true;
+            }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = aup(n);
+        auto it = std::lower_bound(free_list.begin(), free_list.end(), std::make_pair(off, (size_t)0));
+        it = free_list.insert(it, {off, n});
+        // merge with neighbours
+        size_t i = it - free_list.begin();
+        if (i + 1 < free_list.size() && free_list[i].first + free_list[i].second == free_list[i + 1].first) {
+            free_list[i].second += free_list[i + 1].second;
+            free_list.erase(free_list.begin() + i + 1);
+        }
+        if (i > 0 && free_list[i - 1].first + free_list[i - 1].second == free_list[i].first) {
+            free_list[i - 1].second += free_list[i].second;
+            free_list.erase(free_list.begin() + i);
+        }
+    }
+    size_t free_bytes() const {
+        size_t s = 0;
+        for (auto& f : free_list) s += f.second;
+        return s;
+    }
+};
+
+const int RING = 4;  // tick tables in flight
+
+}  // namespace
+
+struct gsim_engine {
+    char* pool_base = nullptr;
+    Pool pool;
+    int max_live = 0;
+    int64_t max_tiles = 0;
+    hipStream_t stream = nullptr;
+    // per-tick table ring: device blobs (carved from the pool) and pinned host copies
+    size_t blob_bytes = 0;
+    char* blob_dev[RING] = {};
+    char* blob_host[RING] = {};
+    hipEvent_t blob_evt[RING] = {};
+    int ring = 0;
+    int64_t next_id = 1;
+    std::deque<std::unique_ptr<Query>> queue;
+    std::vector<Live> live;
+    std::vector<Done> done;
+    int64_t ticks = 0, admitted = 0, completed = 0;
+    double live_sum = 0;  // sum over ticks of live queries (mean concurrency)
+};
+
+namespace {
+
+// Builds and uploads the device buffers of an admitted query.
+int admit(gsim_engine* E, std::unique_ptr<Query>& q, size_t off) {
+    Live L;
+    L.off = off;
+    L.base = E->pool_base + off;
+    const QLayout& ly = q->lay;
+    int rc = model_init<float>(q->plan.get(), q->T, q->K, L.base + ly.ws, ly.ws_bytes, E->stream, &L.model);
+    if (rc) return rc;
+    hipStream_t s = E->stream;
+    auto up = [&](size_t o, const std::vector<float>& v) -> hipError_t {
+        if (v.empty()) return hipSuccess;
+        return hipMemcpyAsync(L.base + o, v.data(), v.size() * 4, hipMemcpyHostToDevice, s);
+    };
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
+    chk(up(ly.s0, q->x0v0));
+    chk(up(ly.target, q->target));
+    chk(up(ly.mu, q->mu));
+    chk(up(ly.lam, q->lam));
+    chk(up(ly.ktri, q->ktri));
+    chk(up(ly.mass, q->mass));
+    chk(up(ly.contact, q->contact));
+    if (e != hipSuccess) {
+        gsim_model_destroy(L.model);
+        return hip_fail(e, "upload query");
+    }
+    // zero gradients and contact partial rows (fill kernels)
+    const ModelDev<float>* md = reinterpret_cast<const ModelDev<float>*>(L.model->md_host.data());
+    LAUNCH_TRY(launch_fill<float>(L.F(ly.g_mu), q->ne, 0.f, s), "clear");
+    LAUNCH_TRY(launch_fill<float>(L.F(ly.g_lam), q->ne, 0.f, s), "clear");
+    LAUNCH_TRY(launch_fill<float>(L.F(ly.g_ktri), q->nt, 0.f, s), "clear");
+    LAUNCH_TRY(launch_fill<float>(L.F(ly.g_mass), q->np, 0.f, s), "clear");
+    LAUNCH_TRY(launch_fill<float>(L.F(ly.g_contact), 4, 0.f, s), "clear");
+    LAUNCH_TRY(launch_fill<float>(md->cpart, 4 * (int64_t)(L.model->n_ptile_rows + 1), 0.f, s), "clear");
+    L.q = std::move(q);
+    L.t_admit = now_s();
+    E->live.push_back(std::move(L));
+    E->admitted++;
+    return GSIM_OK;
+}
+
+void base_step(const Live& L, StepDev<float>& r) {
+    std::memset(&r, 0, sizeof r);
+    const QLayout& ly = L.q->lay;
+    r.mu = L.q->ne ? L.F(ly.mu) : nullptr;
+    r.lam = L.q->ne ? L.F(ly.lam) : nullptr;
+    r.ktri = L.q->nt ? L.F(ly.ktri) : nullptr;
+    r.mass = L.F(ly.mass);
+    r.contact = L.F(ly.contact);
+}
+
+// Decides the next micro-step of a live query and fills its launch record.
+int next_op(const Live& L, StepDev<float>& r) {
+    const Query& q = *L.q;
+    const QLayout& ly = q.lay;
+    const int64_t S = 6 * q.np, np = q.np;
+    base_step(L, r);
+    if (L.phase == PH_FWD) {
+        const int t = L.t;
+        r.x = t == 0 ? L.F(ly.s0) : L.F((t - 1) & 1 ? ly.sB : ly.sA);
+        r.v = r.x + 3 * np;
+        r.xo = L.F(t & 1 ? ly.sB : ly.sA);
+        r.vo = r.xo + 3 * np;
+        if (t % q.K == 0) {
+            r.ckx = L.F(ly.ckpt) + (int64_t)(t / q.K) * S;
+            r.ckv = r.ckx + 3 * np;
+        }
+        return OP_FWD;
+    }
+    if (L.phase == PH_LOSS) {
+        const int t = q.T - 1;
+        r.x = L.F(t & 1 ? ly.sB : ly.sA);
+        r.target = L.F(ly.target);
+        r.loss = L.F(ly.loss);
+        r.xbo = L.F(ly.seed);
+        r.vbo = r.xbo + 3 * np;
+        return OP_LOSS;
+    }
+    if (L.phase == PH_BWD) {
+        const int t0 = L.seg * q.K, t1 = std::min(q.T, t0 + q.K), Ls = t1 - t0;
+        const float* ck = L.F(ly.ckpt) + (int64_t)L.seg * S;
+        float* sg = L.F(ly.seg);
+        if (L.j + 1 < Ls) {  // recompute state t0 + j + 1
+            r.x = L.j == 0 ? ck : sg + (int64_t)(L.j - 1) * S;
+            r.v = r.x + 3 * np;
+            r.xo = sg + (int64_t)L.j * S;
+            r.vo = r.xo + 3 * np;
+            return OP_FWD;
+        }
+        const int t = L.ta;
+        r.x = t == t0 ? ck : sg + (int64_t)(t - t0 - 1) * S;
+        r.v = r.x + 3 * np;
+        r.xb = L.qa == 0 ? L.F(ly.seed) : L.F((L.qa - 1) & 1 ? ly.aB : ly.aA);
+        r.vb = r.xb + 3 * np;
+        r.xbo = L.F(L.qa & 1 ? ly.aB : ly.aA);
+        r.vbo = r.xbo + 3 * np;
+        r.g_mu = q.ne ? L.F(ly.g_mu) : nullptr;
+        r.g_lam = q.ne ? L.F(ly.g_lam) : nullptr;
+        r.g_ktri = q.nt ? L.F(ly.g_ktri) : nullptr;
+        r.g_mass = L.F(ly.g_mass);
+        r.g_contact = L.F(ly.g_contact);
+        return OP_ADJ;
+    }
+    r.g_contact = L.F(ly.g_contact);
+    return OP_FIN;
+}
+
+void advance(Live& L, int op) {
+    const Query& q = *L.q;
+    if (op == OP_FWD && L.phase == PH_FWD) {
+        if (++L.t == q.T) L.phase = PH_LOSS;
+        return;
+    }
+    if (op == OP_LOSS) {
+        L.phase = PH_BWD;
+        L.seg = (q.T + q.K - 1) / q.K - 1;
+        L.j = 0;
+        L.ta = q.T - 1;
+        L.qa = 0;
+        return;
+    }
+    if (op == OP_FWD) {  // recompute
+        L.j++;
+        return;
+    }
+    if (op == OP_ADJ) {
+        L.qa++;
+        const int t0 = L.seg * q.K;
+        if (L.ta == t0) {
+            if (L.seg == 0) {
+                L.phase = PH_FIN;
+                return;
+            }
+            L.seg--;
+            L.j = 0;
+        }
+        L.ta--;
+    }
+}
+
+int finish(gsim_engine* E, Live& L) {
+    Query& q = *L.q;
+    const QLayout& ly = q.lay;
+    hipStream_t s = E->stream;
+    float loss = 0.f;
+    auto down = [&](float* dst, size_t o, int64_t n) -> hipError_t {
+        if (!dst || n == 0) return hipSuccess;
+        return hipMemcpyAsync(dst, L.base + o, n * 4, hipMemcpyDeviceToHost, s);
+    };
+    HIP_TRY(down(&loss, ly.loss, 1), "copy out");
+    HIP_TRY(down(q.o_mu, ly.g_mu, q.ne), "copy out");
+    HIP_TRY(down(q.o_lam, ly.g_lam, q.ne), "copy out");
+    HIP_TRY(down(q.o_ktri, ly.g_ktri, q.nt), "copy out");
+    HIP_TRY(down(q.o_mass, ly.g_mass, q.np), "copy out");
+    HIP_TRY(down(q.o_contact, ly.g_contact, 4), "copy out");
+    HIP_TRY(hipStreamSynchronize(s), "copy out");
+    E->done.push_back({q.id, loss, q.t_submit, L.t_admit, now_s()});
+    gsim_model_destroy(L.model);
+    E->pool.release(L.off, q.lay.total);
+    E->completed++;
+    return GSIM_OK;
+}
+
+int tick(gsim_engine* E, int* n_live, int* n_queued) {
+    // 1. admission, FIFO while the head fits
+    while (!E->queue.empty() && (int)E->live.size() < E->max_live) {
+        size_t off;
+        if (!E->pool.alloc(E->queue.front()->lay.total, off)) break;
+        std::unique_ptr<Query> q = std::move(E->queue.front());
+        E->queue.pop_front();
+        int rc = admit(E, q, off);
+        if (rc) {
+            E->pool.release(off, q ? q->lay.total : 0);
+            return rc;
+        }
+    }
+    const int n = (int)E->live.size();
+    if (n_live) *n_live = n;
+    if (n_queued) *n_queued = (int)E->queue.size();
+    if (n == 0) return GSIM_OK;
+    E->ticks++;
+    E->live_sum += n;
+
+    // 2. plan this tick: one micro-step per live query
+    std::vector<int> ops(n);
+    std::vector<StepDev<float>> sd(n);
+    for (int i = 0; i < n; ++i) ops[i] = next_op(E->live[i], sd[i]);
+    std::vector<Tile> nat[4];  // elem fwd, part fwd, elem adj, part adj
+    for (int i = 0; i < n; ++i) {
+        const gsim_model* m = E->live[i].model;
+        if (ops[i] != OP_FWD && ops[i] != OP_ADJ) continue;
+        const int k = ops[i] == OP_FWD ? 0 : 2;
+        for (Tile t : m->etiles_nat) {
+            t.model = i;
+            nat[k].push_back(t);
+        }
+        for (Tile t : m->ptiles_nat) {
+            t.model = i;
+            nat[k + 1].push_back(t);
+        }
+    }
+    std::vector<Tile> ord[4];
+    int grid[4] = {0, 0, 0, 0};
+    const int dummy_row = E->live[0].model->n_ptile_rows;  // empty tiles reduce into model 0's spare row
+    for (int k = 0; k < 4; ++k) xcd_order(nat[k], (k & 1) ? TILE_PART : TILE_TET, dummy_row, ord[k], grid[k]);
+    // 3. one blob: [ModelDev x n][StepDev x n][tiles x 4 lists]
+    const size_t md_sz = sizeof(ModelDev<float>), sd_sz = sizeof(StepDev<float>);
+    size_t o_md = 0, o_sd = aup(md_sz * n), o_t[4];
+    size_t o = aup(o_sd + sd_sz * n);
+    for (int k = 0; k < 4; ++k) {
+        o_t[k] = o;
+        o = aup(o + sizeof(Tile) * ord[k].size());
+    }
+    if (o > E->blob_bytes) return fail(GSIM_E_WORKSPACE, "tick tables exceed the engine's table capacity");
+    const int r = E->ring;
+    E->ring = (E->ring + 1) % RING;
+    HIP_TRY(hipEventSynchronize(E->blob_evt[r]), "wait for table ring");
+    char* h = E->blob_host[r];
+    for (int i = 0; i < n; ++i) std::memcpy(h + o_md + i * md_sz, E->live[i].model->md_host.data(), md_sz);
+    std::memcpy(h + o_sd, sd.data(), sd_sz * n);
+    for (int k = 0; k < 4; ++k) std::memcpy(h + o_t[k], ord[k].data(), sizeof(Tile) * ord[k].size());
+    char* d = E->blob_dev[r];
+    HIP_TRY(hipMemcpyAsync(d, h, o, hipMemcpyHostToDevice, E->stream), "upload tick tables");
+    const ModelDev<float>* dmd = reinterpret_cast<const ModelDev<float>*>(d + o_md);
+    const StepDev<float>* dsd = reinterpret_cast<const StepDev<float>*>(d + o_sd);
+    // 4. per-query singular launches (loss seed, contact reduction)
+    for (int i = 0; i < n; ++i) {
+        gsim_model* m = E->live[i].model;
+        const ModelDev<float>* own = reinterpret_cast<const ModelDev<float>*>(m->ws + m->L.model);
+        const Tile* own_pt = reinterpret_cast<const Tile*>(m->ws + m->L.ptiles);
+        if (ops[i] == OP_LOSS)
+            LAUNCH_TRY(launch_loss<float>(own, dsd + i, own_pt, m->n_ptiles, m->block, m->items, 1, E->stream), "loss");
+        if (ops[i] == OP_FIN) LAUNCH_TRY(launch_contact_reduce<float>(own, dsd + i, 1, E->stream), "contact reduce");
+    }
+    // 5. batched passes over all queries' tiles
+    const int block = 256;
+    auto T_ = [&](int k) { return reinterpret_cast<const Tile*>(d + o_t[k]); };
+    LAUNCH_TRY(launch_elem_fwd<float>(dmd, dsd, T_(0), grid[0], block, 1, E->stream), "element pass");
+    LAUNCH_TRY(launch_part_fwd<float>(dmd, dsd, T_(1), grid[1], block, 1, E->stream), "particle pass");
+    LAUNCH_TRY(launch_elem_adj<float>(dmd, dsd, T_(2), grid[2], block, 1, E->stream), "element adjoint");
+    LAUNCH_TRY(launch_part_adj<float>(dmd, dsd, T_(3), grid[3], block, 1, E->stream), "particle adjoint");
+    HIP_TRY(hipEventRecord(E->blob_evt[r], E->stream), "record tick");
+    // 6. advance; finish completed queries
+    std::vector<Live> keep;
+    keep.reserve(n);
+    for (int i = 0; i < n; ++i) {
+        Live& L = E->live[i];
+        if (ops[i] == OP_FIN) {
+            int rc = finish(E, L);
+            if (rc) return rc;
+            continue;
+        }
+        advance(L, ops[i]);
+        keep.push_back(std::move(L));
+    }
+    E->live.swap(keep);
+    return GSIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gsim_engine_create(void* d_pool, size_t pool_bytes, int max_live, int64_t max_tiles, void* stream,
+                       gsim_engine** out) {
+    if (!d_pool || !out || max_live < 1 || max_tiles < 64) return fail(GSIM_E_INVALID, "bad engine arguments");
+    if (((uintptr_t)d_pool & 255) != 0) return fail(GSIM_E_INVALID, "pool must be 256-byte aligned");
+    gsim_engine* E = new (std::nothrow) gsim_engine();
+    if (!E) return fail(GSIM_E_INVALID, "out of host memory");
+    E->pool_base = (char*)d_pool;
+    E->max_live = max_live;
+    E->max_tiles = max_tiles;
+    E->stream = (hipStream_t)stream;
+    E->blob_bytes = aup((sizeof(ModelDev<float>) + sizeof(StepDev<float>)) * max_live + 4096) +
+                    aup(sizeof(Tile) * (size_t)max_tiles + 4 * 8 * sizeof(Tile)) + 5 * 256;
+    if ((size_t)RING * E->blob_bytes >= pool_bytes) {
+        delete E;
+        return fail(GSIM_E_WORKSPACE, "pool too small for the engine's tables");
+    }
+    for (int r = 0; r < RING; ++r) {
+        E->blob_dev[r] = E->pool_base + r * E->blob_bytes;
+        hipError_t e = hipHostMalloc((void**)&E->blob_host[r], E->blob_bytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&E->blob_evt[r], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(E->blob_evt[r], E->stream);
+        if (e != hipSuccess) {
+            gsim_engine_destroy(E);
+            return hip_fail(e, "engine tables");
+        }
+    }
+    const size_t used = RING * E->blob_bytes;
+    E->pool.init(pool_bytes - used);
+    E->pool_base += used;
+    *out = E;
+    return GSIM_OK;
+}
+
+int gsim_engine_destroy(gsim_engine* E) {
+    if (!E) return GSIM_OK;
+    (void)hipStreamSynchronize(E->stream);
+    for (Live& L : E->live) gsim_model_destroy(L.model);
+    for (int r = 0; r < RING; ++r) {
+        if (E->blob_evt[r]) (void)hipEventDestroy(E->blob_evt[r]);
+        if (E->blob_host[r]) (void)hipHostFree(E->blob_host[r]);
+    }
+    delete E;
+    return GSIM_OK;
+}
+
+int gsim_engine_query_bytes(const gsim_query* q, size_t* bytes) {
+    if (!q || !q->desc || !bytes) return fail(GSIM_E_INVALID, "NULL argument");
+    gsim_plan* P = nullptr;
+    int rc = gsim_plan_create(q->desc, &P);
+    if (rc) return rc;
+    *bytes = qlayout(P, q->n_steps, q->ckpt_every).total;
+    gsim_plan_destroy(P);
+    return GSIM_OK;
+}
+
+int gsim_engine_submit(gsim_engine* E, const gsim_query* in, int64_t* id) {
+    if (!E || !in || !in->desc) return fail(GSIM_E_INVALID, "NULL argument");
+    const gsim_model_desc* d = in->desc;
+    if (d->dtype != GSIM_F32 || d->n_bodies != 1) return fail(GSIM_E_UNSUPPORTED, "queries are single FP32 bodies");
+    if (in->n_steps < 1 || in->ckpt_every < 1) return fail(GSIM_E_INVALID, "n_steps and ckpt_every must be >= 1");
+    if (!in->mass || !in->contact || !in->x0 || !in->v0 || !in->target) return fail(GSIM_E_INVALID, "NULL input");
+    if (d->n_tets && (!in->mu || !in->lam)) return fail(GSIM_E_INVALID, "mu and lam are required");
+    if (d->n_tris && !in->k_tri) return fail(GSIM_E_INVALID, "k_tri is required");
+    try {
+        std::unique_ptr<Query> q(new Query());
+        gsim_plan* P = nullptr;
+        int rc = gsim_plan_create(d, &P);
+        if (rc) return rc;
+        q->plan.reset(P);
+        q->T = in->n_steps;
+        q->K = in->ckpt_every;
+        q->np = P->np;
+        q->ne = P->ne;
+        q->nt = P->nt;
+        q->lay = qlayout(P, q->T, q->K);
+        if (q->lay.total > E->pool.size)
+            return fail(GSIM_E_WORKSPACE, "query needs %zu bytes, the pool has %zu", q->lay.total, E->pool.size);
+        auto cp = [](std::vector<float>& v, const float* src, int64_t n) { v.assign(src, src + n); };
+        if (q->ne) {
+            cp(q->mu, in->mu, q->ne);
+            cp(q->lam, in->lam, q->ne);
+        }
+        if (q->nt) cp(q->ktri, in->k_tri, q->nt);
+        cp(q->mass, in->mass, q->np);
+        cp(q->contact, in->contact, 4);
+        q->x0v0.resize(6 * q->np);
+        std::memcpy(q->x0v0.data(), in->x0, 12 * q->np);
+        std::memcpy(q->x0v0.data() + 3 * q->np, in->v0, 12 * q->np);
+        cp(q->target, in->target, 3 * q->np);
+        q->o_mu = in->out_mu;
+        q->o_lam = in->out_lam;
+        q->o_ktri = in->out_k_tri;
+        q->o_mass = in->out_mass;
+        q->o_contact = in->out_contact;
+        q->id = E->next_id++;
+        q->t_submit = now_s();
+        if (id) *id = q->id;
+        E->queue.push_back(std::move(q));
+    } catch (const std::bad_alloc&) {
+        return fail(GSIM_E_INVALID, "out of host memory");
+    }
+    return GSIM_OK;
+}
+
+int gsim_engine_tick(gsim_engine* E, int* n_live, int* n_queued) {
+    if (!E) return fail(GSIM_E_INVALID, "NULL engine");
+    try {
+        return tick(E, n_live, n_queued);
+    } catch (const std::bad_alloc&) {
+        return fail(GSIM_E_INVALID, "out of host memory");
+    }
+}
+
+int gsim_engine_poll(gsim_engine* E, gsim_result* out, int max, int* n) {
+    if (!E || !n) return fail(GSIM_E_INVALID, "NULL argument");
+    int k = 0;
+    while (k < max && !E->done.empty()) {
+        const Done& d = E->done.front();
+        out[k].id = d.id;
+        out[k].loss = d.loss;
+        out[k].t_submit = d.t_submit;
+        out[k].t_admit = d.t_admit;
+        out[k].t_done = d.t_done;
+        E->done.erase(E->done.begin());
+        ++k;
+    }
+    *n = k;
+    return GSIM_OK;
+}
+
+int gsim_engine_stats(const gsim_engine* E, int64_t* ticks, int64_t* admitted, int64_t* completed,
+                      double* mean_live, size_t* pool_free) {
+    if (!E) return fail(GSIM_E_INVALID, "NULL engine");
+    if (ticks) *ticks = E->ticks;
+    if (admitted) *admitted = E->admitted;
+    if (completed) *completed = E->completed;
+    if (mean_live) *mean_live = E->ticks ? E->live_sum / E->ticks : 0.0;
+    if (pool_free) *pool_free = E->pool.free_bytes();
+    return GSIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Host-side objects of libgsim shared by the C-ABI runtime (gsim_api.cpp) and
+// the serving engine (gsim_engine.cpp).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/gsim.h"
+#include "gsim_internal.h"
+
+// ------------------------------------------------------------------ plan ---
+struct gsim_plan {
+    int dtype = 32;
+    int nb = 0;
+    int64_t np = 0, ne = 0, nt = 0, nh = 0, nslot = 0;
+    std::vector<int64_t> poff, eoff, toff, hoff;   // per-body ranges
+    std::vector<int32_t> tet_idx, tet_slot;        // SoA [4][ne]
+    std::vector<double> tet_dinv, tet_vol;         // SoA [9][ne], [ne]
+    std::vector<int32_t> tri_idx, tri_slot;        // [3][nt]
+    std::vector<double> tri_dinv, tri_area;        // [4][nt], [nt]
+    std::vector<int32_t> hin_idx, hin_slot;        // [4][nh]
+    std::vector<double> hin_phi0;                  // [nh]
+    std::vector<int32_t> gbase;                    // [n_slices] sliced-ELL slice bases
+    std::vector<int32_t> pdeg;                     // [np]
+    std::vector<int32_t> body_g0;                  // [nb] first slice of each body
+    std::vector<uint8_t> pinned;                   // [np]
+    std::vector<double> dt, grav, plane, kb;       // per body
+    std::vector<uint8_t> contact_on;               // per body
+};
+
+namespace gsim {
+
+const int N_XCD = 8;  // workgroups are dispatched round-robin over the XCDs
+
+struct Layout {
+    size_t model, bodies, etiles, ptiles;
+    size_t tet_idx, tet_slot, tet_dinv, tet_vol;
+    size_t tri_idx, tri_slot, tri_dinv, tri_area;
+    size_t hin_idx, hin_slot, hin_phi0;
+    size_t gbase, pdeg, pinned, slots, cpart, lpart;
+    size_t fbuf, abuf;  // forward / adjoint internal ping-pong states
+    size_t table;
+    int64_t table_cap;
+    size_t total;
+};
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+};
+
+// Records an error message for gsim_last_error() and returns `code`.
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b on XCD b % 8).
+// Permutes a natural-order tile list so that consecutive tiles (which share
+// particles, hence L2 lines) land on the same XCD; pads with empty tiles.
+void xcd_order(const std::vector<Tile>& nat, int empty_kind, int dummy_id, std::vector<Tile>& out, int& grid);
+
+template <typename T>
+int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t bytes, void* stream, gsim_model** out);
+
+}  // namespace gsim
+
+struct gsim_model {
+    int dtype = 32;
+    int nb = 0;
+    int64_t np = 0, ne = 0, nt = 0, nh = 0;
+    int max_steps = 0, K = 1;
+    char* ws = nullptr;
+    gsim::Layout L{};
+    std::vector<int64_t> poff, eoff, toff, hoff;
+    int exec = GSIM_EXEC_PLAIN, block = 256, items = 1;
+    int n_etiles = 0, n_ptiles = 0;   // launched grid sizes (including XCD padding)
+    int n_ptile_rows = 0;             // real particle tiles (contact / loss partial rows)
+    std::vector<char> bodies_host;    // BodyDev<T>[nb] as last uploaded
+    char* stage = nullptr;            // pinned copy of the launch table as last uploaded
+    hipEvent_t stage_evt = nullptr;   // completes when the last table upload has read `stage`
+    std::vector<gsim::Tile> etiles_nat, ptiles_nat;  // natural-order tiles (current tile size)
+    std::vector<char> md_host;                       // ModelDev<T> as uploaded
+    std::map<long long, gsim::GraphEntry> graphs;
+    // per-kernel timing: HIP events around each launch of the kernels in timing_mask
+    int timing_mask = 0;
+    std::vector<hipEvent_t> evt_pool;
+    struct Pending {
+        int kernel;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    double timing_ms[4] = {0, 0, 0, 0};
+    int64_t timing_n[4] = {0, 0, 0, 0};
+};

@@ -6,7 +6,11 @@
 //             row-major), vol[ne], slot[4][ne] (corner -> gather slot)
 //     tris    idx[3][nt], dinv[4][nt], area[nt], slot[3][nt]
 //     hinges  idx[4][nh] (wing0, wing1, edge0, edge1), phi0[nh], slot[4][nh]
-//   gather table csr[np+1]: particle p sums slots csr[p] .. csr[p+1]-1 in order;
+//   gather table in sliced-ELL form: the particles of a body are cut into
+//     slices of 64 (one wavefront); slice g stores its particles' corner slots
+//     interleaved, so corner k of lane j sits at gbase[g] + 64 k + j and one
+//     wavefront load of "corner k" is one contiguous 1 KB (FP32) access;
+//     pdeg[p] = number of element corners of particle p (summed in order k = 0..);
 //   slots[nslot][4]: one 4-vector per element corner, written once per pass by
 //     the element kernel (forward: the corner force; adjoint: the corner's
 //     position-adjoint contribution and f_corner . fbar for the mass gradient).
@@ -36,7 +40,7 @@ struct BodyDev {
     int64_t p0, np;      // particle range
     int32_t pt0, pt1;    // particle-tile id range (contact-gradient partials)
     int32_t contact_on;  // ground contact active
-    int32_t pad;
+    int32_t g0;          // first gather slice of the body
     T dt;
     T g[3];
     T plane[4];          // n.x = d
@@ -58,7 +62,8 @@ struct ModelDev {
     const int32_t* hin_idx;
     const T* hin_phi0;
     const int32_t* hin_slot;
-    const int32_t* csr;
+    const int32_t* gbase;  // [n_slices] first slot of each 64-particle slice
+    const int32_t* pdeg;   // [np] element corners per particle
     const uint8_t* pinned;
     const BodyDev<T>* bodies;
     T* slots;   // [nslot][4]

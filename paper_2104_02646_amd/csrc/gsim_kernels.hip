@@ -5,7 +5,9 @@
 //                  the element force (tet / membrane / bending, App. A.1) and
 //                  writes each corner's 4-vector into that corner's gather slot;
 //   particle pass  one thread per particle: sums its slots in a fixed order (no
-//                  atomics, bitwise deterministic), adds ground contact and
+//                  atomics, bitwise deterministic; slots are interleaved per
+//                  64-particle slice so each gather load is coalesced), adds
+//                  ground contact and
 //                  friction (App. A.1 "Contact", App. B.2) and integrates.
 // The adjoint step (App. A, App. A.2 Jacobians) has the same two passes in the
 // same layout: the element pass applies the hand-written reverse mode of each
@@ -504,10 +506,12 @@ __global__ void __launch_bounds__(512) k_part_fwd(const ModelDev<T>* __restrict_
     for (int64_t l = threadIdx.x; l < tl.count; l += blockDim.x) {
         const int64_t i = tl.begin + l;
         V3<T> f = zero3<T>();
-        const int32_t s0 = M.csr[i], s1 = M.csr[i + 1];
-        for (int32_t s = s0; s < s1; ++s) {
+        const int64_t li = i - B.p0;
+        const int64_t base = M.gbase[B.g0 + (li >> 6)] + (li & 63);
+        const int32_t deg = M.pdeg[i];
+        for (int32_t k = 0; k < deg; ++k) {
             T a, b, c, d;
-            ld_slot(M.slots, s, a, b, c, d);
+            ld_slot(M.slots, base + 64 * k, a, b, c, d);
             f += mk3(a, b, c);
         }
         const V3<T> x = ld3(S.x, np, i), v = ld3(S.v, np, i);
@@ -615,10 +619,12 @@ __global__ void __launch_bounds__(512) k_part_adj(const ModelDev<T>* __restrict_
         const V3<T> fb = vt * (dt * w);
         V3<T> xs = zero3<T>();
         T ds = T(0);
-        const int32_t s0 = M.csr[i], s1 = M.csr[i + 1];
-        for (int32_t s = s0; s < s1; ++s) {
+        const int64_t li = i - B.p0;
+        const int64_t base = M.gbase[B.g0 + (li >> 6)] + (li & 63);
+        const int32_t deg = M.pdeg[i];
+        for (int32_t k = 0; k < deg; ++k) {
             T a, b, c, d;
-            ld_slot(M.slots, s, a, b, c, d);
+            ld_slot(M.slots, base + 64 * k, a, b, c, d);
             xs += mk3(a, b, c);
             ds += d;
         }

@@ -28,7 +28,8 @@ EXEC_PLAIN, EXEC_GRAPH, EXEC_FUSED = 0, 1, 2
 ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan_destroy", "gsim_plan_sizes",
                "gsim_plan_counts", "gsim_model_init", "gsim_model_destroy", "gsim_model_set_exec",
                "gsim_model_get_exec", "gsim_step", "gsim_step_backward", "gsim_rollout", "gsim_rollout_backward",
-               "gsim_loss_mse")
+               "gsim_loss_mse", "gsim_model_set_timing", "gsim_model_read_timing")
+KERNELS = ("element_fwd", "particle_fwd", "element_adj", "particle_adj")
 
 
 class GsimError(RuntimeError):
@@ -86,6 +87,8 @@ def load():
         lib.gsim_rollout.argtypes = [vp, C.POINTER(_Params), _State, ip, vp, _State, vp]
         lib.gsim_rollout_backward.argtypes = [vp, C.POINTER(_Params), vp, ip, vp, _State, _State, C.POINTER(_Grads), vp]
         lib.gsim_loss_mse.argtypes = [vp, _State, vp, vp, _State, vp]
+        lib.gsim_model_set_timing.argtypes = [vp, ip]
+        lib.gsim_model_read_timing.argtypes = [vp, ip, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         _lib = lib
     return _lib
 
@@ -242,6 +245,22 @@ class Model:
         _check(load().gsim_model_get_exec(self._h, C.byref(e), C.byref(b), C.byref(i)))
         return e.value, b.value, i.value
 
+    def set_timing(self, kernels=KERNELS):
+        """Bracket every launch of the named kernels with HIP events (plain execution)."""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << KERNELS.index(k)
+        _check(load().gsim_model_set_timing(self._h, mask))
+
+    def read_timing(self):
+        """{kernel: (launches, total_ms)} since the last read."""
+        out = {}
+        for i, k in enumerate(KERNELS):
+            n, ms = C.c_int64(), C.c_double()
+            _check(load().gsim_model_read_timing(self._h, i, C.byref(n), C.byref(ms)))
+            out[k] = (n.value, ms.value)
+        return out
+
     # -- tensors ----------------------------------------------------------------
     def empty_state(self):
         return (torch.empty(3, self.np, dtype=self.dtype, device=self.device),
@@ -305,15 +324,21 @@ class Model:
                                          C.byref(self._grads(grads)), _stream(stream)))
         return xbm, vbm
 
-    def rollout(self, params, x0, v0, n_steps, checkpoint=True, out=None, stream=None):
+    def new_checkpoints(self):
+        """A checkpoint buffer of its own (for rollouts whose backward comes later)."""
+        return torch.empty_like(self.ckpt)
+
+    def rollout(self, params, x0, v0, n_steps, checkpoint=True, out=None, stream=None, ckpt=None):
         xo, vo = self.empty_state() if out is None else out
+        ck = (self.ckpt if ckpt is None else ckpt) if checkpoint else None
         _check(load().gsim_rollout(self._h, C.byref(self._params(params)), self._state(x0, v0), int(n_steps),
-                                   _ptr(self.ckpt) if checkpoint else None, self._state(xo, vo), _stream(stream)))
+                                   _ptr(ck), self._state(xo, vo), _stream(stream)))
         return xo, vo
 
-    def rollout_backward(self, params, n_steps, xb_final, vb_final, grads=None, out=None, stream=None):
+    def rollout_backward(self, params, n_steps, xb_final, vb_final, grads=None, out=None, stream=None, ckpt=None):
         xbi, vbi = self.empty_state() if out is None else out
-        _check(load().gsim_rollout_backward(self._h, C.byref(self._params(params)), _ptr(self.ckpt), int(n_steps),
+        ck = self.ckpt if ckpt is None else ckpt
+        _check(load().gsim_rollout_backward(self._h, C.byref(self._params(params)), _ptr(ck), int(n_steps),
                                             _ptr(self.segment), self._state(xb_final, vb_final), self._state(xbi, vbi),
                                             C.byref(self._grads(grads)), _stream(stream)))
         return xbi, vbi

@@ -1,0 +1,218 @@
+"""Serving: system-identification gradient queries through the continuous-batching
+engine of libgsim (``gsim_engine_*``), and the one-query-per-launch FIFO path.
+
+Each query is one body (tet mesh or cloth grid), a step count and a target; its
+answer is the loss of its final positions and the gradients w.r.t. its
+parameters (tet: mu, lambda, mass, contact; cloth: k_tri, mass).  The engine
+(C++) owns admission, the device pool, the per-tick batching and the micro-step
+schedule of every query; this module marshals queries and drives ticks.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import time
+
+import numpy as np
+import torch
+
+from . import gsim
+from .gsim import _check, _Desc, load
+
+
+class _Query(C.Structure):
+    _fields_ = [("desc", C.POINTER(_Desc)), ("n_steps", C.c_int), ("ckpt_every", C.c_int),
+                ("mu", C.c_void_p), ("lam", C.c_void_p), ("k_tri", C.c_void_p), ("mass", C.c_void_p),
+                ("contact", C.c_void_p), ("x0", C.c_void_p), ("v0", C.c_void_p), ("target", C.c_void_p),
+                ("out_mu", C.c_void_p), ("out_lam", C.c_void_p), ("out_k_tri", C.c_void_p),
+                ("out_mass", C.c_void_p), ("out_contact", C.c_void_p)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("id", C.c_int64), ("loss", C.c_float), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double)]
+
+
+_ready = False
+
+
+def _load():
+    global _ready
+    lib = load()
+    if not _ready:
+        vp = C.c_void_p
+        lib.gsim_engine_create.argtypes = [vp, C.c_size_t, C.c_int, C.c_int64, vp, C.POINTER(vp)]
+        lib.gsim_engine_destroy.argtypes = [vp]
+        lib.gsim_engine_query_bytes.argtypes = [C.POINTER(_Query), C.POINTER(C.c_size_t)]
+        lib.gsim_engine_submit.argtypes = [vp, C.POINTER(_Query), C.POINTER(C.c_int64)]
+        lib.gsim_engine_tick.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        lib.gsim_engine_poll.argtypes = [vp, C.POINTER(_Result), C.c_int, C.POINTER(C.c_int)]
+        lib.gsim_engine_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                          C.POINTER(C.c_double), C.POINTER(C.c_size_t)]
+        _ready = True
+    return lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(np.asarray(a, np.float64), dtype=np.float32)
+
+
+class QueryBuffers:
+    """Host arrays of one query (inputs in the engine's layout, outputs filled on completion)."""
+
+    def __init__(self, body, n_steps, ckpt_every):
+        self.body = body
+        self.plan_src = gsim.pack([body])
+        pk = self.plan_src
+        d = _Desc()
+        d.dtype, d.n_bodies = 32, 1
+        d.n_particles, d.n_tets, d.n_tris, d.n_hinges = len(pk.X), len(pk.tets), len(pk.tris), len(pk.hinges)
+        a = lambda arr: arr.ctypes.data if arr is not None and arr.size else None
+        d.body_particle_off = a(pk.poff)
+        d.body_tet_off = a(pk.eoff) if len(pk.tets) else None
+        d.body_tri_off = a(pk.toff) if len(pk.tris) else None
+        d.body_hinge_off = a(pk.hoff) if len(pk.hinges) else None
+        d.rest_x, d.tet_idx, d.tri_idx, d.hinge_idx = a(pk.X), a(pk.tets), a(pk.tris), a(pk.hinges)
+        d.pinned, d.gravity, d.dt, d.ground = a(pk.pinned), a(pk.gravity), a(pk.dt), a(pk.ground)
+        d.contact_on, d.k_bend = a(pk.contact_on), a(pk.k_bend)
+        self.desc = d
+        self.inp = {"mu": _f32(body.mu) if body.ne else None, "lam": _f32(body.lam) if body.ne else None,
+                    "k_tri": _f32(body.ktri) if body.nt else None, "mass": _f32(body.mass),
+                    "contact": _f32([body.ke, body.kd, body.kf, body.muf]),
+                    "x0": _f32(np.asarray(body.x0).T), "v0": _f32(np.asarray(body.v0).T),
+                    "target": _f32(np.asarray(body.target).T)}
+        self.out = {"mu": np.zeros(body.ne, np.float32), "lam": np.zeros(body.ne, np.float32),
+                    "k_tri": np.zeros(body.nt, np.float32), "mass": np.zeros(body.np, np.float32),
+                    "contact": np.zeros(4, np.float32)}
+        q = _Query()
+        q.desc = C.pointer(d)
+        q.n_steps, q.ckpt_every = int(n_steps), int(ckpt_every)
+        for k, v in self.inp.items():
+            setattr(q, k, None if v is None else v.ctypes.data)
+        for k, v in self.out.items():
+            setattr(q, "out_" + k, v.ctypes.data if v.size else None)
+        self.q = q
+        self.loss = None
+
+    def bytes(self):
+        n = C.c_size_t()
+        _check(_load().gsim_engine_query_bytes(C.byref(self.q), C.byref(n)))
+        return n.value
+
+
+class Engine:
+    """``gsim_engine_*`` over a torch-allocated device pool."""
+
+    def __init__(self, pool_bytes=4 << 30, max_live=64, max_tiles=1 << 17, device="cuda", stream=None):
+        lib = _load()
+        self.device = torch.device(device)
+        self.pool = torch.empty(pool_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.pool.data_ptr() + (-self.pool.data_ptr()) % 256
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
+        h = C.c_void_p()
+        _check(lib.gsim_engine_create(C.c_void_p(base), pool_bytes, int(max_live), int(max_tiles),
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self._h = h
+        self.pending = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _load().gsim_engine_destroy(h)
+            self._h = None
+
+    def submit(self, qb: QueryBuffers) -> int:
+        i = C.c_int64()
+        _check(_load().gsim_engine_submit(self._h, C.byref(qb.q), C.byref(i)))
+        self.pending[i.value] = qb
+        return i.value
+
+    def tick(self):
+        nl, nq = C.c_int(), C.c_int()
+        _check(_load().gsim_engine_tick(self._h, C.byref(nl), C.byref(nq)))
+        return nl.value, nq.value
+
+    def poll(self, max_n=256):
+        res = (_Result * max_n)()
+        n = C.c_int()
+        _check(_load().gsim_engine_poll(self._h, res, max_n, C.byref(n)))
+        out = []
+        for k in range(n.value):
+            r = res[k]
+            qb = self.pending.pop(r.id)
+            qb.loss = r.loss
+            out.append((r.id, qb, r.t_submit, r.t_admit, r.t_done))
+        return out
+
+    def stats(self):
+        t, a, c = C.c_int64(), C.c_int64(), C.c_int64()
+        ml, pf = C.c_double(), C.c_size_t()
+        _check(_load().gsim_engine_stats(self._h, C.byref(t), C.byref(a), C.byref(c), C.byref(ml), C.byref(pf)))
+        return {"ticks": t.value, "admitted": a.value, "completed": c.value, "mean_live": ml.value,
+                "pool_free": pf.value}
+
+    def run_until_idle(self, max_ticks=10_000_000):
+        done = []
+        for _ in range(max_ticks):
+            nl, nq = self.tick()
+            done += self.poll()
+            if nl == 0 and nq == 0:
+                break
+        return done
+
+
+def solve_alone(qb: QueryBuffers, block=256, device="cuda"):
+    """One query on a model of its own: rollout + loss + checkpointed adjoint (plain
+    launches).  The one-query-per-launch reference path."""
+    b = qb.body
+    T, K = qb.q.n_steps, qb.q.ckpt_every
+    m = gsim.Model([b], torch.float32, max_steps=T, ckpt_every=K, device=device)
+    p = m.params_from_bodies()
+    xT, _ = m.rollout(p, gsim.soa(b.x0, device=device), gsim.soa(b.v0, device=device), T)
+    loss, xb, vb = m.loss_mse(xT, gsim.soa(b.target, device=device))
+    g = m.zero_grads()
+    m.rollout_backward(p, T, xb, vb, g)
+    torch.cuda.synchronize()
+    return float(loss[0]), {k: v.detach().cpu().numpy().reshape(-1) for k, v in g.items()}
+
+
+def replay_trace(trace, bodies, engine: Engine, ckpt_every=10, time_scale=1.0, log=None):
+    """Real-time replay: query i is submitted at its arrival time (seconds from the
+    start, scaled); the engine ticks continuously.  Returns per-query latency
+    (completion - arrival) and the engine's statistics."""
+    qbs = [QueryBuffers(b, q.steps, ckpt_every) for q, b in zip(trace, bodies)]
+    arrivals = np.array([q.arrival for q in trace]) * time_scale
+    t0 = time.perf_counter()
+    nxt = 0
+    lat = {}
+    id2idx = {}
+    n = len(trace)
+    while len(lat) < n:
+        now = time.perf_counter() - t0
+        while nxt < n and arrivals[nxt] <= now:
+            id2idx[engine.submit(qbs[nxt])] = nxt
+            nxt += 1
+        nl, nq = engine.tick()
+        for qid, qb, ts, ta, td in engine.poll():
+            i = id2idx[qid]
+            lat[i] = (time.perf_counter() - t0) - arrivals[i]
+        if nl == 0 and nq == 0 and nxt < n:
+            time.sleep(max(0.0, min(0.001, arrivals[nxt] - (time.perf_counter() - t0))))
+        if log and len(lat) and len(lat) % 200 == 0:
+            log("served %d/%d" % (len(lat), n))
+    wall = time.perf_counter() - t0
+    return np.array([lat[i] for i in range(n)]), wall, qbs
+
+
+def replay_fifo(trace, bodies, ckpt_every=10, time_scale=1.0, device="cuda"):
+    """The same arrivals through the one-query-per-launch path, first come first served."""
+    qbs = [QueryBuffers(b, q.steps, ckpt_every) for q, b in zip(trace, bodies)]
+    arrivals = np.array([q.arrival for q in trace]) * time_scale
+    t0 = time.perf_counter()
+    lat = np.zeros(len(trace))
+    for i, qb in enumerate(qbs):
+        now = time.perf_counter() - t0
+        if arrivals[i] > now:
+            time.sleep(arrivals[i] - now)
+        solve_alone(qb, device=device)
+        lat[i] = (time.perf_counter() - t0) - arrivals[i]
+    return lat, time.perf_counter() - t0

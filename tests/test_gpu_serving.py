@@ -1,0 +1,103 @@
+"""Continuous-batching engine: every query's answer is bit-for-bit the answer it
+gets alone, queries that arrive while others run are admitted as memory frees up,
+and admission respects the device pool (FIFO)."""
+import numpy as np
+import pytest
+
+from paper_2104_02646_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def sv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2104_02646_amd import serve
+    serve.gsim.load()
+    return serve
+
+
+def mixed_queries():
+    qs = []
+    for i, (kind, size, T, K) in enumerate([("tet", 800, 60, 10), ("cloth", 16, 45, 7), ("tet", 3000, 80, 20),
+                                            ("cloth", 24, 30, 30), ("tet", 1500, 25, 4), ("tet", 500, 90, 9),
+                                            ("cloth", 12, 70, 10), ("tet", 5000, 40, 10)]):
+        b = W.batch_body(50000 + i, lo=size, hi=size) if kind == "tet" else W.cloth(60 + i, n=size, size=0.5)
+        b.target = W.synthetic_target(b, 70 + i)
+        qs.append((b, T, K))
+    return qs
+
+
+def test_alone_equals_in_mix_bitwise(sv):
+    qs = mixed_queries()
+    eng = sv.Engine(pool_bytes=1 << 30, max_live=16)
+    qbs = [sv.QueryBuffers(b, T, K) for b, T, K in qs]
+    # half now, the rest while the first half is in flight
+    for qb in qbs[:4]:
+        eng.submit(qb)
+    done = []
+    for _ in range(20):
+        eng.tick()
+        done += eng.poll()
+    for qb in qbs[4:]:
+        eng.submit(qb)
+    done += eng.run_until_idle()
+    assert len(done) == len(qbs)
+    st = eng.stats()
+    assert st["mean_live"] > 1.5, st
+    times = {qid: (ta, td) for qid, qb, ts, ta, td in done}
+    late = [times[q] for q in list(times)[4:]]
+    early_done = max(td for ta, td in list(times.values())[:4])
+    assert any(ta < early_done for ta, td in late), "late queries must be admitted while early ones run"
+    for qb in qbs:
+        loss, g = sv.solve_alone(qb)
+        assert np.float32(loss) == np.float32(qb.loss), (loss, qb.loss)
+        b = qb.body
+        assert np.array_equal(g["mass"], qb.out["mass"])
+        if b.ne:
+            assert np.array_equal(g["mu"], qb.out["mu"])
+            assert np.array_equal(g["lam"], qb.out["lam"])
+            assert np.array_equal(g["contact"], qb.out["contact"])
+        if b.nt:
+            assert np.array_equal(g["ktri"], qb.out["k_tri"])
+
+
+def test_admission_by_footprint_fifo(sv):
+    """A pool that holds only two of the queries at once: the rest wait, admission
+    follows submission order, everything completes with the right answers."""
+    qs = [(W.batch_body(51000 + i, lo=2000, hi=2000), 40, 10) for i in range(5)]
+    for i, (b, T, K) in enumerate(qs):
+        b.target = W.synthetic_target(b, 90 + i)
+    qbs = [sv.QueryBuffers(b, T, K) for b, T, K in qs]
+    need = max(qb.bytes() for qb in qbs)
+    tables = 4 * (1 << 20)
+    eng = sv.Engine(pool_bytes=int(2.5 * need) + tables, max_live=16, max_tiles=1 << 14)
+    for qb in qbs:
+        eng.submit(qb)
+    peak = 0
+    done = []
+    while True:
+        nl, nq = eng.tick()
+        peak = max(peak, nl)
+        done += eng.poll()
+        if nl == 0 and nq == 0:
+            break
+    assert peak == 2
+    admits = [ta for qid, qb, ts, ta, td in sorted(done, key=lambda r: r[0])]
+    assert admits == sorted(admits)
+    for qb in qbs:
+        loss, g = sv.solve_alone(qb)
+        assert np.array_equal(g["mu"], qb.out["mu"])
+
+
+def test_rejects_query_larger_than_pool(sv):
+    from paper_2104_02646_amd import gsim
+    b = W.batch_body(52000, lo=4000, hi=4000)
+    b.target = W.synthetic_target(b, 1)
+    qb = sv.QueryBuffers(b, 100, 10)
+    eng = sv.Engine(pool_bytes=qb.bytes() // 2 + 8 * (1 << 20), max_live=4, max_tiles=1 << 14)
+    with pytest.raises(gsim.GsimError) as ei:
+        eng.submit(qb)
+    assert ei.value.code == gsim.GSIM_E_WORKSPACE
