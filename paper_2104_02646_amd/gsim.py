@@ -28,7 +28,9 @@ EXEC_PLAIN, EXEC_GRAPH, EXEC_FUSED = 0, 1, 2
 ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan_destroy", "gsim_plan_sizes",
                "gsim_plan_counts", "gsim_model_init", "gsim_model_destroy", "gsim_model_set_exec",
                "gsim_model_get_exec", "gsim_step", "gsim_step_backward", "gsim_rollout", "gsim_rollout_backward",
-               "gsim_loss_mse", "gsim_model_set_timing", "gsim_model_read_timing")
+               "gsim_loss_mse", "gsim_model_set_timing", "gsim_model_read_timing",
+               "gsim_engine_create", "gsim_engine_destroy", "gsim_engine_query_bytes", "gsim_engine_submit",
+               "gsim_engine_tick", "gsim_engine_poll", "gsim_engine_stats")
 KERNELS = ("element_fwd", "particle_fwd", "element_adj", "particle_adj")
 
 
