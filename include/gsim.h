@@ -132,11 +132,19 @@ int gsim_model_init(const gsim_plan* plan, int max_steps, int ckpt_every, void* 
                     void* stream, gsim_model** out);
 int gsim_model_destroy(gsim_model* model);
 
-/* Selects the rollout execution strategy (GSIM_EXEC_*) and launch shape:
- * block = threads per workgroup (64..512, multiple of 64), items = elements
- * (or particles) per thread (1..8).  0 keeps the current value. */
+/* Selects the rollout execution strategy (GSIM_EXEC_*) and, for both passes,
+ * the launch shape: block = threads per workgroup (64..512, multiple of 64),
+ * items = elements (or particles) per thread (1..8); a workgroup's tile is
+ * block * items items.  0 keeps the current value.  get_exec reports the
+ * element-pass shape. */
 int gsim_model_set_exec(gsim_model* model, int exec, int block, int items);
 int gsim_model_get_exec(const gsim_model* model, int* exec, int* block, int* items);
+
+/* Launch shape of one pass (0 = element passes, 1 = particle passes), as above.
+ * Results do not depend on the element-pass shape; the particle-pass shape
+ * fixes the summation tree of per-body contact gradients and losses. */
+int gsim_model_set_launch(gsim_model* model, int pass, int block, int items);
+int gsim_model_get_launch(const gsim_model* model, int pass, int* block, int* items);
 
 /* Kernel timing for measurement: with bit k of `mask` set, every launch of
  * kernel k is bracketed by HIP events on its stream (k: 0 element pass,

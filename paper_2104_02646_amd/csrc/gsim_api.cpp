@@ -401,7 +401,7 @@ int upload_tiles(gsim_model* m, void* stream) {
     std::vector<Tile> et, pt;
     int rows_e = 0;
     natural_tiles(m, false, m->block * m->items, m->etiles_nat, rows_e);
-    natural_tiles(m, true, m->block * m->items, m->ptiles_nat, m->n_ptile_rows);
+    natural_tiles(m, true, m->pblock * m->pitems, m->ptiles_nat, m->n_ptile_rows);
     xcd_order(m->etiles_nat, TILE_TET, 0, et, m->n_etiles);
     xcd_order(m->ptiles_nat, TILE_PART, m->n_ptile_rows, pt, m->n_ptiles);
     hipStream_t s = (hipStream_t)stream;
@@ -410,7 +410,7 @@ int upload_tiles(gsim_model* m, void* stream) {
     // body particle-tile ranges (contact / loss partial rows) depend on the tile size
     BodyDev<T>* bodies = reinterpret_cast<BodyDev<T>*>(m->bodies_host.data());
     int row = 0;
-    const int tile = m->block * m->items;
+    const int tile = m->pblock * m->pitems;
     for (int b = 0; b < m->nb; ++b) {
         bodies[b].pt0 = row;
         row += (int)((m->poff[b + 1] - m->poff[b] + tile - 1) / tile);
@@ -491,11 +491,11 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
         switch (l.op) {
             case OP_FWD:
                 LAUNCH_TRY(timed(m, 0, stream, [&] { return launch_elem_fwd<T>(md, sd, c.et, m->n_etiles, m->block, m->items, stream); }), "element pass");
-                LAUNCH_TRY(timed(m, 1, stream, [&] { return launch_part_fwd<T>(md, sd, c.pt, m->n_ptiles, m->block, m->items, stream); }), "particle pass");
+                LAUNCH_TRY(timed(m, 1, stream, [&] { return launch_part_fwd<T>(md, sd, c.pt, m->n_ptiles, m->pblock, m->pitems, stream); }), "particle pass");
                 break;
             case OP_ADJ:
                 LAUNCH_TRY(timed(m, 2, stream, [&] { return launch_elem_adj<T>(md, sd, c.et, m->n_etiles, m->block, m->items, stream); }), "element adjoint");
-                LAUNCH_TRY(timed(m, 3, stream, [&] { return launch_part_adj<T>(md, sd, c.pt, m->n_ptiles, m->block, m->items, stream); }), "particle adjoint");
+                LAUNCH_TRY(timed(m, 3, stream, [&] { return launch_part_adj<T>(md, sd, c.pt, m->n_ptiles, m->pblock, m->pitems, stream); }), "particle adjoint");
                 break;
             case OP_FILL_CPART:
                 LAUNCH_TRY(launch_fill<T>((T*)(m->ws + m->L.cpart), 4 * (int64_t)(m->n_ptile_rows + 1), T(0), stream), "clear");
@@ -504,7 +504,7 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
                 LAUNCH_TRY(launch_contact_reduce<T>(md, sd, m->nb, stream), "contact reduce");
                 break;
             case OP_LOSS:
-                LAUNCH_TRY(launch_loss<T>(md, sd, c.pt, m->n_ptiles, m->block, m->items, m->nb, stream), "loss");
+                LAUNCH_TRY(launch_loss<T>(md, sd, c.pt, m->n_ptiles, m->pblock, m->pitems, m->nb, stream), "loss");
                 break;
         }
     }
@@ -979,6 +979,29 @@ int gsim_model_destroy(gsim_model* m) {
     return GSIM_OK;
 }
 
+int gsim_model_set_launch(gsim_model* m, int pass, int block, int items) {
+    if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    if (pass != 0 && pass != 1) return fail(GSIM_E_INVALID, "pass must be 0 (element) or 1 (particle)");
+    if (block < 64 || block > 512 || block % 64) return fail(GSIM_E_INVALID, "block must be 64..512, multiple of 64");
+    if (items < 1 || items > 8) return fail(GSIM_E_INVALID, "items must be 1..8");
+    int& b = pass == 0 ? m->block : m->pblock;
+    int& i = pass == 0 ? m->items : m->pitems;
+    if (b == block && i == items) return GSIM_OK;
+    // the tile lists are rewritten in place: wait until no launch can still read them
+    HIP_TRY(hipDeviceSynchronize(), "synchronize before retiling");
+    b = block;
+    i = items;
+    return guarded<double>([&]() { return m->dtype == GSIM_F64 ? upload_tiles<double>(m, nullptr) : upload_tiles<float>(m, nullptr); });
+}
+
+int gsim_model_get_launch(const gsim_model* m, int pass, int* block, int* items) {
+    if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    if (pass != 0 && pass != 1) return fail(GSIM_E_INVALID, "pass must be 0 (element) or 1 (particle)");
+    if (block) *block = pass == 0 ? m->block : m->pblock;
+    if (items) *items = pass == 0 ? m->items : m->pitems;
+    return GSIM_OK;
+}
+
 int gsim_model_set_exec(gsim_model* m, int exec, int block, int items) {
     if (!m) return fail(GSIM_E_INVALID, "NULL model");
     if (exec != GSIM_EXEC_PLAIN && exec != GSIM_EXEC_GRAPH && exec != GSIM_EXEC_FUSED)
@@ -987,10 +1010,11 @@ int gsim_model_set_exec(gsim_model* m, int exec, int block, int items) {
     if (block && (block < 64 || block > 512 || block % 64)) return fail(GSIM_E_INVALID, "block must be 64..512, multiple of 64");
     if (items && (items < 1 || items > 8)) return fail(GSIM_E_INVALID, "items must be 1..8");
     m->exec = exec;
-    if ((block && block != m->block) || (items && items != m->items)) {
-        if (block) m->block = block;
-        if (items) m->items = items;
-        return guarded<double>([&]() { return m->dtype == GSIM_F64 ? upload_tiles<double>(m, nullptr) : upload_tiles<float>(m, nullptr); });
+    for (int pass = 0; pass < 2; ++pass) {
+        int b = 0, i = 0;
+        gsim_model_get_launch(m, pass, &b, &i);
+        int rc = gsim_model_set_launch(m, pass, block ? block : b, items ? items : i);
+        if (rc) return rc;
     }
     return GSIM_OK;
 }

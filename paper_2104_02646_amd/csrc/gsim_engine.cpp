@@ -425,7 +425,7 @@ int tick(gsim_engine* E, int* n_live, int* n_queued) {
         const ModelDev<float>* own = reinterpret_cast<const ModelDev<float>*>(m->ws + m->L.model);
         const Tile* own_pt = reinterpret_cast<const Tile*>(m->ws + m->L.ptiles);
         if (ops[i] == OP_LOSS)
-            LAUNCH_TRY(launch_loss<float>(own, dsd + i, own_pt, m->n_ptiles, m->block, m->items, 1, E->stream), "loss");
+            LAUNCH_TRY(launch_loss<float>(own, dsd + i, own_pt, m->n_ptiles, m->pblock, m->pitems, 1, E->stream), "loss");
         if (ops[i] == OP_FIN) LAUNCH_TRY(launch_contact_reduce<float>(own, dsd + i, 1, E->stream), "contact reduce");
     }
     // 5. batched passes over all queries' tiles

@@ -72,7 +72,9 @@ struct gsim_model {
     char* ws = nullptr;
     gsim::Layout L{};
     std::vector<int64_t> poff, eoff, toff, hoff;
-    int exec = GSIM_EXEC_PLAIN, block = 256, items = 1;
+    int exec = GSIM_EXEC_PLAIN;
+    int block = 256, items = 1;    // element passes: threads per workgroup, elements per thread
+    int pblock = 256, pitems = 1;  // particle passes
     int n_etiles = 0, n_ptiles = 0;   // launched grid sizes (including XCD padding)
     int n_ptile_rows = 0;             // real particle tiles (contact / loss partial rows)
     std::vector<char> bodies_host;    // BodyDev<T>[nb] as last uploaded
