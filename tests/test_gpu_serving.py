@@ -19,6 +19,12 @@ def sv():
     return serve
 
 
+def _table_bytes(sv, max_live, max_tiles):
+    """Pool bytes the engine keeps for its own per-tick tables."""
+    probe = sv.Engine(pool_bytes=64 << 20, max_live=max_live, max_tiles=max_tiles)
+    return (64 << 20) - probe.stats()["pool_free"]
+
+
 def mixed_queries():
     qs = []
     for i, (kind, size, T, K) in enumerate([("tet", 800, 60, 10), ("cloth", 16, 45, 7), ("tet", 3000, 80, 20),
@@ -72,7 +78,7 @@ def test_admission_by_footprint_fifo(sv):
         b.target = W.synthetic_target(b, 90 + i)
     qbs = [sv.QueryBuffers(b, T, K) for b, T, K in qs]
     need = max(qb.bytes() for qb in qbs)
-    tables = 4 * (1 << 20)
+    tables = _table_bytes(sv, 16, 1 << 14)
     eng = sv.Engine(pool_bytes=int(2.5 * need) + tables, max_live=16, max_tiles=1 << 14)
     for qb in qbs:
         eng.submit(qb)
@@ -97,7 +103,7 @@ def test_rejects_query_larger_than_pool(sv):
     b = W.batch_body(52000, lo=4000, hi=4000)
     b.target = W.synthetic_target(b, 1)
     qb = sv.QueryBuffers(b, 100, 10)
-    eng = sv.Engine(pool_bytes=qb.bytes() // 2 + 8 * (1 << 20), max_live=4, max_tiles=1 << 14)
+    eng = sv.Engine(pool_bytes=qb.bytes() // 2 + _table_bytes(sv, 4, 1 << 14), max_live=4, max_tiles=1 << 14)
     with pytest.raises(gsim.GsimError) as ei:
         eng.submit(qb)
     assert ei.value.code == gsim.GSIM_E_WORKSPACE
