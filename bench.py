@@ -36,18 +36,30 @@ METRIC = "element-steps/s fwd+adjoint (FP32, grad err ≤1e-3); served p50/p99 q
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_bytes(kernel, ne, nt, nh, np_, nslot, K):
-    """Compulsory bytes one launch of `kernel` moves (FP32 / int32), each array touched
-    once: element records, gathered particle data (once per particle), gather slots,
-    outputs, gradient read-modify-writes."""
+def kernel_bytes(kernel, ne, np_, nslot, T, K):
+    """Compulsory bytes (FP32 / int32) that all launches of `kernel` in one bench step
+    move, each array touched once per pass: element records, gathered particle data
+    (once per particle), gather slots, outputs, gradient read-modify-writes.  Tet
+    bodies only (the batch workload)."""
+    nseg = -(-T // K)
+    fwd_passes = T + (T - nseg)  # rollout + segment recompute
     if kernel == "element_fwd":
-        return 144 * ne + 96 * nt + 100 * nh + 12 * np_
+        return fwd_passes * (144 * ne + 12 * np_)
     if kernel == "particle_fwd":
-        return 57 * np_ + 16 * nslot + 24 * np_ // K
+        return fwd_passes * (57 * np_ + 16 * nslot) + nseg * 24 * np_
     if kernel == "element_adj":
-        return 160 * ne + 104 * nt + 100 * nh + 41 * np_
+        return T * (160 * ne + 41 * np_)
     if kernel == "particle_adj":
-        return 89 * np_ + 16 * nslot
+        return T * (89 * np_ + 16 * nslot)
+    if kernel == "fused_fwd":
+        # per step: tet record 56 + mu, lambda 8 + original index 4; mass, pinned 5 per particle;
+        # per launch: state in 24 (+ out 24 for the rollout); stores: checkpoints, segment states
+        return (fwd_passes * (68 * ne + 5 * np_) + (1 + nseg) * 24 * np_ + 24 * np_
+                + nseg * 24 * np_ + (T - nseg) * 24 * np_)
+    if kernel == "fused_adj":
+        # per step: record 68 + mu-bar, lambda-bar read-modify-write 16 per tet; per particle:
+        # state x, v 24, adjoint state read+write 48, mass, pinned 5, mass-bar read-modify-write 8
+        return T * (84 * ne + 85 * np_) + nseg * 48 * np_
     raise ValueError(kernel)
 
 
@@ -88,7 +100,7 @@ def main():
     ap.add_argument("--bodies", type=int, default=256)
     ap.add_argument("--sim-steps", type=int, default=100)
     ap.add_argument("--ckpt-every", type=int, default=10)
-    ap.add_argument("--exec", choices=("graph", "plain"), default="graph")
+    ap.add_argument("--exec", choices=("fused", "graph", "plain"), default="fused")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--items", type=int, default=1)
     ap.add_argument("--cpu-tets", type=int, default=15000, help="oracle sample size (tets)")
@@ -130,7 +142,8 @@ def main():
     t_plan = time.perf_counter()
     with torch.cuda.stream(stream):
         model = gsim.Model(bodies, torch.float32, max_steps=T, ckpt_every=K, device=dev)
-        model.set_exec(gsim.EXEC_GRAPH if args.exec == "graph" else gsim.EXEC_PLAIN, args.block, args.items)
+        exec_mode = {"fused": gsim.EXEC_FUSED, "graph": gsim.EXEC_GRAPH, "plain": gsim.EXEC_PLAIN}[args.exec]
+        model.set_exec(exec_mode, args.block, args.items)
         p = model.params_from_bodies()
         x0 = gsim.soa(np.concatenate([b.x0 for b in bodies]))
         v0 = gsim.soa(np.concatenate([b.v0 for b in bodies]))
@@ -167,8 +180,9 @@ def main():
             model.rollout(p, x0, v0, T, out=(xT, vT), stream=stream)
         torch.cuda.synchronize()
         sec_fwd = (time.perf_counter() - t0) / args.steps
-        # per-kernel durations: one more bench step in plain execution with event timing
-        model.set_exec(gsim.EXEC_PLAIN)
+        # per-kernel durations: one more bench step with HIP events around every launch
+        # (graph replay cannot carry them: the two-pass path is timed with plain launches)
+        model.set_exec(gsim.EXEC_FUSED if args.exec == "fused" else gsim.EXEC_PLAIN)
         model.set_timing()
         bench_step()
         torch.cuda.synchronize()
@@ -176,13 +190,27 @@ def main():
         model.set_timing(())
         g_np = {k: t.detach().double().cpu().numpy() for k, t in g.items()}
         xT_np = gsim.aos(xT)
+        # the other batched execution, same model and buffers
+        other = gsim.EXEC_GRAPH if args.exec == "fused" else gsim.EXEC_FUSED
+        alt = None
+        try:
+            model.set_exec(other)
+            bench_step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                bench_step()
+            torch.cuda.synchronize()
+            alt = (time.perf_counter() - t0) / args.steps
+        except gsim.GsimError as e:
+            alt = str(e)
 
     value = ne * T / sec
     kern = {}
     for k, (n, ms) in timing.items():
         if n:
             avg = ms / n
-            by = kernel_bytes(k, ne, 0, 0, np_, nslot, K)
+            by = kernel_bytes(k, ne, np_, nslot, T, K) / n
             kern[k] = {"launches": n, "avg_us": avg * 1e3, "total_ms": ms, "bytes_per_launch": by,
                        "GBps": by / (avg * 1e-3) / 1e9}
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
@@ -207,6 +235,9 @@ def main():
                              "bytes_per_elem_step": (2 * bf + ba) / ne},
         "setup_s": {"generate": t_gen, "plan_and_upload": t_plan},
     }
+    name = {gsim.EXEC_GRAPH: "two_pass_graph", gsim.EXEC_FUSED: "fused"}[other]
+    result[name] = ({"value": ne * T / alt, "ms_per_step": alt * 1e3} if isinstance(alt, float)
+                    else {"unavailable": alt})
 
     # plain one-body-per-launch path on the same GPU
     if not args.no_plain:

@@ -70,7 +70,10 @@ enum {
     GSIM_EXEC_PLAIN = 0,   /* two kernel launches per step (element pass, particle pass) */
     GSIM_EXEC_GRAPH = 1,   /* the same launches captured once into a hipGraph and replayed
                               (needs a non-default stream) */
-    GSIM_EXEC_FUSED = 2    /* persistent fused launch: whole step segments per launch */
+    GSIM_EXEC_FUSED = 2    /* one workgroup per body keeps the body in LDS and runs a whole
+                              checkpoint segment of steps per launch (forward rollout: one
+                              launch; backward: two launches per segment).  Needs every
+                              body's particles to fit in LDS (36 B each for FP32) */
 };
 
 const char* gsim_last_error(void);
@@ -148,7 +151,8 @@ int gsim_model_get_launch(const gsim_model* model, int pass, int* block, int* it
 
 /* Kernel timing for measurement: with bit k of `mask` set, every launch of
  * kernel k is bracketed by HIP events on its stream (k: 0 element pass,
- * 1 particle pass, 2 element adjoint pass, 3 particle adjoint pass).  Plain
+ * 1 particle pass, 2 element adjoint pass, 3 particle adjoint pass, 4 fused
+ * forward segment, 5 fused adjoint segment).  Plain
  * execution only (GSIM_E_UNSUPPORTED under GSIM_EXEC_GRAPH).
  * gsim_model_read_timing waits for the recorded events and returns (then
  * clears) kernel k's launch count and summed duration in milliseconds. */

@@ -115,6 +115,67 @@ double rest_angle(const D3 x[4]) {
     return std::atan2(-dt3(crs(N1, N2), E) / el, dt3(N1, N2));
 }
 
+// Greedy colouring for the fused path: per body and element kind, each element
+// (in index order) takes the smallest colour none of its particles has seen yet.
+// Elements are then listed by (colour, index) with colour boundaries in coff.
+void colour_elements(gsim_plan* P) {
+    const int nb = P->nb;
+    P->ftet.assign(P->ne, 0);
+    P->ftri.assign(P->nt, 0);
+    P->fhin.assign(P->nh, 0);
+    P->coff.clear();
+    P->cbase.assign(3 * nb, 0);
+    P->ncol.assign(3 * nb, 0);
+    P->fused_ok = true;
+    std::vector<uint64_t> used_lo, used_hi;
+    for (int b = 0; b < nb; ++b) {
+        const int64_t p0 = P->poff[b], npb = P->poff[b + 1] - p0;
+        for (int kind = 0; kind < 3; ++kind) {
+            const std::vector<int64_t>& off = kind == 0 ? P->eoff : kind == 1 ? P->toff : P->hoff;
+            const std::vector<int32_t>& idx = kind == 0 ? P->tet_idx : kind == 1 ? P->tri_idx : P->hin_idx;
+            std::vector<int32_t>& ford = kind == 0 ? P->ftet : kind == 1 ? P->ftri : P->fhin;
+            const int64_t n = kind == 0 ? P->ne : kind == 1 ? P->nt : P->nh;
+            const int nc = kind == 1 ? 3 : 4;
+            const int64_t e0 = off[b], e1 = off[b + 1];
+            used_lo.assign(npb, 0);
+            used_hi.assign(npb, 0);
+            std::vector<int> col(e1 - e0, 0);
+            int ncolours = 0;
+            for (int64_t e = e0; e < e1; ++e) {
+                uint64_t lo = 0, hi = 0;
+                for (int c = 0; c < nc; ++c) {
+                    const int64_t li = idx[c * n + e] - p0;
+                    lo |= used_lo[li];
+                    hi |= used_hi[li];
+                }
+                int k = -1;
+                if (~lo) k = __builtin_ctzll(~lo);
+                else if (~hi) k = 64 + __builtin_ctzll(~hi);
+                if (k < 0) {
+                    P->fused_ok = false;
+                    k = 0;
+                }
+                col[e - e0] = k;
+                ncolours = std::max(ncolours, k + 1);
+                for (int c = 0; c < nc; ++c) {
+                    const int64_t li = idx[c * n + e] - p0;
+                    if (k < 64) used_lo[li] |= 1ull << k;
+                    else used_hi[li] |= 1ull << (k - 64);
+                }
+            }
+            // counting sort by colour (stable: index order inside a colour)
+            std::vector<int64_t> start(ncolours + 1, 0);
+            for (int64_t e = e0; e < e1; ++e) start[col[e - e0] + 1]++;
+            for (int k = 0; k < ncolours; ++k) start[k + 1] += start[k];
+            P->cbase[3 * b + kind] = (int32_t)P->coff.size();
+            P->ncol[3 * b + kind] = ncolours;
+            for (int k = 0; k <= ncolours; ++k) P->coff.push_back((int32_t)(e0 + start[k]));
+            std::vector<int64_t> pos(start.begin(), start.end() - 1);
+            for (int64_t e = e0; e < e1; ++e) ford[e0 + pos[col[e - e0]]++] = (int32_t)e;
+        }
+    }
+}
+
 int build_plan(const gsim_model_desc* d, gsim_plan* P) {
     if (!d) return fail(GSIM_E_INVALID, "NULL description");
     if (d->dtype != GSIM_F32 && d->dtype != GSIM_F64) return fail(GSIM_E_INVALID, "dtype must be 32 or 64");
@@ -300,6 +361,7 @@ int build_plan(const gsim_model_desc* d, gsim_plan* P) {
         for (int c = 0; c < 3; ++c) P->tri_slot[c * nt + t] = slot_of(P->tri_idx[c * nt + t]);
     for (int64_t h = 0; h < nh; ++h)
         for (int c = 0; c < 4; ++c) P->hin_slot[c * nh + h] = slot_of(P->hin_idx[c * nh + h]);
+    colour_elements(P);
     return GSIM_OK;
 }
 
@@ -356,6 +418,18 @@ Layout make_layout(const gsim_plan* P, int max_steps) {
     L.lpart = take((cap_p + 1) * sizeof(T));
     L.fbuf = take(2 * 6 * np * sizeof(T));
     L.abuf = take(2 * 6 * np * sizeof(T));
+    L.f_tet_idx = take(4 * ne * 4);
+    L.f_tet_dinv = take(9 * ne * sizeof(T));
+    L.f_tet_vol = take(ne * sizeof(T));
+    L.f_tet_orig = take(ne * 4);
+    L.f_tri_idx = take(3 * nt * 4);
+    L.f_tri_dinv = take(4 * nt * sizeof(T));
+    L.f_tri_area = take(nt * sizeof(T));
+    L.f_tri_orig = take(nt * 4);
+    L.f_hin_idx = take(4 * nh * 4);
+    L.f_hin_phi0 = take(nh * sizeof(T));
+    L.coff = take(P->coff.size() * 4 + 4);
+    L.border = take(P->nb * 4 + 4);
     L.table_cap = 4 * (int64_t)max_steps + 8;
     L.table = take(sizeof(StepDev<T>) * L.table_cap);
     L.total = align_up(o, 256);
@@ -453,7 +527,20 @@ Ctx<T> ctx(gsim_model* m) {
 }
 
 // One launch of the sequence a call replays: pass kind and its table row.
-enum Op : int { OP_FWD = 0, OP_ADJ = 1, OP_FILL_CPART = 2, OP_CONTACT_REDUCE = 3, OP_LOSS = 4 };
+enum Op : int {
+    OP_FWD = 0,
+    OP_ADJ = 1,
+    OP_FILL_CPART = 2,
+    OP_CONTACT_REDUCE = 3,
+    OP_LOSS = 4,
+    OP_FUSED_FWD = 5,  // whole segment of forward steps, one workgroup per body
+    OP_FUSED_ADJ = 6   // whole segment of adjoint steps, one workgroup per body
+};
+
+template <typename T>
+size_t fused_lds(const gsim_model* m, bool adjoint) {
+    return (size_t)(adjoint ? FUSED_ADJ_LDS_WORDS : FUSED_FWD_LDS_WORDS) * sizeof(T) * (size_t)m->max_body_np;
+}
 struct Launch {
     int op;
     int64_t row;
@@ -502,6 +589,16 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
                 break;
             case OP_CONTACT_REDUCE:
                 LAUNCH_TRY(launch_contact_reduce<T>(md, sd, m->nb, stream), "contact reduce");
+                break;
+            case OP_FUSED_FWD:
+                LAUNCH_TRY(timed(m, 4, stream, [&] {
+                    return launch_fused_fwd<T>(md, sd, (const int32_t*)(m->ws + m->L.border), m->nb, fused_lds<T>(m, false), stream);
+                }), "fused forward");
+                break;
+            case OP_FUSED_ADJ:
+                LAUNCH_TRY(timed(m, 5, stream, [&] {
+                    return launch_fused_adj<T>(md, sd, (const int32_t*)(m->ws + m->L.border), m->nb, fused_lds<T>(m, true), stream);
+                }), "fused adjoint");
                 break;
             case OP_LOSS:
                 LAUNCH_TRY(launch_loss<T>(md, sd, c.pt, m->n_ptiles, m->pblock, m->pitems, m->nb, stream), "loss");
@@ -589,12 +686,95 @@ int64_t region_backward(const gsim_model* m) { return m->max_steps + 2; }
 int64_t region_step(const gsim_model* m) { return 3 * (int64_t)m->max_steps + 4; }
 int64_t region_misc(const gsim_model* m) { return 4 * (int64_t)m->max_steps + 6; }
 
+// Fused-path sequences: each launch runs a whole segment of steps for every body.
+template <typename T>
+StepDev<T> fused_row(const gsim_params* p, const gsim_grads* g) {
+    StepDev<T> r;
+    std::memset(&r, 0, sizeof r);
+    fill_params<T>(r, p, g);
+    return r;
+}
+
+template <typename T>
+int do_fused_forward(gsim_model* m, const gsim_params* p, const T* x, const T* v, T* xo, T* vo, T* ckpt, int n,
+                     int64_t row0, long long key, void* stream) {
+    std::vector<StepDev<T>> rows(1, fused_row<T>(p, nullptr));
+    StepDev<T>& r = rows[0];
+    r.x = x;
+    r.v = v;
+    r.xo = xo;
+    r.vo = vo;
+    r.ckx = ckpt;
+    r.ckv = ckpt ? ckpt + 3 * m->np : nullptr;
+    r.ckpt_every = m->K;
+    r.nsteps = n;
+    r.t_base = 0;
+    int rc = upload_rows<T>(m, row0, rows, stream);
+    if (rc) return rc;
+    std::vector<Launch> seq{{OP_FUSED_FWD, row0}};
+    return execute<T>(m, key, seq, stream);
+}
+
+template <typename T>
+int do_fused_rollout_backward(gsim_model* m, const gsim_params* p, const T* ck, int n, T* seg, gsim_state af,
+                              gsim_state ai, const gsim_grads* g, void* stream) {
+    Ctx<T> c = ctx<T>(m);
+    const int64_t S = 6 * c.np, np = c.np;
+    const int K = m->K, nseg = (n + K - 1) / K;
+    std::vector<StepDev<T>> rows;
+    std::vector<Launch> seq;
+    const int64_t r0 = region_backward(m);
+    for (int s = nseg - 1, q = 0; s >= 0; --s, ++q) {
+        const int t0 = s * K, L = std::min(n, t0 + K) - t0;
+        if (L > 1) {  // recompute states t0+1 .. t0+L-1 into seg[0 .. L-2]
+            StepDev<T> r = fused_row<T>(p, nullptr);
+            r.x = ck + s * S;
+            r.v = r.x + 3 * np;
+            r.seg = seg;
+            r.nsteps = L - 1;
+            r.t_base = t0;
+            r.ckpt_every = K;
+            rows.push_back(r);
+            seq.push_back({OP_FUSED_FWD, r0 + (int64_t)rows.size() - 1});
+        }
+        StepDev<T> r = fused_row<T>(p, g);
+        r.x = ck + s * S;
+        r.v = r.x + 3 * np;
+        r.seg_in = seg;
+        r.nsteps = L;
+        r.t_base = t0;
+        r.ckpt_every = K;
+        if (q == 0) {
+            r.xb = (const T*)af.x;
+            r.vb = (const T*)af.v;
+        } else {
+            r.xb = c.abuf + ((q - 1) & 1) * S;
+            r.vb = r.xb + 3 * np;
+        }
+        if (s == 0) {
+            r.xbo = (T*)ai.x;
+            r.vbo = (T*)ai.v;
+        } else {
+            r.xbo = c.abuf + (q & 1) * S;
+            r.vbo = r.xbo + 3 * np;
+        }
+        rows.push_back(r);
+        seq.push_back({OP_FUSED_ADJ, r0 + (int64_t)rows.size() - 1});
+    }
+    int rc = upload_rows<T>(m, r0, rows, stream);
+    if (rc) return rc;
+    return execute<T>(m, (7LL << 40) | ((long long)n << 1), seq, stream);
+}
+
 template <typename T>
 int do_step(gsim_model* m, const gsim_params* p, gsim_state in, gsim_state out, int n, void* stream) {
     if (n < 1 || n > m->max_steps) return fail(GSIM_E_INVALID, "n_steps must be in [1, %d]", m->max_steps);
     if (!in.x || !in.v || !out.x || !out.v) return fail(GSIM_E_INVALID, "NULL state");
     int rc = check_params(m, p);
     if (rc) return rc;
+    if (m->exec == GSIM_EXEC_FUSED)
+        return do_fused_forward<T>(m, p, (const T*)in.x, (const T*)in.v, (T*)out.x, (T*)out.v, nullptr, n, region_step(m),
+                                   (8LL << 40) | n, stream);
     Ctx<T> c = ctx<T>(m);
     const int64_t S = 6 * c.np;
     std::vector<StepDev<T>> rows(n);
@@ -641,8 +821,14 @@ int do_step_backward(gsim_model* m, const gsim_params* p, gsim_state s, gsim_sta
     r.vb = (const T*)ap.v;
     r.xbo = (T*)am.x;
     r.vbo = (T*)am.v;
+    r.nsteps = 1;
+    r.ckpt_every = m->K;
     const int64_t r0 = region_misc(m);
     if ((rc = upload_rows<T>(m, r0, rows, stream))) return rc;
+    if (m->exec == GSIM_EXEC_FUSED) {
+        std::vector<Launch> fseq{{OP_FUSED_ADJ, r0}};
+        return execute<T>(m, 9LL << 40, fseq, stream);
+    }
     std::vector<Launch> seq;
     if (g && g->contact) seq.push_back({OP_FILL_CPART, r0});
     seq.push_back({OP_ADJ, r0});
@@ -656,6 +842,9 @@ int do_rollout(gsim_model* m, const gsim_params* p, gsim_state s0, int n, void* 
     if (!s0.x || !s0.v || !sf.x || !sf.v) return fail(GSIM_E_INVALID, "NULL state");
     int rc = check_params(m, p);
     if (rc) return rc;
+    if (m->exec == GSIM_EXEC_FUSED)
+        return do_fused_forward<T>(m, p, (const T*)s0.x, (const T*)s0.v, (T*)sf.x, (T*)sf.v, (T*)ckpt, n,
+                                   region_rollout(m), (6LL << 40) | ((long long)n << 1) | (ckpt ? 1 : 0), stream);
     Ctx<T> c = ctx<T>(m);
     const int64_t S = 6 * c.np;
     std::vector<StepDev<T>> rows(n);
@@ -696,6 +885,8 @@ int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, i
     if (!af.x || !af.v || !ai.x || !ai.v) return fail(GSIM_E_INVALID, "NULL adjoint state");
     int rc = check_params(m, p);
     if (rc) return rc;
+    if (m->exec == GSIM_EXEC_FUSED)
+        return do_fused_rollout_backward<T>(m, p, (const T*)ckpt, n, (T*)seg, af, ai, g, stream);
     Ctx<T> c = ctx<T>(m);
     const int64_t S = 6 * c.np, np = c.np;
     const int K = m->K;
@@ -832,6 +1023,46 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     chk(up(L.gbase, P->gbase.data(), P->gbase.size() * 4));
     chk(up(L.pdeg, P->pdeg.data(), P->pdeg.size() * 4));
     chk(up(L.pinned, P->pinned.data(), P->pinned.size()));
+    // colour-ordered copies of the element records (fused path)
+    auto perm_i = [](const std::vector<int32_t>& a, const std::vector<int32_t>& ord, int rows, int64_t n) {
+        std::vector<int32_t> out(a.size());
+        for (int r = 0; r < rows; ++r)
+            for (int64_t e = 0; e < n; ++e) out[r * n + e] = a[r * n + ord[e]];
+        return out;
+    };
+    auto perm_t = [](const std::vector<T>& a, const std::vector<int32_t>& ord, int rows, int64_t n) {
+        std::vector<T> out(a.size());
+        for (int r = 0; r < rows; ++r)
+            for (int64_t e = 0; e < n; ++e) out[r * n + e] = a[r * n + ord[e]];
+        return out;
+    };
+    std::vector<int32_t> f_tet_idx = perm_i(P->tet_idx, P->ftet, 4, P->ne), f_tri_idx = perm_i(P->tri_idx, P->ftri, 3, P->nt),
+                         f_hin_idx = perm_i(P->hin_idx, P->fhin, 4, P->nh);
+    std::vector<T> f_tet_dinv = perm_t(tet_dinv, P->ftet, 9, P->ne), f_tet_vol = perm_t(tet_vol, P->ftet, 1, P->ne),
+                   f_tri_dinv = perm_t(tri_dinv, P->ftri, 4, P->nt), f_tri_area = perm_t(tri_area, P->ftri, 1, P->nt),
+                   f_hin_phi0 = perm_t(hin_phi0, P->fhin, 1, P->nh);
+    chk(up(L.f_tet_idx, f_tet_idx.data(), f_tet_idx.size() * 4));
+    chk(up(L.f_tet_dinv, f_tet_dinv.data(), f_tet_dinv.size() * sizeof(T)));
+    chk(up(L.f_tet_vol, f_tet_vol.data(), f_tet_vol.size() * sizeof(T)));
+    chk(up(L.f_tet_orig, P->ftet.data(), P->ftet.size() * 4));
+    chk(up(L.f_tri_idx, f_tri_idx.data(), f_tri_idx.size() * 4));
+    chk(up(L.f_tri_dinv, f_tri_dinv.data(), f_tri_dinv.size() * sizeof(T)));
+    chk(up(L.f_tri_area, f_tri_area.data(), f_tri_area.size() * sizeof(T)));
+    chk(up(L.f_tri_orig, P->ftri.data(), P->ftri.size() * 4));
+    chk(up(L.f_hin_idx, f_hin_idx.data(), f_hin_idx.size() * 4));
+    chk(up(L.f_hin_phi0, f_hin_phi0.data(), f_hin_phi0.size() * sizeof(T)));
+    chk(up(L.coff, P->coff.data(), P->coff.size() * 4));
+    // fused launch order: largest bodies first (they bound the makespan)
+    std::vector<int32_t> border(P->nb);
+    for (int b = 0; b < P->nb; ++b) border[b] = b;
+    std::stable_sort(border.begin(), border.end(), [&](int32_t a, int32_t c) {
+        const int64_t wa = (P->eoff[a + 1] - P->eoff[a]) + (P->toff[a + 1] - P->toff[a]) + (P->hoff[a + 1] - P->hoff[a]);
+        const int64_t wc = (P->eoff[c + 1] - P->eoff[c]) + (P->toff[c + 1] - P->toff[c]) + (P->hoff[c + 1] - P->hoff[c]);
+        return wa > wc;
+    });
+    chk(up(L.border, border.data(), border.size() * 4));
+    m->fused_ok = P->fused_ok;
+    for (int b = 0; b < P->nb; ++b) m->max_body_np = std::max<int64_t>(m->max_body_np, P->poff[b + 1] - P->poff[b]);
     std::vector<BodyDev<T>> bodies(P->nb);
     for (int b = 0; b < P->nb; ++b) {
         BodyDev<T>& B = bodies[b];
@@ -840,6 +1071,10 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
         B.np = P->poff[b + 1] - P->poff[b];
         B.contact_on = P->contact_on[b];
         B.g0 = P->body_g0[b];
+        for (int k = 0; k < 3; ++k) {
+            B.cbase[k] = P->cbase[3 * b + k];
+            B.ncol[k] = P->ncol[3 * b + k];
+        }
         B.dt = (T)P->dt[b];
         for (int c = 0; c < 3; ++c) B.g[c] = (T)P->grav[3 * b + c];
         for (int c = 0; c < 4; ++c) B.plane[c] = (T)P->plane[4 * b + c];
@@ -873,6 +1108,17 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     M.slots = (T*)(ws + L.slots);
     M.cpart = (T*)(ws + L.cpart);
     M.lpart = (T*)(ws + L.lpart);
+    M.f_tet_idx = (const int32_t*)(ws + L.f_tet_idx);
+    M.f_tet_dinv = (const T*)(ws + L.f_tet_dinv);
+    M.f_tet_vol = (const T*)(ws + L.f_tet_vol);
+    M.f_tet_orig = (const int32_t*)(ws + L.f_tet_orig);
+    M.f_tri_idx = (const int32_t*)(ws + L.f_tri_idx);
+    M.f_tri_dinv = (const T*)(ws + L.f_tri_dinv);
+    M.f_tri_area = (const T*)(ws + L.f_tri_area);
+    M.f_tri_orig = (const int32_t*)(ws + L.f_tri_orig);
+    M.f_hin_idx = (const int32_t*)(ws + L.f_hin_idx);
+    M.f_hin_phi0 = (const T*)(ws + L.f_hin_phi0);
+    M.coff = (const int32_t*)(ws + L.coff);
     chk(up(L.model, &M, sizeof M));
     m->md_host.assign(reinterpret_cast<const char*>(&M), reinterpret_cast<const char*>(&M) + sizeof M);
     chk(hipHostMalloc((void**)&m->stage, sizeof(StepDev<T>) * L.table_cap, hipHostMallocDefault));
@@ -1006,7 +1252,17 @@ int gsim_model_set_exec(gsim_model* m, int exec, int block, int items) {
     if (!m) return fail(GSIM_E_INVALID, "NULL model");
     if (exec != GSIM_EXEC_PLAIN && exec != GSIM_EXEC_GRAPH && exec != GSIM_EXEC_FUSED)
         return fail(GSIM_E_INVALID, "unknown exec %d", exec);
-    if (exec == GSIM_EXEC_FUSED) return fail(GSIM_E_UNSUPPORTED, "fused execution is not available in this build");
+    if (exec == GSIM_EXEC_FUSED) {
+        if (!m->fused_ok) return fail(GSIM_E_UNSUPPORTED, "fused execution: an element kind needs more than 128 colours");
+        int dev = 0, lds_max = 0;
+        HIP_TRY(hipGetDevice(&dev), "get device");
+        HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "device LDS size");
+        const size_t need = m->dtype == GSIM_F64 ? std::max(fused_lds<double>(m, false), fused_lds<double>(m, true))
+                                                 : std::max(fused_lds<float>(m, false), fused_lds<float>(m, true));
+        if (need > (size_t)lds_max)
+            return fail(GSIM_E_UNSUPPORTED, "fused execution: the largest body needs %zu bytes of LDS, the device has %d",
+                        need, lds_max);
+    }
     if (block && (block < 64 || block > 512 || block % 64)) return fail(GSIM_E_INVALID, "block must be 64..512, multiple of 64");
     if (items && (items < 1 || items > 8)) return fail(GSIM_E_INVALID, "items must be 1..8");
     m->exec = exec;
@@ -1029,14 +1285,14 @@ int gsim_model_get_exec(const gsim_model* m, int* exec, int* block, int* items) 
 
 int gsim_model_set_timing(gsim_model* m, int mask) {
     if (!m) return fail(GSIM_E_INVALID, "NULL model");
-    if (mask < 0 || mask > 15) return fail(GSIM_E_INVALID, "timing mask must be in [0, 15]");
+    if (mask < 0 || mask > 63) return fail(GSIM_E_INVALID, "timing mask must be in [0, 63]");
     m->timing_mask = mask;
     return GSIM_OK;
 }
 
 int gsim_model_read_timing(gsim_model* m, int kernel, int64_t* launches, double* total_ms) {
     if (!m) return fail(GSIM_E_INVALID, "NULL model");
-    if (kernel < 0 || kernel > 3) return fail(GSIM_E_INVALID, "kernel must be in [0, 3]");
+    if (kernel < 0 || kernel > 5) return fail(GSIM_E_INVALID, "kernel must be in [0, 5]");
     for (auto& p : m->pending) {
         HIP_TRY(hipEventSynchronize(p.b), "timing sync");
         float ms = 0.f;

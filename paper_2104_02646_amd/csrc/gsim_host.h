@@ -25,6 +25,12 @@ struct gsim_plan {
     std::vector<int32_t> gbase;                    // [n_slices] sliced-ELL slice bases
     std::vector<int32_t> pdeg;                     // [np]
     std::vector<int32_t> body_g0;                  // [nb] first slice of each body
+    // colour-ordered element copies for the fused path: within each body and kind,
+    // elements sorted by (colour, index); no two elements of a colour share a particle
+    bool fused_ok = false;                         // every kind of every body coloured with <= 128 colours
+    std::vector<int32_t> ftet, ftri, fhin;         // fused position -> element index
+    std::vector<int32_t> coff;                     // colour boundaries (fused element positions)
+    std::vector<int32_t> cbase, ncol;              // [nb][3] first entry in coff, number of colours
     std::vector<uint8_t> pinned;                   // [np]
     std::vector<double> dt, grav, plane, kb;       // per body
     std::vector<uint8_t> contact_on;               // per body
@@ -41,6 +47,9 @@ struct Layout {
     size_t hin_idx, hin_slot, hin_phi0;
     size_t gbase, pdeg, pinned, slots, cpart, lpart;
     size_t fbuf, abuf;  // forward / adjoint internal ping-pong states
+    // fused path: colour-ordered element records, colour bounds, body launch order
+    size_t f_tet_idx, f_tet_dinv, f_tet_vol, f_tet_orig, f_tri_idx, f_tri_dinv, f_tri_area, f_tri_orig;
+    size_t f_hin_idx, f_hin_phi0, coff, border;
     size_t table;
     int64_t table_cap;
     size_t total;
@@ -91,6 +100,9 @@ struct gsim_model {
         hipEvent_t a, b;
     };
     std::vector<Pending> pending;
-    double timing_ms[4] = {0, 0, 0, 0};
-    int64_t timing_n[4] = {0, 0, 0, 0};
+    double timing_ms[6] = {0, 0, 0, 0, 0, 0};
+    int64_t timing_n[6] = {0, 0, 0, 0, 0, 0};
+    // fused path
+    bool fused_ok = false;   // colouring succeeded for every body and kind
+    int64_t max_body_np = 0;  // particles of the largest body (dynamic LDS size)
 };

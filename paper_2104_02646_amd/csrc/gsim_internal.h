@@ -41,6 +41,8 @@ struct BodyDev {
     int32_t pt0, pt1;    // particle-tile id range (contact-gradient partials)
     int32_t contact_on;  // ground contact active
     int32_t g0;          // first gather slice of the body
+    int32_t cbase[3];    // fused path: first colour boundary of each element kind in coff
+    int32_t ncol[3];     // fused path: colours of each element kind
     T dt;
     T g[3];
     T plane[4];          // n.x = d
@@ -69,6 +71,19 @@ struct ModelDev {
     T* slots;   // [nslot][4]
     T* cpart;   // [n_ptiles][4] contact-gradient partial sums
     T* lpart;   // [n_ptiles] loss partial sums
+    // fused path: element records in colour order (same SoA layouts), the original
+    // element index of each position (for parameters and gradients), colour bounds
+    const int32_t* f_tet_idx;
+    const T* f_tet_dinv;
+    const T* f_tet_vol;
+    const int32_t* f_tet_orig;
+    const int32_t* f_tri_idx;
+    const T* f_tri_dinv;
+    const T* f_tri_area;
+    const int32_t* f_tri_orig;
+    const int32_t* f_hin_idx;
+    const T* f_hin_phi0;
+    const int32_t* coff;
 };
 
 template <typename T>
@@ -96,6 +111,13 @@ struct StepDev {
     T* g_contact;      // [n_bodies][4]
     const T* target;   // loss target, SoA [3][np]
     T* loss;           // [n_bodies]
+    // fused path
+    T* seg;            // forward: store the state after every step here ([step][x|v][3][np])
+    const T* seg_in;   // adjoint: states t0+1.. of the segment (the state at t0 is x, v)
+    int32_t nsteps;    // steps run by one fused launch
+    int32_t t_base;    // absolute index of its first step (checkpoint slots)
+    int32_t ckpt_every;
+    int32_t pad;
 };
 
 // Host-side launch helpers (defined in gsim_kernels.hip).  `stream` is a hipStream_t.
@@ -118,5 +140,16 @@ int launch_contact_reduce(const ModelDev<T>* md, const StepDev<T>* sd, int n_bod
 template <typename T>
 int launch_loss(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int items,
                 int n_bodies, void* stream);
+// Fused path: one workgroup per body (bodies in `order`), the whole segment of steps
+// in one launch; `lds` bytes of dynamic LDS.
+template <typename T>
+int launch_fused_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t* order, int n_bodies, size_t lds,
+                     void* stream);
+template <typename T>
+int launch_fused_adj(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t* order, int n_bodies, size_t lds,
+                     void* stream);
+const int FUSED_FWD_BLOCK = 1024, FUSED_ADJ_BLOCK = 512;
+// dynamic LDS per particle of the largest body: x, v, f (forward); fbar, xbar-acc, f.fbar (adjoint)
+const int FUSED_FWD_LDS_WORDS = 9, FUSED_ADJ_LDS_WORDS = 7;
 
 }  // namespace gsim

@@ -701,6 +701,306 @@ __global__ void k_fill(T* __restrict__ p, int64_t n, T value) {
         p[i] = value;
 }
 
+
+// ------------------------------------------------------------ fused path ---
+// One workgroup owns one body for a whole segment of steps.  Positions (forward)
+// or adjoint forces (reverse) of the body's particles live in LDS; element
+// contributions are accumulated in LDS colour by colour: the elements of a
+// colour share no particle, so each LDS update is race-free, and every particle
+// receives its contributions in colour order (deterministic).  A workgroup
+// barrier separates colours; nothing else synchronises, and every barrier sits
+// in loops whose trip counts are uniform over the workgroup.
+
+template <typename T>
+__device__ __forceinline__ void lds_add3(T* a, int n, int i, V3<T> v) {
+    a[i] += v.x;
+    a[n + i] += v.y;
+    a[2 * n + i] += v.z;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>* __restrict__ md,
+                                                               const StepDev<T>* __restrict__ sd,
+                                                               const int32_t* __restrict__ order) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const ModelDev<T>& M = md[0];
+    const StepDev<T>& S = sd[0];
+    const int b = order[blockIdx.x];
+    const BodyDev<T>& B = M.bodies[b];
+    const int npb = (int)B.np;
+    const int64_t np = M.np, p0 = B.p0;
+    T* xs = reinterpret_cast<T*>(smem);  // [3][npb] positions
+    T* vs = xs + 3 * npb;                // [3][npb] velocities
+    T* fs = vs + 3 * npb;                // [3][npb] force accumulators
+    const T dt = B.dt;
+    const V3<T> g = mk3(B.g[0], B.g[1], B.g[2]);
+    const bool contact = B.contact_on != 0;
+    T pl[4], cp[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        pl[k] = B.plane[k];
+        cp[k] = contact ? S.contact[4 * b + k] : T(0);
+    }
+    for (int li = threadIdx.x; li < npb; li += blockDim.x) {
+        const V3<T> x = ld3(S.x, np, p0 + li), v = ld3(S.v, np, p0 + li);
+        xs[li] = x.x;
+        xs[npb + li] = x.y;
+        xs[2 * npb + li] = x.z;
+        vs[li] = v.x;
+        vs[npb + li] = v.y;
+        vs[2 * npb + li] = v.z;
+    }
+    const int ncol0 = B.ncol[0], ncol1 = B.ncol[1], ncol2 = B.ncol[2];
+    for (int step = 0; step < S.nsteps; ++step) {
+        const int t = S.t_base + step;
+        const bool ck = S.ckx != nullptr && t % S.ckpt_every == 0;
+        for (int li = threadIdx.x; li < npb; li += blockDim.x) {
+            if (ck) {
+                T* cx = S.ckx + (int64_t)(t / S.ckpt_every) * 6 * np;
+                st3(cx, np, p0 + li, mk3(xs[li], xs[npb + li], xs[2 * npb + li]));
+                st3(cx + 3 * np, np, p0 + li, mk3(vs[li], vs[npb + li], vs[2 * npb + li]));
+            }
+            fs[li] = T(0);
+            fs[npb + li] = T(0);
+            fs[2 * npb + li] = T(0);
+        }
+        __syncthreads();
+        for (int c = 0; c < ncol0; ++c) {
+            const int e0 = M.coff[B.cbase[0] + c], e1 = M.coff[B.cbase[0] + c + 1];
+            for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+                V3<T> x[4], f[4];
+                int li[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    li[q] = (int)(M.f_tet_idx[q * M.ne + e] - p0);
+                    x[q] = mk3(xs[li[q]], xs[npb + li[q]], xs[2 * npb + li[q]]);
+                }
+                T D[9];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) D[q] = M.f_tet_dinv[q * M.ne + e];
+                const int32_t o = M.f_tet_orig[e];
+                tet_force(x, D, M.f_tet_vol[e], S.mu[o], S.lam[o], S.act ? S.act[o] : T(0), f);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) lds_add3(fs, npb, li[q], f[q]);
+            }
+            __syncthreads();
+        }
+        for (int c = 0; c < ncol1; ++c) {
+            const int e0 = M.coff[B.cbase[1] + c], e1 = M.coff[B.cbase[1] + c + 1];
+            for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+                V3<T> x[3], f[3];
+                int li[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    li[q] = (int)(M.f_tri_idx[q * M.nt + e] - p0);
+                    x[q] = mk3(xs[li[q]], xs[npb + li[q]], xs[2 * npb + li[q]]);
+                }
+                T D[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) D[q] = M.f_tri_dinv[q * M.nt + e];
+                tri_force(x, D, M.f_tri_area[e], S.ktri[M.f_tri_orig[e]], f);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) lds_add3(fs, npb, li[q], f[q]);
+            }
+            __syncthreads();
+        }
+        for (int c = 0; c < ncol2; ++c) {
+            const int e0 = M.coff[B.cbase[2] + c], e1 = M.coff[B.cbase[2] + c + 1];
+            for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+                V3<T> x[4], f[4];
+                int li[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    li[q] = (int)(M.f_hin_idx[q * M.nh + e] - p0);
+                    x[q] = mk3(xs[li[q]], xs[npb + li[q]], xs[2 * npb + li[q]]);
+                }
+                hinge_force(x, M.f_hin_phi0[e], B.kb, f);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) lds_add3(fs, npb, li[q], f[q]);
+            }
+            __syncthreads();
+        }
+        // contact + semi-implicit Euler on the workgroup's own particles
+        for (int li = threadIdx.x; li < npb; li += blockDim.x) {
+            const int64_t p = p0 + li;
+            V3<T> f = mk3(fs[li], fs[npb + li], fs[2 * npb + li]);
+            V3<T> x = mk3(xs[li], xs[npb + li], xs[2 * npb + li]);
+            V3<T> v = mk3(vs[li], vs[npb + li], vs[2 * npb + li]);
+            if (contact) f += contact_force(x, v, pl, cp);
+            const T w = inv_mass(M, S, p);
+            const T gate = w > T(0) ? T(1) : T(0);
+            v = v + (f * w + g * gate) * dt;
+            x = x + v * dt;
+            xs[li] = x.x;
+            xs[npb + li] = x.y;
+            xs[2 * npb + li] = x.z;
+            vs[li] = v.x;
+            vs[npb + li] = v.y;
+            vs[2 * npb + li] = v.z;
+            if (S.seg) {
+                T* sx = S.seg + (int64_t)step * 6 * np;
+                st3(sx, np, p, x);
+                st3(sx + 3 * np, np, p, v);
+            }
+        }
+        __syncthreads();
+    }
+    if (S.xo)
+        for (int li = threadIdx.x; li < npb; li += blockDim.x) {
+            st3(S.xo, np, p0 + li, mk3(xs[li], xs[npb + li], xs[2 * npb + li]));
+            st3(S.vo, np, p0 + li, mk3(vs[li], vs[npb + li], vs[2 * npb + li]));
+        }
+}
+
+// Adjoint steps t0 + nsteps - 1 .. t0 of one body.  The state at t0 is (S.x, S.v),
+// later states come from S.seg_in.  The adjoint state is carried in S.xbo / S.vbo
+// (each particle's entries are touched only by its own thread).
+template <typename T>
+__global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>* __restrict__ md,
+                                                               const StepDev<T>* __restrict__ sd,
+                                                               const int32_t* __restrict__ order) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const ModelDev<T>& M = md[0];
+    const StepDev<T>& S = sd[0];
+    const int b = order[blockIdx.x];
+    const BodyDev<T>& B = M.bodies[b];
+    const int npb = (int)B.np;
+    const int64_t np = M.np, p0 = B.p0;
+    T* fbs = reinterpret_cast<T*>(smem);  // [3][npb] adjoint force
+    T* acc = fbs + 3 * npb;               // [4][npb] xbar contributions, f . fbar
+    const T dt = B.dt;
+    const bool contact = B.contact_on != 0;
+    T pl[4], cp[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        pl[k] = B.plane[k];
+        cp[k] = contact ? S.contact[4 * b + k] : T(0);
+    }
+    if (S.xbo != S.xb)
+        for (int li = threadIdx.x; li < npb; li += blockDim.x) {
+            st3(S.xbo, np, p0 + li, ld3(S.xb, np, p0 + li));
+            st3(S.vbo, np, p0 + li, ld3(S.vb, np, p0 + li));
+        }
+    T gc[4] = {T(0), T(0), T(0), T(0)};
+    const int ncol0 = B.ncol[0], ncol1 = B.ncol[1], ncol2 = B.ncol[2];
+    for (int step = S.nsteps - 1; step >= 0; --step) {
+        const T* sx = step == 0 ? S.x : S.seg_in + (int64_t)(step - 1) * 6 * np;
+        const T* sv = step == 0 ? S.v : sx + 3 * np;
+        for (int li = threadIdx.x; li < npb; li += blockDim.x) {
+            const V3<T> vt = ld3(S.vbo, np, p0 + li) + ld3(S.xbo, np, p0 + li) * dt;
+            const V3<T> fb = vt * (dt * inv_mass(M, S, p0 + li));
+            fbs[li] = fb.x;
+            fbs[npb + li] = fb.y;
+            fbs[2 * npb + li] = fb.z;
+            acc[li] = T(0);
+            acc[npb + li] = T(0);
+            acc[2 * npb + li] = T(0);
+            acc[3 * npb + li] = T(0);
+        }
+        __syncthreads();
+        for (int c = 0; c < ncol0; ++c) {
+            const int e0 = M.coff[B.cbase[0] + c], e1 = M.coff[B.cbase[0] + c + 1];
+            for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+                V3<T> x[4], f[4], fb[4], xb[4];
+                int li[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t p = M.f_tet_idx[q * M.ne + e];
+                    li[q] = (int)(p - p0);
+                    x[q] = ld3(sx, np, p);
+                    fb[q] = mk3(fbs[li[q]], fbs[npb + li[q]], fbs[2 * npb + li[q]]);
+                }
+                T D[9];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) D[q] = M.f_tet_dinv[q * M.ne + e];
+                const int32_t o = M.f_tet_orig[e];
+                T gmu, glam;
+                tet_adjoint(x, D, M.f_tet_vol[e], S.mu[o], S.lam[o], S.act ? S.act[o] : T(0), fb, f, xb, gmu, glam);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    lds_add3(acc, npb, li[q], xb[q]);
+                    acc[3 * npb + li[q]] += dot(f[q], fb[q]);
+                }
+                if (S.g_mu) S.g_mu[o] += gmu;
+                if (S.g_lam) S.g_lam[o] += glam;
+            }
+            __syncthreads();
+        }
+        for (int c = 0; c < ncol1; ++c) {
+            const int e0 = M.coff[B.cbase[1] + c], e1 = M.coff[B.cbase[1] + c + 1];
+            for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+                V3<T> x[3], f[3], fb[3], xb[3];
+                int li[3];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    const int32_t p = M.f_tri_idx[q * M.nt + e];
+                    li[q] = (int)(p - p0);
+                    x[q] = ld3(sx, np, p);
+                    fb[q] = mk3(fbs[li[q]], fbs[npb + li[q]], fbs[2 * npb + li[q]]);
+                }
+                T D[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) D[q] = M.f_tri_dinv[q * M.nt + e];
+                const int32_t o = M.f_tri_orig[e];
+                T gk;
+                tri_adjoint(x, D, M.f_tri_area[e], S.ktri[o], fb, f, xb, gk);
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    lds_add3(acc, npb, li[q], xb[q]);
+                    acc[3 * npb + li[q]] += dot(f[q], fb[q]);
+                }
+                if (S.g_ktri) S.g_ktri[o] += gk;
+            }
+            __syncthreads();
+        }
+        for (int c = 0; c < ncol2; ++c) {
+            const int e0 = M.coff[B.cbase[2] + c], e1 = M.coff[B.cbase[2] + c + 1];
+            for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+                V3<T> x[4], f[4], fb[4], xb[4];
+                int li[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t p = M.f_hin_idx[q * M.nh + e];
+                    li[q] = (int)(p - p0);
+                    x[q] = ld3(sx, np, p);
+                    fb[q] = mk3(fbs[li[q]], fbs[npb + li[q]], fbs[2 * npb + li[q]]);
+                }
+                hinge_adjoint(x, M.f_hin_phi0[e], B.kb, fb, f, xb);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    lds_add3(acc, npb, li[q], xb[q]);
+                    acc[3 * npb + li[q]] += dot(f[q], fb[q]);
+                }
+            }
+            __syncthreads();
+        }
+        // contact adjoint and the integrator's adjoint on the workgroup's own particles
+        for (int li = threadIdx.x; li < npb; li += blockDim.x) {
+            const int64_t p = p0 + li;
+            const V3<T> xbp = ld3(S.xbo, np, p);
+            const V3<T> vt = ld3(S.vbo, np, p) + xbp * dt;
+            const V3<T> fb = mk3(fbs[li], fbs[npb + li], fbs[2 * npb + li]);
+            T ds = acc[3 * npb + li];
+            V3<T> xcb = zero3<T>(), vcb = zero3<T>();
+            if (contact) {
+                const V3<T> fc = contact_adjoint(ld3(sx, np, p), ld3(sv, np, p), pl, cp, fb, xcb, vcb, gc);
+                ds += dot(fc, fb);
+            }
+            st3(S.xbo, np, p, xbp + mk3(acc[li], acc[npb + li], acc[2 * npb + li]) + xcb);
+            st3(S.vbo, np, p, vt + vcb);
+            const T w = inv_mass(M, S, p);
+            if (S.g_mass && w > T(0)) S.g_mass[p] += -w * ds;
+        }
+    }
+    if (contact && S.g_contact) {
+        T tot[4];
+        block_sum<T, 4>(gc, tot);
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) S.g_contact[4 * b + k] += tot[k];
+    }
+}
+
 int check_launch() {
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? 0 : (int)e;
@@ -760,6 +1060,25 @@ int launch_loss(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, 
     return check_launch();
 }
 
+template <typename T>
+int launch_fused_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t* order, int n_bodies, size_t lds,
+                     void* stream) {
+    if (n_bodies <= 0) return 0;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused_fwd<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    hipLaunchKernelGGL(k_fused_fwd<T>, dim3(n_bodies), dim3(FUSED_FWD_BLOCK), lds, (hipStream_t)stream, md, sd, order);
+    return check_launch();
+}
+template <typename T>
+int launch_fused_adj(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t* order, int n_bodies, size_t lds,
+                     void* stream) {
+    if (n_bodies <= 0) return 0;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused_adj<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    hipLaunchKernelGGL(k_fused_adj<T>, dim3(n_bodies), dim3(FUSED_ADJ_BLOCK), lds, (hipStream_t)stream, md, sd, order);
+    return check_launch();
+}
+
 #define GSIM_INSTANTIATE(T)                                                                                          \
     template int launch_elem_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
     template int launch_part_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
@@ -767,7 +1086,9 @@ int launch_loss(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, 
     template int launch_part_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
     template int launch_fill<T>(T*, int64_t, T, void*);                                                             \
     template int launch_contact_reduce<T>(const ModelDev<T>*, const StepDev<T>*, int, void*);                       \
-    template int launch_loss<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, int, void*);
+    template int launch_loss<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, int, void*);     \
+    template int launch_fused_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const int32_t*, int, size_t, void*);     \
+    template int launch_fused_adj<T>(const ModelDev<T>*, const StepDev<T>*, const int32_t*, int, size_t, void*);
 
 GSIM_INSTANTIATE(float)
 GSIM_INSTANTIATE(double)

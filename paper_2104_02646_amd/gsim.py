@@ -31,7 +31,7 @@ ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan
                "gsim_loss_mse", "gsim_model_set_timing", "gsim_model_read_timing",
                "gsim_engine_create", "gsim_engine_destroy", "gsim_engine_query_bytes", "gsim_engine_submit",
                "gsim_engine_tick", "gsim_engine_poll", "gsim_engine_stats")
-KERNELS = ("element_fwd", "particle_fwd", "element_adj", "particle_adj")
+KERNELS = ("element_fwd", "particle_fwd", "element_adj", "particle_adj", "fused_fwd", "fused_adj")
 
 
 class GsimError(RuntimeError):
