@@ -92,6 +92,36 @@ def cpu_baseline(bodies, targets, T, budget_tets):
     return sample, tot, dt, out
 
 
+def serving(n_measured, n_warm, ckpt_every, log):
+    """Poisson stream (200 req/s) of tet / cloth gradient queries through the
+    continuous-batching engine and through the one-query-per-launch FIFO path."""
+    import torch
+    from paper_2104_02646_amd import serve, workloads as W
+    trace = W.serving_trace(40, n_measured + n_warm)
+    bodies = [W.query_body(q) for q in trace]
+    work = np.array([(b.ne + b.nt) * q.steps for q, b in zip(trace, bodies)], float)
+    eng = serve.Engine(pool_bytes=8 << 30, max_live=256, max_tiles=1 << 18)
+    lat, wall, _ = serve.replay_trace(trace, bodies, eng, ckpt_every=ckpt_every)
+    st = eng.stats()
+    del eng
+    torch.cuda.synchronize()
+    log("serving: engine done (%.1f s)" % wall)
+    flat, fwall = serve.replay_fifo(trace, bodies, ckpt_every=ckpt_every)
+    log("serving: fifo done (%.1f s)" % fwall)
+    m = slice(n_warm, None)
+    arr = np.array([q.arrival for q in trace])
+    span = arr[-1] - arr[n_warm]
+
+    def summary(l, w):
+        return {"p50_ms": float(np.percentile(l[m], 50) * 1e3), "p99_ms": float(np.percentile(l[m], 99) * 1e3),
+                "mean_ms": float(l[m].mean() * 1e3), "wall_s": w,
+                "req_per_s": float(len(trace) / w), "element_steps_per_s": float(work.sum() / w)}
+    return {"queries": n_measured, "warmup_queries": n_warm, "arrival_rate": 200.0,
+            "trace_span_s": float(span), "engine": dict(summary(lat, wall), mean_live=st["mean_live"],
+                                                        ticks=st["ticks"]),
+            "one_query_per_launch_fifo": summary(flat, fwall)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +136,7 @@ def main():
     ap.add_argument("--cpu-tets", type=int, default=15000, help="oracle sample size (tets)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serve-queries", type=int, default=400, help="measured queries of the serving trace (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device tensor copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -285,6 +316,9 @@ def main():
                                   "sample": "bodies 0..%d of the batch (%d tets), %d steps fwd + loss + adjoint, "
                                             "FP64, single thread" % (sample[-1], tot, T)}
         result["parity_sample"] = {"bodies": len(sample), "max_rel_err": errs}
+    if args.serve_queries > 0:
+        result["serving"] = serving(args.serve_queries, max(20, args.serve_queries // 10), K,
+                                    lambda msg: print(msg, file=sys.stderr, flush=True))
     print(json.dumps(result), flush=True)
 
 

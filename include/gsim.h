@@ -128,6 +128,20 @@ int gsim_plan_sizes(const gsim_plan* plan, int max_steps, int ckpt_every, size_t
 int gsim_plan_counts(const gsim_plan* plan, int64_t* n_particles, int64_t* n_tets, int64_t* n_tris,
                      int64_t* n_hinges, int* n_bodies);
 
+/* Host-only plan introspection (for checking the planner; no device needed).
+ * kind: 0 tets, 1 triangles, 2 hinges.
+ * gsim_plan_colouring: order[i] = element at colour-ordered position i (a
+ * permutation of the kind's elements); bounds[] = colour boundaries over
+ * positions, per body in body order (n_bounds entries written, at most
+ * max_bounds); returns GSIM_E_UNSUPPORTED if colouring failed (> 128 colours).
+ * gsim_plan_gather: slots[c * n + e] = gather slot of corner c of element e;
+ * slice_base[g] and degree[p] describe the sliced-ELL table (corner k of the
+ * particle at lane j of slice g is slot slice_base[g] + 64 k + j). */
+int gsim_plan_colouring(const gsim_plan* plan, int kind, int32_t* order, int32_t* bounds, int max_bounds,
+                        int* n_bounds);
+int gsim_plan_gather(const gsim_plan* plan, int kind, int32_t* slots, int32_t* slice_base, int64_t* n_slices,
+                     int32_t* degree, int64_t* n_slots);
+
 /* Binds a plan to a caller-owned device workspace (>= workspace_bytes of
  * gsim_plan_sizes for the same max_steps / ckpt_every) and uploads the
  * element records on `stream`.  The plan may be destroyed afterwards. */

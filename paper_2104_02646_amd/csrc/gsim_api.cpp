@@ -1175,6 +1175,33 @@ int gsim_plan_destroy(gsim_plan* plan) {
     return GSIM_OK;
 }
 
+int gsim_plan_colouring(const gsim_plan* P, int kind, int32_t* order, int32_t* bounds, int max_bounds, int* n_bounds) {
+    if (!P || kind < 0 || kind > 2) return fail(GSIM_E_INVALID, "bad plan or kind");
+    if (!P->fused_ok) return fail(GSIM_E_UNSUPPORTED, "colouring failed");
+    const std::vector<int32_t>& ord = kind == 0 ? P->ftet : kind == 1 ? P->ftri : P->fhin;
+    if (order) std::copy(ord.begin(), ord.end(), order);
+    int n = 0;
+    for (int b = 0; b < P->nb; ++b) {
+        const int base = P->cbase[3 * b + kind], nc = P->ncol[3 * b + kind];
+        for (int c = 0; c <= nc; ++c, ++n)
+            if (bounds && n < max_bounds) bounds[n] = P->coff[base + c];
+    }
+    if (n_bounds) *n_bounds = n;
+    return n <= max_bounds || !bounds ? GSIM_OK : fail(GSIM_E_WORKSPACE, "bounds array too small (%d needed)", n);
+}
+
+int gsim_plan_gather(const gsim_plan* P, int kind, int32_t* slots, int32_t* slice_base, int64_t* n_slices,
+                     int32_t* degree, int64_t* n_slots) {
+    if (!P || kind < 0 || kind > 2) return fail(GSIM_E_INVALID, "bad plan or kind");
+    const std::vector<int32_t>& sl = kind == 0 ? P->tet_slot : kind == 1 ? P->tri_slot : P->hin_slot;
+    if (slots) std::copy(sl.begin(), sl.end(), slots);
+    if (slice_base) std::copy(P->gbase.begin(), P->gbase.end(), slice_base);
+    if (n_slices) *n_slices = (int64_t)P->gbase.size();
+    if (degree) std::copy(P->pdeg.begin(), P->pdeg.end(), degree);
+    if (n_slots) *n_slots = P->nslot;
+    return GSIM_OK;
+}
+
 int gsim_plan_counts(const gsim_plan* P, int64_t* np, int64_t* ne, int64_t* nt, int64_t* nh, int* nb) {
     if (!P) return fail(GSIM_E_INVALID, "NULL plan");
     if (np) *np = P->np;

@@ -26,7 +26,7 @@ GSIM_E_WORKSPACE, GSIM_E_HIP, GSIM_E_NONFINITE, GSIM_E_UNSUPPORTED = -4, -5, -6,
 EXEC_PLAIN, EXEC_GRAPH, EXEC_FUSED = 0, 1, 2
 
 ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan_destroy", "gsim_plan_sizes",
-               "gsim_plan_counts", "gsim_model_init", "gsim_model_destroy", "gsim_model_set_exec",
+               "gsim_plan_counts", "gsim_plan_colouring", "gsim_plan_gather", "gsim_model_init", "gsim_model_destroy", "gsim_model_set_exec",
                "gsim_model_get_exec", "gsim_model_set_launch", "gsim_model_get_launch", "gsim_step", "gsim_step_backward", "gsim_rollout", "gsim_rollout_backward",
                "gsim_loss_mse", "gsim_model_set_timing", "gsim_model_read_timing",
                "gsim_engine_create", "gsim_engine_destroy", "gsim_engine_query_bytes", "gsim_engine_submit",
@@ -80,6 +80,8 @@ def load():
         lib.gsim_plan_destroy.argtypes = [vp]
         lib.gsim_plan_sizes.argtypes = [vp, ip, ip, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
         lib.gsim_plan_counts.argtypes = [vp] + [C.POINTER(C.c_int64)] * 4 + [C.POINTER(C.c_int)]
+        lib.gsim_plan_colouring.argtypes = [vp, ip, vp, vp, ip, C.POINTER(ip)]
+        lib.gsim_plan_gather.argtypes = [vp, ip, vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
         lib.gsim_model_init.argtypes = [vp, ip, ip, vp, C.c_size_t, vp, C.POINTER(vp)]
         lib.gsim_model_destroy.argtypes = [vp]
         lib.gsim_model_set_exec.argtypes = [vp, ip, ip, ip]
@@ -197,6 +199,29 @@ class Plan:
         _check(lib.gsim_plan_create(C.byref(d), C.byref(h)))
         self._h = h
         self.np, self.ne, self.nt, self.nh, self.nb = d.n_particles, d.n_tets, d.n_tris, d.n_hinges, d.n_bodies
+
+    def colouring(self, kind):
+        """(order, bounds) of the colour-ordered element list of one kind (0 tet, 1 tri, 2 hinge)."""
+        n = (self.ne, self.nt, self.nh)[kind]
+        order = np.zeros(max(n, 1), np.int32)
+        nb = C.c_int()
+        _check(load().gsim_plan_colouring(self._h, kind, None, None, 0, C.byref(nb)))
+        bounds = np.zeros(max(nb.value, 1), np.int32)
+        _check(load().gsim_plan_colouring(self._h, kind, order.ctypes.data, bounds.ctypes.data, nb.value, C.byref(nb)))
+        return order[:n], bounds[:nb.value]
+
+    def gather(self, kind):
+        """(slots [corners, n], slice_base, degree, n_slots) of the sliced-ELL gather table."""
+        n = (self.ne, self.nt, self.nh)[kind]
+        nc = 3 if kind == 1 else 4
+        ns, nsl = C.c_int64(), C.c_int64()
+        _check(load().gsim_plan_gather(self._h, kind, None, None, C.byref(ns), None, C.byref(nsl)))
+        slots = np.zeros(max(nc * n, 1), np.int32)
+        base = np.zeros(max(ns.value, 1), np.int32)
+        deg = np.zeros(self.np, np.int32)
+        _check(load().gsim_plan_gather(self._h, kind, slots.ctypes.data, base.ctypes.data, C.byref(ns),
+                                       deg.ctypes.data, C.byref(nsl)))
+        return slots[:nc * n].reshape(nc, n), base[:ns.value], deg, nsl.value
 
     def sizes(self, max_steps, ckpt_every):
         w, c, s = C.c_size_t(), C.c_size_t(), C.c_size_t()

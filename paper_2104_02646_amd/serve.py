@@ -186,6 +186,7 @@ def replay_trace(trace, bodies, engine: Engine, ckpt_every=10, time_scale=1.0, l
     lat = {}
     id2idx = {}
     n = len(trace)
+    logged = 0
     while len(lat) < n:
         now = time.perf_counter() - t0
         while nxt < n and arrivals[nxt] <= now:
@@ -197,7 +198,8 @@ def replay_trace(trace, bodies, engine: Engine, ckpt_every=10, time_scale=1.0, l
             lat[i] = (time.perf_counter() - t0) - arrivals[i]
         if nl == 0 and nq == 0 and nxt < n:
             time.sleep(max(0.0, min(0.001, arrivals[nxt] - (time.perf_counter() - t0))))
-        if log and len(lat) and len(lat) % 200 == 0:
+        if log and len(lat) >= logged + 200:
+            logged = len(lat)
             log("served %d/%d" % (len(lat), n))
     wall = time.perf_counter() - t0
     return np.array([lat[i] for i in range(n)]), wall, qbs

@@ -94,14 +94,26 @@ def cloth_grid(n: int, spacing: float, height: float):
 
 
 def hinges_from_tris(tris: np.ndarray) -> np.ndarray:
-    """Interior edges shared by exactly two triangles, as (wing0, wing1, e0, e1)."""
-    edges = {}
-    for t, (p, q, r) in enumerate(np.asarray(tris)):
-        for (u, v, w) in ((p, q, r), (q, r, p), (r, p, q)):
-            key = (min(u, v), max(u, v))
-            edges.setdefault(key, []).append(w)
-    out = [(ws[0], ws[1], e[0], e[1]) for e, ws in sorted(edges.items()) if len(ws) == 2]
-    return np.asarray(out, np.int32).reshape(-1, 4)
+    """Interior edges shared by exactly two triangles, as (wing0, wing1, e0, e1) with
+    e0 < e1, sorted by edge; wing0 belongs to the triangle listed first."""
+    t = np.asarray(tris, np.int64).reshape(-1, 3)
+    if len(t) == 0:
+        return np.zeros((0, 4), np.int32)
+    u = np.concatenate([t[:, 0], t[:, 1], t[:, 2]])
+    v = np.concatenate([t[:, 1], t[:, 2], t[:, 0]])
+    w = np.concatenate([t[:, 2], t[:, 0], t[:, 1]])
+    tri = np.concatenate([np.arange(len(t))] * 3)
+    lo, hi = np.minimum(u, v), np.maximum(u, v)
+    order = np.lexsort((tri, hi, lo))
+    lo, hi, w = lo[order], hi[order], w[order]
+    same = (lo[1:] == lo[:-1]) & (hi[1:] == hi[:-1])
+    first = np.nonzero(same)[0]
+    # an edge shared by three or more triangles is not a hinge
+    bad = np.zeros(len(lo) + 1, bool)
+    bad[first[1:][first[1:] - 1 == first[:-1]]] = True
+    bad[first[:-1][first[1:] - 1 == first[:-1]]] = True
+    keep = first[~bad[first]]
+    return np.stack([w[keep], w[keep + 1], lo[keep], hi[keep]], 1).astype(np.int32)
 
 
 def sphere_mask(r_vox: float):

@@ -104,3 +104,56 @@ def test_orients_negative_tets(gs):
     b.tets[:, [1, 2]] = b.tets[:, [2, 1]]
     p = gs.Plan([b])
     assert p.ne == 162
+
+
+@pytest.mark.parametrize("which", ["batch", "cloth"])
+def test_colouring_classes_are_particle_disjoint(gs, which):
+    """Fused-path colouring: a permutation of each kind's elements; within every colour
+    class of every body no two elements share a particle."""
+    bodies = [W.batch_body(20000 + i, lo=500, hi=3000) for i in range(3)] if which == "batch" else \
+        [W.cloth(3, n=20), W.cloth(4, n=9)]
+    p = gs.Plan(bodies)
+    pk = gs.pack(bodies)
+    for kind, idx in ((0, pk.tets), (1, pk.tris), (2, pk.hinges)):
+        n = len(idx)
+        if n == 0:
+            continue
+        order, bounds = p.colouring(kind)
+        assert np.array_equal(np.sort(order), np.arange(n))
+        ncol = 0
+        for b0, b1 in zip(bounds[:-1], bounds[1:]):
+            if b1 < b0:   # next body's list starts
+                continue
+            cls = idx[order[b0:b1]].ravel()
+            assert len(np.unique(cls)) == len(cls), "colour class shares a particle"
+            ncol += 1
+        assert ncol <= 128 * len(bodies) * 3
+
+
+def test_gather_table_is_a_bijection(gs):
+    """Every element corner owns exactly one slot; slot = slice_base + 64 k + lane with
+    k < degree of its particle; corner numbers per particle are 0..degree-1."""
+    bodies = [W.tiny_cube(0), W.cloth(5, n=10), W.batch_body(20001, lo=700, hi=900)]
+    p = gs.Plan(bodies)
+    pk = gs.pack(bodies)
+    all_slots = []
+    seen = {}
+    for kind, idx in ((0, pk.tets), (1, pk.tris), (2, pk.hinges)):
+        if len(idx) == 0:
+            continue
+        slots, base, deg, nslot = p.gather(kind)
+        for c in range(idx.shape[1]):
+            for e in range(len(idx)):
+                part = int(idx[e, c])
+                s = int(slots[c, e])
+                b = int(np.searchsorted(pk.poff, part, side="right") - 1)
+                li = part - int(pk.poff[b])
+                g0 = sum(-(-int(pk.poff[q + 1] - pk.poff[q]) // 64) for q in range(b))
+                g = g0 + li // 64
+                k, lane = divmod(s - int(base[g]), 64)
+                assert lane == li % 64 and 0 <= k < deg[part], (kind, e, c)
+                seen.setdefault(part, []).append(k)
+                all_slots.append(s)
+    assert len(all_slots) == len(set(all_slots)) and max(all_slots) < nslot
+    for part, ks in seen.items():
+        assert sorted(ks) == list(range(len(ks)))
