@@ -430,6 +430,10 @@ Layout make_layout(const gsim_plan* P, int max_steps) {
     L.f_hin_phi0 = take(nh * sizeof(T));
     L.coff = take(P->coff.size() * 4 + 4);
     L.border = take(P->nb * 4 + 4);
+    L.f_par = take(3 * ne * sizeof(T));
+    L.f_ktri = take(nt * sizeof(T));
+    L.f_g = take(2 * ne * sizeof(T));
+    L.f_gk = take(nt * sizeof(T));
     L.table_cap = 4 * (int64_t)max_steps + 8;
     L.table = take(sizeof(StepDev<T>) * L.table_cap);
     L.total = align_up(o, 256);
@@ -534,7 +538,9 @@ enum Op : int {
     OP_CONTACT_REDUCE = 3,
     OP_LOSS = 4,
     OP_FUSED_FWD = 5,  // whole segment of forward steps, one workgroup per body
-    OP_FUSED_ADJ = 6   // whole segment of adjoint steps, one workgroup per body
+    OP_FUSED_ADJ = 6,    // whole segment of adjoint steps, one workgroup per body
+    OP_FUSED_PARAMS = 7, // parameters into colour order (and colour-ordered gradient clear)
+    OP_FUSED_GRADS = 8   // colour-ordered gradients back to element order
 };
 
 template <typename T>
@@ -599,6 +605,12 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
                 LAUNCH_TRY(timed(m, 5, stream, [&] {
                     return launch_fused_adj<T>(md, sd, (const int32_t*)(m->ws + m->L.border), m->nb, fused_lds<T>(m, true), stream);
                 }), "fused adjoint");
+                break;
+            case OP_FUSED_PARAMS:
+                LAUNCH_TRY(launch_fused_params<T>(md, sd, stream), "fused parameters");
+                break;
+            case OP_FUSED_GRADS:
+                LAUNCH_TRY(launch_fused_grads<T>(md, sd, stream), "fused gradients");
                 break;
             case OP_LOSS:
                 LAUNCH_TRY(launch_loss<T>(md, sd, c.pt, m->n_ptiles, m->pblock, m->pitems, m->nb, stream), "loss");
@@ -711,7 +723,7 @@ int do_fused_forward(gsim_model* m, const gsim_params* p, const T* x, const T* v
     r.t_base = 0;
     int rc = upload_rows<T>(m, row0, rows, stream);
     if (rc) return rc;
-    std::vector<Launch> seq{{OP_FUSED_FWD, row0}};
+    std::vector<Launch> seq{{OP_FUSED_PARAMS, row0}, {OP_FUSED_FWD, row0}};
     return execute<T>(m, key, seq, stream);
 }
 
@@ -721,9 +733,9 @@ int do_fused_rollout_backward(gsim_model* m, const gsim_params* p, const T* ck, 
     Ctx<T> c = ctx<T>(m);
     const int64_t S = 6 * c.np, np = c.np;
     const int K = m->K, nseg = (n + K - 1) / K;
-    std::vector<StepDev<T>> rows;
-    std::vector<Launch> seq;
+    std::vector<StepDev<T>> rows(1, fused_row<T>(p, g));
     const int64_t r0 = region_backward(m);
+    std::vector<Launch> seq{{OP_FUSED_PARAMS, r0}};
     for (int s = nseg - 1, q = 0; s >= 0; --s, ++q) {
         const int t0 = s * K, L = std::min(n, t0 + K) - t0;
         if (L > 1) {  // recompute states t0+1 .. t0+L-1 into seg[0 .. L-2]
@@ -761,6 +773,7 @@ int do_fused_rollout_backward(gsim_model* m, const gsim_params* p, const T* ck, 
         rows.push_back(r);
         seq.push_back({OP_FUSED_ADJ, r0 + (int64_t)rows.size() - 1});
     }
+    seq.push_back({OP_FUSED_GRADS, r0});
     int rc = upload_rows<T>(m, r0, rows, stream);
     if (rc) return rc;
     return execute<T>(m, (7LL << 40) | ((long long)n << 1), seq, stream);
@@ -826,7 +839,7 @@ int do_step_backward(gsim_model* m, const gsim_params* p, gsim_state s, gsim_sta
     const int64_t r0 = region_misc(m);
     if ((rc = upload_rows<T>(m, r0, rows, stream))) return rc;
     if (m->exec == GSIM_EXEC_FUSED) {
-        std::vector<Launch> fseq{{OP_FUSED_ADJ, r0}};
+        std::vector<Launch> fseq{{OP_FUSED_PARAMS, r0}, {OP_FUSED_ADJ, r0}, {OP_FUSED_GRADS, r0}};
         return execute<T>(m, 9LL << 40, fseq, stream);
     }
     std::vector<Launch> seq;
@@ -1119,6 +1132,10 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     M.f_hin_idx = (const int32_t*)(ws + L.f_hin_idx);
     M.f_hin_phi0 = (const T*)(ws + L.f_hin_phi0);
     M.coff = (const int32_t*)(ws + L.coff);
+    M.f_par = (T*)(ws + L.f_par);
+    M.f_ktri = (T*)(ws + L.f_ktri);
+    M.f_g = (T*)(ws + L.f_g);
+    M.f_gk = (T*)(ws + L.f_gk);
     chk(up(L.model, &M, sizeof M));
     m->md_host.assign(reinterpret_cast<const char*>(&M), reinterpret_cast<const char*>(&M) + sizeof M);
     chk(hipHostMalloc((void**)&m->stage, sizeof(StepDev<T>) * L.table_cap, hipHostMallocDefault));
@@ -1284,8 +1301,9 @@ int gsim_model_set_exec(gsim_model* m, int exec, int block, int items) {
         int dev = 0, lds_max = 0;
         HIP_TRY(hipGetDevice(&dev), "get device");
         HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "device LDS size");
-        const size_t need = m->dtype == GSIM_F64 ? std::max(fused_lds<double>(m, false), fused_lds<double>(m, true))
-                                                 : std::max(fused_lds<float>(m, false), fused_lds<float>(m, true));
+        // + 1 KB for the kernels' static LDS (block reduction)
+        const size_t need = 1024 + (m->dtype == GSIM_F64 ? std::max(fused_lds<double>(m, false), fused_lds<double>(m, true))
+                                                         : std::max(fused_lds<float>(m, false), fused_lds<float>(m, true)));
         if (need > (size_t)lds_max)
             return fail(GSIM_E_UNSUPPORTED, "fused execution: the largest body needs %zu bytes of LDS, the device has %d",
                         need, lds_max);

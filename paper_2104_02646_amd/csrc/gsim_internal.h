@@ -84,6 +84,10 @@ struct ModelDev {
     const int32_t* f_hin_idx;
     const T* f_hin_phi0;
     const int32_t* coff;
+    T* f_par;   // [3][ne] mu, lambda, actuation in colour order (gathered per call)
+    T* f_ktri;  // [nt] membrane stiffness in colour order
+    T* f_g;     // [2][ne] mu-bar, lambda-bar in colour order (scattered back per call)
+    T* f_gk;    // [nt] k-bar in colour order
 };
 
 template <typename T>
@@ -150,6 +154,12 @@ int launch_fused_adj(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t*
                      void* stream);
 const int FUSED_FWD_BLOCK = 1024, FUSED_ADJ_BLOCK = 512;
 // dynamic LDS per particle of the largest body: x, v, f (forward); fbar, xbar-acc, f.fbar (adjoint)
-const int FUSED_FWD_LDS_WORDS = 9, FUSED_ADJ_LDS_WORDS = 7;
+const int FUSED_FWD_LDS_WORDS = 9, FUSED_ADJ_LDS_WORDS = 10;
+// per-call parameter gather into colour order (and gradient-buffer clear), and the
+// scatter of colour-ordered gradients back to element order
+template <typename T>
+int launch_fused_params(const ModelDev<T>* md, const StepDev<T>* sd, void* stream);
+template <typename T>
+int launch_fused_grads(const ModelDev<T>* md, const StepDev<T>* sd, void* stream);
 
 }  // namespace gsim

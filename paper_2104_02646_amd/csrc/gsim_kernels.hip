@@ -703,19 +703,115 @@ __global__ void k_fill(T* __restrict__ p, int64_t n, T value) {
 
 
 // ------------------------------------------------------------ fused path ---
-// One workgroup owns one body for a whole segment of steps.  Positions (forward)
-// or adjoint forces (reverse) of the body's particles live in LDS; element
-// contributions are accumulated in LDS colour by colour: the elements of a
-// colour share no particle, so each LDS update is race-free, and every particle
-// receives its contributions in colour order (deterministic).  A workgroup
-// barrier separates colours; nothing else synchronises, and every barrier sits
-// in loops whose trip counts are uniform over the workgroup.
+// One workgroup owns one body for a whole segment of steps.  Positions and
+// velocities (forward) or positions and adjoint forces (reverse) of the body's
+// particles live in LDS; element contributions are accumulated in LDS colour by
+// colour: the elements of a colour share no particle, so each LDS update is
+// race-free, and every particle receives its contributions in colour order
+// (deterministic).  A workgroup barrier separates colours; nothing else
+// synchronises, and every barrier sits in a loop whose trip count is uniform
+// over the workgroup.  Each thread loads its element record of the next colour
+// before it processes the current one, so record latency overlaps the current
+// colour's work and barrier.  Per-element parameters are read from a copy in
+// colour order (gathered once per call) and gradients accumulate in colour order
+// (scattered back once per call).
 
 template <typename T>
 __device__ __forceinline__ void lds_add3(T* a, int n, int i, V3<T> v) {
     a[i] += v.x;
     a[n + i] += v.y;
     a[2 * n + i] += v.z;
+}
+template <typename T>
+__device__ __forceinline__ V3<T> lds3(const T* a, int n, int i) {
+    return mk3(a[i], a[n + i], a[2 * n + i]);
+}
+template <typename T>
+__device__ __forceinline__ void lds_st3(T* a, int n, int i, V3<T> v) {
+    a[i] = v.x;
+    a[n + i] = v.y;
+    a[2 * n + i] = v.z;
+}
+
+template <typename T>
+struct TetRec {
+    int li[4];
+    T D[9];
+    T V, mu, lam, act;
+};
+template <typename T>
+struct TriRec {
+    int li[3];
+    T D[4];
+    T A, k;
+};
+template <typename T>
+struct HinRec {
+    int li[4];
+    T phi0;
+};
+
+template <typename T>
+__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, int64_t p0, TetRec<T>& r) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r.li[q] = (int)(M.f_tet_idx[q * M.ne + e] - p0);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) r.D[q] = M.f_tet_dinv[q * M.ne + e];
+    r.V = M.f_tet_vol[e];
+    r.mu = M.f_par[e];
+    r.lam = M.f_par[M.ne + e];
+    r.act = M.f_par[2 * M.ne + e];
+}
+template <typename T>
+__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, int64_t p0, TriRec<T>& r) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) r.li[q] = (int)(M.f_tri_idx[q * M.nt + e] - p0);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r.D[q] = M.f_tri_dinv[q * M.nt + e];
+    r.A = M.f_tri_area[e];
+    r.k = M.f_ktri[e];
+}
+template <typename T>
+__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, int64_t p0, HinRec<T>& r) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r.li[q] = (int)(M.f_hin_idx[q * M.nh + e] - p0);
+    r.phi0 = M.f_hin_phi0[e];
+}
+
+// Processes the colours [0, ncol) of one element kind: `proc(e, rec)` for every
+// element of a colour, then a workgroup barrier.
+template <typename T, typename Rec, typename Proc>
+__device__ __forceinline__ void colour_sweep(const ModelDev<T>& M, int64_t p0, int cbase, int ncol, Proc proc) {
+    const int32_t* coff = M.coff + cbase;
+    Rec nxt;
+    bool has_nxt = false;
+    if (ncol > 0) {
+        const int e = coff[0] + threadIdx.x;
+        if (e < coff[1]) {
+            load_rec(M, e, p0, nxt);
+            has_nxt = true;
+        }
+    }
+    for (int c = 0; c < ncol; ++c) {
+        const int e0 = coff[c], e1 = coff[c + 1];
+        const Rec cur = nxt;
+        const bool has_cur = has_nxt;
+        has_nxt = false;
+        if (c + 1 < ncol) {
+            const int en = e1 + threadIdx.x;
+            if (en < coff[c + 2]) {
+                load_rec(M, en, p0, nxt);
+                has_nxt = true;
+            }
+        }
+        if (has_cur) proc(e0 + (int)threadIdx.x, cur);
+        for (int e = e0 + threadIdx.x + blockDim.x; e < e1; e += blockDim.x) {
+            Rec r;
+            load_rec(M, e, p0, r);
+            proc(e, r);
+        }
+        __syncthreads();
+    }
 }
 
 template <typename T>
@@ -742,101 +838,58 @@ __global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>
         cp[k] = contact ? S.contact[4 * b + k] : T(0);
     }
     for (int li = threadIdx.x; li < npb; li += blockDim.x) {
-        const V3<T> x = ld3(S.x, np, p0 + li), v = ld3(S.v, np, p0 + li);
-        xs[li] = x.x;
-        xs[npb + li] = x.y;
-        xs[2 * npb + li] = x.z;
-        vs[li] = v.x;
-        vs[npb + li] = v.y;
-        vs[2 * npb + li] = v.z;
+        lds_st3(xs, npb, li, ld3(S.x, np, p0 + li));
+        lds_st3(vs, npb, li, ld3(S.v, np, p0 + li));
     }
-    const int ncol0 = B.ncol[0], ncol1 = B.ncol[1], ncol2 = B.ncol[2];
     for (int step = 0; step < S.nsteps; ++step) {
         const int t = S.t_base + step;
         const bool ck = S.ckx != nullptr && t % S.ckpt_every == 0;
         for (int li = threadIdx.x; li < npb; li += blockDim.x) {
             if (ck) {
                 T* cx = S.ckx + (int64_t)(t / S.ckpt_every) * 6 * np;
-                st3(cx, np, p0 + li, mk3(xs[li], xs[npb + li], xs[2 * npb + li]));
-                st3(cx + 3 * np, np, p0 + li, mk3(vs[li], vs[npb + li], vs[2 * npb + li]));
+                st3(cx, np, p0 + li, lds3(xs, npb, li));
+                st3(cx + 3 * np, np, p0 + li, lds3(vs, npb, li));
             }
-            fs[li] = T(0);
-            fs[npb + li] = T(0);
-            fs[2 * npb + li] = T(0);
+            lds_st3(fs, npb, li, zero3<T>());
         }
         __syncthreads();
-        for (int c = 0; c < ncol0; ++c) {
-            const int e0 = M.coff[B.cbase[0] + c], e1 = M.coff[B.cbase[0] + c + 1];
-            for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-                V3<T> x[4], f[4];
-                int li[4];
+        colour_sweep<T, TetRec<T>>(M, p0, B.cbase[0], B.ncol[0], [&](int, const TetRec<T>& r) {
+            V3<T> x[4], f[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    li[q] = (int)(M.f_tet_idx[q * M.ne + e] - p0);
-                    x[q] = mk3(xs[li[q]], xs[npb + li[q]], xs[2 * npb + li[q]]);
-                }
-                T D[9];
+            for (int q = 0; q < 4; ++q) x[q] = lds3(xs, npb, r.li[q]);
+            tet_force(x, r.D, r.V, r.mu, r.lam, r.act, f);
 #pragma unroll
-                for (int q = 0; q < 9; ++q) D[q] = M.f_tet_dinv[q * M.ne + e];
-                const int32_t o = M.f_tet_orig[e];
-                tet_force(x, D, M.f_tet_vol[e], S.mu[o], S.lam[o], S.act ? S.act[o] : T(0), f);
+            for (int q = 0; q < 4; ++q) lds_add3(fs, npb, r.li[q], f[q]);
+        });
+        colour_sweep<T, TriRec<T>>(M, p0, B.cbase[1], B.ncol[1], [&](int, const TriRec<T>& r) {
+            V3<T> x[3], f[3];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) lds_add3(fs, npb, li[q], f[q]);
-            }
-            __syncthreads();
-        }
-        for (int c = 0; c < ncol1; ++c) {
-            const int e0 = M.coff[B.cbase[1] + c], e1 = M.coff[B.cbase[1] + c + 1];
-            for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-                V3<T> x[3], f[3];
-                int li[3];
+            for (int q = 0; q < 3; ++q) x[q] = lds3(xs, npb, r.li[q]);
+            tri_force(x, r.D, r.A, r.k, f);
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    li[q] = (int)(M.f_tri_idx[q * M.nt + e] - p0);
-                    x[q] = mk3(xs[li[q]], xs[npb + li[q]], xs[2 * npb + li[q]]);
-                }
-                T D[4];
+            for (int q = 0; q < 3; ++q) lds_add3(fs, npb, r.li[q], f[q]);
+        });
+        colour_sweep<T, HinRec<T>>(M, p0, B.cbase[2], B.ncol[2], [&](int, const HinRec<T>& r) {
+            V3<T> x[4], f[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) D[q] = M.f_tri_dinv[q * M.nt + e];
-                tri_force(x, D, M.f_tri_area[e], S.ktri[M.f_tri_orig[e]], f);
+            for (int q = 0; q < 4; ++q) x[q] = lds3(xs, npb, r.li[q]);
+            hinge_force(x, r.phi0, B.kb, f);
 #pragma unroll
-                for (int q = 0; q < 3; ++q) lds_add3(fs, npb, li[q], f[q]);
-            }
-            __syncthreads();
-        }
-        for (int c = 0; c < ncol2; ++c) {
-            const int e0 = M.coff[B.cbase[2] + c], e1 = M.coff[B.cbase[2] + c + 1];
-            for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-                V3<T> x[4], f[4];
-                int li[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    li[q] = (int)(M.f_hin_idx[q * M.nh + e] - p0);
-                    x[q] = mk3(xs[li[q]], xs[npb + li[q]], xs[2 * npb + li[q]]);
-                }
-                hinge_force(x, M.f_hin_phi0[e], B.kb, f);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) lds_add3(fs, npb, li[q], f[q]);
-            }
-            __syncthreads();
-        }
+            for (int q = 0; q < 4; ++q) lds_add3(fs, npb, r.li[q], f[q]);
+        });
         // contact + semi-implicit Euler on the workgroup's own particles
         for (int li = threadIdx.x; li < npb; li += blockDim.x) {
             const int64_t p = p0 + li;
-            V3<T> f = mk3(fs[li], fs[npb + li], fs[2 * npb + li]);
-            V3<T> x = mk3(xs[li], xs[npb + li], xs[2 * npb + li]);
-            V3<T> v = mk3(vs[li], vs[npb + li], vs[2 * npb + li]);
+            V3<T> f = lds3(fs, npb, li);
+            V3<T> x = lds3(xs, npb, li);
+            V3<T> v = lds3(vs, npb, li);
             if (contact) f += contact_force(x, v, pl, cp);
             const T w = inv_mass(M, S, p);
             const T gate = w > T(0) ? T(1) : T(0);
             v = v + (f * w + g * gate) * dt;
             x = x + v * dt;
-            xs[li] = x.x;
-            xs[npb + li] = x.y;
-            xs[2 * npb + li] = x.z;
-            vs[li] = v.x;
-            vs[npb + li] = v.y;
-            vs[2 * npb + li] = v.z;
+            lds_st3(xs, npb, li, x);
+            lds_st3(vs, npb, li, v);
             if (S.seg) {
                 T* sx = S.seg + (int64_t)step * 6 * np;
                 st3(sx, np, p, x);
@@ -847,8 +900,8 @@ __global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>
     }
     if (S.xo)
         for (int li = threadIdx.x; li < npb; li += blockDim.x) {
-            st3(S.xo, np, p0 + li, mk3(xs[li], xs[npb + li], xs[2 * npb + li]));
-            st3(S.vo, np, p0 + li, mk3(vs[li], vs[npb + li], vs[2 * npb + li]));
+            st3(S.xo, np, p0 + li, lds3(xs, npb, li));
+            st3(S.vo, np, p0 + li, lds3(vs, npb, li));
         }
 }
 
@@ -866,10 +919,12 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
     const BodyDev<T>& B = M.bodies[b];
     const int npb = (int)B.np;
     const int64_t np = M.np, p0 = B.p0;
-    T* fbs = reinterpret_cast<T*>(smem);  // [3][npb] adjoint force
-    T* acc = fbs + 3 * npb;               // [4][npb] xbar contributions, f . fbar
+    T* xs = reinterpret_cast<T*>(smem);  // [3][npb] positions at the step's start
+    T* fbs = xs + 3 * npb;               // [3][npb] adjoint force
+    T* acc = fbs + 3 * npb;              // [4][npb] xbar contributions, f . fbar
     const T dt = B.dt;
     const bool contact = B.contact_on != 0;
+    const bool want_e = S.g_mu != nullptr || S.g_lam != nullptr, want_k = S.g_ktri != nullptr;
     T pl[4], cp[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -882,115 +937,84 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
             st3(S.vbo, np, p0 + li, ld3(S.vb, np, p0 + li));
         }
     T gc[4] = {T(0), T(0), T(0), T(0)};
-    const int ncol0 = B.ncol[0], ncol1 = B.ncol[1], ncol2 = B.ncol[2];
     for (int step = S.nsteps - 1; step >= 0; --step) {
         const T* sx = step == 0 ? S.x : S.seg_in + (int64_t)(step - 1) * 6 * np;
         const T* sv = step == 0 ? S.v : sx + 3 * np;
         for (int li = threadIdx.x; li < npb; li += blockDim.x) {
+            lds_st3(xs, npb, li, ld3(sx, np, p0 + li));
             const V3<T> vt = ld3(S.vbo, np, p0 + li) + ld3(S.xbo, np, p0 + li) * dt;
-            const V3<T> fb = vt * (dt * inv_mass(M, S, p0 + li));
-            fbs[li] = fb.x;
-            fbs[npb + li] = fb.y;
-            fbs[2 * npb + li] = fb.z;
-            acc[li] = T(0);
-            acc[npb + li] = T(0);
-            acc[2 * npb + li] = T(0);
+            lds_st3(fbs, npb, li, vt * (dt * inv_mass(M, S, p0 + li)));
+            lds_st3(acc, npb, li, zero3<T>());
             acc[3 * npb + li] = T(0);
         }
         __syncthreads();
-        for (int c = 0; c < ncol0; ++c) {
-            const int e0 = M.coff[B.cbase[0] + c], e1 = M.coff[B.cbase[0] + c + 1];
-            for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-                V3<T> x[4], f[4], fb[4], xb[4];
-                int li[4];
+        colour_sweep<T, TetRec<T>>(M, p0, B.cbase[0], B.ncol[0], [&](int e, const TetRec<T>& r) {
+            V3<T> x[4], f[4], fb[4], xb[4];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int32_t p = M.f_tet_idx[q * M.ne + e];
-                    li[q] = (int)(p - p0);
-                    x[q] = ld3(sx, np, p);
-                    fb[q] = mk3(fbs[li[q]], fbs[npb + li[q]], fbs[2 * npb + li[q]]);
-                }
-                T D[9];
-#pragma unroll
-                for (int q = 0; q < 9; ++q) D[q] = M.f_tet_dinv[q * M.ne + e];
-                const int32_t o = M.f_tet_orig[e];
-                T gmu, glam;
-                tet_adjoint(x, D, M.f_tet_vol[e], S.mu[o], S.lam[o], S.act ? S.act[o] : T(0), fb, f, xb, gmu, glam);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    lds_add3(acc, npb, li[q], xb[q]);
-                    acc[3 * npb + li[q]] += dot(f[q], fb[q]);
-                }
-                if (S.g_mu) S.g_mu[o] += gmu;
-                if (S.g_lam) S.g_lam[o] += glam;
+            for (int q = 0; q < 4; ++q) {
+                x[q] = lds3(xs, npb, r.li[q]);
+                fb[q] = lds3(fbs, npb, r.li[q]);
             }
-            __syncthreads();
-        }
-        for (int c = 0; c < ncol1; ++c) {
-            const int e0 = M.coff[B.cbase[1] + c], e1 = M.coff[B.cbase[1] + c + 1];
-            for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-                V3<T> x[3], f[3], fb[3], xb[3];
-                int li[3];
+            T gmu, glam;
+            tet_adjoint(x, r.D, r.V, r.mu, r.lam, r.act, fb, f, xb, gmu, glam);
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    const int32_t p = M.f_tri_idx[q * M.nt + e];
-                    li[q] = (int)(p - p0);
-                    x[q] = ld3(sx, np, p);
-                    fb[q] = mk3(fbs[li[q]], fbs[npb + li[q]], fbs[2 * npb + li[q]]);
-                }
-                T D[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) D[q] = M.f_tri_dinv[q * M.nt + e];
-                const int32_t o = M.f_tri_orig[e];
-                T gk;
-                tri_adjoint(x, D, M.f_tri_area[e], S.ktri[o], fb, f, xb, gk);
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    lds_add3(acc, npb, li[q], xb[q]);
-                    acc[3 * npb + li[q]] += dot(f[q], fb[q]);
-                }
-                if (S.g_ktri) S.g_ktri[o] += gk;
+            for (int q = 0; q < 4; ++q) {
+                lds_add3(acc, npb, r.li[q], xb[q]);
+                acc[3 * npb + r.li[q]] += dot(f[q], fb[q]);
             }
-            __syncthreads();
-        }
-        for (int c = 0; c < ncol2; ++c) {
-            const int e0 = M.coff[B.cbase[2] + c], e1 = M.coff[B.cbase[2] + c + 1];
-            for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-                V3<T> x[4], f[4], fb[4], xb[4];
-                int li[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int32_t p = M.f_hin_idx[q * M.nh + e];
-                    li[q] = (int)(p - p0);
-                    x[q] = ld3(sx, np, p);
-                    fb[q] = mk3(fbs[li[q]], fbs[npb + li[q]], fbs[2 * npb + li[q]]);
-                }
-                hinge_adjoint(x, M.f_hin_phi0[e], B.kb, fb, f, xb);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    lds_add3(acc, npb, li[q], xb[q]);
-                    acc[3 * npb + li[q]] += dot(f[q], fb[q]);
-                }
+            if (want_e) {
+                M.f_g[e] += gmu;
+                M.f_g[M.ne + e] += glam;
             }
-            __syncthreads();
-        }
+        });
+        colour_sweep<T, TriRec<T>>(M, p0, B.cbase[1], B.ncol[1], [&](int e, const TriRec<T>& r) {
+            V3<T> x[3], f[3], fb[3], xb[3];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                x[q] = lds3(xs, npb, r.li[q]);
+                fb[q] = lds3(fbs, npb, r.li[q]);
+            }
+            T gk;
+            tri_adjoint(x, r.D, r.A, r.k, fb, f, xb, gk);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                lds_add3(acc, npb, r.li[q], xb[q]);
+                acc[3 * npb + r.li[q]] += dot(f[q], fb[q]);
+            }
+            if (want_k) M.f_gk[e] += gk;
+        });
+        colour_sweep<T, HinRec<T>>(M, p0, B.cbase[2], B.ncol[2], [&](int, const HinRec<T>& r) {
+            V3<T> x[4], f[4], fb[4], xb[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                x[q] = lds3(xs, npb, r.li[q]);
+                fb[q] = lds3(fbs, npb, r.li[q]);
+            }
+            hinge_adjoint(x, r.phi0, B.kb, fb, f, xb);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                lds_add3(acc, npb, r.li[q], xb[q]);
+                acc[3 * npb + r.li[q]] += dot(f[q], fb[q]);
+            }
+        });
         // contact adjoint and the integrator's adjoint on the workgroup's own particles
         for (int li = threadIdx.x; li < npb; li += blockDim.x) {
             const int64_t p = p0 + li;
             const V3<T> xbp = ld3(S.xbo, np, p);
             const V3<T> vt = ld3(S.vbo, np, p) + xbp * dt;
-            const V3<T> fb = mk3(fbs[li], fbs[npb + li], fbs[2 * npb + li]);
+            const V3<T> fb = lds3(fbs, npb, li);
             T ds = acc[3 * npb + li];
             V3<T> xcb = zero3<T>(), vcb = zero3<T>();
             if (contact) {
-                const V3<T> fc = contact_adjoint(ld3(sx, np, p), ld3(sv, np, p), pl, cp, fb, xcb, vcb, gc);
+                const V3<T> fc = contact_adjoint(lds3(xs, npb, li), ld3(sv, np, p), pl, cp, fb, xcb, vcb, gc);
                 ds += dot(fc, fb);
             }
-            st3(S.xbo, np, p, xbp + mk3(acc[li], acc[npb + li], acc[2 * npb + li]) + xcb);
+            st3(S.xbo, np, p, xbp + lds3(acc, npb, li) + xcb);
             st3(S.vbo, np, p, vt + vcb);
             const T w = inv_mass(M, S, p);
             if (S.g_mass && w > T(0)) S.g_mass[p] += -w * ds;
         }
+        __syncthreads();
     }
     if (contact && S.g_contact) {
         T tot[4];
@@ -999,6 +1023,43 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
 #pragma unroll
             for (int k = 0; k < 4; ++k) S.g_contact[4 * b + k] += tot[k];
     }
+}
+
+template <typename T>
+__global__ void k_fused_params(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd) {
+    const ModelDev<T>& M = md[0];
+    const StepDev<T>& S = sd[0];
+    const bool clear_e = S.g_mu != nullptr || S.g_lam != nullptr, clear_k = S.g_ktri != nullptr;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < M.ne; e += stride) {
+        const int32_t o = M.f_tet_orig[e];
+        M.f_par[e] = S.mu[o];
+        M.f_par[M.ne + e] = S.lam[o];
+        M.f_par[2 * M.ne + e] = S.act ? S.act[o] : T(0);
+        if (clear_e) {
+            M.f_g[e] = T(0);
+            M.f_g[M.ne + e] = T(0);
+        }
+    }
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < M.nt; t += stride) {
+        M.f_ktri[t] = S.ktri[M.f_tri_orig[t]];
+        if (clear_k) M.f_gk[t] = T(0);
+    }
+}
+
+template <typename T>
+__global__ void k_fused_grads(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd) {
+    const ModelDev<T>& M = md[0];
+    const StepDev<T>& S = sd[0];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < M.ne; e += stride) {
+        const int32_t o = M.f_tet_orig[e];
+        if (S.g_mu) S.g_mu[o] += M.f_g[e];
+        if (S.g_lam) S.g_lam[o] += M.f_g[M.ne + e];
+    }
+    if (S.g_ktri)
+        for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < M.nt; t += stride)
+            S.g_ktri[M.f_tri_orig[t]] += M.f_gk[t];
 }
 
 int check_launch() {
@@ -1079,6 +1140,17 @@ int launch_fused_adj(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t*
     return check_launch();
 }
 
+template <typename T>
+int launch_fused_params(const ModelDev<T>* md, const StepDev<T>* sd, void* stream) {
+    hipLaunchKernelGGL(k_fused_params<T>, dim3(1024), dim3(256), 0, (hipStream_t)stream, md, sd);
+    return check_launch();
+}
+template <typename T>
+int launch_fused_grads(const ModelDev<T>* md, const StepDev<T>* sd, void* stream) {
+    hipLaunchKernelGGL(k_fused_grads<T>, dim3(1024), dim3(256), 0, (hipStream_t)stream, md, sd);
+    return check_launch();
+}
+
 #define GSIM_INSTANTIATE(T)                                                                                          \
     template int launch_elem_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
     template int launch_part_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
@@ -1088,7 +1160,9 @@ int launch_fused_adj(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t*
     template int launch_contact_reduce<T>(const ModelDev<T>*, const StepDev<T>*, int, void*);                       \
     template int launch_loss<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, int, void*);     \
     template int launch_fused_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const int32_t*, int, size_t, void*);     \
-    template int launch_fused_adj<T>(const ModelDev<T>*, const StepDev<T>*, const int32_t*, int, size_t, void*);
+    template int launch_fused_adj<T>(const ModelDev<T>*, const StepDev<T>*, const int32_t*, int, size_t, void*);     \
+    template int launch_fused_params<T>(const ModelDev<T>*, const StepDev<T>*, void*);                               \
+    template int launch_fused_grads<T>(const ModelDev<T>*, const StepDev<T>*, void*);
 
 GSIM_INSTANTIATE(float)
 GSIM_INSTANTIATE(double)
