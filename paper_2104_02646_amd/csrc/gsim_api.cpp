@@ -1301,9 +1301,9 @@ int gsim_model_set_exec(gsim_model* m, int exec, int block, int items) {
         int dev = 0, lds_max = 0;
         HIP_TRY(hipGetDevice(&dev), "get device");
         HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "device LDS size");
-        // + 1 KB for the kernels' static LDS (block reduction)
-        const size_t need = 1024 + (m->dtype == GSIM_F64 ? std::max(fused_lds<double>(m, false), fused_lds<double>(m, true))
-                                                         : std::max(fused_lds<float>(m, false), fused_lds<float>(m, true)));
+        // + the adjoint kernel's static LDS (16 x 4 block-reduction words)
+        const size_t need = m->dtype == GSIM_F64 ? 512 + std::max(fused_lds<double>(m, false), fused_lds<double>(m, true))
+                                                 : 256 + std::max(fused_lds<float>(m, false), fused_lds<float>(m, true));
         if (need > (size_t)lds_max)
             return fail(GSIM_E_UNSUPPORTED, "fused execution: the largest body needs %zu bytes of LDS, the device has %d",
                         need, lds_max);
