@@ -130,7 +130,7 @@ def main():
     ap.add_argument("--bodies", type=int, default=256)
     ap.add_argument("--sim-steps", type=int, default=100)
     ap.add_argument("--ckpt-every", type=int, default=10)
-    ap.add_argument("--exec", choices=("fused", "graph", "plain"), default="fused")
+    ap.add_argument("--exec", choices=("fused", "graph", "plain"), default="graph")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--items", type=int, default=1)
     ap.add_argument("--cpu-tets", type=int, default=15000, help="oracle sample size (tets)")

@@ -176,6 +176,15 @@ void colour_elements(gsim_plan* P) {
     }
 }
 
+// The corners of an element are distinct particles (the fused kernels update an
+// element's corners in LDS with all reads before all writes).
+bool distinct(const int32_t* id, int n) {
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j)
+            if (id[i] == id[j]) return false;
+    return true;
+}
+
 int build_plan(const gsim_model_desc* d, gsim_plan* P) {
     if (!d) return fail(GSIM_E_INVALID, "NULL description");
     if (d->dtype != GSIM_F32 && d->dtype != GSIM_F64) return fail(GSIM_E_INVALID, "dtype must be 32 or 64");
@@ -257,6 +266,7 @@ int build_plan(const gsim_model_desc* d, gsim_plan* P) {
                 id[c] = d->tet_idx[4 * e + c];
                 if (!in_body(id[c], b)) return fail(GSIM_E_TOPOLOGY, "tet %lld corner %d outside body %d", (long long)e, c, b);
             }
+            if (!distinct(id, 4)) return fail(GSIM_E_TOPOLOGY, "tet %lld repeats a particle", (long long)e);
             D3 c0 = sub(X[id[1]], X[id[0]]), c1 = sub(X[id[2]], X[id[0]]), c2 = sub(X[id[3]], X[id[0]]);
             double det = dt3(c0, crs(c1, c2));
             if (det < 0) {  // orient: swap corners 1 and 2
@@ -286,6 +296,7 @@ int build_plan(const gsim_model_desc* d, gsim_plan* P) {
                 id[c] = d->tri_idx[3 * t + c];
                 if (!in_body(id[c], b)) return fail(GSIM_E_TOPOLOGY, "tri %lld corner %d outside body %d", (long long)t, c, b);
             }
+            if (!distinct(id, 3)) return fail(GSIM_E_TOPOLOGY, "tri %lld repeats a particle", (long long)t);
             D3 a = sub(X[id[1]], X[id[0]]), c = sub(X[id[2]], X[id[0]]);
             D3 n = crs(a, c);
             double la = nrm(a), ln = nrm(n);
@@ -315,6 +326,7 @@ int build_plan(const gsim_model_desc* d, gsim_plan* P) {
                     return fail(GSIM_E_TOPOLOGY, "hinge %lld corner %d outside body %d", (long long)h, c, b);
                 x[c] = X[id[c]];
             }
+            if (!distinct(id, 4)) return fail(GSIM_E_TOPOLOGY, "hinge %lld repeats a particle", (long long)h);
             D3 E = sub(x[3], x[2]);
             double el = nrm(E);
             double n1 = nrm(crs(sub(x[0], x[2]), sub(x[0], x[3]))), n2 = nrm(crs(sub(x[1], x[3]), sub(x[1], x[2])));
@@ -545,7 +557,7 @@ enum Op : int {
 
 template <typename T>
 size_t fused_lds(const gsim_model* m, bool adjoint) {
-    return (size_t)(adjoint ? FUSED_ADJ_LDS_WORDS : FUSED_FWD_LDS_WORDS) * sizeof(T) * (size_t)m->max_body_np;
+    return m->fused_dyn[adjoint ? 1 : 0];
 }
 struct Launch {
     int op;
@@ -1037,10 +1049,14 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     chk(up(L.pdeg, P->pdeg.data(), P->pdeg.size() * 4));
     chk(up(L.pinned, P->pinned.data(), P->pinned.size()));
     // colour-ordered copies of the element records (fused path)
-    auto perm_i = [](const std::vector<int32_t>& a, const std::vector<int32_t>& ord, int rows, int64_t n) {
+    // corner indices become body-local (the fused kernels address the body's particles in LDS)
+    auto perm_i = [P](const std::vector<int32_t>& a, const std::vector<int32_t>& ord, int rows, int64_t n,
+                      const std::vector<int64_t>& off) {
         std::vector<int32_t> out(a.size());
-        for (int r = 0; r < rows; ++r)
-            for (int64_t e = 0; e < n; ++e) out[r * n + e] = a[r * n + ord[e]];
+        for (int b = 0; b < P->nb; ++b)
+            for (int r = 0; r < rows; ++r)
+                for (int64_t e = off[b]; e < off[b + 1]; ++e)
+                    out[r * n + e] = (int32_t)(a[r * n + ord[e]] - P->poff[b]);
         return out;
     };
     auto perm_t = [](const std::vector<T>& a, const std::vector<int32_t>& ord, int rows, int64_t n) {
@@ -1049,8 +1065,9 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
             for (int64_t e = 0; e < n; ++e) out[r * n + e] = a[r * n + ord[e]];
         return out;
     };
-    std::vector<int32_t> f_tet_idx = perm_i(P->tet_idx, P->ftet, 4, P->ne), f_tri_idx = perm_i(P->tri_idx, P->ftri, 3, P->nt),
-                         f_hin_idx = perm_i(P->hin_idx, P->fhin, 4, P->nh);
+    std::vector<int32_t> f_tet_idx = perm_i(P->tet_idx, P->ftet, 4, P->ne, P->eoff),
+                         f_tri_idx = perm_i(P->tri_idx, P->ftri, 3, P->nt, P->toff),
+                         f_hin_idx = perm_i(P->hin_idx, P->fhin, 4, P->nh, P->hoff);
     std::vector<T> f_tet_dinv = perm_t(tet_dinv, P->ftet, 9, P->ne), f_tet_vol = perm_t(tet_vol, P->ftet, 1, P->ne),
                    f_tri_dinv = perm_t(tri_dinv, P->ftri, 4, P->nt), f_tri_area = perm_t(tri_area, P->ftri, 1, P->nt),
                    f_hin_phi0 = perm_t(hin_phi0, P->fhin, 1, P->nh);
@@ -1075,7 +1092,15 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     });
     chk(up(L.border, border.data(), border.size() * 4));
     m->fused_ok = P->fused_ok;
-    for (int b = 0; b < P->nb; ++b) m->max_body_np = std::max<int64_t>(m->max_body_np, P->poff[b + 1] - P->poff[b]);
+    // fused dynamic LDS of a body: its particle arrays, then its colour bounds (int32,
+    // ncol + 1 per element kind)
+    for (int b = 0; b < P->nb; ++b) {
+        const int64_t npb = P->poff[b + 1] - P->poff[b];
+        const size_t cbb = 4 * (size_t)(P->ncol[3 * b] + P->ncol[3 * b + 1] + P->ncol[3 * b + 2] + 3);
+        m->max_body_np = std::max<int64_t>(m->max_body_np, npb);
+        m->fused_dyn[0] = std::max(m->fused_dyn[0], FUSED_FWD_LDS_WORDS * sizeof(T) * (size_t)npb + cbb);
+        m->fused_dyn[1] = std::max(m->fused_dyn[1], FUSED_ADJ_LDS_WORDS * sizeof(T) * (size_t)npb + cbb);
+    }
     std::vector<BodyDev<T>> bodies(P->nb);
     for (int b = 0; b < P->nb; ++b) {
         BodyDev<T>& B = bodies[b];
@@ -1301,9 +1326,13 @@ int gsim_model_set_exec(gsim_model* m, int exec, int block, int items) {
         int dev = 0, lds_max = 0;
         HIP_TRY(hipGetDevice(&dev), "get device");
         HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "device LDS size");
-        // + the adjoint kernel's static LDS (16 x 4 block-reduction words)
-        const size_t need = m->dtype == GSIM_F64 ? 512 + std::max(fused_lds<double>(m, false), fused_lds<double>(m, true))
-                                                 : 256 + std::max(fused_lds<float>(m, false), fused_lds<float>(m, true));
+        // each kernel's static LDS (colour bounds, block reduction) + its dynamic LDS
+        size_t st_f = 0, st_a = 0, need = 0;
+        const bool f64 = m->dtype == GSIM_F64;
+        HIP_TRY(f64 ? fused_static_lds<double>(false, &st_f) : fused_static_lds<float>(false, &st_f), "fused LDS size");
+        HIP_TRY(f64 ? fused_static_lds<double>(true, &st_a) : fused_static_lds<float>(true, &st_a), "fused LDS size");
+        need = f64 ? std::max(st_f + fused_lds<double>(m, false), st_a + fused_lds<double>(m, true))
+                   : std::max(st_f + fused_lds<float>(m, false), st_a + fused_lds<float>(m, true));
         if (need > (size_t)lds_max)
             return fail(GSIM_E_UNSUPPORTED, "fused execution: the largest body needs %zu bytes of LDS, the device has %d",
                         need, lds_max);

@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/gsim.h"
+#include "gsim.h"
 #include "gsim_internal.h"
 
 // ------------------------------------------------------------------ plan ---
@@ -104,5 +104,6 @@ struct gsim_model {
     int64_t timing_n[6] = {0, 0, 0, 0, 0, 0};
     // fused path
     bool fused_ok = false;   // colouring succeeded for every body and kind
-    int64_t max_body_np = 0;  // particles of the largest body (dynamic LDS size)
+    int64_t max_body_np = 0;  // particles of the largest body
+    size_t fused_dyn[2] = {0, 0};  // dynamic LDS bytes of the fused forward / adjoint launch (max over bodies)
 };

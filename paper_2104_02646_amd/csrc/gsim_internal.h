@@ -71,8 +71,9 @@ struct ModelDev {
     T* slots;   // [nslot][4]
     T* cpart;   // [n_ptiles][4] contact-gradient partial sums
     T* lpart;   // [n_ptiles] loss partial sums
-    // fused path: element records in colour order (same SoA layouts), the original
-    // element index of each position (for parameters and gradients), colour bounds
+    // fused path: element records in colour order (same SoA layouts, corner indices
+    // local to the element's body), the original element index of each position
+    // (for parameters and gradients), colour bounds
     const int32_t* f_tet_idx;
     const T* f_tet_dinv;
     const T* f_tet_vol;
@@ -155,11 +156,16 @@ int launch_fused_adj(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t*
 const int FUSED_FWD_BLOCK = 1024, FUSED_ADJ_BLOCK = 512;
 // dynamic LDS per particle of the largest body: x, v, f (forward); fbar, xbar-acc, f.fbar (adjoint)
 const int FUSED_FWD_LDS_WORDS = 9, FUSED_ADJ_LDS_WORDS = 10;
+// fused sweeps: elements computed per thread before their contributions are added
+constexpr int FUSED_AHEAD_FWD = 2, FUSED_AHEAD_ADJ = 2;
 // per-call parameter gather into colour order (and gradient-buffer clear), and the
 // scatter of colour-ordered gradients back to element order
 template <typename T>
 int launch_fused_params(const ModelDev<T>* md, const StepDev<T>* sd, void* stream);
 template <typename T>
 int launch_fused_grads(const ModelDev<T>* md, const StepDev<T>* sd, void* stream);
+// static LDS bytes of the fused forward (adjoint = false) or adjoint kernel
+template <typename T>
+hipError_t fused_static_lds(bool adjoint, size_t* bytes);
 
 }  // namespace gsim

@@ -56,13 +56,23 @@ __device__ __forceinline__ double gcos(double a) { return cos(a); }
 __device__ __forceinline__ float gatan2(float y, float x) { return atan2f(y, x); }
 __device__ __forceinline__ double gatan2(double y, double x) { return atan2(y, x); }
 
+// Device-memory accesses through address space 1: pointers read out of the
+// launch tables are generic, and generic (flat) loads both count against the
+// LDS wait counter and may alias LDS, which would order every record load
+// before the next LDS barrier.  Global loads do neither.
+template <typename T> __device__ __forceinline__ T gld(const T* p, int64_t i) {
+    return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+template <typename T> __device__ __forceinline__ void gst(T* p, int64_t i, T v) {
+    ((__attribute__((address_space(1))) T*)p)[i] = v;
+}
 template <typename T> __device__ __forceinline__ V3<T> ld3(const T* __restrict__ p, int64_t n, int64_t i) {
-    return mk3(p[i], p[n + i], p[2 * n + i]);
+    return mk3(gld(p, i), gld(p, n + i), gld(p, 2 * n + i));
 }
 template <typename T> __device__ __forceinline__ void st3(T* __restrict__ p, int64_t n, int64_t i, V3<T> a) {
-    p[i] = a.x;
-    p[n + i] = a.y;
-    p[2 * n + i] = a.z;
+    gst(p, i, a.x);
+    gst(p, n + i, a.y);
+    gst(p, 2 * n + i, a.z);
 }
 
 __device__ __forceinline__ void st_slot(float* s, int64_t k, float a, float b, float c, float d) {
@@ -84,7 +94,7 @@ __device__ __forceinline__ void ld_slot(const double* s, int64_t k, double& a, d
 }
 
 template <typename T> __device__ __forceinline__ T inv_mass(const ModelDev<T>& M, const StepDev<T>& S, int64_t i) {
-    return M.pinned[i] ? T(0) : T(1) / S.mass[i];
+    return gld(M.pinned, i) ? T(0) : T(1) / gld(S.mass, i);
 }
 
 // ---------------------------------------------------------- tet (NH) ---
@@ -716,11 +726,28 @@ __global__ void k_fill(T* __restrict__ p, int64_t n, T value) {
 // colour order (gathered once per call) and gradients accumulate in colour order
 // (scattered back once per call).
 
-template <typename T>
-__device__ __forceinline__ void lds_add3(T* a, int n, int i, V3<T> v) {
-    a[i] += v.x;
-    a[n + i] += v.y;
-    a[2 * n + i] += v.z;
+// Adds v[q] to the LDS accumulators [3][n] of an element's corners li[q]; with
+// w, also w[q] to the fourth row (a + 3n).  An element's corners are distinct
+// particles (the planner rejects elements that repeat one), so all reads are
+// issued before all writes: one LDS round trip per element instead of one per
+// corner component.  Each word gets the same single add as a plain `+=`.
+template <int NC, typename T>
+__device__ __forceinline__ void lds_add_corners(T* a, int n, const int* li, const V3<T>* v, const T* w = nullptr) {
+    T c[NC][4];
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        c[q][0] = a[li[q]];
+        c[q][1] = a[n + li[q]];
+        c[q][2] = a[2 * n + li[q]];
+        if (w) c[q][3] = a[3 * n + li[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+        a[li[q]] = c[q][0] + v[q].x;
+        a[n + li[q]] = c[q][1] + v[q].y;
+        a[2 * n + li[q]] = c[q][2] + v[q].z;
+        if (w) a[3 * n + li[q]] = c[q][3] + w[q];
+    }
 }
 template <typename T>
 __device__ __forceinline__ V3<T> lds3(const T* a, int n, int i) {
@@ -752,65 +779,128 @@ struct HinRec {
 };
 
 template <typename T>
-__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, int64_t p0, TetRec<T>& r) {
+__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, TetRec<T>& r) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) r.li[q] = (int)(M.f_tet_idx[q * M.ne + e] - p0);
+    for (int q = 0; q < 4; ++q) r.li[q] = gld(M.f_tet_idx, q * M.ne + e);
 #pragma unroll
-    for (int q = 0; q < 9; ++q) r.D[q] = M.f_tet_dinv[q * M.ne + e];
-    r.V = M.f_tet_vol[e];
-    r.mu = M.f_par[e];
-    r.lam = M.f_par[M.ne + e];
-    r.act = M.f_par[2 * M.ne + e];
+    for (int q = 0; q < 9; ++q) r.D[q] = gld(M.f_tet_dinv, q * M.ne + e);
+    r.V = gld(M.f_tet_vol, e);
+    r.mu = gld(M.f_par, e);
+    r.lam = gld(M.f_par, M.ne + e);
+    r.act = gld(M.f_par, 2 * M.ne + e);
 }
 template <typename T>
-__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, int64_t p0, TriRec<T>& r) {
+__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, TriRec<T>& r) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) r.li[q] = (int)(M.f_tri_idx[q * M.nt + e] - p0);
+    for (int q = 0; q < 3; ++q) r.li[q] = gld(M.f_tri_idx, q * M.nt + e);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) r.D[q] = M.f_tri_dinv[q * M.nt + e];
-    r.A = M.f_tri_area[e];
-    r.k = M.f_ktri[e];
+    for (int q = 0; q < 4; ++q) r.D[q] = gld(M.f_tri_dinv, q * M.nt + e);
+    r.A = gld(M.f_tri_area, e);
+    r.k = gld(M.f_ktri, e);
 }
 template <typename T>
-__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, int64_t p0, HinRec<T>& r) {
+__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, HinRec<T>& r) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) r.li[q] = (int)(M.f_hin_idx[q * M.nh + e] - p0);
-    r.phi0 = M.f_hin_phi0[e];
+    for (int q = 0; q < 4; ++q) r.li[q] = gld(M.f_hin_idx, q * M.nh + e);
+    r.phi0 = gld(M.f_hin_phi0, e);
 }
 
-// Processes the colours [0, ncol) of one element kind: `proc(e, rec)` for every
-// element of a colour, then a workgroup barrier.
-template <typename T, typename Rec, typename Proc>
-__device__ __forceinline__ void colour_sweep(const ModelDev<T>& M, int64_t p0, int cbase, int ncol, Proc proc) {
-    const int32_t* coff = M.coff + cbase;
-    Rec nxt;
-    bool has_nxt = false;
-    if (ncol > 0) {
-        const int e = coff[0] + threadIdx.x;
-        if (e < coff[1]) {
-            load_rec(M, e, p0, nxt);
-            has_nxt = true;
-        }
-    }
-    for (int c = 0; c < ncol; ++c) {
-        const int e0 = coff[c], e1 = coff[c + 1];
-        const Rec cur = nxt;
-        const bool has_cur = has_nxt;
-        has_nxt = false;
-        if (c + 1 < ncol) {
-            const int en = e1 + threadIdx.x;
-            if (en < coff[c + 2]) {
-                load_rec(M, en, p0, nxt);
-                has_nxt = true;
+// Adjoint records also carry the element's running parameter gradient, read
+// with the record so that the per-element read-modify-write does not wait on a
+// load issued after the previous element's store.
+template <typename T>
+struct TetRecA : TetRec<T> {
+    T gmu, glam;
+};
+template <typename T>
+struct TriRecA : TriRec<T> {
+    T gk;
+};
+template <typename T>
+__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, TetRecA<T>& r) {
+    load_rec(M, e, static_cast<TetRec<T>&>(r));
+    r.gmu = gld(M.f_g, e);
+    r.glam = gld(M.f_g, M.ne + e);
+}
+template <typename T>
+__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, TriRecA<T>& r) {
+    load_rec(M, e, static_cast<TriRec<T>&>(r));
+    r.gk = gld(M.f_gk, e);
+}
+
+// Copies the body's colour bounds of all three kinds to LDS (kind k's ncol + 1
+// bounds at cb[k]), once per launch: read before every colour, they would
+// otherwise put a global-load latency in front of each colour's record loads.
+template <typename T>
+__device__ __forceinline__ void stage_colour_bounds(const ModelDev<T>& M, const BodyDev<T>& B, int32_t* base,
+                                                    int32_t* cb[3]) {
+    cb[0] = base;
+    cb[1] = cb[0] + B.ncol[0] + 1;
+    cb[2] = cb[1] + B.ncol[1] + 1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        for (int i = threadIdx.x; i <= B.ncol[k]; i += blockDim.x) cb[k][i] = gld(M.coff, (int64_t)B.cbase[k] + i);
+}
+
+// Corner contributions of one element: corners li, 3-vectors v (and a scalar w
+// per corner for a fourth accumulator row).
+template <typename T, int NC>
+struct Contrib {
+    int li[NC];
+    V3<T> v[NC];
+    T w[NC];
+};
+
+// Processes the colours [0, ncol) of one element kind.  The elements of a colour
+// share no particle, so a colour with more elements than the workgroup has
+// threads runs in several rounds without a barrier between them; the sweep walks
+// the sequence of (colour, round) slots, one element per thread per slot, with a
+// workgroup barrier after each colour's last round.  Element contributions do not
+// depend on the accumulators (positions and adjoint forces are fixed during a
+// sweep), so K slots are taken at a time: first the records of all K are loaded
+// and their contributions computed (indices clamped into the colour, so this is
+// straight-line code and the K elements overlap), then they are added slot by
+// slot.  `compute(e, rec, valid, out)` must not write anything shared unless
+// `valid`; `W` adds the fourth accumulator row.
+template <int K, int NC, bool W, typename T, typename Rec, typename Compute>
+__device__ __forceinline__ void colour_sweep(const ModelDev<T>& M, const int32_t* cb, int ncol, T* acc, int npb,
+                                             Compute compute) {
+    const int tid = threadIdx.x, nth = blockDim.x;
+    int c = 0, round = 0;
+    while (c < ncol) {
+        int e[K], hi[K];
+        bool live[K], last[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            live[k] = c < ncol;
+            const int cc = min(c, ncol - 1);
+            const int lo = cb[cc];
+            hi[k] = cb[cc + 1];
+            e[k] = lo + round * nth + tid;
+            last[k] = lo + (round + 1) * nth >= hi[k];
+            if (live[k]) {
+                if (last[k]) {
+                    ++c;
+                    round = 0;
+                } else {
+                    ++round;
+                }
             }
         }
-        if (has_cur) proc(e0 + (int)threadIdx.x, cur);
-        for (int e = e0 + threadIdx.x + blockDim.x; e < e1; e += blockDim.x) {
+        Contrib<T, NC> o[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int ek = min(e[k], hi[k] - 1);
             Rec r;
-            load_rec(M, e, p0, r);
-            proc(e, r);
+            load_rec(M, ek, r);
+            compute(ek, r, live[k] && e[k] < hi[k], o[k]);
         }
-        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (live[k]) {
+                if (e[k] < hi[k]) lds_add_corners<NC>(acc, npb, o[k].li, o[k].v, W ? o[k].w : nullptr);
+                if (last[k]) __syncthreads();
+            }
     }
 }
 
@@ -828,6 +918,8 @@ __global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>
     T* xs = reinterpret_cast<T*>(smem);  // [3][npb] positions
     T* vs = xs + 3 * npb;                // [3][npb] velocities
     T* fs = vs + 3 * npb;                // [3][npb] force accumulators
+    int32_t* cb[3];                      // colour bounds, after the particle arrays
+    stage_colour_bounds(M, B, reinterpret_cast<int32_t*>(fs + 3 * npb), cb);
     const T dt = B.dt;
     const V3<T> g = mk3(B.g[0], B.g[1], B.g[2]);
     const bool contact = B.contact_on != 0;
@@ -853,29 +945,35 @@ __global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>
             lds_st3(fs, npb, li, zero3<T>());
         }
         __syncthreads();
-        colour_sweep<T, TetRec<T>>(M, p0, B.cbase[0], B.ncol[0], [&](int, const TetRec<T>& r) {
-            V3<T> x[4], f[4];
+        colour_sweep<FUSED_AHEAD_FWD, 4, false, T, TetRec<T>>(M, cb[0], B.ncol[0], fs, npb,
+                                                          [&](int, const TetRec<T>& r, bool, Contrib<T, 4>& o) {
+            V3<T> x[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) x[q] = lds3(xs, npb, r.li[q]);
-            tet_force(x, r.D, r.V, r.mu, r.lam, r.act, f);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) lds_add3(fs, npb, r.li[q], f[q]);
+            for (int q = 0; q < 4; ++q) {
+                o.li[q] = r.li[q];
+                x[q] = lds3(xs, npb, r.li[q]);
+            }
+            tet_force(x, r.D, r.V, r.mu, r.lam, r.act, o.v);
         });
-        colour_sweep<T, TriRec<T>>(M, p0, B.cbase[1], B.ncol[1], [&](int, const TriRec<T>& r) {
-            V3<T> x[3], f[3];
+        colour_sweep<FUSED_AHEAD_FWD, 3, false, T, TriRec<T>>(M, cb[1], B.ncol[1], fs, npb,
+                                                          [&](int, const TriRec<T>& r, bool, Contrib<T, 3>& o) {
+            V3<T> x[3];
 #pragma unroll
-            for (int q = 0; q < 3; ++q) x[q] = lds3(xs, npb, r.li[q]);
-            tri_force(x, r.D, r.A, r.k, f);
-#pragma unroll
-            for (int q = 0; q < 3; ++q) lds_add3(fs, npb, r.li[q], f[q]);
+            for (int q = 0; q < 3; ++q) {
+                o.li[q] = r.li[q];
+                x[q] = lds3(xs, npb, r.li[q]);
+            }
+            tri_force(x, r.D, r.A, r.k, o.v);
         });
-        colour_sweep<T, HinRec<T>>(M, p0, B.cbase[2], B.ncol[2], [&](int, const HinRec<T>& r) {
-            V3<T> x[4], f[4];
+        colour_sweep<FUSED_AHEAD_FWD, 4, false, T, HinRec<T>>(M, cb[2], B.ncol[2], fs, npb,
+                                                          [&](int, const HinRec<T>& r, bool, Contrib<T, 4>& o) {
+            V3<T> x[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) x[q] = lds3(xs, npb, r.li[q]);
-            hinge_force(x, r.phi0, B.kb, f);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) lds_add3(fs, npb, r.li[q], f[q]);
+            for (int q = 0; q < 4; ++q) {
+                o.li[q] = r.li[q];
+                x[q] = lds3(xs, npb, r.li[q]);
+            }
+            hinge_force(x, r.phi0, B.kb, o.v);
         });
         // contact + semi-implicit Euler on the workgroup's own particles
         for (int li = threadIdx.x; li < npb; li += blockDim.x) {
@@ -922,6 +1020,8 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
     T* xs = reinterpret_cast<T*>(smem);  // [3][npb] positions at the step's start
     T* fbs = xs + 3 * npb;               // [3][npb] adjoint force
     T* acc = fbs + 3 * npb;              // [4][npb] xbar contributions, f . fbar
+    int32_t* cb[3];                      // colour bounds, after the particle arrays
+    stage_colour_bounds(M, B, reinterpret_cast<int32_t*>(acc + 4 * npb), cb);
     const T dt = B.dt;
     const bool contact = B.contact_on != 0;
     const bool want_e = S.g_mu != nullptr || S.g_lam != nullptr, want_k = S.g_ktri != nullptr;
@@ -948,54 +1048,51 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
             acc[3 * npb + li] = T(0);
         }
         __syncthreads();
-        colour_sweep<T, TetRec<T>>(M, p0, B.cbase[0], B.ncol[0], [&](int e, const TetRec<T>& r) {
-            V3<T> x[4], f[4], fb[4], xb[4];
+        colour_sweep<FUSED_AHEAD_ADJ, 4, true, T, TetRecA<T>>(M, cb[0], B.ncol[0], acc, npb,
+                                                          [&](int e, const TetRecA<T>& r, bool valid, Contrib<T, 4>& o) {
+            V3<T> x[4], f[4], fb[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
+                o.li[q] = r.li[q];
                 x[q] = lds3(xs, npb, r.li[q]);
                 fb[q] = lds3(fbs, npb, r.li[q]);
             }
             T gmu, glam;
-            tet_adjoint(x, r.D, r.V, r.mu, r.lam, r.act, fb, f, xb, gmu, glam);
+            tet_adjoint(x, r.D, r.V, r.mu, r.lam, r.act, fb, f, o.v, gmu, glam);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                lds_add3(acc, npb, r.li[q], xb[q]);
-                acc[3 * npb + r.li[q]] += dot(f[q], fb[q]);
-            }
-            if (want_e) {
-                M.f_g[e] += gmu;
-                M.f_g[M.ne + e] += glam;
+            for (int q = 0; q < 4; ++q) o.w[q] = dot(f[q], fb[q]);
+            if (want_e && valid) {
+                gst(M.f_g, e, r.gmu + gmu);
+                gst(M.f_g, M.ne + e, r.glam + glam);
             }
         });
-        colour_sweep<T, TriRec<T>>(M, p0, B.cbase[1], B.ncol[1], [&](int e, const TriRec<T>& r) {
-            V3<T> x[3], f[3], fb[3], xb[3];
+        colour_sweep<FUSED_AHEAD_ADJ, 3, true, T, TriRecA<T>>(M, cb[1], B.ncol[1], acc, npb,
+                                                          [&](int e, const TriRecA<T>& r, bool valid, Contrib<T, 3>& o) {
+            V3<T> x[3], f[3], fb[3];
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
+                o.li[q] = r.li[q];
                 x[q] = lds3(xs, npb, r.li[q]);
                 fb[q] = lds3(fbs, npb, r.li[q]);
             }
             T gk;
-            tri_adjoint(x, r.D, r.A, r.k, fb, f, xb, gk);
+            tri_adjoint(x, r.D, r.A, r.k, fb, f, o.v, gk);
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                lds_add3(acc, npb, r.li[q], xb[q]);
-                acc[3 * npb + r.li[q]] += dot(f[q], fb[q]);
-            }
-            if (want_k) M.f_gk[e] += gk;
+            for (int q = 0; q < 3; ++q) o.w[q] = dot(f[q], fb[q]);
+            if (want_k && valid) gst(M.f_gk, e, r.gk + gk);
         });
-        colour_sweep<T, HinRec<T>>(M, p0, B.cbase[2], B.ncol[2], [&](int, const HinRec<T>& r) {
-            V3<T> x[4], f[4], fb[4], xb[4];
+        colour_sweep<FUSED_AHEAD_ADJ, 4, true, T, HinRec<T>>(M, cb[2], B.ncol[2], acc, npb,
+                                                         [&](int, const HinRec<T>& r, bool, Contrib<T, 4>& o) {
+            V3<T> x[4], f[4], fb[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
+                o.li[q] = r.li[q];
                 x[q] = lds3(xs, npb, r.li[q]);
                 fb[q] = lds3(fbs, npb, r.li[q]);
             }
-            hinge_adjoint(x, r.phi0, B.kb, fb, f, xb);
+            hinge_adjoint(x, r.phi0, B.kb, fb, f, o.v);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                lds_add3(acc, npb, r.li[q], xb[q]);
-                acc[3 * npb + r.li[q]] += dot(f[q], fb[q]);
-            }
+            for (int q = 0; q < 4; ++q) o.w[q] = dot(f[q], fb[q]);
         });
         // contact adjoint and the integrator's adjoint on the workgroup's own particles
         for (int li = threadIdx.x; li < npb; li += blockDim.x) {
@@ -1012,7 +1109,7 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
             st3(S.xbo, np, p, xbp + lds3(acc, npb, li) + xcb);
             st3(S.vbo, np, p, vt + vcb);
             const T w = inv_mass(M, S, p);
-            if (S.g_mass && w > T(0)) S.g_mass[p] += -w * ds;
+            if (S.g_mass && w > T(0)) gst(S.g_mass, p, gld(S.g_mass, p) - w * ds);
         }
         __syncthreads();
     }
@@ -1141,6 +1238,14 @@ int launch_fused_adj(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t*
 }
 
 template <typename T>
+hipError_t fused_static_lds(bool adjoint, size_t* bytes) {
+    hipFuncAttributes a;
+    const void* f = adjoint ? reinterpret_cast<const void*>(&k_fused_adj<T>) : reinterpret_cast<const void*>(&k_fused_fwd<T>);
+    const hipError_t e = hipFuncGetAttributes(&a, f);
+    *bytes = e == hipSuccess ? a.sharedSizeBytes : 0;
+    return e;
+}
+template <typename T>
 int launch_fused_params(const ModelDev<T>* md, const StepDev<T>* sd, void* stream) {
     hipLaunchKernelGGL(k_fused_params<T>, dim3(1024), dim3(256), 0, (hipStream_t)stream, md, sd);
     return check_launch();
@@ -1162,7 +1267,8 @@ int launch_fused_grads(const ModelDev<T>* md, const StepDev<T>* sd, void* stream
     template int launch_fused_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const int32_t*, int, size_t, void*);     \
     template int launch_fused_adj<T>(const ModelDev<T>*, const StepDev<T>*, const int32_t*, int, size_t, void*);     \
     template int launch_fused_params<T>(const ModelDev<T>*, const StepDev<T>*, void*);                               \
-    template int launch_fused_grads<T>(const ModelDev<T>*, const StepDev<T>*, void*);
+    template int launch_fused_grads<T>(const ModelDev<T>*, const StepDev<T>*, void*);                               \
+    template hipError_t fused_static_lds<T>(bool, size_t*);
 
 GSIM_INSTANTIATE(float)
 GSIM_INSTANTIATE(double)

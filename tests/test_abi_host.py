@@ -79,6 +79,18 @@ def test_rejects_element_crossing_bodies(gs):
     assert pk.poff[-1] == 128
 
 
+def test_rejects_repeated_corner(gs):
+    """Every element's corners are distinct particles (tet, triangle, hinge)."""
+    b = W.tiny_cube(0)
+    b.tets = b.tets.copy()
+    b.tets[3, 2] = b.tets[3, 0]
+    _expect(gs, gs.GSIM_E_TOPOLOGY, [b])
+    c = W.cloth(1, n=6)
+    c.hinges = c.hinges.copy()
+    c.hinges[4, 1] = c.hinges[4, 0]   # both wing tips the same particle: not caught by geometry
+    _expect(gs, gs.GSIM_E_TOPOLOGY, [c])
+
+
 def test_rejects_degenerate_tet(gs):
     b = W.tiny_cube(0)
     b.X = b.X.copy()
