@@ -36,21 +36,28 @@ METRIC = "element-steps/s fwd+adjoint (FP32, grad err ≤1e-3); served p50/p99 q
 HBM_PEAK_GBS = 8000.0
 
 
-def kernel_bytes(kernel, ne, np_, nslot, T, K):
+def kernel_bytes(kernel, ne, np_, ntp, T, K):
     """Compulsory bytes (FP32 / int32) that all launches of `kernel` in one bench step
-    move, each array touched once per pass: element records, gathered particle data
-    (once per particle), gather slots, outputs, gradient read-modify-writes.  Tet
-    bodies only (the batch workload)."""
+    move, each array touched once per pass.  Tet bodies only (the batch workload);
+    ntp = tile particles (sum over element tiles of the particles each touches).
+      element pass, per tet: corner codes 16, D_m^-1 36, volume 4, mu + lambda 8
+        (adjoint: + mu-bar, lambda-bar read-modify-write 16); per tile particle:
+        index, run, partial slot 12, positions 12 (adjoint: + xbar+, vbar+ 24, mass 4,
+        pinned 1), partial write 16;
+      particle pass, per particle: partial count 4, x, v 24, mass 4, pinned 1, writes
+        24 (adjoint: xbar+, vbar+ 24, x, v 24, mass 4, pinned 1, partial count 4,
+        writes 24, mass-bar read-modify-write 8); per partial: 16; checkpoint stores
+        24 per particle per segment."""
     nseg = -(-T // K)
     fwd_passes = T + (T - nseg)  # rollout + segment recompute
     if kernel == "element_fwd":
-        return fwd_passes * (144 * ne + 12 * np_)
+        return fwd_passes * (64 * ne + 40 * ntp)
     if kernel == "particle_fwd":
-        return fwd_passes * (57 * np_ + 16 * nslot) + nseg * 24 * np_
+        return fwd_passes * (57 * np_ + 16 * ntp) + nseg * 24 * np_
     if kernel == "element_adj":
-        return T * (160 * ne + 41 * np_)
+        return T * (80 * ne + 69 * ntp)
     if kernel == "particle_adj":
-        return T * (89 * np_ + 16 * nslot)
+        return T * (89 * np_ + 16 * ntp)
     if kernel == "fused_fwd":
         # per step: tet record 56 + mu, lambda 8 + original index 4; mass, pinned 5 per particle;
         # per launch: state in 24 (+ out 24 for the rollout); stores: checkpoints, segment states
@@ -184,7 +191,7 @@ def main():
         g = model.zero_grads(("mu", "lam", "mass", "contact"))
     stream.synchronize()
     t_plan = time.perf_counter() - t_plan
-    nslot = 4 * ne
+    ntp = len(gsim.Plan(bodies).tiles()[1])  # tile particles of the element tiles
 
     def bench_step():
         model.rollout(p, x0, v0, T, out=(xT, vT), stream=stream)
@@ -241,7 +248,7 @@ def main():
     for k, (n, ms) in timing.items():
         if n:
             avg = ms / n
-            by = kernel_bytes(k, ne, np_, nslot, T, K) / n
+            by = kernel_bytes(k, ne, np_, ntp, T, K) / n
             kern[k] = {"launches": n, "avg_us": avg * 1e3, "total_ms": ms, "bytes_per_launch": by,
                        "GBps": by / (avg * 1e-3) / 1e9}
     dom = max(kern, key=lambda k: kern[k]["total_ms"])

@@ -134,13 +134,30 @@ int gsim_plan_counts(const gsim_plan* plan, int64_t* n_particles, int64_t* n_tet
  * permutation of the kind's elements); bounds[] = colour boundaries over
  * positions, per body in body order (n_bounds entries written, at most
  * max_bounds); returns GSIM_E_UNSUPPORTED if colouring failed (> 128 colours).
- * gsim_plan_gather: slots[c * n + e] = gather slot of corner c of element e;
- * slice_base[g] and degree[p] describe the sliced-ELL table (corner k of the
- * particle at lane j of slice g is slot slice_base[g] + 64 k + j). */
+ * Two-pass element tiles (Sec. 2.1 step; the force scatter of App. A.1 as a
+ * segmented reduction): per body and kind, consecutive elements are cut into
+ * tiles of at most 512 elements (fewer when the tile's particles would need
+ * more than 16384 words of adjoint LDS).  The tile particles of a tile are the
+ * particles its elements touch, in increasing order; its corners are ordered by
+ * (tile particle, element, corner), so each tile particle owns one run of
+ * corners; the element pass sums each run into one partial, written to the
+ * particle's sliced-ELL table of partials.
+ * gsim_plan_tiles: tiles[5 i .. 5 i + 4] = kind (0 tet, 1 tri, 2 hinge), body,
+ * first element, element count, first tile particle of tile i (plan order);
+ * per tile particle (tiles' lists concatenated): particle index, run (first
+ * sorted corner | corner count << 16), partial slot.
+ * gsim_plan_codes: codes[c * n + e] = tile-local index of the particle of corner
+ * c of element e | position of the corner in its tile's sorted order << 16.
+ * gsim_plan_partials: the partial table; the k-th tile (plan order) touching
+ * the particle at lane j of 64-particle slice g writes slot slice_base[g] +
+ * 64 k + j, k < degree[p].  Any output pointer may be NULL (sizes only). */
 int gsim_plan_colouring(const gsim_plan* plan, int kind, int32_t* order, int32_t* bounds, int max_bounds,
                         int* n_bounds);
-int gsim_plan_gather(const gsim_plan* plan, int kind, int32_t* slots, int32_t* slice_base, int64_t* n_slices,
-                     int32_t* degree, int64_t* n_slots);
+int gsim_plan_tiles(const gsim_plan* plan, int64_t* tiles, int64_t* n_tiles, int32_t* tile_particles, int32_t* runs,
+                    int32_t* slots, int64_t* n_tile_particles);
+int gsim_plan_codes(const gsim_plan* plan, int kind, uint32_t* codes);
+int gsim_plan_partials(const gsim_plan* plan, int32_t* slice_base, int64_t* n_slices, int32_t* degree,
+                       int64_t* n_slots);
 
 /* Binds a plan to a caller-owned device workspace (>= workspace_bytes of
  * gsim_plan_sizes for the same max_steps / ckpt_every) and uploads the
@@ -151,9 +168,11 @@ int gsim_model_destroy(gsim_model* model);
 
 /* Selects the rollout execution strategy (GSIM_EXEC_*) and, for both passes,
  * the launch shape: block = threads per workgroup (64..512, multiple of 64),
- * items = elements (or particles) per thread (1..8); a workgroup's tile is
- * block * items items.  0 keeps the current value.  get_exec reports the
- * element-pass shape. */
+ * items = particles per thread (1..8; particle passes: a workgroup's tile is
+ * block * items particles).  Element passes run one workgroup per planned
+ * element tile (see gsim_plan_tiles); their items value is kept but has no
+ * effect.  0 keeps the current value.  get_exec reports the element-pass
+ * shape. */
 int gsim_model_set_exec(gsim_model* model, int exec, int block, int items);
 int gsim_model_get_exec(const gsim_model* model, int* exec, int* block, int* items);
 
@@ -282,7 +301,7 @@ typedef struct {
 
 /* d_pool: caller-owned device memory (256-byte aligned); max_live: live query
  * slots; max_tiles: capacity of one tick's tile lists (sum over live queries of
- * their element and particle tiles at 256 items per tile). */
+ * their planned element tiles and their particle tiles of 256 particles). */
 int gsim_engine_create(void* d_pool, size_t pool_bytes, int max_live, int64_t max_tiles, void* stream,
                        gsim_engine** out);
 int gsim_engine_destroy(gsim_engine* engine);

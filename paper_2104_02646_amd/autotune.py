@@ -1,8 +1,9 @@
 """Launch-shape autotuner with a JSON cache.
 
 For a model it times the element passes and the particle passes (forward and
-adjoint) under candidate launch shapes -- threads per workgroup and items per
-thread, i.e. the tile size -- with HIP events around every launch
+adjoint) under candidate launch shapes -- threads per workgroup (element passes:
+per planned element tile) and, for the particle passes, particles per thread,
+i.e. the tile size -- with HIP events around every launch
 (``gsim_model_set_timing``), and keeps the fastest shape of each pass.  Results
 are cached per (GPU architecture, pass, size bucket) in a JSON file
 (``$GSIM_AUTOTUNE_CACHE``, default ``~/.cache/gsim_autotune.json``), so later
@@ -22,7 +23,7 @@ import torch
 
 from . import gsim
 
-ELEMENT_CANDIDATES = ((64, 1), (128, 1), (256, 1), (512, 1), (128, 2), (256, 2), (256, 4), (64, 4))
+ELEMENT_CANDIDATES = ((64, 1), (128, 1), (256, 1), (512, 1))
 PARTICLE_CANDIDATES = ((64, 1), (128, 1), (256, 1), (512, 1), (256, 2), (128, 4))
 
 

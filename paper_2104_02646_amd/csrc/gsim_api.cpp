@@ -176,6 +176,113 @@ void colour_elements(gsim_plan* P) {
     }
 }
 
+// Element tiles of the two-pass path.  Per body and element kind, consecutive
+// elements are cut into tiles of at most ETILE elements, a tile ending early when
+// its adjoint LDS (6 words per tile particle, 4 per corner) would exceed
+// ETILE_WORDS.  Per tile: its particles in increasing index order (the tile
+// particles); its corners ordered by (tile particle, element, corner), so each
+// tile particle's corners form one contiguous run; corner code = tile-local
+// particle | position in that order << 16.  The kernels sum each run into one
+// partial per (tile, particle).  Partials are stored sliced-ELL: each body's
+// particles are cut into slices of 64 from the body's first particle; slice g
+// holds width_g = max partials per particle of its particles, and the k-th tile
+// (plan order) touching the particle at lane j writes slot gbase[g] + 64 k + j.
+// Everything here depends only on the body itself, never on the rest of a batch.
+int build_tiles(gsim_plan* P) {
+    const int nb = P->nb;
+    P->etiles.clear();
+    P->tp_id.clear();
+    P->tp_run.clear();
+    P->tet_code.assign(4 * P->ne, 0);
+    P->tri_code.assign(3 * P->nt, 0);
+    P->hin_code.assign(4 * P->nh, 0);
+    P->etile_words[0] = P->etile_words[1] = 0;
+    std::vector<int32_t> mark(P->np, -1), loc(P->np, 0), parts, cnt, fill;
+    for (int b = 0; b < nb; ++b)
+        for (int kind = 0; kind < 3; ++kind) {
+            const std::vector<int64_t>& off = kind == 0 ? P->eoff : kind == 1 ? P->toff : P->hoff;
+            const std::vector<int32_t>& idx = kind == 0 ? P->tet_idx : kind == 1 ? P->tri_idx : P->hin_idx;
+            std::vector<uint32_t>& code = kind == 0 ? P->tet_code : kind == 1 ? P->tri_code : P->hin_code;
+            const int64_t n = kind == 0 ? P->ne : kind == 1 ? P->nt : P->nh;
+            const int nc = kind == 1 ? 3 : 4;
+            int64_t e = off[b];
+            while (e < off[b + 1]) {
+                const int32_t tile = (int32_t)P->etiles.size();
+                const int64_t s = e;
+                parts.clear();
+                while (e < off[b + 1] && e - s < ETILE) {
+                    int add = 0;
+                    for (int c = 0; c < nc; ++c) add += mark[idx[c * n + e]] != tile;
+                    const int64_t words = 6 * (int64_t)(parts.size() + add) + 4 * (int64_t)nc * (e - s + 1);
+                    if (e > s && words > ETILE_WORDS) break;
+                    for (int c = 0; c < nc; ++c) {
+                        const int32_t p = idx[c * n + e];
+                        if (mark[p] != tile) {
+                            mark[p] = tile;
+                            parts.push_back(p);
+                        }
+                    }
+                    ++e;
+                }
+                std::sort(parts.begin(), parts.end());
+                const int m = (int)parts.size();
+                for (int j = 0; j < m; ++j) loc[parts[j]] = j;
+                cnt.assign(m, 0);
+                for (int64_t l = s; l < e; ++l)
+                    for (int c = 0; c < nc; ++c) cnt[loc[idx[c * n + l]]]++;
+                fill.assign(m, 0);
+                for (int j = 1; j < m; ++j) fill[j] = fill[j - 1] + cnt[j - 1];
+                for (int j = 0; j < m; ++j) P->tp_run.push_back(fill[j] | (cnt[j] << 16));
+                for (int64_t l = s; l < e; ++l)
+                    for (int c = 0; c < nc; ++c) {
+                        const int j = loc[idx[c * n + l]];
+                        code[c * n + l] = (uint32_t)j | ((uint32_t)fill[j]++ << 16);
+                    }
+                Tile t{};
+                t.model = 0;
+                t.body = b;
+                t.kind = kind == 0 ? TILE_TET : kind == 1 ? TILE_TRI : TILE_HINGE;
+                t.count = (int32_t)(e - s);
+                t.begin = s;
+                t.id = (int32_t)P->tp_id.size();
+                t.pad = m;
+                P->etiles.push_back(t);
+                P->tp_id.insert(P->tp_id.end(), parts.begin(), parts.end());
+                const int64_t corners = (int64_t)nc * (e - s);
+                P->etile_words[0] = std::max<int64_t>(P->etile_words[0], 3 * (int64_t)m + 3 * corners);
+                P->etile_words[1] = std::max<int64_t>(P->etile_words[1], 6 * (int64_t)m + 4 * corners);
+                if ((int64_t)P->tp_id.size() > INT32_MAX) return fail(GSIM_E_UNSUPPORTED, "too many tile particles");
+            }
+        }
+    // partial slots (sliced ELL)
+    P->pdeg.assign(P->np, 0);
+    for (int32_t p : P->tp_id) P->pdeg[p]++;
+    P->gbase.clear();
+    P->body_g0.assign(nb, 0);
+    std::vector<int64_t> pbase(P->np);  // slot of partial 0 of each particle
+    int64_t total = 0;
+    for (int b = 0; b < nb; ++b) {
+        P->body_g0[b] = (int32_t)P->gbase.size();
+        for (int64_t s0 = P->poff[b]; s0 < P->poff[b + 1]; s0 += 64) {
+            const int64_t s1 = std::min<int64_t>(s0 + 64, P->poff[b + 1]);
+            int32_t w = 0;
+            for (int64_t i = s0; i < s1; ++i) w = std::max(w, P->pdeg[i]);
+            if (total + 64 * (int64_t)w > INT32_MAX) return fail(GSIM_E_UNSUPPORTED, "partial table exceeds 32-bit slots");
+            P->gbase.push_back((int32_t)total);
+            for (int64_t i = s0; i < s1; ++i) pbase[i] = total + (i - s0);
+            total += 64 * (int64_t)w;
+        }
+    }
+    P->nslot = total;
+    std::vector<int32_t> cur(P->np, 0);
+    P->tp_slot.resize(P->tp_id.size());
+    for (size_t i = 0; i < P->tp_id.size(); ++i) {
+        const int32_t p = P->tp_id[i];
+        P->tp_slot[i] = (int32_t)(pbase[p] + 64 * (int64_t)cur[p]++);
+    }
+    return GSIM_OK;
+}
+
 // The corners of an element are distinct particles (the fused kernels update an
 // element's corners in LDS with all reads before all writes).
 bool distinct(const int32_t* id, int n) {
@@ -336,43 +443,7 @@ int build_plan(const gsim_model_desc* d, gsim_plan* P) {
             for (int c = 0; c < 4; ++c) P->hin_idx[c * nh + h] = id[c];
         }
 
-    // gather table (sliced ELL): each body's particles are cut into slices of 64
-    // from the body's first particle; slice g holds width_g = max degree of its
-    // particles, and corner k of the particle at lane j is slot gbase[g] + 64 k + j.
-    // Corners are numbered per particle in the order (tets, then triangles,
-    // then hinges; element index; corner).
-    P->pdeg.assign(P->np, 0);
-    for (int64_t k = 0; k < 4 * ne; ++k) P->pdeg[P->tet_idx[k]]++;
-    for (int64_t k = 0; k < 3 * nt; ++k) P->pdeg[P->tri_idx[k]]++;
-    for (int64_t k = 0; k < 4 * nh; ++k) P->pdeg[P->hin_idx[k]]++;
-    P->gbase.clear();
-    P->body_g0.assign(nb, 0);
-    std::vector<int64_t> pbase(P->np);  // slot of corner 0 of each particle
-    int64_t total = 0;
-    for (int b = 0; b < nb; ++b) {
-        P->body_g0[b] = (int32_t)P->gbase.size();
-        for (int64_t s0 = P->poff[b]; s0 < P->poff[b + 1]; s0 += 64) {
-            const int64_t s1 = std::min<int64_t>(s0 + 64, P->poff[b + 1]);
-            int32_t w = 0;
-            for (int64_t i = s0; i < s1; ++i) w = std::max(w, P->pdeg[i]);
-            if (total + 64 * (int64_t)w > INT32_MAX) return fail(GSIM_E_UNSUPPORTED, "gather table exceeds 32-bit slots");
-            P->gbase.push_back((int32_t)total);
-            for (int64_t i = s0; i < s1; ++i) pbase[i] = total + (i - s0);
-            total += 64 * (int64_t)w;
-        }
-    }
-    P->nslot = total;
-    std::vector<int32_t> cur(P->np, 0);
-    auto slot_of = [&](int32_t p) { return (int32_t)(pbase[p] + 64 * (int64_t)cur[p]++); };
-    P->tet_slot.resize(4 * ne);
-    P->tri_slot.resize(3 * nt);
-    P->hin_slot.resize(4 * nh);
-    for (int64_t e = 0; e < ne; ++e)
-        for (int c = 0; c < 4; ++c) P->tet_slot[c * ne + e] = slot_of(P->tet_idx[c * ne + e]);
-    for (int64_t t = 0; t < nt; ++t)
-        for (int c = 0; c < 3; ++c) P->tri_slot[c * nt + t] = slot_of(P->tri_idx[c * nt + t]);
-    for (int64_t h = 0; h < nh; ++h)
-        for (int c = 0; c < 4; ++c) P->hin_slot[c * nh + h] = slot_of(P->hin_idx[c * nh + h]);
+    if (int rc = build_tiles(P)) return rc;
     colour_elements(P);
     return GSIM_OK;
 }
@@ -381,16 +452,9 @@ int build_plan(const gsim_model_desc* d, gsim_plan* P) {
 const int MIN_TILE = 64;  // smallest tile (block 64, 1 item): bounds the tile-list capacity
 
 int64_t tile_capacity(const gsim_plan* P, bool particles) {
+    if (!particles) return (int64_t)P->etiles.size() + N_XCD;  // element tiles are planned
     int64_t n = 0;
-    for (int b = 0; b < P->nb; ++b) {
-        if (particles) {
-            n += (P->poff[b + 1] - P->poff[b] + MIN_TILE - 1) / MIN_TILE;
-        } else {
-            n += (P->eoff[b + 1] - P->eoff[b] + MIN_TILE - 1) / MIN_TILE;
-            n += (P->toff[b + 1] - P->toff[b] + MIN_TILE - 1) / MIN_TILE;
-            n += (P->hoff[b + 1] - P->hoff[b] + MIN_TILE - 1) / MIN_TILE;
-        }
-    }
+    for (int b = 0; b < P->nb; ++b) n += (P->poff[b + 1] - P->poff[b] + MIN_TILE - 1) / MIN_TILE;
     return n + N_XCD;
 }
 
@@ -411,17 +475,17 @@ Layout make_layout(const gsim_plan* P, int max_steps) {
     L.bodies = take(sizeof(BodyDev<T>) * P->nb);
     L.etiles = take(sizeof(Tile) * cap_e);
     L.ptiles = take(sizeof(Tile) * cap_p);
-    L.tet_idx = take(4 * ne * 4);
-    L.tet_slot = take(4 * ne * 4);
+    L.tet_code = take(4 * ne * 4);
     L.tet_dinv = take(9 * ne * sizeof(T));
     L.tet_vol = take(ne * sizeof(T));
-    L.tri_idx = take(3 * nt * 4);
-    L.tri_slot = take(3 * nt * 4);
+    L.tri_code = take(3 * nt * 4);
     L.tri_dinv = take(4 * nt * sizeof(T));
     L.tri_area = take(nt * sizeof(T));
-    L.hin_idx = take(4 * nh * 4);
-    L.hin_slot = take(4 * nh * 4);
+    L.hin_code = take(4 * nh * 4);
     L.hin_phi0 = take(nh * sizeof(T));
+    L.tp_id = take(P->tp_id.size() * 4 + 4);
+    L.tp_run = take(P->tp_run.size() * 4 + 4);
+    L.tp_slot = take(P->tp_slot.size() * 4 + 4);
     L.gbase = take(P->gbase.size() * 4 + 4);
     L.pdeg = take(np * 4);
     L.pinned = take(np);
@@ -457,40 +521,34 @@ Layout make_layout(const gsim_plan* P, int max_steps) {
 
 namespace {
 
-// Natural-order tile list of one pass: per body, `tile`-sized chunks of each
-// element kind (or of particles), starting at the body's first item.  Particle
-// tiles get consecutive partial-buffer rows.
+// Natural-order tile list of one pass.  Element tiles are the plan's; particle
+// tiles are `tile`-sized chunks of each body's particles and get consecutive
+// partial-buffer rows.
 void natural_tiles(const gsim_model* m, bool particles, int tile, std::vector<Tile>& nat, int& rows) {
     nat.clear();
     rows = 0;
-    for (int b = 0; b < m->nb; ++b) {
-        auto add = [&](int kind, int64_t lo, int64_t hi) {
-            for (int64_t s = lo; s < hi; s += tile) {
-                Tile t{};
-                t.model = 0;
-                t.body = b;
-                t.kind = kind;
-                t.count = (int32_t)std::min<int64_t>(tile, hi - s);
-                t.begin = s;
-                t.id = particles ? rows++ : 0;
-                nat.push_back(t);
-            }
-        };
-        if (particles) {
-            add(TILE_PART, m->poff[b], m->poff[b + 1]);
-        } else {
-            add(TILE_TET, m->eoff[b], m->eoff[b + 1]);
-            add(TILE_TRI, m->toff[b], m->toff[b + 1]);
-            add(TILE_HINGE, m->hoff[b], m->hoff[b + 1]);
-        }
+    if (!particles) {
+        nat = m->etiles_plan;
+        return;
     }
+    for (int b = 0; b < m->nb; ++b)
+        for (int64_t s = m->poff[b]; s < m->poff[b + 1]; s += tile) {
+            Tile t{};
+            t.model = 0;
+            t.body = b;
+            t.kind = TILE_PART;
+            t.count = (int32_t)std::min<int64_t>(tile, m->poff[b + 1] - s);
+            t.begin = s;
+            t.id = rows++;
+            nat.push_back(t);
+        }
 }
 
 template <typename T>
 int upload_tiles(gsim_model* m, void* stream) {
     std::vector<Tile> et, pt;
     int rows_e = 0;
-    natural_tiles(m, false, m->block * m->items, m->etiles_nat, rows_e);
+    natural_tiles(m, false, 0, m->etiles_nat, rows_e);
     natural_tiles(m, true, m->pblock * m->pitems, m->ptiles_nat, m->n_ptile_rows);
     xcd_order(m->etiles_nat, TILE_TET, 0, et, m->n_etiles);
     xcd_order(m->ptiles_nat, TILE_PART, m->n_ptile_rows, pt, m->n_ptiles);
@@ -595,11 +653,11 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
         const StepDev<T>* sd = c.table + l.row;
         switch (l.op) {
             case OP_FWD:
-                LAUNCH_TRY(timed(m, 0, stream, [&] { return launch_elem_fwd<T>(md, sd, c.et, m->n_etiles, m->block, m->items, stream); }), "element pass");
+                LAUNCH_TRY(timed(m, 0, stream, [&] { return launch_elem_fwd<T>(md, sd, c.et, m->n_etiles, m->block, m->etile_words[0] * sizeof(T), stream); }), "element pass");
                 LAUNCH_TRY(timed(m, 1, stream, [&] { return launch_part_fwd<T>(md, sd, c.pt, m->n_ptiles, m->pblock, m->pitems, stream); }), "particle pass");
                 break;
             case OP_ADJ:
-                LAUNCH_TRY(timed(m, 2, stream, [&] { return launch_elem_adj<T>(md, sd, c.et, m->n_etiles, m->block, m->items, stream); }), "element adjoint");
+                LAUNCH_TRY(timed(m, 2, stream, [&] { return launch_elem_adj<T>(md, sd, c.et, m->n_etiles, m->block, m->etile_words[1] * sizeof(T), stream); }), "element adjoint");
                 LAUNCH_TRY(timed(m, 3, stream, [&] { return launch_part_adj<T>(md, sd, c.pt, m->n_ptiles, m->pblock, m->pitems, stream); }), "particle adjoint");
                 break;
             case OP_FILL_CPART:
@@ -1034,17 +1092,17 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
                    tri_area = cvt(P->tri_area), hin_phi0 = cvt(P->hin_phi0);
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
-    chk(up(L.tet_idx, P->tet_idx.data(), P->tet_idx.size() * 4));
-    chk(up(L.tet_slot, P->tet_slot.data(), P->tet_slot.size() * 4));
+    chk(up(L.tet_code, P->tet_code.data(), P->tet_code.size() * 4));
     chk(up(L.tet_dinv, tet_dinv.data(), tet_dinv.size() * sizeof(T)));
     chk(up(L.tet_vol, tet_vol.data(), tet_vol.size() * sizeof(T)));
-    chk(up(L.tri_idx, P->tri_idx.data(), P->tri_idx.size() * 4));
-    chk(up(L.tri_slot, P->tri_slot.data(), P->tri_slot.size() * 4));
+    chk(up(L.tri_code, P->tri_code.data(), P->tri_code.size() * 4));
     chk(up(L.tri_dinv, tri_dinv.data(), tri_dinv.size() * sizeof(T)));
     chk(up(L.tri_area, tri_area.data(), tri_area.size() * sizeof(T)));
-    chk(up(L.hin_idx, P->hin_idx.data(), P->hin_idx.size() * 4));
-    chk(up(L.hin_slot, P->hin_slot.data(), P->hin_slot.size() * 4));
+    chk(up(L.hin_code, P->hin_code.data(), P->hin_code.size() * 4));
     chk(up(L.hin_phi0, hin_phi0.data(), hin_phi0.size() * sizeof(T)));
+    chk(up(L.tp_id, P->tp_id.data(), P->tp_id.size() * 4));
+    chk(up(L.tp_run, P->tp_run.data(), P->tp_run.size() * 4));
+    chk(up(L.tp_slot, P->tp_slot.data(), P->tp_slot.size() * 4));
     chk(up(L.gbase, P->gbase.data(), P->gbase.size() * 4));
     chk(up(L.pdeg, P->pdeg.data(), P->pdeg.size() * 4));
     chk(up(L.pinned, P->pinned.data(), P->pinned.size()));
@@ -1092,6 +1150,9 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     });
     chk(up(L.border, border.data(), border.size() * 4));
     m->fused_ok = P->fused_ok;
+    m->etiles_plan = P->etiles;
+    m->etile_words[0] = P->etile_words[0];
+    m->etile_words[1] = P->etile_words[1];
     // fused dynamic LDS of a body: its particle arrays, then its colour bounds (int32,
     // ncol + 1 per element kind)
     for (int b = 0; b < P->nb; ++b) {
@@ -1128,17 +1189,17 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     M.nh = P->nh;
     M.nslot = P->nslot;
     M.n_bodies = P->nb;
-    M.tet_idx = (const int32_t*)(ws + L.tet_idx);
+    M.tet_code = (const uint32_t*)(ws + L.tet_code);
     M.tet_dinv = (const T*)(ws + L.tet_dinv);
     M.tet_vol = (const T*)(ws + L.tet_vol);
-    M.tet_slot = (const int32_t*)(ws + L.tet_slot);
-    M.tri_idx = (const int32_t*)(ws + L.tri_idx);
+    M.tri_code = (const uint32_t*)(ws + L.tri_code);
     M.tri_dinv = (const T*)(ws + L.tri_dinv);
     M.tri_area = (const T*)(ws + L.tri_area);
-    M.tri_slot = (const int32_t*)(ws + L.tri_slot);
-    M.hin_idx = (const int32_t*)(ws + L.hin_idx);
+    M.hin_code = (const uint32_t*)(ws + L.hin_code);
     M.hin_phi0 = (const T*)(ws + L.hin_phi0);
-    M.hin_slot = (const int32_t*)(ws + L.hin_slot);
+    M.tp_id = (const int32_t*)(ws + L.tp_id);
+    M.tp_run = (const int32_t*)(ws + L.tp_run);
+    M.tp_slot = (const int32_t*)(ws + L.tp_slot);
     M.gbase = (const int32_t*)(ws + L.gbase);
     M.pdeg = (const int32_t*)(ws + L.pdeg);
     M.pinned = (const uint8_t*)(ws + L.pinned);
@@ -1232,11 +1293,36 @@ int gsim_plan_colouring(const gsim_plan* P, int kind, int32_t* order, int32_t* b
     return n <= max_bounds || !bounds ? GSIM_OK : fail(GSIM_E_WORKSPACE, "bounds array too small (%d needed)", n);
 }
 
-int gsim_plan_gather(const gsim_plan* P, int kind, int32_t* slots, int32_t* slice_base, int64_t* n_slices,
-                     int32_t* degree, int64_t* n_slots) {
+int gsim_plan_tiles(const gsim_plan* P, int64_t* tiles, int64_t* n_tiles, int32_t* tile_particles, int32_t* runs,
+                    int32_t* slots, int64_t* n_tile_particles) {
+    if (!P) return fail(GSIM_E_INVALID, "NULL plan");
+    if (tiles)
+        for (size_t i = 0; i < P->etiles.size(); ++i) {
+            const Tile& t = P->etiles[i];
+            int64_t* r = tiles + 5 * i;
+            r[0] = t.kind;
+            r[1] = t.body;
+            r[2] = t.begin;
+            r[3] = t.count;
+            r[4] = t.id;
+        }
+    if (n_tiles) *n_tiles = (int64_t)P->etiles.size();
+    if (tile_particles) std::copy(P->tp_id.begin(), P->tp_id.end(), tile_particles);
+    if (runs) std::copy(P->tp_run.begin(), P->tp_run.end(), runs);
+    if (slots) std::copy(P->tp_slot.begin(), P->tp_slot.end(), slots);
+    if (n_tile_particles) *n_tile_particles = (int64_t)P->tp_id.size();
+    return GSIM_OK;
+}
+
+int gsim_plan_codes(const gsim_plan* P, int kind, uint32_t* codes) {
     if (!P || kind < 0 || kind > 2) return fail(GSIM_E_INVALID, "bad plan or kind");
-    const std::vector<int32_t>& sl = kind == 0 ? P->tet_slot : kind == 1 ? P->tri_slot : P->hin_slot;
-    if (slots) std::copy(sl.begin(), sl.end(), slots);
+    const std::vector<uint32_t>& c = kind == 0 ? P->tet_code : kind == 1 ? P->tri_code : P->hin_code;
+    if (codes) std::copy(c.begin(), c.end(), codes);
+    return GSIM_OK;
+}
+
+int gsim_plan_partials(const gsim_plan* P, int32_t* slice_base, int64_t* n_slices, int32_t* degree, int64_t* n_slots) {
+    if (!P) return fail(GSIM_E_INVALID, "NULL plan");
     if (slice_base) std::copy(P->gbase.begin(), P->gbase.end(), slice_base);
     if (n_slices) *n_slices = (int64_t)P->gbase.size();
     if (degree) std::copy(P->pdeg.begin(), P->pdeg.end(), degree);

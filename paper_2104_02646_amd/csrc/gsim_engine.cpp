@@ -428,12 +428,19 @@ int tick(gsim_engine* E, int* n_live, int* n_queued) {
             LAUNCH_TRY(launch_loss<float>(own, dsd + i, own_pt, m->n_ptiles, m->pblock, m->pitems, 1, E->stream), "loss");
         if (ops[i] == OP_FIN) LAUNCH_TRY(launch_contact_reduce<float>(own, dsd + i, 1, E->stream), "contact reduce");
     }
-    // 5. batched passes over all queries' tiles
+    // 5. batched passes over all queries' tiles (element-pass LDS: the largest tile
+    // among the queries in that pass)
     const int block = 256;
+    size_t lds_f = 0, lds_a = 0;
+    for (int i = 0; i < n; ++i) {
+        const gsim_model* m = E->live[i].model;
+        if (ops[i] == OP_FWD) lds_f = std::max(lds_f, (size_t)m->etile_words[0] * sizeof(float));
+        if (ops[i] == OP_ADJ) lds_a = std::max(lds_a, (size_t)m->etile_words[1] * sizeof(float));
+    }
     auto T_ = [&](int k) { return reinterpret_cast<const Tile*>(d + o_t[k]); };
-    LAUNCH_TRY(launch_elem_fwd<float>(dmd, dsd, T_(0), grid[0], block, 1, E->stream), "element pass");
+    LAUNCH_TRY(launch_elem_fwd<float>(dmd, dsd, T_(0), grid[0], block, lds_f, E->stream), "element pass");
     LAUNCH_TRY(launch_part_fwd<float>(dmd, dsd, T_(1), grid[1], block, 1, E->stream), "particle pass");
-    LAUNCH_TRY(launch_elem_adj<float>(dmd, dsd, T_(2), grid[2], block, 1, E->stream), "element adjoint");
+    LAUNCH_TRY(launch_elem_adj<float>(dmd, dsd, T_(2), grid[2], block, lds_a, E->stream), "element adjoint");
     LAUNCH_TRY(launch_part_adj<float>(dmd, dsd, T_(3), grid[3], block, 1, E->stream), "particle adjoint");
     HIP_TRY(hipEventRecord(E->blob_evt[r], E->stream), "record tick");
     // 6. advance; finish completed queries

@@ -16,14 +16,20 @@ struct gsim_plan {
     int nb = 0;
     int64_t np = 0, ne = 0, nt = 0, nh = 0, nslot = 0;
     std::vector<int64_t> poff, eoff, toff, hoff;   // per-body ranges
-    std::vector<int32_t> tet_idx, tet_slot;        // SoA [4][ne]
+    std::vector<int32_t> tet_idx;                  // SoA [4][ne]
     std::vector<double> tet_dinv, tet_vol;         // SoA [9][ne], [ne]
-    std::vector<int32_t> tri_idx, tri_slot;        // [3][nt]
+    std::vector<int32_t> tri_idx;                  // [3][nt]
     std::vector<double> tri_dinv, tri_area;        // [4][nt], [nt]
-    std::vector<int32_t> hin_idx, hin_slot;        // [4][nh]
+    std::vector<int32_t> hin_idx;                  // [4][nh]
     std::vector<double> hin_phi0;                  // [nh]
-    std::vector<int32_t> gbase;                    // [n_slices] sliced-ELL slice bases
-    std::vector<int32_t> pdeg;                     // [np]
+    // two-pass element tiles (see build_tiles): tiles in plan order, corner codes
+    // per kind, per-tile-particle index / corner run / partial slot
+    std::vector<gsim::Tile> etiles;
+    std::vector<uint32_t> tet_code, tri_code, hin_code;  // SoA [corners][n]
+    std::vector<int32_t> tp_id, tp_run, tp_slot;
+    int64_t etile_words[2] = {0, 0};               // largest tile's LDS words, forward / adjoint
+    std::vector<int32_t> gbase;                    // [n_slices] sliced-ELL slice bases of the partials
+    std::vector<int32_t> pdeg;                     // [np] partials per particle (tiles touching it)
     std::vector<int32_t> body_g0;                  // [nb] first slice of each body
     // colour-ordered element copies for the fused path: within each body and kind,
     // elements sorted by (colour, index); no two elements of a colour share a particle
@@ -42,9 +48,10 @@ const int N_XCD = 8;  // workgroups are dispatched round-robin over the XCDs
 
 struct Layout {
     size_t model, bodies, etiles, ptiles;
-    size_t tet_idx, tet_slot, tet_dinv, tet_vol;
-    size_t tri_idx, tri_slot, tri_dinv, tri_area;
-    size_t hin_idx, hin_slot, hin_phi0;
+    size_t tet_code, tet_dinv, tet_vol;
+    size_t tri_code, tri_dinv, tri_area;
+    size_t hin_code, hin_phi0;
+    size_t tp_id, tp_run, tp_slot;
     size_t gbase, pdeg, pinned, slots, cpart, lpart;
     size_t fbuf, abuf;  // forward / adjoint internal ping-pong states
     // fused path: colour-ordered element records, colour bounds, body launch order
@@ -82,14 +89,16 @@ struct gsim_model {
     gsim::Layout L{};
     std::vector<int64_t> poff, eoff, toff, hoff;
     int exec = GSIM_EXEC_PLAIN;
-    int block = 256, items = 1;    // element passes: threads per workgroup, elements per thread
+    int block = 256, items = 1;    // element passes: threads per element tile (items: unused, tiles are planned)
     int pblock = 256, pitems = 1;  // particle passes
     int n_etiles = 0, n_ptiles = 0;   // launched grid sizes (including XCD padding)
     int n_ptile_rows = 0;             // real particle tiles (contact / loss partial rows)
     std::vector<char> bodies_host;    // BodyDev<T>[nb] as last uploaded
     char* stage = nullptr;            // pinned copy of the launch table as last uploaded
     hipEvent_t stage_evt = nullptr;   // completes when the last table upload has read `stage`
-    std::vector<gsim::Tile> etiles_nat, ptiles_nat;  // natural-order tiles (current tile size)
+    std::vector<gsim::Tile> etiles_nat, ptiles_nat;  // natural-order tiles (planned / current tile size)
+    std::vector<gsim::Tile> etiles_plan;             // element tiles of the plan
+    int64_t etile_words[2] = {0, 0};                 // largest element tile's LDS words, forward / adjoint
     std::vector<char> md_host;                       // ModelDev<T> as uploaded
     std::map<long long, gsim::GraphEntry> graphs;
     // per-kernel timing: HIP events around each launch of the kernels in timing_mask

@@ -31,8 +31,9 @@ struct Tile {
     int32_t kind;   // TileKind
     int32_t count;  // items in this tile
     int64_t begin;  // first item (model-global element or particle index)
-    int32_t id;     // particle tiles: row of the contact-gradient partial buffer
-    int32_t pad;
+    int32_t id;     // particle tiles: row of the contact-gradient partial buffer;
+                    // element tiles: first tile particle
+    int32_t pad;    // element tiles: number of tile particles
 };
 
 template <typename T>
@@ -53,22 +54,26 @@ template <typename T>
 struct ModelDev {
     int64_t np, ne, nt, nh, nslot;
     int32_t n_bodies, n_ptiles;
-    const int32_t* tet_idx;
+    // element records (SoA over elements); corner codes: tile-local particle |
+    // position in the tile's particle-sorted corner order << 16
+    const uint32_t* tet_code;
     const T* tet_dinv;
     const T* tet_vol;
-    const int32_t* tet_slot;
-    const int32_t* tri_idx;
+    const uint32_t* tri_code;
     const T* tri_dinv;
     const T* tri_area;
-    const int32_t* tri_slot;
-    const int32_t* hin_idx;
+    const uint32_t* hin_code;
     const T* hin_phi0;
-    const int32_t* hin_slot;
-    const int32_t* gbase;  // [n_slices] first slot of each 64-particle slice
-    const int32_t* pdeg;   // [np] element corners per particle
+    // tile particles (Tile.id = first, Tile.pad = count): particle index, corner run
+    // (first sorted corner | count << 16), partial slot
+    const int32_t* tp_id;
+    const int32_t* tp_run;
+    const int32_t* tp_slot;
+    const int32_t* gbase;  // [n_slices] first partial slot of each 64-particle slice
+    const int32_t* pdeg;   // [np] partials per particle
     const uint8_t* pinned;
     const BodyDev<T>* bodies;
-    T* slots;   // [nslot][4]
+    T* slots;   // [nslot][4] per-(tile, particle) partial sums
     T* cpart;   // [n_ptiles][4] contact-gradient partial sums
     T* lpart;   // [n_ptiles] loss partial sums
     // fused path: element records in colour order (same SoA layouts, corner indices
@@ -126,14 +131,17 @@ struct StepDev {
 };
 
 // Host-side launch helpers (defined in gsim_kernels.hip).  `stream` is a hipStream_t.
+// element passes: one workgroup (block threads) per element tile, `lds` bytes of
+// dynamic LDS (the largest tile's: forward 3 words per tile particle + 3 per
+// corner, adjoint 6 + 4)
 template <typename T>
-int launch_elem_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int items,
+int launch_elem_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, size_t lds,
                     void* stream);
 template <typename T>
 int launch_part_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int items,
                     void* stream);
 template <typename T>
-int launch_elem_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int items,
+int launch_elem_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, size_t lds,
                     void* stream);
 template <typename T>
 int launch_part_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int items,
@@ -153,6 +161,11 @@ int launch_fused_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t*
 template <typename T>
 int launch_fused_adj(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t* order, int n_bodies, size_t lds,
                      void* stream);
+// two-pass element tiles: at most ETILE consecutive elements of one kind of one
+// body, and at most ETILE_WORDS words of adjoint LDS (6 per tile particle, 4 per
+// corner)
+const int ETILE = 512, ETILE_WORDS = 16384;
+
 const int FUSED_FWD_BLOCK = 1024, FUSED_ADJ_BLOCK = 512;
 // dynamic LDS per particle of the largest body: x, v, f (forward); fbar, xbar-acc, f.fbar (adjoint)
 const int FUSED_FWD_LDS_WORDS = 9, FUSED_ADJ_LDS_WORDS = 10;

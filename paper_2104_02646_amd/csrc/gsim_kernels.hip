@@ -75,21 +75,27 @@ template <typename T> __device__ __forceinline__ void st3(T* __restrict__ p, int
     gst(p, 2 * n + i, a.z);
 }
 
+// Slots are 4-vectors accessed as one 16-byte (FP32) or two 16-byte (FP64)
+// global accesses (clang vector types: they can live in address space 1).
+typedef float gf4 __attribute__((ext_vector_type(4)));
+typedef double gd2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void st_slot(float* s, int64_t k, float a, float b, float c, float d) {
-    *reinterpret_cast<float4*>(s + 4 * k) = make_float4(a, b, c, d);
+    gf4 v = {a, b, c, d};
+    ((__attribute__((address_space(1))) gf4*)(s + 4 * k))[0] = v;
 }
 __device__ __forceinline__ void st_slot(double* s, int64_t k, double a, double b, double c, double d) {
-    double2* p = reinterpret_cast<double2*>(s + 4 * k);
-    p[0] = make_double2(a, b);
-    p[1] = make_double2(c, d);
+    __attribute__((address_space(1))) gd2* p = (__attribute__((address_space(1))) gd2*)(s + 4 * k);
+    gd2 v0 = {a, b}, v1 = {c, d};
+    p[0] = v0;
+    p[1] = v1;
 }
 __device__ __forceinline__ void ld_slot(const float* s, int64_t k, float& a, float& b, float& c, float& d) {
-    float4 q = *reinterpret_cast<const float4*>(s + 4 * k);
+    const gf4 q = ((const __attribute__((address_space(1))) gf4*)(s + 4 * k))[0];
     a = q.x; b = q.y; c = q.z; d = q.w;
 }
 __device__ __forceinline__ void ld_slot(const double* s, int64_t k, double& a, double& b, double& c, double& d) {
-    const double2* p = reinterpret_cast<const double2*>(s + 4 * k);
-    double2 q0 = p[0], q1 = p[1];
+    const __attribute__((address_space(1))) gd2* p = (const __attribute__((address_space(1))) gd2*)(s + 4 * k);
+    const gd2 q0 = p[0], q1 = p[1];
     a = q0.x; b = q0.y; c = q1.x; d = q1.y;
 }
 
@@ -444,53 +450,89 @@ __device__ __forceinline__ void block_sum(T v[N], T out[N]) {
 }
 
 // ------------------------------------------------------------- kernels ---
+// LDS accessors of the element kernels (SoA rows of length n).
 template <typename T>
-__device__ __forceinline__ void load_corners(const T* __restrict__ x, int64_t np, const int32_t* __restrict__ idx,
-                                             int64_t n, int64_t e, int nc, V3<T>* xe, int32_t* id) {
-    for (int c = 0; c < nc; ++c) {
-        id[c] = idx[c * n + e];
-        xe[c] = ld3(x, np, id[c]);
-    }
+__device__ __forceinline__ V3<T> lds3(const T* a, int n, int i) {
+    return mk3(a[i], a[n + i], a[2 * n + i]);
+}
+template <typename T>
+__device__ __forceinline__ void lds_st3(T* a, int n, int i, V3<T> v) {
+    a[i] = v.x;
+    a[n + i] = v.y;
+    a[2 * n + i] = v.z;
 }
 
+// Element pass: one workgroup per planned element tile.  The positions of the
+// tile's particles are staged in LDS once (instead of one gather per corner);
+// each element writes its corners' forces at their positions in the tile's
+// particle-sorted corner order; after one barrier each tile particle sums its
+// contiguous run of corners in that fixed order and writes one partial.  No
+// atomics; the result does not depend on the block size.
 template <typename T>
 __global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
                                                    const Tile* __restrict__ tiles) {
+    extern __shared__ __align__(16) unsigned char smem[];
     const Tile tl = tiles[blockIdx.x];
     const ModelDev<T>& M = md[tl.model];
     const StepDev<T>& S = sd[tl.model];
     const int64_t np = M.np;
-    for (int64_t l = threadIdx.x; l < tl.count; l += blockDim.x) {
+    const int m = tl.pad, ncn = (tl.kind == TILE_TRI ? 3 : 4) * tl.count;
+    T* xs = reinterpret_cast<T*>(smem);  // [3][m] tile-particle positions
+    T* cs = xs + 3 * m;                  // [3][ncn] corner forces, particle-sorted
+    for (int j = threadIdx.x; j < m; j += blockDim.x)
+        lds_st3(xs, m, j, ld3(S.x, np, (int64_t)gld(M.tp_id, (int64_t)tl.id + j)));
+    __syncthreads();
+    for (int l = threadIdx.x; l < tl.count; l += blockDim.x) {
         const int64_t e = tl.begin + l;
         if (tl.kind == TILE_TET) {
+            uint32_t cd[4];
             V3<T> x[4], f[4];
-            int32_t id[4];
-            load_corners(S.x, np, M.tet_idx, M.ne, e, 4, x, id);
             T D[9];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) D[k] = M.tet_dinv[k * M.ne + e];
-            const T act = S.act ? S.act[e] : T(0);
-            tet_force(x, D, M.tet_vol[e], S.mu[e], S.lam[e], act, f);
+            for (int c = 0; c < 4; ++c) {
+                cd[c] = gld(M.tet_code, c * M.ne + e);
+                x[c] = lds3(xs, m, (int)(cd[c] & 0xffffu));
+            }
 #pragma unroll
-            for (int c = 0; c < 4; ++c) st_slot(M.slots, M.tet_slot[c * M.ne + e], f[c].x, f[c].y, f[c].z, T(0));
+            for (int k = 0; k < 9; ++k) D[k] = gld(M.tet_dinv, k * M.ne + e);
+            const T act = S.act ? gld(S.act, e) : T(0);
+            tet_force(x, D, gld(M.tet_vol, e), gld(S.mu, e), gld(S.lam, e), act, f);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) lds_st3(cs, ncn, (int)(cd[c] >> 16), f[c]);
         } else if (tl.kind == TILE_TRI) {
+            uint32_t cd[3];
             V3<T> x[3], f[3];
-            int32_t id[3];
-            load_corners(S.x, np, M.tri_idx, M.nt, e, 3, x, id);
             T D[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) D[k] = M.tri_dinv[k * M.nt + e];
-            tri_force(x, D, M.tri_area[e], S.ktri[e], f);
+            for (int c = 0; c < 3; ++c) {
+                cd[c] = gld(M.tri_code, c * M.nt + e);
+                x[c] = lds3(xs, m, (int)(cd[c] & 0xffffu));
+            }
 #pragma unroll
-            for (int c = 0; c < 3; ++c) st_slot(M.slots, M.tri_slot[c * M.nt + e], f[c].x, f[c].y, f[c].z, T(0));
+            for (int k = 0; k < 4; ++k) D[k] = gld(M.tri_dinv, k * M.nt + e);
+            tri_force(x, D, gld(M.tri_area, e), gld(S.ktri, e), f);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) lds_st3(cs, ncn, (int)(cd[c] >> 16), f[c]);
         } else {
+            uint32_t cd[4];
             V3<T> x[4], f[4];
-            int32_t id[4];
-            load_corners(S.x, np, M.hin_idx, M.nh, e, 4, x, id);
-            hinge_force(x, M.hin_phi0[e], M.bodies[tl.body].kb, f);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) st_slot(M.slots, M.hin_slot[c * M.nh + e], f[c].x, f[c].y, f[c].z, T(0));
+            for (int c = 0; c < 4; ++c) {
+                cd[c] = gld(M.hin_code, c * M.nh + e);
+                x[c] = lds3(xs, m, (int)(cd[c] & 0xffffu));
+            }
+            hinge_force(x, gld(M.hin_phi0, e), M.bodies[tl.body].kb, f);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) lds_st3(cs, ncn, (int)(cd[c] >> 16), f[c]);
         }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        const int32_t run = gld(M.tp_run, (int64_t)tl.id + j);
+        const int r0 = run & 0xffff, rn = run >> 16;
+        V3<T> f = zero3<T>();
+        for (int k = 0; k < rn; ++k) f += lds3(cs, ncn, r0 + k);
+        st_slot(M.slots, gld(M.tp_slot, (int64_t)tl.id + j), f.x, f.y, f.z, T(0));
     }
 }
 
@@ -546,59 +588,105 @@ __device__ __forceinline__ V3<T> corner_fbar(const ModelDev<T>& M, const StepDev
     return vt * (dt * w);
 }
 
+// Adjoint element pass, same tiling: the tile particles' positions and adjoint
+// forces fbar are staged in LDS; each element writes (xbar contribution, f.fbar)
+// of its corners in particle-sorted order; each tile particle sums its run into
+// one partial.  Element-owned parameter gradients are read-modify-writes by the
+// element's own thread.
 template <typename T>
 __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
                                                    const Tile* __restrict__ tiles) {
+    extern __shared__ __align__(16) unsigned char smem[];
     const Tile tl = tiles[blockIdx.x];
     const ModelDev<T>& M = md[tl.model];
     const StepDev<T>& S = sd[tl.model];
     const int64_t np = M.np;
     const T dt = M.bodies[tl.body].dt;
-    for (int64_t l = threadIdx.x; l < tl.count; l += blockDim.x) {
+    const int m = tl.pad, ncn = (tl.kind == TILE_TRI ? 3 : 4) * tl.count;
+    T* xs = reinterpret_cast<T*>(smem);  // [3][m] tile-particle positions
+    T* fbs = xs + 3 * m;                 // [3][m] tile-particle adjoint forces
+    T* cs = fbs + 3 * m;                 // [4][ncn] corner (xbar, f.fbar), particle-sorted
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        const int64_t p = gld(M.tp_id, (int64_t)tl.id + j);
+        lds_st3(xs, m, j, ld3(S.x, np, p));
+        lds_st3(fbs, m, j, corner_fbar(M, S, p, dt));
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < tl.count; l += blockDim.x) {
         const int64_t e = tl.begin + l;
         if (tl.kind == TILE_TET) {
+            uint32_t cd[4];
             V3<T> x[4], f[4], fb[4], xb[4];
-            int32_t id[4];
-            load_corners(S.x, np, M.tet_idx, M.ne, e, 4, x, id);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) fb[c] = corner_fbar(M, S, id[c], dt);
             T D[9];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) D[k] = M.tet_dinv[k * M.ne + e];
-            const T act = S.act ? S.act[e] : T(0);
+            for (int c = 0; c < 4; ++c) {
+                cd[c] = gld(M.tet_code, c * M.ne + e);
+                x[c] = lds3(xs, m, (int)(cd[c] & 0xffffu));
+                fb[c] = lds3(fbs, m, (int)(cd[c] & 0xffffu));
+            }
+#pragma unroll
+            for (int k = 0; k < 9; ++k) D[k] = gld(M.tet_dinv, k * M.ne + e);
+            const T act = S.act ? gld(S.act, e) : T(0);
             T gmu, glam;
-            tet_adjoint(x, D, M.tet_vol[e], S.mu[e], S.lam[e], act, fb, f, xb, gmu, glam);
+            tet_adjoint(x, D, gld(M.tet_vol, e), gld(S.mu, e), gld(S.lam, e), act, fb, f, xb, gmu, glam);
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                st_slot(M.slots, M.tet_slot[c * M.ne + e], xb[c].x, xb[c].y, xb[c].z, dot(f[c], fb[c]));
-            if (S.g_mu) S.g_mu[e] += gmu;
-            if (S.g_lam) S.g_lam[e] += glam;
+            for (int c = 0; c < 4; ++c) {
+                const int q = (int)(cd[c] >> 16);
+                lds_st3(cs, ncn, q, xb[c]);
+                cs[3 * ncn + q] = dot(f[c], fb[c]);
+            }
+            if (S.g_mu) gst(S.g_mu, e, gld(S.g_mu, e) + gmu);
+            if (S.g_lam) gst(S.g_lam, e, gld(S.g_lam, e) + glam);
         } else if (tl.kind == TILE_TRI) {
+            uint32_t cd[3];
             V3<T> x[3], f[3], fb[3], xb[3];
-            int32_t id[3];
-            load_corners(S.x, np, M.tri_idx, M.nt, e, 3, x, id);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) fb[c] = corner_fbar(M, S, id[c], dt);
             T D[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) D[k] = M.tri_dinv[k * M.nt + e];
+            for (int c = 0; c < 3; ++c) {
+                cd[c] = gld(M.tri_code, c * M.nt + e);
+                x[c] = lds3(xs, m, (int)(cd[c] & 0xffffu));
+                fb[c] = lds3(fbs, m, (int)(cd[c] & 0xffffu));
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) D[k] = gld(M.tri_dinv, k * M.nt + e);
             T gk;
-            tri_adjoint(x, D, M.tri_area[e], S.ktri[e], fb, f, xb, gk);
+            tri_adjoint(x, D, gld(M.tri_area, e), gld(S.ktri, e), fb, f, xb, gk);
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                st_slot(M.slots, M.tri_slot[c * M.nt + e], xb[c].x, xb[c].y, xb[c].z, dot(f[c], fb[c]));
-            if (S.g_ktri) S.g_ktri[e] += gk;
+            for (int c = 0; c < 3; ++c) {
+                const int q = (int)(cd[c] >> 16);
+                lds_st3(cs, ncn, q, xb[c]);
+                cs[3 * ncn + q] = dot(f[c], fb[c]);
+            }
+            if (S.g_ktri) gst(S.g_ktri, e, gld(S.g_ktri, e) + gk);
         } else {
+            uint32_t cd[4];
             V3<T> x[4], f[4], fb[4], xb[4];
-            int32_t id[4];
-            load_corners(S.x, np, M.hin_idx, M.nh, e, 4, x, id);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) fb[c] = corner_fbar(M, S, id[c], dt);
-            hinge_adjoint(x, M.hin_phi0[e], M.bodies[tl.body].kb, fb, f, xb);
+            for (int c = 0; c < 4; ++c) {
+                cd[c] = gld(M.hin_code, c * M.nh + e);
+                x[c] = lds3(xs, m, (int)(cd[c] & 0xffffu));
+                fb[c] = lds3(fbs, m, (int)(cd[c] & 0xffffu));
+            }
+            hinge_adjoint(x, gld(M.hin_phi0, e), M.bodies[tl.body].kb, fb, f, xb);
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-                st_slot(M.slots, M.hin_slot[c * M.nh + e], xb[c].x, xb[c].y, xb[c].z, dot(f[c], fb[c]));
+            for (int c = 0; c < 4; ++c) {
+                const int q = (int)(cd[c] >> 16);
+                lds_st3(cs, ncn, q, xb[c]);
+                cs[3 * ncn + q] = dot(f[c], fb[c]);
+            }
         }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        const int32_t run = gld(M.tp_run, (int64_t)tl.id + j);
+        const int r0 = run & 0xffff, rn = run >> 16;
+        V3<T> xb = zero3<T>();
+        T d = T(0);
+        for (int k = 0; k < rn; ++k) {
+            xb += lds3(cs, ncn, r0 + k);
+            d += cs[3 * ncn + r0 + k];
+        }
+        st_slot(M.slots, gld(M.tp_slot, (int64_t)tl.id + j), xb.x, xb.y, xb.z, d);
     }
 }
 
@@ -748,16 +836,6 @@ __device__ __forceinline__ void lds_add_corners(T* a, int n, const int* li, cons
         a[2 * n + li[q]] = c[q][2] + v[q].z;
         if (w) a[3 * n + li[q]] = c[q][3] + w[q];
     }
-}
-template <typename T>
-__device__ __forceinline__ V3<T> lds3(const T* a, int n, int i) {
-    return mk3(a[i], a[n + i], a[2 * n + i]);
-}
-template <typename T>
-__device__ __forceinline__ void lds_st3(T* a, int n, int i, V3<T> v) {
-    a[i] = v.x;
-    a[n + i] = v.y;
-    a[2 * n + i] = v.z;
 }
 
 template <typename T>
@@ -1036,7 +1114,6 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
             st3(S.xbo, np, p0 + li, ld3(S.xb, np, p0 + li));
             st3(S.vbo, np, p0 + li, ld3(S.vb, np, p0 + li));
         }
-    T gc[4] = {T(0), T(0), T(0), T(0)};
     for (int step = S.nsteps - 1; step >= 0; --step) {
         const T* sx = step == 0 ? S.x : S.seg_in + (int64_t)(step - 1) * 6 * np;
         const T* sv = step == 0 ? S.v : sx + 3 * np;
@@ -1095,6 +1172,7 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
             for (int q = 0; q < 4; ++q) o.w[q] = dot(f[q], fb[q]);
         });
         // contact adjoint and the integrator's adjoint on the workgroup's own particles
+        T gc[4] = {T(0), T(0), T(0), T(0)};
         for (int li = threadIdx.x; li < npb; li += blockDim.x) {
             const int64_t p = p0 + li;
             const V3<T> xbp = ld3(S.xbo, np, p);
@@ -1111,14 +1189,18 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
             const T w = inv_mass(M, S, p);
             if (S.g_mass && w > T(0)) gst(S.g_mass, p, gld(S.g_mass, p) - w * ds);
         }
-        __syncthreads();
-    }
-    if (contact && S.g_contact) {
-        T tot[4];
-        block_sum<T, 4>(gc, tot);
-        if (threadIdx.x == 0)
+        // This step's contact-parameter gradient, reduced over the workgroup and added
+        // by one thread.  (No per-thread accumulator lives across steps: when such a
+        // value is spilled, the FP64 build was seen to restore it only in the lanes that
+        // ran the contact branch, leaving the other lanes' copies clobbered.)
+        if (contact && S.g_contact) {
+            T tot[4];
+            block_sum<T, 4>(gc, tot);
+            if (threadIdx.x == 0)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) S.g_contact[4 * b + k] += tot[k];
+                for (int k = 0; k < 4; ++k) gst(S.g_contact, 4 * b + k, gld(S.g_contact, 4 * b + k) + tot[k]);
+        }
+        __syncthreads();
     }
 }
 
@@ -1166,11 +1248,21 @@ int check_launch() {
 
 }  // namespace
 
+// The element kernels' dynamic LDS can exceed the default limit (FP64 tiles).
+// (raised once per kernel and size, outside any steady-state launch sequence)
+void allow_lds(const void* kernel, size_t lds, size_t& allowed) {
+    if (lds > allowed) {
+        (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        allowed = lds;
+    }
+}
 template <typename T>
-int launch_elem_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int,
+int launch_elem_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, size_t lds,
                     void* stream) {
     if (ntiles <= 0) return 0;
-    hipLaunchKernelGGL(k_elem_fwd<T>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
+    static size_t allowed = 48 * 1024;
+    allow_lds(reinterpret_cast<const void*>(&k_elem_fwd<T>), lds, allowed);
+    hipLaunchKernelGGL(k_elem_fwd<T>, dim3(ntiles), dim3(block), lds, (hipStream_t)stream, md, sd, tiles);
     return check_launch();
 }
 template <typename T>
@@ -1181,10 +1273,12 @@ int launch_part_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* til
     return check_launch();
 }
 template <typename T>
-int launch_elem_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int,
+int launch_elem_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, size_t lds,
                     void* stream) {
     if (ntiles <= 0) return 0;
-    hipLaunchKernelGGL(k_elem_adj<T>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
+    static size_t allowed = 48 * 1024;
+    allow_lds(reinterpret_cast<const void*>(&k_elem_adj<T>), lds, allowed);
+    hipLaunchKernelGGL(k_elem_adj<T>, dim3(ntiles), dim3(block), lds, (hipStream_t)stream, md, sd, tiles);
     return check_launch();
 }
 template <typename T>
@@ -1257,9 +1351,9 @@ int launch_fused_grads(const ModelDev<T>* md, const StepDev<T>* sd, void* stream
 }
 
 #define GSIM_INSTANTIATE(T)                                                                                          \
-    template int launch_elem_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
+    template int launch_elem_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, size_t, void*);     \
     template int launch_part_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
-    template int launch_elem_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
+    template int launch_elem_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, size_t, void*);     \
     template int launch_part_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
     template int launch_fill<T>(T*, int64_t, T, void*);                                                             \
     template int launch_contact_reduce<T>(const ModelDev<T>*, const StepDev<T>*, int, void*);                       \

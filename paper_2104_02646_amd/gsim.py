@@ -26,7 +26,7 @@ GSIM_E_WORKSPACE, GSIM_E_HIP, GSIM_E_NONFINITE, GSIM_E_UNSUPPORTED = -4, -5, -6,
 EXEC_PLAIN, EXEC_GRAPH, EXEC_FUSED = 0, 1, 2
 
 ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan_destroy", "gsim_plan_sizes",
-               "gsim_plan_counts", "gsim_plan_colouring", "gsim_plan_gather", "gsim_model_init", "gsim_model_destroy", "gsim_model_set_exec",
+               "gsim_plan_counts", "gsim_plan_colouring", "gsim_plan_tiles", "gsim_plan_codes", "gsim_plan_partials", "gsim_model_init", "gsim_model_destroy", "gsim_model_set_exec",
                "gsim_model_get_exec", "gsim_model_set_launch", "gsim_model_get_launch", "gsim_step", "gsim_step_backward", "gsim_rollout", "gsim_rollout_backward",
                "gsim_loss_mse", "gsim_model_set_timing", "gsim_model_read_timing",
                "gsim_engine_create", "gsim_engine_destroy", "gsim_engine_query_bytes", "gsim_engine_submit",
@@ -81,7 +81,9 @@ def load():
         lib.gsim_plan_sizes.argtypes = [vp, ip, ip, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
         lib.gsim_plan_counts.argtypes = [vp] + [C.POINTER(C.c_int64)] * 4 + [C.POINTER(C.c_int)]
         lib.gsim_plan_colouring.argtypes = [vp, ip, vp, vp, ip, C.POINTER(ip)]
-        lib.gsim_plan_gather.argtypes = [vp, ip, vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
+        lib.gsim_plan_tiles.argtypes = [vp, vp, C.POINTER(C.c_int64), vp, vp, vp, C.POINTER(C.c_int64)]
+        lib.gsim_plan_codes.argtypes = [vp, ip, vp]
+        lib.gsim_plan_partials.argtypes = [vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
         lib.gsim_model_init.argtypes = [vp, ip, ip, vp, C.c_size_t, vp, C.POINTER(vp)]
         lib.gsim_model_destroy.argtypes = [vp]
         lib.gsim_model_set_exec.argtypes = [vp, ip, ip, ip]
@@ -210,19 +212,34 @@ class Plan:
         _check(load().gsim_plan_colouring(self._h, kind, order.ctypes.data, bounds.ctypes.data, nb.value, C.byref(nb)))
         return order[:n], bounds[:nb.value]
 
-    def gather(self, kind):
-        """(slots [corners, n], slice_base, degree, n_slots) of the sliced-ELL gather table."""
+    def tiles(self):
+        """Element tiles of the two-pass path: (tiles [n, 5] = kind, body, first element,
+        count, first tile particle; tile-particle index, run, partial slot arrays)."""
+        nt, ntp = C.c_int64(), C.c_int64()
+        _check(load().gsim_plan_tiles(self._h, None, C.byref(nt), None, None, None, C.byref(ntp)))
+        tiles = np.zeros((max(nt.value, 1), 5), np.int64)
+        tp, run, slot = (np.zeros(max(ntp.value, 1), np.int32) for _ in range(3))
+        _check(load().gsim_plan_tiles(self._h, tiles.ctypes.data, C.byref(nt), tp.ctypes.data, run.ctypes.data,
+                                      slot.ctypes.data, C.byref(ntp)))
+        k = ntp.value
+        return tiles[:nt.value], tp[:k], run[:k], slot[:k]
+
+    def codes(self, kind):
+        """Corner codes [corners, n] of one kind: tile-local particle | sorted position << 16."""
         n = (self.ne, self.nt, self.nh)[kind]
         nc = 3 if kind == 1 else 4
+        out = np.zeros(max(nc * n, 1), np.uint32)
+        _check(load().gsim_plan_codes(self._h, kind, out.ctypes.data))
+        return out[:nc * n].reshape(nc, n)
+
+    def partials(self):
+        """(slice_base, degree, n_slots) of the sliced-ELL table of partials."""
         ns, nsl = C.c_int64(), C.c_int64()
-        _check(load().gsim_plan_gather(self._h, kind, None, None, C.byref(ns), None, C.byref(nsl)))
-        slots = np.zeros(max(nc * n, 1), np.int32)
+        _check(load().gsim_plan_partials(self._h, None, C.byref(ns), None, C.byref(nsl)))
         base = np.zeros(max(ns.value, 1), np.int32)
         deg = np.zeros(self.np, np.int32)
-        _check(load().gsim_plan_gather(self._h, kind, slots.ctypes.data, base.ctypes.data, C.byref(ns),
-                                       deg.ctypes.data, C.byref(nsl)))
-        return slots[:nc * n].reshape(nc, n), base[:ns.value], deg, nsl.value
-
+        _check(load().gsim_plan_partials(self._h, base.ctypes.data, C.byref(ns), deg.ctypes.data, C.byref(nsl)))
+        return base[:ns.value], deg, nsl.value
     def sizes(self, max_steps, ckpt_every):
         w, c, s = C.c_size_t(), C.c_size_t(), C.c_size_t()
         _check(load().gsim_plan_sizes(self._h, int(max_steps), int(ckpt_every), C.byref(w), C.byref(c), C.byref(s)))

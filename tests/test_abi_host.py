@@ -142,30 +142,55 @@ def test_colouring_classes_are_particle_disjoint(gs, which):
         assert ncol <= 128 * len(bodies) * 3
 
 
-def test_gather_table_is_a_bijection(gs):
-    """Every element corner owns exactly one slot; slot = slice_base + 64 k + lane with
-    k < degree of its particle; corner numbers per particle are 0..degree-1."""
-    bodies = [W.tiny_cube(0), W.cloth(5, n=10), W.batch_body(20001, lo=700, hi=900)]
+@pytest.mark.parametrize("which", ["mixed", "batch"])
+def test_element_tiles_and_partials(gs, which):
+    """Two-pass element tiles: they partition each body's elements of each kind into
+    runs of consecutive elements (at most 512, adjoint LDS within 16384 words); each
+    tile's particle list is exactly the sorted set of particles its elements touch;
+    corner codes point at the right tile particle and the sorted positions form one
+    contiguous run per tile particle, ordered by (element, corner); partial slots
+    are a bijection onto the sliced-ELL table (slot = slice base + 64 k + lane,
+    k < degree, k increasing in tile order)."""
+    bodies = ([W.tiny_cube(0), W.cloth(5, n=30), W.batch_body(20001, lo=700, hi=900)] if which == "mixed" else
+              [W.batch_body(20000 + i, lo=3000, hi=20000) for i in range(3)])
     p = gs.Plan(bodies)
     pk = gs.pack(bodies)
-    all_slots = []
-    seen = {}
-    for kind, idx in ((0, pk.tets), (1, pk.tris), (2, pk.hinges)):
-        if len(idx) == 0:
-            continue
-        slots, base, deg, nslot = p.gather(kind)
-        for c in range(idx.shape[1]):
-            for e in range(len(idx)):
-                part = int(idx[e, c])
-                s = int(slots[c, e])
-                b = int(np.searchsorted(pk.poff, part, side="right") - 1)
-                li = part - int(pk.poff[b])
-                g0 = sum(-(-int(pk.poff[q + 1] - pk.poff[q]) // 64) for q in range(b))
-                g = g0 + li // 64
-                k, lane = divmod(s - int(base[g]), 64)
-                assert lane == li % 64 and 0 <= k < deg[part], (kind, e, c)
-                seen.setdefault(part, []).append(k)
-                all_slots.append(s)
-    assert len(all_slots) == len(set(all_slots)) and max(all_slots) < nslot
-    for part, ks in seen.items():
-        assert sorted(ks) == list(range(len(ks)))
+    tiles, tp, run, slot = p.tiles()
+    base, deg, nslot = p.partials()
+    offs = {0: pk.eoff, 1: pk.toff, 2: pk.hoff}
+    idxs = {0: pk.tets, 1: pk.tris, 2: pk.hinges}
+    codes = {k: p.codes(k) for k in range(3) if len(idxs[k])}
+    covered = {k: np.zeros(len(idxs[k]), int) for k in range(3)}
+    seen_k = {}
+    ends = list(tiles[1:, 4]) + [len(tp)]
+    for i, (kind, body, e0, cnt, t0) in enumerate(tiles):
+        kind, body, e0, cnt, t0 = map(int, (kind, body, e0, cnt, t0))
+        idx, nc = idxs[kind], (3 if kind == 1 else 4)
+        assert 1 <= cnt <= 512 and offs[kind][body] <= e0 and e0 + cnt <= offs[kind][body + 1]
+        covered[kind][e0:e0 + cnt] += 1
+        parts = tp[t0:ends[i]]
+        m = len(parts)
+        assert np.array_equal(parts, np.unique(idx[e0:e0 + cnt].ravel()))
+        assert 6 * m + 4 * nc * cnt <= 16384
+        cd = codes[kind][:, e0:e0 + cnt]
+        lj, pos = cd & 0xFFFF, cd >> 16
+        assert np.array_equal(parts[lj], idx[e0:e0 + cnt].T)
+        assert np.array_equal(np.sort(pos.ravel()), np.arange(nc * cnt))
+        r0, rn = run[t0:ends[i]] & 0xFFFF, run[t0:ends[i]] >> 16
+        for j in range(m):
+            # the run of tile particle j: its corners, in (element, corner) order
+            mine = [(l, c) for l in range(cnt) for c in range(nc) if lj[c, l] == j]
+            assert rn[j] == len(mine)
+            assert [int(pos[c, l]) for l, c in mine] == list(range(r0[j], r0[j] + rn[j]))
+        for j, q in enumerate(parts):
+            q = int(q)
+            b = int(np.searchsorted(pk.poff, q, side="right") - 1)
+            li = q - int(pk.poff[b])
+            g = int(np.sum([-(-int(pk.poff[r + 1] - pk.poff[r]) // 64) for r in range(b)])) + li // 64
+            k, lane = divmod(int(slot[t0 + j]) - int(base[g]), 64)
+            assert lane == li % 64 and k == seen_k.get(q, 0) and k < deg[q]
+            seen_k[q] = k + 1
+    for k in range(3):
+        assert (covered[k] == 1).all()
+    assert len(set(slot.tolist())) == len(slot) and slot.max() < nslot
+    assert all(seen_k.get(q, 0) == deg[q] for q in range(len(deg)))
