@@ -136,7 +136,7 @@ int gsim_plan_counts(const gsim_plan* plan, int64_t* n_particles, int64_t* n_tet
  * max_bounds); returns GSIM_E_UNSUPPORTED if colouring failed (> 128 colours).
  * Two-pass element tiles (Sec. 2.1 step; the force scatter of App. A.1 as a
  * segmented reduction): per body and kind, consecutive elements are cut into
- * tiles of at most 512 elements (fewer when the tile's particles would need
+ * tiles of at most 256 elements (fewer when the tile's particles would need
  * more than 16384 words of adjoint LDS).  The tile particles of a tile are the
  * particles its elements touch, in increasing order; its corners are ordered by
  * (tile particle, element, corner), so each tile particle owns one run of
@@ -181,6 +181,16 @@ int gsim_model_get_exec(const gsim_model* model, int* exec, int* block, int* ite
  * fixes the summation tree of per-body contact gradients and losses. */
 int gsim_model_set_launch(gsim_model* model, int pass, int block, int items);
 int gsim_model_get_launch(const gsim_model* model, int pass, int* block, int* items);
+
+/* Launch lanes of the two-pass path (1 or 2; default 2 for models with at least
+ * two bodies).  With 2, the bodies are split into two groups of about equal
+ * work, and the element and particle passes of consecutive steps of the two
+ * groups run on two streams: the caller's and one the model owns (default
+ * priority), forked from and joined back into the caller's stream within each
+ * call, so a captured graph holds two parallel branches.  Results do not depend
+ * on the lanes.  GSIM_E_UNSUPPORTED for 2 lanes with a single body. */
+int gsim_model_set_lanes(gsim_model* model, int lanes);
+int gsim_model_get_lanes(const gsim_model* model, int* lanes);
 
 /* Kernel timing for measurement: with bit k of `mask` set, every launch of
  * kernel k is bracketed by HIP events on its stream (k: 0 element pass,

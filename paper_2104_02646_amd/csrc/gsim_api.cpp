@@ -178,7 +178,7 @@ void colour_elements(gsim_plan* P) {
 
 // Element tiles of the two-pass path.  Per body and element kind, consecutive
 // elements are cut into tiles of at most ETILE elements, a tile ending early when
-// its adjoint LDS (6 words per tile particle, 4 per corner) would exceed
+// its adjoint LDS (8 words per tile particle, 4 per corner) would exceed
 // ETILE_WORDS.  Per tile: its particles in increasing index order (the tile
 // particles); its corners ordered by (tile particle, element, corner), so each
 // tile particle's corners form one contiguous run; corner code = tile-local
@@ -213,7 +213,7 @@ int build_tiles(gsim_plan* P) {
                 while (e < off[b + 1] && e - s < ETILE) {
                     int add = 0;
                     for (int c = 0; c < nc; ++c) add += mark[idx[c * n + e]] != tile;
-                    const int64_t words = 6 * (int64_t)(parts.size() + add) + 4 * (int64_t)nc * (e - s + 1);
+                    const int64_t words = 8 * (int64_t)(parts.size() + add) + 4 * (int64_t)nc * (e - s + 1);
                     if (e > s && words > ETILE_WORDS) break;
                     for (int c = 0; c < nc; ++c) {
                         const int32_t p = idx[c * n + e];
@@ -249,8 +249,8 @@ int build_tiles(gsim_plan* P) {
                 P->etiles.push_back(t);
                 P->tp_id.insert(P->tp_id.end(), parts.begin(), parts.end());
                 const int64_t corners = (int64_t)nc * (e - s);
-                P->etile_words[0] = std::max<int64_t>(P->etile_words[0], 3 * (int64_t)m + 3 * corners);
-                P->etile_words[1] = std::max<int64_t>(P->etile_words[1], 6 * (int64_t)m + 4 * corners);
+                P->etile_words[0] = std::max<int64_t>(P->etile_words[0], 4 * (int64_t)m + 4 * corners);
+                P->etile_words[1] = std::max<int64_t>(P->etile_words[1], 8 * (int64_t)m + 4 * corners);
                 if ((int64_t)P->tp_id.size() > INT32_MAX) return fail(GSIM_E_UNSUPPORTED, "too many tile particles");
             }
         }
@@ -451,11 +451,12 @@ int build_plan(const gsim_model_desc* d, gsim_plan* P) {
 // ---------------------------------------------------------------- layout ---
 const int MIN_TILE = 64;  // smallest tile (block 64, 1 item): bounds the tile-list capacity
 
+// (each of the two launch lanes pads its list to a multiple of N_XCD)
 int64_t tile_capacity(const gsim_plan* P, bool particles) {
-    if (!particles) return (int64_t)P->etiles.size() + N_XCD;  // element tiles are planned
+    if (!particles) return (int64_t)P->etiles.size() + 2 * N_XCD;  // element tiles are planned
     int64_t n = 0;
     for (int b = 0; b < P->nb; ++b) n += (P->poff[b + 1] - P->poff[b] + MIN_TILE - 1) / MIN_TILE;
-    return n + N_XCD;
+    return n + 2 * N_XCD;
 }
 
 
@@ -550,8 +551,41 @@ int upload_tiles(gsim_model* m, void* stream) {
     int rows_e = 0;
     natural_tiles(m, false, 0, m->etiles_nat, rows_e);
     natural_tiles(m, true, m->pblock * m->pitems, m->ptiles_nat, m->n_ptile_rows);
-    xcd_order(m->etiles_nat, TILE_TET, 0, et, m->n_etiles);
-    xcd_order(m->ptiles_nat, TILE_PART, m->n_ptile_rows, pt, m->n_ptiles);
+    // launch lanes: bodies assigned largest first to the lane with less work so far;
+    // each lane's tiles are XCD-ordered on their own and the lists are concatenated
+    std::vector<int> lane(m->nb, 0);
+    if (m->lanes == 2) {
+        std::vector<int> order(m->nb);
+        for (int b = 0; b < m->nb; ++b) order[b] = b;
+        auto work = [&](int b) {
+            return (m->eoff[b + 1] - m->eoff[b]) + (m->toff[b + 1] - m->toff[b]) + (m->hoff[b + 1] - m->hoff[b]) +
+                   (m->poff[b + 1] - m->poff[b]);
+        };
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+        int64_t load[2] = {0, 0};
+        for (int b : order) {
+            const int l = load[1] < load[0] ? 1 : 0;
+            lane[b] = l;
+            load[l] += work(b);
+        }
+    }
+    auto by_lane = [&](const std::vector<Tile>& nat, int kind, int dummy, std::vector<Tile>& out, int* bounds) {
+        out.clear();
+        bounds[0] = 0;
+        for (int l = 0; l < 2; ++l) {
+            std::vector<Tile> mine, ord;
+            for (const Tile& t : nat)
+                if (lane[t.body] == l) mine.push_back(t);
+            int grid = 0;
+            xcd_order(mine, kind, dummy, ord, grid);
+            out.insert(out.end(), ord.begin(), ord.begin() + grid);
+            bounds[l + 1] = (int)out.size();
+        }
+    };
+    by_lane(m->etiles_nat, TILE_TET, 0, et, m->lane_e);
+    by_lane(m->ptiles_nat, TILE_PART, m->n_ptile_rows, pt, m->lane_p);
+    m->n_etiles = m->lane_e[2];
+    m->n_ptiles = m->lane_p[2];
     hipStream_t s = (hipStream_t)stream;
     if (!et.empty()) HIP_TRY(hipMemcpyAsync(m->ws + m->L.etiles, et.data(), et.size() * sizeof(Tile), hipMemcpyHostToDevice, s), "upload tiles");
     if (!pt.empty()) HIP_TRY(hipMemcpyAsync(m->ws + m->L.ptiles, pt.data(), pt.size() * sizeof(Tile), hipMemcpyHostToDevice, s), "upload tiles");
@@ -645,21 +679,60 @@ int timed(gsim_model* m, int k, void* stream, F launch) {
     return rc;
 }
 
+// Launch sequences.  Forward and adjoint passes of consecutive steps run on the
+// model's two lanes when it has them: lane 0 on the caller's stream, lane 1 on the
+// model's lane stream, forked from the caller's stream before the first such pass
+// and joined back before any launch that spans all bodies (and at the end).  The
+// lanes hold disjoint bodies, so results do not depend on the lanes.  With kernel
+// timing on, each pass is one launch over both lanes' tiles.
 template <typename T>
 int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
     Ctx<T> c = ctx<T>(m);
     const ModelDev<T>* md = c.md;
+    const bool two = m->lanes == 2 && m->timing_mask == 0;
+    hipStream_t s0 = (hipStream_t)stream, s1 = m->lane_stream;
+    bool forked = false;
+    auto join = [&]() -> int {
+        if (forked) {
+            HIP_TRY(hipEventRecord(m->ev_join, s1), "join lanes");
+            HIP_TRY(hipStreamWaitEvent(s0, m->ev_join, 0), "join lanes");
+            forked = false;
+        }
+        return GSIM_OK;
+    };
+    // one pass over lane l's tiles (l < 0: all tiles, one launch)
+    auto pass = [&](int l, const StepDev<T>* sd, bool adjoint) -> int {
+        const int e0 = l < 0 ? 0 : m->lane_e[l], e1 = l < 0 ? m->n_etiles : m->lane_e[l + 1];
+        const int p0 = l < 0 ? 0 : m->lane_p[l], p1 = l < 0 ? m->n_ptiles : m->lane_p[l + 1];
+        void* st = l == 1 ? (void*)s1 : stream;
+        if (!adjoint) {
+            LAUNCH_TRY(timed(m, 0, st, [&] { return launch_elem_fwd<T>(md, sd, c.et + e0, e1 - e0, m->block, m->etile_words[0] * sizeof(T), st); }), "element pass");
+            LAUNCH_TRY(timed(m, 1, st, [&] { return launch_part_fwd<T>(md, sd, c.pt + p0, p1 - p0, m->pblock, m->pitems, st); }), "particle pass");
+        } else {
+            LAUNCH_TRY(timed(m, 2, st, [&] { return launch_elem_adj<T>(md, sd, c.et + e0, e1 - e0, m->block, m->etile_words[1] * sizeof(T), st); }), "element adjoint");
+            LAUNCH_TRY(timed(m, 3, st, [&] { return launch_part_adj<T>(md, sd, c.pt + p0, p1 - p0, m->pblock, m->pitems, st); }), "particle adjoint");
+        }
+        return GSIM_OK;
+    };
     for (const Launch& l : seq) {
         const StepDev<T>* sd = c.table + l.row;
+        if (l.op == OP_FWD || l.op == OP_ADJ) {
+            const bool adjoint = l.op == OP_ADJ;
+            if (!two) {
+                if (int rc = pass(-1, sd, adjoint)) return rc;
+                continue;
+            }
+            if (!forked) {
+                HIP_TRY(hipEventRecord(m->ev_fork, s0), "fork lanes");
+                HIP_TRY(hipStreamWaitEvent(s1, m->ev_fork, 0), "fork lanes");
+                forked = true;
+            }
+            if (int rc = pass(0, sd, adjoint)) return rc;
+            if (int rc = pass(1, sd, adjoint)) return rc;
+            continue;
+        }
+        if (int rc = join()) return rc;
         switch (l.op) {
-            case OP_FWD:
-                LAUNCH_TRY(timed(m, 0, stream, [&] { return launch_elem_fwd<T>(md, sd, c.et, m->n_etiles, m->block, m->etile_words[0] * sizeof(T), stream); }), "element pass");
-                LAUNCH_TRY(timed(m, 1, stream, [&] { return launch_part_fwd<T>(md, sd, c.pt, m->n_ptiles, m->pblock, m->pitems, stream); }), "particle pass");
-                break;
-            case OP_ADJ:
-                LAUNCH_TRY(timed(m, 2, stream, [&] { return launch_elem_adj<T>(md, sd, c.et, m->n_etiles, m->block, m->etile_words[1] * sizeof(T), stream); }), "element adjoint");
-                LAUNCH_TRY(timed(m, 3, stream, [&] { return launch_part_adj<T>(md, sd, c.pt, m->n_ptiles, m->pblock, m->pitems, stream); }), "particle adjoint");
-                break;
             case OP_FILL_CPART:
                 LAUNCH_TRY(launch_fill<T>((T*)(m->ws + m->L.cpart), 4 * (int64_t)(m->n_ptile_rows + 1), T(0), stream), "clear");
                 break;
@@ -687,7 +760,7 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
                 break;
         }
     }
-    return GSIM_OK;
+    return join();
 }
 
 // Uploads table rows [row0, row0 + n) if they differ from the last upload.  The
@@ -1226,10 +1299,19 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     m->md_host.assign(reinterpret_cast<const char*>(&M), reinterpret_cast<const char*>(&M) + sizeof M);
     chk(hipHostMalloc((void**)&m->stage, sizeof(StepDev<T>) * L.table_cap, hipHostMallocDefault));
     chk(hipEventCreateWithFlags(&m->stage_evt, hipEventDisableTiming));
+    if (P->nb >= 2) {  // the second launch lane's stream and fork / join events
+        chk(hipStreamCreateWithFlags(&m->lane_stream, hipStreamNonBlocking));
+        chk(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
+        chk(hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming));
+        m->lanes = 2;
+    }
     if (e == hipSuccess) std::memset(m->stage, 0, sizeof(StepDev<T>) * L.table_cap);
     if (e != hipSuccess) {
         if (m->stage) (void)hipHostFree(m->stage);
         if (m->stage_evt) (void)hipEventDestroy(m->stage_evt);
+        if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+        if (m->ev_join) (void)hipEventDestroy(m->ev_join);
+        if (m->lane_stream) (void)hipStreamDestroy(m->lane_stream);
         delete m;
         return hip_fail(e, "upload model");
     }
@@ -1370,6 +1452,12 @@ int gsim_model_destroy(gsim_model* m) {
         (void)hipEventDestroy(m->stage_evt);
     }
     if (m->stage) (void)hipHostFree(m->stage);
+    if (m->lane_stream) {
+        (void)hipStreamSynchronize(m->lane_stream);
+        (void)hipStreamDestroy(m->lane_stream);
+    }
+    if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+    if (m->ev_join) (void)hipEventDestroy(m->ev_join);
     for (auto& p : m->pending) {
         (void)hipEventSynchronize(p.b);
         m->evt_pool.push_back(p.a);
@@ -1393,6 +1481,22 @@ int gsim_model_set_launch(gsim_model* m, int pass, int block, int items) {
     b = block;
     i = items;
     return guarded<double>([&]() { return m->dtype == GSIM_F64 ? upload_tiles<double>(m, nullptr) : upload_tiles<float>(m, nullptr); });
+}
+
+int gsim_model_set_lanes(gsim_model* m, int lanes) {
+    if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    if (lanes != 1 && lanes != 2) return fail(GSIM_E_INVALID, "lanes must be 1 or 2");
+    if (lanes == 2 && m->nb < 2) return fail(GSIM_E_UNSUPPORTED, "two lanes need at least two bodies");
+    if (m->lanes == lanes) return GSIM_OK;
+    HIP_TRY(hipDeviceSynchronize(), "synchronize before retiling");
+    m->lanes = lanes;
+    return guarded<double>([&]() { return m->dtype == GSIM_F64 ? upload_tiles<double>(m, nullptr) : upload_tiles<float>(m, nullptr); });
+}
+
+int gsim_model_get_lanes(const gsim_model* m, int* lanes) {
+    if (!m || !lanes) return fail(GSIM_E_INVALID, "NULL argument");
+    *lanes = m->lanes;
+    return GSIM_OK;
 }
 
 int gsim_model_get_launch(const gsim_model* m, int pass, int* block, int* items) {

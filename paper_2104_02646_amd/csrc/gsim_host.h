@@ -92,6 +92,14 @@ struct gsim_model {
     int block = 256, items = 1;    // element passes: threads per element tile (items: unused, tiles are planned)
     int pblock = 256, pitems = 1;  // particle passes
     int n_etiles = 0, n_ptiles = 0;   // launched grid sizes (including XCD padding)
+    // launch lanes: with 2, the bodies are split into two groups of about equal work
+    // whose passes run on two streams (the caller's and lane_stream) between a fork
+    // and a join; lane l's tiles are [lane_e[l], lane_e[l + 1]) of the element list
+    // and [lane_p[l], lane_p[l + 1]) of the particle list
+    int lanes = 1;
+    int lane_e[3] = {0, 0, 0}, lane_p[3] = {0, 0, 0};
+    hipStream_t lane_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int n_ptile_rows = 0;             // real particle tiles (contact / loss partial rows)
     std::vector<char> bodies_host;    // BodyDev<T>[nb] as last uploaded
     char* stage = nullptr;            // pinned copy of the launch table as last uploaded

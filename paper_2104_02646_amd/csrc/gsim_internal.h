@@ -132,8 +132,8 @@ struct StepDev {
 
 // Host-side launch helpers (defined in gsim_kernels.hip).  `stream` is a hipStream_t.
 // element passes: one workgroup (block threads) per element tile, `lds` bytes of
-// dynamic LDS (the largest tile's: forward 3 words per tile particle + 3 per
-// corner, adjoint 6 + 4)
+// dynamic LDS (the largest tile's: forward 4 words per tile particle + 4 per
+// corner, adjoint 8 + 4)
 template <typename T>
 int launch_elem_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, size_t lds,
                     void* stream);
@@ -162,9 +162,9 @@ template <typename T>
 int launch_fused_adj(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t* order, int n_bodies, size_t lds,
                      void* stream);
 // two-pass element tiles: at most ETILE consecutive elements of one kind of one
-// body, and at most ETILE_WORDS words of adjoint LDS (6 per tile particle, 4 per
+// body, and at most ETILE_WORDS words of adjoint LDS (8 per tile particle, 4 per
 // corner)
-const int ETILE = 512, ETILE_WORDS = 16384;
+const int ETILE = 256, ETILE_WORDS = 16384;
 
 const int FUSED_FWD_BLOCK = 1024, FUSED_ADJ_BLOCK = 512;
 // dynamic LDS per particle of the largest body: x, v, f (forward); fbar, xbar-acc, f.fbar (adjoint)

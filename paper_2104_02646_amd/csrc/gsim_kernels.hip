@@ -450,7 +450,21 @@ __device__ __forceinline__ void block_sum(T v[N], T out[N]) {
 }
 
 // ------------------------------------------------------------- kernels ---
-// LDS accessors of the element kernels (SoA rows of length n).
+// A 4-vector in LDS, read and written as one 16-byte (FP32) access.
+template <typename T>
+struct alignas(4 * sizeof(T)) L4 {
+    T x, y, z, w;
+};
+template <typename T>
+__device__ __forceinline__ V3<T> v3(const L4<T>& a) {
+    return mk3(a.x, a.y, a.z);
+}
+template <typename T>
+__device__ __forceinline__ L4<T> l4(V3<T> v, T w) {
+    return L4<T>{v.x, v.y, v.z, w};
+}
+
+// LDS accessors of the fused kernels (SoA rows of length n).
 template <typename T>
 __device__ __forceinline__ V3<T> lds3(const T* a, int n, int i) {
     return mk3(a[i], a[n + i], a[2 * n + i]);
@@ -463,7 +477,8 @@ __device__ __forceinline__ void lds_st3(T* a, int n, int i, V3<T> v) {
 }
 
 // Element pass: one workgroup per planned element tile.  The positions of the
-// tile's particles are staged in LDS once (instead of one gather per corner);
+// tile's particles are staged in LDS once (instead of one gather per corner), as
+// 16-byte 4-vectors like the corner contributions (one LDS access per corner);
 // each element writes its corners' forces at their positions in the tile's
 // particle-sorted corner order; after one barrier each tile particle sums its
 // contiguous run of corners in that fixed order and writes one partial.  No
@@ -476,11 +491,11 @@ __global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict_
     const ModelDev<T>& M = md[tl.model];
     const StepDev<T>& S = sd[tl.model];
     const int64_t np = M.np;
-    const int m = tl.pad, ncn = (tl.kind == TILE_TRI ? 3 : 4) * tl.count;
-    T* xs = reinterpret_cast<T*>(smem);  // [3][m] tile-particle positions
-    T* cs = xs + 3 * m;                  // [3][ncn] corner forces, particle-sorted
+    const int m = tl.pad;
+    L4<T>* xs = reinterpret_cast<L4<T>*>(smem);  // [m] tile-particle positions
+    L4<T>* cs = xs + m;                          // [corners] corner forces, particle-sorted
     for (int j = threadIdx.x; j < m; j += blockDim.x)
-        lds_st3(xs, m, j, ld3(S.x, np, (int64_t)gld(M.tp_id, (int64_t)tl.id + j)));
+        xs[j] = l4(ld3(S.x, np, (int64_t)gld(M.tp_id, (int64_t)tl.id + j)), T(0));
     __syncthreads();
     for (int l = threadIdx.x; l < tl.count; l += blockDim.x) {
         const int64_t e = tl.begin + l;
@@ -491,14 +506,14 @@ __global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict_
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 cd[c] = gld(M.tet_code, c * M.ne + e);
-                x[c] = lds3(xs, m, (int)(cd[c] & 0xffffu));
+                x[c] = v3(xs[cd[c] & 0xffffu]);
             }
 #pragma unroll
             for (int k = 0; k < 9; ++k) D[k] = gld(M.tet_dinv, k * M.ne + e);
             const T act = S.act ? gld(S.act, e) : T(0);
             tet_force(x, D, gld(M.tet_vol, e), gld(S.mu, e), gld(S.lam, e), act, f);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) lds_st3(cs, ncn, (int)(cd[c] >> 16), f[c]);
+            for (int c = 0; c < 4; ++c) cs[cd[c] >> 16] = l4(f[c], T(0));
         } else if (tl.kind == TILE_TRI) {
             uint32_t cd[3];
             V3<T> x[3], f[3];
@@ -506,24 +521,24 @@ __global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict_
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 cd[c] = gld(M.tri_code, c * M.nt + e);
-                x[c] = lds3(xs, m, (int)(cd[c] & 0xffffu));
+                x[c] = v3(xs[cd[c] & 0xffffu]);
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) D[k] = gld(M.tri_dinv, k * M.nt + e);
             tri_force(x, D, gld(M.tri_area, e), gld(S.ktri, e), f);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) lds_st3(cs, ncn, (int)(cd[c] >> 16), f[c]);
+            for (int c = 0; c < 3; ++c) cs[cd[c] >> 16] = l4(f[c], T(0));
         } else {
             uint32_t cd[4];
             V3<T> x[4], f[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 cd[c] = gld(M.hin_code, c * M.nh + e);
-                x[c] = lds3(xs, m, (int)(cd[c] & 0xffffu));
+                x[c] = v3(xs[cd[c] & 0xffffu]);
             }
             hinge_force(x, gld(M.hin_phi0, e), M.bodies[tl.body].kb, f);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) lds_st3(cs, ncn, (int)(cd[c] >> 16), f[c]);
+            for (int c = 0; c < 4; ++c) cs[cd[c] >> 16] = l4(f[c], T(0));
         }
     }
     __syncthreads();
@@ -531,7 +546,7 @@ __global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict_
         const int32_t run = gld(M.tp_run, (int64_t)tl.id + j);
         const int r0 = run & 0xffff, rn = run >> 16;
         V3<T> f = zero3<T>();
-        for (int k = 0; k < rn; ++k) f += lds3(cs, ncn, r0 + k);
+        for (int k = 0; k < rn; ++k) f += v3(cs[r0 + k]);
         st_slot(M.slots, gld(M.tp_slot, (int64_t)tl.id + j), f.x, f.y, f.z, T(0));
     }
 }
@@ -602,14 +617,14 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
     const StepDev<T>& S = sd[tl.model];
     const int64_t np = M.np;
     const T dt = M.bodies[tl.body].dt;
-    const int m = tl.pad, ncn = (tl.kind == TILE_TRI ? 3 : 4) * tl.count;
-    T* xs = reinterpret_cast<T*>(smem);  // [3][m] tile-particle positions
-    T* fbs = xs + 3 * m;                 // [3][m] tile-particle adjoint forces
-    T* cs = fbs + 3 * m;                 // [4][ncn] corner (xbar, f.fbar), particle-sorted
+    const int m = tl.pad;
+    L4<T>* xs = reinterpret_cast<L4<T>*>(smem);  // [m] tile-particle positions
+    L4<T>* fbs = xs + m;                         // [m] tile-particle adjoint forces
+    L4<T>* cs = fbs + m;                         // [corners] corner (xbar, f.fbar), particle-sorted
     for (int j = threadIdx.x; j < m; j += blockDim.x) {
         const int64_t p = gld(M.tp_id, (int64_t)tl.id + j);
-        lds_st3(xs, m, j, ld3(S.x, np, p));
-        lds_st3(fbs, m, j, corner_fbar(M, S, p, dt));
+        xs[j] = l4(ld3(S.x, np, p), T(0));
+        fbs[j] = l4(corner_fbar(M, S, p, dt), T(0));
     }
     __syncthreads();
     for (int l = threadIdx.x; l < tl.count; l += blockDim.x) {
@@ -621,8 +636,8 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 cd[c] = gld(M.tet_code, c * M.ne + e);
-                x[c] = lds3(xs, m, (int)(cd[c] & 0xffffu));
-                fb[c] = lds3(fbs, m, (int)(cd[c] & 0xffffu));
+                x[c] = v3(xs[cd[c] & 0xffffu]);
+                fb[c] = v3(fbs[cd[c] & 0xffffu]);
             }
 #pragma unroll
             for (int k = 0; k < 9; ++k) D[k] = gld(M.tet_dinv, k * M.ne + e);
@@ -631,9 +646,7 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
             tet_adjoint(x, D, gld(M.tet_vol, e), gld(S.mu, e), gld(S.lam, e), act, fb, f, xb, gmu, glam);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const int q = (int)(cd[c] >> 16);
-                lds_st3(cs, ncn, q, xb[c]);
-                cs[3 * ncn + q] = dot(f[c], fb[c]);
+                cs[cd[c] >> 16] = l4(xb[c], dot(f[c], fb[c]));
             }
             if (S.g_mu) gst(S.g_mu, e, gld(S.g_mu, e) + gmu);
             if (S.g_lam) gst(S.g_lam, e, gld(S.g_lam, e) + glam);
@@ -644,8 +657,8 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 cd[c] = gld(M.tri_code, c * M.nt + e);
-                x[c] = lds3(xs, m, (int)(cd[c] & 0xffffu));
-                fb[c] = lds3(fbs, m, (int)(cd[c] & 0xffffu));
+                x[c] = v3(xs[cd[c] & 0xffffu]);
+                fb[c] = v3(fbs[cd[c] & 0xffffu]);
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) D[k] = gld(M.tri_dinv, k * M.nt + e);
@@ -653,9 +666,7 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
             tri_adjoint(x, D, gld(M.tri_area, e), gld(S.ktri, e), fb, f, xb, gk);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const int q = (int)(cd[c] >> 16);
-                lds_st3(cs, ncn, q, xb[c]);
-                cs[3 * ncn + q] = dot(f[c], fb[c]);
+                cs[cd[c] >> 16] = l4(xb[c], dot(f[c], fb[c]));
             }
             if (S.g_ktri) gst(S.g_ktri, e, gld(S.g_ktri, e) + gk);
         } else {
@@ -664,15 +675,13 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 cd[c] = gld(M.hin_code, c * M.nh + e);
-                x[c] = lds3(xs, m, (int)(cd[c] & 0xffffu));
-                fb[c] = lds3(fbs, m, (int)(cd[c] & 0xffffu));
+                x[c] = v3(xs[cd[c] & 0xffffu]);
+                fb[c] = v3(fbs[cd[c] & 0xffffu]);
             }
             hinge_adjoint(x, gld(M.hin_phi0, e), M.bodies[tl.body].kb, fb, f, xb);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const int q = (int)(cd[c] >> 16);
-                lds_st3(cs, ncn, q, xb[c]);
-                cs[3 * ncn + q] = dot(f[c], fb[c]);
+                cs[cd[c] >> 16] = l4(xb[c], dot(f[c], fb[c]));
             }
         }
     }
@@ -683,8 +692,9 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
         V3<T> xb = zero3<T>();
         T d = T(0);
         for (int k = 0; k < rn; ++k) {
-            xb += lds3(cs, ncn, r0 + k);
-            d += cs[3 * ncn + r0 + k];
+            const L4<T> c = cs[r0 + k];
+            xb += v3(c);
+            d += c.w;
         }
         st_slot(M.slots, gld(M.tp_slot, (int64_t)tl.id + j), xb.x, xb.y, xb.z, d);
     }

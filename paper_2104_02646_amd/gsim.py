@@ -27,7 +27,7 @@ EXEC_PLAIN, EXEC_GRAPH, EXEC_FUSED = 0, 1, 2
 
 ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan_destroy", "gsim_plan_sizes",
                "gsim_plan_counts", "gsim_plan_colouring", "gsim_plan_tiles", "gsim_plan_codes", "gsim_plan_partials", "gsim_model_init", "gsim_model_destroy", "gsim_model_set_exec",
-               "gsim_model_get_exec", "gsim_model_set_launch", "gsim_model_get_launch", "gsim_step", "gsim_step_backward", "gsim_rollout", "gsim_rollout_backward",
+               "gsim_model_get_exec", "gsim_model_set_launch", "gsim_model_get_launch", "gsim_model_set_lanes", "gsim_model_get_lanes", "gsim_step", "gsim_step_backward", "gsim_rollout", "gsim_rollout_backward",
                "gsim_loss_mse", "gsim_model_set_timing", "gsim_model_read_timing",
                "gsim_engine_create", "gsim_engine_destroy", "gsim_engine_query_bytes", "gsim_engine_submit",
                "gsim_engine_tick", "gsim_engine_poll", "gsim_engine_stats")
@@ -90,6 +90,8 @@ def load():
         lib.gsim_model_get_exec.argtypes = [vp, C.POINTER(ip), C.POINTER(ip), C.POINTER(ip)]
         lib.gsim_model_set_launch.argtypes = [vp, ip, ip, ip]
         lib.gsim_model_get_launch.argtypes = [vp, ip, C.POINTER(ip), C.POINTER(ip)]
+        lib.gsim_model_set_lanes.argtypes = [vp, ip]
+        lib.gsim_model_get_lanes.argtypes = [vp, C.POINTER(ip)]
         lib.gsim_step.argtypes = [vp, C.POINTER(_Params), _State, _State, ip, vp]
         lib.gsim_step_backward.argtypes = [vp, C.POINTER(_Params), _State, _State, _State, C.POINTER(_Grads), vp]
         lib.gsim_rollout.argtypes = [vp, C.POINTER(_Params), _State, ip, vp, _State, vp]
@@ -294,6 +296,15 @@ class Model:
         b, i = C.c_int(), C.c_int()
         _check(load().gsim_model_get_launch(self._h, int(pass_), C.byref(b), C.byref(i)))
         return b.value, i.value
+
+    def set_lanes(self, lanes):
+        """Launch lanes of the two-pass path (1 or 2; bodies split in two concurrent groups)."""
+        _check(load().gsim_model_set_lanes(self._h, int(lanes)))
+
+    def get_lanes(self):
+        n = C.c_int()
+        _check(load().gsim_model_get_lanes(self._h, C.byref(n)))
+        return n.value
 
     def get_exec(self):
         e, b, i = C.c_int(), C.c_int(), C.c_int()

@@ -145,7 +145,7 @@ def test_colouring_classes_are_particle_disjoint(gs, which):
 @pytest.mark.parametrize("which", ["mixed", "batch"])
 def test_element_tiles_and_partials(gs, which):
     """Two-pass element tiles: they partition each body's elements of each kind into
-    runs of consecutive elements (at most 512, adjoint LDS within 16384 words); each
+    runs of consecutive elements (at most 256, adjoint LDS within 16384 words); each
     tile's particle list is exactly the sorted set of particles its elements touch;
     corner codes point at the right tile particle and the sorted positions form one
     contiguous run per tile particle, ordered by (element, corner); partial slots
@@ -166,12 +166,12 @@ def test_element_tiles_and_partials(gs, which):
     for i, (kind, body, e0, cnt, t0) in enumerate(tiles):
         kind, body, e0, cnt, t0 = map(int, (kind, body, e0, cnt, t0))
         idx, nc = idxs[kind], (3 if kind == 1 else 4)
-        assert 1 <= cnt <= 512 and offs[kind][body] <= e0 and e0 + cnt <= offs[kind][body + 1]
+        assert 1 <= cnt <= 256 and offs[kind][body] <= e0 and e0 + cnt <= offs[kind][body + 1]
         covered[kind][e0:e0 + cnt] += 1
         parts = tp[t0:ends[i]]
         m = len(parts)
         assert np.array_equal(parts, np.unique(idx[e0:e0 + cnt].ravel()))
-        assert 6 * m + 4 * nc * cnt <= 16384
+        assert 8 * m + 4 * nc * cnt <= 16384
         cd = codes[kind][:, e0:e0 + cnt]
         lj, pos = cd & 0xFFFF, cd >> 16
         assert np.array_equal(parts[lj], idx[e0:e0 + cnt].T)

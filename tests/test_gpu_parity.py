@@ -274,3 +274,39 @@ def test_repeat_runs_bitwise(gs):
     assert np.array_equal(a[0], b[0])
     for k in a[2]:
         assert np.array_equal(a[2][k], b[2][k])
+
+def test_lanes_bitwise(gs):
+    """Two launch lanes (bodies split into two concurrently running groups, plain and
+    graph execution) give the same bits as one lane."""
+    bodies = [W.batch_body(21000 + i, lo=300, hi=4000) for i in range(7)] + [W.cloth(8, n=12, size=0.5)]
+    for b in bodies:
+        b.target = W.synthetic_target(b, 2)
+    T, K = 24, 5
+    stream = torch.cuda.Stream()
+    out = {}
+    with torch.cuda.stream(stream):
+        m = gs.Model(bodies, torch.float32, max_steps=T, ckpt_every=K)
+        assert m.get_lanes() == 2
+        p = m.params_from_bodies()
+        x0 = gs.soa(np.concatenate([b.x0 for b in bodies]))
+        v0 = gs.soa(np.concatenate([b.v0 for b in bodies]))
+        tgt = gs.soa(np.concatenate([b.target for b in bodies]))
+        for lanes in (1, 2):
+            for mode in (gs.EXEC_PLAIN, gs.EXEC_GRAPH):
+                m.set_lanes(lanes)
+                m.set_exec(mode)
+                for rep in range(2):
+                    xT, vT = m.rollout(p, x0, v0, T, stream=stream)
+                    loss, xb, vb = m.loss_mse(xT, tgt, stream=stream)
+                    g = m.zero_grads()
+                    xb0, vb0 = m.rollout_backward(p, T, xb, vb, g, stream=stream)
+                    torch.cuda.synchronize()
+                    out[(lanes, mode, rep)] = [xT.clone(), loss.clone(), xb0.clone()] + [v.clone() for v in g.values()]
+    ref = out[(1, gs.EXEC_PLAIN, 0)]
+    for key, val in out.items():
+        for a, b in zip(val, ref):
+            assert torch.equal(a, b), key
+    single = gs.Model([bodies[0]], torch.float32, max_steps=T, ckpt_every=K)
+    assert single.get_lanes() == 1
+    with pytest.raises(gs.GsimError):
+        single.set_lanes(2)
