@@ -42,8 +42,8 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
     ntp = tile particles (sum over element tiles of the particles each touches).
       element pass, per tet: corner codes 16, D_m^-1 36, volume 4, mu + lambda 8
         (adjoint: + mu-bar, lambda-bar read-modify-write 16); per tile particle:
-        index, run, partial slot 12, positions 12 (adjoint: + xbar+, vbar+ 24, mass 4,
-        pinned 1), partial write 16;
+        record (index, run, partial slot, pad) 16, positions 12 (adjoint: + xbar+,
+        vbar+ 24, mass 4, pinned 1), partial write 16;
       particle pass, per particle: partial count 4, x, v 24, mass 4, pinned 1, writes
         24 (adjoint: xbar+, vbar+ 24, x, v 24, mass 4, pinned 1, partial count 4,
         writes 24, mass-bar read-modify-write 8); per partial: 16; checkpoint stores
@@ -51,11 +51,11 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
     nseg = -(-T // K)
     fwd_passes = T + (T - nseg)  # rollout + segment recompute
     if kernel == "element_fwd":
-        return fwd_passes * (64 * ne + 40 * ntp)
+        return fwd_passes * (64 * ne + 44 * ntp)
     if kernel == "particle_fwd":
         return fwd_passes * (57 * np_ + 16 * ntp) + nseg * 24 * np_
     if kernel == "element_adj":
-        return T * (80 * ne + 69 * ntp)
+        return T * (80 * ne + 73 * ntp)
     if kernel == "particle_adj":
         return T * (89 * np_ + 16 * ntp)
     if kernel == "fused_fwd":

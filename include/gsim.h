@@ -182,13 +182,13 @@ int gsim_model_get_exec(const gsim_model* model, int* exec, int* block, int* ite
 int gsim_model_set_launch(gsim_model* model, int pass, int block, int items);
 int gsim_model_get_launch(const gsim_model* model, int pass, int* block, int* items);
 
-/* Launch lanes of the two-pass path (1 or 2; default 2 for models with at least
- * two bodies).  With 2, the bodies are split into two groups of about equal
- * work, and the element and particle passes of consecutive steps of the two
- * groups run on two streams: the caller's and one the model owns (default
+/* Launch lanes of the two-pass path (1..4; a new model with at least two bodies
+ * starts with 2).  With L lanes the bodies are split into L groups of about
+ * equal work, and the element and particle passes of consecutive steps of the
+ * groups run on L streams: the caller's and L - 1 the model owns (default
  * priority), forked from and joined back into the caller's stream within each
- * call, so a captured graph holds two parallel branches.  Results do not depend
- * on the lanes.  GSIM_E_UNSUPPORTED for 2 lanes with a single body. */
+ * call, so a captured graph holds L parallel branches.  Results do not depend
+ * on the lanes.  GSIM_E_UNSUPPORTED for more lanes than bodies. */
 int gsim_model_set_lanes(gsim_model* model, int lanes);
 int gsim_model_get_lanes(const gsim_model* model, int* lanes);
 

@@ -451,12 +451,12 @@ int build_plan(const gsim_model_desc* d, gsim_plan* P) {
 // ---------------------------------------------------------------- layout ---
 const int MIN_TILE = 64;  // smallest tile (block 64, 1 item): bounds the tile-list capacity
 
-// (each of the two launch lanes pads its list to a multiple of N_XCD)
+// (each launch lane pads its list to a multiple of N_XCD)
 int64_t tile_capacity(const gsim_plan* P, bool particles) {
-    if (!particles) return (int64_t)P->etiles.size() + 2 * N_XCD;  // element tiles are planned
+    if (!particles) return (int64_t)P->etiles.size() + MAX_LANES * N_XCD;  // element tiles are planned
     int64_t n = 0;
     for (int b = 0; b < P->nb; ++b) n += (P->poff[b + 1] - P->poff[b] + MIN_TILE - 1) / MIN_TILE;
-    return n + 2 * N_XCD;
+    return n + MAX_LANES * N_XCD;
 }
 
 
@@ -484,9 +484,7 @@ Layout make_layout(const gsim_plan* P, int max_steps) {
     L.tri_area = take(nt * sizeof(T));
     L.hin_code = take(4 * nh * 4);
     L.hin_phi0 = take(nh * sizeof(T));
-    L.tp_id = take(P->tp_id.size() * 4 + 4);
-    L.tp_run = take(P->tp_run.size() * 4 + 4);
-    L.tp_slot = take(P->tp_slot.size() * 4 + 4);
+    L.tp = take(P->tp_id.size() * 16 + 16);
     L.gbase = take(P->gbase.size() * 4 + 4);
     L.pdeg = take(np * 4);
     L.pinned = take(np);
@@ -551,10 +549,10 @@ int upload_tiles(gsim_model* m, void* stream) {
     int rows_e = 0;
     natural_tiles(m, false, 0, m->etiles_nat, rows_e);
     natural_tiles(m, true, m->pblock * m->pitems, m->ptiles_nat, m->n_ptile_rows);
-    // launch lanes: bodies assigned largest first to the lane with less work so far;
-    // each lane's tiles are XCD-ordered on their own and the lists are concatenated
+    // launch lanes: bodies assigned largest first to the lane with the least work so
+    // far; each lane's tiles are XCD-ordered on their own and the lists concatenated
     std::vector<int> lane(m->nb, 0);
-    if (m->lanes == 2) {
+    if (m->lanes > 1) {
         std::vector<int> order(m->nb);
         for (int b = 0; b < m->nb; ++b) order[b] = b;
         auto work = [&](int b) {
@@ -562,17 +560,19 @@ int upload_tiles(gsim_model* m, void* stream) {
                    (m->poff[b + 1] - m->poff[b]);
         };
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
-        int64_t load[2] = {0, 0};
+        int64_t load[MAX_LANES] = {};
         for (int b : order) {
-            const int l = load[1] < load[0] ? 1 : 0;
+            int l = 0;
+            for (int k = 1; k < m->lanes; ++k)
+                if (load[k] < load[l]) l = k;
             lane[b] = l;
             load[l] += work(b);
         }
     }
     auto by_lane = [&](const std::vector<Tile>& nat, int kind, int dummy, std::vector<Tile>& out, int* bounds) {
         out.clear();
-        bounds[0] = 0;
-        for (int l = 0; l < 2; ++l) {
+        for (int l = 0; l <= MAX_LANES; ++l) bounds[l] = 0;
+        for (int l = 0; l < m->lanes; ++l) {
             std::vector<Tile> mine, ord;
             for (const Tile& t : nat)
                 if (lane[t.body] == l) mine.push_back(t);
@@ -584,8 +584,8 @@ int upload_tiles(gsim_model* m, void* stream) {
     };
     by_lane(m->etiles_nat, TILE_TET, 0, et, m->lane_e);
     by_lane(m->ptiles_nat, TILE_PART, m->n_ptile_rows, pt, m->lane_p);
-    m->n_etiles = m->lane_e[2];
-    m->n_ptiles = m->lane_p[2];
+    m->n_etiles = m->lane_e[m->lanes];
+    m->n_ptiles = m->lane_p[m->lanes];
     hipStream_t s = (hipStream_t)stream;
     if (!et.empty()) HIP_TRY(hipMemcpyAsync(m->ws + m->L.etiles, et.data(), et.size() * sizeof(Tile), hipMemcpyHostToDevice, s), "upload tiles");
     if (!pt.empty()) HIP_TRY(hipMemcpyAsync(m->ws + m->L.ptiles, pt.data(), pt.size() * sizeof(Tile), hipMemcpyHostToDevice, s), "upload tiles");
@@ -680,22 +680,24 @@ int timed(gsim_model* m, int k, void* stream, F launch) {
 }
 
 // Launch sequences.  Forward and adjoint passes of consecutive steps run on the
-// model's two lanes when it has them: lane 0 on the caller's stream, lane 1 on the
-// model's lane stream, forked from the caller's stream before the first such pass
-// and joined back before any launch that spans all bodies (and at the end).  The
-// lanes hold disjoint bodies, so results do not depend on the lanes.  With kernel
-// timing on, each pass is one launch over both lanes' tiles.
+// model's lanes when it has more than one: lane 0 on the caller's stream, lane l
+// on the model's lane stream l, forked from the caller's stream before the first
+// such pass and joined back before any launch that spans all bodies (and at the
+// end).  The lanes hold disjoint bodies, so results do not depend on the lanes.
+// With kernel timing on, each pass is one launch over all lanes' tiles.
 template <typename T>
 int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
     Ctx<T> c = ctx<T>(m);
     const ModelDev<T>* md = c.md;
-    const bool two = m->lanes == 2 && m->timing_mask == 0;
-    hipStream_t s0 = (hipStream_t)stream, s1 = m->lane_stream;
+    const int nl = m->timing_mask == 0 ? m->lanes : 1;
+    hipStream_t s0 = (hipStream_t)stream;
     bool forked = false;
     auto join = [&]() -> int {
         if (forked) {
-            HIP_TRY(hipEventRecord(m->ev_join, s1), "join lanes");
-            HIP_TRY(hipStreamWaitEvent(s0, m->ev_join, 0), "join lanes");
+            for (int l = 1; l < nl; ++l) {
+                HIP_TRY(hipEventRecord(m->ev_join[l], m->lane_stream[l]), "join lanes");
+                HIP_TRY(hipStreamWaitEvent(s0, m->ev_join[l], 0), "join lanes");
+            }
             forked = false;
         }
         return GSIM_OK;
@@ -704,7 +706,7 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
     auto pass = [&](int l, const StepDev<T>* sd, bool adjoint) -> int {
         const int e0 = l < 0 ? 0 : m->lane_e[l], e1 = l < 0 ? m->n_etiles : m->lane_e[l + 1];
         const int p0 = l < 0 ? 0 : m->lane_p[l], p1 = l < 0 ? m->n_ptiles : m->lane_p[l + 1];
-        void* st = l == 1 ? (void*)s1 : stream;
+        void* st = l > 0 ? (void*)m->lane_stream[l] : stream;
         if (!adjoint) {
             LAUNCH_TRY(timed(m, 0, st, [&] { return launch_elem_fwd<T>(md, sd, c.et + e0, e1 - e0, m->block, m->etile_words[0] * sizeof(T), st); }), "element pass");
             LAUNCH_TRY(timed(m, 1, st, [&] { return launch_part_fwd<T>(md, sd, c.pt + p0, p1 - p0, m->pblock, m->pitems, st); }), "particle pass");
@@ -718,17 +720,17 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
         const StepDev<T>* sd = c.table + l.row;
         if (l.op == OP_FWD || l.op == OP_ADJ) {
             const bool adjoint = l.op == OP_ADJ;
-            if (!two) {
+            if (nl == 1) {
                 if (int rc = pass(-1, sd, adjoint)) return rc;
                 continue;
             }
             if (!forked) {
                 HIP_TRY(hipEventRecord(m->ev_fork, s0), "fork lanes");
-                HIP_TRY(hipStreamWaitEvent(s1, m->ev_fork, 0), "fork lanes");
+                for (int k = 1; k < nl; ++k) HIP_TRY(hipStreamWaitEvent(m->lane_stream[k], m->ev_fork, 0), "fork lanes");
                 forked = true;
             }
-            if (int rc = pass(0, sd, adjoint)) return rc;
-            if (int rc = pass(1, sd, adjoint)) return rc;
+            for (int k = 0; k < nl; ++k)
+                if (int rc = pass(k, sd, adjoint)) return rc;
             continue;
         }
         if (int rc = join()) return rc;
@@ -1173,9 +1175,13 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     chk(up(L.tri_area, tri_area.data(), tri_area.size() * sizeof(T)));
     chk(up(L.hin_code, P->hin_code.data(), P->hin_code.size() * 4));
     chk(up(L.hin_phi0, hin_phi0.data(), hin_phi0.size() * sizeof(T)));
-    chk(up(L.tp_id, P->tp_id.data(), P->tp_id.size() * 4));
-    chk(up(L.tp_run, P->tp_run.data(), P->tp_run.size() * 4));
-    chk(up(L.tp_slot, P->tp_slot.data(), P->tp_slot.size() * 4));
+    std::vector<int32_t> tp4(4 * P->tp_id.size(), 0);
+    for (size_t i = 0; i < P->tp_id.size(); ++i) {
+        tp4[4 * i] = P->tp_id[i];
+        tp4[4 * i + 1] = P->tp_run[i];
+        tp4[4 * i + 2] = P->tp_slot[i];
+    }
+    chk(up(L.tp, tp4.data(), tp4.size() * 4));
     chk(up(L.gbase, P->gbase.data(), P->gbase.size() * 4));
     chk(up(L.pdeg, P->pdeg.data(), P->pdeg.size() * 4));
     chk(up(L.pinned, P->pinned.data(), P->pinned.size()));
@@ -1270,9 +1276,7 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     M.tri_area = (const T*)(ws + L.tri_area);
     M.hin_code = (const uint32_t*)(ws + L.hin_code);
     M.hin_phi0 = (const T*)(ws + L.hin_phi0);
-    M.tp_id = (const int32_t*)(ws + L.tp_id);
-    M.tp_run = (const int32_t*)(ws + L.tp_run);
-    M.tp_slot = (const int32_t*)(ws + L.tp_slot);
+    M.tp = (const int32_t*)(ws + L.tp);
     M.gbase = (const int32_t*)(ws + L.gbase);
     M.pdeg = (const int32_t*)(ws + L.pdeg);
     M.pinned = (const uint8_t*)(ws + L.pinned);
@@ -1299,19 +1303,23 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     m->md_host.assign(reinterpret_cast<const char*>(&M), reinterpret_cast<const char*>(&M) + sizeof M);
     chk(hipHostMalloc((void**)&m->stage, sizeof(StepDev<T>) * L.table_cap, hipHostMallocDefault));
     chk(hipEventCreateWithFlags(&m->stage_evt, hipEventDisableTiming));
-    if (P->nb >= 2) {  // the second launch lane's stream and fork / join events
-        chk(hipStreamCreateWithFlags(&m->lane_stream, hipStreamNonBlocking));
+    if (P->nb >= 2) {  // launch lanes' streams and fork / join events
         chk(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
-        chk(hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming));
-        m->lanes = 2;
+        for (int l = 1; l < MAX_LANES; ++l) {
+            chk(hipStreamCreateWithFlags(&m->lane_stream[l], hipStreamNonBlocking));
+            chk(hipEventCreateWithFlags(&m->ev_join[l], hipEventDisableTiming));
+        }
+        m->lanes = std::min(DEFAULT_LANES, P->nb);
     }
     if (e == hipSuccess) std::memset(m->stage, 0, sizeof(StepDev<T>) * L.table_cap);
     if (e != hipSuccess) {
         if (m->stage) (void)hipHostFree(m->stage);
         if (m->stage_evt) (void)hipEventDestroy(m->stage_evt);
         if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
-        if (m->ev_join) (void)hipEventDestroy(m->ev_join);
-        if (m->lane_stream) (void)hipStreamDestroy(m->lane_stream);
+        for (int l = 1; l < MAX_LANES; ++l) {
+            if (m->ev_join[l]) (void)hipEventDestroy(m->ev_join[l]);
+            if (m->lane_stream[l]) (void)hipStreamDestroy(m->lane_stream[l]);
+        }
         delete m;
         return hip_fail(e, "upload model");
     }
@@ -1452,12 +1460,14 @@ int gsim_model_destroy(gsim_model* m) {
         (void)hipEventDestroy(m->stage_evt);
     }
     if (m->stage) (void)hipHostFree(m->stage);
-    if (m->lane_stream) {
-        (void)hipStreamSynchronize(m->lane_stream);
-        (void)hipStreamDestroy(m->lane_stream);
+    for (int l = 1; l < MAX_LANES; ++l) {
+        if (m->lane_stream[l]) {
+            (void)hipStreamSynchronize(m->lane_stream[l]);
+            (void)hipStreamDestroy(m->lane_stream[l]);
+        }
+        if (m->ev_join[l]) (void)hipEventDestroy(m->ev_join[l]);
     }
     if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
-    if (m->ev_join) (void)hipEventDestroy(m->ev_join);
     for (auto& p : m->pending) {
         (void)hipEventSynchronize(p.b);
         m->evt_pool.push_back(p.a);
@@ -1485,8 +1495,8 @@ int gsim_model_set_launch(gsim_model* m, int pass, int block, int items) {
 
 int gsim_model_set_lanes(gsim_model* m, int lanes) {
     if (!m) return fail(GSIM_E_INVALID, "NULL model");
-    if (lanes != 1 && lanes != 2) return fail(GSIM_E_INVALID, "lanes must be 1 or 2");
-    if (lanes == 2 && m->nb < 2) return fail(GSIM_E_UNSUPPORTED, "two lanes need at least two bodies");
+    if (lanes < 1 || lanes > MAX_LANES) return fail(GSIM_E_INVALID, "lanes must be 1..%d", MAX_LANES);
+    if (lanes > m->nb) return fail(GSIM_E_UNSUPPORTED, "%d lanes need at least %d bodies", lanes, lanes);
     if (m->lanes == lanes) return GSIM_OK;
     HIP_TRY(hipDeviceSynchronize(), "synchronize before retiling");
     m->lanes = lanes;

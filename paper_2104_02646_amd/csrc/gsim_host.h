@@ -45,13 +45,15 @@ struct gsim_plan {
 namespace gsim {
 
 const int N_XCD = 8;  // workgroups are dispatched round-robin over the XCDs
+const int MAX_LANES = 4;      // concurrent launch lanes of the two-pass path
+const int DEFAULT_LANES = 2;  // lanes of a new model with that many bodies or more
 
 struct Layout {
     size_t model, bodies, etiles, ptiles;
     size_t tet_code, tet_dinv, tet_vol;
     size_t tri_code, tri_dinv, tri_area;
     size_t hin_code, hin_phi0;
-    size_t tp_id, tp_run, tp_slot;
+    size_t tp;
     size_t gbase, pdeg, pinned, slots, cpart, lpart;
     size_t fbuf, abuf;  // forward / adjoint internal ping-pong states
     // fused path: colour-ordered element records, colour bounds, body launch order
@@ -92,14 +94,14 @@ struct gsim_model {
     int block = 256, items = 1;    // element passes: threads per element tile (items: unused, tiles are planned)
     int pblock = 256, pitems = 1;  // particle passes
     int n_etiles = 0, n_ptiles = 0;   // launched grid sizes (including XCD padding)
-    // launch lanes: with 2, the bodies are split into two groups of about equal work
-    // whose passes run on two streams (the caller's and lane_stream) between a fork
-    // and a join; lane l's tiles are [lane_e[l], lane_e[l + 1]) of the element list
-    // and [lane_p[l], lane_p[l + 1]) of the particle list
+    // launch lanes: with L > 1, the bodies are split into L groups of about equal
+    // work whose passes run on L streams (the caller's and lane_stream[1 .. L-1])
+    // between a fork and a join; lane l's tiles are [lane_e[l], lane_e[l + 1]) of
+    // the element list and [lane_p[l], lane_p[l + 1]) of the particle list
     int lanes = 1;
-    int lane_e[3] = {0, 0, 0}, lane_p[3] = {0, 0, 0};
-    hipStream_t lane_stream = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int lane_e[gsim::MAX_LANES + 1] = {}, lane_p[gsim::MAX_LANES + 1] = {};
+    hipStream_t lane_stream[gsim::MAX_LANES] = {};
+    hipEvent_t ev_fork = nullptr, ev_join[gsim::MAX_LANES] = {};
     int n_ptile_rows = 0;             // real particle tiles (contact / loss partial rows)
     std::vector<char> bodies_host;    // BodyDev<T>[nb] as last uploaded
     char* stage = nullptr;            // pinned copy of the launch table as last uploaded

@@ -64,11 +64,9 @@ struct ModelDev {
     const T* tri_area;
     const uint32_t* hin_code;
     const T* hin_phi0;
-    // tile particles (Tile.id = first, Tile.pad = count): particle index, corner run
-    // (first sorted corner | count << 16), partial slot
-    const int32_t* tp_id;
-    const int32_t* tp_run;
-    const int32_t* tp_slot;
+    // tile particles (Tile.id = first, Tile.pad = count), one 16-byte record each:
+    // particle index, corner run (first sorted corner | count << 16), partial slot, 0
+    const int32_t* tp;
     const int32_t* gbase;  // [n_slices] first partial slot of each 64-particle slice
     const int32_t* pdeg;   // [np] partials per particle
     const uint8_t* pinned;

@@ -476,6 +476,13 @@ __device__ __forceinline__ void lds_st3(T* a, int n, int i, V3<T> v) {
     a[2 * n + i] = v.z;
 }
 
+// A tile particle's record (particle index, corner run, partial slot), one
+// 16-byte load.
+typedef int gi4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ gi4 ld_tp(const int32_t* tp, int64_t i) {
+    return ((const __attribute__((address_space(1))) gi4*)(tp + 4 * i))[0];
+}
+
 // Element pass: one workgroup per planned element tile.  The positions of the
 // tile's particles are staged in LDS once (instead of one gather per corner), as
 // 16-byte 4-vectors like the corner contributions (one LDS access per corner);
@@ -491,11 +498,15 @@ __global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict_
     const ModelDev<T>& M = md[tl.model];
     const StepDev<T>& S = sd[tl.model];
     const int64_t np = M.np;
-    const int m = tl.pad;
+    const int m = tl.pad, tid = threadIdx.x, nth = blockDim.x;
     L4<T>* xs = reinterpret_cast<L4<T>*>(smem);  // [m] tile-particle positions
     L4<T>* cs = xs + m;                          // [corners] corner forces, particle-sorted
-    for (int j = threadIdx.x; j < m; j += blockDim.x)
-        xs[j] = l4(ld3(S.x, np, (int64_t)gld(M.tp_id, (int64_t)tl.id + j)), T(0));
+    gi4 mine = {0, 0, 0, 0};                     // this thread's first tile particle
+    for (int j = tid; j < m; j += nth) {
+        const gi4 r = ld_tp(M.tp, (int64_t)tl.id + j);
+        if (j == tid) mine = r;
+        xs[j] = l4(ld3(S.x, np, (int64_t)r.x), T(0));
+    }
     __syncthreads();
     for (int l = threadIdx.x; l < tl.count; l += blockDim.x) {
         const int64_t e = tl.begin + l;
@@ -542,12 +553,12 @@ __global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict_
         }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
-        const int32_t run = gld(M.tp_run, (int64_t)tl.id + j);
-        const int r0 = run & 0xffff, rn = run >> 16;
+    for (int j = tid; j < m; j += nth) {
+        const gi4 r = j == tid ? mine : ld_tp(M.tp, (int64_t)tl.id + j);
+        const int r0 = r.y & 0xffff, rn = r.y >> 16;
         V3<T> f = zero3<T>();
         for (int k = 0; k < rn; ++k) f += v3(cs[r0 + k]);
-        st_slot(M.slots, gld(M.tp_slot, (int64_t)tl.id + j), f.x, f.y, f.z, T(0));
+        st_slot(M.slots, r.z, f.x, f.y, f.z, T(0));
     }
 }
 
@@ -617,12 +628,15 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
     const StepDev<T>& S = sd[tl.model];
     const int64_t np = M.np;
     const T dt = M.bodies[tl.body].dt;
-    const int m = tl.pad;
+    const int m = tl.pad, tid = threadIdx.x, nth = blockDim.x;
     L4<T>* xs = reinterpret_cast<L4<T>*>(smem);  // [m] tile-particle positions
     L4<T>* fbs = xs + m;                         // [m] tile-particle adjoint forces
     L4<T>* cs = fbs + m;                         // [corners] corner (xbar, f.fbar), particle-sorted
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
-        const int64_t p = gld(M.tp_id, (int64_t)tl.id + j);
+    gi4 mine = {0, 0, 0, 0};                     // this thread's first tile particle
+    for (int j = tid; j < m; j += nth) {
+        const gi4 r = ld_tp(M.tp, (int64_t)tl.id + j);
+        if (j == tid) mine = r;
+        const int64_t p = r.x;
         xs[j] = l4(ld3(S.x, np, p), T(0));
         fbs[j] = l4(corner_fbar(M, S, p, dt), T(0));
     }
@@ -686,9 +700,9 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
         }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
-        const int32_t run = gld(M.tp_run, (int64_t)tl.id + j);
-        const int r0 = run & 0xffff, rn = run >> 16;
+    for (int j = tid; j < m; j += nth) {
+        const gi4 r = j == tid ? mine : ld_tp(M.tp, (int64_t)tl.id + j);
+        const int r0 = r.y & 0xffff, rn = r.y >> 16;
         V3<T> xb = zero3<T>();
         T d = T(0);
         for (int k = 0; k < rn; ++k) {
@@ -696,7 +710,7 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
             xb += v3(c);
             d += c.w;
         }
-        st_slot(M.slots, gld(M.tp_slot, (int64_t)tl.id + j), xb.x, xb.y, xb.z, d);
+        st_slot(M.slots, r.z, xb.x, xb.y, xb.z, d);
     }
 }
 
