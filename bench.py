@@ -76,10 +76,10 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
 # WRITE_SIZE by 1.0, the factors a 1 GiB copy gives).  They hold for the kernel
 # source with this SHA-1 only; for any other source the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "source_sha1": "314168c0de216b4ff02125ac518c9f4c2bd1cae2",
+    "source_sha1": "17a0331289ff1ca0c224894b111d580a01130769",
     "workload": (256, 100, 10),
-    "per_launch": {"element_fwd": 108.54e6, "particle_fwd": 28.47e6, "element_adj": 139.51e6,
-                   "particle_adj": 35.19e6},
+    "per_launch": {"element_fwd": 114.05e6, "particle_fwd": 30.54e6, "element_adj": 144.94e6,
+                   "particle_adj": 37.26e6},
 }
 
 
@@ -163,6 +163,7 @@ def main():
     ap.add_argument("--exec", choices=("fused", "graph", "plain"), default="graph")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--items", type=int, default=1)
+    ap.add_argument("--lanes", type=int, default=2, help="concurrent launch lanes of the two-pass path (1..4)")
     ap.add_argument("--cpu-tets", type=int, default=15000, help="oracle sample size (tets)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -205,6 +206,7 @@ def main():
         model = gsim.Model(bodies, torch.float32, max_steps=T, ckpt_every=K, device=dev)
         exec_mode = {"fused": gsim.EXEC_FUSED, "graph": gsim.EXEC_GRAPH, "plain": gsim.EXEC_PLAIN}[args.exec]
         model.set_exec(exec_mode, args.block, args.items)
+        model.set_lanes(args.lanes)
         p = model.params_from_bodies()
         x0 = gsim.soa(np.concatenate([b.x0 for b in bodies]))
         v0 = gsim.soa(np.concatenate([b.v0 for b in bodies]))
@@ -286,7 +288,7 @@ def main():
         "config": {"workload": "batch of %d tet bodies (log-uniform 500-20000 tets), %d steps fwd + "
                                "checkpointed adjoint (every %d), ground contact + friction" % (len(bodies), T, K),
                    "bodies": len(bodies), "tets": ne, "particles": np_, "sim_steps": T, "ckpt_every": K,
-                   "exec": args.exec, "block": args.block, "items": args.items},
+                   "exec": args.exec, "block": args.block, "items": args.items, "lanes": args.lanes},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom, len(bodies), T, K),
                      "avg_launch_us": d["avg_us"], "bytes_per_launch": d["bytes_per_launch"]},
