@@ -148,23 +148,33 @@ def test_force_adjoint_dot_test(oracle_lib):
     rng = np.random.default_rng(3)
     p = b.params()
     p["act"] = rng.normal(0, 0.01, b.ne)
+    p["hact"] = rng.normal(0, 0.05, b.nh)
     x = b.X + rng.normal(0, 0.002, b.X.shape)
     x[:20, 1] -= 0.01  # some particles below the ground
     v = rng.normal(0, 0.5, b.X.shape)
     dx = rng.normal(size=x.shape); dv = rng.normal(size=x.shape)
     dp = {"mu": rng.normal(size=b.ne), "lam": rng.normal(size=b.ne), "act": rng.normal(size=b.ne),
-          "ktri": rng.normal(size=b.nt), "kb": rng.normal(), "ke": rng.normal(), "kd": rng.normal(),
-          "kf": rng.normal(), "muf": rng.normal()}
+          "ktri": rng.normal(size=b.nt), "hact": rng.normal(size=b.nh), "kb": rng.normal(), "ke": rng.normal(),
+          "kd": rng.normal(), "kf": rng.normal(), "muf": rng.normal()}
     dp_full = dict(dp)
     for k in ("mass",):
         dp_full[k] = np.zeros(b.np)
     jd = orc.force_jvp(p, dp_full, x, v, dx, dv)
     fbar = rng.normal(size=x.shape)
-    xb, vb, g = orc.force_vjp(p, x, v, fbar, want=("mu", "lam", "act", "ktri"))
+    xb, vb, g = orc.force_vjp(p, x, v, fbar, want=("mu", "lam", "act", "ktri", "hact"))
     lhs = (fbar * jd).sum()
     rhs = (xb * dx).sum() + (vb * dv).sum() + g["mu"] @ dp["mu"] + g["lam"] @ dp["lam"] + g["act"] @ dp["act"] \
-        + g["ktri"] @ dp["ktri"] + g["kb"] * dp["kb"] + g["contact"] @ np.array([dp[k] for k in ("ke", "kd", "kf", "muf")])
+        + g["ktri"] @ dp["ktri"] + g["hact"] @ dp["hact"] + g["kb"] * dp["kb"] \
+        + g["contact"] @ np.array([dp[k] for k in ("ke", "kd", "kf", "muf")])
     assert abs(lhs - rhs) < 1e-10 * (abs(lhs) + 1e-30)
+    # FD of the force along the actuation directions alone
+    for key in ("act", "hact"):
+        h = 1e-6
+        qp = dict(p); qp[key] = p[key] + h * dp[key]
+        qm = dict(p); qm[key] = p[key] - h * dp[key]
+        fd = (orc.forces(qp, x, v) - orc.forces(qm, x, v)) / (2 * h)
+        jd_a = orc.force_jvp(p, {"mass": np.zeros(b.np), key: dp[key]}, x, v, np.zeros_like(x), np.zeros_like(v))
+        assert np.linalg.norm(fd - jd_a) < 1e-6 * np.linalg.norm(jd_a), key
     # FD of the force along the same direction (positions and velocities only)
     h = 1e-7
     fp = orc.forces(p, x + h * dx, v + h * dv)
@@ -254,3 +264,79 @@ def test_special_case_gradients(oracle_lib):
                                      [[0.01, 0.0, 0.0]], 20, [[0.1, 0.0, 0.0]], want=("mass",))
     assert g["contact"][3] == 0.0
     assert g["contact"][2] != 0.0
+
+
+def _per_step_rollout(orc, p, acts, x0, v0):
+    """Rollout whose step t reads the actuation rows acts[k][t] (k = "act", "hact")."""
+    x, v = x0, v0
+    for t in range(len(next(iter(acts.values())))):
+        q = dict(p)
+        for k, a in acts.items():
+            q[k] = a[t]
+        x, v = orc.step(q, x, v)
+    return x, v
+
+
+def test_actuation_gradients_central_fd(oracle_lib):
+    """Tet and hinge actuation gradients (App. A: the muscle / control inputs are
+    parameters like any other): one actuation held for the whole rollout, and one per
+    step, each against central differences of the rollout loss.  The per-step
+    gradient of step t is the step adjoint's actuation gradient at that step; their
+    sum over steps is the constant-actuation gradient."""
+    o = oracle_lib
+    b = _mixed_body()
+    orc = make(o, b)
+    rng = np.random.default_rng(5)
+    T = 24
+    p = b.params()
+    p["act"] = rng.normal(0, 0.02, b.ne)
+    p["hact"] = rng.normal(0, 0.1, b.nh)
+    x0 = b.X.copy()
+    v0 = np.zeros_like(x0)
+    v0[:b.np - 25] = [1.0, -0.5, 0.0]
+    target = b.X + rng.normal(0, 0.02, b.X.shape)
+    L, g, xs, vs = orc.loss_and_grad(p, x0, v0, T, target, want=("act", "hact"))
+    for key in ("act", "hact"):
+        d = rng.normal(size=p[key].shape)
+        h = 1e-6
+        qp = dict(p); qp[key] = p[key] + h * d
+        qm = dict(p); qm[key] = p[key] - h * d
+        num = (_rollout_loss(orc, qp, x0, v0, T, target) - _rollout_loss(orc, qm, x0, v0, T, target)) / (2 * h)
+        ana = float(g[key] @ d)
+        assert abs(num - ana) <= 2e-5 * abs(ana), (key, num, ana)
+    # per step: step t's gradient from the step adjoint at state t
+    acts = {"act": p["act"] + rng.normal(0, 0.02, (T, b.ne)), "hact": p["hact"] + rng.normal(0, 0.1, (T, b.nh))}
+    xs = [x0]; vs = [v0]
+    for t in range(T):
+        q = dict(p); q["act"] = acts["act"][t]; q["hact"] = acts["hact"][t]
+        xn, vn = orc.step(q, xs[-1], vs[-1])
+        xs.append(xn); vs.append(vn)
+    L, xb = orc.loss(xs[-1], target, with_grad=True)
+    vb = np.zeros_like(xb)
+    per = {"act": np.zeros((T, b.ne)), "hact": np.zeros((T, b.nh))}
+    for t in range(T - 1, -1, -1):
+        q = dict(p); q["act"] = acts["act"][t]; q["hact"] = acts["hact"][t]
+        xb, vb, gt = orc.step_vjp(q, xs[t], vs[t], xb, vb, want=("act", "hact"))
+        per["act"][t], per["hact"][t] = gt["act"], gt["hact"]
+    for key, t in (("act", 0), ("act", T // 2), ("hact", 3), ("hact", T - 1)):
+        d = rng.normal(size=acts[key][t].shape)
+        h = 1e-6
+        ap = {k: a.copy() for k, a in acts.items()}; ap[key][t] += h * d
+        am = {k: a.copy() for k, a in acts.items()}; am[key][t] -= h * d
+        num = (orc.loss(_per_step_rollout(orc, p, ap, x0, v0)[0], target)
+               - orc.loss(_per_step_rollout(orc, p, am, x0, v0)[0], target)) / (2 * h)
+        ana = float(per[key][t] @ d)
+        assert abs(num - ana) <= 2e-5 * abs(ana) + 1e-12 * abs(L), (key, t, num, ana)
+    # with every row equal, the per-step gradients sum to the constant-actuation one
+    xs = [x0]; vs = [v0]
+    for t in range(T):
+        xn, vn = orc.step(p, xs[-1], vs[-1])
+        xs.append(xn); vs.append(vn)
+    _, xb = orc.loss(xs[-1], target, with_grad=True)
+    vb = np.zeros_like(xb)
+    tot = {"act": 0.0, "hact": 0.0}
+    for t in range(T - 1, -1, -1):
+        xb, vb, gt = orc.step_vjp(p, xs[t], vs[t], xb, vb, want=("act", "hact"))
+        tot["act"] = tot["act"] + gt["act"]; tot["hact"] = tot["hact"] + gt["hact"]
+    for key in ("act", "hact"):
+        assert np.allclose(tot[key], g[key], rtol=1e-10, atol=1e-14 * np.abs(g[key]).max()), key
