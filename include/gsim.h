@@ -210,6 +210,12 @@ typedef struct {
     void* v; /* [3][n_particles] */
 } gsim_state;
 
+/* Actuation (App. A.1): a tet's actuation a shifts alpha in its energy
+ * (alpha = 1 + 3 mu / (4 lambda) + a); a hinge's actuation shifts the bending
+ * force's angle, f = -k_b s sin((phi - phi0)/2 + a_h) u.  Both may vary from
+ * step to step: in gsim_step (over its n_steps), gsim_rollout and
+ * gsim_rollout_backward, step t of the call reads act + t * act_stride (and
+ * hact + t * hact_stride); a stride of 0 uses the same array every step. */
 typedef struct {
     const void* mu;      /* [n_tets] Lame mu            (required if n_tets)  */
     const void* lam;     /* [n_tets] Lame lambda        (required if n_tets)  */
@@ -217,14 +223,25 @@ typedef struct {
     const void* k_tri;   /* [n_tris] membrane stiffness (required if n_tris)  */
     const void* mass;    /* [n_particles] mass > 0 (pinned particles ignore it) */
     const void* contact; /* [n_bodies][4] = k_e, k_d, k_f, mu_f (required if any contact) */
+    const void* hact;    /* [n_hinges] hinge actuation, NULL = 0              */
+    int64_t act_stride;  /* elements between consecutive steps' act arrays (>= 0) */
+    int64_t hact_stride; /* same for hact */
 } gsim_params;
 
+/* Gradients accumulate (+=).  The actuation gradients of step t go to
+ * act + t * act_stride (hact + t * hact_stride): with a stride of 0 every
+ * step's contribution is summed into one array; with n_tets (n_hinges) each
+ * step has its own. */
 typedef struct {         /* any pointer may be NULL = gradient not requested */
     void* mu;            /* [n_tets]      */
     void* lam;           /* [n_tets]      */
     void* k_tri;         /* [n_tris]      */
     void* mass;          /* [n_particles] */
     void* contact;       /* [n_bodies][4] */
+    void* act;           /* [n_tets] (per step: see act_stride) */
+    void* hact;          /* [n_hinges] (per step: see hact_stride) */
+    int64_t act_stride;
+    int64_t hact_stride;
 } gsim_grads;
 
 /* ------------------------------------------------------------------------ */

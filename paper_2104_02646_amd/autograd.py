@@ -14,23 +14,26 @@ import torch
 
 from . import gsim
 
-_PARAM_KEYS = ("mu", "lam", "ktri", "mass", "contact")
+_PARAM_KEYS = ("mu", "lam", "ktri", "mass", "contact", "act", "hact")
 
 
 class SimRollout(torch.autograd.Function):
-    """(x0, v0, mu, lam, ktri, mass, contact) -> (xT, vT) after n_steps steps.
+    """(x0, v0, mu, lam, ktri, mass, contact, act, hact) -> (xT, vT) after n_steps steps.
 
-    States are SoA [3, n_particles]; contact is [n_bodies, 4] = (k_e, k_d, k_f, mu_f).
+    States are SoA [3, n_particles]; contact is [n_bodies, 4] = (k_e, k_d, k_f, mu_f);
+    act / hact (tet / hinge actuation) are [n] for one value over the whole rollout
+    or [n_steps, n] for a value per step, and their gradients have the same shape.
     Pass None for parameters the model does not have (mu/lam without tets, ktri
-    without triangles)."""
+    without triangles) or does not actuate."""
 
     @staticmethod
-    def forward(ctx, model, n_steps, x0, v0, mu, lam, ktri, mass, contact):
-        params = {k: v.detach() for k, v in zip(_PARAM_KEYS, (mu, lam, ktri, mass, contact)) if v is not None}
+    def forward(ctx, model, n_steps, x0, v0, mu, lam, ktri, mass, contact, act, hact):
+        vals = (mu, lam, ktri, mass, contact, act, hact)
+        params = {k: v.detach().contiguous() for k, v in zip(_PARAM_KEYS, vals) if v is not None}
         ckpt = model.new_checkpoints()
         xT, vT = model.rollout(params, x0.detach().contiguous(), v0.detach().contiguous(), int(n_steps), ckpt=ckpt)
         ctx.model, ctx.n_steps, ctx.params, ctx.ckpt = model, int(n_steps), params, ckpt
-        ctx.present = tuple(v is not None for v in (mu, lam, ktri, mass, contact))
+        ctx.present = tuple(v is not None for v in vals)
         return xT, vT
 
     @staticmethod
@@ -38,7 +41,7 @@ class SimRollout(torch.autograd.Function):
         m = ctx.model
         gx = torch.zeros(3, m.np, dtype=m.dtype, device=m.device) if gx is None else gx.contiguous()
         gv = torch.zeros(3, m.np, dtype=m.dtype, device=m.device) if gv is None else gv.contiguous()
-        grads = m.zero_grads(tuple(k for k, p in zip(_PARAM_KEYS, ctx.present) if p))
+        grads = {k: torch.zeros_like(ctx.params[k]) for k, p in zip(_PARAM_KEYS, ctx.present) if p}
         xb0, vb0 = m.rollout_backward(ctx.params, ctx.n_steps, gx, gv, grads, ckpt=ctx.ckpt)
         out = [grads.get(k) if p else None for k, p in zip(_PARAM_KEYS, ctx.present)]
         return (None, None, xb0, vb0, *out)

@@ -503,12 +503,15 @@ Layout make_layout(const gsim_plan* P, int max_steps) {
     L.f_tri_orig = take(nt * 4);
     L.f_hin_idx = take(4 * nh * 4);
     L.f_hin_phi0 = take(nh * sizeof(T));
+    L.f_hin_orig = take(nh * 4);
     L.coff = take(P->coff.size() * 4 + 4);
     L.border = take(P->nb * 4 + 4);
     L.f_par = take(3 * ne * sizeof(T));
     L.f_ktri = take(nt * sizeof(T));
-    L.f_g = take(2 * ne * sizeof(T));
+    L.f_g = take(3 * ne * sizeof(T));
     L.f_gk = take(nt * sizeof(T));
+    L.f_hpar = take(nh * sizeof(T));
+    L.f_gh = take(nh * sizeof(T));
     L.table_cap = 4 * (int64_t)max_steps + 8;
     L.table = take(sizeof(StepDev<T>) * L.table_cap);
     L.total = align_up(o, 256);
@@ -819,17 +822,35 @@ void fill_params(StepDev<T>& r, const gsim_params* p, const gsim_grads* g) {
     r.ktri = (const T*)p->k_tri;
     r.mass = (const T*)p->mass;
     r.contact = (const T*)p->contact;
+    r.hact = (const T*)p->hact;
     if (g) {
         r.g_mu = (T*)g->mu;
         r.g_lam = (T*)g->lam;
         r.g_ktri = (T*)g->k_tri;
         r.g_mass = (T*)g->mass;
         r.g_contact = (T*)g->contact;
+        r.g_act = (T*)g->act;
+        r.g_hact = (T*)g->hact;
     }
 }
 
-int check_params(const gsim_model* m, const gsim_params* p) {
+// Step t of a call reads (and accumulates into) the actuation arrays of step t.
+template <typename T>
+void at_step(StepDev<T>& r, const gsim_params* p, const gsim_grads* g, int64_t t) {
+    if (p->act) r.act = (const T*)p->act + t * p->act_stride;
+    if (p->hact) r.hact = (const T*)p->hact + t * p->hact_stride;
+    if (g && g->act) r.g_act = (T*)g->act + t * g->act_stride;
+    if (g && g->hact) r.g_hact = (T*)g->hact + t * g->hact_stride;
+}
+
+int check_params(const gsim_model* m, const gsim_params* p, const gsim_grads* g = nullptr) {
     if (!p) return fail(GSIM_E_INVALID, "NULL params");
+    if (p->act_stride < 0 || p->hact_stride < 0 || (g && (g->act_stride < 0 || g->hact_stride < 0)))
+        return fail(GSIM_E_INVALID, "actuation strides must be >= 0");
+    const bool per_step = (p->act && p->act_stride) || (p->hact && p->hact_stride) ||
+                          (g && ((g->act && g->act_stride) || (g->hact && g->hact_stride)));
+    if (m->exec == GSIM_EXEC_FUSED && per_step)
+        return fail(GSIM_E_UNSUPPORTED, "the fused path takes one actuation array for all steps (strides must be 0)");
     if (m->ne && (!p->mu || !p->lam)) return fail(GSIM_E_INVALID, "mu and lam are required for tets");
     if (m->nt && !p->k_tri) return fail(GSIM_E_INVALID, "k_tri is required for triangles");
     if (!p->mass) return fail(GSIM_E_INVALID, "mass is required");
@@ -942,6 +963,7 @@ int do_step(gsim_model* m, const gsim_params* p, gsim_state in, gsim_state out, 
         StepDev<T>& r = rows[t];
         std::memset(&r, 0, sizeof r);
         fill_params<T>(r, p, nullptr);
+        at_step<T>(r, p, nullptr, t);
         if (t == 0) {
             r.x = (const T*)in.x;
             r.v = (const T*)in.v;
@@ -967,7 +989,7 @@ int do_step_backward(gsim_model* m, const gsim_params* p, gsim_state s, gsim_sta
                      const gsim_grads* g, void* stream) {
     if (!s.x || !s.v || !ap.x || !ap.v || !am.x || !am.v) return fail(GSIM_E_INVALID, "NULL state");
     if (ap.x == am.x || ap.v == am.v) return fail(GSIM_E_INVALID, "adj_plus and adj_minus must not alias");
-    int rc = check_params(m, p);
+    int rc = check_params(m, p, g);
     if (rc) return rc;
     std::vector<StepDev<T>> rows(1);
     std::memset(rows.data(), 0, sizeof(StepDev<T>));
@@ -1011,6 +1033,7 @@ int do_rollout(gsim_model* m, const gsim_params* p, gsim_state s0, int n, void* 
         StepDev<T>& r = rows[t];
         std::memset(&r, 0, sizeof r);
         fill_params<T>(r, p, nullptr);
+        at_step<T>(r, p, nullptr, t);
         if (t == 0) {
             r.x = (const T*)s0.x;
             r.v = (const T*)s0.v;
@@ -1041,7 +1064,7 @@ int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, i
     if (n < 1 || n > m->max_steps) return fail(GSIM_E_INVALID, "n_steps must be in [1, %d]", m->max_steps);
     if (!ckpt || !seg) return fail(GSIM_E_INVALID, "checkpoint and segment buffers are required");
     if (!af.x || !af.v || !ai.x || !ai.v) return fail(GSIM_E_INVALID, "NULL adjoint state");
-    int rc = check_params(m, p);
+    int rc = check_params(m, p, g);
     if (rc) return rc;
     if (m->exec == GSIM_EXEC_FUSED)
         return do_fused_rollout_backward<T>(m, p, (const T*)ckpt, n, (T*)seg, af, ai, g, stream);
@@ -1068,7 +1091,8 @@ int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, i
         // recompute states t0+1 .. t1-1 into seg[0 .. L-2]
         for (int j = 0; j + 1 < L; ++j) {
             StepDev<T> r = base;
-            r.g_mu = r.g_lam = r.g_ktri = r.g_mass = r.g_contact = nullptr;
+            r.g_mu = r.g_lam = r.g_ktri = r.g_mass = r.g_contact = r.g_act = r.g_hact = nullptr;
+            at_step<T>(r, p, nullptr, t0 + j);
             r.x = j == 0 ? ck + s * S : segT + (j - 1) * S;
             r.v = r.x + 3 * np;
             r.xo = segT + j * S;
@@ -1078,6 +1102,7 @@ int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, i
         }
         for (int t = t1 - 1; t >= t0; --t, ++q) {
             StepDev<T> r = base;
+            at_step<T>(r, p, g, t);
             r.x = t == t0 ? ck + s * S : segT + (t - t0 - 1) * S;
             r.v = r.x + 3 * np;
             if (q == 0) {
@@ -1218,6 +1243,7 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     chk(up(L.f_tri_orig, P->ftri.data(), P->ftri.size() * 4));
     chk(up(L.f_hin_idx, f_hin_idx.data(), f_hin_idx.size() * 4));
     chk(up(L.f_hin_phi0, f_hin_phi0.data(), f_hin_phi0.size() * sizeof(T)));
+    chk(up(L.f_hin_orig, P->fhin.data(), P->fhin.size() * 4));
     chk(up(L.coff, P->coff.data(), P->coff.size() * 4));
     // fused launch order: largest bodies first (they bound the makespan)
     std::vector<int32_t> border(P->nb);
@@ -1294,11 +1320,14 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     M.f_tri_orig = (const int32_t*)(ws + L.f_tri_orig);
     M.f_hin_idx = (const int32_t*)(ws + L.f_hin_idx);
     M.f_hin_phi0 = (const T*)(ws + L.f_hin_phi0);
+    M.f_hin_orig = (const int32_t*)(ws + L.f_hin_orig);
     M.coff = (const int32_t*)(ws + L.coff);
     M.f_par = (T*)(ws + L.f_par);
     M.f_ktri = (T*)(ws + L.f_ktri);
     M.f_g = (T*)(ws + L.f_g);
     M.f_gk = (T*)(ws + L.f_gk);
+    M.f_hpar = (T*)(ws + L.f_hpar);
+    M.f_gh = (T*)(ws + L.f_gh);
     chk(up(L.model, &M, sizeof M));
     m->md_host.assign(reinterpret_cast<const char*>(&M), reinterpret_cast<const char*>(&M) + sizeof M);
     chk(hipHostMalloc((void**)&m->stage, sizeof(StepDev<T>) * L.table_cap, hipHostMallocDefault));

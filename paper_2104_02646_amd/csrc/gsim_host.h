@@ -58,7 +58,7 @@ struct Layout {
     size_t fbuf, abuf;  // forward / adjoint internal ping-pong states
     // fused path: colour-ordered element records, colour bounds, body launch order
     size_t f_tet_idx, f_tet_dinv, f_tet_vol, f_tet_orig, f_tri_idx, f_tri_dinv, f_tri_area, f_tri_orig;
-    size_t f_hin_idx, f_hin_phi0, coff, border, f_par, f_ktri, f_g, f_gk;
+    size_t f_hin_idx, f_hin_phi0, f_hin_orig, coff, border, f_par, f_ktri, f_g, f_gk, f_hpar, f_gh;
     size_t table;
     int64_t table_cap;
     size_t total;

@@ -87,11 +87,14 @@ struct ModelDev {
     const int32_t* f_tri_orig;
     const int32_t* f_hin_idx;
     const T* f_hin_phi0;
+    const int32_t* f_hin_orig;
     const int32_t* coff;
     T* f_par;   // [3][ne] mu, lambda, actuation in colour order (gathered per call)
     T* f_ktri;  // [nt] membrane stiffness in colour order
-    T* f_g;     // [2][ne] mu-bar, lambda-bar in colour order (scattered back per call)
+    T* f_g;     // [3][ne] mu-bar, lambda-bar, actuation-bar in colour order (scattered back per call)
     T* f_gk;    // [nt] k-bar in colour order
+    T* f_hpar;  // [nh] hinge actuation in colour order
+    T* f_gh;    // [nh] hinge actuation-bar in colour order
 };
 
 template <typename T>
@@ -112,11 +115,14 @@ struct StepDev {
     const T* ktri;
     const T* mass;
     const T* contact;  // [n_bodies][4]
+    const T* hact;     // [nh] hinge actuation (this step's), may be null
     T* g_mu;
     T* g_lam;
     T* g_ktri;
     T* g_mass;
     T* g_contact;      // [n_bodies][4]
+    T* g_act;          // [ne] tet actuation gradient (this step's slot), may be null
+    T* g_hact;         // [nh] hinge actuation gradient, may be null
     const T* target;   // loss target, SoA [3][np]
     T* loss;           // [n_bodies]
     // fused path

@@ -131,11 +131,11 @@ __device__ __forceinline__ void tet_force(const V3<T> x[4], const T D[9], T V, T
 }
 
 // Reverse mode of tet_force for corner adjoints fb: position adjoints xb (the
-// transpose of df/dx applied to fb), d/dmu and d/dlambda of <fb, f>; also
+// transpose of df/dx applied to fb), d/dmu, d/dlambda and d/da of <fb, f>; also
 // returns the forces themselves (for the mass gradient).
 template <typename T>
 __device__ __forceinline__ void tet_adjoint(const V3<T> x[4], const T D[9], T V, T mu, T lam, T act, const V3<T> fb[4],
-                                            V3<T> f[4], V3<T> xb[4], T& gmu, T& glam) {
+                                            V3<T> f[4], V3<T> xb[4], T& gmu, T& glam, T& gact) {
     const V3<T> d0 = x[1] - x[0], d1 = x[2] - x[0], d2 = x[3] - x[0];
     V3<T> F[3];
 #pragma unroll
@@ -165,6 +165,7 @@ __device__ __forceinline__ void tet_adjoint(const V3<T> x[4], const T D[9], T V,
     const T Bb = dot(Pb[0], C[0]) + dot(Pb[1], C[1]) + dot(Pb[2], C[2]);
     gmu = (T(1) - ip) * Ab - T(0.75) * Bb;  // dA/dmu = 1 - 1/(Ic+1), dB/dmu = -3/4
     glam = (J - T(1) - act) * Bb;          // dB/dlambda = J - alpha + 3mu/(4 lambda)
+    gact = -lam * Bb;                      // dB/da = -lambda
     const T Icb = Ab * mu * ip * ip;
     const T Jb = Bb * lam;
     V3<T> Fb[3], Cb[3];
@@ -288,24 +289,26 @@ __device__ __forceinline__ void hinge_geo(const V3<T> x[4], HingeGeo<T>& h) {
     h.phi = gatan2(-dot(cross(h.N1, h.N2), h.Eh), dot(h.N1, h.N2));
 }
 
+// Bending force with actuation a: the half-angle term is sin((phi - phi0)/2 + a).
 template <typename T>
-__device__ __forceinline__ void hinge_force(const V3<T> x[4], T phi0, T kb, V3<T> f[4]) {
+__device__ __forceinline__ void hinge_force(const V3<T> x[4], T phi0, T kb, T act, V3<T> f[4]) {
     HingeGeo<T> h;
     hinge_geo(x, h);
     const T sc = h.el * h.el / (h.n1 + h.n2);
-    const T mag = -kb * sc * gsin(T(0.5) * (h.phi - phi0));
+    const T mag = -kb * sc * gsin(T(0.5) * (h.phi - phi0) + act);
 #pragma unroll
     for (int i = 0; i < 4; ++i) f[i] = h.u[i] * mag;
 }
 
+// Reverse mode of hinge_force: position adjoints xb and d/da of <fb, f> (gact).
 template <typename T>
-__device__ __forceinline__ void hinge_adjoint(const V3<T> x[4], T phi0, T kb, const V3<T> fb[4], V3<T> f[4],
-                                              V3<T> xb[4]) {
+__device__ __forceinline__ void hinge_adjoint(const V3<T> x[4], T phi0, T kb, T act, const V3<T> fb[4], V3<T> f[4],
+                                              V3<T> xb[4], T& gact) {
     HingeGeo<T> h;
     hinge_geo(x, h);
     const T q = h.n1 + h.n2;
     const T sc = h.el * h.el / q;
-    const T psi = T(0.5) * (h.phi - phi0);
+    const T psi = T(0.5) * (h.phi - phi0) + act;
     const T sn = gsin(psi), cs = gcos(psi);
     const T mag = -kb * sc * sn;
     T magb = T(0);
@@ -317,7 +320,9 @@ __device__ __forceinline__ void hinge_adjoint(const V3<T> x[4], T phi0, T kb, co
         magb += dot(fb[i], h.u[i]);
     }
     const T scb = -kb * sn * magb;
-    const T phib = -kb * sc * cs * T(0.5) * magb;
+    const T psib = -kb * sc * cs * magb;
+    const T phib = T(0.5) * psib;
+    gact = psib;
     // phi: its gradient is u (exact identity of the dihedral angle)
 #pragma unroll
     for (int i = 0; i < 4; ++i) xb[i] = h.u[i] * phib;
@@ -547,7 +552,7 @@ __global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict_
                 cd[c] = gld(M.hin_code, c * M.nh + e);
                 x[c] = v3(xs[cd[c] & 0xffffu]);
             }
-            hinge_force(x, gld(M.hin_phi0, e), M.bodies[tl.body].kb, f);
+            hinge_force(x, gld(M.hin_phi0, e), M.bodies[tl.body].kb, S.hact ? gld(S.hact, e) : T(0), f);
 #pragma unroll
             for (int c = 0; c < 4; ++c) cs[cd[c] >> 16] = l4(f[c], T(0));
         }
@@ -656,14 +661,15 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
 #pragma unroll
             for (int k = 0; k < 9; ++k) D[k] = gld(M.tet_dinv, k * M.ne + e);
             const T act = S.act ? gld(S.act, e) : T(0);
-            T gmu, glam;
-            tet_adjoint(x, D, gld(M.tet_vol, e), gld(S.mu, e), gld(S.lam, e), act, fb, f, xb, gmu, glam);
+            T gmu, glam, gact;
+            tet_adjoint(x, D, gld(M.tet_vol, e), gld(S.mu, e), gld(S.lam, e), act, fb, f, xb, gmu, glam, gact);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 cs[cd[c] >> 16] = l4(xb[c], dot(f[c], fb[c]));
             }
             if (S.g_mu) gst(S.g_mu, e, gld(S.g_mu, e) + gmu);
             if (S.g_lam) gst(S.g_lam, e, gld(S.g_lam, e) + glam);
+            if (S.g_act) gst(S.g_act, e, gld(S.g_act, e) + gact);
         } else if (tl.kind == TILE_TRI) {
             uint32_t cd[3];
             V3<T> x[3], f[3], fb[3], xb[3];
@@ -692,11 +698,13 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
                 x[c] = v3(xs[cd[c] & 0xffffu]);
                 fb[c] = v3(fbs[cd[c] & 0xffffu]);
             }
-            hinge_adjoint(x, gld(M.hin_phi0, e), M.bodies[tl.body].kb, fb, f, xb);
+            T gact;
+            hinge_adjoint(x, gld(M.hin_phi0, e), M.bodies[tl.body].kb, S.hact ? gld(S.hact, e) : T(0), fb, f, xb, gact);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 cs[cd[c] >> 16] = l4(xb[c], dot(f[c], fb[c]));
             }
+            if (S.g_hact) gst(S.g_hact, e, gld(S.g_hact, e) + gact);
         }
     }
     __syncthreads();
@@ -877,7 +885,7 @@ struct TriRec {
 template <typename T>
 struct HinRec {
     int li[4];
-    T phi0;
+    T phi0, act;
 };
 
 template <typename T>
@@ -905,6 +913,7 @@ __device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, HinRec<T>&
 #pragma unroll
     for (int q = 0; q < 4; ++q) r.li[q] = gld(M.f_hin_idx, q * M.nh + e);
     r.phi0 = gld(M.f_hin_phi0, e);
+    r.act = gld(M.f_hpar, e);
 }
 
 // Adjoint records also carry the element's running parameter gradient, read
@@ -912,22 +921,32 @@ __device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, HinRec<T>&
 // load issued after the previous element's store.
 template <typename T>
 struct TetRecA : TetRec<T> {
-    T gmu, glam;
+    T gmu, glam, gact;
 };
 template <typename T>
 struct TriRecA : TriRec<T> {
     T gk;
 };
 template <typename T>
+struct HinRecA : HinRec<T> {
+    T gact;
+};
+template <typename T>
 __device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, TetRecA<T>& r) {
     load_rec(M, e, static_cast<TetRec<T>&>(r));
     r.gmu = gld(M.f_g, e);
     r.glam = gld(M.f_g, M.ne + e);
+    r.gact = gld(M.f_g, 2 * M.ne + e);
 }
 template <typename T>
 __device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, TriRecA<T>& r) {
     load_rec(M, e, static_cast<TriRec<T>&>(r));
     r.gk = gld(M.f_gk, e);
+}
+template <typename T>
+__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, HinRecA<T>& r) {
+    load_rec(M, e, static_cast<HinRec<T>&>(r));
+    r.gact = gld(M.f_gh, e);
 }
 
 // Copies the body's colour bounds of all three kinds to LDS (kind k's ncol + 1
@@ -1075,7 +1094,7 @@ __global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>
                 o.li[q] = r.li[q];
                 x[q] = lds3(xs, npb, r.li[q]);
             }
-            hinge_force(x, r.phi0, B.kb, o.v);
+            hinge_force(x, r.phi0, B.kb, r.act, o.v);
         });
         // contact + semi-implicit Euler on the workgroup's own particles
         for (int li = threadIdx.x; li < npb; li += blockDim.x) {
@@ -1126,7 +1145,8 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
     stage_colour_bounds(M, B, reinterpret_cast<int32_t*>(acc + 4 * npb), cb);
     const T dt = B.dt;
     const bool contact = B.contact_on != 0;
-    const bool want_e = S.g_mu != nullptr || S.g_lam != nullptr, want_k = S.g_ktri != nullptr;
+    const bool want_e = S.g_mu != nullptr || S.g_lam != nullptr || S.g_act != nullptr,
+               want_k = S.g_ktri != nullptr, want_h = S.g_hact != nullptr;
     T pl[4], cp[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -1158,13 +1178,14 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
                 x[q] = lds3(xs, npb, r.li[q]);
                 fb[q] = lds3(fbs, npb, r.li[q]);
             }
-            T gmu, glam;
-            tet_adjoint(x, r.D, r.V, r.mu, r.lam, r.act, fb, f, o.v, gmu, glam);
+            T gmu, glam, gact;
+            tet_adjoint(x, r.D, r.V, r.mu, r.lam, r.act, fb, f, o.v, gmu, glam, gact);
 #pragma unroll
             for (int q = 0; q < 4; ++q) o.w[q] = dot(f[q], fb[q]);
             if (want_e && valid) {
                 gst(M.f_g, e, r.gmu + gmu);
                 gst(M.f_g, M.ne + e, r.glam + glam);
+                gst(M.f_g, 2 * M.ne + e, r.gact + gact);
             }
         });
         colour_sweep<FUSED_AHEAD_ADJ, 3, true, T, TriRecA<T>>(M, cb[1], B.ncol[1], acc, npb,
@@ -1182,8 +1203,8 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
             for (int q = 0; q < 3; ++q) o.w[q] = dot(f[q], fb[q]);
             if (want_k && valid) gst(M.f_gk, e, r.gk + gk);
         });
-        colour_sweep<FUSED_AHEAD_ADJ, 4, true, T, HinRec<T>>(M, cb[2], B.ncol[2], acc, npb,
-                                                         [&](int, const HinRec<T>& r, bool, Contrib<T, 4>& o) {
+        colour_sweep<FUSED_AHEAD_ADJ, 4, true, T, HinRecA<T>>(M, cb[2], B.ncol[2], acc, npb,
+                                                          [&](int e, const HinRecA<T>& r, bool valid, Contrib<T, 4>& o) {
             V3<T> x[4], f[4], fb[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -1191,9 +1212,11 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
                 x[q] = lds3(xs, npb, r.li[q]);
                 fb[q] = lds3(fbs, npb, r.li[q]);
             }
-            hinge_adjoint(x, r.phi0, B.kb, fb, f, o.v);
+            T gact;
+            hinge_adjoint(x, r.phi0, B.kb, r.act, fb, f, o.v, gact);
 #pragma unroll
             for (int q = 0; q < 4; ++q) o.w[q] = dot(f[q], fb[q]);
+            if (want_h && valid) gst(M.f_gh, e, r.gact + gact);
         });
         // contact adjoint and the integrator's adjoint on the workgroup's own particles
         T gc[4] = {T(0), T(0), T(0), T(0)};
@@ -1232,7 +1255,8 @@ template <typename T>
 __global__ void k_fused_params(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd) {
     const ModelDev<T>& M = md[0];
     const StepDev<T>& S = sd[0];
-    const bool clear_e = S.g_mu != nullptr || S.g_lam != nullptr, clear_k = S.g_ktri != nullptr;
+    const bool clear_e = S.g_mu != nullptr || S.g_lam != nullptr || S.g_act != nullptr,
+               clear_k = S.g_ktri != nullptr, clear_h = S.g_hact != nullptr;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < M.ne; e += stride) {
         const int32_t o = M.f_tet_orig[e];
@@ -1242,7 +1266,12 @@ __global__ void k_fused_params(const ModelDev<T>* __restrict__ md, const StepDev
         if (clear_e) {
             M.f_g[e] = T(0);
             M.f_g[M.ne + e] = T(0);
+            M.f_g[2 * M.ne + e] = T(0);
         }
+    }
+    for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < M.nh; h += stride) {
+        M.f_hpar[h] = S.hact ? S.hact[M.f_hin_orig[h]] : T(0);
+        if (clear_h) M.f_gh[h] = T(0);
     }
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < M.nt; t += stride) {
         M.f_ktri[t] = S.ktri[M.f_tri_orig[t]];
@@ -1259,7 +1288,11 @@ __global__ void k_fused_grads(const ModelDev<T>* __restrict__ md, const StepDev<
         const int32_t o = M.f_tet_orig[e];
         if (S.g_mu) S.g_mu[o] += M.f_g[e];
         if (S.g_lam) S.g_lam[o] += M.f_g[M.ne + e];
+        if (S.g_act) S.g_act[o] += M.f_g[2 * M.ne + e];
     }
+    if (S.g_hact)
+        for (int64_t h = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; h < M.nh; h += stride)
+            S.g_hact[M.f_hin_orig[h]] += M.f_gh[h];
     if (S.g_ktri)
         for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < M.nt; t += stride)
             S.g_ktri[M.f_tri_orig[t]] += M.f_gk[t];

@@ -56,12 +56,14 @@ class _State(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("mu", C.c_void_p), ("lam", C.c_void_p), ("act", C.c_void_p), ("k_tri", C.c_void_p),
-                ("mass", C.c_void_p), ("contact", C.c_void_p)]
+                ("mass", C.c_void_p), ("contact", C.c_void_p), ("hact", C.c_void_p), ("act_stride", C.c_int64),
+                ("hact_stride", C.c_int64)]
 
 
 class _Grads(C.Structure):
     _fields_ = [("mu", C.c_void_p), ("lam", C.c_void_p), ("k_tri", C.c_void_p), ("mass", C.c_void_p),
-                ("contact", C.c_void_p)]
+                ("contact", C.c_void_p), ("act", C.c_void_p), ("hact", C.c_void_p), ("act_stride", C.c_int64),
+                ("hact_stride", C.c_int64)]
 
 
 _lib = None
@@ -345,29 +347,52 @@ class Model:
             p["ktri"] = t(np.concatenate([b.ktri for b in bodies if b.nt]))
         return p
 
-    def zero_grads(self, which=("mu", "lam", "ktri", "mass", "contact")):
-        n = {"mu": self.ne, "lam": self.ne, "ktri": self.nt, "mass": self.np, "contact": 4 * self.nb}
+    def zero_grads(self, which=("mu", "lam", "ktri", "mass", "contact"), steps=None):
+        """Zeroed gradient buffers.  "act" and "hact" (tet and hinge actuation) are
+        [ne] / [nh], or [steps, ne] / [steps, nh] for one gradient per step."""
+        n = {"mu": self.ne, "lam": self.ne, "ktri": self.nt, "mass": self.np, "contact": 4 * self.nb,
+             "act": self.ne, "hact": self.nh}
         g = {}
         for k in which:
             if n[k]:
-                g[k] = torch.zeros(n[k], dtype=self.dtype, device=self.device)
+                shape = (steps, n[k]) if steps is not None and k in ("act", "hact") else (n[k],)
+                g[k] = torch.zeros(shape, dtype=self.dtype, device=self.device)
         if "contact" in g:
             g["contact"] = g["contact"].view(self.nb, 4)
         return g
 
-    @staticmethod
-    def _params(p):
+    def _actuation(self, d, key, n_steps):
+        """Pointer and step stride of an actuation tensor: [n] (the same for every
+        step) or [steps, n] (row t for step t; at least n_steps rows)."""
+        a = d.get(key) if d else None
+        if a is None:
+            return None, 0
+        n = self.ne if key == "act" else self.nh
+        if a.dim() == 1:
+            if a.shape[0] != n or a.stride(0) != 1:
+                raise ValueError(f"{key}: expected a contiguous [{n}] tensor")
+            return _ptr(a), 0
+        if a.dim() != 2 or a.shape[1] != n or a.stride(1) != 1 or a.stride(0) < n:
+            raise ValueError(f"{key}: expected [steps, {n}] with contiguous rows")
+        if a.shape[0] < n_steps:
+            raise ValueError(f"{key}: {a.shape[0]} rows for {n_steps} steps")
+        return _ptr(a), a.stride(0)
+
+    def _params(self, p, n_steps=1):
         s = _Params()
-        s.mu, s.lam, s.act = _ptr(p.get("mu")), _ptr(p.get("lam")), _ptr(p.get("act"))
+        s.mu, s.lam = _ptr(p.get("mu")), _ptr(p.get("lam"))
         s.k_tri, s.mass, s.contact = _ptr(p.get("ktri")), _ptr(p.get("mass")), _ptr(p.get("contact"))
+        s.act, s.act_stride = self._actuation(p, "act", n_steps)
+        s.hact, s.hact_stride = self._actuation(p, "hact", n_steps)
         return s
 
-    @staticmethod
-    def _grads(g):
+    def _grads(self, g, n_steps=1):
         s = _Grads()
         if g:
             s.mu, s.lam, s.k_tri = _ptr(g.get("mu")), _ptr(g.get("lam")), _ptr(g.get("ktri"))
             s.mass, s.contact = _ptr(g.get("mass")), _ptr(g.get("contact"))
+            s.act, s.act_stride = self._actuation(g, "act", n_steps)
+            s.hact, s.hact_stride = self._actuation(g, "hact", n_steps)
         return s
 
     @staticmethod
@@ -379,7 +404,7 @@ class Model:
     # -- entry points -------------------------------------------------------------
     def step(self, params, x, v, n_steps=1, out=None, stream=None):
         xo, vo = self.empty_state() if out is None else out
-        _check(load().gsim_step(self._h, C.byref(self._params(params)), self._state(x, v), self._state(xo, vo),
+        _check(load().gsim_step(self._h, C.byref(self._params(params, n_steps)), self._state(x, v), self._state(xo, vo),
                                 int(n_steps), _stream(stream)))
         return xo, vo
 
@@ -397,16 +422,16 @@ class Model:
     def rollout(self, params, x0, v0, n_steps, checkpoint=True, out=None, stream=None, ckpt=None):
         xo, vo = self.empty_state() if out is None else out
         ck = (self.ckpt if ckpt is None else ckpt) if checkpoint else None
-        _check(load().gsim_rollout(self._h, C.byref(self._params(params)), self._state(x0, v0), int(n_steps),
+        _check(load().gsim_rollout(self._h, C.byref(self._params(params, n_steps)), self._state(x0, v0), int(n_steps),
                                    _ptr(ck), self._state(xo, vo), _stream(stream)))
         return xo, vo
 
     def rollout_backward(self, params, n_steps, xb_final, vb_final, grads=None, out=None, stream=None, ckpt=None):
         xbi, vbi = self.empty_state() if out is None else out
         ck = self.ckpt if ckpt is None else ckpt
-        _check(load().gsim_rollout_backward(self._h, C.byref(self._params(params)), _ptr(ck), int(n_steps),
+        _check(load().gsim_rollout_backward(self._h, C.byref(self._params(params, n_steps)), _ptr(ck), int(n_steps),
                                             _ptr(self.segment), self._state(xb_final, vb_final), self._state(xbi, vbi),
-                                            C.byref(self._grads(grads)), _stream(stream)))
+                                            C.byref(self._grads(grads, n_steps)), _stream(stream)))
         return xbi, vbi
 
     def loss_mse(self, x, target, seed=True, stream=None):

@@ -194,3 +194,28 @@ def test_element_tiles_and_partials(gs, which):
         assert (covered[k] == 1).all()
     assert len(set(slot.tolist())) == len(slot) and slot.max() < nslot
     assert all(seen_k.get(q, 0) == deg[q] for q in range(len(deg)))
+
+
+def test_ctypes_structs_match_header(gs, tmp_path):
+    """Every struct the Python binding mirrors has the header's size and field
+    offsets (compiled against include/gsim.h with the host C compiler)."""
+    import ctypes
+    import subprocess
+    from paper_2104_02646_amd import serve
+    mirrors = {"gsim_model_desc": gs._Desc, "gsim_state": gs._State, "gsim_params": gs._Params,
+               "gsim_grads": gs._Grads, "gsim_query": serve._Query, "gsim_result": serve._Result}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gsim.h"', "int main(void) {"]
+    expect = []
+    for cname, cls in mirrors.items():
+        lines.append('printf("%%zu\\n", sizeof(%s));' % cname)
+        expect.append(ctypes.sizeof(cls))
+        for fname, _ in cls._fields_:
+            lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (cname, fname))
+            expect.append(getattr(cls, fname).offset)
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(s) for s in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == expect
