@@ -283,6 +283,44 @@ int gsim_loss_mse(gsim_model* model, gsim_state s, const void* d_target, void* d
                   void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* OPEN-LOOP ACTUATION CONTROLLER                                            */
+/* ------------------------------------------------------------------------ */
+/* The paper's control policy (App. "MPC controller architecture"; Sec. 5.3,
+ * control-walker and control-fem): N phase-shifted sinusoids of the simulation
+ * time feed one fully connected layer without bias and a tanh, which gives one
+ * actuation value per output element (tet or hinge) per step:
+ *
+ *     s_k(t)    = sin(omega * (t0 + t) * dt + 2 pi k / N),      k = 0 .. N-1
+ *     act[t][e] = scale * tanh(sum_k W[k][e] * s_k(t)),         t = 0 .. n_steps-1
+ *
+ * (the sum over k in increasing k).  The rows act[t] are the per-step actuation
+ * rows of gsim_params (act = the array, act_stride = n); the gradient rows that
+ * gsim_rollout_backward writes with act_stride = n are the act_grad input of
+ * gsim_controller_backward.  The signals are evaluated in FP64 and rounded to
+ * the dtype; everything else runs in the dtype. */
+#define GSIM_CTRL_MAX_SIGNALS 16
+typedef struct {
+    int n_signals; /* N, 1 .. GSIM_CTRL_MAX_SIGNALS */
+    double omega;  /* angular frequency (radians per unit of simulation time) */
+    double dt;     /* simulation time of one step */
+    double scale;  /* output amplitude; 1 gives the plain tanh */
+} gsim_controller;
+
+/* act[n_steps][n] (device, dtype elements) from the weights W[N][n] (device,
+ * row k contiguous over the n outputs), for steps t0 .. t0 + n_steps - 1.
+ * n == 0 or n_steps == 0 does nothing.  Asynchronous on `stream`.
+ * Errors (nothing launched): GSIM_E_INVALID for a bad dtype, NULL pointers with
+ * work to do, N outside 1..GSIM_CTRL_MAX_SIGNALS, negative n / t0 / n_steps, or
+ * non-finite omega, dt, scale. */
+int gsim_controller_forward(int dtype, const gsim_controller* ctrl, const void* W, int64_t n, int64_t t0,
+                            int64_t n_steps, void* act, void* stream);
+/* W_grad[N][n] += the gradient of sum_{t,e} act_grad[t][e] * act[t][e] with
+ * respect to W, for the same steps; recomputes the layer from W (act itself
+ * is not read).  act_grad is [n_steps][n].  Same errors as the forward. */
+int gsim_controller_backward(int dtype, const gsim_controller* ctrl, const void* W, const void* act_grad, int64_t n,
+                             int64_t t0, int64_t n_steps, void* W_grad, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* SERVING ENGINE: continuous batching of rollout-gradient queries           */
 /* ------------------------------------------------------------------------ */
 /* A query is one FP32 body (n_bodies == 1) with parameters, start state and

@@ -50,3 +50,30 @@ class SimRollout(torch.autograd.Function):
 def rollout(model, params, x0, v0, n_steps):
     """Differentiable rollout: params is a dict of (possibly requires_grad) tensors."""
     return SimRollout.apply(model, n_steps, x0, v0, *(params.get(k) for k in _PARAM_KEYS))
+
+
+class Controller(torch.autograd.Function):
+    """W [n_signals, n] -> act [n_steps, n], the open-loop actuation controller
+    (sinusoids of the simulation time -> bias-free linear layer -> tanh; App. "MPC
+    controller architecture").  Forward and backward are the HIP kernels behind
+    ``gsim_controller_forward`` / ``gsim_controller_backward``; feed the result to
+    ``rollout`` as per-step ``act`` (or ``hact``) rows."""
+
+    @staticmethod
+    def forward(ctx, W, omega, dt, n_steps, t0, scale):
+        W = W.detach().contiguous()
+        ctx.save_for_backward(W)
+        ctx.args = (float(omega), float(dt), int(t0), float(scale))
+        return gsim.controller_forward(W, omega, dt, int(n_steps), t0=int(t0), scale=scale)
+
+    @staticmethod
+    def backward(ctx, g):
+        (W,) = ctx.saved_tensors
+        omega, dt, t0, scale = ctx.args
+        gW = gsim.controller_backward(W, g.contiguous(), omega, dt, t0=t0, scale=scale)
+        return gW, None, None, None, None, None
+
+
+def controller(W, omega, dt, n_steps, t0=0, scale=1.0):
+    """Differentiable per-step actuation rows from controller weights W."""
+    return Controller.apply(W, omega, dt, n_steps, t0, scale)

@@ -26,11 +26,15 @@ GSIM_E_WORKSPACE, GSIM_E_HIP, GSIM_E_NONFINITE, GSIM_E_UNSUPPORTED = -4, -5, -6,
 EXEC_PLAIN, EXEC_GRAPH, EXEC_FUSED = 0, 1, 2
 
 ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan_destroy", "gsim_plan_sizes",
-               "gsim_plan_counts", "gsim_plan_colouring", "gsim_plan_tiles", "gsim_plan_codes", "gsim_plan_partials", "gsim_model_init", "gsim_model_destroy", "gsim_model_set_exec",
-               "gsim_model_get_exec", "gsim_model_set_launch", "gsim_model_get_launch", "gsim_model_set_lanes", "gsim_model_get_lanes", "gsim_step", "gsim_step_backward", "gsim_rollout", "gsim_rollout_backward",
+               "gsim_plan_counts", "gsim_plan_colouring", "gsim_plan_tiles", "gsim_plan_codes", "gsim_plan_partials",
+               "gsim_model_init", "gsim_model_destroy", "gsim_model_set_exec", "gsim_model_get_exec",
+               "gsim_model_set_launch", "gsim_model_get_launch", "gsim_model_set_lanes", "gsim_model_get_lanes",
+               "gsim_step", "gsim_step_backward", "gsim_rollout", "gsim_rollout_backward",
                "gsim_loss_mse", "gsim_model_set_timing", "gsim_model_read_timing",
+               "gsim_controller_forward", "gsim_controller_backward",
                "gsim_engine_create", "gsim_engine_destroy", "gsim_engine_query_bytes", "gsim_engine_submit",
                "gsim_engine_tick", "gsim_engine_poll", "gsim_engine_stats")
+GSIM_F32, GSIM_F64 = 32, 64
 KERNELS = ("element_fwd", "particle_fwd", "element_adj", "particle_adj", "fused_fwd", "fused_adj")
 
 
@@ -58,6 +62,10 @@ class _Params(C.Structure):
     _fields_ = [("mu", C.c_void_p), ("lam", C.c_void_p), ("act", C.c_void_p), ("k_tri", C.c_void_p),
                 ("mass", C.c_void_p), ("contact", C.c_void_p), ("hact", C.c_void_p), ("act_stride", C.c_int64),
                 ("hact_stride", C.c_int64)]
+
+
+class _Ctrl(C.Structure):
+    _fields_ = [("n_signals", C.c_int), ("omega", C.c_double), ("dt", C.c_double), ("scale", C.c_double)]
 
 
 class _Grads(C.Structure):
@@ -101,6 +109,9 @@ def load():
         lib.gsim_loss_mse.argtypes = [vp, _State, vp, vp, _State, vp]
         lib.gsim_model_set_timing.argtypes = [vp, ip]
         lib.gsim_model_read_timing.argtypes = [vp, ip, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        i64 = C.c_int64
+        lib.gsim_controller_forward.argtypes = [ip, C.POINTER(_Ctrl), vp, i64, i64, i64, vp, vp]
+        lib.gsim_controller_backward.argtypes = [ip, C.POINTER(_Ctrl), vp, vp, i64, i64, i64, vp, vp]
         _lib = lib
     return _lib
 
@@ -132,6 +143,45 @@ def aos(t):
 # ----------------------------------------------------------------------------------
 # Plan / Model
 # ----------------------------------------------------------------------------------
+
+# ----------------------------------------------------------------------------------
+# Open-loop actuation controller (gsim_controller_*)
+# ----------------------------------------------------------------------------------
+
+def _ctrl_args(W, omega, dt, scale):
+    if W.dim() != 2 or not W.is_contiguous() or W.dtype not in (torch.float32, torch.float64):
+        raise ValueError("W must be a contiguous float32/float64 [n_signals, n] tensor")
+    c = _Ctrl()
+    c.n_signals, c.omega, c.dt, c.scale = W.shape[0], float(omega), float(dt), float(scale)
+    return c, (GSIM_F32 if W.dtype == torch.float32 else GSIM_F64)
+
+
+def controller_forward(W, omega, dt, n_steps, t0=0, scale=1.0, out=None, stream=None):
+    """act[n_steps, n] = scale tanh(S W) for steps t0.. (rows feed the per-step
+    actuation of a rollout)."""
+    c, dt_code = _ctrl_args(W, omega, dt, scale)
+    n = W.shape[1]
+    act = torch.empty(int(n_steps), n, dtype=W.dtype, device=W.device) if out is None else out
+    if act.shape != (int(n_steps), n) or act.dtype != W.dtype or not act.is_contiguous():
+        raise ValueError("out must be a contiguous [n_steps, n] tensor of W's dtype")
+    _check(load().gsim_controller_forward(dt_code, C.byref(c), _ptr(W), n, int(t0), int(n_steps), _ptr(act),
+                                          _stream(stream)))
+    return act
+
+
+def controller_backward(W, act_grad, omega, dt, t0=0, scale=1.0, W_grad=None, stream=None):
+    """W_grad[n_signals, n] += d<act_grad, act>/dW (a new zeroed tensor if None)."""
+    c, dt_code = _ctrl_args(W, omega, dt, scale)
+    n = W.shape[1]
+    if act_grad.dim() != 2 or act_grad.shape[1] != n or act_grad.dtype != W.dtype or not act_grad.is_contiguous():
+        raise ValueError("act_grad must be a contiguous [n_steps, n] tensor of W's dtype")
+    gW = torch.zeros_like(W) if W_grad is None else W_grad
+    if gW.shape != W.shape or gW.dtype != W.dtype or not gW.is_contiguous():
+        raise ValueError("W_grad must be a contiguous tensor shaped like W")
+    _check(load().gsim_controller_backward(dt_code, C.byref(c), _ptr(W), _ptr(act_grad), n, int(t0),
+                                           act_grad.shape[0], _ptr(gW), _stream(stream)))
+    return gW
+
 
 @dataclass
 class Packed:
@@ -190,7 +240,7 @@ class Plan:
         pk = pack(self.bodies)
         self.packed = pk
         d = _Desc()
-        d.dtype = 64 if dtype == torch.float64 else 32
+        d.dtype = GSIM_F64 if dtype == torch.float64 else GSIM_F32
         d.n_bodies = pk.n_bodies
         d.n_particles, d.n_tets, d.n_tris, d.n_hinges = len(pk.X), len(pk.tets), len(pk.tris), len(pk.hinges)
         a = lambda arr: arr.ctypes.data if arr is not None and arr.size else None

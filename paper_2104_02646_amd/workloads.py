@@ -16,6 +16,7 @@ App. B, with every constant the paper leaves open written out here):
 * ``batch_bodies``   256 tet bodies, counts log-uniform in [500, 20000]
 * ``large_blob``     ~200k tets voxelised from a sum-of-5-spheres implicit blob
 * ``serving_trace``  Poisson stream of tet / cloth gradient queries
+* ``gear``, ``walker``  actuated bodies of the control tasks (1152 / 168 tets)
 """
 from __future__ import annotations
 
@@ -382,6 +383,65 @@ def large_blob(seed: int = 30, target_tets: int = 200_000):
     v0 = np.tile([1.0, -0.5, 0.0], (len(X), 1))
     return Body(X=X, tets=tets, mu=mu, lam=lam, mass=mass, ke=1e5, kd=0.0, kf=100.0, muf=0.5, ground=True,
                 gravity=(0.0, 0.0, 0.0), dt=1e-3, x0=X.copy(), v0=v0)
+
+
+def gear(seed: int = 50, n_teeth: int = 16, layers: int = 4, r_in: float = 0.06, dr: float = 0.03,
+         dz: float = 0.02):
+    """Soft gear for the actuated-locomotion control task (Sec. 5.3 control-fem: a
+    gear of 1152 tets driven by per-tet actuation).  A ring of 2 n_teeth angular hex
+    segments one hex deep (radii r_in .. r_in + dr) with a tooth hex (out to
+    r_in + 2 dr) on every other segment, `layers` hexes thick along z; each hex is 6
+    Kuhn tets: (32 + 16) x 4 = 192 hexes = 1152 tets and 480 particles for the
+    defaults.  The axis is horizontal (z), so the gear stands on its teeth on the
+    ground.  Rubber-like: mu, lambda ~ U(5e4, 1.5e5) Pa per tet, particle mass
+    4.5 g (about 1100 kg/m^3), gravity, ground k_e = 1e4, k_d = 0, k_f = 100,
+    mu_f = 0.5, dt = 5e-4 (explicit-stable for these elements), at rest 5 mm above
+    the ground."""
+    rng = np.random.default_rng(seed)
+    na = 2 * n_teeth
+    mask = np.zeros((na, 2, layers), bool)
+    mask[:, 0, :] = True
+    mask[0::2, 1, :] = True
+    G, tets = voxel_tets(mask, 1.0)
+    g = np.rint(G).astype(np.int64)
+    g[:, 0] %= na  # angular index na is index 0: close the ring
+    key = (g[:, 0] * 8 + g[:, 1]) * (layers + 1) + g[:, 2]
+    uniq, first, inv = np.unique(key, return_index=True, return_inverse=True)
+    tets = inv[tets].astype(np.int32)
+    g = g[first]
+    theta = 2.0 * np.pi * g[:, 0] / na
+    r = r_in + dr * g[:, 1]
+    X = np.stack([r * np.cos(theta), r * np.sin(theta), dz * g[:, 2]], 1)
+    # (angle, radius) -> (x, y) reverses orientation: swap two corners of every tet
+    tets = tets[:, [0, 2, 1, 3]].copy()
+    X = _place_on_ground(X, 0.005)
+    mu, lam = _tet_materials(rng, len(tets), 5e4, 1.5e5)
+    mass = np.full(len(X), 0.0045)
+    return Body(X=X, tets=tets, mu=mu, lam=lam, mass=mass, ke=1e4, kd=0.0, kf=100.0, muf=0.5,
+                ground=True, dt=5e-4, x0=X.copy())
+
+
+def walker(seed: int = 51, h: float = 0.02):
+    """Planar two-legged walker for the control-walker task (Sec. 5.3: a 2D walker
+    actuated per element), one voxel thick: a 10 x 2 voxel torso on two 2 x 2 voxel
+    legs, 28 voxels = 168 tets.  Materials, mass and contact as for the gear; stands
+    on its feet 2 mm above the ground."""
+    rng = np.random.default_rng(seed)
+    mask = np.zeros((10, 4, 1), bool)
+    mask[:, 2:4, 0] = True
+    mask[0:2, 0:2, 0] = True
+    mask[8:10, 0:2, 0] = True
+    X, tets = voxel_tets(mask, h)
+    X = _place_on_ground(X, 0.002)
+    mu, lam = _tet_materials(rng, len(tets), 5e4, 1.5e5)
+    mass = np.full(len(X), 0.0045)
+    return Body(X=X, tets=tets, mu=mu, lam=lam, mass=mass, ke=1e4, kd=0.0, kf=100.0, muf=0.5,
+                ground=True, dt=5e-4, x0=X.copy())
+
+
+def controller_weights(seed: int, n_signals: int, n: int, std: float = 0.5):
+    """Initial controller weights W[n_signals, n] ~ N(0, std^2)."""
+    return np.random.default_rng(seed).normal(0.0, std, (n_signals, n))
 
 
 def synthetic_target(body: Body, seed: int, drop: float = 0.05, noise: float = 0.005):

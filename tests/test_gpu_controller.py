@@ -1,0 +1,149 @@
+"""Controller kernels (gsim_controller_forward / _backward) vs the FP64 oracle, and the
+control task end to end (needs an MI355X).
+
+Shapes cover one and several workgroups with a ragged tail (n = 1, 255, 257,
+1000), one and several LDS step chunks (n_steps = 1, 64, 65, 200), N = 1, 8, 16
+signals and a nonzero first step t0.  The control task (Sec. 5.3 control-fem /
+control-walker) chains controller -> per-step actuation rows -> checkpointed
+rollout -> loss, backward through both autograd Functions, against the oracle's
+step-by-step adjoint and controller backward.
+"""
+import numpy as np
+import pytest
+
+from helpers import oracle_for, rel
+from oracle import controller as OC
+from paper_2104_02646_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2104_02646_amd import gsim
+    gsim.load()
+    return gsim
+
+
+SHAPES = [(1, 1, 1, 0), (8, 255, 64, 0), (8, 257, 65, 3), (16, 1000, 200, 17), (1, 300, 7, 5)]
+
+
+@pytest.mark.parametrize("N,n,T,t0", SHAPES)
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_controller_kernels_vs_oracle(gs, N, n, T, t0, dtype):
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    npdt = np.float64 if dtype == "f64" else np.float32
+    rng = np.random.default_rng(N * 1000 + n + T)
+    omega, dt, scale = 2 * np.pi * 3.0, 1e-3, 0.3
+    Wt = rng.normal(0, 0.8, (N, n)).astype(npdt).astype(np.float64)
+    G = rng.normal(size=(T, n)).astype(npdt).astype(np.float64)
+    print("controller case", dtype, N, n, T, t0, flush=True)
+    Wd = torch.as_tensor(Wt).to("cuda", tdt).contiguous()
+    act = gs.controller_forward(Wd, omega, dt, T, t0=t0, scale=scale)
+    gW0 = torch.full_like(Wd, 0.5)
+    gW = gs.controller_backward(Wd, torch.as_tensor(G).to("cuda", tdt).contiguous(), omega, dt, t0=t0, scale=scale,
+                                W_grad=gW0.clone())
+    torch.cuda.synchronize()
+    act_ref = OC.forward(Wt, omega, dt, t0, T, scale)
+    gW_ref = OC.backward(Wt, G, omega, dt, t0, scale) + 0.5
+    a = act.double().cpu().numpy()
+    g = gW.double().cpu().numpy()
+    if dtype == "f64":
+        assert np.abs(a - act_ref).max() < 1e-14
+        assert rel(g, gW_ref) < 1e-13
+    else:
+        # FP32: the pre-activation sum of N products (signals rounded once) carries at
+        # most (N + 2) u sum_k |W_k s_k| of rounding, tanh a few ulp; u = 2^-24
+        u = 2.0 ** -24
+        zabs = np.abs(OC.signals(N, omega, dt, t0, T)) @ np.abs(Wt)
+        assert np.all(np.abs(a - act_ref) <= scale * ((N + 2) * u * zabs + 4 * u))
+        assert rel(g, gW_ref) < 1e-5
+
+
+def test_controller_empty_and_errors(gs):
+    W0 = torch.zeros(8, 0, device="cuda")
+    assert gs.controller_forward(W0, 1.0, 1e-3, 5).shape == (5, 0)
+    Wd = torch.randn(8, 10, device="cuda")
+    assert gs.controller_forward(Wd, 1.0, 1e-3, 0).shape == (0, 10)
+    with pytest.raises(gs.GsimError, match="n_signals"):
+        gs.controller_forward(torch.randn(17, 10, device="cuda"), 1.0, 1e-3, 5)
+    with pytest.raises(gs.GsimError, match="finite"):
+        gs.controller_forward(Wd, float("nan"), 1e-3, 5)
+    with pytest.raises(gs.GsimError, match=">= 0"):
+        gs.controller_forward(Wd, 1.0, 1e-3, 5, t0=-1)
+    with pytest.raises(ValueError):
+        gs.controller_backward(Wd, torch.randn(5, 11, device="cuda"), 1.0, 1e-3)
+
+
+def _oracle_control_grad(orc, body, Wt, omega, scale, T, target):
+    act = OC.forward(Wt, omega, body.dt, 0, T, scale)
+    p = body.params()
+    xs, vs = [body.x0], [body.v0]
+    for t in range(T):
+        xn, vn = orc.step(dict(p, act=act[t]), xs[-1], vs[-1])
+        xs.append(xn)
+        vs.append(vn)
+    L, xb = orc.loss(xs[-1], target, with_grad=True)
+    vb = np.zeros_like(xb)
+    gact = np.zeros_like(act)
+    for t in range(T - 1, -1, -1):
+        xb, vb, g = orc.step_vjp(dict(p, act=act[t]), xs[t], vs[t], xb, vb, want=("act",))
+        gact[t] = g["act"]
+    return xs[-1], L, OC.backward(Wt, gact, omega, body.dt, 0, scale)
+
+
+@pytest.mark.parametrize("which,dtype,tol", [("gear", "f64", 1e-8), ("gear", "f32", 1e-3), ("walker", "f32", 1e-3)])
+def test_control_task_gradient(gs, oracle_lib, which, dtype, tol):
+    """controller -> rollout (checkpoints every 9) -> mean-square loss to a shifted
+    target; dL/dW through both autograd Functions vs the oracle chain."""
+    from paper_2104_02646_amd.autograd import controller, rollout
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    npdt = np.float64 if dtype == "f64" else np.float32
+    body = W.gear() if which == "gear" else W.walker()
+    if dtype == "f32":
+        body = body.round_to(np.float32)
+    T, omega, scale = 60, 2 * np.pi * 4.0, 0.2
+    Wt = W.controller_weights(7, 8, body.ne).astype(npdt).astype(np.float64)
+    target = (body.X + np.array([0.01, 0.0, 0.0])).astype(npdt).astype(np.float64)
+    orc = oracle_for(oracle_lib, body)
+    xT_ref, L_ref, gW_ref = _oracle_control_grad(orc, body, Wt, omega, scale, T, target)
+    m = gs.Model([body], tdt, max_steps=T, ckpt_every=9)
+    Wd = torch.as_tensor(Wt).to("cuda", tdt).contiguous().requires_grad_(True)
+    p = m.params_from_bodies()
+    p["act"] = controller(Wd, omega, body.dt, T, scale=scale)
+    xT, _ = rollout(m, p, gs.soa(body.x0, tdt), gs.soa(body.v0, tdt), T)
+    loss = ((xT - gs.soa(target, tdt)) ** 2).sum() / body.np
+    loss.backward()
+    errs = {"x": rel(gs.aos(xT), xT_ref), "loss": abs(float(loss) - L_ref) / L_ref,
+            "W": rel(Wd.grad.double().cpu().numpy(), gW_ref)}
+    print("control task %s %s errors:" % (which, dtype), {k: "%.2e" % v for k, v in errs.items()})
+    assert errs["x"] < (1e-10 if dtype == "f64" else 1e-4)
+    assert errs["W"] < tol
+
+
+def test_control_task_descends(gs):
+    """A few Adam steps on the controller weights lower the gear's distance to a
+    target 5 cm to the side (gradients are useful, not only correct)."""
+    from paper_2104_02646_amd.autograd import controller, rollout
+    body = W.gear()
+    T, omega, scale = 200, 2 * np.pi * 4.0, 0.2
+    m = gs.Model([body], torch.float32, max_steps=T, ckpt_every=20)
+    base = m.params_from_bodies()
+    Wd = torch.as_tensor(W.controller_weights(8, 8, body.ne)).to("cuda", torch.float32).requires_grad_(True)
+    goal = torch.as_tensor(body.X.mean(0) + np.array([0.05, 0.0, 0.0]), dtype=torch.float32, device="cuda")
+    opt = torch.optim.Adam([Wd], lr=0.1)
+    losses = []
+    for it in range(8):
+        opt.zero_grad()
+        p = dict(base, act=controller(Wd, omega, body.dt, T, scale=scale))
+        xT, _ = rollout(m, p, gs.soa(body.x0), gs.soa(body.v0), T)
+        loss = ((xT.mean(1) - goal) ** 2).sum()
+        loss.backward()
+        opt.step()
+        losses.append(float(loss))
+    print("control descent losses", ["%.3e" % v for v in losses])
+    assert all(np.isfinite(losses))
+    assert min(losses[1:]) < losses[0]
