@@ -152,6 +152,63 @@ def serving(n_measured, n_warm, ckpt_every, log):
             "one_query_per_launch_fifo": summary(flat, fwall)}
 
 
+def control_step(model, p, x0, v0, tgt, T, steps, stream, ne, n_signals=8):
+    """The actuated step of the control tasks at the batch's scale: controller
+    forward (per-step actuation rows for every tet), rollout driven by those rows,
+    loss, adjoint with per-step actuation gradients, controller backward.  Also the
+    two controller kernels alone (HIP events on the launch stream) against their
+    algorithmic bytes: forward reads W once and writes T rows, backward reads W
+    and T rows of act-bar and read-modify-writes W-bar."""
+    import torch
+    from paper_2104_02646_amd import gsim
+    omega, dt, scale = 2 * np.pi * 4.0, 1.0 / 600.0, 0.05
+    rng = np.random.default_rng(99)
+    Wc = torch.as_tensor(rng.normal(0, 0.5, (n_signals, ne)), dtype=torch.float32, device="cuda")
+    act = torch.empty(T, ne, dtype=torch.float32, device="cuda")
+    gact = torch.zeros_like(act)
+    gW = torch.zeros_like(Wc)
+    g = model.zero_grads(("mu", "lam", "mass", "contact"))
+    xT, vT = model.empty_state()
+    xb0, vb0 = model.empty_state()
+
+    def one():
+        gsim.controller_forward(Wc, omega, dt, T, scale=scale, out=act, stream=stream)
+        q = dict(p, act=act)
+        model.rollout(q, x0, v0, T, out=(xT, vT), stream=stream)
+        loss, xb, vb = model.loss_mse(xT, tgt, stream=stream)
+        for t in g.values():
+            t.zero_()
+        gact.zero_()
+        model.rollout_backward(q, T, xb, vb, dict(g, act=gact), out=(xb0, vb0), stream=stream)
+        gW.zero_()
+        gsim.controller_backward(Wc, gact, omega, dt, scale=scale, W_grad=gW, stream=stream)
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    reps = 10
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    for _ in range(reps):
+        gsim.controller_forward(Wc, omega, dt, T, scale=scale, out=act, stream=stream)
+    ev[1].record(stream)
+    for _ in range(reps):
+        gsim.controller_backward(Wc, gact, omega, dt, scale=scale, W_grad=gW, stream=stream)
+    ev[2].record(stream)
+    ev[2].synchronize()
+    f_ms, b_ms = ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps
+    f_bytes = 4 * (n_signals * ne + T * ne)
+    b_bytes = 4 * (n_signals * ne + T * ne + 2 * n_signals * ne)
+    return {"workload": "controller (%d sinusoids -> linear -> tanh) driving every tet of the batch, per-step "
+                        "actuation rows and gradients" % n_signals,
+            "value": ne * T / sec, "unit": "element-steps/s", "ms_per_step": sec * 1e3,
+            "controller_fwd": {"avg_us": f_ms * 1e3, "bytes": f_bytes, "GBps": f_bytes / (f_ms * 1e-3) / 1e9},
+            "controller_bwd": {"avg_us": b_ms * 1e3, "bytes": b_bytes, "GBps": b_bytes / (b_ms * 1e-3) / 1e9}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +225,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=400, help="measured queries of the serving trace (0 = skip)")
+    ap.add_argument("--no-control", action="store_true", help="skip the actuated (controller-driven) step")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device tensor copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -243,6 +301,7 @@ def main():
             model.rollout(p, x0, v0, T, out=(xT, vT), stream=stream)
         torch.cuda.synchronize()
         sec_fwd = (time.perf_counter() - t0) / args.steps
+        control = None if args.no_control else control_step(model, p, x0, v0, tgt, T, args.steps, stream, ne)
         # per-kernel durations: one more bench step with HIP events around every launch
         # (graph replay cannot carry them: the two-pass path is timed with plain launches)
         model.set_exec(gsim.EXEC_FUSED if args.exec == "fused" else gsim.EXEC_PLAIN)
@@ -348,6 +407,9 @@ def main():
                                   "sample": "bodies 0..%d of the batch (%d tets), %d steps fwd + loss + adjoint, "
                                             "FP64, single thread" % (sample[-1], tot, T)}
         result["parity_sample"] = {"bodies": len(sample), "max_rel_err": errs}
+    if control is not None:
+        control["overhead_vs_unactuated_step"] = control["ms_per_step"] / (sec * 1e3)
+        result["control"] = control
     if args.serve_queries > 0:
         result["serving"] = serving(args.serve_queries, max(20, args.serve_queries // 10), K,
                                     lambda msg: print(msg, file=sys.stderr, flush=True))
