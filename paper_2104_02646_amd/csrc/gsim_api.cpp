@@ -647,7 +647,8 @@ enum Op : int {
     OP_FUSED_FWD = 5,  // whole segment of forward steps, one workgroup per body
     OP_FUSED_ADJ = 6,    // whole segment of adjoint steps, one workgroup per body
     OP_FUSED_PARAMS = 7, // parameters into colour order (and colour-ordered gradient clear)
-    OP_FUSED_GRADS = 8   // colour-ordered gradients back to element order
+    OP_FUSED_GRADS = 8,  // colour-ordered gradients back to element order
+    OP_FUSED_ADJ_ACT = 9 // OP_FUSED_ADJ that also accumulates actuation gradients
 };
 
 template <typename T>
@@ -750,8 +751,10 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
                 }), "fused forward");
                 break;
             case OP_FUSED_ADJ:
+            case OP_FUSED_ADJ_ACT:
                 LAUNCH_TRY(timed(m, 5, stream, [&] {
-                    return launch_fused_adj<T>(md, sd, (const int32_t*)(m->ws + m->L.border), m->nb, fused_lds<T>(m, true), stream);
+                    return launch_fused_adj<T>(md, sd, (const int32_t*)(m->ws + m->L.border), m->nb,
+                                               fused_lds<T>(m, true), l.op == OP_FUSED_ADJ_ACT, stream);
                 }), "fused adjoint");
                 break;
             case OP_FUSED_PARAMS:
@@ -899,6 +902,7 @@ int do_fused_rollout_backward(gsim_model* m, const gsim_params* p, const T* ck, 
     Ctx<T> c = ctx<T>(m);
     const int64_t S = 6 * c.np, np = c.np;
     const int K = m->K, nseg = (n + K - 1) / K;
+    const bool act = g && (g->act || g->hact);
     std::vector<StepDev<T>> rows(1, fused_row<T>(p, g));
     const int64_t r0 = region_backward(m);
     std::vector<Launch> seq{{OP_FUSED_PARAMS, r0}};
@@ -937,12 +941,12 @@ int do_fused_rollout_backward(gsim_model* m, const gsim_params* p, const T* ck, 
             r.vbo = r.xbo + 3 * np;
         }
         rows.push_back(r);
-        seq.push_back({OP_FUSED_ADJ, r0 + (int64_t)rows.size() - 1});
+        seq.push_back({act ? OP_FUSED_ADJ_ACT : OP_FUSED_ADJ, r0 + (int64_t)rows.size() - 1});
     }
     seq.push_back({OP_FUSED_GRADS, r0});
     int rc = upload_rows<T>(m, r0, rows, stream);
     if (rc) return rc;
-    return execute<T>(m, (7LL << 40) | ((long long)n << 1), seq, stream);
+    return execute<T>(m, (7LL << 40) | ((long long)n << 1) | (act ? 1 : 0), seq, stream);
 }
 
 template <typename T>
@@ -1006,8 +1010,9 @@ int do_step_backward(gsim_model* m, const gsim_params* p, gsim_state s, gsim_sta
     const int64_t r0 = region_misc(m);
     if ((rc = upload_rows<T>(m, r0, rows, stream))) return rc;
     if (m->exec == GSIM_EXEC_FUSED) {
-        std::vector<Launch> fseq{{OP_FUSED_PARAMS, r0}, {OP_FUSED_ADJ, r0}, {OP_FUSED_GRADS, r0}};
-        return execute<T>(m, 9LL << 40, fseq, stream);
+        const bool act = g && (g->act || g->hact);
+        std::vector<Launch> fseq{{OP_FUSED_PARAMS, r0}, {act ? OP_FUSED_ADJ_ACT : OP_FUSED_ADJ, r0}, {OP_FUSED_GRADS, r0}};
+        return execute<T>(m, (9LL << 40) | (act ? 1 : 0), fseq, stream);
     }
     std::vector<Launch> seq;
     if (g && g->contact) seq.push_back({OP_FILL_CPART, r0});

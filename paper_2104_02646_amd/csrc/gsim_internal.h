@@ -162,9 +162,10 @@ int launch_loss(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, 
 template <typename T>
 int launch_fused_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t* order, int n_bodies, size_t lds,
                      void* stream);
+// act: the variant that also accumulates the actuation gradients
 template <typename T>
 int launch_fused_adj(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t* order, int n_bodies, size_t lds,
-                     void* stream);
+                     bool act, void* stream);
 // two-pass element tiles: at most ETILE consecutive elements of one kind of one
 // body, and at most ETILE_WORDS words of adjoint LDS (8 per tile particle, 4 per
 // corner)

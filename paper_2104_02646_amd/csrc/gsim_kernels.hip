@@ -23,6 +23,8 @@
 // algorithm against the FP64 oracle independently of FP32 rounding.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "gsim_internal.h"
 
 namespace gsim {
@@ -921,14 +923,19 @@ __device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, HinRec<T>&
 // load issued after the previous element's store.
 template <typename T>
 struct TetRecA : TetRec<T> {
-    T gmu, glam, gact;
+    T gmu, glam;
 };
 template <typename T>
 struct TriRecA : TriRec<T> {
     T gk;
 };
+// with the actuation gradients (only in the variant launched when they are requested)
 template <typename T>
-struct HinRecA : HinRec<T> {
+struct TetRecAct : TetRecA<T> {
+    T gact;
+};
+template <typename T>
+struct HinRecAct : HinRec<T> {
     T gact;
 };
 template <typename T>
@@ -936,6 +943,10 @@ __device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, TetRecA<T>
     load_rec(M, e, static_cast<TetRec<T>&>(r));
     r.gmu = gld(M.f_g, e);
     r.glam = gld(M.f_g, M.ne + e);
+}
+template <typename T>
+__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, TetRecAct<T>& r) {
+    load_rec(M, e, static_cast<TetRecA<T>&>(r));
     r.gact = gld(M.f_g, 2 * M.ne + e);
 }
 template <typename T>
@@ -944,7 +955,7 @@ __device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, TriRecA<T>
     r.gk = gld(M.f_gk, e);
 }
 template <typename T>
-__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, HinRecA<T>& r) {
+__device__ __forceinline__ void load_rec(const ModelDev<T>& M, int e, HinRecAct<T>& r) {
     load_rec(M, e, static_cast<HinRec<T>&>(r));
     r.gact = gld(M.f_gh, e);
 }
@@ -1127,10 +1138,14 @@ __global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>
 // Adjoint steps t0 + nsteps - 1 .. t0 of one body.  The state at t0 is (S.x, S.v),
 // later states come from S.seg_in.  The adjoint state is carried in S.xbo / S.vbo
 // (each particle's entries are touched only by its own thread).
-template <typename T>
+// ACT: also accumulate the tet / hinge actuation gradients (the variant launched
+// only when the call requests them, so the other one moves no bytes for them).
+template <typename T, bool ACT>
 __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>* __restrict__ md,
                                                                const StepDev<T>* __restrict__ sd,
                                                                const int32_t* __restrict__ order) {
+    using TetR = typename std::conditional<ACT, TetRecAct<T>, TetRecA<T>>::type;
+    using HinR = typename std::conditional<ACT, HinRecAct<T>, HinRec<T>>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     const ModelDev<T>& M = md[0];
     const StepDev<T>& S = sd[0];
@@ -1145,8 +1160,8 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
     stage_colour_bounds(M, B, reinterpret_cast<int32_t*>(acc + 4 * npb), cb);
     const T dt = B.dt;
     const bool contact = B.contact_on != 0;
-    const bool want_e = S.g_mu != nullptr || S.g_lam != nullptr || S.g_act != nullptr,
-               want_k = S.g_ktri != nullptr, want_h = S.g_hact != nullptr;
+    const bool want_e = S.g_mu != nullptr || S.g_lam != nullptr || (ACT && S.g_act != nullptr),
+               want_k = S.g_ktri != nullptr, want_h = ACT && S.g_hact != nullptr;
     T pl[4], cp[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -1169,8 +1184,8 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
             acc[3 * npb + li] = T(0);
         }
         __syncthreads();
-        colour_sweep<FUSED_AHEAD_ADJ, 4, true, T, TetRecA<T>>(M, cb[0], B.ncol[0], acc, npb,
-                                                          [&](int e, const TetRecA<T>& r, bool valid, Contrib<T, 4>& o) {
+        colour_sweep<FUSED_AHEAD_ADJ, 4, true, T, TetR>(M, cb[0], B.ncol[0], acc, npb,
+                                                    [&](int e, const TetR& r, bool valid, Contrib<T, 4>& o) {
             V3<T> x[4], f[4], fb[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -1185,7 +1200,7 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
             if (want_e && valid) {
                 gst(M.f_g, e, r.gmu + gmu);
                 gst(M.f_g, M.ne + e, r.glam + glam);
-                gst(M.f_g, 2 * M.ne + e, r.gact + gact);
+                if constexpr (ACT) gst(M.f_g, 2 * M.ne + e, r.gact + gact);
             }
         });
         colour_sweep<FUSED_AHEAD_ADJ, 3, true, T, TriRecA<T>>(M, cb[1], B.ncol[1], acc, npb,
@@ -1203,8 +1218,8 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
             for (int q = 0; q < 3; ++q) o.w[q] = dot(f[q], fb[q]);
             if (want_k && valid) gst(M.f_gk, e, r.gk + gk);
         });
-        colour_sweep<FUSED_AHEAD_ADJ, 4, true, T, HinRecA<T>>(M, cb[2], B.ncol[2], acc, npb,
-                                                          [&](int e, const HinRecA<T>& r, bool valid, Contrib<T, 4>& o) {
+        colour_sweep<FUSED_AHEAD_ADJ, 4, true, T, HinR>(M, cb[2], B.ncol[2], acc, npb,
+                                                    [&](int e, const HinR& r, bool valid, Contrib<T, 4>& o) {
             V3<T> x[4], f[4], fb[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -1216,7 +1231,8 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
             hinge_adjoint(x, r.phi0, B.kb, r.act, fb, f, o.v, gact);
 #pragma unroll
             for (int q = 0; q < 4; ++q) o.w[q] = dot(f[q], fb[q]);
-            if (want_h && valid) gst(M.f_gh, e, r.gact + gact);
+            if constexpr (ACT)
+                if (want_h && valid) gst(M.f_gh, e, r.gact + gact);
         });
         // contact adjoint and the integrator's adjoint on the workgroup's own particles
         T gc[4] = {T(0), T(0), T(0), T(0)};
@@ -1378,23 +1394,39 @@ int launch_fused_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t*
     hipLaunchKernelGGL(k_fused_fwd<T>, dim3(n_bodies), dim3(FUSED_FWD_BLOCK), lds, (hipStream_t)stream, md, sd, order);
     return check_launch();
 }
+template <typename T, bool ACT>
+int launch_fused_adj_v(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t* order, int n_bodies, size_t lds,
+                       void* stream) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused_adj<T, ACT>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_fused_adj<T, ACT>), dim3(n_bodies), dim3(FUSED_ADJ_BLOCK), lds, (hipStream_t)stream, md, sd,
+                       order);
+    return check_launch();
+}
 template <typename T>
 int launch_fused_adj(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t* order, int n_bodies, size_t lds,
-                     void* stream) {
+                     bool act, void* stream) {
     if (n_bodies <= 0) return 0;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fused_adj<T>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    hipLaunchKernelGGL(k_fused_adj<T>, dim3(n_bodies), dim3(FUSED_ADJ_BLOCK), lds, (hipStream_t)stream, md, sd, order);
-    return check_launch();
+    return act ? launch_fused_adj_v<T, true>(md, sd, order, n_bodies, lds, stream)
+               : launch_fused_adj_v<T, false>(md, sd, order, n_bodies, lds, stream);
 }
 
 template <typename T>
 hipError_t fused_static_lds(bool adjoint, size_t* bytes) {
-    hipFuncAttributes a;
-    const void* f = adjoint ? reinterpret_cast<const void*>(&k_fused_adj<T>) : reinterpret_cast<const void*>(&k_fused_fwd<T>);
-    const hipError_t e = hipFuncGetAttributes(&a, f);
-    *bytes = e == hipSuccess ? a.sharedSizeBytes : 0;
-    return e;
+    *bytes = 0;
+    const void* fs[2] = {reinterpret_cast<const void*>(&k_fused_fwd<T>), nullptr};
+    if (adjoint) {
+        fs[0] = reinterpret_cast<const void*>(&k_fused_adj<T, false>);
+        fs[1] = reinterpret_cast<const void*>(&k_fused_adj<T, true>);
+    }
+    for (const void* f : fs) {
+        if (!f) continue;
+        hipFuncAttributes a;
+        const hipError_t e = hipFuncGetAttributes(&a, f);
+        if (e != hipSuccess) return e;
+        if (a.sharedSizeBytes > *bytes) *bytes = a.sharedSizeBytes;
+    }
+    return hipSuccess;
 }
 template <typename T>
 int launch_fused_params(const ModelDev<T>* md, const StepDev<T>* sd, void* stream) {
@@ -1416,7 +1448,7 @@ int launch_fused_grads(const ModelDev<T>* md, const StepDev<T>* sd, void* stream
     template int launch_contact_reduce<T>(const ModelDev<T>*, const StepDev<T>*, int, void*);                       \
     template int launch_loss<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, int, void*);     \
     template int launch_fused_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const int32_t*, int, size_t, void*);     \
-    template int launch_fused_adj<T>(const ModelDev<T>*, const StepDev<T>*, const int32_t*, int, size_t, void*);     \
+    template int launch_fused_adj<T>(const ModelDev<T>*, const StepDev<T>*, const int32_t*, int, size_t, bool, void*); \
     template int launch_fused_params<T>(const ModelDev<T>*, const StepDev<T>*, void*);                               \
     template int launch_fused_grads<T>(const ModelDev<T>*, const StepDev<T>*, void*);                               \
     template hipError_t fused_static_lds<T>(bool, size_t*);

@@ -239,7 +239,7 @@ def test_simrollout_actuation_grad(gs, oracle_lib):
     loss.backward()
     orc = oracle_for(oracle_lib, body)
     _, L_ref, per, _ = _oracle_per_step(orc, body.params(), acts, body.x0, body.v0, target)
-    assert abs(float(loss) - L_ref) / L_ref < 1e-3
+    assert abs(float(loss.detach()) - L_ref) / L_ref < 1e-3
     for k in ("act", "hact"):
         assert p[k].grad.shape == (T, per[k].shape[1])
         assert rel(_np(p[k].grad), per[k]) < 1e-3, k

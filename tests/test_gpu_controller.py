@@ -125,13 +125,15 @@ def test_control_task_gradient(gs, oracle_lib, which, dtype, tol):
 
 
 def test_control_task_first_order_decrease(gs):
-    """The gradient is useful, not only correct: 200 steps of the gear driven by the
+    """The gradient is useful, not only correct: 60 steps of the gear driven by the
     controller, loss = squared distance of its centre of mass to a point 5 cm to the
     side; a step of length h against dL/dW lowers the loss by h |dL/dW| to first order
-    (checked for two step lengths: the decrease matches within 10% and halves with h)."""
+    (two step lengths: the decrease matches within 2% and halves with h).  Over 200
+    steps the same loss is not locally linear at any step length (the FP64 oracle
+    shows it too): stick-slip switches along the way dominate its gradient."""
     from paper_2104_02646_amd.autograd import controller, rollout
     body = W.gear()
-    T, omega, scale = 200, 2 * np.pi * 4.0, 0.2
+    T, omega, scale = 60, 2 * np.pi * 4.0, 0.2
     m = gs.Model([body], torch.float64, max_steps=T, ckpt_every=20)
     base = m.params_from_bodies()
     goal = torch.as_tensor(body.X.mean(0) + np.array([0.05, 0.0, 0.0]), dtype=torch.float64, device="cuda")
@@ -151,6 +153,6 @@ def test_control_task_first_order_decrease(gs):
         with torch.no_grad():
             L1 = float(loss_of(Wd.detach() - h * g / gn))
         drops.append(float(L0) - L1)
-        print("step %.0e: loss %.6e -> %.6e, predicted drop %.3e, actual %.3e" % (h, float(L0), L1, h * gn, drops[-1]))
-        assert abs(drops[-1] - h * gn) < 0.1 * h * gn
-    assert abs(drops[0] / drops[1] - 2.0) < 0.2
+        print("step %.0e: loss %.9e -> %.9e, predicted drop %.4e, actual %.4e" % (h, float(L0), L1, h * gn, drops[-1]))
+        assert abs(drops[-1] - h * gn) < 0.02 * h * gn
+    assert abs(drops[0] / drops[1] - 2.0) < 0.04
