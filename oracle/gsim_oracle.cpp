@@ -318,6 +318,31 @@ V3<S> contact_force(const V3<S>& x, const V3<S>& v, const double nrm[4], S ke, S
     return fn + ff;
 }
 
+/* Air force on one cloth triangle (App. A.1 thin shells: a lift/drag model of the
+ * surrounding air; the paper gives no formula, reading R20).  Still air; u is the
+ * mean corner velocity, n the unit normal, A the current area, s = n.u:
+ *   drag  F_d = -k_d A |s| u                          (quadratic, projected area)
+ *   lift  F_l = -k_l A s (|u|^2 n - s u) / |u|          (flat plate: perpendicular
+ *         to u, magnitude k_l A |u|^2 sin(2 a) / 2 for the angle a between u and
+ *         the plate; F_l = 0 at u = 0, where it and its Jacobian vanish)
+ * and each corner receives (F_d + F_l) / 3. */
+template <class S>
+void air_force(const V3<S> x[3], const V3<S> v[3], S kd, S kl, V3<S> f[3]) {
+    V3<S> N = cross(x[1] - x[0], x[2] - x[0]);
+    S nn = norm(N);
+    V3<S> n = N * (1.0 / nn);
+    S A = 0.5 * nn;
+    V3<S> u = (v[0] + v[1] + v[2]) * (1.0 / 3.0);
+    S s = dot(n, u);
+    S q = dot(u, u);
+    V3<S> F = u * (-(kd * A * fabs(s)));
+    if (val(q) > 0.0) {
+        S r = sqrt(q);
+        F = F + (n * q - u * s) * (-(kl * A * s / r));
+    }
+    for (int i = 0; i < 3; ++i) f[i] = F * (1.0 / 3.0);
+}
+
 /* One-sided quadratic contact potential k_e C^2 / 2 (its negative gradient is
  * the elastic part of f_n). */
 double contact_energy(const V3<double>& x, const double nrm[4], double ke) {
@@ -337,6 +362,7 @@ struct Model {
     std::vector<unsigned char> pinned;
     double g[3];
     int ground;
+    int air;  /* lift/drag on the triangles */
     double plane[4];
     double dt;
     int status;
@@ -353,12 +379,14 @@ typedef struct {
     const double *mass;           /* [np] */
     double kb;                    /* bending stiffness (per body) */
     double ke, kd, kf, muf;       /* contact parameters */
+    double kdrag, klift;          /* air force coefficients (used when the model has air on) */
 } oc_params;
 
 typedef struct {
     double *mu, *lam, *act, *ktri, *hact, *mass; /* NULL = not requested */
     double kb;
     double contact[4]; /* ke, kd, kf, muf */
+    double air[2];     /* kdrag, klift */
 } oc_grads;
 
 }  // extern "C"
@@ -385,6 +413,12 @@ void total_force(const Model* m, const oc_params* p, const double* x, const doub
         for (int k = 0; k < 3; ++k) xe[k] = load3(&x[3 * id[k]]);
         tri_force<double>(xe, &m->triDmInv[4 * t], m->triA[t], p->ktri[t], fe);
         for (int k = 0; k < 3; ++k) add3(&f[3 * id[k]], fe[k]);
+        if (m->air) {
+            V3<double> ve[3];
+            for (int k = 0; k < 3; ++k) ve[k] = load3(&v[3 * id[k]]);
+            air_force<double>(xe, ve, p->kdrag, p->klift, fe);
+            for (int k = 0; k < 3; ++k) add3(&f[3 * id[k]], fe[k]);
+        }
     }
     for (int h = 0; h < m->nh; ++h) {
         const int* id = &m->hinge[4 * h];
@@ -476,6 +510,22 @@ void force_vjp(const Model* m, const oc_params* p, const double* x, const double
         for (int s = 0; s < ND; ++s) pb[s] = 0.0;
         apply_transpose<3>(fe, id, fbar, xbar, pb);
         if (g && g->ktri) g->ktri[t] += pb[9];
+        if (m->air) {
+            /* two passes: positions and the coefficients, then velocities */
+            V3<Dual> ve[3];
+            for (int c = 0; c < 3; ++c) ve[c] = mk<Dual>(Dual(v[3 * id[c]]), Dual(v[3 * id[c] + 1]), Dual(v[3 * id[c] + 2]));
+            air_force<Dual>(xe, ve, dvar(p->kdrag, 9), dvar(p->klift, 10), fe);
+            for (int s = 0; s < ND; ++s) pb[s] = 0.0;
+            apply_transpose<3>(fe, id, fbar, xbar, pb);
+            if (g) {
+                g->air[0] += pb[9];
+                g->air[1] += pb[10];
+            }
+            for (int c = 0; c < 3; ++c) xe[c] = mk<Dual>(Dual(x[3 * id[c]]), Dual(x[3 * id[c] + 1]), Dual(x[3 * id[c] + 2]));
+            seed_positions<3>(v, id, ve);
+            air_force<Dual>(xe, ve, Dual(p->kdrag), Dual(p->klift), fe);
+            apply_transpose<3>(fe, id, fbar, vbar, pb);
+        }
     }
     for (int h = 0; h < m->nh; ++h) {
         const int* id = &m->hinge[4 * h];
@@ -557,6 +607,7 @@ void* oc_create(int np, int ne, int nt, int nh, const double* X, const int* tet,
     if (pinned) for (int i = 0; i < np; ++i) m->pinned[i] = pinned[i] ? 1 : 0;
     for (int c = 0; c < 3; ++c) m->g[c] = gravity[c];
     m->ground = ground;
+    m->air = 0;
     for (int c = 0; c < 4; ++c) m->plane[c] = plane ? plane[c] : (c == 1 ? 1.0 : 0.0);
     m->dt = dt;
     m->status = 0;
@@ -594,6 +645,8 @@ void* oc_create(int np, int ne, int nt, int nh, const double* X, const int* tet,
 }
 
 int oc_status(void* h) { return static_cast<Model*>(h)->status; }
+/* Switches the lift/drag force on the triangles on (nonzero) or off. */
+void oc_set_air(void* h, int on) { static_cast<Model*>(h)->air = on ? 1 : 0; }
 void oc_free(void* h) { delete static_cast<Model*>(h); }
 
 /* Rest data as computed by the oracle (for inspection in tests). */
@@ -720,6 +773,12 @@ int oc_force_jvp(void* h, const oc_params* p, const oc_params* dp, const double*
         for (int k = 0; k < 3; ++k) xe[k] = xp(id[k]);
         tri_force<Dual>(xe, &m->triDmInv[4 * t], m->triA[t], tang(p->ktri[t], opt(dp->ktri, t)), fe);
         for (int k = 0; k < 3; ++k) fd[id[k]] = fd[id[k]] + fe[k];
+        if (m->air) {
+            V3<Dual> ve[3];
+            for (int k = 0; k < 3; ++k) ve[k] = vp(id[k]);
+            air_force<Dual>(xe, ve, tang(p->kdrag, dp->kdrag), tang(p->klift, dp->klift), fe);
+            for (int k = 0; k < 3; ++k) fd[id[k]] = fd[id[k]] + fe[k];
+        }
     }
     for (int q = 0; q < m->nh; ++q) {
         const int* id = &m->hinge[4 * q];
@@ -813,6 +872,20 @@ double oc_hinge_angle1(const double* x) {
     unpack(x, 4, xe);
     return hinge_angle<double>(xe);
 }
+void oc_air_force1(const double* x, const double* v, double kd, double kl, double* f) {
+    V3<double> xe[3], ve[3], fe[3];
+    for (int k = 0; k < 3; ++k) {
+        xe[k] = load3(&x[3 * k]);
+        ve[k] = load3(&v[3 * k]);
+    }
+    air_force<double>(xe, ve, kd, kl, fe);
+    for (int k = 0; k < 3; ++k) {
+        f[3 * k] = fe[k].x;
+        f[3 * k + 1] = fe[k].y;
+        f[3 * k + 2] = fe[k].z;
+    }
+}
+
 void oc_hinge_force1(const double* x, double phi0, double kb, double act, double* f) {
     V3<double> xe[4], fe[4];
     unpack(x, 4, xe);

@@ -42,12 +42,12 @@ _up = C.POINTER(C.c_ubyte)
 class _Params(C.Structure):
     _fields_ = [("mu", _dp), ("lam", _dp), ("act", _dp), ("ktri", _dp), ("hact", _dp), ("mass", _dp),
                 ("kb", C.c_double), ("ke", C.c_double), ("kd", C.c_double), ("kf", C.c_double),
-                ("muf", C.c_double)]
+                ("muf", C.c_double), ("kdrag", C.c_double), ("klift", C.c_double)]
 
 
 class _Grads(C.Structure):
     _fields_ = [("mu", _dp), ("lam", _dp), ("act", _dp), ("ktri", _dp), ("hact", _dp), ("mass", _dp),
-                ("kb", C.c_double), ("contact", C.c_double * 4)]
+                ("kb", C.c_double), ("contact", C.c_double * 4), ("air", C.c_double * 2)]
 
 
 _lib = None
@@ -62,6 +62,7 @@ def _load():
         lib.oc_create.restype = C.c_void_p
         lib.oc_create.argtypes = [C.c_int] * 4 + [_dp, _ip, _ip, _ip, _up, _dp, C.c_int, _dp, C.c_double]
         lib.oc_status.argtypes = [C.c_void_p]
+        lib.oc_set_air.argtypes = [C.c_void_p, C.c_int]
         lib.oc_free.argtypes = [C.c_void_p]
         lib.oc_rest_data.argtypes = [C.c_void_p, _dp, _dp, _dp]
         P = C.POINTER(_Params)
@@ -90,6 +91,7 @@ def _load():
         lib.oc_hinge_angle1.argtypes = [_dp]
         lib.oc_hinge_force1.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp]
         lib.oc_contact_force1.argtypes = [_dp, _dp, _dp] + [C.c_double] * 4 + [_dp]
+        lib.oc_air_force1.argtypes = [_dp, _dp, C.c_double, C.c_double, _dp]
         _lib = lib
     return _lib
 
@@ -149,6 +151,15 @@ def hinge_force(x, phi0, kb, act=0.0):
     return f
 
 
+def air_force(x, v, kdrag, klift):
+    """Corner forces [3,3] of the lift/drag model on one triangle (corner positions
+    x [3,3], velocities v [3,3])."""
+    lib = _load()
+    x = _f64(x, (3, 3)); v = _f64(v, (3, 3)); f = np.zeros((3, 3))
+    lib.oc_air_force1(_ptr(x), _ptr(v), kdrag, klift, _ptr(f))
+    return f
+
+
 def contact_force(x, v, plane, ke, kd, kf, muf):
     lib = _load()
     x = _f64(x, (3,)); v = _f64(v, (3,)); pl = _f64(plane, (4,)); f = np.zeros(3)
@@ -163,10 +174,11 @@ def contact_force(x, v, plane, ke, kd, kf, muf):
 class Oracle:
     """One body: topology, rest shape, environment.  Parameters are passed per call
     as a dict with keys mu, lam, act, ktri, hact, mass (arrays) and kb, ke, kd, kf,
-    muf (scalars); missing arrays mean zero actuation / no such elements."""
+    muf, kdrag, klift (scalars); missing arrays mean zero actuation / no such
+    elements.  air=True adds the lift/drag force to every triangle."""
 
     def __init__(self, X, tets=None, tris=None, hinges=None, pinned=None, gravity=(0.0, -9.81, 0.0),
-                 ground=False, plane=(0.0, 1.0, 0.0, 0.0), dt=1.0 / 600.0):
+                 ground=False, plane=(0.0, 1.0, 0.0, 0.0), dt=1.0 / 600.0, air=False):
         lib = _load()
         self.X = _f64(X).reshape(-1, 3)
         self.np = self.X.shape[0]
@@ -184,6 +196,8 @@ class Oracle:
                                 self.hinges.ctypes.data_as(_ip), self.pinned.ctypes.data_as(_up),
                                 _ptr(self.gravity), int(self.ground), _ptr(self.plane), self.dt)
         self.status = lib.oc_status(self._h)
+        self.air = bool(air)
+        lib.oc_set_air(self._h, int(self.air))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -207,6 +221,7 @@ class Oracle:
         s.ktri = arr("ktri", self.nt); s.hact = arr("hact", self.nh); s.mass = arr("mass", self.np)
         s.kb = float(p.get("kb", 0.0)); s.ke = float(p.get("ke", 0.0)); s.kd = float(p.get("kd", 0.0))
         s.kf = float(p.get("kf", 0.0)); s.muf = float(p.get("muf", 0.0))
+        s.kdrag = float(p.get("kdrag", 0.0)); s.klift = float(p.get("klift", 0.0))
         return s, keep
 
     def _grads(self, want):
@@ -225,6 +240,7 @@ class Oracle:
     def _collect(g, out):
         out["kb"] = g.kb
         out["contact"] = np.array(list(g.contact))  # ke, kd, kf, muf
+        out["air"] = np.array(list(g.air))  # kdrag, klift
         return out
 
     # -- API -------------------------------------------------------------------

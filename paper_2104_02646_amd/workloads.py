@@ -17,6 +17,7 @@ App. B, with every constant the paper leaves open written out here):
 * ``large_blob``     ~200k tets voxelised from a sum-of-5-spheres implicit blob
 * ``serving_trace``  Poisson stream of tet / cloth gradient queries
 * ``gear``, ``walker``  actuated bodies of the control tasks (1152 / 168 tets)
+* ``control_cloth``  free cloth under lift/drag (72 .. 2048 triangles)
 """
 from __future__ import annotations
 
@@ -209,6 +210,9 @@ class Body:
     kd: float = 0.0
     kf: float = 0.0
     muf: float = 0.0
+    air: bool = False        # lift/drag on the triangles
+    kdrag: float = 0.0
+    klift: float = 0.0
     gravity: tuple = GRAVITY
     ground: bool = False
     plane: tuple = GROUND
@@ -245,6 +249,9 @@ class Body:
     def params(self):
         """Parameter dict (the keys the oracle and the binding both accept)."""
         p = {"mass": self.mass, "kb": self.kb, "ke": self.ke, "kd": self.kd, "kf": self.kf, "muf": self.muf}
+        if self.air:
+            p["kdrag"] = self.kdrag
+            p["klift"] = self.klift
         if self.ne:
             p["mu"] = self.mu
             p["lam"] = self.lam
@@ -267,7 +274,7 @@ class Body:
         r = lambda a: None if a is None else np.asarray(a, dtype).astype(np.float64)
         for k in ("X", "mu", "lam", "ktri", "mass", "x0", "v0", "target"):
             setattr(b, k, r(getattr(self, k)))
-        for k in ("kb", "ke", "kd", "kf", "muf", "dt"):
+        for k in ("kb", "ke", "kd", "kf", "muf", "kdrag", "klift", "dt"):
             setattr(b, k, float(np.asarray(getattr(self, k), dtype)))
         b.gravity = tuple(float(np.asarray(g, dtype)) for g in self.gravity)
         b.plane = tuple(float(np.asarray(g, dtype)) for g in self.plane)
@@ -322,6 +329,29 @@ def cloth(seed: int = 10, n: int = 64, size: float = 2.0, height: float = 1.0, m
     ktri = rng.uniform(1e3, 1e4, len(tris))
     return Body(X=X, tris=tris, hinges=hinges, pinned=pinned, ktri=ktri, mass=np.full(len(X), mass), kb=kb,
                 ground=False, dt=1e-3)
+
+
+def control_cloth(seed: int = 60, n: int | None = None, kdrag: float = 2.0, klift: float = 2.0):
+    """Free cloth under lift/drag for the control-cloth task (Sec. 5.3: a random cloth
+    of 64 to 2048 triangles is thrown towards a target; its initial velocity is
+    optimised under nonlinear lift/drag).  n x n grid, n ~ U{7..33} unless given
+    (2 (n-1)^2 = 72 .. 2048 triangles), side 0.5 m, 1.5 m above the ground plane
+    (no contact: the task ends in the air), membrane k_t ~ U(1e3, 1e4), bending
+    k_b = 0.01, particle mass 0.1 kg, gravity, air k_drag, k_lift, dt = 1e-3.
+    Start: tilted 20 degrees about x, thrown with v0 = (2, 3, 0) m/s plus a seeded
+    per-particle perturbation N(0, 0.1^2)."""
+    rng = np.random.default_rng(seed)
+    if n is None:
+        n = int(rng.integers(7, 34))
+    X, tris, hinges = cloth_grid(n, 0.5 / (n - 1), 0.0)
+    a = np.deg2rad(20.0)
+    X = X - X.mean(0)
+    X = X @ np.array([[1, 0, 0], [0, np.cos(a), -np.sin(a)], [0, np.sin(a), np.cos(a)]]).T
+    X[:, 1] += 1.5
+    ktri = rng.uniform(1e3, 1e4, len(tris))
+    v0 = np.tile([2.0, 3.0, 0.0], (len(X), 1)) + rng.normal(0.0, 0.1, X.shape)
+    return Body(X=X, tris=tris, hinges=hinges, ktri=ktri, mass=np.full(len(X), 0.1), kb=0.01, ground=False,
+                air=True, kdrag=kdrag, klift=klift, dt=1e-3, x0=X.copy(), v0=v0)
 
 
 def redraw_cloth_params(body: Body, seed: int):

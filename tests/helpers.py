@@ -7,7 +7,7 @@ from paper_2104_02646_amd import workloads as W
 
 def oracle_for(o, body):
     return o.Oracle(body.X, tets=body.tets, tris=body.tris, hinges=body.hinges, pinned=body.pinned,
-                    gravity=body.gravity, ground=body.ground, plane=body.plane, dt=body.dt)
+                    gravity=body.gravity, ground=body.ground, plane=body.plane, dt=body.dt, air=body.air)
 
 
 def rel(a, b):
