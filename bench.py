@@ -76,9 +76,9 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
 # WRITE_SIZE by 1.0, the factors a 1 GiB copy gives).  They hold for the kernel
 # source with this SHA-1 only; for any other source the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "source_sha1": "8f37f605288640bf1c5c23c05aa3378560926e6d",
+    "source_sha1": "8259fb00d5f60975a4799fc07c530e9eaf4e7ddf",
     "workload": (256, 100, 10),
-    "per_launch": {"element_fwd": 114.06e6, "particle_fwd": 30.54e6, "element_adj": 144.93e6,
+    "per_launch": {"element_fwd": 114.07e6, "particle_fwd": 30.54e6, "element_adj": 144.95e6,
                    "particle_adj": 37.26e6},
 }
 

@@ -100,6 +100,8 @@ typedef struct {
     const double* ground;              /* [n_bodies][4] plane n.x = d as (nx, ny, nz, d), or NULL */
     const uint8_t* contact_on;         /* [n_bodies] nonzero = ground contact active, or NULL (off) */
     const double* k_bend;              /* [n_bodies] bending stiffness, or NULL (0) */
+    const uint8_t* air_on;             /* [n_bodies] nonzero = lift/drag on the body's triangles
+                                          (see gsim_params.air), or NULL (off) */
 } gsim_model_desc;
 
 typedef struct gsim_plan gsim_plan;    /* host object: validated topology, rest data, tiles */
@@ -226,7 +228,18 @@ typedef struct {
     const void* hact;    /* [n_hinges] hinge actuation, NULL = 0              */
     int64_t act_stride;  /* elements between consecutive steps' act arrays (>= 0) */
     int64_t hact_stride; /* same for hact */
+    const void* air;     /* [n_bodies][2] = k_drag, k_lift (required if any body has air_on) */
 } gsim_params;
+
+/* Air (App. A.1 thin shells: a lift/drag model of the surrounding air, whose form
+ * the paper leaves open).  On each triangle of a body with air_on, with u the
+ * mean of its corner velocities (still air), n its unit normal, A its area and
+ * s = n.u, the force F = -A (k_drag |s| u + k_lift s (|u|^2 n - s u) / |u|)
+ * (quadratic drag on the projected area plus flat-plate lift perpendicular to u;
+ * F = 0 at u = 0) is shared equally by its three corners.  k_drag and k_lift
+ * are inputs only: no gradient is produced for them.  The position and velocity
+ * adjoints include the force's dependence on both.  The fused path does not
+ * model air (GSIM_E_UNSUPPORTED). */
 
 /* Gradients accumulate (+=).  The actuation gradients of step t go to
  * act + t * act_stride (hact + t * hact_stride): with a stride of 0 every

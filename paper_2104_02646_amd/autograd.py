@@ -15,6 +15,7 @@ import torch
 from . import gsim
 
 _PARAM_KEYS = ("mu", "lam", "ktri", "mass", "contact", "act", "hact")
+_INPUT_KEYS = ("air",)  # inputs without a gradient
 
 
 class SimRollout(torch.autograd.Function):
@@ -22,14 +23,17 @@ class SimRollout(torch.autograd.Function):
 
     States are SoA [3, n_particles]; contact is [n_bodies, 4] = (k_e, k_d, k_f, mu_f);
     act / hact (tet / hinge actuation) are [n] for one value over the whole rollout
-    or [n_steps, n] for a value per step, and their gradients have the same shape.
-    Pass None for parameters the model does not have (mu/lam without tets, ktri
-    without triangles) or does not actuate."""
+    or [n_steps, n] for a value per step, and their gradients have the same shape;
+    air [n_bodies, 2] = (k_drag, k_lift) of bodies with lift/drag is an input
+    without a gradient.  Pass None for parameters the model does not have
+    (mu/lam without tets, ktri without triangles) or does not actuate."""
 
     @staticmethod
-    def forward(ctx, model, n_steps, x0, v0, mu, lam, ktri, mass, contact, act, hact):
+    def forward(ctx, model, n_steps, x0, v0, mu, lam, ktri, mass, contact, act, hact, air):
         vals = (mu, lam, ktri, mass, contact, act, hact)
         params = {k: v.detach().contiguous() for k, v in zip(_PARAM_KEYS, vals) if v is not None}
+        if air is not None:
+            params["air"] = air.detach().contiguous()
         ckpt = model.new_checkpoints()
         xT, vT = model.rollout(params, x0.detach().contiguous(), v0.detach().contiguous(), int(n_steps), ckpt=ckpt)
         ctx.model, ctx.n_steps, ctx.params, ctx.ckpt = model, int(n_steps), params, ckpt
@@ -44,12 +48,12 @@ class SimRollout(torch.autograd.Function):
         grads = {k: torch.zeros_like(ctx.params[k]) for k, p in zip(_PARAM_KEYS, ctx.present) if p}
         xb0, vb0 = m.rollout_backward(ctx.params, ctx.n_steps, gx, gv, grads, ckpt=ctx.ckpt)
         out = [grads.get(k) if p else None for k, p in zip(_PARAM_KEYS, ctx.present)]
-        return (None, None, xb0, vb0, *out)
+        return (None, None, xb0, vb0, *out, None)
 
 
 def rollout(model, params, x0, v0, n_steps):
     """Differentiable rollout: params is a dict of (possibly requires_grad) tensors."""
-    return SimRollout.apply(model, n_steps, x0, v0, *(params.get(k) for k in _PARAM_KEYS))
+    return SimRollout.apply(model, n_steps, x0, v0, *(params.get(k) for k in _PARAM_KEYS + _INPUT_KEYS))
 
 
 class Controller(torch.autograd.Function):

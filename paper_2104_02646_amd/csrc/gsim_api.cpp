@@ -205,6 +205,10 @@ int build_tiles(gsim_plan* P) {
             std::vector<uint32_t>& code = kind == 0 ? P->tet_code : kind == 1 ? P->tri_code : P->hin_code;
             const int64_t n = kind == 0 ? P->ne : kind == 1 ? P->nt : P->nh;
             const int nc = kind == 1 ? 3 : 4;
+            // LDS words of the adjoint per tile particle and per corner (triangles with
+            // air also stage velocities and keep a velocity adjoint per corner)
+            const bool air = kind == 1 && P->air_on[b];
+            const int64_t wp = air ? 12 : 8, wc = air ? 8 : 4;
             int64_t e = off[b];
             while (e < off[b + 1]) {
                 const int32_t tile = (int32_t)P->etiles.size();
@@ -213,7 +217,7 @@ int build_tiles(gsim_plan* P) {
                 while (e < off[b + 1] && e - s < ETILE) {
                     int add = 0;
                     for (int c = 0; c < nc; ++c) add += mark[idx[c * n + e]] != tile;
-                    const int64_t words = 8 * (int64_t)(parts.size() + add) + 4 * (int64_t)nc * (e - s + 1);
+                    const int64_t words = wp * (int64_t)(parts.size() + add) + wc * (int64_t)nc * (e - s + 1);
                     if (e > s && words > ETILE_WORDS) break;
                     for (int c = 0; c < nc; ++c) {
                         const int32_t p = idx[c * n + e];
@@ -249,8 +253,8 @@ int build_tiles(gsim_plan* P) {
                 P->etiles.push_back(t);
                 P->tp_id.insert(P->tp_id.end(), parts.begin(), parts.end());
                 const int64_t corners = (int64_t)nc * (e - s);
-                P->etile_words[0] = std::max<int64_t>(P->etile_words[0], 4 * (int64_t)m + 4 * corners);
-                P->etile_words[1] = std::max<int64_t>(P->etile_words[1], 8 * (int64_t)m + 4 * corners);
+                P->etile_words[0] = std::max<int64_t>(P->etile_words[0], (air ? 8 : 4) * (int64_t)m + 4 * corners);
+                P->etile_words[1] = std::max<int64_t>(P->etile_words[1], wp * (int64_t)m + wc * corners);
                 if ((int64_t)P->tp_id.size() > INT32_MAX) return fail(GSIM_E_UNSUPPORTED, "too many tile particles");
             }
         }
@@ -342,6 +346,8 @@ int build_plan(const gsim_model_desc* d, gsim_plan* P) {
     P->plane.resize(4 * nb);
     P->kb.resize(nb);
     P->contact_on.assign(nb, 0);
+    P->air_on.assign(nb, 0);
+    P->any_air = false;
     for (int b = 0; b < nb; ++b) {
         P->dt[b] = d->dt[b];
         if (!(d->dt[b] > 0) || !finite(d->dt[b])) return fail(GSIM_E_INVALID, "dt of body %d must be > 0", b);
@@ -358,6 +364,8 @@ int build_plan(const gsim_model_desc* d, gsim_plan* P) {
         P->plane[4 * b + 3] = pl[3] / nn;
         P->kb[b] = d->k_bend ? d->k_bend[b] : 0.0;
         P->contact_on[b] = d->contact_on ? (d->contact_on[b] ? 1 : 0) : 0;
+        P->air_on[b] = d->air_on ? (d->air_on[b] ? 1 : 0) : 0;
+        P->any_air = P->any_air || P->air_on[b];
     }
 
     // element -> body checks
@@ -453,10 +461,10 @@ const int MIN_TILE = 64;  // smallest tile (block 64, 1 item): bounds the tile-l
 
 // (each launch lane pads its list to a multiple of N_XCD)
 int64_t tile_capacity(const gsim_plan* P, bool particles) {
-    if (!particles) return (int64_t)P->etiles.size() + MAX_LANES * N_XCD;  // element tiles are planned
+    if (!particles) return (int64_t)P->etiles.size() + 2 * MAX_LANES * N_XCD;  // element tiles are planned
     int64_t n = 0;
     for (int b = 0; b < P->nb; ++b) n += (P->poff[b + 1] - P->poff[b] + MIN_TILE - 1) / MIN_TILE;
-    return n + MAX_LANES * N_XCD;
+    return n + 2 * MAX_LANES * N_XCD;
 }
 
 
@@ -489,6 +497,7 @@ Layout make_layout(const gsim_plan* P, int max_steps) {
     L.pdeg = take(np * 4);
     L.pinned = take(np);
     L.slots = take(4 * std::max<int64_t>(P->nslot, 1) * sizeof(T));
+    L.vslots = P->any_air ? take(4 * std::max<int64_t>(P->nslot, 1) * sizeof(T)) : 0;
     L.cpart = take(4 * (cap_p + 1) * sizeof(T));
     L.lpart = take((cap_p + 1) * sizeof(T));
     L.fbuf = take(2 * 6 * np * sizeof(T));
@@ -572,21 +581,28 @@ int upload_tiles(gsim_model* m, void* stream) {
             load[l] += work(b);
         }
     }
-    auto by_lane = [&](const std::vector<Tile>& nat, int kind, int dummy, std::vector<Tile>& out, int* bounds) {
+    // per lane: the plain bodies' tiles, then the air bodies' (each group XCD-ordered)
+    auto by_lane = [&](const std::vector<Tile>& nat, int kind, int dummy, std::vector<Tile>& out, int* bounds,
+                       int* air_from) {
         out.clear();
         for (int l = 0; l <= MAX_LANES; ++l) bounds[l] = 0;
+        for (int l = 0; l < MAX_LANES; ++l) air_from[l] = 0;
         for (int l = 0; l < m->lanes; ++l) {
-            std::vector<Tile> mine, ord;
-            for (const Tile& t : nat)
-                if (lane[t.body] == l) mine.push_back(t);
-            int grid = 0;
-            xcd_order(mine, kind, dummy, ord, grid);
-            out.insert(out.end(), ord.begin(), ord.begin() + grid);
+            for (int air = 0; air < 2; ++air) {
+                std::vector<Tile> mine, ord;
+                for (const Tile& t : nat)
+                    if (lane[t.body] == l && (m->air_on[t.body] != 0) == (air != 0)) mine.push_back(t);
+                if (air) air_from[l] = (int)out.size();
+                if (mine.empty()) continue;
+                int grid = 0;
+                xcd_order(mine, kind, dummy, ord, grid);
+                out.insert(out.end(), ord.begin(), ord.begin() + grid);
+            }
             bounds[l + 1] = (int)out.size();
         }
     };
-    by_lane(m->etiles_nat, TILE_TET, 0, et, m->lane_e);
-    by_lane(m->ptiles_nat, TILE_PART, m->n_ptile_rows, pt, m->lane_p);
+    by_lane(m->etiles_nat, TILE_TET, 0, et, m->lane_e, m->lane_e_air);
+    by_lane(m->ptiles_nat, TILE_PART, m->n_ptile_rows, pt, m->lane_p, m->lane_p_air);
     m->n_etiles = m->lane_e[m->lanes];
     m->n_ptiles = m->lane_p[m->lanes];
     hipStream_t s = (hipStream_t)stream;
@@ -707,17 +723,35 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
         return GSIM_OK;
     };
     // one pass over lane l's tiles (l < 0: all tiles, one launch)
-    auto pass = [&](int l, const StepDev<T>* sd, bool adjoint) -> int {
-        const int e0 = l < 0 ? 0 : m->lane_e[l], e1 = l < 0 ? m->n_etiles : m->lane_e[l + 1];
-        const int p0 = l < 0 ? 0 : m->lane_p[l], p1 = l < 0 ? m->n_ptiles : m->lane_p[l + 1];
-        void* st = l > 0 ? (void*)m->lane_stream[l] : stream;
+    // One pass over the tile ranges [e0, e1) / [p0, p1) on stream st: element passes
+    // and the particle adjoint launch the plain tiles [x0, xa) and the air bodies'
+    // tiles [xa, x1) with their kernel variants (one launch when either is empty).
+    auto ranges = [&](int e0, int ea, int e1, int p0, int pa, int p1, void* st, const StepDev<T>* sd,
+                      bool adjoint) -> int {
+        const size_t wf = m->etile_words[0] * sizeof(T), wa = m->etile_words[1] * sizeof(T);
         if (!adjoint) {
-            LAUNCH_TRY(timed(m, 0, st, [&] { return launch_elem_fwd<T>(md, sd, c.et + e0, e1 - e0, m->block, m->etile_words[0] * sizeof(T), st); }), "element pass");
+            if (ea > e0) LAUNCH_TRY(timed(m, 0, st, [&] { return launch_elem_fwd<T>(md, sd, c.et + e0, ea - e0, m->block, wf, false, st); }), "element pass");
+            if (e1 > ea) LAUNCH_TRY(timed(m, 0, st, [&] { return launch_elem_fwd<T>(md, sd, c.et + ea, e1 - ea, m->block, wf, true, st); }), "element pass");
             LAUNCH_TRY(timed(m, 1, st, [&] { return launch_part_fwd<T>(md, sd, c.pt + p0, p1 - p0, m->pblock, m->pitems, st); }), "particle pass");
         } else {
-            LAUNCH_TRY(timed(m, 2, st, [&] { return launch_elem_adj<T>(md, sd, c.et + e0, e1 - e0, m->block, m->etile_words[1] * sizeof(T), st); }), "element adjoint");
-            LAUNCH_TRY(timed(m, 3, st, [&] { return launch_part_adj<T>(md, sd, c.pt + p0, p1 - p0, m->pblock, m->pitems, st); }), "particle adjoint");
+            if (ea > e0) LAUNCH_TRY(timed(m, 2, st, [&] { return launch_elem_adj<T>(md, sd, c.et + e0, ea - e0, m->block, wa, false, st); }), "element adjoint");
+            if (e1 > ea) LAUNCH_TRY(timed(m, 2, st, [&] { return launch_elem_adj<T>(md, sd, c.et + ea, e1 - ea, m->block, wa, true, st); }), "element adjoint");
+            if (pa > p0) LAUNCH_TRY(timed(m, 3, st, [&] { return launch_part_adj<T>(md, sd, c.pt + p0, pa - p0, m->pblock, m->pitems, false, st); }), "particle adjoint");
+            if (p1 > pa) LAUNCH_TRY(timed(m, 3, st, [&] { return launch_part_adj<T>(md, sd, c.pt + pa, p1 - pa, m->pblock, m->pitems, true, st); }), "particle adjoint");
         }
+        return GSIM_OK;
+    };
+    // one pass of lane l on its stream; l < 0: every lane on the caller's stream, as
+    // one launch per kernel when no body has air
+    auto pass = [&](int l, const StepDev<T>* sd, bool adjoint) -> int {
+        if (l >= 0)
+            return ranges(m->lane_e[l], m->lane_e_air[l], m->lane_e[l + 1], m->lane_p[l], m->lane_p_air[l],
+                          m->lane_p[l + 1], l > 0 ? (void*)m->lane_stream[l] : stream, sd, adjoint);
+        if (!m->any_air) return ranges(0, m->n_etiles, m->n_etiles, 0, m->n_ptiles, m->n_ptiles, stream, sd, adjoint);
+        for (int k = 0; k < m->lanes; ++k)
+            if (int rc = ranges(m->lane_e[k], m->lane_e_air[k], m->lane_e[k + 1], m->lane_p[k], m->lane_p_air[k],
+                                m->lane_p[k + 1], stream, sd, adjoint))
+                return rc;
         return GSIM_OK;
     };
     for (const Launch& l : seq) {
@@ -826,6 +860,7 @@ void fill_params(StepDev<T>& r, const gsim_params* p, const gsim_grads* g) {
     r.mass = (const T*)p->mass;
     r.contact = (const T*)p->contact;
     r.hact = (const T*)p->hact;
+    r.air = (const T*)p->air;
     if (g) {
         r.g_mu = (T*)g->mu;
         r.g_lam = (T*)g->lam;
@@ -858,6 +893,7 @@ int check_params(const gsim_model* m, const gsim_params* p, const gsim_grads* g 
     if (m->nt && !p->k_tri) return fail(GSIM_E_INVALID, "k_tri is required for triangles");
     if (!p->mass) return fail(GSIM_E_INVALID, "mass is required");
     if (!p->contact) return fail(GSIM_E_INVALID, "contact parameters are required ([n_bodies][4])");
+    if (m->any_air && !p->air) return fail(GSIM_E_INVALID, "air coefficients are required ([n_bodies][2]): a body has air_on");
     return GSIM_OK;
 }
 
@@ -1260,6 +1296,8 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     });
     chk(up(L.border, border.data(), border.size() * 4));
     m->fused_ok = P->fused_ok;
+    m->any_air = P->any_air;
+    m->air_on = P->air_on;
     m->etiles_plan = P->etiles;
     m->etile_words[0] = P->etile_words[0];
     m->etile_words[1] = P->etile_words[1];
@@ -1279,6 +1317,7 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
         B.p0 = P->poff[b];
         B.np = P->poff[b + 1] - P->poff[b];
         B.contact_on = P->contact_on[b];
+        B.air_on = P->air_on[b];
         B.g0 = P->body_g0[b];
         for (int k = 0; k < 3; ++k) {
             B.cbase[k] = P->cbase[3 * b + k];
@@ -1313,6 +1352,7 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     M.pinned = (const uint8_t*)(ws + L.pinned);
     M.bodies = (const BodyDev<T>*)(ws + L.bodies);
     M.slots = (T*)(ws + L.slots);
+    M.vslots = P->any_air ? (T*)(ws + L.vslots) : nullptr;
     M.cpart = (T*)(ws + L.cpart);
     M.lpart = (T*)(ws + L.lpart);
     M.f_tet_idx = (const int32_t*)(ws + L.f_tet_idx);
@@ -1557,6 +1597,7 @@ int gsim_model_set_exec(gsim_model* m, int exec, int block, int items) {
         return fail(GSIM_E_INVALID, "unknown exec %d", exec);
     if (exec == GSIM_EXEC_FUSED) {
         if (!m->fused_ok) return fail(GSIM_E_UNSUPPORTED, "fused execution: an element kind needs more than 128 colours");
+        if (m->any_air) return fail(GSIM_E_UNSUPPORTED, "fused execution does not model lift/drag (a body has air_on)");
         int dev = 0, lds_max = 0;
         HIP_TRY(hipGetDevice(&dev), "get device");
         HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "device LDS size");

@@ -438,10 +438,10 @@ int tick(gsim_engine* E, int* n_live, int* n_queued) {
         if (ops[i] == OP_ADJ) lds_a = std::max(lds_a, (size_t)m->etile_words[1] * sizeof(float));
     }
     auto T_ = [&](int k) { return reinterpret_cast<const Tile*>(d + o_t[k]); };
-    LAUNCH_TRY(launch_elem_fwd<float>(dmd, dsd, T_(0), grid[0], block, lds_f, E->stream), "element pass");
+    LAUNCH_TRY(launch_elem_fwd<float>(dmd, dsd, T_(0), grid[0], block, lds_f, false, E->stream), "element pass");
     LAUNCH_TRY(launch_part_fwd<float>(dmd, dsd, T_(1), grid[1], block, 1, E->stream), "particle pass");
-    LAUNCH_TRY(launch_elem_adj<float>(dmd, dsd, T_(2), grid[2], block, lds_a, E->stream), "element adjoint");
-    LAUNCH_TRY(launch_part_adj<float>(dmd, dsd, T_(3), grid[3], block, 1, E->stream), "particle adjoint");
+    LAUNCH_TRY(launch_elem_adj<float>(dmd, dsd, T_(2), grid[2], block, lds_a, false, E->stream), "element adjoint");
+    LAUNCH_TRY(launch_part_adj<float>(dmd, dsd, T_(3), grid[3], block, 1, false, E->stream), "particle adjoint");
     HIP_TRY(hipEventRecord(E->blob_evt[r], E->stream), "record tick");
     // 6. advance; finish completed queries
     std::vector<Live> keep;
@@ -523,6 +523,7 @@ int gsim_engine_submit(gsim_engine* E, const gsim_query* in, int64_t* id) {
     if (!E || !in || !in->desc) return fail(GSIM_E_INVALID, "NULL argument");
     const gsim_model_desc* d = in->desc;
     if (d->dtype != GSIM_F32 || d->n_bodies != 1) return fail(GSIM_E_UNSUPPORTED, "queries are single FP32 bodies");
+    if (d->air_on && d->air_on[0]) return fail(GSIM_E_UNSUPPORTED, "queries do not model lift/drag");
     if (in->n_steps < 1 || in->ckpt_every < 1) return fail(GSIM_E_INVALID, "n_steps and ckpt_every must be >= 1");
     if (!in->mass || !in->contact || !in->x0 || !in->v0 || !in->target) return fail(GSIM_E_INVALID, "NULL input");
     if (d->n_tets && (!in->mu || !in->lam)) return fail(GSIM_E_INVALID, "mu and lam are required");

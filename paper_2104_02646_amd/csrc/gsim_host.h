@@ -40,6 +40,8 @@ struct gsim_plan {
     std::vector<uint8_t> pinned;                   // [np]
     std::vector<double> dt, grav, plane, kb;       // per body
     std::vector<uint8_t> contact_on;               // per body
+    std::vector<uint8_t> air_on;                   // per body: lift/drag on its triangles
+    bool any_air = false;
 };
 
 namespace gsim {
@@ -54,7 +56,7 @@ struct Layout {
     size_t tri_code, tri_dinv, tri_area;
     size_t hin_code, hin_phi0;
     size_t tp;
-    size_t gbase, pdeg, pinned, slots, cpart, lpart;
+    size_t gbase, pdeg, pinned, slots, vslots, cpart, lpart;  // vslots: only when a body has air
     size_t fbuf, abuf;  // forward / adjoint internal ping-pong states
     // fused path: colour-ordered element records, colour bounds, body launch order
     size_t f_tet_idx, f_tet_dinv, f_tet_vol, f_tet_orig, f_tri_idx, f_tri_dinv, f_tri_area, f_tri_orig;
@@ -97,9 +99,13 @@ struct gsim_model {
     // launch lanes: with L > 1, the bodies are split into L groups of about equal
     // work whose passes run on L streams (the caller's and lane_stream[1 .. L-1])
     // between a fork and a join; lane l's tiles are [lane_e[l], lane_e[l + 1]) of
-    // the element list and [lane_p[l], lane_p[l + 1]) of the particle list
+    // the element list and [lane_p[l], lane_p[l + 1]) of the particle list.  Within a
+    // lane the tiles of bodies with air come last, from lane_e_air[l] / lane_p_air[l]:
+    // they run the kernel variant with lift/drag, the others the plain one, so a
+    // body's arithmetic never depends on the rest of its batch.
     int lanes = 1;
     int lane_e[gsim::MAX_LANES + 1] = {}, lane_p[gsim::MAX_LANES + 1] = {};
+    int lane_e_air[gsim::MAX_LANES] = {}, lane_p_air[gsim::MAX_LANES] = {};
     hipStream_t lane_stream[gsim::MAX_LANES] = {};
     hipEvent_t ev_fork = nullptr, ev_join[gsim::MAX_LANES] = {};
     int n_ptile_rows = 0;             // real particle tiles (contact / loss partial rows)
@@ -123,6 +129,8 @@ struct gsim_model {
     int64_t timing_n[6] = {0, 0, 0, 0, 0, 0};
     // fused path
     bool fused_ok = false;   // colouring succeeded for every body and kind
+    bool any_air = false;    // some body has lift/drag (not modelled by the fused path)
+    std::vector<uint8_t> air_on;  // per body
     int64_t max_body_np = 0;  // particles of the largest body
     size_t fused_dyn[2] = {0, 0};  // dynamic LDS bytes of the fused forward / adjoint launch (max over bodies)
 };

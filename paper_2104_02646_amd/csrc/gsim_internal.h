@@ -42,6 +42,7 @@ struct BodyDev {
     int32_t pt0, pt1;    // particle-tile id range (contact-gradient partials)
     int32_t contact_on;  // ground contact active
     int32_t g0;          // first gather slice of the body
+    int32_t air_on;      // lift/drag on the body's triangles
     int32_t cbase[3];    // fused path: first colour boundary of each element kind in coff
     int32_t ncol[3];     // fused path: colours of each element kind
     T dt;
@@ -72,6 +73,7 @@ struct ModelDev {
     const uint8_t* pinned;
     const BodyDev<T>* bodies;
     T* slots;   // [nslot][4] per-(tile, particle) partial sums
+    T* vslots;  // [nslot][4] velocity-adjoint partials of air tiles (null when no body has air)
     T* cpart;   // [n_ptiles][4] contact-gradient partial sums
     T* lpart;   // [n_ptiles] loss partial sums
     // fused path: element records in colour order (same SoA layouts, corner indices
@@ -116,6 +118,7 @@ struct StepDev {
     const T* mass;
     const T* contact;  // [n_bodies][4]
     const T* hact;     // [nh] hinge actuation (this step's), may be null
+    const T* air;      // [n_bodies][2] k_drag, k_lift (bodies with air_on)
     T* g_mu;
     T* g_lam;
     T* g_ktri;
@@ -134,22 +137,23 @@ struct StepDev {
     int32_t pad;
 };
 
-// Host-side launch helpers (defined in gsim_kernels.hip).  `stream` is a hipStream_t.
+// Host-side launch helpers (defined in gsim_kernels.hip).  `stream` is a hipStream_t;
+// `air` selects the kernel variant that models lift/drag (models with an air body).
 // element passes: one workgroup (block threads) per element tile, `lds` bytes of
 // dynamic LDS (the largest tile's: forward 4 words per tile particle + 4 per
 // corner, adjoint 8 + 4)
 template <typename T>
 int launch_elem_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, size_t lds,
-                    void* stream);
+                    bool air, void* stream);
 template <typename T>
 int launch_part_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int items,
                     void* stream);
 template <typename T>
 int launch_elem_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, size_t lds,
-                    void* stream);
+                    bool air, void* stream);
 template <typename T>
 int launch_part_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int items,
-                    void* stream);
+                    bool air, void* stream);
 template <typename T>
 int launch_fill(T* p, int64_t n, T value, void* stream);
 template <typename T>
@@ -168,7 +172,7 @@ int launch_fused_adj(const ModelDev<T>* md, const StepDev<T>* sd, const int32_t*
                      bool act, void* stream);
 // two-pass element tiles: at most ETILE consecutive elements of one kind of one
 // body, and at most ETILE_WORDS words of adjoint LDS (8 per tile particle, 4 per
-// corner)
+// corner; triangle tiles of bodies with air: 12 and 8)
 const int ETILE = 256, ETILE_WORDS = 16384;
 
 const int FUSED_FWD_BLOCK = 1024, FUSED_ADJ_BLOCK = 512;

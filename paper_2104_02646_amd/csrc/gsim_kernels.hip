@@ -55,6 +55,8 @@ __device__ __forceinline__ float gsin(float a) { return sinf(a); }
 __device__ __forceinline__ double gsin(double a) { return sin(a); }
 __device__ __forceinline__ float gcos(float a) { return cosf(a); }
 __device__ __forceinline__ double gcos(double a) { return cos(a); }
+__device__ __forceinline__ float gabs(float a) { return fabsf(a); }
+__device__ __forceinline__ double gabs(double a) { return fabs(a); }
 __device__ __forceinline__ float gatan2(float y, float x) { return atan2f(y, x); }
 __device__ __forceinline__ double gatan2(double y, double x) { return atan2(y, x); }
 
@@ -372,6 +374,71 @@ __device__ __forceinline__ void hinge_adjoint(const V3<T> x[4], T phi0, T kb, T 
     }
 }
 
+// ----------------------------------------------------------------- air ---
+// Lift/drag on one triangle (App. A.1 thin shells; flat-plate reading): u = mean
+// corner velocity (still air), N = (x1 - x0) x (x2 - x0), A = |N|/2, n = N/|N|,
+// s = n.u, q = |u|^2:
+//   F = -A (k_d |s| u + k_l s (q n - s u) / sqrt(q))     (lift term 0 at q = 0)
+// and every corner receives F / 3.  |s| takes slope +1 at s = 0.
+template <typename T>
+__device__ __forceinline__ V3<T> air_total(const V3<T> x[3], const V3<T> v[3], T kd, T kl) {
+    const V3<T> N = cross(x[1] - x[0], x[2] - x[0]);
+    const T nn = gsqrt(dot(N, N));
+    const V3<T> n = N * (T(1) / nn);
+    const T A = T(0.5) * nn;
+    const V3<T> u = (v[0] + v[1] + v[2]) * (T(1) / T(3));
+    const T s = dot(n, u), q = dot(u, u);
+    V3<T> F = u * (-(kd * A * gabs(s)));
+    if (q > T(0)) F += (n * q - u * s) * (-(kl * A * s / gsqrt(q)));
+    return F;
+}
+
+// Reverse mode of air_total for G, the adjoint of F (the mean of the corners'
+// adjoints, as each corner receives F / 3).  With gu = G.u, gn = G.n and
+// P = s q gn - s^2 gu the scalar <G, F> = -k_d A |s| gu - k_l A P / sqrt(q); its
+// partials in A, s, q, n and u (direct) are chained through s = n.u, q = u.u,
+// n = N/|N|, A = |N|/2 and N = a x b.  Returns F; adds the position adjoints to
+// xb and writes each corner's velocity adjoint (ubar / 3) to vbc.
+template <typename T>
+__device__ __forceinline__ V3<T> air_adjoint(const V3<T> x[3], const V3<T> v[3], T kd, T kl, V3<T> G, V3<T> xb[3],
+                                             V3<T>& vbc) {
+    const V3<T> a = x[1] - x[0], b = x[2] - x[0];
+    const V3<T> N = cross(a, b);
+    const T nn = gsqrt(dot(N, N));
+    const T inn = T(1) / nn;
+    const V3<T> n = N * inn;
+    const T A = T(0.5) * nn;
+    const V3<T> u = (v[0] + v[1] + v[2]) * (T(1) / T(3));
+    const T s = dot(n, u), q = dot(u, u);
+    const T as = gabs(s), sg = s < T(0) ? T(-1) : T(1);
+    const T gu = dot(G, u), gn = dot(G, n);
+    V3<T> F = u * (-(kd * A * as));
+    T Ab = -kd * as * gu;          // d/dA
+    T sb = -kd * A * sg * gu;      // d/ds
+    T qb = T(0);                   // d/dq
+    V3<T> nb = zero3<T>();         // d/dn through gn
+    V3<T> ub = G * (-kd * A * as); // d/du through gu
+    if (q > T(0)) {
+        const T r = gsqrt(q), ir = T(1) / r;
+        F += (n * q - u * s) * (-(kl * A * s * ir));
+        const T P = s * q * gn - s * s * gu;
+        Ab += -kl * P * ir;
+        sb += -kl * A * (q * gn - T(2) * s * gu) * ir;
+        qb += -kl * A * s * ir * (T(0.5) * gn + s * gu / (T(2) * q));
+        nb += G * (-kl * A * s * r);
+        ub += G * (kl * A * s * s * ir);
+    }
+    nb += u * sb;
+    ub += n * sb + u * (T(2) * qb);
+    const V3<T> Nb = (nb - n * dot(nb, n)) * inn + n * (T(0.5) * Ab);
+    const V3<T> abar = cross(b, Nb), bbar = cross(Nb, a);
+    xb[1] += abar;
+    xb[2] += bbar;
+    xb[0] -= abar + bbar;
+    vbc = ub * (T(1) / T(3));
+    return F;
+}
+
 // ------------------------------------------------------------- contact ---
 // gap = n.x - d; C = -gap when gap < 0; lambda_n = k_e C + k_d Cdot, Cdot = -n.v;
 // f_n = lambda_n n; u_t = v - (n.v) n; stick if k_f |u_t| <= mu_f |lambda_n|:
@@ -497,7 +564,9 @@ __device__ __forceinline__ gi4 ld_tp(const int32_t* tp, int64_t i) {
 // particle-sorted corner order; after one barrier each tile particle sums its
 // contiguous run of corners in that fixed order and writes one partial.  No
 // atomics; the result does not depend on the block size.
-template <typename T>
+// AIR: the variant launched for models with a lift/drag body (the other compiles
+// without any of that code).
+template <typename T, bool AIR>
 __global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
                                                    const Tile* __restrict__ tiles) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -506,13 +575,17 @@ __global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict_
     const StepDev<T>& S = sd[tl.model];
     const int64_t np = M.np;
     const int m = tl.pad, tid = threadIdx.x, nth = blockDim.x;
+    // triangle tiles of bodies with air also stage the velocities (lift/drag)
+    const bool air = AIR && tl.kind == TILE_TRI && M.bodies[tl.body].air_on != 0;
     L4<T>* xs = reinterpret_cast<L4<T>*>(smem);  // [m] tile-particle positions
-    L4<T>* cs = xs + m;                          // [corners] corner forces, particle-sorted
+    L4<T>* vs = xs + m;                          // [m] velocities (air tiles)
+    L4<T>* cs = xs + (air ? 2 * m : m);          // [corners] corner forces, particle-sorted
     gi4 mine = {0, 0, 0, 0};                     // this thread's first tile particle
     for (int j = tid; j < m; j += nth) {
         const gi4 r = ld_tp(M.tp, (int64_t)tl.id + j);
         if (j == tid) mine = r;
         xs[j] = l4(ld3(S.x, np, (int64_t)r.x), T(0));
+        if (air) vs[j] = l4(ld3(S.v, np, (int64_t)r.x), T(0));
     }
     __syncthreads();
     for (int l = threadIdx.x; l < tl.count; l += blockDim.x) {
@@ -544,6 +617,14 @@ __global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict_
 #pragma unroll
             for (int k = 0; k < 4; ++k) D[k] = gld(M.tri_dinv, k * M.nt + e);
             tri_force(x, D, gld(M.tri_area, e), gld(S.ktri, e), f);
+            if (air) {
+                V3<T> v[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[c] = v3(vs[cd[c] & 0xffffu]);
+                const V3<T> F = air_total(x, v, S.air[2 * tl.body], S.air[2 * tl.body + 1]) * (T(1) / T(3));
+#pragma unroll
+                for (int c = 0; c < 3; ++c) f[c] += F;
+            }
 #pragma unroll
             for (int c = 0; c < 3; ++c) cs[cd[c] >> 16] = l4(f[c], T(0));
         } else {
@@ -625,8 +706,11 @@ __device__ __forceinline__ V3<T> corner_fbar(const ModelDev<T>& M, const StepDev
 // forces fbar are staged in LDS; each element writes (xbar contribution, f.fbar)
 // of its corners in particle-sorted order; each tile particle sums its run into
 // one partial.  Element-owned parameter gradients are read-modify-writes by the
-// element's own thread.
-template <typename T>
+// element's own thread.  Bodies with air: triangle tiles also stage velocities
+// and sum each particle's velocity adjoint into a second partial (vslots); the
+// body's other tiles write zero there, so every partial the particle pass reads
+// is written.
+template <typename T, bool AIR>
 __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
                                                    const Tile* __restrict__ tiles) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -636,9 +720,13 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
     const int64_t np = M.np;
     const T dt = M.bodies[tl.body].dt;
     const int m = tl.pad, tid = threadIdx.x, nth = blockDim.x;
+    const bool air_body = AIR && M.bodies[tl.body].air_on != 0;
+    const bool air = air_body && tl.kind == TILE_TRI;
     L4<T>* xs = reinterpret_cast<L4<T>*>(smem);  // [m] tile-particle positions
     L4<T>* fbs = xs + m;                         // [m] tile-particle adjoint forces
-    L4<T>* cs = fbs + m;                         // [corners] corner (xbar, f.fbar), particle-sorted
+    L4<T>* vs = fbs + m;                         // [m] velocities (air tiles)
+    L4<T>* cs = fbs + (air ? 2 * m : m);         // [corners] corner (xbar, f.fbar), particle-sorted
+    L4<T>* cv = cs + 3 * tl.count;               // [corners] corner vbar (air tiles)
     gi4 mine = {0, 0, 0, 0};                     // this thread's first tile particle
     for (int j = tid; j < m; j += nth) {
         const gi4 r = ld_tp(M.tp, (int64_t)tl.id + j);
@@ -646,6 +734,7 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
         const int64_t p = r.x;
         xs[j] = l4(ld3(S.x, np, p), T(0));
         fbs[j] = l4(corner_fbar(M, S, p, dt), T(0));
+        if (air) vs[j] = l4(ld3(S.v, np, p), T(0));
     }
     __syncthreads();
     for (int l = threadIdx.x; l < tl.count; l += blockDim.x) {
@@ -686,6 +775,19 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
             for (int k = 0; k < 4; ++k) D[k] = gld(M.tri_dinv, k * M.nt + e);
             T gk;
             tri_adjoint(x, D, gld(M.tri_area, e), gld(S.ktri, e), fb, f, xb, gk);
+            if (air) {
+                V3<T> v[3], vbc;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) v[c] = v3(vs[cd[c] & 0xffffu]);
+                const V3<T> G = (fb[0] + fb[1] + fb[2]) * (T(1) / T(3));
+                const V3<T> F =
+                    air_adjoint(x, v, S.air[2 * tl.body], S.air[2 * tl.body + 1], G, xb, vbc) * (T(1) / T(3));
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    f[c] += F;
+                    cv[cd[c] >> 16] = l4(vbc, T(0));
+                }
+            }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 cs[cd[c] >> 16] = l4(xb[c], dot(f[c], fb[c]));
@@ -721,10 +823,16 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
             d += c.w;
         }
         st_slot(M.slots, r.z, xb.x, xb.y, xb.z, d);
+        if (air_body) {
+            V3<T> vb = zero3<T>();
+            if (air)
+                for (int k = 0; k < rn; ++k) vb += v3(cv[r0 + k]);
+            st_slot(M.vslots, r.z, vb.x, vb.y, vb.z, T(0));
+        }
     }
 }
 
-template <typename T>
+template <typename T, bool AIR>
 __global__ void __launch_bounds__(512) k_part_adj(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
                                                    const Tile* __restrict__ tiles) {
     const Tile tl = tiles[blockIdx.x];
@@ -761,6 +869,12 @@ __global__ void __launch_bounds__(512) k_part_adj(const ModelDev<T>* __restrict_
             ds += d;
         }
         V3<T> xcb = zero3<T>(), vcb = zero3<T>();
+        if (AIR && B.air_on)  // velocity adjoint of the lift/drag force, same partial slots
+            for (int32_t k = 0; k < deg; ++k) {
+                T a, b, c, d;
+                ld_slot(M.vslots, base + 64 * k, a, b, c, d);
+                vcb += mk3(a, b, c);
+            }
         if (contact) {
             const V3<T> x = ld3(S.x, np, i), v = ld3(S.v, np, i);
             const V3<T> fc = contact_adjoint(x, v, pl, cp, fb, xcb, vcb, gc);
@@ -1329,14 +1443,20 @@ void allow_lds(const void* kernel, size_t lds, size_t& allowed) {
         allowed = lds;
     }
 }
+template <typename T, bool AIR>
+int launch_elem_fwd_v(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, size_t lds,
+                      void* stream) {
+    static size_t allowed = 48 * 1024;
+    allow_lds(reinterpret_cast<const void*>(&k_elem_fwd<T, AIR>), lds, allowed);
+    hipLaunchKernelGGL((k_elem_fwd<T, AIR>), dim3(ntiles), dim3(block), lds, (hipStream_t)stream, md, sd, tiles);
+    return check_launch();
+}
 template <typename T>
 int launch_elem_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, size_t lds,
-                    void* stream) {
+                    bool air, void* stream) {
     if (ntiles <= 0) return 0;
-    static size_t allowed = 48 * 1024;
-    allow_lds(reinterpret_cast<const void*>(&k_elem_fwd<T>), lds, allowed);
-    hipLaunchKernelGGL(k_elem_fwd<T>, dim3(ntiles), dim3(block), lds, (hipStream_t)stream, md, sd, tiles);
-    return check_launch();
+    return air ? launch_elem_fwd_v<T, true>(md, sd, tiles, ntiles, block, lds, stream)
+               : launch_elem_fwd_v<T, false>(md, sd, tiles, ntiles, block, lds, stream);
 }
 template <typename T>
 int launch_part_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int,
@@ -1345,20 +1465,29 @@ int launch_part_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* til
     hipLaunchKernelGGL(k_part_fwd<T>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
     return check_launch();
 }
-template <typename T>
-int launch_elem_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, size_t lds,
-                    void* stream) {
-    if (ntiles <= 0) return 0;
+template <typename T, bool AIR>
+int launch_elem_adj_v(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, size_t lds,
+                      void* stream) {
     static size_t allowed = 48 * 1024;
-    allow_lds(reinterpret_cast<const void*>(&k_elem_adj<T>), lds, allowed);
-    hipLaunchKernelGGL(k_elem_adj<T>, dim3(ntiles), dim3(block), lds, (hipStream_t)stream, md, sd, tiles);
+    allow_lds(reinterpret_cast<const void*>(&k_elem_adj<T, AIR>), lds, allowed);
+    hipLaunchKernelGGL((k_elem_adj<T, AIR>), dim3(ntiles), dim3(block), lds, (hipStream_t)stream, md, sd, tiles);
     return check_launch();
 }
 template <typename T>
-int launch_part_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int,
-                    void* stream) {
+int launch_elem_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, size_t lds,
+                    bool air, void* stream) {
     if (ntiles <= 0) return 0;
-    hipLaunchKernelGGL(k_part_adj<T>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
+    return air ? launch_elem_adj_v<T, true>(md, sd, tiles, ntiles, block, lds, stream)
+               : launch_elem_adj_v<T, false>(md, sd, tiles, ntiles, block, lds, stream);
+}
+template <typename T>
+int launch_part_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int,
+                    bool air, void* stream) {
+    if (ntiles <= 0) return 0;
+    if (air)
+        hipLaunchKernelGGL((k_part_adj<T, true>), dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
+    else
+        hipLaunchKernelGGL((k_part_adj<T, false>), dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
     return check_launch();
 }
 template <typename T>
@@ -1440,10 +1569,10 @@ int launch_fused_grads(const ModelDev<T>* md, const StepDev<T>* sd, void* stream
 }
 
 #define GSIM_INSTANTIATE(T)                                                                                          \
-    template int launch_elem_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, size_t, void*);     \
+    template int launch_elem_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, size_t, bool, void*); \
     template int launch_part_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
-    template int launch_elem_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, size_t, void*);     \
-    template int launch_part_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, void*);     \
+    template int launch_elem_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, size_t, bool, void*); \
+    template int launch_part_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, bool, void*); \
     template int launch_fill<T>(T*, int64_t, T, void*);                                                             \
     template int launch_contact_reduce<T>(const ModelDev<T>*, const StepDev<T>*, int, void*);                       \
     template int launch_loss<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, int, void*);     \

@@ -51,7 +51,7 @@ class _Desc(C.Structure):
                 ("body_hinge_off", C.c_void_p), ("rest_x", C.c_void_p), ("tet_idx", C.c_void_p),
                 ("tri_idx", C.c_void_p), ("hinge_idx", C.c_void_p), ("pinned", C.c_void_p),
                 ("gravity", C.c_void_p), ("dt", C.c_void_p), ("ground", C.c_void_p), ("contact_on", C.c_void_p),
-                ("k_bend", C.c_void_p)]
+                ("k_bend", C.c_void_p), ("air_on", C.c_void_p)]
 
 
 class _State(C.Structure):
@@ -61,7 +61,7 @@ class _State(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("mu", C.c_void_p), ("lam", C.c_void_p), ("act", C.c_void_p), ("k_tri", C.c_void_p),
                 ("mass", C.c_void_p), ("contact", C.c_void_p), ("hact", C.c_void_p), ("act_stride", C.c_int64),
-                ("hact_stride", C.c_int64)]
+                ("hact_stride", C.c_int64), ("air", C.c_void_p)]
 
 
 class _Ctrl(C.Structure):
@@ -201,6 +201,7 @@ class Packed:
     ground: np.ndarray
     contact_on: np.ndarray
     k_bend: np.ndarray
+    air_on: np.ndarray
 
 
 def pack(bodies) -> Packed:
@@ -227,7 +228,8 @@ def pack(bodies) -> Packed:
                   np.ascontiguousarray([b.dt for b in bodies], np.float64),
                   np.ascontiguousarray([b.plane for b in bodies], np.float64),
                   np.ascontiguousarray([1 if b.ground else 0 for b in bodies], np.uint8),
-                  np.ascontiguousarray([b.kb for b in bodies], np.float64))
+                  np.ascontiguousarray([b.kb for b in bodies], np.float64),
+                  np.ascontiguousarray([1 if getattr(b, "air", False) else 0 for b in bodies], np.uint8))
 
 
 class Plan:
@@ -251,6 +253,7 @@ class Plan:
         d.rest_x, d.tet_idx, d.tri_idx, d.hinge_idx = a(pk.X), a(pk.tets), a(pk.tris), a(pk.hinges)
         d.pinned, d.gravity, d.dt, d.ground = a(pk.pinned), a(pk.gravity), a(pk.dt), a(pk.ground)
         d.contact_on, d.k_bend = a(pk.contact_on), a(pk.k_bend)
+        d.air_on = a(pk.air_on) if pk.air_on.any() else None
         h = C.c_void_p()
         _check(lib.gsim_plan_create(C.byref(d), C.byref(h)))
         self._h = h
@@ -385,11 +388,14 @@ class Model:
                 torch.empty(3, self.np, dtype=self.dtype, device=self.device))
 
     def params_from_bodies(self, bodies=None):
-        """Device parameter tensors: mu, lam [ne], ktri [nt], mass [np], contact [nb, 4]."""
+        """Device parameter tensors: mu, lam [ne], ktri [nt], mass [np], contact [nb, 4],
+        and air [nb, 2] = (k_drag, k_lift) when a body has lift/drag."""
         bodies = self.plan.bodies if bodies is None else bodies
         t = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64)).to(self.device, self.dtype)
         p = {"mass": t(np.concatenate([b.mass for b in bodies])),
              "contact": t([[b.ke, b.kd, b.kf, b.muf] for b in bodies])}
+        if any(getattr(b, "air", False) for b in bodies):
+            p["air"] = t([[b.kdrag, b.klift] if b.air else [0.0, 0.0] for b in bodies])
         if self.ne:
             p["mu"] = t(np.concatenate([b.mu for b in bodies if b.ne]))
             p["lam"] = t(np.concatenate([b.lam for b in bodies if b.ne]))
@@ -434,6 +440,7 @@ class Model:
         s.k_tri, s.mass, s.contact = _ptr(p.get("ktri")), _ptr(p.get("mass")), _ptr(p.get("contact"))
         s.act, s.act_stride = self._actuation(p, "act", n_steps)
         s.hact, s.hact_stride = self._actuation(p, "hact", n_steps)
+        s.air = _ptr(p.get("air"))
         return s
 
     def _grads(self, g, n_steps=1):

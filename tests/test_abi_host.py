@@ -142,7 +142,7 @@ def test_colouring_classes_are_particle_disjoint(gs, which):
         assert ncol <= 128 * len(bodies) * 3
 
 
-@pytest.mark.parametrize("which", ["mixed", "batch"])
+@pytest.mark.parametrize("which", ["mixed", "batch", "air"])
 def test_element_tiles_and_partials(gs, which):
     """Two-pass element tiles: they partition each body's elements of each kind into
     runs of consecutive elements (at most 256, adjoint LDS within 16384 words); each
@@ -152,6 +152,7 @@ def test_element_tiles_and_partials(gs, which):
     are a bijection onto the sliced-ELL table (slot = slice base + 64 k + lane,
     k < degree, k increasing in tile order)."""
     bodies = ([W.tiny_cube(0), W.cloth(5, n=30), W.batch_body(20001, lo=700, hi=900)] if which == "mixed" else
+              [W.tiny_cube(1), W.control_cloth(62, n=33), W.cloth(6, n=40)] if which == "air" else
               [W.batch_body(20000 + i, lo=3000, hi=20000) for i in range(3)])
     p = gs.Plan(bodies)
     pk = gs.pack(bodies)
@@ -171,7 +172,10 @@ def test_element_tiles_and_partials(gs, which):
         parts = tp[t0:ends[i]]
         m = len(parts)
         assert np.array_equal(parts, np.unique(idx[e0:e0 + cnt].ravel()))
-        assert 8 * m + 4 * nc * cnt <= 16384
+        air = kind == 1 and bodies[body].air
+        # adjoint LDS words: triangles of bodies with air also stage velocities and keep
+        # a velocity adjoint per corner
+        assert (12 * m + 8 * nc * cnt if air else 8 * m + 4 * nc * cnt) <= 16384
         cd = codes[kind][:, e0:e0 + cnt]
         lj, pos = cd & 0xFFFF, cd >> 16
         assert np.array_equal(parts[lj], idx[e0:e0 + cnt].T)

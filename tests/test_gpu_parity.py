@@ -275,10 +275,15 @@ def test_repeat_runs_bitwise(gs):
     for k in a[2]:
         assert np.array_equal(a[2][k], b[2][k])
 
-def test_lanes_bitwise(gs):
+@pytest.mark.parametrize("with_air", [False, True])
+def test_lanes_bitwise(gs, with_air):
     """Two launch lanes (bodies split into two concurrently running groups, plain and
-    graph execution) give the same bits as one lane."""
+    graph execution) and kernel-timing mode (every pass on the caller's stream, with
+    events around each launch) give the same bits as one lane; also for a batch with
+    a lift/drag cloth, whose tiles run the air kernel variant."""
     bodies = [W.batch_body(21000 + i, lo=300, hi=4000) for i in range(7)] + [W.cloth(8, n=12, size=0.5)]
+    if with_air:
+        bodies.insert(3, W.control_cloth(9, n=14))
     for b in bodies:
         b.target = W.synthetic_target(b, 2)
     T, K = 24, 5
@@ -292,16 +297,23 @@ def test_lanes_bitwise(gs):
         v0 = gs.soa(np.concatenate([b.v0 for b in bodies]))
         tgt = gs.soa(np.concatenate([b.target for b in bodies]))
         for lanes in (1, 2):
-            for mode in (gs.EXEC_PLAIN, gs.EXEC_GRAPH):
+            for mode in (gs.EXEC_PLAIN, gs.EXEC_GRAPH, "timing"):
                 m.set_lanes(lanes)
-                m.set_exec(mode)
+                m.set_exec(gs.EXEC_PLAIN if mode == "timing" else mode)
+                if mode == "timing":
+                    m.set_timing()
                 for rep in range(2):
                     xT, vT = m.rollout(p, x0, v0, T, stream=stream)
                     loss, xb, vb = m.loss_mse(xT, tgt, stream=stream)
                     g = m.zero_grads()
                     xb0, vb0 = m.rollout_backward(p, T, xb, vb, g, stream=stream)
                     torch.cuda.synchronize()
-                    out[(lanes, mode, rep)] = [xT.clone(), loss.clone(), xb0.clone()] + [v.clone() for v in g.values()]
+                    out[(lanes, mode, rep)] = [xT.clone(), loss.clone(), xb0.clone(), vb0.clone()] + \
+                        [v.clone() for v in g.values()]
+                if mode == "timing":
+                    launches = m.read_timing()
+                    m.set_timing(())
+                    assert launches["element_fwd"][0] > 0
     ref = out[(1, gs.EXEC_PLAIN, 0)]
     for key, val in out.items():
         for a, b in zip(val, ref):
