@@ -209,6 +209,52 @@ def control_step(model, p, x0, v0, tgt, T, steps, stream, ne, n_signals=8):
             "controller_bwd": {"avg_us": b_ms * 1e3, "bytes": b_bytes, "GBps": b_bytes / (b_ms * 1e-3) / 1e9}}
 
 
+def cloth_air_batch(steps, n_cloths=64, T=100, K=10):
+    """The control-cloth step at batch scale: 64 free cloths (72 .. 2048 triangles,
+    seeded sizes) under lift/drag, T steps forward with checkpoints, loss, adjoint
+    with the initial-velocity gradient; the same batch without air for comparison.
+    Rate: (triangles + hinges) x steps per second, forward + adjoint."""
+    import torch
+    from paper_2104_02646_amd import gsim, workloads as W
+    out = {}
+    for air in (True, False):
+        bodies = [W.control_cloth(900 + i).round_to(np.float32) for i in range(n_cloths)]
+        if not air:
+            bodies = [b.with_params(air=False) for b in bodies]
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            m = gsim.Model(bodies, torch.float32, max_steps=T, ckpt_every=K)
+            p = m.params_from_bodies()
+            x0 = gsim.soa(np.concatenate([b.x0 for b in bodies]))
+            v0 = gsim.soa(np.concatenate([b.v0 for b in bodies]))
+            tgt = gsim.soa(np.concatenate([b.x0 + 0.3 for b in bodies]))
+            xT, vT = m.empty_state()
+            xb0, vb0 = m.empty_state()
+            g = m.zero_grads(("ktri", "mass"))
+
+            def one():
+                m.rollout(p, x0, v0, T, out=(xT, vT), stream=stream)
+                loss, xb, vb = m.loss_mse(xT, tgt, stream=stream)
+                for t in g.values():
+                    t.zero_()
+                m.rollout_backward(p, T, xb, vb, g, out=(xb0, vb0), stream=stream)
+            one()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                one()
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / steps
+        n_el = sum(b.nt + b.nh for b in bodies)
+        out["air" if air else "no_air"] = {"ms_per_step": sec * 1e3, "value": n_el * T / sec}
+        out["workload"] = ("%d free cloths (%d triangles, %d hinges in all), %d steps fwd + checkpointed adjoint "
+                           "(every %d), initial-velocity gradient" % (n_cloths, sum(b.nt for b in bodies),
+                                                                      sum(b.nh for b in bodies), T, K))
+    out["unit"] = "element-steps/s (triangles + hinges)"
+    out["air_overhead"] = out["air"]["ms_per_step"] / out["no_air"]["ms_per_step"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +272,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serve-queries", type=int, default=400, help="measured queries of the serving trace (0 = skip)")
     ap.add_argument("--no-control", action="store_true", help="skip the actuated (controller-driven) step")
+    ap.add_argument("--no-cloth", action="store_true", help="skip the lift/drag cloth batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device tensor copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -410,6 +457,8 @@ def main():
     if control is not None:
         control["overhead_vs_unactuated_step"] = control["ms_per_step"] / (sec * 1e3)
         result["control"] = control
+    if not args.no_cloth:
+        result["control_cloth"] = cloth_air_batch(args.steps)
     if args.serve_queries > 0:
         result["serving"] = serving(args.serve_queries, max(20, args.serve_queries // 10), K,
                                     lambda msg: print(msg, file=sys.stderr, flush=True))
