@@ -899,3 +899,164 @@ void oc_contact_force1(const double* x, const double* v, const double* plane, do
 }
 
 }  // extern "C"
+
+/* ====================================================================== */
+/* Rigid bodies (App. A.1 "Rigid bodies" and "Contact")                    */
+/* ====================================================================== */
+/* State s = [x (3), r (4) = (w, i, j, k), v (3), omega (3)]: centre-of-mass
+ * position, orientation quaternion (body to world), linear and angular velocity
+ * (world frame).  Parameters: mass m, body-frame inertia about the centre of mass
+ * I = [Ixx, Iyy, Izz, Ixy, Ixz, Iyz], contact [ke, kd, kf, muf].  Vertices p_k are
+ * body-frame positions relative to the centre of mass; each is tested against
+ * the ground plane with the particle contact model. */
+namespace {
+
+/* Rotation matrix (row-major) of a unit quaternion. */
+template <class S> void quat_rot(const S q[4], S R[9]) {
+    const S w = q[0], a = q[1], b = q[2], c = q[3];
+    R[0] = 1.0 - 2.0 * (b * b + c * c); R[1] = 2.0 * (a * b - w * c);       R[2] = 2.0 * (a * c + w * b);
+    R[3] = 2.0 * (a * b + w * c);       R[4] = 1.0 - 2.0 * (a * a + c * c); R[5] = 2.0 * (b * c - w * a);
+    R[6] = 2.0 * (a * c - w * b);       R[7] = 2.0 * (b * c + w * a);       R[8] = 1.0 - 2.0 * (a * a + b * b);
+}
+
+template <class S> V3<S> mat_vec(const S M[9], const V3<S>& v) {
+    return mk<S>(M[0] * v.x + M[1] * v.y + M[2] * v.z, M[3] * v.x + M[4] * v.y + M[5] * v.z,
+                 M[6] * v.x + M[7] * v.y + M[8] * v.z);
+}
+
+/* One semi-implicit Euler step of one rigid body (App. A.2 applied to the
+ * Newton-Euler equations): forces and torques at the step's start state,
+ *   v+ = v + dt (F / m + g)
+ *   omega+ = omega + dt Iw^-1 (tau - omega x (Iw omega)),  Iw = R I R^T
+ *   x+ = x + dt v+,   r+ = normalise(r + dt/2 [0, omega+] (x) r). */
+template <class S>
+void rigid_step(const S s[13], S m, const S I[6], const S c[4], const double* p, int nv, const double g[3],
+                const double plane[4], int ground, double dt, S out[13]) {
+    const V3<S> x = mk<S>(s[0], s[1], s[2]);
+    const S* r = &s[3];
+    const V3<S> v = mk<S>(s[7], s[8], s[9]);
+    const V3<S> w = mk<S>(s[10], s[11], s[12]);
+    S R[9];
+    quat_rot<S>(r, R);
+    V3<S> F = zero3<S>(), tau = zero3<S>();
+    if (ground)
+        for (int k = 0; k < nv; ++k) {
+            const V3<S> pk = mk<S>(S(p[3 * k]), S(p[3 * k + 1]), S(p[3 * k + 2]));
+            const V3<S> a = mat_vec<S>(R, pk);
+            const V3<S> f = contact_force<S>(x + a, v + cross(w, a), plane, c[0], c[1], c[2], c[3]);
+            F = F + f;
+            tau = tau + cross(a, f);
+        }
+    /* Iw = R Ib R^T */
+    const S Ib[9] = {I[0], I[3], I[4], I[3], I[1], I[5], I[4], I[5], I[2]};
+    S T1[9], Iw[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            S acc = S(0.0);
+            for (int k = 0; k < 3; ++k) acc = acc + R[3 * i + k] * Ib[3 * k + j];
+            T1[3 * i + j] = acc;
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            S acc = S(0.0);
+            for (int k = 0; k < 3; ++k) acc = acc + T1[3 * i + k] * R[3 * j + k];
+            Iw[3 * i + j] = acc;
+        }
+    const V3<S> L = mat_vec<S>(Iw, w);
+    const V3<S> h = tau - cross(w, L);
+    /* alpha = Iw^-1 h by the adjugate */
+    const S det = Iw[0] * (Iw[4] * Iw[8] - Iw[5] * Iw[7]) - Iw[1] * (Iw[3] * Iw[8] - Iw[5] * Iw[6]) +
+                  Iw[2] * (Iw[3] * Iw[7] - Iw[4] * Iw[6]);
+    S inv[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int r1 = (j + 1) % 3, r2 = (j + 2) % 3, c1 = (i + 1) % 3, c2 = (i + 2) % 3;
+            inv[3 * i + j] = (Iw[3 * r1 + c1] * Iw[3 * r2 + c2] - Iw[3 * r1 + c2] * Iw[3 * r2 + c1]) / det;
+        }
+    const V3<S> alpha = mat_vec<S>(inv, h);
+    const V3<S> vn = v + (F * (S(1.0) / m) + mk<S>(S(g[0]), S(g[1]), S(g[2]))) * dt;
+    const V3<S> wn = w + alpha * dt;
+    const V3<S> xn = x + vn * dt;
+    /* [0, wn] (x) r = [-wn . u, r0 wn + wn x u], u = (r1, r2, r3) */
+    const V3<S> u = mk<S>(r[1], r[2], r[3]);
+    const S q0 = r[0] - 0.5 * dt * dot(wn, u);
+    const V3<S> qv = u + (wn * r[0] + cross(wn, u)) * (0.5 * dt);
+    const S qn = sqrt(q0 * q0 + dot(qv, qv));
+    out[0] = xn.x; out[1] = xn.y; out[2] = xn.z;
+    out[3] = q0 / qn; out[4] = qv.x / qn; out[5] = qv.y / qn; out[6] = qv.z / qn;
+    out[7] = vn.x; out[8] = vn.y; out[9] = vn.z;
+    out[10] = wn.x; out[11] = wn.y; out[12] = wn.z;
+}
+
+/* Mean squared distance of the body's world vertices to target points. */
+template <class S> S rigid_loss(const S s[13], const double* p, int nv, const double* target) {
+    S R[9];
+    quat_rot<S>(&s[3], R);
+    S L = S(0.0);
+    for (int k = 0; k < nv; ++k) {
+        const V3<S> a = mat_vec<S>(R, mk<S>(S(p[3 * k]), S(p[3 * k + 1]), S(p[3 * k + 2])));
+        const V3<S> d = mk<S>(s[0] + a.x - target[3 * k], s[1] + a.y - target[3 * k + 1], s[2] + a.z - target[3 * k + 2]);
+        L = L + dot(d, d);
+    }
+    return L / double(nv);
+}
+
+}  // namespace
+
+extern "C" {
+
+/* One rigid step; s, out [13]; I [6]; c [4]; p [nv][3]; g [3]; plane [4]. */
+void oc_rigid_step(int nv, const double* p, const double* s, double m, const double* I, const double* c,
+                   const double* g, const double* plane, int ground, double dt, double* out) {
+    rigid_step<double>(s, m, I, c, p, nv, g, plane, ground, dt, out);
+}
+
+/* Reverse mode of one rigid step by forward-mode duals: the 24 inputs
+ * [s (13), m, I (6), c (4)] are seeded in two passes of up to ND tangents; each
+ * input's adjoint is sum_o out_bar[o] d out_o / d input.  Adds into s_bar [13],
+ * m_bar [1], I_bar [6], c_bar [4]. */
+void oc_rigid_step_vjp(int nv, const double* p, const double* s, double m, const double* I, const double* c,
+                       const double* g, const double* plane, int ground, double dt, const double* out_bar,
+                       double* s_bar, double* m_bar, double* I_bar, double* c_bar) {
+    const int NIN = 24;
+    double in[NIN];
+    for (int k = 0; k < 13; ++k) in[k] = s[k];
+    in[13] = m;
+    for (int k = 0; k < 6; ++k) in[14 + k] = I[k];
+    for (int k = 0; k < 4; ++k) in[20 + k] = c[k];
+    double grad[NIN];
+    for (int first = 0; first < NIN; first += ND) {
+        Dual z[NIN];
+        for (int k = 0; k < NIN; ++k) {
+            z[k] = Dual(in[k]);
+            if (k >= first && k < first + ND) z[k].d[k - first] = 1.0;
+        }
+        Dual out[13];
+        rigid_step<Dual>(z, z[13], &z[14], &z[20], p, nv, g, plane, ground, dt, out);
+        for (int k = first; k < NIN && k < first + ND; ++k) {
+            double acc = 0.0;
+            for (int o = 0; o < 13; ++o) acc += out_bar[o] * out[o].d[k - first];
+            grad[k] = acc;
+        }
+    }
+    for (int k = 0; k < 13; ++k) s_bar[k] += grad[k];
+    m_bar[0] += grad[13];
+    for (int k = 0; k < 6; ++k) I_bar[k] += grad[14 + k];
+    for (int k = 0; k < 4; ++k) c_bar[k] += grad[20 + k];
+}
+
+/* Vertex loss of one body and its gradient with respect to the state (s_bar [13],
+ * overwritten; only x and r enter). */
+double oc_rigid_loss(int nv, const double* p, const double* s, const double* target, double* s_bar) {
+    Dual z[13];
+    for (int k = 0; k < 13; ++k) {
+        z[k] = Dual(s[k]);
+        if (k < ND) z[k].d[k] = 1.0;
+    }
+    Dual L = rigid_loss<Dual>(z, p, nv, target);
+    if (s_bar)
+        for (int k = 0; k < 13; ++k) s_bar[k] = L.d[k];
+    return L.v;
+}
+
+}  // extern "C"

@@ -92,6 +92,11 @@ def _load():
         lib.oc_hinge_force1.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp]
         lib.oc_contact_force1.argtypes = [_dp, _dp, _dp] + [C.c_double] * 4 + [_dp]
         lib.oc_air_force1.argtypes = [_dp, _dp, C.c_double, C.c_double, _dp]
+        d, i = C.c_double, C.c_int
+        lib.oc_rigid_step.argtypes = [i, _dp, _dp, d, _dp, _dp, _dp, _dp, i, d, _dp]
+        lib.oc_rigid_step_vjp.argtypes = [i, _dp, _dp, d, _dp, _dp, _dp, _dp, i, d, _dp, _dp, _dp, _dp, _dp]
+        lib.oc_rigid_loss.restype = d
+        lib.oc_rigid_loss.argtypes = [i, _dp, _dp, _dp, _dp]
         _lib = lib
     return _lib
 
@@ -343,3 +348,65 @@ class Oracle:
         g["x0"] = xb0
         g["v0"] = vb0
         return L, g, xs, vs
+
+
+# ----------------------------------------------------------------------------------
+# rigid bodies
+# ----------------------------------------------------------------------------------
+
+class RigidOracle:
+    """One rigid body (App. A.1 "Rigid bodies", "Contact"): body-frame vertices p
+    [nv, 3] relative to the centre of mass, gravity, ground plane (vertex contact
+    with the particle contact model), dt.  State s [13] = x (3), quaternion r (4,
+    w first), v (3), omega (3); parameters m, I = [Ixx, Iyy, Izz, Ixy, Ixz, Iyz]
+    (body frame, about the centre of mass), c = [ke, kd, kf, muf]."""
+
+    def __init__(self, p, gravity=(0.0, -9.81, 0.0), ground=True, plane=(0.0, 1.0, 0.0, 0.0), dt=1.0 / 600.0):
+        self.p = _f64(p).reshape(-1, 3)
+        self.nv = self.p.shape[0]
+        self.g = _f64(gravity, (3,))
+        self.plane = _f64(plane, (4,))
+        self.ground = int(bool(ground))
+        self.dt = float(dt)
+
+    def step(self, s, m, I, c):
+        s = _f64(s, (13,)); I = _f64(I, (6,)); c = _f64(c, (4,)); out = np.zeros(13)
+        _load().oc_rigid_step(self.nv, _ptr(self.p), _ptr(s), float(m), _ptr(I), _ptr(c), _ptr(self.g),
+                              _ptr(self.plane), self.ground, self.dt, _ptr(out))
+        return out
+
+    def step_vjp(self, s, m, I, c, out_bar):
+        s = _f64(s, (13,)); I = _f64(I, (6,)); c = _f64(c, (4,)); ob = _f64(out_bar, (13,))
+        sb, mb, Ib, cb = np.zeros(13), np.zeros(1), np.zeros(6), np.zeros(4)
+        _load().oc_rigid_step_vjp(self.nv, _ptr(self.p), _ptr(s), float(m), _ptr(I), _ptr(c), _ptr(self.g),
+                                  _ptr(self.plane), self.ground, self.dt, _ptr(ob), _ptr(sb), _ptr(mb), _ptr(Ib),
+                                  _ptr(cb))
+        return sb, mb[0], Ib, cb
+
+    def rollout(self, s0, m, I, c, T):
+        """All T+1 states [T+1, 13]."""
+        out = np.zeros((T + 1, 13))
+        out[0] = _f64(s0, (13,))
+        for t in range(T):
+            out[t + 1] = self.step(out[t], m, I, c)
+        return out
+
+    def loss(self, s, target):
+        """Mean squared distance of the world vertices to target [nv, 3]; its state gradient."""
+        s = _f64(s, (13,)); t = _f64(target, (self.nv, 3)); sb = np.zeros(13)
+        L = _load().oc_rigid_loss(self.nv, _ptr(self.p), _ptr(s), _ptr(t), _ptr(sb))
+        return L, sb
+
+    def loss_and_grad(self, s0, m, I, c, T, target):
+        """Rollout, vertex loss of the final state, and the reverse pass over the
+        stored states (App. A): gradients for s0, m, I and c."""
+        states = self.rollout(s0, m, I, c, T)
+        L, sb = self.loss(states[-1], target)
+        g = {"m": 0.0, "I": np.zeros(6), "c": np.zeros(4)}
+        for t in range(T - 1, -1, -1):
+            sb, mb, Ib, cb = self.step_vjp(states[t], m, I, c, sb)
+            g["m"] += mb
+            g["I"] += Ib
+            g["c"] += cb
+        g["s0"] = sb
+        return L, g, states
