@@ -334,6 +334,69 @@ int gsim_controller_backward(int dtype, const gsim_controller* ctrl, const void*
                              int64_t t0, int64_t n_steps, void* W_grad, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* RIGID BODIES                                                              */
+/* ------------------------------------------------------------------------ */
+/* App. A.1 "Rigid bodies": state per body s = [x (3), r (4), v (3), omega (3)]
+ * (centre-of-mass position; unit quaternion (w, i, j, k), body to world; linear
+ * and angular velocity, world frame), stored [n_bodies][13].  Parameters per
+ * body: mass m > 0, body-frame inertia about the centre of mass I = [Ixx, Iyy,
+ * Izz, Ixy, Ixz, Iyz] (positive definite), contact [k_e, k_d, k_f, mu_f] (the
+ * particle contact model of App. A.1 applied at every vertex).  One step
+ * (semi-implicit Euler, App. A.2), with a_k = R(r) p_k for the body-frame
+ * vertices p_k:
+ *     F = sum_k f_k, tau = sum_k a_k x f_k, f_k = contact(x + a_k, v + omega x a_k)
+ *     v+ = v + dt (F / m + g)
+ *     omega+ = omega + dt Iw^-1 (tau - omega x (Iw omega)),  Iw = R I R^T
+ *     x+ = x + dt v+,   r+ = normalise(r + dt/2 [0, omega+] (x) r)
+ * R(r) is the rotation matrix of a unit quaternion: pass unit r0 (later states
+ * are normalised by the step). */
+#define GSIM_RIGID_MAX_VERTS 256
+typedef struct gsim_rigid gsim_rigid;
+typedef struct {
+    int dtype;                 /* GSIM_F32 or GSIM_F64 */
+    int n_bodies;              /* >= 1 */
+    const int64_t* vert_off;   /* [n_bodies+1]; body b owns vertices [off[b], off[b+1]), 1..256 of them */
+    const double* verts;       /* [n_verts][3] body-frame positions relative to the centre of mass */
+    const double* gravity;     /* [n_bodies][3] */
+    const double* dt;          /* [n_bodies] */
+    const double* ground;      /* [n_bodies][4] plane (nx, ny, nz, d), or NULL (y = 0) */
+    const uint8_t* contact_on; /* [n_bodies] nonzero = vertex contact with the plane, or NULL (off) */
+} gsim_rigid_desc;
+typedef struct {
+    const void* mass;    /* [n_bodies] */
+    const void* inertia; /* [n_bodies][6] */
+    const void* contact; /* [n_bodies][4] */
+} gsim_rigid_params;
+typedef struct {         /* gradients accumulate (+=); NULL = not requested */
+    void* mass;
+    void* inertia;
+    void* contact;       /* only bodies with contact_on */
+} gsim_rigid_grads;
+
+/* Exact device bytes of a rigid model's workspace.  Errors: GSIM_E_INVALID,
+ * GSIM_E_UNSUPPORTED (a body with more than GSIM_RIGID_MAX_VERTS vertices),
+ * GSIM_E_NONFINITE. */
+int gsim_rigid_sizes(const gsim_rigid_desc* desc, size_t* workspace_bytes);
+/* Binds a rigid model to a caller-owned, 256-byte aligned device workspace and
+ * uploads the bodies (synchronises `stream`). */
+int gsim_rigid_init(const gsim_rigid_desc* desc, void* d_workspace, size_t bytes, void* stream, gsim_rigid** out);
+int gsim_rigid_destroy(gsim_rigid* model);
+/* n_steps steps from s0 [n_bodies][13]; writes every state to traj
+ * [(n_steps + 1)][n_bodies][13] (traj[0] = s0; the adjoint reads them).  One
+ * launch for the whole rollout. */
+int gsim_rigid_rollout(gsim_rigid* model, const gsim_rigid_params* params, const void* s0, int n_steps, void* traj,
+                       void* stream);
+/* loss[b] = mean over body b's vertices of |x + R p_k - target_k|^2 (target
+ * [n_verts][3], world frame); state_bar [n_bodies][13] (or NULL) receives its
+ * gradient with respect to the state (x and r; the velocity entries are 0). */
+int gsim_rigid_loss(gsim_rigid* model, const void* state, const void* target, void* loss, void* state_bar,
+                    void* stream);
+/* Reverse pass over the stored trajectory (App. A): from adj_final (the adjoint
+ * of state n_steps) to adj_init (of state 0), accumulating parameter gradients. */
+int gsim_rigid_rollout_backward(gsim_rigid* model, const gsim_rigid_params* params, const void* traj, int n_steps,
+                                const void* adj_final, void* adj_init, const gsim_rigid_grads* grads, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* SERVING ENGINE: continuous batching of rollout-gradient queries           */
 /* ------------------------------------------------------------------------ */
 /* A query is one FP32 body (n_bodies == 1) with parameters, start state and

@@ -81,3 +81,30 @@ class Controller(torch.autograd.Function):
 def controller(W, omega, dt, n_steps, t0=0, scale=1.0):
     """Differentiable per-step actuation rows from controller weights W."""
     return Controller.apply(W, omega, dt, n_steps, t0, scale)
+
+
+class RigidRollout(torch.autograd.Function):
+    """(s0 [nb, 13], mass [nb], inertia [nb, 6], contact [nb, 4]) -> final state after
+    n_steps rigid-body steps (App. A.1 "Rigid bodies"); the forward stores every
+    state (13 numbers per body per step) and the backward is the reverse-pass kernel
+    over them."""
+
+    @staticmethod
+    def forward(ctx, model, n_steps, s0, mass, inertia, contact):
+        params = {"mass": mass.detach().contiguous(), "inertia": inertia.detach().contiguous(),
+                  "contact": contact.detach().contiguous()}
+        traj = model.rollout(params, s0.detach().contiguous(), int(n_steps))
+        ctx.model, ctx.n_steps, ctx.params, ctx.traj = model, int(n_steps), params, traj
+        return traj[-1].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        m = ctx.model
+        grads = m.zero_grads()
+        s0b = m.rollout_backward(ctx.params, ctx.traj, ctx.n_steps, g.contiguous(), grads)
+        return None, None, s0b, grads["mass"], grads["inertia"], grads["contact"]
+
+
+def rigid_rollout(model, params, s0, n_steps):
+    """Differentiable rigid rollout: params = {mass, inertia, contact} tensors."""
+    return RigidRollout.apply(model, n_steps, s0, params["mass"], params["inertia"], params["contact"])

@@ -32,6 +32,8 @@ ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan
                "gsim_step", "gsim_step_backward", "gsim_rollout", "gsim_rollout_backward",
                "gsim_loss_mse", "gsim_model_set_timing", "gsim_model_read_timing",
                "gsim_controller_forward", "gsim_controller_backward",
+               "gsim_rigid_sizes", "gsim_rigid_init", "gsim_rigid_destroy", "gsim_rigid_rollout", "gsim_rigid_loss",
+               "gsim_rigid_rollout_backward",
                "gsim_engine_create", "gsim_engine_destroy", "gsim_engine_query_bytes", "gsim_engine_submit",
                "gsim_engine_tick", "gsim_engine_poll", "gsim_engine_stats")
 GSIM_F32, GSIM_F64 = 32, 64
@@ -62,6 +64,19 @@ class _Params(C.Structure):
     _fields_ = [("mu", C.c_void_p), ("lam", C.c_void_p), ("act", C.c_void_p), ("k_tri", C.c_void_p),
                 ("mass", C.c_void_p), ("contact", C.c_void_p), ("hact", C.c_void_p), ("act_stride", C.c_int64),
                 ("hact_stride", C.c_int64), ("air", C.c_void_p)]
+
+
+class _RigidDesc(C.Structure):
+    _fields_ = [("dtype", C.c_int), ("n_bodies", C.c_int), ("vert_off", C.c_void_p), ("verts", C.c_void_p),
+                ("gravity", C.c_void_p), ("dt", C.c_void_p), ("ground", C.c_void_p), ("contact_on", C.c_void_p)]
+
+
+class _RigidParams(C.Structure):
+    _fields_ = [("mass", C.c_void_p), ("inertia", C.c_void_p), ("contact", C.c_void_p)]
+
+
+class _RigidGrads(C.Structure):
+    _fields_ = [("mass", C.c_void_p), ("inertia", C.c_void_p), ("contact", C.c_void_p)]
 
 
 class _Ctrl(C.Structure):
@@ -112,6 +127,13 @@ def load():
         i64 = C.c_int64
         lib.gsim_controller_forward.argtypes = [ip, C.POINTER(_Ctrl), vp, i64, i64, i64, vp, vp]
         lib.gsim_controller_backward.argtypes = [ip, C.POINTER(_Ctrl), vp, vp, i64, i64, i64, vp, vp]
+        RP, RG = C.POINTER(_RigidParams), C.POINTER(_RigidGrads)
+        lib.gsim_rigid_sizes.argtypes = [C.POINTER(_RigidDesc), C.POINTER(C.c_size_t)]
+        lib.gsim_rigid_init.argtypes = [C.POINTER(_RigidDesc), vp, C.c_size_t, vp, C.POINTER(vp)]
+        lib.gsim_rigid_destroy.argtypes = [vp]
+        lib.gsim_rigid_rollout.argtypes = [vp, RP, vp, ip, vp, vp]
+        lib.gsim_rigid_loss.argtypes = [vp, vp, vp, vp, vp, vp]
+        lib.gsim_rigid_rollout_backward.argtypes = [vp, RP, vp, ip, vp, vp, RG, vp]
         _lib = lib
     return _lib
 
@@ -497,3 +519,100 @@ class Model:
         _check(load().gsim_loss_mse(self._h, self._state(x, None), _ptr(target), _ptr(loss), self._state(xb, vb),
                                     _stream(stream)))
         return loss, xb, vb
+
+
+# ----------------------------------------------------------------------------------
+# Rigid bodies (gsim_rigid_*)
+# ----------------------------------------------------------------------------------
+
+class RigidModel:
+    """A batch of rigid bodies (``workloads.RigidBody``-like) bound to a device
+    workspace.  States are [n_bodies, 13] = x, quaternion (w first), v, omega;
+    trajectories [(T + 1), n_bodies, 13]; parameters mass [nb], inertia [nb, 6],
+    contact [nb, 4]."""
+
+    def __init__(self, bodies, dtype=torch.float32, device="cuda"):
+        lib = load()
+        self.bodies = list(bodies)
+        self.dtype, self.device = dtype, torch.device(device)
+        self.nb = len(self.bodies)
+        self.vert_off = np.zeros(self.nb + 1, np.int64)
+        for i, b in enumerate(self.bodies):
+            self.vert_off[i + 1] = self.vert_off[i] + len(b.verts)
+        self.n_verts = int(self.vert_off[-1])
+        self._verts = np.ascontiguousarray(np.concatenate([np.asarray(b.verts, np.float64) for b in self.bodies]))
+        self._grav = np.ascontiguousarray([b.gravity for b in self.bodies], np.float64)
+        self._dt = np.ascontiguousarray([b.dt for b in self.bodies], np.float64)
+        self._plane = np.ascontiguousarray([b.plane for b in self.bodies], np.float64)
+        self._on = np.ascontiguousarray([1 if b.ground else 0 for b in self.bodies], np.uint8)
+        d = _RigidDesc()
+        d.dtype = GSIM_F64 if dtype == torch.float64 else GSIM_F32
+        d.n_bodies = self.nb
+        d.vert_off, d.verts = self.vert_off.ctypes.data, self._verts.ctypes.data
+        d.gravity, d.dt, d.ground, d.contact_on = (self._grav.ctypes.data, self._dt.ctypes.data,
+                                                   self._plane.ctypes.data, self._on.ctypes.data)
+        nbytes = C.c_size_t()
+        _check(lib.gsim_rigid_sizes(C.byref(d), C.byref(nbytes)))
+        self.workspace = torch.empty(max(int(nbytes.value), 256) + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        h = C.c_void_p()
+        _check(lib.gsim_rigid_init(C.byref(d), C.c_void_p(self.workspace.data_ptr() + off), nbytes.value,
+                                   _stream(None), C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.gsim_rigid_destroy(h)
+            self._h = None
+
+    def _t(self, a):
+        return torch.as_tensor(np.ascontiguousarray(a, np.float64)).to(self.device, self.dtype)
+
+    def params_from_bodies(self):
+        return {"mass": self._t([b.mass for b in self.bodies]), "inertia": self._t([b.inertia for b in self.bodies]),
+                "contact": self._t([b.contact() for b in self.bodies])}
+
+    def initial_state(self):
+        return self._t([b.s0 for b in self.bodies])
+
+    def zero_grads(self):
+        return {"mass": torch.zeros(self.nb, dtype=self.dtype, device=self.device),
+                "inertia": torch.zeros(self.nb, 6, dtype=self.dtype, device=self.device),
+                "contact": torch.zeros(self.nb, 4, dtype=self.dtype, device=self.device)}
+
+    @staticmethod
+    def _params(p):
+        s = _RigidParams()
+        s.mass, s.inertia, s.contact = _ptr(p["mass"]), _ptr(p["inertia"]), _ptr(p["contact"])
+        return s
+
+    def new_trajectory(self, n_steps):
+        return torch.empty(int(n_steps) + 1, self.nb, 13, dtype=self.dtype, device=self.device)
+
+    def rollout(self, params, s0, n_steps, traj=None, stream=None):
+        traj = self.new_trajectory(n_steps) if traj is None else traj
+        if traj.shape != (int(n_steps) + 1, self.nb, 13) or not traj.is_contiguous():
+            raise ValueError("traj must be a contiguous [n_steps + 1, n_bodies, 13] tensor")
+        _check(load().gsim_rigid_rollout(self._h, C.byref(self._params(params)), _ptr(s0.contiguous()), int(n_steps),
+                                         _ptr(traj), _stream(stream)))
+        return traj
+
+    def loss(self, state, target, stream=None):
+        """(loss [nb], d loss / d state [nb, 13]) for world target vertices [n_verts, 3]."""
+        loss = torch.empty(self.nb, dtype=self.dtype, device=self.device)
+        sbar = torch.empty(self.nb, 13, dtype=self.dtype, device=self.device)
+        _check(load().gsim_rigid_loss(self._h, _ptr(state.contiguous()), _ptr(target.contiguous()), _ptr(loss),
+                                      _ptr(sbar), _stream(stream)))
+        return loss, sbar
+
+    def rollout_backward(self, params, traj, n_steps, sbar_final, grads=None, stream=None):
+        """Adjoint of the initial state; parameter gradients accumulate into grads."""
+        out = torch.empty(self.nb, 13, dtype=self.dtype, device=self.device)
+        g = _RigidGrads()
+        if grads:
+            g.mass, g.inertia, g.contact = _ptr(grads.get("mass")), _ptr(grads.get("inertia")), _ptr(grads.get("contact"))
+        _check(load().gsim_rigid_rollout_backward(self._h, C.byref(self._params(params)), _ptr(traj), int(n_steps),
+                                                  _ptr(sbar_final.contiguous()), _ptr(out), C.byref(g),
+                                                  _stream(stream)))
+        return out

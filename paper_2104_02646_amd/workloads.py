@@ -521,3 +521,120 @@ def query_body(q: Query) -> Body:
         b = cloth(q.seed, n=q.size)
     b.target = synthetic_target(b, q.seed + 1)
     return b
+
+
+# ----------------------------------------------------------------------------------
+# Rigid bodies
+# ----------------------------------------------------------------------------------
+
+@dataclass
+class RigidBody:
+    """One rigid body: body-frame vertices about the centre of mass, mass, body-frame
+    inertia [Ixx, Iyy, Izz, Ixy, Ixz, Iyz], vertex contact [k_e, k_d, k_f, mu_f],
+    environment, and the start state s0 = [x, quaternion (w first), v, omega]."""
+    verts: np.ndarray
+    mass: float
+    inertia: np.ndarray
+    ke: float = 300.0
+    kd: float = 1.0
+    kf: float = 100.0
+    muf: float = 0.5
+    gravity: tuple = GRAVITY
+    ground: bool = True
+    plane: tuple = GROUND
+    dt: float = 1.0 / 600.0
+    s0: np.ndarray = field(default_factory=lambda: np.array([0, 0, 0, 1, 0, 0, 0, 0, 0, 0, 0, 0, 0], float))
+
+    @property
+    def nv(self):
+        return len(self.verts)
+
+    def contact(self):
+        return np.array([self.ke, self.kd, self.kf, self.muf], np.float64)
+
+    def round_to(self, dtype):
+        import copy
+        b = copy.copy(self)
+        r = lambda a: np.asarray(a, dtype).astype(np.float64)
+        b.verts, b.inertia, b.s0 = r(self.verts), r(self.inertia), r(self.s0)
+        for k in ("mass", "ke", "kd", "kf", "muf", "dt"):
+            setattr(b, k, float(np.asarray(getattr(self, k), dtype)))
+        b.gravity = tuple(float(np.asarray(g, dtype)) for g in self.gravity)
+        b.plane = tuple(float(np.asarray(g, dtype)) for g in self.plane)
+        return b
+
+
+def _box_surface(a, b, c, n):
+    """Vertices on the surface of an a x b x c box (n points per edge), centred."""
+    t = np.linspace(-0.5, 0.5, n)
+    g = np.array(np.meshgrid(t, t, t, indexing="ij")).reshape(3, -1).T
+    on = (np.abs(g) == 0.5).any(1)
+    return g[on] * np.array([a, b, c])
+
+
+def _cylinder_surface(r, h, n_around, n_rings):
+    """Vertices on two rims and intermediate rings of a cylinder along y, plus the
+    two cap centres, centred."""
+    th = 2 * np.pi * np.arange(n_around) / n_around
+    ys = np.linspace(-h / 2, h / 2, n_rings)
+    pts = [np.stack([r * np.cos(th), np.full(n_around, y), r * np.sin(th)], 1) for y in ys]
+    return np.concatenate(pts + [np.array([[0, -h / 2, 0], [0, h / 2, 0]])])
+
+
+def _sphere_surface(r, n_lat, n_lon):
+    """Latitude-longitude vertices of a sphere plus its poles."""
+    lat = np.pi * (np.arange(1, n_lat + 1) / (n_lat + 1) - 0.5)
+    lon = 2 * np.pi * np.arange(n_lon) / n_lon
+    la, lo = np.meshgrid(lat, lon, indexing="ij")
+    pts = np.stack([r * np.cos(la) * np.cos(lo), r * np.sin(la), r * np.cos(la) * np.sin(lo)], -1).reshape(-1, 3)
+    return np.concatenate([pts, [[0, -r, 0], [0, r, 0]]])
+
+
+def _random_quaternion(rng):
+    q = rng.normal(size=4)
+    return q / np.linalg.norm(q)
+
+
+def rigid_body(seed: int, kind: str | None = None):
+    """A seeded rigid body for the rigid parameter-estimation task (Sec. 5.1 rigid;
+    App. "Dataset": primitive shapes of at most 250 vertices with sampled sizes,
+    densities, contact parameters, poses and initial velocities).  Shapes: box,
+    cylinder or sphere (solid, uniform density; analytic inertia), scale U(0.5, 1.5)
+    m per axis, density U(2, 12) kg/m^3, k_e U(100, 500), k_d U(0, 5) (the paper's
+    1 .. 500 range for k_d is not stable with explicit steps at these masses),
+    k_f U(1, 500), mu_f U(0.2, 1.0); start 0.2 .. 1 m above the ground in a random
+    orientation with v0 ~ U(-2, 2)^3 (plus 1 m/s downwards) and omega0 ~ U(-3, 3)^3;
+    gravity, dt = 1/600."""
+    rng = np.random.default_rng(seed)
+    kind = kind or ["box", "cylinder", "sphere"][int(rng.integers(3))]
+    rho = rng.uniform(2.0, 12.0)
+    if kind == "box":
+        a, b, c = rng.uniform(0.5, 1.5, 3)
+        verts = _box_surface(a, b, c, int(rng.integers(2, 7)))
+        m = rho * a * b * c
+        inertia = np.array([m * (b * b + c * c) / 12, m * (a * a + c * c) / 12, m * (a * a + b * b) / 12, 0, 0, 0])
+    elif kind == "cylinder":
+        r, h = rng.uniform(0.25, 0.75), rng.uniform(0.5, 1.5)
+        verts = _cylinder_surface(r, h, int(rng.integers(8, 33)), int(rng.integers(2, 7)))
+        m = rho * np.pi * r * r * h
+        inertia = np.array([m * (3 * r * r + h * h) / 12, m * r * r / 2, m * (3 * r * r + h * h) / 12, 0, 0, 0])
+    else:
+        r = rng.uniform(0.25, 0.75)
+        verts = _sphere_surface(r, int(rng.integers(4, 12)), int(rng.integers(6, 20)))
+        m = rho * 4 / 3 * np.pi * r ** 3
+        inertia = np.array([0.4 * m * r * r] * 3 + [0, 0, 0])
+    verts = verts[:250]
+    q = _random_quaternion(rng)
+    s0 = np.zeros(13)
+    s0[3:7] = q
+    lowest = -(np.abs(verts).sum(1)).max()  # bound on the lowest point in any orientation
+    s0[1] = -lowest + rng.uniform(0.2, 1.0)
+    s0[7:10] = rng.uniform(-2, 2, 3) + np.array([0.0, -1.0, 0.0])
+    s0[10:13] = rng.uniform(-3, 3, 3)
+    return RigidBody(verts=verts, mass=m, inertia=inertia, ke=rng.uniform(100, 500), kd=rng.uniform(0, 5),
+                     kf=rng.uniform(1, 500), muf=rng.uniform(0.2, 1.0), s0=s0)
+
+
+def rigid_batch(seed: int = 80, n: int = 1024):
+    """n seeded rigid bodies (box / cylinder / sphere, 8 .. 250 vertices each)."""
+    return [rigid_body(seed * 100000 + i) for i in range(n)]

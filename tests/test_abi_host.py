@@ -207,7 +207,9 @@ def test_ctypes_structs_match_header(gs, tmp_path):
     import subprocess
     from paper_2104_02646_amd import serve
     mirrors = {"gsim_model_desc": gs._Desc, "gsim_state": gs._State, "gsim_params": gs._Params,
-               "gsim_grads": gs._Grads, "gsim_query": serve._Query, "gsim_result": serve._Result}
+               "gsim_grads": gs._Grads, "gsim_query": serve._Query, "gsim_result": serve._Result,
+               "gsim_controller": gs._Ctrl, "gsim_rigid_desc": gs._RigidDesc, "gsim_rigid_params": gs._RigidParams,
+               "gsim_rigid_grads": gs._RigidGrads}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gsim.h"', "int main(void) {"]
     expect = []
     for cname, cls in mirrors.items():
@@ -223,3 +225,30 @@ def test_ctypes_structs_match_header(gs, tmp_path):
     subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(s) for s in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
     assert got == expect
+
+
+def test_rigid_description_validation(gs):
+    """gsim_rigid_sizes validates on the host: vertex counts 1..256 per body,
+    finite vertices, dt > 0; the workspace size grows with the vertex count."""
+    import ctypes as C
+    lib = gs.load()
+
+    def sizes(nv_per_body, verts_fill=0.1, dt=1e-3):
+        off = np.cumsum([0] + list(nv_per_body)).astype(np.int64)
+        verts = np.full((int(off[-1]), 3), verts_fill, np.float64)
+        nb = len(nv_per_body)
+        grav = np.zeros((nb, 3))
+        dts = np.full(nb, dt)
+        d = gs._RigidDesc()
+        d.dtype, d.n_bodies = 32, nb
+        d.vert_off, d.verts, d.gravity, d.dt = off.ctypes.data, verts.ctypes.data, grav.ctypes.data, dts.ctypes.data
+        out = C.c_size_t()
+        rc = lib.gsim_rigid_sizes(C.byref(d), C.byref(out))
+        return rc, out.value
+    rc, small = sizes([8, 250])
+    assert rc == 0
+    rc, big = sizes([8, 250, 256])
+    assert rc == 0 and big > small
+    assert sizes([257])[0] == -7          # GSIM_E_UNSUPPORTED
+    assert sizes([8], verts_fill=float("nan"))[0] == -6
+    assert sizes([8], dt=0.0)[0] == -1

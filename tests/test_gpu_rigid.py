@@ -1,0 +1,134 @@
+"""Rigid bodies on the HIP path vs the FP64 oracle (needs an MI355X).
+
+One wavefront per body, whole rollout per launch.  Cases: FP64 rollouts of boxes,
+cylinders and spheres with ground contact (every state against the oracle's) and
+their gradients for mass, inertia, contact and the initial state against the
+oracle's reverse pass (forward-mode duals); FP32 at the stated tolerances; a batch
+where each body equals itself alone; free flight; the autograd Function.
+"""
+import numpy as np
+import pytest
+
+from helpers import rel
+from oracle.oracle import RigidOracle
+from paper_2104_02646_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2104_02646_amd import gsim
+    gsim.load()
+    return gsim
+
+
+def oracle_of(b):
+    return RigidOracle(b.verts, gravity=b.gravity, ground=b.ground, plane=b.plane, dt=b.dt)
+
+
+def target_of(b, seed):
+    rng = np.random.default_rng(seed)
+    return b.verts + b.s0[:3] + np.array([0.3, -0.2, 0.1]) + rng.normal(0, 0.01, b.verts.shape)
+
+
+def _gpu(gs, bodies, T, dtype, targets):
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    m = gs.RigidModel(bodies, tdt)
+    p = m.params_from_bodies()
+    traj = m.rollout(p, m.initial_state(), T)
+    tgt = torch.as_tensor(np.concatenate(targets)).to("cuda", tdt)
+    loss, sbar = m.loss(traj[-1], tgt)
+    g = m.zero_grads()
+    s0b = m.rollout_backward(p, traj, T, sbar, g)
+    torch.cuda.synchronize()
+    n = lambda t: t.double().cpu().numpy()
+    return n(traj), n(loss), {"s0": n(s0b), "m": n(g["mass"]), "I": n(g["inertia"]), "c": n(g["contact"])}
+
+
+@pytest.mark.parametrize("dtype,pos_tol,grad_tol", [("f64", 1e-10, 1e-8), ("f32", 1e-4, 1e-3)])
+def test_rigid_batch_against_oracle(gs, dtype, pos_tol, grad_tol):
+    """Six bodies (2 boxes, 2 cylinders, 2 spheres, 8 .. 250 vertices), 240 steps with
+    ground contact and friction: trajectories, loss and every gradient per body."""
+    T = 240
+    bodies = [W.rigid_body(700 + i, kind) for i, kind in enumerate(["box", "cylinder", "sphere"] * 2)]
+    if dtype == "f32":
+        bodies = [b.round_to(np.float32) for b in bodies]
+    targets = [target_of(b, 9 + i).astype(np.float32 if dtype == "f32" else np.float64).astype(np.float64)
+               for i, b in enumerate(bodies)]
+    traj, loss, g = _gpu(gs, bodies, T, dtype, targets)
+    worst = {}
+    touched = 0
+    for i, b in enumerate(bodies):
+        o = oracle_of(b)
+        L, gr, st = o.loss_and_grad(b.s0, b.mass, b.inertia, b.contact(), T, targets[i])
+        errs = {"x": rel(traj[:, i, :], st), "loss": abs(loss[i] - L) / L, "s0": rel(g["s0"][i], gr["s0"]),
+                "I": rel(g["I"][i], gr["I"])}
+        if np.abs(gr["c"]).max() > 0:  # bodies that reached the ground (the others have m-bar = c-bar = 0)
+            touched += 1
+            errs["c"] = rel(g["c"][i], gr["c"])
+            errs["m"] = abs(g["m"][i] - gr["m"]) / abs(gr["m"])
+        else:
+            assert g["m"][i] == 0.0 and np.all(g["c"][i] == 0.0)
+        for k, v in errs.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+    print("rigid %s worst errors:" % dtype, {k: "%.2e" % v for k, v in worst.items()})
+    assert touched >= 3, "most bodies must hit the ground"
+    assert worst["x"] < pos_tol
+    for k in ("loss", "s0", "m", "I", "c"):
+        assert worst[k] < grad_tol, (k, worst[k])
+
+
+def test_rigid_batch_alone_equals_in_mix_bitwise(gs):
+    T = 120
+    bodies = [W.rigid_body(800 + i) for i in range(9)]
+    targets = [target_of(b, i) for i, b in enumerate(bodies)]
+    traj, loss, g = _gpu(gs, bodies, T, "f32", targets)
+    for i in (0, 4, 8):
+        t1, l1, g1 = _gpu(gs, [bodies[i]], T, "f32", [targets[i]])
+        assert np.array_equal(traj[:, i], t1[:, 0])
+        assert loss[i] == l1[0]
+        for k in g:
+            assert np.array_equal(g[k][i], g1[k][0]), k
+
+
+def test_rigid_free_flight_closed_form(gs):
+    b = W.rigid_body(810, "box")
+    b.ground = False
+    T = 100
+    m = gs.RigidModel([b], torch.float64)
+    traj = m.rollout(m.params_from_bodies(), m.initial_state(), T).cpu().numpy()
+    n = np.arange(T + 1)[:, None]
+    g = np.array(b.gravity)
+    exp = b.s0[:3] + n * b.dt * b.s0[7:10] + g * b.dt ** 2 * n * (n + 1) / 2
+    assert np.abs(traj[:, 0, 0:3] - exp).max() < 1e-12
+    assert np.abs(np.linalg.norm(traj[:, 0, 3:7], axis=1) - 1).max() < 1e-14
+
+
+def test_rigid_autograd(gs):
+    from paper_2104_02646_amd.autograd import rigid_rollout
+    T = 150
+    bodies = [W.rigid_body(820 + i).round_to(np.float32) for i in range(3)]
+    m = gs.RigidModel(bodies, torch.float32)
+    p = {k: v.clone().requires_grad_(True) for k, v in m.params_from_bodies().items()}
+    s0 = m.initial_state().requires_grad_(True)
+    sT = rigid_rollout(m, p, s0, T)
+    goal = torch.tensor([1.0, 0.5, -0.5], device="cuda")
+    loss = ((sT[:, 0:3] - goal) ** 2).sum()
+    loss.backward()
+    for i, b in enumerate(bodies):
+        o = oracle_of(b)
+        st = o.rollout(b.s0, b.mass, b.inertia, b.contact(), T)
+        sb = np.zeros(13)
+        sb[0:3] = 2 * (st[-1, 0:3] - goal.cpu().numpy())
+        g = {"m": 0.0, "I": np.zeros(6)}
+        for t in range(T - 1, -1, -1):
+            sb, mb, Ib, cb = o.step_vjp(st[t], b.mass, b.inertia, b.contact(), sb)
+            g["m"] += mb
+            g["I"] += Ib
+        assert rel(s0.grad[i].double().cpu().numpy(), sb) < 1e-3
+        assert abs(float(p["mass"].grad[i]) - g["m"]) <= 1e-3 * abs(g["m"])  # 0 == 0 for a body in the air
+        assert rel(p["inertia"].grad[i].double().cpu().numpy(), g["I"]) < 1e-3
