@@ -255,6 +255,54 @@ def cloth_air_batch(steps, n_cloths=64, T=100, K=10):
     return out
 
 
+def rigid_batch_bench(steps, n_bodies=1024, T=400):
+    """The rigid parameter-estimation step at batch scale: 1024 rigid bodies (boxes,
+    cylinders, spheres of 8 .. 250 vertices) with vertex contact, T steps forward
+    (one launch, every state stored), vertex loss, reverse pass (one launch) with
+    mass, inertia, contact and initial-state gradients.  Each body's steps form one
+    dependent chain inside one wavefront, so the launches are bound by that chain's
+    latency, not by HBM (a body-step moves 104 bytes of state)."""
+    import torch
+    from paper_2104_02646_amd import gsim, workloads as W
+    bodies = [b.round_to(np.float32) for b in W.rigid_batch(80, n_bodies)]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        m = gsim.RigidModel(bodies, torch.float32)
+        p = m.params_from_bodies()
+        s0 = m.initial_state()
+        tgt = torch.as_tensor(np.concatenate([b.verts + b.s0[:3] + 0.2 for b in bodies]), dtype=torch.float32,
+                              device="cuda")
+        traj = m.new_trajectory(T)
+        g = m.zero_grads()
+
+        def one():
+            m.rollout(p, s0, T, traj=traj, stream=stream)
+            loss, sbar = m.loss(traj[-1], tgt, stream=stream)
+            for t in g.values():
+                t.zero_()
+            return m.rollout_backward(p, traj, T, sbar, g, stream=stream)
+        one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            one()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        m.rollout(p, s0, T, traj=traj, stream=stream)
+        ev[1].record(stream)
+        loss, sbar = m.loss(traj[-1], tgt, stream=stream)
+        m.rollout_backward(p, traj, T, sbar, g, stream=stream)
+        ev[2].record(stream)
+        ev[2].synchronize()
+    nv = sum(b.nv for b in bodies)
+    return {"workload": "%d rigid bodies (%d vertices in all), %d steps forward + vertex loss + reverse pass"
+                        % (n_bodies, nv, T),
+            "ms_per_step": sec * 1e3, "body_steps_per_s": n_bodies * T / sec, "vertex_steps_per_s": nv * T / sec,
+            "forward_launch_ms": ev[0].elapsed_time(ev[1]), "loss_and_adjoint_ms": ev[1].elapsed_time(ev[2])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +321,7 @@ def main():
     ap.add_argument("--serve-queries", type=int, default=400, help="measured queries of the serving trace (0 = skip)")
     ap.add_argument("--no-control", action="store_true", help="skip the actuated (controller-driven) step")
     ap.add_argument("--no-cloth", action="store_true", help="skip the lift/drag cloth batch")
+    ap.add_argument("--no-rigid", action="store_true", help="skip the rigid-body batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device tensor copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -459,6 +508,8 @@ def main():
         result["control"] = control
     if not args.no_cloth:
         result["control_cloth"] = cloth_air_batch(args.steps)
+    if not args.no_rigid:
+        result["rigid"] = rigid_batch_bench(args.steps)
     if args.serve_queries > 0:
         result["serving"] = serving(args.serve_queries, max(20, args.serve_queries // 10), K,
                                     lambda msg: print(msg, file=sys.stderr, flush=True))
