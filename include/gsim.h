@@ -397,6 +397,38 @@ int gsim_rigid_rollout_backward(gsim_rigid* model, const gsim_rigid_params* para
                                 const void* adj_final, void* adj_init, const gsim_rigid_grads* grads, void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* SOFT SILHOUETTE RENDERER                                                  */
+/* ------------------------------------------------------------------------ */
+/* The paper puts its losses on rendered pixels through a differentiable soft
+ * rasterizer (Sec. 3, rendering appendix: SoftRas, DIB-R).  Built here: SoftRas's
+ * silhouette.  Vertex X (SoA positions, e.g. a model's particle state) projects to
+ * pixel coordinates u = P0.[X,1] / P2.[X,1], v = P1.[X,1] / P2.[X,1] (P a 3x4
+ * matrix, row-major; vertices must have P2.[X,1] > 0); triangle j covers pixel
+ * (row, col), centre (col + 0.5, row + 0.5), with D_j = sigmoid(+-d^2 / sigma), d the
+ * distance to its edges (+ inside); image[row][col] = 1 - prod_j (1 - D_j).  Terms
+ * outside a triangle with d^2 > 13.8155 sigma (D < 1e-6) are dropped. */
+typedef struct gsim_raster gsim_raster;
+typedef struct {
+    double P[12];  /* camera matrix, world -> homogeneous pixel coordinates */
+    double sigma;  /* blur, pixel^2 (> 0) */
+} gsim_camera;
+/* Exact device bytes of a renderer for n_verts vertices, n_tris triangles and an
+ * image of height x width pixels. */
+int gsim_raster_sizes(int dtype, int64_t n_verts, int64_t n_tris, int height, int width, size_t* workspace_bytes);
+/* tris: host [n_tris][3] vertex indices (copied).  Errors: GSIM_E_INVALID,
+ * GSIM_E_TOPOLOGY (index out of range), GSIM_E_WORKSPACE. */
+int gsim_raster_init(int dtype, int64_t n_verts, int64_t n_tris, const int32_t* tris, int height, int width,
+                     void* d_workspace, size_t bytes, void* stream, gsim_raster** out);
+int gsim_raster_destroy(gsim_raster* raster);
+/* image [height][width] of the vertices x ([3][n_verts] SoA, device). */
+int gsim_raster_forward(gsim_raster* raster, const gsim_camera* camera, const void* x, void* image, void* stream);
+/* x_bar ([3][n_verts], +=) of sum(image_bar * image) for the same x and camera
+ * (recomputes what it needs; independent of earlier forward calls).  Calls on one
+ * renderer must not overlap (they share its workspace). */
+int gsim_raster_backward(gsim_raster* raster, const gsim_camera* camera, const void* x, const void* image_bar,
+                         void* x_bar, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* SERVING ENGINE: continuous batching of rollout-gradient queries           */
 /* ------------------------------------------------------------------------ */
 /* A query is one FP32 body (n_bodies == 1) with parameters, start state and

@@ -108,3 +108,26 @@ class RigidRollout(torch.autograd.Function):
 def rigid_rollout(model, params, s0, n_steps):
     """Differentiable rigid rollout: params = {mass, inertia, contact} tensors."""
     return RigidRollout.apply(model, n_steps, s0, params["mass"], params["inertia"], params["contact"])
+
+
+class SoftSilhouette(torch.autograd.Function):
+    """x [3, n_verts] (SoA positions) -> soft silhouette image [H, W] through the
+    renderer's mesh and a 3x4 camera matrix P (the paper's pixel losses; SoftRas
+    silhouette).  Forward and backward are the renderer's HIP kernels."""
+
+    @staticmethod
+    def forward(ctx, renderer, P, sigma, x):
+        x = x.detach().contiguous()
+        ctx.save_for_backward(x)
+        ctx.renderer, ctx.P, ctx.sigma = renderer, P, sigma
+        return renderer.forward(x, P, sigma)
+
+    @staticmethod
+    def backward(ctx, g):
+        (x,) = ctx.saved_tensors
+        return None, None, None, ctx.renderer.backward(x, ctx.P, ctx.sigma, g.contiguous())
+
+
+def render(renderer, x, P, sigma):
+    """Differentiable soft silhouette of positions x [3, n_verts]."""
+    return SoftSilhouette.apply(renderer, P, sigma, x)

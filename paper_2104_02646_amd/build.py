@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libgsim.so")
-SOURCES = ["gsim_kernels.hip", "gsim_control.hip", "gsim_rigid.hip", "gsim_api.cpp", "gsim_engine.cpp"]
+SOURCES = ["gsim_kernels.hip", "gsim_control.hip", "gsim_rigid.hip", "gsim_raster.hip", "gsim_api.cpp", "gsim_engine.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU ops.

@@ -1,0 +1,396 @@
+// Soft silhouette renderer (SoftRas-style; the paper renders its meshes with a
+// differentiable soft rasterizer so that losses sit on pixels, Sec. 3 and the
+// rendering appendix) and its adjoint, on CDNA4.
+//
+// Each vertex X is projected by a 3x4 camera matrix P to pixel coordinates
+// u = P0.[X,1] / P2.[X,1], v = P1.[X,1] / P2.[X,1].  Triangle j covers pixel p
+// (centre (col + 0.5, row + 0.5)) with probability D_j = sigmoid(x_j),
+// x_j = +-d_j^2 / sigma (d_j: distance from p to the triangle's edges; + inside);
+// the image is I = 1 - prod_j (1 - D_j) = 1 - T with the transmittance
+// T = exp(-sum_j softplus(x_j)).  Terms of pixels outside a triangle with
+// d^2 > CUT sigma (D < 1e-6) are dropped.
+//
+// Adjoint: dI / dx_j = T D_j (prod over the other triangles times D_j (1 - D_j)),
+// which needs no division by 1 - D_j, and d(d^2) / d(endpoint) of the nearest edge
+// point q = s0 + t (s1 - s0) is -2 (1 - t) (p - q) and -2 t (p - q).
+//
+// Kernels: projection (one thread per vertex); forward (one thread per pixel of a
+// 16 x 16 tile, triangles staged through LDS 256 at a time, a uniform
+// tile-vs-bounding-box test skipping triangles that cannot reach the tile);
+// triangle adjoint (one thread per triangle over the pixels of its widened
+// bounding box, the transmittance recomputed by the forward kernel first); vertex
+// gather (one thread per vertex summing its triangle corners in a fixed order, then
+// through the projection).  No atomics anywhere: results are bitwise repeatable.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gsim.h"
+#include "gsim_device.h"
+#include "gsim_host.h"
+
+namespace gsim {
+namespace {
+
+constexpr int RT = 16;            // pixel tile edge
+constexpr int RCHUNK = 256;       // triangles per LDS chunk
+const double RCUT = 13.815510557964274;  // -ln(1e-6)
+
+template <typename T>
+struct RasterArgs {
+    const int32_t* tris;   // [nt][3]
+    const int32_t* coff;   // [nv + 1] vertex -> corner list
+    const int32_t* cent;   // [3 nt] corner = 3 tri + k
+    T* uvw;                // [nv][3]: u, v, P2.[X,1]
+    T* trans;              // [H][W]
+    T* cg;                 // [nt][6] screen-space gradient of each corner
+    int64_t nv, nt;
+    int32_t H, W;
+    T P[12];
+    T sigma, cut;          // cut = CUT sigma
+};
+
+template <typename T>
+__device__ __forceinline__ T cr2(T ax, T ay, T bx, T by) {
+    return ax * by - ay * bx;
+}
+
+// Squared distance from p to segment s0 -> s1 and the parameter t of the nearest point.
+template <typename T>
+__device__ __forceinline__ T seg_d2(T px, T py, T ax, T ay, T bx, T by, T& t) {
+    const T ex = bx - ax, ey = by - ay, wx = px - ax, wy = py - ay;
+    t = (wx * ex + wy * ey) / (ex * ex + ey * ey);
+    t = t < T(0) ? T(0) : (t > T(1) ? T(1) : t);
+    const T dx = wx - t * ex, dy = wy - t * ey;
+    return dx * dx + dy * dy;
+}
+
+// Signed scaled distance x = +-d^2 / sigma of pixel p to triangle (a, b, c);
+// returns false when the term is dropped.  edge / t: the nearest edge (0: ab,
+// 1: bc, 2: ca; the first minimum) and its parameter.
+template <typename T>
+__device__ __forceinline__ bool tri_term(T px, T py, const T v[6], T sigma, T cut, T& x, int& edge, T& t) {
+    const T ax = v[0], ay = v[1], bx = v[2], by = v[3], cx = v[4], cy = v[5];
+    const T e0 = cr2(bx - ax, by - ay, px - ax, py - ay);
+    const T e1 = cr2(cx - bx, cy - by, px - bx, py - by);
+    const T e2 = cr2(ax - cx, ay - cy, px - cx, py - cy);
+    const T area = cr2(bx - ax, by - ay, cx - ax, cy - ay);
+    const bool inside = (e0 >= T(0) && e1 >= T(0) && e2 >= T(0) && area > T(0)) ||
+                        (e0 <= T(0) && e1 <= T(0) && e2 <= T(0) && area < T(0));
+    T t0, t1, t2;
+    const T d0 = seg_d2(px, py, ax, ay, bx, by, t0);
+    const T d1 = seg_d2(px, py, bx, by, cx, cy, t1);
+    const T d2 = seg_d2(px, py, cx, cy, ax, ay, t2);
+    T d = d0;
+    edge = 0;
+    t = t0;
+    if (d1 < d) { d = d1; edge = 1; t = t1; }
+    if (d2 < d) { d = d2; edge = 2; t = t2; }
+    if (!inside && d > cut) return false;
+    x = (inside ? d : -d) / sigma;
+    return true;
+}
+
+__device__ __forceinline__ float softplus(float x) { return fmaxf(x, 0.f) + log1pf(expf(-fabsf(x))); }
+__device__ __forceinline__ double softplus(double x) { return fmax(x, 0.0) + log1p(exp(-fabs(x))); }
+__device__ __forceinline__ float sigm(float x) { return 1.f / (1.f + expf(-x)); }
+__device__ __forceinline__ double sigm(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_raster_project(RasterArgs<T> A, const T* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= A.nv) return;
+    const V3<T> X = ld3(x, A.nv, i);
+    const T n0 = A.P[0] * X.x + A.P[1] * X.y + A.P[2] * X.z + A.P[3];
+    const T n1 = A.P[4] * X.x + A.P[5] * X.y + A.P[6] * X.z + A.P[7];
+    const T dn = A.P[8] * X.x + A.P[9] * X.y + A.P[10] * X.z + A.P[11];
+    A.uvw[3 * i] = n0 / dn;
+    A.uvw[3 * i + 1] = n1 / dn;
+    A.uvw[3 * i + 2] = dn;
+}
+
+// One 16 x 16 pixel tile per workgroup; writes the image (if not null) and the
+// transmittance.
+template <typename T>
+__global__ __launch_bounds__(256) void k_raster_fwd(RasterArgs<T> A, T* __restrict__ image) {
+    __shared__ T tv[RCHUNK][6];
+    __shared__ T tb[RCHUNK][4];  // widened bounding box: xmin, xmax, ymin, ymax
+    const int col = blockIdx.x * RT + (threadIdx.x % RT), row = blockIdx.y * RT + (threadIdx.x / RT);
+    const T px = (T)col + T(0.5), py = (T)row + T(0.5);
+    // the tile's pixel-centre extent
+    const T tx0 = (T)(blockIdx.x * RT) + T(0.5), tx1 = tx0 + T(RT - 1);
+    const T ty0 = (T)(blockIdx.y * RT) + T(0.5), ty1 = ty0 + T(RT - 1);
+    const T r = sqrt(A.cut);
+    T S = T(0);
+    for (int64_t c0 = 0; c0 < A.nt; c0 += RCHUNK) {
+        __syncthreads();  // the previous chunk is no longer read
+        const int64_t j = c0 + threadIdx.x;
+        if (j < A.nt) {
+            T v[6];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int32_t q = A.tris[3 * j + k];
+                v[2 * k] = A.uvw[3 * q];
+                v[2 * k + 1] = A.uvw[3 * q + 1];
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) tv[threadIdx.x][k] = v[k];
+            tb[threadIdx.x][0] = fmin(fmin(v[0], v[2]), v[4]) - r;
+            tb[threadIdx.x][1] = fmax(fmax(v[0], v[2]), v[4]) + r;
+            tb[threadIdx.x][2] = fmin(fmin(v[1], v[3]), v[5]) - r;
+            tb[threadIdx.x][3] = fmax(fmax(v[1], v[3]), v[5]) + r;
+        }
+        __syncthreads();
+        const int n = (int)(A.nt - c0 < RCHUNK ? A.nt - c0 : RCHUNK);
+        for (int k = 0; k < n; ++k) {
+            // uniform over the tile: skip triangles whose widened box misses it
+            if (tb[k][1] < tx0 || tb[k][0] > tx1 || tb[k][3] < ty0 || tb[k][2] > ty1) continue;
+            if (px < tb[k][0] || px > tb[k][1] || py < tb[k][2] || py > tb[k][3]) continue;
+            T x, t;
+            int e;
+            if (tri_term(px, py, tv[k], A.sigma, A.cut, x, e, t)) S -= softplus(x);
+        }
+    }
+    if (col < A.W && row < A.H) {
+        const T tr = exp(S);
+        A.trans[(int64_t)row * A.W + col] = tr;
+        if (image) image[(int64_t)row * A.W + col] = T(1) - tr;
+    }
+}
+
+// One thread per triangle: d <Ibar, I> / d (screen corners) over its widened box.
+template <typename T>
+__global__ __launch_bounds__(256) void k_raster_tri_adj(RasterArgs<T> A, const T* __restrict__ ibar) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= A.nt) return;
+    T v[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int32_t q = A.tris[3 * j + k];
+        v[2 * k] = A.uvw[3 * q];
+        v[2 * k + 1] = A.uvw[3 * q + 1];
+    }
+    const T r = sqrt(A.cut);
+    // pixel index range whose centres lie inside the widened box, clamped into the
+    // image before any conversion to int (far or non-finite corners stay in range)
+    const T bx0 = fmin(fmin(v[0], v[2]), v[4]) - r, bx1 = fmax(fmax(v[0], v[2]), v[4]) + r;
+    const T by0 = fmin(fmin(v[1], v[3]), v[5]) - r, by1 = fmax(fmax(v[1], v[3]), v[5]) + r;
+    const int c0 = (int)fmin(T(A.W), fmax(T(0), ceil(bx0 - T(0.5))));
+    const int c1 = (int)fmax(T(-1), fmin(T(A.W - 1), floor(bx1 - T(0.5))));
+    const int r0 = (int)fmin(T(A.H), fmax(T(0), ceil(by0 - T(0.5))));
+    const int r1 = (int)fmax(T(-1), fmin(T(A.H - 1), floor(by1 - T(0.5))));
+    T g[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    for (int row = r0; row <= r1; ++row)
+        for (int col = c0; col <= c1; ++col) {
+            const T px = (T)col + T(0.5), py = (T)row + T(0.5);
+            T x, t;
+            int e;
+            if (!tri_term(px, py, v, A.sigma, A.cut, x, e, t)) continue;
+            const int64_t pi = (int64_t)row * A.W + col;
+            const T gx = ibar[pi] * A.trans[pi] * sigm(x);
+            if (gx == T(0)) continue;
+            // x = +-d2 / sigma; d2 = |p - q|^2, q on edge e = (s0, s1)
+            const T sgn = x >= T(0) ? T(1) : T(-1);
+            const int i0 = e, i1 = e == 2 ? 0 : e + 1;
+            const T s0x = v[2 * i0], s0y = v[2 * i0 + 1], s1x = v[2 * i1], s1y = v[2 * i1 + 1];
+            const T qx = s0x + t * (s1x - s0x), qy = s0y + t * (s1y - s0y);
+            const T k = gx * sgn / A.sigma * T(-2);
+            g[2 * i0] += k * (T(1) - t) * (px - qx);
+            g[2 * i0 + 1] += k * (T(1) - t) * (py - qy);
+            g[2 * i1] += k * t * (px - qx);
+            g[2 * i1 + 1] += k * t * (py - qy);
+        }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) A.cg[6 * j + k] = g[k];
+}
+
+// One thread per vertex: sum its corners' screen gradients (fixed order), then
+// through the projection; adds to xbar (SoA [3][nv]).
+template <typename T>
+__global__ __launch_bounds__(256) void k_raster_vertex_adj(RasterArgs<T> A, T* __restrict__ xbar) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= A.nv) return;
+    T gu = T(0), gv = T(0);
+    for (int32_t k = A.coff[i]; k < A.coff[i + 1]; ++k) {
+        const int32_t c = A.cent[k];
+        gu += A.cg[6 * (c / 3) + 2 * (c % 3)];
+        gv += A.cg[6 * (c / 3) + 2 * (c % 3) + 1];
+    }
+    const T u = A.uvw[3 * i], v = A.uvw[3 * i + 1], dn = A.uvw[3 * i + 2];
+    const T id = T(1) / dn;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) xbar[k * A.nv + i] += (gu * (A.P[k] - u * A.P[8 + k]) + gv * (A.P[4 + k] - v * A.P[8 + k])) * id;
+}
+
+}  // namespace
+}  // namespace gsim
+
+using namespace gsim;
+
+// ------------------------------------------------------------------ host ---
+struct gsim_raster {
+    int dtype = GSIM_F32;
+    int64_t nv = 0, nt = 0;
+    int H = 0, W = 0;
+    char* ws = nullptr;
+    size_t o_tris = 0, o_coff = 0, o_cent = 0, o_uvw = 0, o_trans = 0, o_cg = 0;
+};
+
+namespace {
+
+size_t raster_layout(gsim_raster* R, size_t tsize) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        o = (o + 255) & ~size_t(255);
+        const size_t at = o;
+        o += std::max<size_t>(bytes, 1);
+        return at;
+    };
+    R->o_tris = take(12 * (size_t)R->nt);
+    R->o_coff = take(4 * (size_t)(R->nv + 1));
+    R->o_cent = take(12 * (size_t)R->nt);
+    R->o_uvw = take(3 * tsize * (size_t)R->nv);
+    R->o_trans = take(tsize * (size_t)R->H * R->W);
+    R->o_cg = take(6 * tsize * (size_t)R->nt);
+    return (o + 255) & ~size_t(255);
+}
+
+int raster_check(int dtype, int64_t nv, int64_t nt, int H, int W) {
+    if (dtype != GSIM_F32 && dtype != GSIM_F64) return fail(GSIM_E_INVALID, "dtype must be GSIM_F32 or GSIM_F64");
+    if (nv < 1 || nt < 1 || nt > (int64_t)INT32_MAX / 3 || nv >= INT32_MAX)
+        return fail(GSIM_E_INVALID, "n_verts and n_tris must be >= 1 (and below 2^31 / 3 triangles)");
+    if (H < 1 || W < 1 || (int64_t)H * W > (int64_t)1 << 28) return fail(GSIM_E_INVALID, "bad image size");
+    return GSIM_OK;
+}
+
+template <typename T>
+RasterArgs<T> raster_args(const gsim_raster* R, const gsim_camera* cam) {
+    RasterArgs<T> A;
+    std::memset(&A, 0, sizeof A);
+    A.tris = (const int32_t*)(R->ws + R->o_tris);
+    A.coff = (const int32_t*)(R->ws + R->o_coff);
+    A.cent = (const int32_t*)(R->ws + R->o_cent);
+    A.uvw = (T*)(R->ws + R->o_uvw);
+    A.trans = (T*)(R->ws + R->o_trans);
+    A.cg = (T*)(R->ws + R->o_cg);
+    A.nv = R->nv;
+    A.nt = R->nt;
+    A.H = R->H;
+    A.W = R->W;
+    for (int k = 0; k < 12; ++k) A.P[k] = (T)cam->P[k];
+    A.sigma = (T)cam->sigma;
+    A.cut = (T)(RCUT * cam->sigma);
+    return A;
+}
+
+int raster_cam_check(const gsim_raster* R, const gsim_camera* cam) {
+    if (!R || !cam) return fail(GSIM_E_INVALID, "NULL renderer or camera");
+    if (!(cam->sigma > 0) || !std::isfinite(cam->sigma)) return fail(GSIM_E_INVALID, "sigma must be > 0");
+    for (int k = 0; k < 12; ++k)
+        if (!std::isfinite(cam->P[k])) return fail(GSIM_E_NONFINITE, "camera matrix");
+    return GSIM_OK;
+}
+
+template <typename T>
+int raster_forward(gsim_raster* R, const gsim_camera* cam, const T* x, T* image, hipStream_t s) {
+    RasterArgs<T> A = raster_args<T>(R, cam);
+    hipLaunchKernelGGL(k_raster_project<T>, dim3((unsigned)((R->nv + 255) / 256)), dim3(256), 0, s, A, x);
+    hipLaunchKernelGGL(k_raster_fwd<T>, dim3((R->W + RT - 1) / RT, (R->H + RT - 1) / RT), dim3(256), 0, s, A, image);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GSIM_OK : hip_fail(e, "raster forward");
+}
+
+template <typename T>
+int raster_backward(gsim_raster* R, const gsim_camera* cam, const T* x, const T* ibar, T* xbar, hipStream_t s) {
+    int rc = raster_forward<T>(R, cam, x, nullptr, s);  // transmittance and projection of this x
+    if (rc) return rc;
+    RasterArgs<T> A = raster_args<T>(R, cam);
+    hipLaunchKernelGGL(k_raster_tri_adj<T>, dim3((unsigned)((R->nt + 255) / 256)), dim3(256), 0, s, A, ibar);
+    hipLaunchKernelGGL(k_raster_vertex_adj<T>, dim3((unsigned)((R->nv + 255) / 256)), dim3(256), 0, s, A, xbar);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GSIM_OK : hip_fail(e, "raster backward");
+}
+
+}  // namespace
+
+extern "C" {
+
+int gsim_raster_sizes(int dtype, int64_t n_verts, int64_t n_tris, int height, int width, size_t* workspace_bytes) {
+    if (int rc = raster_check(dtype, n_verts, n_tris, height, width)) return rc;
+    if (!workspace_bytes) return fail(GSIM_E_INVALID, "NULL output");
+    gsim_raster R;
+    R.nv = n_verts;
+    R.nt = n_tris;
+    R.H = height;
+    R.W = width;
+    *workspace_bytes = raster_layout(&R, dtype == GSIM_F64 ? 8 : 4);
+    return GSIM_OK;
+}
+
+int gsim_raster_init(int dtype, int64_t n_verts, int64_t n_tris, const int32_t* tris, int height, int width,
+                     void* d_workspace, size_t bytes, void* stream, gsim_raster** out) {
+    if (int rc = raster_check(dtype, n_verts, n_tris, height, width)) return rc;
+    if (!tris || !d_workspace || !out) return fail(GSIM_E_INVALID, "NULL argument");
+    if (((uintptr_t)d_workspace) & 255) return fail(GSIM_E_INVALID, "workspace must be 256-byte aligned");
+    for (int64_t k = 0; k < 3 * n_tris; ++k)
+        if (tris[k] < 0 || tris[k] >= n_verts) return fail(GSIM_E_TOPOLOGY, "triangle %lld index out of range", (long long)(k / 3));
+    gsim_raster* R = new (std::nothrow) gsim_raster();
+    if (!R) return fail(GSIM_E_INVALID, "out of host memory");
+    R->dtype = dtype;
+    R->nv = n_verts;
+    R->nt = n_tris;
+    R->H = height;
+    R->W = width;
+    R->ws = (char*)d_workspace;
+    const size_t need = raster_layout(R, dtype == GSIM_F64 ? 8 : 4);
+    if (bytes < need) {
+        delete R;
+        return fail(GSIM_E_WORKSPACE, "workspace of %zu bytes, %zu needed", bytes, need);
+    }
+    // vertex -> corner lists (corner = 3 tri + k), in increasing corner order
+    std::vector<int32_t> coff(n_verts + 1, 0), cent(3 * n_tris);
+    for (int64_t k = 0; k < 3 * n_tris; ++k) coff[tris[k] + 1]++;
+    for (int64_t i = 0; i < n_verts; ++i) coff[i + 1] += coff[i];
+    std::vector<int32_t> fill(coff.begin(), coff.end() - 1);
+    for (int64_t k = 0; k < 3 * n_tris; ++k) cent[fill[tris[k]]++] = (int32_t)k;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(R->ws + R->o_tris, tris, 12 * (size_t)n_tris, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(R->ws + R->o_coff, coff.data(), 4 * coff.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(R->ws + R->o_cent, cent.data(), 4 * cent.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete R;
+        return hip_fail(e, "raster upload");
+    }
+    *out = R;
+    return GSIM_OK;
+}
+
+int gsim_raster_destroy(gsim_raster* R) {
+    delete R;
+    return GSIM_OK;
+}
+
+int gsim_raster_forward(gsim_raster* R, const gsim_camera* cam, const void* x, void* image, void* stream) {
+    if (int rc = raster_cam_check(R, cam)) return rc;
+    if (!x || !image) return fail(GSIM_E_INVALID, "NULL x or image");
+    return R->dtype == GSIM_F64 ? raster_forward<double>(R, cam, (const double*)x, (double*)image, (hipStream_t)stream)
+                                : raster_forward<float>(R, cam, (const float*)x, (float*)image, (hipStream_t)stream);
+}
+
+int gsim_raster_backward(gsim_raster* R, const gsim_camera* cam, const void* x, const void* image_bar, void* x_bar,
+                         void* stream) {
+    if (int rc = raster_cam_check(R, cam)) return rc;
+    if (!x || !image_bar || !x_bar) return fail(GSIM_E_INVALID, "NULL argument");
+    return R->dtype == GSIM_F64
+               ? raster_backward<double>(R, cam, (const double*)x, (const double*)image_bar, (double*)x_bar,
+                                         (hipStream_t)stream)
+               : raster_backward<float>(R, cam, (const float*)x, (const float*)image_bar, (float*)x_bar,
+                                        (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -34,6 +34,8 @@ ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan
                "gsim_controller_forward", "gsim_controller_backward",
                "gsim_rigid_sizes", "gsim_rigid_init", "gsim_rigid_destroy", "gsim_rigid_rollout", "gsim_rigid_loss",
                "gsim_rigid_rollout_backward",
+               "gsim_raster_sizes", "gsim_raster_init", "gsim_raster_destroy", "gsim_raster_forward",
+               "gsim_raster_backward",
                "gsim_engine_create", "gsim_engine_destroy", "gsim_engine_query_bytes", "gsim_engine_submit",
                "gsim_engine_tick", "gsim_engine_poll", "gsim_engine_stats")
 GSIM_F32, GSIM_F64 = 32, 64
@@ -77,6 +79,10 @@ class _RigidParams(C.Structure):
 
 class _RigidGrads(C.Structure):
     _fields_ = [("mass", C.c_void_p), ("inertia", C.c_void_p), ("contact", C.c_void_p)]
+
+
+class _Camera(C.Structure):
+    _fields_ = [("P", C.c_double * 12), ("sigma", C.c_double)]
 
 
 class _Ctrl(C.Structure):
@@ -134,6 +140,12 @@ def load():
         lib.gsim_rigid_rollout.argtypes = [vp, RP, vp, ip, vp, vp]
         lib.gsim_rigid_loss.argtypes = [vp, vp, vp, vp, vp, vp]
         lib.gsim_rigid_rollout_backward.argtypes = [vp, RP, vp, ip, vp, vp, RG, vp]
+        CP = C.POINTER(_Camera)
+        lib.gsim_raster_sizes.argtypes = [ip, i64, i64, ip, ip, C.POINTER(C.c_size_t)]
+        lib.gsim_raster_init.argtypes = [ip, i64, i64, vp, ip, ip, vp, C.c_size_t, vp, C.POINTER(vp)]
+        lib.gsim_raster_destroy.argtypes = [vp]
+        lib.gsim_raster_forward.argtypes = [vp, CP, vp, vp, vp]
+        lib.gsim_raster_backward.argtypes = [vp, CP, vp, vp, vp, vp]
         _lib = lib
     return _lib
 
@@ -616,3 +628,56 @@ class RigidModel:
                                                   _ptr(sbar_final.contiguous()), _ptr(out), C.byref(g),
                                                   _stream(stream)))
         return out
+
+
+# ----------------------------------------------------------------------------------
+# Soft silhouette renderer (gsim_raster_*)
+# ----------------------------------------------------------------------------------
+
+class Renderer:
+    """Soft silhouette of a triangle mesh (tris [nt, 3] over n_verts vertices) into a
+    height x width image, for vertex positions given as SoA [3, n_verts] (a model's
+    particle state)."""
+
+    def __init__(self, tris, n_verts, height, width, dtype=torch.float32, device="cuda"):
+        lib = load()
+        self.tris = np.ascontiguousarray(np.asarray(tris, np.int32).reshape(-1, 3))
+        self.nv, self.nt = int(n_verts), len(self.tris)
+        self.H, self.W = int(height), int(width)
+        self.dtype, self.device = dtype, torch.device(device)
+        code = GSIM_F64 if dtype == torch.float64 else GSIM_F32
+        nbytes = C.c_size_t()
+        _check(lib.gsim_raster_sizes(code, self.nv, self.nt, self.H, self.W, C.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        h = C.c_void_p()
+        _check(lib.gsim_raster_init(code, self.nv, self.nt, self.tris.ctypes.data, self.H, self.W,
+                                    C.c_void_p(self.workspace.data_ptr() + off), nbytes.value, _stream(None),
+                                    C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.gsim_raster_destroy(h)
+            self._h = None
+
+    @staticmethod
+    def camera(P, sigma):
+        c = _Camera()
+        for k, v in enumerate(np.asarray(P, np.float64).ravel()):
+            c.P[k] = float(v)
+        c.sigma = float(sigma)
+        return c
+
+    def forward(self, x, P, sigma, stream=None):
+        img = torch.empty(self.H, self.W, dtype=self.dtype, device=self.device)
+        _check(load().gsim_raster_forward(self._h, C.byref(self.camera(P, sigma)), _ptr(x.contiguous()), _ptr(img),
+                                          _stream(stream)))
+        return img
+
+    def backward(self, x, P, sigma, image_bar, x_bar=None, stream=None):
+        xb = torch.zeros(3, self.nv, dtype=self.dtype, device=self.device) if x_bar is None else x_bar
+        _check(load().gsim_raster_backward(self._h, C.byref(self.camera(P, sigma)), _ptr(x.contiguous()),
+                                           _ptr(image_bar.contiguous()), _ptr(xb), _stream(stream)))
+        return xb

@@ -209,7 +209,7 @@ def test_ctypes_structs_match_header(gs, tmp_path):
     mirrors = {"gsim_model_desc": gs._Desc, "gsim_state": gs._State, "gsim_params": gs._Params,
                "gsim_grads": gs._Grads, "gsim_query": serve._Query, "gsim_result": serve._Result,
                "gsim_controller": gs._Ctrl, "gsim_rigid_desc": gs._RigidDesc, "gsim_rigid_params": gs._RigidParams,
-               "gsim_rigid_grads": gs._RigidGrads}
+               "gsim_rigid_grads": gs._RigidGrads, "gsim_camera": gs._Camera}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gsim.h"', "int main(void) {"]
     expect = []
     for cname, cls in mirrors.items():
