@@ -303,6 +303,44 @@ def rigid_batch_bench(steps, n_bodies=1024, T=400):
             "forward_launch_ms": ev[0].elapsed_time(ev[1]), "loss_and_adjoint_ms": ev[1].elapsed_time(ev[2])}
 
 
+def raster_bench(reps=20, H=256, W=256):
+    """The soft silhouette renderer on the cloth workload's mesh (64 x 64 particles,
+    7938 triangles) seen by a perspective camera at H x W pixels: forward (projection
+    + per-pixel pass) and backward (recomputed forward + per-triangle adjoint + vertex
+    gather), HIP events over `reps` calls each."""
+    import torch
+    from paper_2104_02646_amd import gsim, workloads as W_
+    b = W_.cloth(10)
+    eye, tgt, up = np.array([1.0, 3.0, 4.0]), np.array([1.0, 0.6, 1.0]), np.array([0.0, 1.0, 0.0])
+    fwd = (tgt - eye) / np.linalg.norm(tgt - eye)
+    right = np.cross(fwd, up)
+    right /= np.linalg.norm(right)
+    down = np.cross(fwd, right)
+    Rm = np.stack([right, down, fwd])
+    K = np.array([[1.1 * W, 0, W / 2], [0, 1.1 * W, H / 2], [0, 0, 1.0]])
+    P = K @ np.concatenate([Rm, (-Rm @ eye)[:, None]], 1)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        r = gsim.Renderer(b.tris, b.np, H, W)
+        x = gsim.soa(b.X)
+        ib = torch.ones(H, W, device="cuda")
+        xb = torch.zeros(3, b.np, device="cuda")
+        img = r.forward(x, P, 1.0, stream=stream)
+        r.backward(x, P, 1.0, ib, xb, stream=stream)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        for _ in range(reps):
+            r.forward(x, P, 1.0, stream=stream)
+        ev[1].record(stream)
+        for _ in range(reps):
+            r.backward(x, P, 1.0, ib, xb, stream=stream)
+        ev[2].record(stream)
+        ev[2].synchronize()
+    return {"workload": "soft silhouette of the 64x64 cloth (%d triangles) at %dx%d" % (b.nt, H, W),
+            "coverage": float(img.mean()), "forward_ms": ev[0].elapsed_time(ev[1]) / reps,
+            "backward_ms": ev[1].elapsed_time(ev[2]) / reps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,6 +360,7 @@ def main():
     ap.add_argument("--no-control", action="store_true", help="skip the actuated (controller-driven) step")
     ap.add_argument("--no-cloth", action="store_true", help="skip the lift/drag cloth batch")
     ap.add_argument("--no-rigid", action="store_true", help="skip the rigid-body batch")
+    ap.add_argument("--no-raster", action="store_true", help="skip the renderer")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device tensor copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -510,6 +549,8 @@ def main():
         result["control_cloth"] = cloth_air_batch(args.steps)
     if not args.no_rigid:
         result["rigid"] = rigid_batch_bench(args.steps)
+    if not args.no_raster:
+        result["raster"] = raster_bench()
     if args.serve_queries > 0:
         result["serving"] = serving(args.serve_queries, max(20, args.serve_queries // 10), K,
                                     lambda msg: print(msg, file=sys.stderr, flush=True))
