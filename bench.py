@@ -74,9 +74,10 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs summarised in
 # profiles/batch256_tiled_two_pass_kernel_stats.md (FETCH_SIZE scaled by 2.0 and
 # WRITE_SIZE by 1.0, the factors a 1 GiB copy gives).  They hold for the kernel
-# source with this SHA-1 only; for any other source the traffic is reported as null.
+# sources with this SHA-1 (of gsim_kernels.hip followed by gsim_device.h) only; for any
+# other source the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "source_sha1": "8259fb00d5f60975a4799fc07c530e9eaf4e7ddf",
+    "source_sha1": "a52ff34507399d1f3b22f4717855f81c93af92b0",
     "workload": (256, 100, 10),
     "per_launch": {"element_fwd": 114.07e6, "particle_fwd": 30.54e6, "element_adj": 144.95e6,
                    "particle_adj": 37.26e6},
@@ -85,9 +86,11 @@ MEASURED_TRAFFIC = {
 
 def measured_traffic(kernel, bodies, T, K):
     import hashlib
-    src = os.path.join(ROOT, "paper_2104_02646_amd", "csrc", "gsim_kernels.hip")
-    with open(src, "rb") as fh:
-        sha = hashlib.sha1(fh.read()).hexdigest()
+    h = hashlib.sha1()
+    for name in ("gsim_kernels.hip", "gsim_device.h"):
+        with open(os.path.join(ROOT, "paper_2104_02646_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    sha = h.hexdigest()
     if sha != MEASURED_TRAFFIC["source_sha1"] or (bodies, T, K) != MEASURED_TRAFFIC["workload"]:
         return None
     return MEASURED_TRAFFIC["per_launch"].get(kernel)
