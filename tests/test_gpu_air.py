@@ -139,3 +139,45 @@ def test_fused_refuses_air(gs):
     m = gs.Model([W.control_cloth(77, n=8)], torch.float32, max_steps=8, ckpt_every=4)
     with pytest.raises(gs.GsimError, match="lift/drag"):
         m.set_exec(gs.EXEC_FUSED)
+
+
+def test_control_cloth_bench_batch_sampled(gs, oracle_lib):
+    """The bench's lift/drag workload in its launch configuration (64 control cloths,
+    seeds 900 .. 963, FP32, 100 steps, checkpoints every 10, graph execution on the
+    default lanes; target x0 + 0.3 m): four cloths of different sizes against the FP64
+    oracle (final positions, loss, initial-velocity, initial-position, stiffness and
+    mass gradients)."""
+    T, K = 100, 10
+    bodies = [W.control_cloth(900 + i).round_to(np.float32) for i in range(64)]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        m = gs.Model(bodies, torch.float32, max_steps=T, ckpt_every=K)
+        p = m.params_from_bodies()
+        x0 = gs.soa(np.concatenate([b.x0 for b in bodies]))
+        v0 = gs.soa(np.concatenate([b.v0 for b in bodies]))
+        tgt = np.concatenate([b.x0 + 0.3 for b in bodies]).astype(np.float32)
+        xT, vT = m.rollout(p, x0, v0, T)
+        loss, xb, vb = m.loss_mse(xT, gs.soa(tgt))
+        g = m.zero_grads(("ktri", "mass"))
+        xb0, vb0 = m.rollout_backward(p, T, xb, vb, g)
+    stream.synchronize()
+    po = np.cumsum([0] + [b.np for b in bodies])
+    to = np.cumsum([0] + [b.nt for b in bodies])
+    xT, xb0, vb0 = gs.aos(xT), gs.aos(xb0), gs.aos(vb0)
+    loss, gk, gm = loss.double().cpu().numpy(), g["ktri"].double().cpu().numpy(), g["mass"].double().cpu().numpy()
+    sizes = [b.nt for b in bodies]
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 40})
+    worst = {}
+    for i in picks:
+        b = bodies[i]
+        ps, ts = slice(po[i], po[i + 1]), slice(to[i], to[i + 1])
+        L, gr, xs, _ = oracle_for(oracle_lib, b).loss_and_grad(b.params(), b.x0, b.v0, T,
+                                                             tgt[ps].astype(np.float64), want=("ktri", "mass"))
+        errs = {"x": rel(xT[ps], xs[-1]), "loss": abs(loss[i] - L) / L, "v0": rel(vb0[ps], gr["v0"]),
+                "x0": rel(xb0[ps], gr["x0"]), "ktri": rel(gk[ts], gr["ktri"]), "mass": rel(gm[ps], gr["mass"])}
+        print("control cloth %d (%d triangles):" % (i, b.nt), {k: "%.2e" % v for k, v in errs.items()})
+        for k, v in errs.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+    assert worst["x"] < 1e-4
+    for k in ("loss", "v0", "x0", "ktri", "mass"):
+        assert worst[k] < 1e-3, (k, worst[k])

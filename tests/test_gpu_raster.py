@@ -1,12 +1,14 @@
 """Soft silhouette renderer on the HIP path vs the FP64 oracle (needs an MI355X).
 
 Cases: forward image and vertex gradient of cloth meshes seen by a perspective
-camera (image sizes that are not multiples of the 16-pixel tile; more triangles
+camera (image sizes that are not multiples of the 8-pixel tile; more triangles
 than one LDS chunk), FP64 and FP32; run-to-run bitwise repeatability; and the
 paper's whole pipeline on pixels: cloth rollout -> silhouette -> pixel loss ->
 gradient with respect to the per-triangle stiffness through both autograd
 Functions, against the oracle rollout + oracle renderer (autograd) + oracle
-adjoint.
+adjoint.  At the bench's size (256 x 256, 7938 triangles): 16 x 16 windows rendered by the
+oracle through the camera shifted to each window, and the vertex gradient of a loss on
+those windows.
 """
 import numpy as np
 import pytest
@@ -145,3 +147,49 @@ def test_pixel_loss_to_stiffness_gradient(gs, oracle_lib, dtype, tol):
     # rounded to FP32 after every step, moves it by 8.0e-4: the error is that of FP32
     # state storage, not of the renderer or the adjoint kernels)
     assert errs["loss"] < tol and errs["ktri"] < tol
+
+
+def test_bench_view_windows_vs_oracle(gs):
+    """The renderer at the bench's size and launch configuration (the 64 x 64 cloth,
+    7938 triangles, 256 x 256 pixels, sigma 1, FP32): 16 x 16 windows around the
+    projections of the four cloth corners and of its centre, each rendered by the
+    oracle through the camera shifted by the window's origin (the same pixels of the
+    same image), and the vertex gradient of a loss that weights only those windows."""
+    from oracle import raster as R
+    H = Wd = 256
+    sigma = 1.0
+    b = W.cloth(10)
+    X = b.X.astype(np.float32).astype(np.float64)
+    P = look_at([1.0, 3.0, 4.0], [1.0, 0.6, 1.0], [0, 1, 0], 1.1 * Wd, Wd / 2, H / 2)
+    n = int(round(np.sqrt(b.np)))
+    picks = [0, n - 1, n * (n - 1), n * n - 1, (n // 2) * n + n // 2]
+    q = np.concatenate([X[picks], np.ones((len(picks), 1))], 1) @ P.T
+    uv = q[:, :2] / q[:, 2:3]
+    rng = np.random.default_rng(5)
+    ibar = np.zeros((H, Wd))
+    wins = []
+    for u, v in uv:
+        c0 = int(min(max(np.floor(u) - 8, 0), Wd - 16))
+        r0 = int(min(max(np.floor(v) - 8, 0), H - 16))
+        wins.append((r0, c0))
+        ibar[r0:r0 + 16, c0:c0 + 16] = rng.normal(size=(16, 16))
+    r = gs.Renderer(b.tris, b.np, H, Wd)
+    x = gs.soa(X)
+    img = r.forward(x, P, sigma).double().cpu().numpy()
+    xb = r.backward(x, P, sigma, torch.as_tensor(ibar, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    Xo = torch.tensor(X, requires_grad=True)
+    tris = torch.as_tensor(b.tris, dtype=torch.long)
+    img_err, cov = 0.0, []
+    for r0, c0 in wins:
+        Pw = torch.tensor(np.array([[1.0, 0, -c0], [0, 1.0, -r0], [0, 0, 1.0]]) @ P)
+        ref = R.silhouette(Xo, tris, Pw, 16, 16, sigma)
+        (ref * torch.tensor(ibar[r0:r0 + 16, c0:c0 + 16])).sum().backward()
+        ref = ref.detach().numpy()
+        img_err = max(img_err, np.abs(img[r0:r0 + 16, c0:c0 + 16] - ref).max())
+        cov.append(float(ref.mean()))
+    g_err = rel(gs.aos(xb), Xo.grad.numpy())
+    print("bench view windows %s: coverage %s, image max abs err %.2e, gradient %.2e" %
+          (wins, ["%.2f" % c for c in cov], img_err, g_err))
+    assert all(0.05 < c < 0.95 for c in cov[:4]) and cov[4] > 0.95  # corners on the edge, centre inside
+    assert img_err < 2e-5 and g_err < 1e-4

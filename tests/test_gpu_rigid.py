@@ -132,3 +132,61 @@ def test_rigid_autograd(gs):
         assert rel(s0.grad[i].double().cpu().numpy(), sb) < 1e-3
         assert abs(float(p["mass"].grad[i]) - g["m"]) <= 1e-3 * abs(g["m"])  # 0 == 0 for a body in the air
         assert rel(p["inertia"].grad[i].double().cpu().numpy(), g["I"]) < 1e-3
+
+
+def _oracle_fp32_state_grad(o, b, T, target):
+    """The oracle's own sensitivity to FP32 state storage: its FP64 step with the
+    state rounded to FP32 after every step, then its FP64 reverse pass along that
+    trajectory."""
+    st = [np.asarray(b.s0, np.float64)]
+    for _ in range(T):
+        st.append(o.step(st[-1], b.mass, b.inertia, b.contact()).astype(np.float32).astype(np.float64))
+    _, sb = o.loss(st[-1], target)
+    g = {"m": 0.0, "I": np.zeros(6), "c": np.zeros(4)}
+    for t in range(T - 1, -1, -1):
+        sb, mb, Ib, cb = o.step_vjp(st[t], b.mass, b.inertia, b.contact(), sb)
+        g["m"] += mb
+        g["I"] += Ib
+        g["c"] += cb
+    g["s0"] = sb
+    return g
+
+
+def test_rigid_bench_batch_sampled_bodies(gs):
+    """The bench's rigid workload in its launch configuration (1024 bodies of the
+    seed-80 batch, FP32, 400 steps, one forward and one reverse launch; target =
+    the rest vertices moved by the start position + 0.2 m): every 32nd body against
+    the FP64 oracle.  Trajectory within 1e-4 and loss within 1e-3.  Over 400 steps
+    with contact some bodies' gradients are conditioned beyond FP32: the oracle
+    itself, with only its state rounded to FP32 after each step, moves them by up to
+    1.6e-3 (body 896).  Each gradient is therefore checked against 1e-3 plus that
+    sensitivity (x 1.25), which is printed beside it."""
+    T = 400
+    bodies = [b.round_to(np.float32) for b in W.rigid_batch(80, 1024)]
+    targets = [(b.verts + b.s0[:3] + 0.2).astype(np.float32).astype(np.float64) for b in bodies]
+    traj, loss, g = _gpu(gs, bodies, T, "f32", targets)
+    worst, where, over = {}, {}, []
+    for i in range(0, len(bodies), 32):
+        b = bodies[i]
+        o = oracle_of(b)
+        L, gr, st = o.loss_and_grad(b.s0, b.mass, b.inertia, b.contact(), T, targets[i])
+        g32 = _oracle_fp32_state_grad(o, b, T, targets[i])
+        errs = {"x": rel(traj[:, i, :], st), "loss": abs(loss[i] - L) / L}
+        sens = {}
+        keys = [("s0", "s0"), ("I", "I")]
+        if np.abs(gr["c"]).max() > 0:
+            keys += [("c", "c"), ("m", "m")]
+        for k, ko in keys:
+            errs[k] = rel(g[k][i], gr[ko])
+            sens[k] = rel(g32[ko], gr[ko])
+            if errs[k] >= 1.25 * sens[k] + 1e-3:
+                over.append((i, k, errs[k], sens[k]))
+        for k, v in errs.items():
+            if v > worst.get(k, -1.0):
+                worst[k], where[k] = v, i
+                if k in sens:
+                    worst[k + " (oracle FP32-state)"] = sens[k]
+    print("rigid bench batch, 32 sampled bodies, worst errors:",
+          {k: "%.2e (body %d)" % (v, where[k]) if k in where else "%.2e" % v for k, v in worst.items()})
+    assert worst["x"] < 1e-4 and worst["loss"] < 1e-3
+    assert not over, over
