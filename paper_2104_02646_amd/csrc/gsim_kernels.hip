@@ -59,6 +59,39 @@ template <typename T> __device__ __forceinline__ T inv_mass(const ModelDev<T>& M
     return gld(M.pinned, i) ? T(0) : T(1) / gld(S.mass, i);
 }
 
+// The same, with the mass loaded whether or not the particle is pinned (the mass
+// array covers every particle), so its load need not wait for the pin flag.
+template <typename T> __device__ __forceinline__ T inv_mass_eager(const ModelDev<T>& M, const StepDev<T>& S, int64_t i) {
+    const bool pin = gld(M.pinned, i) != 0;
+    const T m = gld(S.mass, i);
+    return pin ? T(0) : T(1) / m;
+}
+
+// Sum, in slot order, of a particle's deg partial slots at base, base + 64, ...
+// (xyz into f, w into d).  The first SLOT_BATCH slots are fetched before any is
+// used, so their loads overlap instead of waiting one after another; the sum order
+// is the same as a plain loop's.
+constexpr int SLOT_BATCH = 4;
+template <typename T>
+__device__ __forceinline__ void sum_slots(const T* slots, int64_t base, int32_t deg, V3<T>& f, T& d) {
+    T q[SLOT_BATCH][4];
+#pragma unroll
+    for (int k = 0; k < SLOT_BATCH; ++k)
+        if (k < deg) ld_slot(slots, base + 64 * k, q[k][0], q[k][1], q[k][2], q[k][3]);
+#pragma unroll
+    for (int k = 0; k < SLOT_BATCH; ++k)
+        if (k < deg) {
+            f += mk3(q[k][0], q[k][1], q[k][2]);
+            d += q[k][3];
+        }
+    for (int32_t k = SLOT_BATCH; k < deg; ++k) {
+        T a, b, c, e;
+        ld_slot(slots, base + 64 * k, a, b, c, e);
+        f += mk3(a, b, c);
+        d += e;
+    }
+}
+
 // ---------------------------------------------------------- tet (NH) ---
 // F = Ds Dm^-1; P = mu (1 - 1/(Ic+1)) F + lambda (J - alpha) cof F with
 // alpha = 1 + 3 mu/(4 lambda) + a; corner forces [f1 f2 f3] = -V P Dm^-T,
@@ -562,22 +595,20 @@ __global__ void __launch_bounds__(512) k_part_fwd(const ModelDev<T>* __restrict_
     const V3<T> g = mk3(B.g[0], B.g[1], B.g[2]);
     for (int64_t l = threadIdx.x; l < tl.count; l += blockDim.x) {
         const int64_t i = tl.begin + l;
-        V3<T> f = zero3<T>();
+        // every load that does not depend on another is issued first
         const int64_t li = i - B.p0;
-        const int64_t base = M.gbase[B.g0 + (li >> 6)] + (li & 63);
+        const int64_t gb = M.gbase[B.g0 + (li >> 6)];
         const int32_t deg = M.pdeg[i];
-        for (int32_t k = 0; k < deg; ++k) {
-            T a, b, c, d;
-            ld_slot(M.slots, base + 64 * k, a, b, c, d);
-            f += mk3(a, b, c);
-        }
         const V3<T> x = ld3(S.x, np, i), v = ld3(S.v, np, i);
+        const T w = inv_mass_eager(M, S, i);
+        V3<T> f = zero3<T>();
+        T unused = T(0);
+        sum_slots(M.slots, gb + (li & 63), deg, f, unused);
         if (S.ckx) {
             st3(S.ckx, np, i, x);
             st3(S.ckv, np, i, v);
         }
         if (contact) f += contact_force(x, v, pl, cp);
-        const T w = inv_mass(M, S, i);
         const T gate = w > T(0) ? T(1) : T(0);
         const V3<T> vn = v + (f * w + g * gate) * dt;
         st3(S.vo, np, i, vn);
@@ -744,30 +775,29 @@ __global__ void __launch_bounds__(512) k_part_adj(const ModelDev<T>* __restrict_
     T gc[4] = {T(0), T(0), T(0), T(0)};
     for (int64_t l = threadIdx.x; l < tl.count; l += blockDim.x) {
         const int64_t i = tl.begin + l;
-        const V3<T> xbp = ld3(S.xb, np, i);
-        const V3<T> vt = ld3(S.vb, np, i) + xbp * dt;
-        const T w = inv_mass(M, S, i);
-        const V3<T> fb = vt * (dt * w);
+        // every load that does not depend on another is issued first
+        const int64_t li = i - B.p0;
+        const int64_t gb = M.gbase[B.g0 + (li >> 6)];
+        const int32_t deg = M.pdeg[i];
+        const V3<T> xbp = ld3(S.xb, np, i), vbp = ld3(S.vb, np, i);
+        const T w = inv_mass_eager(M, S, i);
+        V3<T> x = zero3<T>(), v = zero3<T>();
+        if (contact) {
+            x = ld3(S.x, np, i);
+            v = ld3(S.v, np, i);
+        }
+        const int64_t base = gb + (li & 63);
         V3<T> xs = zero3<T>();
         T ds = T(0);
-        const int64_t li = i - B.p0;
-        const int64_t base = M.gbase[B.g0 + (li >> 6)] + (li & 63);
-        const int32_t deg = M.pdeg[i];
-        for (int32_t k = 0; k < deg; ++k) {
-            T a, b, c, d;
-            ld_slot(M.slots, base + 64 * k, a, b, c, d);
-            xs += mk3(a, b, c);
-            ds += d;
-        }
+        sum_slots(M.slots, base, deg, xs, ds);
+        const V3<T> vt = vbp + xbp * dt;
+        const V3<T> fb = vt * (dt * w);
         V3<T> xcb = zero3<T>(), vcb = zero3<T>();
-        if (AIR && B.air_on)  // velocity adjoint of the lift/drag force, same partial slots
-            for (int32_t k = 0; k < deg; ++k) {
-                T a, b, c, d;
-                ld_slot(M.vslots, base + 64 * k, a, b, c, d);
-                vcb += mk3(a, b, c);
-            }
+        if (AIR && B.air_on) {  // velocity adjoint of the lift/drag force, same partial slots
+            T unused = T(0);
+            sum_slots(M.vslots, base, deg, vcb, unused);
+        }
         if (contact) {
-            const V3<T> x = ld3(S.x, np, i), v = ld3(S.v, np, i);
             const V3<T> fc = contact_adjoint(x, v, pl, cp, fb, xcb, vcb, gc);
             ds += dot(fc, fb);
         }
