@@ -55,13 +55,10 @@ __device__ __forceinline__ void ld_slot(const double* s, int64_t k, double& a, d
     a = q0.x; b = q0.y; c = q1.x; d = q1.y;
 }
 
+// w = 1/m, 0 for pinned particles.  The mass is loaded whether or not the particle
+// is pinned (the mass array covers every particle), so its load does not wait for
+// the pin flag.
 template <typename T> __device__ __forceinline__ T inv_mass(const ModelDev<T>& M, const StepDev<T>& S, int64_t i) {
-    return gld(M.pinned, i) ? T(0) : T(1) / gld(S.mass, i);
-}
-
-// The same, with the mass loaded whether or not the particle is pinned (the mass
-// array covers every particle), so its load need not wait for the pin flag.
-template <typename T> __device__ __forceinline__ T inv_mass_eager(const ModelDev<T>& M, const StepDev<T>& S, int64_t i) {
     const bool pin = gld(M.pinned, i) != 0;
     const T m = gld(S.mass, i);
     return pin ? T(0) : T(1) / m;
@@ -600,7 +597,7 @@ __global__ void __launch_bounds__(512) k_part_fwd(const ModelDev<T>* __restrict_
         const int64_t gb = M.gbase[B.g0 + (li >> 6)];
         const int32_t deg = M.pdeg[i];
         const V3<T> x = ld3(S.x, np, i), v = ld3(S.v, np, i);
-        const T w = inv_mass_eager(M, S, i);
+        const T w = inv_mass(M, S, i);
         V3<T> f = zero3<T>();
         T unused = T(0);
         sum_slots(M.slots, gb + (li & 63), deg, f, unused);
@@ -780,7 +777,7 @@ __global__ void __launch_bounds__(512) k_part_adj(const ModelDev<T>* __restrict_
         const int64_t gb = M.gbase[B.g0 + (li >> 6)];
         const int32_t deg = M.pdeg[i];
         const V3<T> xbp = ld3(S.xb, np, i), vbp = ld3(S.vb, np, i);
-        const T w = inv_mass_eager(M, S, i);
+        const T w = inv_mass(M, S, i);
         V3<T> x = zero3<T>(), v = zero3<T>();
         if (contact) {
             x = ld3(S.x, np, i);
