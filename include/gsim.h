@@ -245,7 +245,9 @@ typedef struct {
  * act + t * act_stride (hact + t * hact_stride): with a stride of 0 every
  * step's contribution is summed into one array; with n_tets (n_hinges) each
  * step has its own. */
-typedef struct {         /* any pointer may be NULL = gradient not requested */
+typedef struct {         /* any pointer may be NULL = gradient not requested; the
+                            per-tet buffers mu, lam and act must be distinct
+                            (GSIM_E_INVALID otherwise) */
     void* mu;            /* [n_tets]      */
     void* lam;           /* [n_tets]      */
     void* k_tri;         /* [n_tris]      */

@@ -889,6 +889,8 @@ int check_params(const gsim_model* m, const gsim_params* p, const gsim_grads* g 
                           (g && ((g->act && g->act_stride) || (g->hact && g->hact_stride)));
     if (m->exec == GSIM_EXEC_FUSED && per_step)
         return fail(GSIM_E_UNSUPPORTED, "the fused path takes one actuation array for all steps (strides must be 0)");
+    if (g && ((g->mu && (g->mu == g->lam || g->mu == g->act)) || (g->lam && g->lam == g->act)))
+        return fail(GSIM_E_INVALID, "the mu, lam and act gradient buffers must be distinct");
     if (m->ne && (!p->mu || !p->lam)) return fail(GSIM_E_INVALID, "mu and lam are required for tets");
     if (m->nt && !p->k_tri) return fail(GSIM_E_INVALID, "k_tri is required for triangles");
     if (!p->mass) return fail(GSIM_E_INVALID, "mass is required");

@@ -671,15 +671,19 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
 #pragma unroll
             for (int k = 0; k < 9; ++k) D[k] = gld(M.tet_dinv, k * M.ne + e);
             const T act = S.act ? gld(S.act, e) : T(0);
+            // the accumulated gradients are read before the adjoint is computed, so
+            // their loads overlap with the element's other loads
+            const T gmu0 = S.g_mu ? gld(S.g_mu, e) : T(0), glam0 = S.g_lam ? gld(S.g_lam, e) : T(0),
+                    gact0 = S.g_act ? gld(S.g_act, e) : T(0);
             T gmu, glam, gact;
             tet_adjoint(x, D, gld(M.tet_vol, e), gld(S.mu, e), gld(S.lam, e), act, fb, f, xb, gmu, glam, gact);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 cs[cd[c] >> 16] = l4(xb[c], dot(f[c], fb[c]));
             }
-            if (S.g_mu) gst(S.g_mu, e, gld(S.g_mu, e) + gmu);
-            if (S.g_lam) gst(S.g_lam, e, gld(S.g_lam, e) + glam);
-            if (S.g_act) gst(S.g_act, e, gld(S.g_act, e) + gact);
+            if (S.g_mu) gst(S.g_mu, e, gmu0 + gmu);
+            if (S.g_lam) gst(S.g_lam, e, glam0 + glam);
+            if (S.g_act) gst(S.g_act, e, gact0 + gact);
         } else if (tl.kind == TILE_TRI) {
             uint32_t cd[3];
             V3<T> x[3], f[3], fb[3], xb[3];
@@ -692,6 +696,7 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k) D[k] = gld(M.tri_dinv, k * M.nt + e);
+            const T gk0 = S.g_ktri ? gld(S.g_ktri, e) : T(0);
             T gk;
             tri_adjoint(x, D, gld(M.tri_area, e), gld(S.ktri, e), fb, f, xb, gk);
             if (air) {
@@ -711,7 +716,7 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
             for (int c = 0; c < 3; ++c) {
                 cs[cd[c] >> 16] = l4(xb[c], dot(f[c], fb[c]));
             }
-            if (S.g_ktri) gst(S.g_ktri, e, gld(S.g_ktri, e) + gk);
+            if (S.g_ktri) gst(S.g_ktri, e, gk0 + gk);
         } else {
             uint32_t cd[4];
             V3<T> x[4], f[4], fb[4], xb[4];
@@ -721,13 +726,14 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
                 x[c] = v3(xs[cd[c] & 0xffffu]);
                 fb[c] = v3(fbs[cd[c] & 0xffffu]);
             }
+            const T gact0 = S.g_hact ? gld(S.g_hact, e) : T(0);
             T gact;
             hinge_adjoint(x, gld(M.hin_phi0, e), M.bodies[tl.body].kb, S.hact ? gld(S.hact, e) : T(0), fb, f, xb, gact);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 cs[cd[c] >> 16] = l4(xb[c], dot(f[c], fb[c]));
             }
-            if (S.g_hact) gst(S.g_hact, e, gld(S.g_hact, e) + gact);
+            if (S.g_hact) gst(S.g_hact, e, gact0 + gact);
         }
     }
     __syncthreads();
