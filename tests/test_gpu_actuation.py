@@ -243,3 +243,20 @@ def test_simrollout_actuation_grad(gs, oracle_lib):
     for k in ("act", "hact"):
         assert p[k].grad.shape == (T, per[k].shape[1])
         assert rel(_np(p[k].grad), per[k]) < 1e-3, k
+
+
+def test_aliased_tet_gradient_buffers_are_refused(gs):
+    """The adjoint element pass reads each per-tet gradient before adding to it, so
+    the mu, lam and act gradient buffers must be distinct: one buffer passed twice is
+    refused before anything is launched."""
+    body = mixed_body(1)
+    m = gs.Model([body], torch.float32, max_steps=4, ckpt_every=2)
+    p = m.params_from_bodies()
+    xT, vT = m.rollout(p, gs.soa(body.x0), gs.soa(body.v0), 4)
+    xb = torch.ones_like(xT)
+    g = m.zero_grads(("mu", "lam"))
+    g["lam"] = g["mu"]
+    with pytest.raises(gs.GsimError, match="distinct"):
+        m.rollout_backward(p, 4, xb, torch.zeros_like(xb), g)
+    torch.cuda.synchronize()
+    assert not g["mu"].any()
