@@ -77,10 +77,10 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
 # sources with this SHA-1 (of gsim_kernels.hip followed by gsim_device.h) only; for any
 # other source the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "source_sha1": "a52ff34507399d1f3b22f4717855f81c93af92b0",
+    "source_sha1": "cbcac3c6cc97fd904ff011daf05d83d5c439a666",
     "workload": (256, 100, 10),
-    "per_launch": {"element_fwd": 114.07e6, "particle_fwd": 30.54e6, "element_adj": 144.95e6,
-                   "particle_adj": 37.26e6},
+    "per_launch": {"element_fwd": 114.07e6, "particle_fwd": 30.55e6, "element_adj": 144.94e6,
+                   "particle_adj": 40.00e6},
 }
 
 
