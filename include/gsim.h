@@ -422,7 +422,10 @@ int gsim_raster_sizes(int dtype, int64_t n_verts, int64_t n_tris, int height, in
 int gsim_raster_init(int dtype, int64_t n_verts, int64_t n_tris, const int32_t* tris, int height, int width,
                      void* d_workspace, size_t bytes, void* stream, gsim_raster** out);
 int gsim_raster_destroy(gsim_raster* raster);
-/* image [height][width] of the vertices x ([3][n_verts] SoA, device). */
+/* image [height][width] of the vertices x ([3][n_verts] SoA, device; image
+ * device, caller-owned, dtype of the renderer).  Asynchronous on stream.  Errors
+ * (returned before anything is launched): GSIM_E_INVALID (NULL pointer, sigma not
+ * > 0), GSIM_E_NONFINITE (camera matrix); GSIM_E_HIP from the launch. */
 int gsim_raster_forward(gsim_raster* raster, const gsim_camera* camera, const void* x, void* image, void* stream);
 /* x_bar ([3][n_verts], +=) of sum(image_bar * image) for the same x and camera
  * (recomputes what it needs; independent of earlier forward calls).  Calls on one
