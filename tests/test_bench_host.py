@@ -1,0 +1,58 @@
+"""Host-side checks of bench.py's accounting (no GPU).
+
+The compulsory bytes per launch follow the per-unit figures of the kernels (64 B per
+tet and 44 B per tile particle in the forward element pass, ...), recomputed here by
+hand for the 256-body batch; measured HBM traffic is reported only for the kernel
+source it was taken with; more than one GPU is refused with a message.
+"""
+import hashlib
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+NE, NP, NTP = 1367346, 307196, 676018  # the 256-body batch: tets, particles, tile particles
+
+
+def test_kernel_bytes_per_unit():
+    # one pass over one tet / one particle / one tile particle (T = K = 1: one forward pass)
+    assert bench.kernel_bytes("element_fwd", 1, 0, 0, 1, 1) == 64
+    assert bench.kernel_bytes("element_fwd", 0, 0, 1, 1, 1) == 44
+    assert bench.kernel_bytes("element_adj", 1, 0, 0, 1, 1) == 80
+    assert bench.kernel_bytes("element_adj", 0, 0, 1, 1, 1) == 73
+    assert bench.kernel_bytes("particle_adj", 0, 1, 0, 1, 1) == 89
+    # particle forward: 57 per particle and pass, plus one checkpoint store (24) per segment
+    assert bench.kernel_bytes("particle_fwd", 0, 1, 0, 1, 1) == 57 + 24
+
+
+def test_batch_bytes_per_launch():
+    T, K = 100, 10
+    fwd_launches = T + (T - T // K)  # rollout + recompute of 9 of every 10 steps
+    assert fwd_launches == 190
+    per = bench.kernel_bytes("element_fwd", NE, NP, NTP, T, K) / fwd_launches
+    assert per == 64 * NE + 44 * NTP == 117254936
+    per_adj = bench.kernel_bytes("element_adj", NE, NP, NTP, T, K) / T
+    assert per_adj == 80 * NE + 73 * NTP
+
+
+def test_measured_traffic_only_for_its_source():
+    h = hashlib.sha1()
+    for name in ("gsim_kernels.hip", "gsim_device.h"):
+        with open(os.path.join(ROOT, "paper_2104_02646_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    current = h.hexdigest() == bench.MEASURED_TRAFFIC["source_sha1"]
+    v = bench.measured_traffic("element_fwd", 256, 100, 10)
+    assert (v == bench.MEASURED_TRAFFIC["per_launch"]["element_fwd"]) if current else v is None
+    assert bench.measured_traffic("element_fwd", 128, 100, 10) is None
+    assert bench.measured_traffic("element_fwd", 256, 50, 10) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120, env=dict(os.environ, HIP_VISIBLE_DEVICES=""))
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
