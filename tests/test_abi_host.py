@@ -252,3 +252,25 @@ def test_rigid_description_validation(gs):
     assert sizes([257])[0] == -7          # GSIM_E_UNSUPPORTED
     assert sizes([8], verts_fill=float("nan"))[0] == -6
     assert sizes([8], dt=0.0)[0] == -1
+
+
+def test_raster_sizes_validation(gs):
+    """gsim_raster_sizes validates on the host (dtype, counts, image size) and its
+    workspace grows with the triangles and the pixels; FP64 needs more than FP32."""
+    import ctypes as C
+    lib = gs.load()
+
+    def sizes(dtype, nv, nt, h, w):
+        out = C.c_size_t()
+        rc = lib.gsim_raster_sizes(dtype, C.c_int64(nv), C.c_int64(nt), h, w, C.byref(out))
+        return rc, out.value
+    rc, base = sizes(gs.GSIM_F32, 100, 150, 64, 64)
+    assert rc == 0 and base > 0 and base % 256 == 0
+    assert sizes(gs.GSIM_F32, 100, 1500, 64, 64)[1] > base
+    assert sizes(gs.GSIM_F32, 100, 150, 256, 256)[1] > base
+    assert sizes(gs.GSIM_F64, 100, 150, 64, 64)[1] > base
+    assert sizes(7, 100, 150, 64, 64)[0] == -1         # dtype
+    assert sizes(gs.GSIM_F32, 100, 0, 64, 64)[0] == -1  # no triangles
+    assert sizes(gs.GSIM_F32, 0, 150, 64, 64)[0] == -1  # no vertices
+    assert sizes(gs.GSIM_F32, 100, 150, 0, 64)[0] == -1  # empty image
+    assert sizes(gs.GSIM_F32, 100, 150, 1 << 15, 1 << 15)[0] == -1  # image beyond 2^28 pixels
