@@ -18,7 +18,7 @@
 // triangle: widened box, corners, orientation, reciprocal edge lengths, and each
 // chunk's box); forward (an 8 x 8 pixel tile per workgroup; the records of the
 // triangles whose widened box reaches the tile are compacted through LDS in order,
-// 256 at a time, and split over the workgroup's four wavefronts); triangle adjoint
+// RCHUNK at a time, and split over the workgroup's RSLICE wavefronts); triangle adjoint
 // (16 lanes per triangle over the pixels of its widened box, the transmittance
 // recomputed by the forward kernels first); vertex gather (one thread per vertex
 // summing its triangle corners in a fixed order, then through the projection).  No
@@ -39,8 +39,8 @@ namespace gsim {
 namespace {
 
 constexpr int RT = 8;             // pixel tile edge: one wavefront's 8 x 8 pixels
-constexpr int RSLICE = 4;         // wavefronts per tile, each over every 4th kept triangle
-constexpr int RCHUNK = 256;       // triangles staged per LDS chunk
+constexpr int RSLICE = 8;         // wavefronts per tile, each over every 8th kept triangle
+constexpr int RCHUNK = 512;       // triangles staged per LDS chunk (one per thread)
 constexpr int RREC = 16;          // values per triangle record
 constexpr int RLANES = 16;        // lanes per triangle in the adjoint
 const double RCUT = 13.815510557964274;  // -ln(1e-6)
