@@ -387,7 +387,8 @@ class Model:
         return b.value, i.value
 
     def set_lanes(self, lanes):
-        """Launch lanes of the two-pass path (1 or 2; bodies split in two concurrent groups)."""
+        """Launch lanes of the two-pass path (1..4, at most one per body; the bodies are
+        split into that many concurrent groups of about equal work; default 2)."""
         _check(load().gsim_model_set_lanes(self._h, int(lanes)))
 
     def get_lanes(self):
