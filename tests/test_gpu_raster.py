@@ -193,3 +193,48 @@ def test_bench_view_windows_vs_oracle(gs):
           (wins, ["%.2f" % c for c in cov], img_err, g_err))
     assert all(0.05 < c < 0.95 for c in cov[:4]) and cov[4] > 0.95  # corners on the edge, centre inside
     assert img_err < 2e-5 and g_err < 1e-4
+
+
+def test_degenerate_views_vs_oracle(gs):
+    """Edge cases of the renderer against the oracle (FP64): a mesh entirely outside
+    the image (image and gradient exactly 0), a 1 x 1 image, a collinear (zero-area)
+    triangle next to an ordinary one, and a triangle much larger than the image."""
+    from oracle import raster as R
+    P = torch.tensor([[10.0, 0, 0, 0], [0, 10.0, 0, 0], [0, 0, 1.0, 0]], dtype=torch.float64)  # u = 10 X / Z
+
+    def both(Xw, tris, H, Wd, sigma=1.0, seed=0):
+        ibar = np.random.default_rng(seed).normal(size=(H, Wd))
+        Xo = torch.tensor(Xw, dtype=torch.float64, requires_grad=True)
+        ref = R.silhouette(Xo, torch.as_tensor(tris, dtype=torch.long), P, H, Wd, sigma)
+        (ref * torch.tensor(ibar)).sum().backward()
+        r = gs.Renderer(np.asarray(tris, np.int32), len(Xw), H, Wd, torch.float64)
+        x = gs.soa(np.asarray(Xw, np.float64), torch.float64)
+        img = r.forward(x, P.numpy(), sigma)
+        xb = r.backward(x, P.numpy(), sigma, torch.as_tensor(ibar, device="cuda"))
+        torch.cuda.synchronize()
+        return img.cpu().numpy(), gs.aos(xb), ref.detach().numpy(), Xo.grad.numpy()
+
+    def screen(uv, z=2.0):
+        uv = np.asarray(uv, np.float64)
+        return np.concatenate([uv * z / 10.0, np.full((len(uv), 1), z)], 1)
+    # far outside: every term dropped
+    img, xb, ref, g = both(screen([[100, 100], [120, 100], [100, 130]]), [[0, 1, 2]], 16, 16)
+    assert np.all(img == 0) and np.all(xb == 0) and np.all(ref == 0)
+    # 1 x 1 image with a triangle edge near its pixel centre
+    img, xb, ref, g = both(screen([[0.2, -3], [4, 0.6], [0.2, 5]]), [[0, 1, 2]], 1, 1)
+    assert np.abs(img - ref).max() < 1e-14 and rel(xb, g) < 1e-12 and 0 < ref[0, 0] < 1
+    # zero-area triangle (collinear, distinct corners) beside an ordinary one.  Its long
+    # edge ca overlaps ab and bc, so a pixel is at the same distance from two edges
+    # that depend on different corners: a kink, where the kernels take the first
+    # nearest edge and the oracle's autograd splits between the two.  Unique, and
+    # compared: the image, the ordinary triangle's corner gradients, and the sum of the
+    # degenerate triangle's corner gradients (a common translation moves both edges
+    # alike).
+    X = screen([[2, 2], [6, 2], [10, 2], [3, 5], [9, 6], [5, 11]])
+    img, xb, ref, g = both(X, [[0, 1, 2], [3, 4, 5]], 14, 13)
+    assert np.abs(img - ref).max() < 1e-13 and np.isfinite(xb).all()
+    assert rel(xb[3:], g[3:]) < 1e-11 and rel(xb[:3].sum(0), g[:3].sum(0)) < 1e-11
+    # one triangle far larger than the image: interior pixels saturate
+    img, xb, ref, g = both(screen([[-500, -500], [800, -400], [-300, 900]]), [[0, 1, 2]], 20, 24)
+    assert np.abs(img - ref).max() < 1e-14 and ref.min() > 0.999
+    assert rel(xb, g) < 1e-10 or np.linalg.norm(g) < 1e-12

@@ -190,3 +190,38 @@ def test_rigid_bench_batch_sampled_bodies(gs):
           {k: "%.2e (body %d)" % (v, where[k]) if k in where else "%.2e" % v for k, v in worst.items()})
     assert worst["x"] < 1e-4 and worst["loss"] < 1e-3
     assert not over, over
+
+
+def test_rigid_vertex_count_extremes(gs):
+    """The smallest and largest bodies one wavefront holds: a single vertex (a point
+    mass with an inertia, contact at one point) and 256 vertices (4 per lane), next to
+    an ordinary body, FP64, 200 steps with ground contact, against the oracle."""
+    T = 200
+    rng = np.random.default_rng(12)
+    one = W.RigidBody(verts=np.array([[0.0, -0.05, 0.0]]), mass=1.3, inertia=np.array([0.02, 0.03, 0.025, 0, 0, 0]),
+                      s0=np.array([0.1, 0.3, -0.2, 1, 0, 0, 0, 0.5, -1.0, 0.2, 0.3, -0.2, 1.0]))
+    v256 = rng.normal(size=(256, 3))
+    v256 = 0.4 * v256 / np.linalg.norm(v256, axis=1, keepdims=True)
+    v256 -= v256.mean(0)
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    big = W.RigidBody(verts=v256, mass=2.0, inertia=np.array([0.13, 0.11, 0.12, 0.004, -0.002, 0.003]),
+                      s0=np.concatenate([[0.0, 0.6, 0.0], q, [1.0, -0.5, 0.3], [0.5, -1.0, 2.0]]))
+    mid = W.rigid_body(731, "box")
+    bodies = [one, big, mid]
+    targets = [target_of(b, 40 + i) for i, b in enumerate(bodies)]
+    traj, loss, g = _gpu(gs, bodies, T, "f64", targets)
+    for i, b in enumerate(bodies):
+        L, gr, st = oracle_of(b).loss_and_grad(b.s0, b.mass, b.inertia, b.contact(), T, targets[i])
+        errs = {"x": rel(traj[:, i, :], st), "loss": abs(loss[i] - L) / L, "s0": rel(g["s0"][i], gr["s0"]),
+                "I": rel(g["I"][i], gr["I"])}
+        if i < 2:  # the two extreme bodies reach the ground
+            assert np.abs(gr["c"]).max() > 0
+            errs["c"] = rel(g["c"][i], gr["c"])
+            errs["m"] = rel(g["m"][i], gr["m"])
+        else:
+            assert g["m"][i] == 0.0 and np.all(g["c"][i] == 0.0)
+        print("rigid body with %d vertices:" % b.nv, {k: "%.2e" % v for k, v in errs.items()})
+        assert errs["x"] < 1e-10
+        for k, v in errs.items():
+            assert v < 1e-8, (b.nv, k, v)
