@@ -322,3 +322,20 @@ def test_lanes_bitwise(gs, with_air):
     assert single.get_lanes() == 1
     with pytest.raises(gs.GsimError):
         single.set_lanes(2)
+
+
+def test_tiny_cube_against_stored_oracle_results(gs):
+    """FP64 HIP path against the stored oracle results of tests/golden (written from
+    the oracle alone): the tiny cube, 40 steps, loss and the first gradient entries."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_golden.json")) as fh:
+        ref = json.load(fh)["tiny_cube"]
+    b = W.tiny_cube(0)
+    xT, L, g, xb0, vb0 = _gpu_loss_grad(gs, b, ref["steps"], 8, torch.float64, W.synthetic_target(b, 1))
+    assert abs(L - ref["loss"]) < 1e-12 * abs(ref["loss"])
+    assert rel(xT[:4], ref["x_final_first4"]) < 1e-12
+    for key, name in (("mu", "grad_mu_first6"), ("lam", "grad_lam_first6"), ("mass", "grad_mass_first6")):
+        assert rel(g[key][:6], ref[name]) < 1e-9, key
+    assert rel(np.ravel(g["contact"]), ref["grad_contact"]) < 1e-9
+    assert rel(xb0[:2], ref["grad_x0_first2"]) < 1e-9 and rel(vb0[:2], ref["grad_v0_first2"]) < 1e-9
