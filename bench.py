@@ -77,7 +77,7 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
 # sources with this SHA-1 (of gsim_kernels.hip followed by gsim_device.h) only; for any
 # other source the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "source_sha1": "cbcac3c6cc97fd904ff011daf05d83d5c439a666",
+    "source_sha1": "a0ec579de83257163e4678e4f092912a48d92bf1",
     "workload": (256, 100, 10),
     "per_launch": {"element_fwd": 114.07e6, "particle_fwd": 30.55e6, "element_adj": 144.94e6,
                    "particle_adj": 40.00e6},

@@ -692,9 +692,14 @@ int timed(gsim_model* m, int k, void* stream, F launch) {
     hipEvent_t a, b;
     HIP_TRY(take_event(m, &a), "timing event");
     HIP_TRY(take_event(m, &b), "timing event");
-    HIP_TRY(hipEventRecord(a, (hipStream_t)stream), "timing record");
+    // the kernel itself records a and b as its start and end; a pass with nothing to
+    // launch records them back to back
+    arm_launch_events(a, b);
     int rc = launch();
-    HIP_TRY(hipEventRecord(b, (hipStream_t)stream), "timing record");
+    if (!disarm_launch_events()) {
+        HIP_TRY(hipEventRecord(a, (hipStream_t)stream), "timing record");
+        HIP_TRY(hipEventRecord(b, (hipStream_t)stream), "timing record");
+    }
     m->pending.push_back({k, a, b});
     return rc;
 }

@@ -137,6 +137,13 @@ struct StepDev {
     int32_t pad;
 };
 
+// Kernel timing: when a pair of events is armed, the next launch of the element and
+// particle passes records them as that kernel's own start and end (HIP's extended
+// launch), so their elapsed time is the kernel's execution, without the event packets
+// around it; the launch disarms them.  Returns whether the pair was consumed.
+void arm_launch_events(hipEvent_t start, hipEvent_t stop);
+bool disarm_launch_events();
+
 // Host-side launch helpers (defined in gsim_kernels.hip).  `stream` is a hipStream_t;
 // `air` selects the kernel variant that models lift/drag (models with an air body).
 // element passes: one workgroup (block threads) per element tile, `lds` bytes of

@@ -21,6 +21,7 @@
 // [nslot][4] so one corner is one 16-byte (FP32) access.  The kernels are
 // templated on the scalar type: float for production, double for checking the
 // algorithm against the FP64 oracle independently of FP32 rounding.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -1359,6 +1360,32 @@ int check_launch() {
 
 }  // namespace
 
+namespace {
+thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+
+// Launches kernel, with the armed timing events (if any) as its start and end.
+template <typename K, typename... Args>
+void launch_timed(K kernel, dim3 grid, dim3 block, size_t lds, hipStream_t stream, Args... args) {
+    if (t_ev_start && t_ev_stop) {
+        hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, stream, t_ev_start, t_ev_stop, 0, args...);
+        t_ev_start = t_ev_stop = nullptr;
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, lds, stream, args...);
+    }
+}
+}  // namespace
+
+void arm_launch_events(hipEvent_t start, hipEvent_t stop) {
+    t_ev_start = start;
+    t_ev_stop = stop;
+}
+
+bool disarm_launch_events() {
+    const bool consumed = t_ev_start == nullptr;
+    t_ev_start = t_ev_stop = nullptr;
+    return consumed;
+}
+
 // The element kernels' dynamic LDS can exceed the default limit (FP64 tiles).
 // (raised once per kernel and size, outside any steady-state launch sequence)
 void allow_lds(const void* kernel, size_t lds, size_t& allowed) {
@@ -1372,7 +1399,7 @@ int launch_elem_fwd_v(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* t
                       void* stream) {
     static size_t allowed = 48 * 1024;
     allow_lds(reinterpret_cast<const void*>(&k_elem_fwd<T, AIR>), lds, allowed);
-    hipLaunchKernelGGL((k_elem_fwd<T, AIR>), dim3(ntiles), dim3(block), lds, (hipStream_t)stream, md, sd, tiles);
+    launch_timed(k_elem_fwd<T, AIR>, dim3(ntiles), dim3(block), lds, (hipStream_t)stream, md, sd, tiles);
     return check_launch();
 }
 template <typename T>
@@ -1386,7 +1413,7 @@ template <typename T>
 int launch_part_fwd(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* tiles, int ntiles, int block, int,
                     void* stream) {
     if (ntiles <= 0) return 0;
-    hipLaunchKernelGGL(k_part_fwd<T>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
+    launch_timed(k_part_fwd<T>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
     return check_launch();
 }
 template <typename T, bool AIR>
@@ -1394,7 +1421,7 @@ int launch_elem_adj_v(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* t
                       void* stream) {
     static size_t allowed = 48 * 1024;
     allow_lds(reinterpret_cast<const void*>(&k_elem_adj<T, AIR>), lds, allowed);
-    hipLaunchKernelGGL((k_elem_adj<T, AIR>), dim3(ntiles), dim3(block), lds, (hipStream_t)stream, md, sd, tiles);
+    launch_timed(k_elem_adj<T, AIR>, dim3(ntiles), dim3(block), lds, (hipStream_t)stream, md, sd, tiles);
     return check_launch();
 }
 template <typename T>
@@ -1409,9 +1436,9 @@ int launch_part_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* til
                     bool air, void* stream) {
     if (ntiles <= 0) return 0;
     if (air)
-        hipLaunchKernelGGL((k_part_adj<T, true>), dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
+        launch_timed(k_part_adj<T, true>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
     else
-        hipLaunchKernelGGL((k_part_adj<T, false>), dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
+        launch_timed(k_part_adj<T, false>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
     return check_launch();
 }
 template <typename T>
