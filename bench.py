@@ -42,7 +42,7 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
     ntp = tile particles (sum over element tiles of the particles each touches).
       element pass, per tet: corner codes 16, D_m^-1 36, volume 4, mu + lambda 8
         (adjoint: + mu-bar, lambda-bar read-modify-write 16); per tile particle:
-        record (index, run, partial slot, pad) 16, positions 12 (adjoint: + xbar+,
+        record (index, run, partial slot) 12, positions 12 (adjoint: + xbar+,
         vbar+ 24, mass 4, pinned 1), partial write 16;
       particle pass, per particle: partial count 4, x, v 24, mass 4, pinned 1, writes
         24 (adjoint: xbar+, vbar+ 24, x, v 24, mass 4, pinned 1, partial count 4,
@@ -51,11 +51,11 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
     nseg = -(-T // K)
     fwd_passes = T + (T - nseg)  # rollout + segment recompute
     if kernel == "element_fwd":
-        return fwd_passes * (64 * ne + 44 * ntp)
+        return fwd_passes * (64 * ne + 40 * ntp)
     if kernel == "particle_fwd":
         return fwd_passes * (57 * np_ + 16 * ntp) + nseg * 24 * np_
     if kernel == "element_adj":
-        return T * (80 * ne + 73 * ntp)
+        return T * (80 * ne + 69 * ntp)
     if kernel == "particle_adj":
         return T * (89 * np_ + 16 * ntp)
     if kernel == "fused_fwd":
@@ -77,9 +77,9 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
 # sources with this SHA-1 (of gsim_kernels.hip followed by gsim_device.h) only; for any
 # other source the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "source_sha1": "a0ec579de83257163e4678e4f092912a48d92bf1",
+    "source_sha1": "8c37a4dcec0f803f76f94fdf1763686f2b7bd128",
     "workload": (256, 100, 10),
-    "per_launch": {"element_fwd": 114.07e6, "particle_fwd": 30.55e6, "element_adj": 144.94e6,
+    "per_launch": {"element_fwd": 111.37e6, "particle_fwd": 30.55e6, "element_adj": 142.23e6,
                    "particle_adj": 40.00e6},
 }
 

@@ -492,7 +492,7 @@ Layout make_layout(const gsim_plan* P, int max_steps) {
     L.tri_area = take(nt * sizeof(T));
     L.hin_code = take(4 * nh * 4);
     L.hin_phi0 = take(nh * sizeof(T));
-    L.tp = take(P->tp_id.size() * 16 + 16);
+    L.tp = take(P->tp_id.size() * 12 + 16);
     L.gbase = take(P->gbase.size() * 4 + 4);
     L.pdeg = take(np * 4);
     L.pinned = take(np);
@@ -1248,13 +1248,13 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     chk(up(L.tri_area, tri_area.data(), tri_area.size() * sizeof(T)));
     chk(up(L.hin_code, P->hin_code.data(), P->hin_code.size() * 4));
     chk(up(L.hin_phi0, hin_phi0.data(), hin_phi0.size() * sizeof(T)));
-    std::vector<int32_t> tp4(4 * P->tp_id.size(), 0);
+    std::vector<int32_t> tp3(3 * P->tp_id.size(), 0);
     for (size_t i = 0; i < P->tp_id.size(); ++i) {
-        tp4[4 * i] = P->tp_id[i];
-        tp4[4 * i + 1] = P->tp_run[i];
-        tp4[4 * i + 2] = P->tp_slot[i];
+        tp3[3 * i] = P->tp_id[i];
+        tp3[3 * i + 1] = P->tp_run[i];
+        tp3[3 * i + 2] = P->tp_slot[i];
     }
-    chk(up(L.tp, tp4.data(), tp4.size() * 4));
+    chk(up(L.tp, tp3.data(), tp3.size() * 4));
     chk(up(L.gbase, P->gbase.data(), P->gbase.size() * 4));
     chk(up(L.pdeg, P->pdeg.data(), P->pdeg.size() * 4));
     chk(up(L.pinned, P->pinned.data(), P->pinned.size()));

@@ -472,11 +472,12 @@ __device__ __forceinline__ void lds_st3(T* a, int n, int i, V3<T> v) {
     a[2 * n + i] = v.z;
 }
 
-// A tile particle's record (particle index, corner run, partial slot), one
-// 16-byte load.
+// A tile particle's record (particle index, corner run, partial slot): three
+// consecutive 32-bit words, one 12-byte load.
 typedef int gi4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ gi4 ld_tp(const int32_t* tp, int64_t i) {
-    return ((const __attribute__((address_space(1))) gi4*)(tp + 4 * i))[0];
+    const __attribute__((address_space(1))) int32_t* r = (const __attribute__((address_space(1))) int32_t*)(tp + 3 * i);
+    return gi4{r[0], r[1], r[2], 0};
 }
 
 // Element pass: one workgroup per planned element tile.  The positions of the

@@ -1,7 +1,7 @@
 """Host-side checks of bench.py's accounting (no GPU).
 
 The compulsory bytes per launch follow the per-unit figures of the kernels (64 B per
-tet and 44 B per tile particle in the forward element pass, ...), recomputed here by
+tet and 40 B per tile particle in the forward element pass, ...), recomputed here by
 hand for the 256-body batch; measured HBM traffic is reported only for the kernel
 source it was taken with; more than one GPU is refused with a message.
 """
@@ -21,9 +21,9 @@ NE, NP, NTP = 1367346, 307196, 676018  # the 256-body batch: tets, particles, ti
 def test_kernel_bytes_per_unit():
     # one pass over one tet / one particle / one tile particle (T = K = 1: one forward pass)
     assert bench.kernel_bytes("element_fwd", 1, 0, 0, 1, 1) == 64
-    assert bench.kernel_bytes("element_fwd", 0, 0, 1, 1, 1) == 44
+    assert bench.kernel_bytes("element_fwd", 0, 0, 1, 1, 1) == 40
     assert bench.kernel_bytes("element_adj", 1, 0, 0, 1, 1) == 80
-    assert bench.kernel_bytes("element_adj", 0, 0, 1, 1, 1) == 73
+    assert bench.kernel_bytes("element_adj", 0, 0, 1, 1, 1) == 69
     assert bench.kernel_bytes("particle_adj", 0, 1, 0, 1, 1) == 89
     # particle forward: 57 per particle and pass, plus one checkpoint store (24) per segment
     assert bench.kernel_bytes("particle_fwd", 0, 1, 0, 1, 1) == 57 + 24
@@ -34,9 +34,9 @@ def test_batch_bytes_per_launch():
     fwd_launches = T + (T - T // K)  # rollout + recompute of 9 of every 10 steps
     assert fwd_launches == 190
     per = bench.kernel_bytes("element_fwd", NE, NP, NTP, T, K) / fwd_launches
-    assert per == 64 * NE + 44 * NTP == 117254936
+    assert per == 64 * NE + 40 * NTP == 114550864
     per_adj = bench.kernel_bytes("element_adj", NE, NP, NTP, T, K) / T
-    assert per_adj == 80 * NE + 73 * NTP
+    assert per_adj == 80 * NE + 69 * NTP
 
 
 def test_measured_traffic_only_for_its_source():
