@@ -46,8 +46,12 @@ def main():
     targets = [W.synthetic_target(b, 7000 + i).astype(np.float32).astype(np.float64) for i, b in enumerate(bodies)]
     gpu = {name: run_batch(gsim, bodies, targets, mode) for name, mode in
            (("graph", gsim.EXEC_GRAPH), ("fused", gsim.EXEC_FUSED))}
+    ref = []
     with Pool(args.workers) as pool:
-        ref = pool.map(oracle_body, range(N), chunksize=1)
+        for i, r in enumerate(pool.imap(oracle_body, range(N), chunksize=1)):
+            ref.append(r)
+            if (i + 1) % 32 == 0:
+                print("oracle: %d of %d bodies done" % (i + 1, N), flush=True)
     poff = np.concatenate([[0], np.cumsum([b.np for b in bodies])])
     eoff = np.concatenate([[0], np.cumsum([b.ne for b in bodies])])
     for name, (x, loss, g) in gpu.items():
