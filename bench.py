@@ -355,7 +355,7 @@ def main():
     ap.add_argument("--exec", choices=("fused", "graph", "plain"), default="graph")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--items", type=int, default=1)
-    ap.add_argument("--lanes", type=int, default=2, help="concurrent launch lanes of the two-pass path (1..4)")
+    ap.add_argument("--lanes", type=int, default=3, help="concurrent launch lanes of the two-pass path (1..4)")
     ap.add_argument("--cpu-tets", type=int, default=15000, help="oracle sample size (tets)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")

@@ -1,5 +1,6 @@
 """The 256-body batch at full size, in the launch configuration the benchmark times
-(graph-captured two-pass path, FP32, 100 steps, checkpoints every 10), and through the
+(graph-captured two-pass path over three launch lanes, FP32, 100 steps, checkpoints every
+10), and through the
 fused path: sampled bodies are checked one by one against the FP64 oracle
 (positions 1e-4, gradients 1e-3, norm-relative per body).  The sample holds the two
 bodies whose FP32 gradients are the most sensitive over the whole batch (29: contact
@@ -40,6 +41,7 @@ def run_batch(gs, bodies, targets, exec_mode):
     with torch.cuda.stream(stream):
         m = gs.Model(bodies, torch.float32, max_steps=T, ckpt_every=K)
         m.set_exec(exec_mode, 256, 1)
+        m.set_lanes(3)
         p = m.params_from_bodies()
         x0 = gs.soa(np.concatenate([b.x0 for b in bodies]))
         v0 = gs.soa(np.concatenate([b.v0 for b in bodies]))

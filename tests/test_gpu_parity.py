@@ -277,7 +277,7 @@ def test_repeat_runs_bitwise(gs):
 
 @pytest.mark.parametrize("with_air", [False, True])
 def test_lanes_bitwise(gs, with_air):
-    """Two and four launch lanes (bodies split into concurrently running groups, plain
+    """Two, three and four launch lanes (bodies split into concurrently running groups, plain
     and graph execution) and kernel-timing mode (every pass on the caller's stream, with
     events around each launch) give the same bits as one lane; also for a batch with
     a lift/drag cloth, whose tiles run the air kernel variant."""
@@ -296,7 +296,7 @@ def test_lanes_bitwise(gs, with_air):
         x0 = gs.soa(np.concatenate([b.x0 for b in bodies]))
         v0 = gs.soa(np.concatenate([b.v0 for b in bodies]))
         tgt = gs.soa(np.concatenate([b.target for b in bodies]))
-        for lanes in (1, 2, 4):
+        for lanes in (1, 2, 3, 4):
             for mode in (gs.EXEC_PLAIN, gs.EXEC_GRAPH, "timing"):
                 m.set_lanes(lanes)
                 m.set_exec(gs.EXEC_PLAIN if mode == "timing" else mode)
