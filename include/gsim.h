@@ -102,7 +102,13 @@ typedef struct {
     const double* k_bend;              /* [n_bodies] bending stiffness, or NULL (0) */
     const uint8_t* air_on;             /* [n_bodies] nonzero = lift/drag on the body's triangles
                                           (see gsim_params.air), or NULL (off) */
+    int tile_elems;                    /* elements per element tile of the two-pass path, in
+                                          [GSIM_TILE_MIN, GSIM_TILE_MAX]; 0 = GSIM_TILE_DEFAULT.
+                                          A launch-shape choice (the autotuner searches it): it
+                                          changes the summation order of the scatter, not the model */
 } gsim_model_desc;
+
+enum { GSIM_TILE_MIN = 32, GSIM_TILE_MAX = 2048, GSIM_TILE_DEFAULT = 256 };
 
 typedef struct gsim_plan gsim_plan;    /* host object: validated topology, rest data, tiles */
 typedef struct gsim_model gsim_model;  /* host handle bound to a caller-owned device workspace */

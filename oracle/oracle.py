@@ -261,6 +261,23 @@ class Oracle:
         assert rc == 0, rc
         return f
 
+    def contact_branches(self, p, x, v):
+        """The side of the contact model's two kinks each particle is on at the state
+        (x, v) (App. A.1 "Contact"; readings R4-R6, R15): 0 = no contact (gap n.x - d
+        >= 0), 1 = stick (k_f |u_t| <= mu_f |lambda_n|, the tie included), 2 = slip.
+        lambda_n = k_e C - k_d n.v with C = -gap; u_t = v - (n.v) n.  The plane is
+        taken as given (unit normal), like the force."""
+        x = _f64(x, (self.np, 3)); v = _f64(v, (self.np, 3))
+        if not self.ground:
+            return np.zeros(self.np, np.int8)
+        n, d = self.plane[:3], self.plane[3]
+        gap = x @ n - d
+        vn = v @ n
+        lam = p["ke"] * (-gap) - p.get("kd", 0.0) * vn
+        s = np.linalg.norm(v - vn[:, None] * n[None, :], axis=1)
+        stick = p.get("kf", 0.0) * s <= p["muf"] * np.abs(lam)
+        return np.where(gap < 0, np.where(stick, 1, 2), 0).astype(np.int8)
+
     def energy(self, p, x):
         s, keep = self._params(p)
         x = _f64(x, (self.np, 3))

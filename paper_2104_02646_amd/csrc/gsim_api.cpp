@@ -177,7 +177,7 @@ void colour_elements(gsim_plan* P) {
 }
 
 // Element tiles of the two-pass path.  Per body and element kind, consecutive
-// elements are cut into tiles of at most ETILE elements, a tile ending early when
+// elements are cut into tiles of at most tile_elems elements, a tile ending early when
 // its adjoint LDS (8 words per tile particle, 4 per corner) would exceed
 // ETILE_WORDS.  Per tile: its particles in increasing index order (the tile
 // particles); its corners ordered by (tile particle, element, corner), so each
@@ -214,7 +214,7 @@ int build_tiles(gsim_plan* P) {
                 const int32_t tile = (int32_t)P->etiles.size();
                 const int64_t s = e;
                 parts.clear();
-                while (e < off[b + 1] && e - s < ETILE) {
+                while (e < off[b + 1] && e - s < P->tile_elems) {
                     int add = 0;
                     for (int c = 0; c < nc; ++c) add += mark[idx[c * n + e]] != tile;
                     const int64_t words = wp * (int64_t)(parts.size() + add) + wc * (int64_t)nc * (e - s + 1);
@@ -314,6 +314,9 @@ int build_plan(const gsim_model_desc* d, gsim_plan* P) {
     if ((rc = check_offsets(d->body_tet_off, nb, d->n_tets, "tet"))) return rc;
     if ((rc = check_offsets(d->body_tri_off, nb, d->n_tris, "tri"))) return rc;
     if ((rc = check_offsets(d->body_hinge_off, nb, d->n_hinges, "hinge"))) return rc;
+    if (d->tile_elems != 0 && (d->tile_elems < GSIM_TILE_MIN || d->tile_elems > GSIM_TILE_MAX))
+        return fail(GSIM_E_INVALID, "tile_elems must be 0 or in [%d, %d]", GSIM_TILE_MIN, GSIM_TILE_MAX);
+    P->tile_elems = d->tile_elems ? d->tile_elems : GSIM_TILE_DEFAULT;
     P->dtype = d->dtype;
     P->nb = nb;
     P->np = d->n_particles;
@@ -337,6 +340,12 @@ int build_plan(const gsim_model_desc* d, gsim_plan* P) {
         X[i] = {d->rest_x[3 * i], d->rest_x[3 * i + 1], d->rest_x[3 * i + 2]};
         if (!finite(X[i].x) || !finite(X[i].y) || !finite(X[i].z))
             return fail(GSIM_E_NONFINITE, "rest position %lld is not finite", (long long)i);
+    }
+    P->rest.resize(3 * P->np);
+    for (int64_t i = 0; i < P->np; ++i) {
+        P->rest[3 * i] = X[i].x;
+        P->rest[3 * i + 1] = X[i].y;
+        P->rest[3 * i + 2] = X[i].z;
     }
     P->pinned.assign(P->np, 0);
     if (d->pinned)
@@ -496,12 +505,15 @@ Layout make_layout(const gsim_plan* P, int max_steps) {
     L.gbase = take(P->gbase.size() * 4 + 4);
     L.pdeg = take(np * 4);
     L.pinned = take(np);
+    L.rest = take(3 * np * sizeof(T));
+    L.rgap = take(np * sizeof(T));
     L.slots = take(4 * std::max<int64_t>(P->nslot, 1) * sizeof(T));
     L.vslots = P->any_air ? take(4 * std::max<int64_t>(P->nslot, 1) * sizeof(T)) : 0;
     L.cpart = take(4 * (cap_p + 1) * sizeof(T));
     L.lpart = take((cap_p + 1) * sizeof(T));
     L.fbuf = take(2 * 6 * np * sizeof(T));
     L.abuf = take(2 * 6 * np * sizeof(T));
+    L.fbar = take(2 * 3 * np * sizeof(T));
     L.f_tet_idx = take(4 * ne * 4);
     L.f_tet_dinv = take(9 * ne * sizeof(T));
     L.f_tet_vol = take(ne * sizeof(T));
@@ -926,8 +938,10 @@ int do_fused_forward(gsim_model* m, const gsim_params* p, const T* x, const T* v
     StepDev<T>& r = rows[0];
     r.x = x;
     r.v = v;
+    r.x_abs = 1;
     r.xo = xo;
     r.vo = vo;
+    r.xo_abs = 1;
     r.ckx = ckpt;
     r.ckv = ckpt ? ckpt + 3 * m->np : nullptr;
     r.ckpt_every = m->K;
@@ -1014,6 +1028,7 @@ int do_step(gsim_model* m, const gsim_params* p, gsim_state in, gsim_state out, 
         if (t == 0) {
             r.x = (const T*)in.x;
             r.v = (const T*)in.v;
+            r.x_abs = 1;
         } else {
             r.x = c.fbuf + ((t - 1) & 1) * S;
             r.v = r.x + 3 * c.np;
@@ -1021,6 +1036,7 @@ int do_step(gsim_model* m, const gsim_params* p, gsim_state in, gsim_state out, 
         if (t == n - 1) {
             r.xo = (T*)out.x;
             r.vo = (T*)out.v;
+            r.xo_abs = 1;
         } else {
             r.xo = c.fbuf + (t & 1) * S;
             r.vo = r.xo + 3 * c.np;
@@ -1044,6 +1060,7 @@ int do_step_backward(gsim_model* m, const gsim_params* p, gsim_state s, gsim_sta
     fill_params<T>(r, p, g);
     r.x = (const T*)s.x;
     r.v = (const T*)s.v;
+    r.x_abs = 1;
     r.xb = (const T*)ap.x;
     r.vb = (const T*)ap.v;
     r.xbo = (T*)am.x;
@@ -1085,6 +1102,7 @@ int do_rollout(gsim_model* m, const gsim_params* p, gsim_state s0, int n, void* 
         if (t == 0) {
             r.x = (const T*)s0.x;
             r.v = (const T*)s0.v;
+            r.x_abs = 1;
         } else {
             r.x = c.fbuf + ((t - 1) & 1) * S;
             r.v = r.x + 3 * c.np;
@@ -1092,6 +1110,7 @@ int do_rollout(gsim_model* m, const gsim_params* p, gsim_state s0, int n, void* 
         if (t == n - 1) {
             r.xo = (T*)sf.x;
             r.vo = (T*)sf.v;
+            r.xo_abs = 1;
         } else {
             r.xo = c.fbuf + (t & 1) * S;
             r.vo = r.xo + 3 * c.np;
@@ -1133,6 +1152,7 @@ int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, i
     }
     T* segT = (T*)seg;
     const T* ck = (const T*)ckpt;
+    T* fbar = (T*)(m->ws + m->L.fbar);
     int q = 0;  // adjoint steps done
     for (int s = nseg - 1; s >= 0; --s) {
         const int t0 = s * K, t1 = std::min(n, t0 + K), L = t1 - t0;
@@ -1166,7 +1186,9 @@ int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, i
             } else {
                 r.xbo = c.abuf + (q & 1) * S;
                 r.vbo = r.xbo + 3 * np;
+                r.fbo = fbar + (q & 1) * 3 * np;  // this step hands step t-1 its adjoint force
             }
+            if (q > 0) r.fb = fbar + ((q - 1) & 1) * 3 * np;
             rows.push_back(r);
             seq.push_back({OP_ADJ, r0 + (int64_t)rows.size() - 1});
         }
@@ -1182,6 +1204,7 @@ int do_loss(gsim_model* m, gsim_state s, const void* target, void* loss, gsim_st
     std::vector<StepDev<T>> rows(1);
     std::memset(rows.data(), 0, sizeof(StepDev<T>));
     rows[0].x = (const T*)s.x;
+    rows[0].x_abs = 1;
     rows[0].target = (const T*)target;
     rows[0].loss = (T*)loss;
     rows[0].xbo = (T*)adj.x;
@@ -1258,6 +1281,18 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     chk(up(L.gbase, P->gbase.data(), P->gbase.size() * 4));
     chk(up(L.pdeg, P->pdeg.data(), P->pdeg.size() * 4));
     chk(up(L.pinned, P->pinned.data(), P->pinned.size()));
+    // rest positions (SoA) and each particle's rest gap to its body's ground plane,
+    // n.X - d, formed in FP64 and rounded once
+    std::vector<T> rest(3 * P->np), rgap(P->np);
+    for (int b = 0; b < P->nb; ++b)
+        for (int64_t i = P->poff[b]; i < P->poff[b + 1]; ++i) {
+            const double* x = &P->rest[3 * i];
+            const double* pl = &P->plane[4 * b];
+            for (int c = 0; c < 3; ++c) rest[c * P->np + i] = (T)x[c];
+            rgap[i] = (T)(pl[0] * x[0] + pl[1] * x[1] + pl[2] * x[2] - pl[3]);
+        }
+    chk(up(L.rest, rest.data(), rest.size() * sizeof(T)));
+    chk(up(L.rgap, rgap.data(), rgap.size() * sizeof(T)));
     // colour-ordered copies of the element records (fused path)
     // corner indices become body-local (the fused kernels address the body's particles in LDS)
     auto perm_i = [P](const std::vector<int32_t>& a, const std::vector<int32_t>& ord, int rows, int64_t n,
@@ -1357,6 +1392,8 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     M.gbase = (const int32_t*)(ws + L.gbase);
     M.pdeg = (const int32_t*)(ws + L.pdeg);
     M.pinned = (const uint8_t*)(ws + L.pinned);
+    M.rest = (const T*)(ws + L.rest);
+    M.rgap = (const T*)(ws + L.rgap);
     M.bodies = (const BodyDev<T>*)(ws + L.bodies);
     M.slots = (T*)(ws + L.slots);
     M.vslots = P->any_air ? (T*)(ws + L.vslots) : nullptr;

@@ -62,10 +62,12 @@ template <typename T> __device__ __forceinline__ void st3(T* __restrict__ p, int
 // gap = n.x - d; C = -gap when gap < 0; lambda_n = k_e C + k_d Cdot, Cdot = -n.v;
 // f_n = lambda_n n; u_t = v - (n.v) n; stick if k_f |u_t| <= mu_f |lambda_n|:
 // f_f = -k_f u_t; otherwise f_f = -mu_f |lambda_n| u_t / |u_t|.
+// The deformable kernels pass the gap itself (the rest gap of the particle plus
+// n.u for its displacement u, so that no absolute coordinate is rounded); the
+// rigid kernels pass a world point through the overloads below.
 template <typename T>
-__device__ __forceinline__ V3<T> contact_force(V3<T> x, V3<T> v, const T pl[4], const T c[4]) {
+__device__ __forceinline__ V3<T> contact_force_gap(T gap, V3<T> v, const T pl[4], const T c[4]) {
     const V3<T> n = mk3(pl[0], pl[1], pl[2]);
-    const T gap = dot(n, x) - pl[3];
     if (!(gap < T(0))) return zero3<T>();
     const T C = -gap;
     const T vn = dot(n, v);
@@ -79,13 +81,13 @@ __device__ __forceinline__ V3<T> contact_force(V3<T> x, V3<T> v, const T pl[4], 
     return n * lam + ff;
 }
 
-// Adjoint of contact_force for the force adjoint fb: adds to xb, vb and the
-// contact-parameter gradients gc (k_e, k_d, k_f, mu_f); returns the force.
+// Adjoint of contact_force_gap for the force adjoint fb: adds to xb (through
+// d gap / dx = n), vb and the contact-parameter gradients gc (k_e, k_d, k_f,
+// mu_f); returns the force.
 template <typename T>
-__device__ __forceinline__ V3<T> contact_adjoint(V3<T> x, V3<T> v, const T pl[4], const T c[4], V3<T> fb, V3<T>& xb,
-                                                 V3<T>& vb, T gc[4]) {
+__device__ __forceinline__ V3<T> contact_adjoint_gap(T gap, V3<T> v, const T pl[4], const T c[4], V3<T> fb, V3<T>& xb,
+                                                     V3<T>& vb, T gc[4]) {
     const V3<T> n = mk3(pl[0], pl[1], pl[2]);
-    const T gap = dot(n, x) - pl[3];
     if (!(gap < T(0))) return zero3<T>();
     const T C = -gap;
     const T vn = dot(n, v);
@@ -117,6 +119,16 @@ __device__ __forceinline__ V3<T> contact_adjoint(V3<T> x, V3<T> v, const T pl[4]
     xb -= n * (c[0] * lamb);
     vb -= n * (c[1] * lamb);
     return n * lam + ff;
+}
+
+template <typename T>
+__device__ __forceinline__ V3<T> contact_force(V3<T> x, V3<T> v, const T pl[4], const T c[4]) {
+    return contact_force_gap(dot(mk3(pl[0], pl[1], pl[2]), x) - pl[3], v, pl, c);
+}
+template <typename T>
+__device__ __forceinline__ V3<T> contact_adjoint(V3<T> x, V3<T> v, const T pl[4], const T c[4], V3<T> fb, V3<T>& xb,
+                                                 V3<T>& vb, T gc[4]) {
+    return contact_adjoint_gap(dot(mk3(pl[0], pl[1], pl[2]), x) - pl[3], v, pl, c, fb, xb, vb, gc);
 }
 
 }  // namespace

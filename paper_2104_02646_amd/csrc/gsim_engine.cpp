@@ -255,6 +255,7 @@ int next_op(const Live& L, StepDev<float>& r) {
         const int t = L.t;
         r.x = t == 0 ? L.F(ly.s0) : L.F((t - 1) & 1 ? ly.sB : ly.sA);
         r.v = r.x + 3 * np;
+        r.x_abs = t == 0;  // the uploaded start state is absolute; later states are displacements
         r.xo = L.F(t & 1 ? ly.sB : ly.sA);
         r.vo = r.xo + 3 * np;
         if (t % q.K == 0) {

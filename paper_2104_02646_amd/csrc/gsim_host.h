@@ -27,6 +27,7 @@ struct gsim_plan {
     std::vector<gsim::Tile> etiles;
     std::vector<uint32_t> tet_code, tri_code, hin_code;  // SoA [corners][n]
     std::vector<int32_t> tp_id, tp_run, tp_slot;
+    int tile_elems = gsim::ETILE;                  // elements per two-pass element tile
     int64_t etile_words[2] = {0, 0};               // largest tile's LDS words, forward / adjoint
     std::vector<int32_t> gbase;                    // [n_slices] sliced-ELL slice bases of the partials
     std::vector<int32_t> pdeg;                     // [np] partials per particle (tiles touching it)
@@ -38,6 +39,7 @@ struct gsim_plan {
     std::vector<int32_t> coff;                     // colour boundaries (fused element positions)
     std::vector<int32_t> cbase, ncol;              // [nb][3] first entry in coff, number of colours
     std::vector<uint8_t> pinned;                   // [np]
+    std::vector<double> rest;                      // [np][3] rest positions (state positions are relative to them)
     std::vector<double> dt, grav, plane, kb;       // per body
     std::vector<uint8_t> contact_on;               // per body
     std::vector<uint8_t> air_on;                   // per body: lift/drag on its triangles
@@ -57,7 +59,9 @@ struct Layout {
     size_t hin_code, hin_phi0;
     size_t tp;
     size_t gbase, pdeg, pinned, slots, vslots, cpart, lpart;  // vslots: only when a body has air
+    size_t rest, rgap;  // rest positions [3][np], rest ground gaps [np]
     size_t fbuf, abuf;  // forward / adjoint internal ping-pong states
+    size_t fbar;        // [2][3][np] adjoint forces handed from one adjoint step to the next
     // fused path: colour-ordered element records, colour bounds, body launch order
     size_t f_tet_idx, f_tet_dinv, f_tet_vol, f_tet_orig, f_tri_idx, f_tri_dinv, f_tri_area, f_tri_orig;
     size_t f_hin_idx, f_hin_phi0, f_hin_orig, coff, border, f_par, f_ktri, f_g, f_gk, f_hpar, f_gh;

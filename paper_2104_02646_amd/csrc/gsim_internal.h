@@ -1,6 +1,10 @@
 // Internal layouts shared by the HIP kernels and the host runtime of libgsim.
 //
 // Device data of one model (all inside the caller-owned workspace):
+//   rest positions X [3][np] and rest ground gaps [np]: positions in every state
+//     buffer the library owns (internal ping-pong states, checkpoints, segments)
+//     are displacements u = x - X, so deformation is resolved in FP32 however far
+//     the body is from the origin; the caller's states are absolute;
 //   element records, SoA over elements of each kind:
 //     tets    idx[4][ne] (int32, model-global particle index), dinv[9][ne] (Dm^-1
 //             row-major), vol[ne], slot[4][ne] (corner -> gather slot)
@@ -71,6 +75,8 @@ struct ModelDev {
     const int32_t* gbase;  // [n_slices] first partial slot of each 64-particle slice
     const int32_t* pdeg;   // [np] partials per particle
     const uint8_t* pinned;
+    const T* rest;  // [3][np] rest positions X: the state holds displacements u = x - X
+    const T* rgap;  // [np] rest ground gap n.X - d of each particle (its body's plane)
     const BodyDev<T>* bodies;
     T* slots;   // [nslot][4] per-(tile, particle) partial sums
     T* vslots;  // [nslot][4] velocity-adjoint partials of air tiles (null when no body has air)
@@ -111,6 +117,9 @@ struct StepDev {
     const T* vb;
     T* xbo;       // adjoint of the step input
     T* vbo;
+    const T* fb;  // adjoint: this step's adjoint force dt w (vbar+ + dt xbar+), stored by the
+                  // previous adjoint step's particle pass (null: formed from xb, vb)
+    T* fbo;       // particle adjoint: store the previous step's adjoint force here (or null)
     const T* mu;
     const T* lam;
     const T* act;
@@ -134,6 +143,8 @@ struct StepDev {
     int32_t nsteps;    // steps run by one fused launch
     int32_t t_base;    // absolute index of its first step (checkpoint slots)
     int32_t ckpt_every;
+    int32_t x_abs;     // x holds absolute positions (the caller's state), not displacements
+    int32_t xo_abs;    // forward: write absolute positions to xo (the caller's state)
     int32_t pad;
 };
 

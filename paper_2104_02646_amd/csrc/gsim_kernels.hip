@@ -65,6 +65,26 @@ template <typename T> __device__ __forceinline__ T inv_mass(const ModelDev<T>& M
     return pin ? T(0) : T(1) / m;
 }
 
+// State positions are displacements u from the rest positions, except where a
+// launch record marks its input (x_abs) or output (xo_abs) as absolute positions
+// (the caller's states at the ends of a call).  Tets use u itself; triangles,
+// hinges and lift/drag take the absolute position X + u.
+template <typename T>
+__device__ __forceinline__ V3<T> load_disp(const ModelDev<T>& M, const T* x, int32_t abs, int64_t i) {
+    const V3<T> a = ld3(x, M.np, i);
+    return abs ? a - ld3(M.rest, M.np, i) : a;
+}
+template <typename T>
+__device__ __forceinline__ V3<T> load_pos(const ModelDev<T>& M, const T* x, int32_t abs, int64_t i) {
+    const V3<T> a = ld3(x, M.np, i);
+    return abs ? a : ld3(M.rest, M.np, i) + a;
+}
+// Ground gap of particle i at displacement u: its rest gap n.X - d plus n.u.
+template <typename T>
+__device__ __forceinline__ T gap_of(T rgap, const T pl[4], V3<T> u) {
+    return rgap + dot(mk3(pl[0], pl[1], pl[2]), u);
+}
+
 // Sum, in slot order, of a particle's deg partial slots at base, base + 64, ...
 // (xyz into f, w into d).  The first SLOT_BATCH slots are fetched before any is
 // used, so their loads overlap instead of waiting one after another; the sum order
@@ -91,24 +111,58 @@ __device__ __forceinline__ void sum_slots(const T* slots, int64_t base, int32_t 
 }
 
 // ---------------------------------------------------------- tet (NH) ---
-// F = Ds Dm^-1; P = mu (1 - 1/(Ic+1)) F + lambda (J - alpha) cof F with
-// alpha = 1 + 3 mu/(4 lambda) + a; corner forces [f1 f2 f3] = -V P Dm^-T,
-// f0 = -(f1 + f2 + f3).
+// The state holds each particle's displacement u from its rest position, so the
+// displacement gradient H = F - I = [u1-u0, u2-u0, u3-u0] Dm^-1 comes straight from
+// differences of small numbers, and every term that vanishes at rest is formed
+// from H without subtracting O(1) quantities:
+//   s      = Ic - 3 = 2 tr H + |H|^2,              1 - 1/(Ic+1) = 3/4 + s / (4 (4 + s)),
+//   J - 1  = tr H + tr(cof H) + det H               (characteristic polynomial of H),
+//   cof F  = (1 + tr H) I - H^T + cof H,
+//   Pmu    = (1 - 1/(Ic+1)) F - 3/4 cof F = 3/4 (H + H^T - tr H I - cof H) + s/(4(4+s)) F.
+// With alpha = 1 + 3 mu/(4 lambda) + a the stress is
+//   P = mu (1 - 1/(Ic+1)) F + lambda (J - alpha) cof F = mu Pmu + lambda (J - 1 - a) cof F,
+// whose parameter partials are dP/dmu = Pmu, dP/dlambda = (J - 1 - a) cof F and
+// dP/da = -lambda cof F.  Corner forces [f1 f2 f3] = -V P Dm^-T, f0 = -(f1 + f2 + f3).
 template <typename T>
-__device__ __forceinline__ void tet_force(const V3<T> x[4], const T D[9], T V, T mu, T lam, T act, V3<T> f[4]) {
-    const V3<T> d0 = x[1] - x[0], d1 = x[2] - x[0], d2 = x[3] - x[0];
-    V3<T> F[3];
+struct TetKin {
+    V3<T> F[3];    // columns of F = I + H
+    V3<T> C[3];    // columns of cof F
+    V3<T> Pmu[3];  // columns of dP/dmu
+    T s, J1;       // Ic - 3, J - 1
+};
+
+template <typename T>
+__device__ __forceinline__ void tet_kin(const V3<T> u[4], const T D[9], TetKin<T>& k) {
+    const V3<T> d0 = u[1] - u[0], d1 = u[2] - u[0], d2 = u[3] - u[0];
+    V3<T> H[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) F[j] = d0 * D[j] + d1 * D[3 + j] + d2 * D[6 + j];
-    const T Ic = dot(F[0], F[0]) + dot(F[1], F[1]) + dot(F[2], F[2]);
-    const V3<T> C[3] = {cross(F[1], F[2]), cross(F[2], F[0]), cross(F[0], F[1])};
-    const T J = dot(F[0], C[0]);
-    const T alpha = T(1) + T(0.75) * mu / lam + act;
-    const T A = mu * (T(1) - T(1) / (Ic + T(1)));
-    const T B = lam * (J - alpha);
+    for (int j = 0; j < 3; ++j) H[j] = d0 * D[j] + d1 * D[3 + j] + d2 * D[6 + j];
+    // row j of H, as a vector (column j of H^T)
+    const V3<T> R[3] = {mk3(H[0].x, H[1].x, H[2].x), mk3(H[0].y, H[1].y, H[2].y), mk3(H[0].z, H[1].z, H[2].z)};
+    const T tr = H[0].x + H[1].y + H[2].z;
+    const V3<T> cH[3] = {cross(H[1], H[2]), cross(H[2], H[0]), cross(H[0], H[1])};
+    const T detH = dot(H[0], cH[0]);
+    const T tcH = cH[0].x + cH[1].y + cH[2].z;
+    k.s = T(2) * tr + (dot(H[0], H[0]) + dot(H[1], H[1]) + dot(H[2], H[2]));
+    k.J1 = tr + tcH + detH;
+    const T q = k.s / (T(4) * (T(4) + k.s));
+    const V3<T> E[3] = {mk3(T(1), T(0), T(0)), mk3(T(0), T(1), T(0)), mk3(T(0), T(0), T(1))};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        k.F[j] = H[j] + E[j];
+        k.C[j] = E[j] * (T(1) + tr) - R[j] + cH[j];
+        k.Pmu[j] = (H[j] + R[j] - E[j] * tr - cH[j]) * T(0.75) + k.F[j] * q;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void tet_force(const V3<T> u[4], const T D[9], T V, T mu, T lam, T act, V3<T> f[4]) {
+    TetKin<T> k;
+    tet_kin(u, D, k);
+    const T B = lam * (k.J1 - act);
     V3<T> P[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) P[j] = F[j] * A + C[j] * B;
+    for (int j = 0; j < 3; ++j) P[j] = k.Pmu[j] * mu + k.C[j] * B;
     f[0] = zero3<T>();
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -117,42 +171,41 @@ __device__ __forceinline__ void tet_force(const V3<T> x[4], const T D[9], T V, T
     }
 }
 
-// Reverse mode of tet_force for corner adjoints fb: position adjoints xb (the
-// transpose of df/dx applied to fb), d/dmu, d/dlambda and d/da of <fb, f>; also
-// returns the forces themselves (for the mass gradient).
+// Reverse mode of tet_force for corner adjoints fb: displacement (= position)
+// adjoints xb (the transpose of df/dx applied to fb), d/dmu, d/dlambda and d/da
+// of <fb, f>; also returns the forces themselves (for the mass gradient).  The
+// position adjoint differentiates P = A F + B cof F with A = mu (1 - 1/(Ic+1)) and
+// B = lambda (J - alpha) (both O(mu) at rest, so no cancellation reaches it).
 template <typename T>
-__device__ __forceinline__ void tet_adjoint(const V3<T> x[4], const T D[9], T V, T mu, T lam, T act, const V3<T> fb[4],
+__device__ __forceinline__ void tet_adjoint(const V3<T> u[4], const T D[9], T V, T mu, T lam, T act, const V3<T> fb[4],
                                             V3<T> f[4], V3<T> xb[4], T& gmu, T& glam, T& gact) {
-    const V3<T> d0 = x[1] - x[0], d1 = x[2] - x[0], d2 = x[3] - x[0];
-    V3<T> F[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) F[j] = d0 * D[j] + d1 * D[3 + j] + d2 * D[6 + j];
-    const T Ic = dot(F[0], F[0]) + dot(F[1], F[1]) + dot(F[2], F[2]);
-    const V3<T> C[3] = {cross(F[1], F[2]), cross(F[2], F[0]), cross(F[0], F[1])};
-    const T J = dot(F[0], C[0]);
-    const T alpha = T(1) + T(0.75) * mu / lam + act;
-    const T ip = T(1) / (Ic + T(1));
-    const T A = mu * (T(1) - ip);
-    const T B = lam * (J - alpha);
+    TetKin<T> k;
+    tet_kin(u, D, k);
+    const V3<T>* F = k.F;
+    const V3<T>* C = k.C;
+    const T Ja = k.J1 - act;
     V3<T> P[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) P[j] = F[j] * A + C[j] * B;
+    for (int j = 0; j < 3; ++j) P[j] = k.Pmu[j] * mu + C[j] * (lam * Ja);
     f[0] = zero3<T>();
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         f[i + 1] = (P[0] * D[3 * i] + P[1] * D[3 * i + 1] + P[2] * D[3 * i + 2]) * (-V);
         f[0] -= f[i + 1];
     }
-    // f_{i+1} = H_i, f_0 = -sum H_i  =>  Hbar_i = fb_{i+1} - fb_0
+    // f_{i+1} = G_i, f_0 = -sum G_i  =>  Gbar_i = fb_{i+1} - fb_0
     const V3<T> Hb[3] = {fb[1] - fb[0], fb[2] - fb[0], fb[3] - fb[0]};
     V3<T> Pb[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) Pb[j] = (Hb[0] * D[j] + Hb[1] * D[3 + j] + Hb[2] * D[6 + j]) * (-V);
     const T Ab = dot(Pb[0], F[0]) + dot(Pb[1], F[1]) + dot(Pb[2], F[2]);
     const T Bb = dot(Pb[0], C[0]) + dot(Pb[1], C[1]) + dot(Pb[2], C[2]);
-    gmu = (T(1) - ip) * Ab - T(0.75) * Bb;  // dA/dmu = 1 - 1/(Ic+1), dB/dmu = -3/4
-    glam = (J - T(1) - act) * Bb;          // dB/dlambda = J - alpha + 3mu/(4 lambda)
-    gact = -lam * Bb;                      // dB/da = -lambda
+    gmu = dot(Pb[0], k.Pmu[0]) + dot(Pb[1], k.Pmu[1]) + dot(Pb[2], k.Pmu[2]);
+    glam = Ja * Bb;
+    gact = -lam * Bb;
+    const T ip = T(1) / (T(4) + k.s);             // 1/(Ic+1)
+    const T A = mu * (T(0.75) + k.s * T(0.25) * ip);  // mu (1 - 1/(Ic+1))
+    const T B = lam * Ja - T(0.75) * mu;          // lambda (J - alpha)
     const T Icb = Ab * mu * ip * ip;
     const T Jb = Bb * lam;
     V3<T> Fb[3], Cb[3];
@@ -169,7 +222,7 @@ __device__ __forceinline__ void tet_adjoint(const V3<T> x[4], const T D[9], T V,
     Fb[0] += cross(F[1], Cb[2]);
     Fb[1] += cross(Cb[2], F[0]);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) xb[k + 1] = Fb[0] * D[3 * k] + Fb[1] * D[3 * k + 1] + Fb[2] * D[3 * k + 2];
+    for (int c = 0; c < 3; ++c) xb[c + 1] = Fb[0] * D[3 * c] + Fb[1] * D[3 * c + 1] + Fb[2] * D[3 * c + 2];
     xb[0] = -(xb[1] + xb[2] + xb[3]);
 }
 
@@ -507,7 +560,8 @@ __global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict_
     for (int j = tid; j < m; j += nth) {
         const gi4 r = ld_tp(M.tp, (int64_t)tl.id + j);
         if (j == tid) mine = r;
-        xs[j] = l4(ld3(S.x, np, (int64_t)r.x), T(0));
+        xs[j] = l4(tl.kind == TILE_TET ? load_disp(M, S.x, S.x_abs, (int64_t)r.x) : load_pos(M, S.x, S.x_abs, (int64_t)r.x),
+                   T(0));
         if (air) vs[j] = l4(ld3(S.v, np, (int64_t)r.x), T(0));
     }
     __syncthreads();
@@ -598,29 +652,41 @@ __global__ void __launch_bounds__(512) k_part_fwd(const ModelDev<T>* __restrict_
         const int64_t li = i - B.p0;
         const int64_t gb = M.gbase[B.g0 + (li >> 6)];
         const int32_t deg = M.pdeg[i];
-        const V3<T> x = ld3(S.x, np, i), v = ld3(S.v, np, i);
+        const V3<T> u = load_disp(M, S.x, S.x_abs, i), v = ld3(S.v, np, i);
+        const T rg = contact ? gld(M.rgap, i) : T(0);
         const T w = inv_mass(M, S, i);
         V3<T> f = zero3<T>();
         T unused = T(0);
         sum_slots(M.slots, gb + (li & 63), deg, f, unused);
         if (S.ckx) {
-            st3(S.ckx, np, i, x);
+            st3(S.ckx, np, i, u);
             st3(S.ckv, np, i, v);
         }
-        if (contact) f += contact_force(x, v, pl, cp);
+        if (contact) f += contact_force_gap(gap_of(rg, pl, u), v, pl, cp);
         const T gate = w > T(0) ? T(1) : T(0);
         const V3<T> vn = v + (f * w + g * gate) * dt;
+        const V3<T> un = u + vn * dt;
         st3(S.vo, np, i, vn);
-        st3(S.xo, np, i, x + vn * dt);
+        st3(S.xo, np, i, S.xo_abs ? ld3(M.rest, np, i) + un : un);
     }
 }
 
-// Corner adjoint force of particle p: fbar = dt w (vbar+ + dt xbar+).
+// Adjoint force of a particle: fbar = dt w (vbar+ + dt xbar+), with one explicit
+// fused multiply-add per component so that every kernel forming it from the same
+// adjoint state gets the same bits.
+__device__ __forceinline__ float gfma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double gfma(double a, double b, double c) { return fma(a, b, c); }
+template <typename T>
+__device__ __forceinline__ V3<T> fbar_of(V3<T> xb, V3<T> vb, T dt, T w) {
+    const T s = dt * w;
+    return mk3(gfma(xb.x, dt, vb.x) * s, gfma(xb.y, dt, vb.y) * s, gfma(xb.z, dt, vb.z) * s);
+}
+// Adjoint force of particle p at this adjoint step: the one the previous adjoint
+// step's particle pass stored (S.fb), or formed from the adjoint state.
 template <typename T>
 __device__ __forceinline__ V3<T> corner_fbar(const ModelDev<T>& M, const StepDev<T>& S, int64_t p, T dt) {
-    const T w = inv_mass(M, S, p);
-    const V3<T> vt = ld3(S.vb, M.np, p) + ld3(S.xb, M.np, p) * dt;
-    return vt * (dt * w);
+    if (S.fb) return ld3(S.fb, M.np, p);
+    return fbar_of(ld3(S.xb, M.np, p), ld3(S.vb, M.np, p), dt, inv_mass(M, S, p));
 }
 
 // Adjoint element pass, same tiling: the tile particles' positions and adjoint
@@ -653,7 +719,7 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
         const gi4 r = ld_tp(M.tp, (int64_t)tl.id + j);
         if (j == tid) mine = r;
         const int64_t p = r.x;
-        xs[j] = l4(ld3(S.x, np, p), T(0));
+        xs[j] = l4(tl.kind == TILE_TET ? load_disp(M, S.x, S.x_abs, p) : load_pos(M, S.x, S.x_abs, p), T(0));
         fbs[j] = l4(corner_fbar(M, S, p, dt), T(0));
         if (air) vs[j] = l4(ld3(S.v, np, p), T(0));
     }
@@ -786,28 +852,33 @@ __global__ void __launch_bounds__(512) k_part_adj(const ModelDev<T>* __restrict_
         const int32_t deg = M.pdeg[i];
         const V3<T> xbp = ld3(S.xb, np, i), vbp = ld3(S.vb, np, i);
         const T w = inv_mass(M, S, i);
-        V3<T> x = zero3<T>(), v = zero3<T>();
+        V3<T> u = zero3<T>(), v = zero3<T>();
+        T rg = T(0);
         if (contact) {
-            x = ld3(S.x, np, i);
+            u = load_disp(M, S.x, S.x_abs, i);
             v = ld3(S.v, np, i);
+            rg = gld(M.rgap, i);
         }
         const int64_t base = gb + (li & 63);
         V3<T> xs = zero3<T>();
         T ds = T(0);
         sum_slots(M.slots, base, deg, xs, ds);
         const V3<T> vt = vbp + xbp * dt;
-        const V3<T> fb = vt * (dt * w);
+        const V3<T> fb = fbar_of(xbp, vbp, dt, w);
         V3<T> xcb = zero3<T>(), vcb = zero3<T>();
         if (AIR && B.air_on) {  // velocity adjoint of the lift/drag force, same partial slots
             T unused = T(0);
             sum_slots(M.vslots, base, deg, vcb, unused);
         }
         if (contact) {
-            const V3<T> fc = contact_adjoint(x, v, pl, cp, fb, xcb, vcb, gc);
+            const V3<T> fc = contact_adjoint_gap(gap_of(rg, pl, u), v, pl, cp, fb, xcb, vcb, gc);
             ds += dot(fc, fb);
         }
-        st3(S.xbo, np, i, xbp + xs + xcb);
-        st3(S.vbo, np, i, vt + vcb);
+        const V3<T> xbm = xbp + xs + xcb, vbm = vt + vcb;
+        st3(S.xbo, np, i, xbm);
+        st3(S.vbo, np, i, vbm);
+        // the adjoint force of the previous step, for the next adjoint element pass
+        if (S.fbo) st3(S.fbo, np, i, fbar_of(xbm, vbm, dt, w));
         if (S.g_mass && w > T(0)) S.g_mass[i] += -w * ds;  // dm = -w^2 dw, dw = dt f.vt = f.fbar / w
     }
     if (contact && S.g_contact) {
@@ -845,7 +916,11 @@ __global__ void __launch_bounds__(512) k_loss_part(const ModelDev<T>* __restrict
     T acc[1] = {T(0)};
     for (int64_t l = threadIdx.x; l < tl.count; l += blockDim.x) {
         const int64_t i = tl.begin + l;
-        const V3<T> d = ld3(S.x, np, i) - ld3(S.target, np, i);
+        // displacement input: x = X + u rounded first, exactly as a call's final
+        // state is handed to the caller, so the loss of a state kept on the device
+        // equals the loss of that state taken out and passed back
+        const V3<T> x = S.x_abs ? ld3(S.x, np, i) : ld3(M.rest, np, i) + ld3(S.x, np, i);
+        const V3<T> d = x - ld3(S.target, np, i);
         acc[0] += dot(d, d);
         if (S.xbo) st3(S.xbo, np, i, d * scale);
         if (S.vbo) st3(S.vbo, np, i, zero3<T>());
@@ -1087,7 +1162,7 @@ __global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>
     const BodyDev<T>& B = M.bodies[b];
     const int npb = (int)B.np;
     const int64_t np = M.np, p0 = B.p0;
-    T* xs = reinterpret_cast<T*>(smem);  // [3][npb] positions
+    T* xs = reinterpret_cast<T*>(smem);  // [3][npb] displacements from rest
     T* vs = xs + 3 * npb;                // [3][npb] velocities
     T* fs = vs + 3 * npb;                // [3][npb] force accumulators
     int32_t* cb[3];                      // colour bounds, after the particle arrays
@@ -1102,7 +1177,7 @@ __global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>
         cp[k] = contact ? S.contact[4 * b + k] : T(0);
     }
     for (int li = threadIdx.x; li < npb; li += blockDim.x) {
-        lds_st3(xs, npb, li, ld3(S.x, np, p0 + li));
+        lds_st3(xs, npb, li, load_disp(M, S.x, S.x_abs, p0 + li));
         lds_st3(vs, npb, li, ld3(S.v, np, p0 + li));
     }
     for (int step = 0; step < S.nsteps; ++step) {
@@ -1133,7 +1208,7 @@ __global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 o.li[q] = r.li[q];
-                x[q] = lds3(xs, npb, r.li[q]);
+                x[q] = ld3(M.rest, np, p0 + r.li[q]) + lds3(xs, npb, r.li[q]);
             }
             tri_force(x, r.D, r.A, r.k, o.v);
         });
@@ -1143,7 +1218,7 @@ __global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 o.li[q] = r.li[q];
-                x[q] = lds3(xs, npb, r.li[q]);
+                x[q] = ld3(M.rest, np, p0 + r.li[q]) + lds3(xs, npb, r.li[q]);
             }
             hinge_force(x, r.phi0, B.kb, r.act, o.v);
         });
@@ -1153,7 +1228,7 @@ __global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>
             V3<T> f = lds3(fs, npb, li);
             V3<T> x = lds3(xs, npb, li);
             V3<T> v = lds3(vs, npb, li);
-            if (contact) f += contact_force(x, v, pl, cp);
+            if (contact) f += contact_force_gap(gap_of(gld(M.rgap, p), pl, x), v, pl, cp);
             const T w = inv_mass(M, S, p);
             const T gate = w > T(0) ? T(1) : T(0);
             v = v + (f * w + g * gate) * dt;
@@ -1170,7 +1245,8 @@ __global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>
     }
     if (S.xo)
         for (int li = threadIdx.x; li < npb; li += blockDim.x) {
-            st3(S.xo, np, p0 + li, lds3(xs, npb, li));
+            const V3<T> u = lds3(xs, npb, li);
+            st3(S.xo, np, p0 + li, S.xo_abs ? ld3(M.rest, np, p0 + li) + u : u);
             st3(S.vo, np, p0 + li, lds3(vs, npb, li));
         }
 }
@@ -1193,7 +1269,7 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
     const BodyDev<T>& B = M.bodies[b];
     const int npb = (int)B.np;
     const int64_t np = M.np, p0 = B.p0;
-    T* xs = reinterpret_cast<T*>(smem);  // [3][npb] positions at the step's start
+    T* xs = reinterpret_cast<T*>(smem);  // [3][npb] displacements at the step's start
     T* fbs = xs + 3 * npb;               // [3][npb] adjoint force
     T* acc = fbs + 3 * npb;              // [4][npb] xbar contributions, f . fbar
     int32_t* cb[3];                      // colour bounds, after the particle arrays
@@ -1216,8 +1292,9 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
     for (int step = S.nsteps - 1; step >= 0; --step) {
         const T* sx = step == 0 ? S.x : S.seg_in + (int64_t)(step - 1) * 6 * np;
         const T* sv = step == 0 ? S.v : sx + 3 * np;
+        const int32_t sabs = step == 0 ? S.x_abs : 0;
         for (int li = threadIdx.x; li < npb; li += blockDim.x) {
-            lds_st3(xs, npb, li, ld3(sx, np, p0 + li));
+            lds_st3(xs, npb, li, load_disp(M, sx, sabs, p0 + li));
             const V3<T> vt = ld3(S.vbo, np, p0 + li) + ld3(S.xbo, np, p0 + li) * dt;
             lds_st3(fbs, npb, li, vt * (dt * inv_mass(M, S, p0 + li)));
             lds_st3(acc, npb, li, zero3<T>());
@@ -1249,7 +1326,7 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 o.li[q] = r.li[q];
-                x[q] = lds3(xs, npb, r.li[q]);
+                x[q] = ld3(M.rest, np, p0 + r.li[q]) + lds3(xs, npb, r.li[q]);
                 fb[q] = lds3(fbs, npb, r.li[q]);
             }
             T gk;
@@ -1264,7 +1341,7 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 o.li[q] = r.li[q];
-                x[q] = lds3(xs, npb, r.li[q]);
+                x[q] = ld3(M.rest, np, p0 + r.li[q]) + lds3(xs, npb, r.li[q]);
                 fb[q] = lds3(fbs, npb, r.li[q]);
             }
             T gact;
@@ -1284,7 +1361,8 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
             T ds = acc[3 * npb + li];
             V3<T> xcb = zero3<T>(), vcb = zero3<T>();
             if (contact) {
-                const V3<T> fc = contact_adjoint(lds3(xs, npb, li), ld3(sv, np, p), pl, cp, fb, xcb, vcb, gc);
+                const V3<T> fc = contact_adjoint_gap(gap_of(gld(M.rgap, p), pl, lds3(xs, npb, li)), ld3(sv, np, p), pl,
+                                                     cp, fb, xcb, vcb, gc);
                 ds += dot(fc, fb);
             }
             st3(S.xbo, np, p, xbp + lds3(acc, npb, li) + xcb);

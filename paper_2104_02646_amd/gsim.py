@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(HERE, "libgsim.so")
 GSIM_OK, GSIM_E_INVALID, GSIM_E_TOPOLOGY, GSIM_E_DEGENERATE = 0, -1, -2, -3
 GSIM_E_WORKSPACE, GSIM_E_HIP, GSIM_E_NONFINITE, GSIM_E_UNSUPPORTED = -4, -5, -6, -7
 EXEC_PLAIN, EXEC_GRAPH, EXEC_FUSED = 0, 1, 2
+TILE_DEFAULT = 256
 
 ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan_destroy", "gsim_plan_sizes",
                "gsim_plan_counts", "gsim_plan_colouring", "gsim_plan_tiles", "gsim_plan_codes", "gsim_plan_partials",
@@ -55,7 +56,7 @@ class _Desc(C.Structure):
                 ("body_hinge_off", C.c_void_p), ("rest_x", C.c_void_p), ("tet_idx", C.c_void_p),
                 ("tri_idx", C.c_void_p), ("hinge_idx", C.c_void_p), ("pinned", C.c_void_p),
                 ("gravity", C.c_void_p), ("dt", C.c_void_p), ("ground", C.c_void_p), ("contact_on", C.c_void_p),
-                ("k_bend", C.c_void_p), ("air_on", C.c_void_p)]
+                ("k_bend", C.c_void_p), ("air_on", C.c_void_p), ("tile_elems", C.c_int)]
 
 
 class _State(C.Structure):
@@ -269,10 +270,11 @@ def pack(bodies) -> Packed:
 class Plan:
     """``gsim_plan_create``: validated, oriented, precomputed host plan."""
 
-    def __init__(self, bodies, dtype=torch.float32):
+    def __init__(self, bodies, dtype=torch.float32, tile_elems=0):
         lib = load()
         self.bodies = list(bodies)
         self.dtype = dtype
+        self.tile_elems = int(tile_elems)
         pk = pack(self.bodies)
         self.packed = pk
         d = _Desc()
@@ -288,6 +290,7 @@ class Plan:
         d.pinned, d.gravity, d.dt, d.ground = a(pk.pinned), a(pk.gravity), a(pk.dt), a(pk.ground)
         d.contact_on, d.k_bend = a(pk.contact_on), a(pk.k_bend)
         d.air_on = a(pk.air_on) if pk.air_on.any() else None
+        d.tile_elems = self.tile_elems
         h = C.c_void_p()
         _check(lib.gsim_plan_create(C.byref(d), C.byref(h)))
         self._h = h
@@ -346,8 +349,9 @@ class Plan:
 class Model:
     """``gsim_model_init`` over torch-allocated buffers, plus the per-call entry points."""
 
-    def __init__(self, bodies, dtype=torch.float32, max_steps=100, ckpt_every=10, device="cuda", stream=None):
-        self.plan = Plan(bodies, dtype)
+    def __init__(self, bodies, dtype=torch.float32, max_steps=100, ckpt_every=10, device="cuda", stream=None,
+                 tile_elems=0):
+        self.plan = Plan(bodies, dtype, tile_elems)
         self.dtype = dtype
         self.device = torch.device(device)
         self.max_steps, self.ckpt_every = int(max_steps), int(ckpt_every)

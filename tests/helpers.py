@@ -18,6 +18,18 @@ def rel(a, b):
     return d / n if n > 0 else d
 
 
+def maxrel(a, b):
+    """Largest element-wise difference relative to the largest reference magnitude:
+    a localized error that the norm ratio would average away shows here."""
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    if a.size == 0:
+        return 0.0
+    d = np.abs(a - b).max()
+    n = np.abs(b).max()
+    return d / n if n > 0 else d
+
+
 def mixed_body(seed=0):
     """Tet cube in sliding contact + small pinned cloth with bending (every force term)."""
     tet = W.tiny_cube(seed)

@@ -35,8 +35,28 @@ def test_batch_bytes_per_launch():
     assert fwd_launches == 190
     per = bench.kernel_bytes("element_fwd", NE, NP, NTP, T, K) / fwd_launches
     assert per == 64 * NE + 40 * NTP == 114550864
-    per_adj = bench.kernel_bytes("element_adj", NE, NP, NTP, T, K) / T
-    assert per_adj == 80 * NE + 69 * NTP
+    # the first adjoint step stages the adjoint state (41 B per tile particle), the others
+    # the adjoint force the previous particle adjoint stored (24 B)
+    per_adj = bench.kernel_bytes("element_adj", NE, NP, NTP, T, K)
+    assert per_adj == T * (80 * NE + 52 * NTP) + 17 * NTP
+
+
+def test_algorithmic_bytes():
+    """The scope table's accounting: per launch, and for a whole checkpointed gradient
+    (190 forward passes: 100 in the rollout, 90 recomputed)."""
+    T, K = 100, 10
+    assert bench.algorithmic_bytes("element_fwd", NE, NP, K) == 64 * NE + 12 * NP
+    assert bench.algorithmic_bytes("particle_fwd", NE, NP, K) == 52 * NP
+    assert bench.algorithmic_bytes("element_adj", NE, NP, K) == 64 * NE + 16 * NE / K + 40 * NP
+    assert bench.algorithmic_bytes("particle_adj", NE, NP, K) == 84 * NP
+    bf, ba = bench.step_algorithmic_bytes(NE, NP, K)
+    assert bf == 64 * NE + 52 * NP and ba == 64 * NE + 84 * NP + 16 * NE / K
+    assert 74 < bf / NE < 77 and 80 < ba / NE < 86  # the batch's ~75 B and ~84 B per element-step
+    total, passes = bench.gradient_bytes(NE, NP, T, K)
+    assert passes == 190 and total == 190 * bf + 100 * ba
+    # cloth: triangle 36 B, hinge 20 B per pass, stiffness gradient once per segment
+    bf, ba = bench.step_algorithmic_bytes(0, 4096, 20, nt=7938, nh=11781)
+    assert bf == 36 * 7938 + 20 * 11781 + 52 * 4096 and ba == bf + 32 * 4096 + 8 * 7938 / 20
 
 
 def test_measured_traffic_only_for_its_source():

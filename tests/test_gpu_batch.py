@@ -3,10 +3,9 @@
 10), and through the
 fused path: sampled bodies are checked one by one against the FP64 oracle
 (positions 1e-4, gradients 1e-3, norm-relative per body).  The sample holds the two
-bodies whose FP32 gradients are the most sensitive over the whole batch (29: contact
-parameters; 82: mu, lambda and mass at ~9e-4 from the oracle, with both GPU paths
-alike) and three more drawn with a fixed seed; tests/full_batch_parity.py runs every
-body."""
+bodies whose FP32 gradients were the most sensitive over the whole batch when the
+state held absolute positions (29: contact parameters; 82: mu, lambda and mass) and
+three more drawn with a fixed seed; tests/test_gpu_batch_full.py checks every body."""
 import numpy as np
 import pytest
 
