@@ -36,14 +36,37 @@ METRIC = "element-steps/s fwd+adjoint (FP32, grad err ≤1e-3); served p50/p99 q
 HBM_PEAK_GBS = 8000.0
 
 
+def algorithmic_bytes(kernel, ne, np_, K):
+    """Bytes one launch of `kernel` must move by the method's own arrays (FP32 / int32),
+    each touched once, none of the design's intermediates (tile-particle records,
+    per-tile partials, staged copies): the per-element and per-particle figures of the
+    scope table's accounting, split over the two passes.
+      element_fwd   64 Ne (tet record: corners 16, Dm^-1 36, volume 4, mu + lambda 8)
+                    + 12 Np (positions);
+      particle_fwd  52 Np (x, v, w read; x, v written);
+      element_adj   64 Ne + 16 Ne / K (mu-bar, lambda-bar written once per segment)
+                    + 40 Np (x, xbar+, vbar+, w);
+      particle_adj  84 Np (x, v, w, xbar+, vbar+ read; xbar-, vbar- written; mass-bar
+                    read-modify-write)."""
+    if kernel == "element_fwd":
+        return 64 * ne + 12 * np_
+    if kernel == "particle_fwd":
+        return 52 * np_
+    if kernel == "element_adj":
+        return 64 * ne + 16 * ne / K + 40 * np_
+    if kernel == "particle_adj":
+        return 84 * np_
+    return None
+
+
 def kernel_bytes(kernel, ne, np_, ntp, T, K):
-    """Compulsory bytes (FP32 / int32) that all launches of `kernel` in one bench step
-    move, each array touched once per pass.  Tet bodies only (the batch workload);
+    """Compulsory bytes of this design (FP32 / int32) that all launches of `kernel` in
+    one bench step move, each array touched once per pass.  Tet bodies only;
     ntp = tile particles (sum over element tiles of the particles each touches).
       element pass, per tet: corner codes 16, D_m^-1 36, volume 4, mu + lambda 8
         (adjoint: + mu-bar, lambda-bar read-modify-write 16); per tile particle:
-        record (index, run, partial slot) 12, positions 12 (adjoint: + xbar+,
-        vbar+ 24, mass 4, pinned 1), partial write 16;
+        record (index, run, partial slot) 12, positions 12 (adjoint: + the adjoint force
+        12), partial write 16;
       particle pass, per particle: partial count 4, x, v 24, mass 4, pinned 1, writes
         24 (adjoint: xbar+, vbar+ 24, x, v 24, mass 4, pinned 1, partial count 4,
         writes 24, mass-bar read-modify-write 8); per partial: 16; checkpoint stores
@@ -55,9 +78,13 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
     if kernel == "particle_fwd":
         return fwd_passes * (57 * np_ + 16 * ntp) + nseg * 24 * np_
     if kernel == "element_adj":
-        return T * (80 * ne + 69 * ntp)
+        # adjoint force handed over by the previous particle adjoint: x and fbar (24)
+        # per tile particle, except for the first adjoint step (x, xbar+, vbar+, mass,
+        # pinned: 41)
+        return T * (80 * ne + 52 * ntp) + 17 * ntp
     if kernel == "particle_adj":
-        return T * (89 * np_ + 16 * ntp)
+        # + the adjoint force of the previous step written (12 per particle)
+        return T * (101 * np_ + 16 * ntp) - 12 * np_
     if kernel == "fused_fwd":
         # per step: tet record 56 + mu, lambda 8 + original index 4; mass, pinned 5 per particle;
         # per launch: state in 24 (+ out 24 for the rollout); stores: checkpoints, segment states
@@ -72,36 +99,76 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
 
 # HBM bytes per launch of the two-pass kernels on the default workload, from the
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs summarised in
-# profiles/batch256_tiled_two_pass_kernel_stats.md (FETCH_SIZE scaled by 2.0 and
-# WRITE_SIZE by 1.0, the factors a 1 GiB copy gives).  They hold for the kernel
-# sources with this SHA-1 (of gsim_kernels.hip followed by gsim_device.h) only; for any
-# other source the traffic is reported as null.
+# profiles/batch256_two_pass_kernel_stats.md (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by
+# 1.0, the factors a 1 GiB copy gives).  They hold for the kernel sources with this SHA-1
+# (of gsim_kernels.hip followed by gsim_device.h) and 512-element tiles only; for any other
+# source or tile size the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "source_sha1": "8c37a4dcec0f803f76f94fdf1763686f2b7bd128",
-    "workload": (256, 100, 10),
-    "per_launch": {"element_fwd": 111.37e6, "particle_fwd": 30.55e6, "element_adj": 142.23e6,
-                   "particle_adj": 40.00e6},
+    "source_sha1": "0d1d1e632825bb186887573d7fab86b9885cb962",
+    "workload": (256, 100, 10, 512),  # bodies, steps, checkpoint interval, elements per tile
+    "per_launch": {"element_fwd": 108.48e6, "particle_fwd": 29.74e6, "element_adj": 134.23e6,
+                   "particle_adj": 42.81e6},
 }
 
 
-def measured_traffic(kernel, bodies, T, K):
+def measured_traffic(kernel, bodies, T, K, tile_elems=256):
     import hashlib
     h = hashlib.sha1()
     for name in ("gsim_kernels.hip", "gsim_device.h"):
         with open(os.path.join(ROOT, "paper_2104_02646_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     sha = h.hexdigest()
-    if sha != MEASURED_TRAFFIC["source_sha1"] or (bodies, T, K) != MEASURED_TRAFFIC["workload"]:
+    if sha != MEASURED_TRAFFIC["source_sha1"] or (bodies, T, K, tile_elems) != MEASURED_TRAFFIC["workload"]:
         return None
     return MEASURED_TRAFFIC["per_launch"].get(kernel)
 
 
-def step_algorithmic_bytes(ne, np_, K):
+def step_algorithmic_bytes(ne, np_, K, nt=0, nh=0):
     """Whole-step accounting: B_f = 64 Ne + 52 Np per forward step, B_a = 64 Ne + 84 Np
-    + 16 Ne/K per adjoint step; checkpointed fwd+adj = 2 B_f + B_a per step."""
-    bf = 64 * ne + 52 * np_
-    ba = 64 * ne + 84 * np_ + 16 * ne / K
+    + 16 Ne/K per adjoint step; triangles add 36 B (indices 12, Dm^-1 16, area 4,
+    stiffness 4) per pass and 8 Nt/K for their stiffness gradient, hinges 20 B (indices
+    16, rest angle 4)."""
+    bf = 64 * ne + 36 * nt + 20 * nh + 52 * np_
+    ba = 64 * ne + 36 * nt + 20 * nh + 84 * np_ + (16 * ne + 8 * nt) / K
     return bf, ba
+
+
+def gradient_bytes(ne, np_, T, K, nt=0, nh=0):
+    """Algorithmic bytes of one checkpointed gradient: the forward passes that run (T
+    in the rollout, T - ceil(T/K) recomputed: the first state of each segment is its
+    checkpoint) times B_f, plus T adjoint steps times B_a."""
+    bf, ba = step_algorithmic_bytes(ne, np_, K, nt, nh)
+    fwd_passes = T + (T - -(-T // K))
+    return fwd_passes * bf + T * ba, fwd_passes
+
+
+def kernel_table(timing, ne, np_, ntp, T, K):
+    """Per-kernel averages from the HIP-event timing of one gradient, with the
+    algorithmic and the design's compulsory bytes per launch."""
+    kern = {}
+    for k, (n, ms) in timing.items():
+        if n:
+            avg = ms / n
+            alg = algorithmic_bytes(k, ne, np_, K)
+            comp = kernel_bytes(k, ne, np_, ntp, T, K) / n
+            kern[k] = {"launches": n, "avg_us": avg * 1e3, "total_ms": ms, "compulsory_bytes_per_launch": comp,
+                       "compulsory_GBps": comp / (avg * 1e-3) / 1e9}
+            if alg is not None:
+                kern[k].update(algorithmic_bytes_per_launch=alg, GBps=alg / (avg * 1e-3) / 1e9)
+    return kern
+
+
+def roofline(d, name, traffic):
+    """Roofline object of the dominant kernel: achieved = algorithmic bytes per launch /
+    average launch duration; the design's compulsory bytes and the HBM counter traffic
+    (per launch, null when not taken for this source) beside it, each as a ratio to
+    the algorithmic bytes."""
+    alg = d["algorithmic_bytes_per_launch"]
+    return {"bound": "hbm", "kernel": name, "achieved": d["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_over_algorithmic": None if traffic is None else traffic / alg,
+            "algorithmic_bytes_per_launch": alg, "compulsory_bytes_per_launch": d["compulsory_bytes_per_launch"],
+            "compulsory_over_algorithmic": d["compulsory_bytes_per_launch"] / alg, "avg_launch_us": d["avg_us"]}
 
 
 def cpu_baseline(bodies, targets, T, budget_tets):
@@ -115,14 +182,158 @@ def cpu_baseline(bodies, targets, T, budget_tets):
         sample.append(i)
         tot += b.ne
     out = {}
-    t0 = time.perf_counter()
-    for i in sample:
-        b = bodies[i]
-        o = orc.Oracle(b.X, tets=b.tets, pinned=b.pinned, gravity=b.gravity, ground=True, plane=b.plane, dt=b.dt)
-        L, g, xs, vs = o.loss_and_grad(b.params(), b.x0, b.v0, T, targets[i], want=("mu", "lam", "mass"))
-        out[i] = (L, g, xs[-1])
-    dt = time.perf_counter() - t0
-    return sample, tot, dt, out
+    # one host core, like taskset -c 0: the oracle runs in this thread, pinned to core 0
+    keep = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {min(keep)})
+    try:
+        t0 = time.perf_counter()
+        for i in sample:
+            b = bodies[i]
+            o = orc.Oracle(b.X, tets=b.tets, pinned=b.pinned, gravity=b.gravity, ground=True, plane=b.plane, dt=b.dt)
+            L, g, xs, vs = o.loss_and_grad(b.params(), b.x0, b.v0, T, targets[i], want=("mu", "lam", "mass"))
+            out[i] = (L, g, xs[-1])
+        dt = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, keep)
+    return sample, tot, dt, out, min(keep)
+
+
+# The paper's timing analysis (Table 4, right): differentiable-physics steps per second
+# of deformable simulation by tet count, forward and backward; hardware and precision
+# not stated.  Context only.
+PAPER_TABLE4_RIGHT = {"hardware": "not stated", "unit": "simulation steps/s (Hz)",
+                      "rows": [{"tets": n, "fwd_hz": f, "bwd_hz": b, "fwd_elem_steps_per_s": n * f,
+                                "fwd_plus_bwd_elem_steps_per_s": n / (1.0 / f + 1.0 / b)}
+                               for n, f, b in ((100, 9057, 3721), (200, 9057, 3780), (400, 8751, 3750),
+                                               (1000, 4174, 1644), (2000, 3967, 1655), (5000, 3871, 1553),
+                                               (10000, 3721, 1429))]}
+
+
+def host_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+
+
+def gradient_line(bodies, dtype, T, K, exec_mode, lanes=1, reps=3, timing=False, targets=None):
+    """One model of `bodies`: median ms of a checkpointed gradient (rollout, loss, zeroed
+    gradients, adjoint) and of a forward rollout, HIP events on the launch stream; with
+    `timing`, also one gradient in plain execution with per-kernel events and the
+    dominant kernel's roofline on the algorithmic bytes."""
+    import torch
+    from paper_2104_02646_amd import gsim
+    stream = torch.cuda.Stream()
+    ne = sum(b.ne for b in bodies)
+    nel = sum(b.ne + b.nt + b.nh for b in bodies)
+    np_ = sum(b.np for b in bodies)
+    with torch.cuda.stream(stream):
+        m = gsim.Model(bodies, dtype, max_steps=T, ckpt_every=K)
+        m.set_exec(exec_mode)
+        m.set_lanes(min(lanes, len(bodies)))
+        p = m.params_from_bodies()
+        x0 = gsim.soa(np.concatenate([b.x0 for b in bodies])).to(dtype)
+        v0 = gsim.soa(np.concatenate([b.v0 for b in bodies])).to(dtype)
+        tgt = (gsim.soa(np.concatenate(targets)) if targets is not None else x0 + 0.01).to(dtype)
+        xT, vT = m.empty_state()
+        xb0, vb0 = m.empty_state()
+        want = tuple(k for k, n in (("mu", m.ne), ("lam", m.ne), ("ktri", m.nt)) if n) + ("mass", "contact")
+        g = m.zero_grads(want)
+
+        def grad():
+            m.rollout(p, x0, v0, T, out=(xT, vT), stream=stream)
+            loss, xb, vb = m.loss_mse(xT, tgt, stream=stream)
+            for t in g.values():
+                t.zero_()
+            m.rollout_backward(p, T, xb, vb, g, out=(xb0, vb0), stream=stream)
+
+        def fwd():
+            m.rollout(p, x0, v0, T, out=(xT, vT), stream=stream)
+
+        def median_ms(f):
+            f()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+            ev[0].record(stream)
+            for k in range(reps):
+                f()
+                ev[k + 1].record(stream)
+            ev[-1].synchronize()
+            return float(np.median([ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]))
+        gms, fms = median_ms(grad), median_ms(fwd)
+        out = {"ms_per_gradient": gms, "us_per_sim_step": gms * 1e3 / T, "fwd_us_per_sim_step": fms * 1e3 / T,
+               "value": nel * T / (gms * 1e-3), "forward_value": nel * T / (fms * 1e-3)}
+        if timing:
+            m.set_exec(gsim.EXEC_PLAIN)
+            m.set_timing()
+            grad()
+            torch.cuda.synchronize()
+            t = m.read_timing()
+            m.set_timing(())
+            ntp = len(m.plan.tiles()[1])
+            kern = kernel_table(t, ne, np_, ntp, T, K)
+            dom = max((k for k in kern if "algorithmic_bytes_per_launch" in kern[k]), key=lambda k: kern[k]["total_ms"])
+            out["kernels"] = kern
+            out["roofline"] = roofline(kern[dom], dom, None)
+            gb, _ = gradient_bytes(ne, np_, T, K)
+            out["step_algorithmic"] = {"GBps": gb / (gms * 1e-3) / 1e9, "frac": gb / (gms * 1e-3) / 1e12 / 8.0}
+    del m
+    torch.cuda.synchronize()
+    return out
+
+
+def try_line(*a, **kw):
+    from paper_2104_02646_amd import gsim
+    try:
+        return gradient_line(*a, **kw)
+    except gsim.GsimError as e:
+        return {"unavailable": str(e)}
+
+
+def config_lines(W, log):
+    """The other workloads: tiny cube (FP32 and FP64), 64 x 64 cloth, large blob, and
+    the batch at 2048 bodies (working set beyond the 256 MB last-level cache), each as
+    the two-pass graph path beside the plain one-launch-per-pass path (and the fused
+    path where every body fits one workgroup's LDS)."""
+    import torch
+    from paper_2104_02646_amd import gsim
+    out = {}
+    cube = [W.tiny_cube(0).round_to(np.float32)]
+    tc = {"workload": "tiny cube: 162 tets, 64 particles, 100 steps, checkpoints every 10", "unit": "us per step "
+          "(fwd + checkpointed adjoint of one gradient, divided by its steps)"}
+    for dt, name in ((torch.float32, "f32"), (torch.float64, "f64")):
+        for ex, en in ((gsim.EXEC_GRAPH, "graph"), (gsim.EXEC_FUSED, "fused"), (gsim.EXEC_PLAIN, "plain")):
+            tc["%s_%s" % (name, en)] = try_line(cube, dt, 100, 10, ex)
+    out["tiny_cube"] = tc
+    log("configs: tiny cube done")
+    cl = [W.cloth(10).round_to(np.float32)]
+    c1 = {"workload": "cloth 64x64: 7938 triangles, 11781 hinges, 400 steps, checkpoints every 20",
+          "unit": "us per step; value in (triangle + hinge)-steps/s"}
+    for ex, en in ((gsim.EXEC_GRAPH, "graph"), (gsim.EXEC_FUSED, "fused"), (gsim.EXEC_PLAIN, "plain")):
+        c1[en] = try_line(cl, torch.float32, 400, 20, ex)
+    out["cloth"] = c1
+    log("configs: cloth done")
+    blob = W.large_blob(30).round_to(np.float32)
+    c3 = {"workload": "large blob: %d tets, %d particles, 1000 steps, checkpoints every 50" % (blob.ne, blob.np),
+          "unit": "element-steps/s"}
+    c3["graph"] = gradient_line([blob], torch.float32, 1000, 50, gsim.EXEC_GRAPH, timing=True)
+    c3["plain"] = gradient_line([blob], torch.float32, 1000, 50, gsim.EXEC_PLAIN)
+    out["large_blob"] = c3
+    log("configs: large blob done")
+    big = [b.round_to(np.float32) for b in W.batch_bodies(20, 2048)]
+    out["batch_2048"] = dict(gradient_line(big, torch.float32, 100, 10, gsim.EXEC_GRAPH, lanes=3, timing=True),
+                             workload="batch of 2048 tet bodies (%d tets, %d particles), 100 steps, checkpoints "
+                                      "every 10: working set beyond the 256 MB last-level cache"
+                                      % (sum(b.ne for b in big), sum(b.np for b in big)),
+                             unit="element-steps/s")
+    del big
+    log("configs: 2048-body batch done")
+    return out
 
 
 def serving(n_measured, n_warm, ckpt_every, log):
@@ -149,10 +360,25 @@ def serving(n_measured, n_warm, ckpt_every, log):
         return {"p50_ms": float(np.percentile(l[m], 50) * 1e3), "p99_ms": float(np.percentile(l[m], 99) * 1e3),
                 "mean_ms": float(l[m].mean() * 1e3), "wall_s": w,
                 "req_per_s": float(len(trace) / w), "element_steps_per_s": float(work.sum() / w)}
+    # saturation: the first n_sat queries of the trace all submitted at once, so the
+    # engine's slots stay full; throughput against the queries' algorithmic bytes
+    n_sat = min(400, len(trace))
+    eng = serve.Engine(pool_bytes=8 << 30, max_live=256, max_tiles=1 << 18)
+    slat, swall, _ = serve.replay_trace(trace[:n_sat], bodies[:n_sat], eng, ckpt_every=ckpt_every, time_scale=0.0)
+    sst = eng.stats()
+    del eng
+    torch.cuda.synchronize()
+    log("serving: saturation done (%.1f s)" % swall)
+    sbytes = sum(gradient_bytes(b.ne, b.np, q.steps, ckpt_every, b.nt, b.nh)[0] for q, b in zip(trace[:n_sat],
+                                                                                              bodies[:n_sat]))
+    sat = {"queries": n_sat, "wall_s": swall, "req_per_s": n_sat / swall,
+           "element_steps_per_s": float(work[:n_sat].sum() / swall), "mean_live": sst["mean_live"],
+           "ticks": sst["ticks"], "ms_per_tick": swall * 1e3 / max(sst["ticks"], 1),
+           "algorithmic_GBps": sbytes / swall / 1e9, "frac_of_hbm_peak": sbytes / swall / 1e9 / HBM_PEAK_GBS}
     return {"queries": n_measured, "warmup_queries": n_warm, "arrival_rate": 200.0,
             "trace_span_s": float(span), "engine": dict(summary(lat, wall), mean_live=st["mean_live"],
-                                                        ticks=st["ticks"]),
-            "one_query_per_launch_fifo": summary(flat, fwall)}
+                                                        ticks=st["ticks"], ms_per_tick=wall * 1e3 / max(st["ticks"], 1)),
+            "one_query_per_launch_fifo": summary(flat, fwall), "saturation": sat}
 
 
 def control_step(model, p, x0, v0, tgt, T, steps, stream, ne, n_signals=8):
@@ -352,14 +578,19 @@ def main():
     ap.add_argument("--bodies", type=int, default=256)
     ap.add_argument("--sim-steps", type=int, default=100)
     ap.add_argument("--ckpt-every", type=int, default=10)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (tile size, lanes, execution, pass shapes) and use the flags below")
     ap.add_argument("--exec", choices=("fused", "graph", "plain"), default="graph")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--items", type=int, default=1)
     ap.add_argument("--lanes", type=int, default=3, help="concurrent launch lanes of the two-pass path (1..4)")
+    ap.add_argument("--tile", type=int, default=0, help="elements per element tile (0 = the library default)")
     ap.add_argument("--cpu-tets", type=int, default=15000, help="oracle sample size (tets)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--serve-queries", type=int, default=400, help="measured queries of the serving trace (0 = skip)")
+    ap.add_argument("--serve-queries", type=int, default=2000, help="measured queries of the serving trace (0 = skip)")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="warm-up queries before the measured ones")
+    ap.add_argument("--no-configs", action="store_true", help="skip the tiny cube, cloth, blob and 2048-body lines")
     ap.add_argument("--no-control", action="store_true", help="skip the actuated (controller-driven) step")
     ap.add_argument("--no-cloth", action="store_true", help="skip the lift/drag cloth batch")
     ap.add_argument("--no-rigid", action="store_true", help="skip the rigid-body batch")
@@ -373,7 +604,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2104_02646_amd import gsim, workloads as W
+    from paper_2104_02646_amd import autotune, gsim, workloads as W
 
     if args.calibrate_copy:
         n = 1 << 28  # 2^28 floats = 1 GiB
@@ -385,6 +616,9 @@ def main():
         print(json.dumps({"calibration": "copy", "bytes_read_per_copy": 4 * n, "bytes_written_per_copy": 4 * n,
                           "copies": 3}), flush=True)
         return
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
 
     T, K = args.sim_steps, args.ckpt_every
     t_gen = time.perf_counter()
@@ -398,11 +632,17 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream()
     t_plan = time.perf_counter()
+    tuned, t_tune = None, 0.0
     with torch.cuda.stream(stream):
-        model = gsim.Model(bodies, torch.float32, max_steps=T, ckpt_every=K, device=dev)
-        exec_mode = {"fused": gsim.EXEC_FUSED, "graph": gsim.EXEC_GRAPH, "plain": gsim.EXEC_PLAIN}[args.exec]
-        model.set_exec(exec_mode, args.block, args.items)
-        model.set_lanes(args.lanes)
+        if args.no_tune:
+            model = gsim.Model(bodies, torch.float32, max_steps=T, ckpt_every=K, device=dev, tile_elems=args.tile)
+            exec_mode = {"fused": gsim.EXEC_FUSED, "graph": gsim.EXEC_GRAPH, "plain": gsim.EXEC_PLAIN}[args.exec]
+            model.set_exec(exec_mode, args.block, args.items)
+            model.set_lanes(args.lanes)
+        else:
+            t_tune = time.perf_counter()
+            model, rep = autotune.tune_model(bodies, torch.float32, T, K, device=dev, stream=stream, use_cache=False)
+            tuned = {"model": {k: rep[k] for k in ("choice", "ms_per_gradient", "candidates_ms")}}
         p = model.params_from_bodies()
         x0 = gsim.soa(np.concatenate([b.x0 for b in bodies]))
         v0 = gsim.soa(np.concatenate([b.v0 for b in bodies]))
@@ -410,9 +650,17 @@ def main():
         xT, vT = model.empty_state()
         xb0, vb0 = model.empty_state()
         g = model.zero_grads(("mu", "lam", "mass", "contact"))
+        if tuned is not None:
+            shapes = autotune.tune(model, p, x0, v0, use_cache=False, stream=stream)
+            tuned["pass_shapes"] = {k: v["shape"] for k, v in shapes.items()}
+            t_tune = time.perf_counter() - t_tune
     stream.synchronize()
-    t_plan = time.perf_counter() - t_plan
-    ntp = len(gsim.Plan(bodies).tiles()[1])  # tile particles of the element tiles
+    t_plan = time.perf_counter() - t_plan - t_tune
+    exec_mode, block, items = model.get_exec()
+    args.exec = {gsim.EXEC_FUSED: "fused", gsim.EXEC_GRAPH: "graph", gsim.EXEC_PLAIN: "plain"}[exec_mode]
+    args.block, args.items, args.lanes = block, items, model.get_lanes()
+    tile_elems = model.plan.tile_elems or gsim.TILE_DEFAULT
+    ntp = len(gsim.Plan(bodies, tile_elems=tile_elems).tiles()[1])  # tile particles of the element tiles
 
     def bench_step():
         model.rollout(p, x0, v0, T, out=(xT, vT), stream=stream)
@@ -426,12 +674,17 @@ def main():
         for _ in range(args.warmup):
             bench_step()
         torch.cuda.synchronize()
+        # every step bracketed by HIP events on the launch stream; value = the median
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        ev[0].record(stream)
+        for k in range(args.steps):
             loss = bench_step()
+            ev[k + 1].record(stream)
         torch.cuda.synchronize()
         t_total = time.perf_counter() - t0
-        sec = t_total / args.steps
+        step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
+        sec = float(np.median(step_ms)) * 1e-3
         # forward-only rate (rollout with checkpoints)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -466,17 +719,12 @@ def main():
             alt = str(e)
 
     value = ne * T / sec
-    kern = {}
-    for k, (n, ms) in timing.items():
-        if n:
-            avg = ms / n
-            by = kernel_bytes(k, ne, np_, ntp, T, K) / n
-            kern[k] = {"launches": n, "avg_us": avg * 1e3, "total_ms": ms, "bytes_per_launch": by,
-                       "GBps": by / (avg * 1e-3) / 1e9}
+    kern = kernel_table(timing, ne, np_, ntp, T, K)
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     d = kern[dom]
-    bf, ba = step_algorithmic_bytes(ne, np_, K)
-    step_bw = (2 * bf + ba) * T / sec / 1e9
+    gbytes, fwd_passes = gradient_bytes(ne, np_, T, K)
+    step_bw = gbytes / sec / 1e9
+    traffic = measured_traffic(dom, len(bodies), T, K, tile_elems)
 
     result = {
         "metric": METRIC, "value": value, "unit": "element-steps/s", "n_gpus": 1, "steps": args.steps,
@@ -485,15 +733,17 @@ def main():
         "config": {"workload": "batch of %d tet bodies (log-uniform 500-20000 tets), %d steps fwd + "
                                "checkpointed adjoint (every %d), ground contact + friction" % (len(bodies), T, K),
                    "bodies": len(bodies), "tets": ne, "particles": np_, "sim_steps": T, "ckpt_every": K,
-                   "exec": args.exec, "block": args.block, "items": args.items, "lanes": args.lanes},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": measured_traffic(dom, len(bodies), T, K),
-                     "avg_launch_us": d["avg_us"], "bytes_per_launch": d["bytes_per_launch"]},
+                   "exec": args.exec, "block": args.block, "items": args.items, "lanes": args.lanes,
+                   "tile_elems": tile_elems, "autotuned": tuned},
+        "roofline": roofline(d, dom, traffic),
         "kernels": kern,
+        "step_times_ms": {"median": float(np.median(step_ms)), "mean": float(step_ms.mean()),
+                          "min": float(step_ms.min()), "max": float(step_ms.max())},
         "forward_elem_steps_per_s": ne * T / sec_fwd,
-        "step_algorithmic": {"GBps": step_bw, "frac": step_bw / HBM_PEAK_GBS,
-                             "bytes_per_elem_step": (2 * bf + ba) / ne},
-        "setup_s": {"generate": t_gen, "plan_and_upload": t_plan},
+        "step_algorithmic": {"GBps": step_bw, "frac": step_bw / HBM_PEAK_GBS, "bytes_per_gradient": gbytes,
+                             "forward_passes": fwd_passes, "adjoint_passes": T,
+                             "bytes_per_elem_step": gbytes / (ne * T)},
+        "setup_s": {"generate": t_gen, "plan_and_upload": t_plan, "autotune": t_tune},
     }
     name = {gsim.EXEC_GRAPH: "two_pass_graph", gsim.EXEC_FUSED: "fused"}[other]
     result[name] = ({"value": ne * T / alt, "ms_per_step": alt * 1e3} if isinstance(alt, float)
@@ -526,7 +776,7 @@ def main():
 
     # FP64 oracle on a bounded sample, and the FP32 gradient error of those bodies
     if not args.no_cpu:
-        sample, tot, dt_cpu, ref = cpu_baseline(bodies, targets, T, args.cpu_tets)
+        sample, tot, dt_cpu, ref, core = cpu_baseline(bodies, targets, T, args.cpu_tets)
         errs = {"x": 0.0, "mu": 0.0, "lam": 0.0, "mass": 0.0, "muf": 0.0}
         poffs = np.cumsum([0] + [b.np for b in bodies])
         eoffs = np.cumsum([0] + [b.ne for b in bodies])
@@ -541,10 +791,15 @@ def main():
             errs["mass"] = max(errs["mass"], rel(g_np["mass"][sl], gr["mass"]))
             if gr["contact"][3] != 0:
                 errs["muf"] = max(errs["muf"], abs(g_np["contact"][i, 3] - gr["contact"][3]) / abs(gr["contact"][3]))
-        result["cpu_baseline"] = {"value": tot * T / dt_cpu, "unit": "element-steps/s", "cores": 1, "kind": "oracle",
-                                  "sample": "bodies 0..%d of the batch (%d tets), %d steps fwd + loss + adjoint, "
-                                            "FP64, single thread" % (sample[-1], tot, T)}
+        result["cpu_baseline"] = dict({"value": tot * T / dt_cpu, "unit": "element-steps/s", "cores": 1,
+                                       "kind": "oracle", "pinned_core": core,
+                                       "sample": "bodies 0..%d of the batch (%d tets), %d steps fwd + loss + "
+                                                 "adjoint, FP64, single thread pinned to one core"
+                                                 % (sample[-1], tot, T)}, **host_info())
         result["parity_sample"] = {"bodies": len(sample), "max_rel_err": errs}
+    result["paper_table4_right"] = PAPER_TABLE4_RIGHT
+    if not args.no_configs:
+        result["configs"] = config_lines(W, log)
     if control is not None:
         control["overhead_vs_unactuated_step"] = control["ms_per_step"] / (sec * 1e3)
         result["control"] = control
@@ -555,8 +810,7 @@ def main():
     if not args.no_raster:
         result["raster"] = raster_bench()
     if args.serve_queries > 0:
-        result["serving"] = serving(args.serve_queries, max(20, args.serve_queries // 10), K,
-                                    lambda msg: print(msg, file=sys.stderr, flush=True))
+        result["serving"] = serving(args.serve_queries, args.serve_warmup, K, log)
     print(json.dumps(result), flush=True)
 
 

@@ -218,3 +218,34 @@ def replay_fifo(trace, bodies, ckpt_every=10, time_scale=1.0, device="cuda"):
         solve_alone(qb, device=device)
         lat[i] = (time.perf_counter() - t0) - arrivals[i]
     return lat, time.perf_counter() - t0
+
+
+def main(argv=None):
+    """Replays the seeded Poisson trace (200 req/s) through the engine and prints one
+    JSON line: p50 / p99 latency, throughput, ticks.  ``--saturate`` submits every
+    query at once instead (slots stay full)."""
+    import argparse
+    import json
+    from . import workloads as W
+    ap = argparse.ArgumentParser(prog="python -m paper_2104_02646_amd.serve")
+    ap.add_argument("--queries", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--seed", type=int, default=40)
+    ap.add_argument("--ckpt-every", type=int, default=10)
+    ap.add_argument("--saturate", action="store_true")
+    args = ap.parse_args(argv)
+    trace = W.serving_trace(args.seed, args.queries + args.warmup)
+    bodies = [W.query_body(q) for q in trace]
+    eng = Engine(pool_bytes=8 << 30, max_live=256, max_tiles=1 << 18)
+    lat, wall, _ = replay_trace(trace, bodies, eng, ckpt_every=args.ckpt_every,
+                                time_scale=0.0 if args.saturate else 1.0)
+    st = eng.stats()
+    m = lat[args.warmup:]
+    print(json.dumps({"queries": args.queries, "warmup": args.warmup, "saturate": args.saturate,
+                      "p50_ms": float(np.percentile(m, 50) * 1e3), "p99_ms": float(np.percentile(m, 99) * 1e3),
+                      "wall_s": wall, "req_per_s": len(trace) / wall, "ticks": st["ticks"],
+                      "ms_per_tick": wall * 1e3 / max(st["ticks"], 1), "mean_live": st["mean_live"]}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -65,10 +65,11 @@ def test_measured_traffic_only_for_its_source():
         with open(os.path.join(ROOT, "paper_2104_02646_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     current = h.hexdigest() == bench.MEASURED_TRAFFIC["source_sha1"]
-    v = bench.measured_traffic("element_fwd", 256, 100, 10)
+    v = bench.measured_traffic("element_fwd", 256, 100, 10, 512)
     assert (v == bench.MEASURED_TRAFFIC["per_launch"]["element_fwd"]) if current else v is None
-    assert bench.measured_traffic("element_fwd", 128, 100, 10) is None
-    assert bench.measured_traffic("element_fwd", 256, 50, 10) is None
+    assert bench.measured_traffic("element_fwd", 128, 100, 10, 512) is None
+    assert bench.measured_traffic("element_fwd", 256, 50, 10, 512) is None
+    assert bench.measured_traffic("element_fwd", 256, 100, 10, 256) is None  # other tiles: other traffic
 
 
 def test_more_than_one_gpu_is_refused():
