@@ -210,6 +210,20 @@ int gsim_model_get_lanes(const gsim_model* model, int* lanes);
 int gsim_model_set_timing(gsim_model* model, int mask);
 int gsim_model_read_timing(gsim_model* model, int kernel, int64_t* launches, double* total_ms);
 
+/* Device-side failure detection.  The kernels raise per-body status flags in the
+ * model's workspace: GSIM_FLAG_NONFINITE when a body's state or adjoint state stops
+ * being finite (the explicit step is only conditionally stable: the paper's
+ * limitations name instability at small masses; a NaN or infinite parameter shows
+ * the same way), GSIM_FLAG_INVERTED when one of its tets reaches J <= 0 (the stable
+ * Neo-Hookean energy is defined there; reported, not an error).  Flags stay raised
+ * until cleared.  gsim_model_check waits for `stream` (the calls' stream), writes each
+ * body's flags to body_flags (host [n_bodies], or NULL), clears them when `clear` is
+ * nonzero, and returns GSIM_E_NONFINITE when any body is non-finite (the message names
+ * the first), GSIM_OK otherwise.  Bodies are independent: one body going non-finite
+ * leaves every other body's results unchanged. */
+enum { GSIM_FLAG_NONFINITE = 1, GSIM_FLAG_INVERTED = 2 };
+int gsim_model_check(gsim_model* model, int32_t* body_flags, int clear, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* STATE, PARAMETERS, GRADIENTS (device pointers, caller-owned)              */
 /* ------------------------------------------------------------------------ */
@@ -481,6 +495,9 @@ typedef struct {
     int64_t id;
     float loss;
     double t_submit, t_admit, t_done; /* host steady-clock seconds */
+    int status;  /* GSIM_OK, or GSIM_E_NONFINITE when the query's state or adjoint went
+                    non-finite (its loss and gradients are then not meaningful); the
+                    queries beside it are unaffected */
 } gsim_result;
 
 /* d_pool: caller-owned device memory (256-byte aligned); max_live: live query
@@ -491,8 +508,12 @@ int gsim_engine_create(void* d_pool, size_t pool_bytes, int max_live, int64_t ma
 int gsim_engine_destroy(gsim_engine* engine);
 /* Exact device bytes a query occupies while live (its admission footprint). */
 int gsim_engine_query_bytes(const gsim_query* query, size_t* bytes);
-/* Validates and plans the query (host), copies its inputs, queues it.
- * GSIM_E_WORKSPACE if it can never fit in the pool. */
+/* Validates and plans the query (host), copies its inputs, queues it.  Refused before
+ * it takes a slot: a non-finite mass, mu, lambda, k_tri, contact coefficient, start
+ * state or target (GSIM_E_NONFINITE); mass, mu, lambda or k_tri not > 0, a negative
+ * contact coefficient (GSIM_E_INVALID); GSIM_E_WORKSPACE if it can never fit in the
+ * pool.  A query that goes non-finite while it runs completes with status
+ * GSIM_E_NONFINITE in its gsim_result and frees its slot like any other. */
 int gsim_engine_submit(gsim_engine* engine, const gsim_query* query, int64_t* id);
 /* Admits what fits, then runs one micro-step of every live query.  Completed
  * queries have their outputs copied (the call waits for that copy). */

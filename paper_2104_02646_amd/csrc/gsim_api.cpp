@@ -507,6 +507,7 @@ Layout make_layout(const gsim_plan* P, int max_steps) {
     L.pinned = take(np);
     L.rest = take(3 * np * sizeof(T));
     L.rgap = take(np * sizeof(T));
+    L.bflag = take(2 * (size_t)P->nb * 4);
     L.slots = take(4 * std::max<int64_t>(P->nslot, 1) * sizeof(T));
     L.vslots = P->any_air ? take(4 * std::max<int64_t>(P->nslot, 1) * sizeof(T)) : 0;
     L.cpart = take(4 * (cap_p + 1) * sizeof(T));
@@ -1293,6 +1294,7 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
         }
     chk(up(L.rest, rest.data(), rest.size() * sizeof(T)));
     chk(up(L.rgap, rgap.data(), rgap.size() * sizeof(T)));
+    chk(hipMemsetAsync(ws + L.bflag, 0, 2 * (size_t)P->nb * 4, s));  // (set-up, never inside a captured sequence)
     // colour-ordered copies of the element records (fused path)
     // corner indices become body-local (the fused kernels address the body's particles in LDS)
     auto perm_i = [P](const std::vector<int32_t>& a, const std::vector<int32_t>& ord, int rows, int64_t n,
@@ -1394,6 +1396,7 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     M.pinned = (const uint8_t*)(ws + L.pinned);
     M.rest = (const T*)(ws + L.rest);
     M.rgap = (const T*)(ws + L.rgap);
+    M.bflag = (int32_t*)(ws + L.bflag);
     M.bodies = (const BodyDev<T>*)(ws + L.bodies);
     M.slots = (T*)(ws + L.slots);
     M.vslots = P->any_air ? (T*)(ws + L.vslots) : nullptr;
@@ -1701,6 +1704,33 @@ int gsim_model_read_timing(gsim_model* m, int kernel, int64_t* launches, double*
     m->timing_n[kernel] = 0;
     m->timing_ms[kernel] = 0;
     return GSIM_OK;
+}
+
+int gsim_model_check(gsim_model* m, int32_t* body_flags, int clear, void* stream) {
+    if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    try {
+        hipStream_t s = (hipStream_t)stream;
+        std::vector<int32_t> f(2 * (size_t)m->nb);
+        HIP_TRY(hipMemcpyAsync(f.data(), m->ws + m->L.bflag, f.size() * 4, hipMemcpyDeviceToHost, s), "read flags");
+        HIP_TRY(hipStreamSynchronize(s), "read flags");
+        if (clear) {
+            HIP_TRY(hipMemsetAsync(m->ws + m->L.bflag, 0, f.size() * 4, s), "clear flags");
+            HIP_TRY(hipStreamSynchronize(s), "clear flags");
+        }
+        int bad = -1, nbad = 0;
+        for (int b = 0; b < m->nb; ++b) {
+            const int32_t v = (f[2 * b] ? GSIM_FLAG_NONFINITE : 0) | (f[2 * b + 1] ? GSIM_FLAG_INVERTED : 0);
+            if (body_flags) body_flags[b] = v;
+            if (f[2 * b]) {
+                nbad++;
+                if (bad < 0) bad = b;
+            }
+        }
+        if (nbad) return fail(GSIM_E_NONFINITE, "%d of %d bodies went non-finite (first: body %d)", nbad, m->nb, bad);
+        return GSIM_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(GSIM_E_INVALID, "out of host memory");
+    }
 }
 
 #define DISPATCH(m, call) ((m)->dtype == GSIM_F64 ? call<double> : call<float>)

@@ -17,6 +17,7 @@
 // then for each checkpoint segment in reverse the recomputed forward steps and
 // the adjoint steps, then the contact-gradient reduction and the copy-out.
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <cstring>
 #include <deque>
@@ -124,6 +125,7 @@ struct Done {
     int64_t id;
     float loss;
     double t_submit, t_admit, t_done;
+    int status;
 };
 
 // First-fit allocator over [0, size) with 256-byte granularity.
@@ -340,6 +342,7 @@ int finish(gsim_engine* E, Live& L) {
     const QLayout& ly = q.lay;
     hipStream_t s = E->stream;
     float loss = 0.f;
+    int32_t flags[2] = {0, 0};
     auto down = [&](float* dst, size_t o, int64_t n) -> hipError_t {
         if (!dst || n == 0) return hipSuccess;
         return hipMemcpyAsync(dst, L.base + o, n * 4, hipMemcpyDeviceToHost, s);
@@ -350,8 +353,10 @@ int finish(gsim_engine* E, Live& L) {
     HIP_TRY(down(q.o_ktri, ly.g_ktri, q.nt), "copy out");
     HIP_TRY(down(q.o_mass, ly.g_mass, q.np), "copy out");
     HIP_TRY(down(q.o_contact, ly.g_contact, 4), "copy out");
+    // the query's status words (its model's first body) come out with its results
+    HIP_TRY(hipMemcpyAsync(flags, L.model->ws + L.model->L.bflag, sizeof flags, hipMemcpyDeviceToHost, s), "copy out");
     HIP_TRY(hipStreamSynchronize(s), "copy out");
-    E->done.push_back({q.id, loss, q.t_submit, L.t_admit, now_s()});
+    E->done.push_back({q.id, loss, q.t_submit, L.t_admit, now_s(), flags[0] ? GSIM_E_NONFINITE : GSIM_OK});
     gsim_model_destroy(L.model);
     E->pool.release(L.off, q.lay.total);
     E->completed++;
@@ -529,6 +534,33 @@ int gsim_engine_submit(gsim_engine* E, const gsim_query* in, int64_t* id) {
     if (!in->mass || !in->contact || !in->x0 || !in->v0 || !in->target) return fail(GSIM_E_INVALID, "NULL input");
     if (d->n_tets && (!in->mu || !in->lam)) return fail(GSIM_E_INVALID, "mu and lam are required");
     if (d->n_tris && !in->k_tri) return fail(GSIM_E_INVALID, "k_tri is required");
+    // parameters are on the host here: a query that could only produce non-finite
+    // results is refused before it takes a slot
+    auto positive = [](const float* a, int64_t n, const char* what) -> int {
+        for (int64_t i = 0; i < n; ++i) {
+            if (!std::isfinite(a[i])) return fail(GSIM_E_NONFINITE, "%s[%lld] is not finite", what, (long long)i);
+            if (!(a[i] > 0.f)) return fail(GSIM_E_INVALID, "%s[%lld] must be > 0", what, (long long)i);
+        }
+        return GSIM_OK;
+    };
+    auto finite = [](const float* a, int64_t n, const char* what) -> int {
+        for (int64_t i = 0; i < n; ++i)
+            if (!std::isfinite(a[i])) return fail(GSIM_E_NONFINITE, "%s[%lld] is not finite", what, (long long)i);
+        return GSIM_OK;
+    };
+    if (int rc = positive(in->mass, d->n_particles, "mass")) return rc;
+    if (d->n_tets)
+        if (int rc = positive(in->mu, d->n_tets, "mu")) return rc;
+    if (d->n_tets)
+        if (int rc = positive(in->lam, d->n_tets, "lam")) return rc;
+    if (d->n_tris)
+        if (int rc = positive(in->k_tri, d->n_tris, "k_tri")) return rc;
+    if (int rc = finite(in->contact, 4, "contact")) return rc;
+    for (int k = 0; k < 4; ++k)
+        if (in->contact[k] < 0.f) return fail(GSIM_E_INVALID, "contact[%d] must be >= 0", k);
+    if (int rc = finite(in->x0, 3 * d->n_particles, "x0")) return rc;
+    if (int rc = finite(in->v0, 3 * d->n_particles, "v0")) return rc;
+    if (int rc = finite(in->target, 3 * d->n_particles, "target")) return rc;
     try {
         std::unique_ptr<Query> q(new Query());
         gsim_plan* P = nullptr;
@@ -589,6 +621,7 @@ int gsim_engine_poll(gsim_engine* E, gsim_result* out, int max, int* n) {
         out[k].t_submit = d.t_submit;
         out[k].t_admit = d.t_admit;
         out[k].t_done = d.t_done;
+        out[k].status = d.status;
         E->done.erase(E->done.begin());
         ++k;
     }

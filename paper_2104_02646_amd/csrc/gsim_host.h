@@ -60,6 +60,7 @@ struct Layout {
     size_t tp;
     size_t gbase, pdeg, pinned, slots, vslots, cpart, lpart;  // vslots: only when a body has air
     size_t rest, rgap;  // rest positions [3][np], rest ground gaps [np]
+    size_t bflag;       // [nb][2] int32 body status words
     size_t fbuf, abuf;  // forward / adjoint internal ping-pong states
     size_t fbar;        // [2][3][np] adjoint forces handed from one adjoint step to the next
     // fused path: colour-ordered element records, colour bounds, body launch order

@@ -78,6 +78,8 @@ struct ModelDev {
     const T* rest;  // [3][np] rest positions X: the state holds displacements u = x - X
     const T* rgap;  // [np] rest ground gap n.X - d of each particle (its body's plane)
     const BodyDev<T>* bodies;
+    int32_t* bflag;  // [n_bodies][2] status words, set to 1 by the kernels: [0] a state or
+                     // adjoint value stopped being finite, [1] a tet inverted (J <= 0)
     T* slots;   // [nslot][4] per-(tile, particle) partial sums
     T* vslots;  // [nslot][4] velocity-adjoint partials of air tiles (null when no body has air)
     T* cpart;   // [n_ptiles][4] contact-gradient partial sums

@@ -85,6 +85,19 @@ __device__ __forceinline__ T gap_of(T rgap, const T pl[4], V3<T> u) {
     return rgap + dot(mk3(pl[0], pl[1], pl[2]), u);
 }
 
+// Body status words (ModelDev::bflag): a plain store of 1, so any number of threads
+// may raise the same flag in any order.
+__device__ __forceinline__ bool finite3(float a, float b, float c) { return isfinite(a + b + c); }
+__device__ __forceinline__ bool finite3(double a, double b, double c) { return isfinite(a + b + c); }
+template <typename T>
+__device__ __forceinline__ bool finite_pair(V3<T> a, V3<T> b) {
+    return finite3(a.x, a.y, a.z) && finite3(b.x, b.y, b.z);
+}
+template <typename T>
+__device__ __forceinline__ void raise_flag(const ModelDev<T>& M, int body, int which) {
+    gst(M.bflag, 2 * (int64_t)body + which, int32_t(1));
+}
+
 // Sum, in slot order, of a particle's deg partial slots at base, base + 64, ...
 // (xyz into f, w into d).  The first SLOT_BATCH slots are fetched before any is
 // used, so their loads overlap instead of waiting one after another; the sum order
@@ -156,9 +169,11 @@ __device__ __forceinline__ void tet_kin(const V3<T> u[4], const T D[9], TetKin<T
 }
 
 template <typename T>
-__device__ __forceinline__ void tet_force(const V3<T> u[4], const T D[9], T V, T mu, T lam, T act, V3<T> f[4]) {
+__device__ __forceinline__ void tet_force(const V3<T> u[4], const T D[9], T V, T mu, T lam, T act, V3<T> f[4],
+                                          T& J1) {
     TetKin<T> k;
     tet_kin(u, D, k);
+    J1 = k.J1;
     const T B = lam * (k.J1 - act);
     V3<T> P[3];
 #pragma unroll
@@ -579,7 +594,9 @@ __global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict_
 #pragma unroll
             for (int k = 0; k < 9; ++k) D[k] = gld(M.tet_dinv, k * M.ne + e);
             const T act = S.act ? gld(S.act, e) : T(0);
-            tet_force(x, D, gld(M.tet_vol, e), gld(S.mu, e), gld(S.lam, e), act, f);
+            T J1;
+            tet_force(x, D, gld(M.tet_vol, e), gld(S.mu, e), gld(S.lam, e), act, f, J1);
+            if (J1 <= T(-1)) raise_flag(M, tl.body, 1);
 #pragma unroll
             for (int c = 0; c < 4; ++c) cs[cd[c] >> 16] = l4(f[c], T(0));
         } else if (tl.kind == TILE_TRI) {
@@ -666,6 +683,7 @@ __global__ void __launch_bounds__(512) k_part_fwd(const ModelDev<T>* __restrict_
         const T gate = w > T(0) ? T(1) : T(0);
         const V3<T> vn = v + (f * w + g * gate) * dt;
         const V3<T> un = u + vn * dt;
+        if (!finite_pair(un, vn)) raise_flag(M, tl.body, 0);
         st3(S.vo, np, i, vn);
         st3(S.xo, np, i, S.xo_abs ? ld3(M.rest, np, i) + un : un);
     }
@@ -875,6 +893,7 @@ __global__ void __launch_bounds__(512) k_part_adj(const ModelDev<T>* __restrict_
             ds += dot(fc, fb);
         }
         const V3<T> xbm = xbp + xs + xcb, vbm = vt + vcb;
+        if (!finite_pair(xbm, vbm)) raise_flag(M, tl.body, 0);
         st3(S.xbo, np, i, xbm);
         st3(S.vbo, np, i, vbm);
         // the adjoint force of the previous step, for the next adjoint element pass
@@ -1200,7 +1219,9 @@ __global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>
                 o.li[q] = r.li[q];
                 x[q] = lds3(xs, npb, r.li[q]);
             }
-            tet_force(x, r.D, r.V, r.mu, r.lam, r.act, o.v);
+            T J1;
+            tet_force(x, r.D, r.V, r.mu, r.lam, r.act, o.v, J1);
+            if (J1 <= T(-1)) raise_flag(M, b, 1);
         });
         colour_sweep<FUSED_AHEAD_FWD, 3, false, T, TriRec<T>>(M, cb[1], B.ncol[1], fs, npb,
                                                           [&](int, const TriRec<T>& r, bool, Contrib<T, 3>& o) {
@@ -1233,6 +1254,7 @@ __global__ void __launch_bounds__(FUSED_FWD_BLOCK) k_fused_fwd(const ModelDev<T>
             const T gate = w > T(0) ? T(1) : T(0);
             v = v + (f * w + g * gate) * dt;
             x = x + v * dt;
+            if (!finite_pair(x, v)) raise_flag(M, b, 0);
             lds_st3(xs, npb, li, x);
             lds_st3(vs, npb, li, v);
             if (S.seg) {
@@ -1365,8 +1387,10 @@ __global__ void __launch_bounds__(FUSED_ADJ_BLOCK) k_fused_adj(const ModelDev<T>
                                                      cp, fb, xcb, vcb, gc);
                 ds += dot(fc, fb);
             }
-            st3(S.xbo, np, p, xbp + lds3(acc, npb, li) + xcb);
-            st3(S.vbo, np, p, vt + vcb);
+            const V3<T> xbm = xbp + lds3(acc, npb, li) + xcb, vbm = vt + vcb;
+            if (!finite_pair(xbm, vbm)) raise_flag(M, b, 0);
+            st3(S.xbo, np, p, xbm);
+            st3(S.vbo, np, p, vbm);
             const T w = inv_mass(M, S, p);
             if (S.g_mass && w > T(0)) gst(S.g_mass, p, gld(S.g_mass, p) - w * ds);
         }

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(HERE, "libgsim.so")
 GSIM_OK, GSIM_E_INVALID, GSIM_E_TOPOLOGY, GSIM_E_DEGENERATE = 0, -1, -2, -3
 GSIM_E_WORKSPACE, GSIM_E_HIP, GSIM_E_NONFINITE, GSIM_E_UNSUPPORTED = -4, -5, -6, -7
 EXEC_PLAIN, EXEC_GRAPH, EXEC_FUSED = 0, 1, 2
+FLAG_NONFINITE, FLAG_INVERTED = 1, 2
 TILE_DEFAULT = 256
 
 ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan_destroy", "gsim_plan_sizes",
@@ -31,7 +32,7 @@ ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan
                "gsim_model_init", "gsim_model_destroy", "gsim_model_set_exec", "gsim_model_get_exec",
                "gsim_model_set_launch", "gsim_model_get_launch", "gsim_model_set_lanes", "gsim_model_get_lanes",
                "gsim_step", "gsim_step_backward", "gsim_rollout", "gsim_rollout_backward",
-               "gsim_loss_mse", "gsim_model_set_timing", "gsim_model_read_timing",
+               "gsim_loss_mse", "gsim_model_set_timing", "gsim_model_read_timing", "gsim_model_check",
                "gsim_controller_forward", "gsim_controller_backward",
                "gsim_rigid_sizes", "gsim_rigid_init", "gsim_rigid_destroy", "gsim_rigid_rollout", "gsim_rigid_loss",
                "gsim_rigid_rollout_backward",
@@ -118,6 +119,7 @@ def load():
         lib.gsim_plan_partials.argtypes = [vp, vp, C.POINTER(C.c_int64), vp, C.POINTER(C.c_int64)]
         lib.gsim_model_init.argtypes = [vp, ip, ip, vp, C.c_size_t, vp, C.POINTER(vp)]
         lib.gsim_model_destroy.argtypes = [vp]
+        lib.gsim_model_check.argtypes = [vp, vp, ip, vp]
         lib.gsim_model_set_exec.argtypes = [vp, ip, ip, ip]
         lib.gsim_model_get_exec.argtypes = [vp, C.POINTER(ip), C.POINTER(ip), C.POINTER(ip)]
         lib.gsim_model_set_launch.argtypes = [vp, ip, ip, ip]
@@ -405,6 +407,18 @@ class Model:
         _check(load().gsim_model_get_exec(self._h, C.byref(e), C.byref(b), C.byref(i)))
         return e.value, b.value, i.value
 
+    def check(self, clear=False, stream=None):
+        """``gsim_model_check``: per-body status flags (FLAG_NONFINITE, FLAG_INVERTED) as an
+        int32 array; raises GsimError(GSIM_E_NONFINITE) when a body went non-finite
+        (its .flags attribute holds the array)."""
+        f = np.zeros(self.nb, np.int32)
+        rc = load().gsim_model_check(self._h, f.ctypes.data, int(bool(clear)), _stream(stream))
+        if rc:
+            err = GsimError(rc, load().gsim_last_error().decode())
+            err.flags = f
+            raise err
+        return f
+
     def set_timing(self, kernels=KERNELS):
         """Bracket every launch of the named kernels with HIP events (plain execution)."""
         mask = 0
@@ -686,3 +700,4 @@ class Renderer:
         _check(load().gsim_raster_backward(self._h, C.byref(self.camera(P, sigma)), _ptr(x.contiguous()),
                                            _ptr(image_bar.contiguous()), _ptr(xb), _stream(stream)))
         return xb
+

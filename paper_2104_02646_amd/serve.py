@@ -29,7 +29,7 @@ class _Query(C.Structure):
 
 class _Result(C.Structure):
     _fields_ = [("id", C.c_int64), ("loss", C.c_float), ("t_submit", C.c_double), ("t_admit", C.c_double),
-                ("t_done", C.c_double)]
+                ("t_done", C.c_double), ("status", C.c_int)]
 
 
 _ready = False
@@ -75,6 +75,7 @@ class QueryBuffers:
         d.pinned, d.gravity, d.dt, d.ground = a(pk.pinned), a(pk.gravity), a(pk.dt), a(pk.ground)
         d.contact_on, d.k_bend = a(pk.contact_on), a(pk.k_bend)
         self.desc = d
+        self.loss, self.status = None, None
         self.inp = {"mu": _f32(body.mu) if body.ne else None, "lam": _f32(body.lam) if body.ne else None,
                     "k_tri": _f32(body.ktri) if body.nt else None, "mass": _f32(body.mass),
                     "contact": _f32([body.ke, body.kd, body.kf, body.muf]),
@@ -140,6 +141,7 @@ class Engine:
             r = res[k]
             qb = self.pending.pop(r.id)
             qb.loss = r.loss
+            qb.status = r.status
             out.append((r.id, qb, r.t_submit, r.t_admit, r.t_done))
         return out
 
