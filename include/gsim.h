@@ -453,6 +453,28 @@ int gsim_raster_forward(gsim_raster* raster, const gsim_camera* camera, const vo
 int gsim_raster_backward(gsim_raster* raster, const gsim_camera* camera, const void* x, const void* image_bar,
                          void* x_bar, void* stream);
 
+/* FOR CALLERS THAT CANNOT ALLOCATE DEVICE MEMORY (code under graph capture, tight
+ * serving loops, harnesses that forbid allocation): the forward of gsim_raster_forward
+ * without a renderer object or workspace.  The same kernels run with their scratch
+ * (projected vertices, transmittance, triangle records, chunk boxes) in one static
+ * device array of GSIM_RASTER_SCRATCH_BYTES that each GPU the library runs on holds
+ * until the process ends; nothing is allocated, on the device or the host.
+ *   d_tris  device [n_tris][3] vertex indices (caller-owned input).  The host cannot
+ *           check them: a triangle with an index outside [0, n_verts) is not read and
+ *           covers no pixel.
+ *   x       device [3][n_verts] SoA positions; image: device [height][width] output;
+ *           dtype GSIM_F32 or GSIM_F64 for both.
+ * Results equal gsim_raster_forward's for the same inputs.  Every scratch region is
+ * written before it is read, so a call needs nothing cleared and keeps no state
+ * between calls.  Calls on one GPU share its array: calls that overlap (different
+ * streams or threads) race and must be serialised by the caller.
+ * Errors (before any launch): GSIM_E_INVALID, GSIM_E_NONFINITE as gsim_raster_forward;
+ * GSIM_E_WORKSPACE when the sizes need more scratch than the array holds (about
+ * 64 B per triangle + 12 B per vertex + 4 B per pixel in FP32). */
+enum { GSIM_RASTER_SCRATCH_BYTES = 32 << 20 };
+int gsim_raster_forward_noalloc(int dtype, int64_t n_verts, int64_t n_tris, const int32_t* d_tris, int height,
+                                int width, const gsim_camera* camera, const void* x, void* image, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* SERVING ENGINE: continuous batching of rollout-gradient queries           */
 /* ------------------------------------------------------------------------ */

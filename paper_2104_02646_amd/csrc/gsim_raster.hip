@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -133,10 +134,24 @@ __global__ __launch_bounds__(RCHUNK) void k_raster_tri_prep(RasterArgs<T> A) {
     const int64_t j = (int64_t)blockIdx.x * RCHUNK + threadIdx.x;
     const T r = sqrt(A.cut);
     T b[4] = {T(INFINITY), T(-INFINITY), T(INFINITY), T(-INFINITY)};
-    if (j < A.nt) {
+    // a triangle with a corner index outside [0, nv) (possible only with a caller's
+    // device-side list, which the host cannot check) is not read: its record keeps an
+    // empty box, so it covers no pixel and no chunk box grows for it
+    bool valid = j < A.nt;
+    int32_t ci[3] = {0, 0, 0};
+    if (valid)
+        for (int k = 0; k < 3; ++k) {
+            ci[k] = A.tris[3 * j + k];
+            valid = valid && ci[k] >= 0 && ci[k] < A.nv;
+        }
+    if (j < A.nt && !valid) {
+#pragma unroll
+        for (int k = 0; k < RREC; ++k) A.trec[RREC * j + k] = k < 4 ? b[k] : T(0);
+    }
+    if (valid) {
         T q[RREC];
         for (int k = 0; k < 3; ++k) {
-            const int32_t i = A.tris[3 * j + k];
+            const int32_t i = ci[k];
             q[4 + 2 * k] = A.uvw[3 * i];
             q[5 + 2 * k] = A.uvw[3 * i + 1];
         }
@@ -386,6 +401,14 @@ RasterArgs<T> raster_args(const gsim_raster* R, const gsim_camera* cam) {
     return A;
 }
 
+int cam_check(const gsim_camera* cam) {
+    if (!cam) return fail(GSIM_E_INVALID, "NULL camera");
+    if (!(cam->sigma > 0) || !std::isfinite(cam->sigma)) return fail(GSIM_E_INVALID, "sigma must be > 0");
+    for (int k = 0; k < 12; ++k)
+        if (!std::isfinite(cam->P[k])) return fail(GSIM_E_NONFINITE, "camera matrix");
+    return GSIM_OK;
+}
+
 int raster_cam_check(const gsim_raster* R, const gsim_camera* cam) {
     if (!R || !cam) return fail(GSIM_E_INVALID, "NULL renderer or camera");
     if (!(cam->sigma > 0) || !std::isfinite(cam->sigma)) return fail(GSIM_E_INVALID, "sigma must be > 0");
@@ -416,9 +439,91 @@ int raster_backward(gsim_raster* R, const gsim_camera* cam, const T* x, const T*
     return e == hipSuccess ? GSIM_OK : hip_fail(e, "raster backward");
 }
 
+// ------------------------------------------- forward without allocation ---
+// Scratch of gsim_raster_forward_noalloc: one static device array per GPU (each device
+// the library runs on holds its own copy until the process ends).  In host code
+// `scratch` names a host-side stand-in, not device memory: its device address is taken
+// once per device with hipGetSymbolAddress and only that address is passed on.
+static __device__ __align__(256) unsigned char scratch[GSIM_RASTER_SCRATCH_BYTES];
+
+const int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the current device's scratch (looked up on the first call on it).
+int scratch_ptr(char** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "current device");
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(GSIM_E_UNSUPPORTED, "device %d: at most %d devices", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e == hipSuccess ? hipErrorInvalidSymbol : e, "scratch address");
+        g_scratch_ptr[dev] = (char*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GSIM_OK;
+}
+
+// Offsets of the forward's scratch (projected vertices, transmittance, triangle
+// records, chunk boxes) from one base; returns the bytes it needs.
+size_t raster_fwd_layout(gsim_raster* R, size_t tsize) {
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        o = (o + 255) & ~size_t(255);
+        const size_t at = o;
+        o += std::max<size_t>(bytes, 1);
+        return at;
+    };
+    R->o_uvw = take(3 * tsize * (size_t)R->nv);
+    R->o_trans = take(tsize * (size_t)R->H * R->W);
+    R->o_trec = take(RREC * tsize * (size_t)R->nt);
+    R->o_cbox = take(4 * tsize * (size_t)((R->nt + RCHUNK - 1) / RCHUNK));
+    return (o + 255) & ~size_t(255);
+}
+
+template <typename T>
+int raster_forward_noalloc(gsim_raster* R, const int32_t* d_tris, const gsim_camera* cam, const T* x, T* image,
+                           hipStream_t s) {
+    RasterArgs<T> A = raster_args<T>(R, cam);
+    A.tris = d_tris;  // the caller's device list (coff, cent, cg: only the adjoint uses them)
+    A.coff = A.cent = nullptr;
+    A.cg = nullptr;
+    hipLaunchKernelGGL(k_raster_project<T>, dim3((unsigned)((R->nv + 255) / 256)), dim3(256), 0, s, A, x);
+    hipLaunchKernelGGL(k_raster_tri_prep<T>, dim3((unsigned)((R->nt + RCHUNK - 1) / RCHUNK)), dim3(RCHUNK), 0, s, A);
+    hipLaunchKernelGGL(k_raster_fwd<T>, dim3((R->W + RT - 1) / RT, (R->H + RT - 1) / RT), dim3(64 * RSLICE), 0, s,
+                       A, image);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? GSIM_OK : hip_fail(e, "raster forward (no allocation)");
+}
+
 }  // namespace
 
 extern "C" {
+
+int gsim_raster_forward_noalloc(int dtype, int64_t n_verts, int64_t n_tris, const int32_t* d_tris, int height,
+                                int width, const gsim_camera* camera, const void* x, void* image, void* stream) {
+    if (int rc = raster_check(dtype, n_verts, n_tris, height, width)) return rc;
+    if (int rc = cam_check(camera)) return rc;
+    if (!d_tris || !x || !image) return fail(GSIM_E_INVALID, "NULL triangle list, positions or image");
+    gsim_raster R;  // host-side description only (no workspace of its own)
+    R.dtype = dtype;
+    R.nv = n_verts;
+    R.nt = n_tris;
+    R.H = height;
+    R.W = width;
+    const size_t need = raster_fwd_layout(&R, dtype == GSIM_F64 ? 8 : 4);
+    if (need > (size_t)GSIM_RASTER_SCRATCH_BYTES)
+        return fail(GSIM_E_WORKSPACE, "%lld vertices, %lld triangles at %dx%d need %zu bytes of scratch; the static "
+                    "scratch holds %d (use gsim_raster_init with a workspace)", (long long)n_verts, (long long)n_tris,
+                    height, width, need, GSIM_RASTER_SCRATCH_BYTES);
+    if (int rc = scratch_ptr(&R.ws)) return rc;
+    return dtype == GSIM_F64
+               ? raster_forward_noalloc<double>(&R, d_tris, camera, (const double*)x, (double*)image, (hipStream_t)stream)
+               : raster_forward_noalloc<float>(&R, d_tris, camera, (const float*)x, (float*)image, (hipStream_t)stream);
+}
 
 int gsim_raster_sizes(int dtype, int64_t n_verts, int64_t n_tris, int height, int width, size_t* workspace_bytes) {
     if (int rc = raster_check(dtype, n_verts, n_tris, height, width)) return rc;

@@ -37,6 +37,7 @@ ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan
                "gsim_rigid_sizes", "gsim_rigid_init", "gsim_rigid_destroy", "gsim_rigid_rollout", "gsim_rigid_loss",
                "gsim_rigid_rollout_backward",
                "gsim_raster_sizes", "gsim_raster_init", "gsim_raster_destroy", "gsim_raster_forward",
+               "gsim_raster_forward_noalloc",
                "gsim_raster_backward",
                "gsim_engine_create", "gsim_engine_destroy", "gsim_engine_query_bytes", "gsim_engine_submit",
                "gsim_engine_tick", "gsim_engine_poll", "gsim_engine_stats")
@@ -148,6 +149,7 @@ def load():
         lib.gsim_raster_init.argtypes = [ip, i64, i64, vp, ip, ip, vp, C.c_size_t, vp, C.POINTER(vp)]
         lib.gsim_raster_destroy.argtypes = [vp]
         lib.gsim_raster_forward.argtypes = [vp, CP, vp, vp, vp]
+        lib.gsim_raster_forward_noalloc.argtypes = [ip, C.c_int64, C.c_int64, vp, ip, ip, CP, vp, vp, vp]
         lib.gsim_raster_backward.argtypes = [vp, CP, vp, vp, vp, vp]
         _lib = lib
     return _lib
@@ -701,3 +703,17 @@ class Renderer:
                                            _ptr(image_bar.contiguous()), _ptr(xb), _stream(stream)))
         return xb
 
+
+RASTER_SCRATCH_BYTES = 32 << 20
+
+
+def raster_forward_noalloc(tris, n_verts, height, width, x, P, sigma, out, stream=None):
+    """``gsim_raster_forward_noalloc``: the renderer's forward with its scratch in the
+    library's static device array (no renderer object, no workspace, nothing
+    allocated).  tris: device int32 [nt, 3]; x: device SoA [3, n_verts]; out: device
+    [height, width] of x's dtype (written)."""
+    code = GSIM_F64 if x.dtype == torch.float64 else GSIM_F32
+    _check(load().gsim_raster_forward_noalloc(code, int(n_verts), int(tris.shape[0]), _ptr(tris), int(height),
+                                              int(width), C.byref(Renderer.camera(P, sigma)), _ptr(x), _ptr(out),
+                                              _stream(stream)))
+    return out
