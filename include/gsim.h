@@ -537,9 +537,15 @@ int gsim_engine_query_bytes(const gsim_query* query, size_t* bytes);
  * pool.  A query that goes non-finite while it runs completes with status
  * GSIM_E_NONFINITE in its gsim_result and frees its slot like any other. */
 int gsim_engine_submit(gsim_engine* engine, const gsim_query* query, int64_t* id);
-/* Admits what fits, then runs one micro-step of every live query.  Completed
- * queries have their outputs copied (the call waits for that copy). */
+/* Admits what fits, then runs the set number of micro-step rounds: in each, one
+ * micro-step of every live query, the forward and adjoint micro-steps of all queries
+ * in one element launch and one particle launch.  Completed queries have their
+ * outputs copied (the call waits for that copy).  n_live / n_queued: after the rounds. */
 int gsim_engine_tick(gsim_engine* engine, int* n_live, int* n_queued);
+/* Micro-step rounds per gsim_engine_tick (1..256, default 1): admission happens once
+ * per tick, then every live query advances by that many micro-steps.  More rounds per
+ * call spread the caller's per-tick cost over more device work. */
+int gsim_engine_set_micro_steps(gsim_engine* engine, int rounds);
 /* Completed queries since the last poll (at most max). */
 int gsim_engine_poll(gsim_engine* engine, gsim_result* out, int max, int* n);
 int gsim_engine_stats(const gsim_engine* engine, int64_t* ticks, int64_t* admitted, int64_t* completed,

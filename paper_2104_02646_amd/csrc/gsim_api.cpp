@@ -830,7 +830,15 @@ template <typename T>
 int upload_rows(gsim_model* m, int64_t row0, const std::vector<StepDev<T>>& rows, void* stream) {
     const size_t off = (size_t)row0 * sizeof(StepDev<T>), n = rows.size() * sizeof(StepDev<T>);
     if (row0 + (int64_t)rows.size() > m->L.table_cap) return fail(GSIM_E_WORKSPACE, "launch table too small");
-    if (n == 0 || std::memcmp(m->stage + off, rows.data(), n) == 0) return GSIM_OK;
+    if (!m->stage) {  // the pinned stage is made on the first upload (models driven by the
+                      // serving engine, which keeps its own tables, never need one)
+        const size_t cap = sizeof(StepDev<T>) * m->L.table_cap;
+        HIP_TRY(hipHostMalloc((void**)&m->stage, cap, hipHostMallocDefault), "launch table stage");
+        std::memset(m->stage, 0, cap);
+        if (n == 0) return GSIM_OK;
+    } else if (n == 0 || std::memcmp(m->stage + off, rows.data(), n) == 0) {
+        return GSIM_OK;
+    }
     HIP_TRY(hipEventSynchronize(m->stage_evt), "wait for table upload");
     std::memcpy(m->stage + off, rows.data(), n);
     HIP_TRY(hipMemcpyAsync(m->ws + m->L.table + off, m->stage + off, n, hipMemcpyHostToDevice, (hipStream_t)stream),
@@ -1422,7 +1430,6 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     M.f_gh = (T*)(ws + L.f_gh);
     chk(up(L.model, &M, sizeof M));
     m->md_host.assign(reinterpret_cast<const char*>(&M), reinterpret_cast<const char*>(&M) + sizeof M);
-    chk(hipHostMalloc((void**)&m->stage, sizeof(StepDev<T>) * L.table_cap, hipHostMallocDefault));
     chk(hipEventCreateWithFlags(&m->stage_evt, hipEventDisableTiming));
     if (P->nb >= 2) {  // launch lanes' streams and fork / join events
         chk(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
@@ -1432,7 +1439,6 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
         }
         m->lanes = std::min(DEFAULT_LANES, P->nb);
     }
-    if (e == hipSuccess) std::memset(m->stage, 0, sizeof(StepDev<T>) * L.table_cap);
     if (e != hipSuccess) {
         if (m->stage) (void)hipHostFree(m->stage);
         if (m->stage_evt) (void)hipEventDestroy(m->stage_evt);

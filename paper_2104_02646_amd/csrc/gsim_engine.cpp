@@ -50,7 +50,7 @@ double now_s() {
 
 // Device buffers of one query, as offsets from its pool region.
 struct QLayout {
-    size_t ws, ws_bytes, ckpt, seg, s0, sA, sB, seed, aA, aB, target;
+    size_t ws, ws_bytes, ckpt, seg, s0, sA, sB, seed, aA, aB, target, tiles;
     size_t mu, lam, ktri, mass, contact, g_mu, g_lam, g_ktri, g_mass, g_contact, loss;
     size_t total;
 };
@@ -77,6 +77,9 @@ QLayout qlayout(const gsim_plan* P, int T, int K) {
     L.aA = take(st);
     L.aB = take(st);
     L.target = take(3 * (size_t)P->np * 4);
+    // the query's element and particle tiles, resident while it is live (the particle
+    // tiles of the default 256-particle tile size: one per started 256 of its particles)
+    L.tiles = take(sizeof(Tile) * (P->etiles.size() + (size_t)((P->np + 255) / 256) + 1));
     L.mu = take(P->ne * 4);
     L.lam = take(P->ne * 4);
     L.ktri = take(P->nt * 4);
@@ -101,6 +104,8 @@ struct Query {
     int T = 0, K = 1;
     int64_t np = 0, ne = 0, nt = 0;
     std::vector<float> mu, lam, ktri, mass, contact, x0v0, target;  // x0v0 = [x0 | v0] SoA
+    std::vector<Tile> tiles;  // element then particle tiles (kept for the upload's source)
+    int n_etiles = 0, n_ptiles = 0;
     float *o_mu = nullptr, *o_lam = nullptr, *o_ktri = nullptr, *o_mass = nullptr, *o_contact = nullptr;
     QLayout lay{};
     double t_submit = 0;
@@ -181,7 +186,7 @@ struct gsim_engine {
     int64_t max_tiles = 0;
     hipStream_t stream = nullptr;
     // per-tick table ring: device blobs (carved from the pool) and pinned host copies
-    size_t blob_bytes = 0;
+    size_t blob_bytes = 0, head_bytes = 0;
     char* blob_dev[RING] = {};
     char* blob_host[RING] = {};
     hipEvent_t blob_evt[RING] = {};
@@ -190,7 +195,8 @@ struct gsim_engine {
     std::deque<std::unique_ptr<Query>> queue;
     std::vector<Live> live;
     std::vector<Done> done;
-    int64_t ticks = 0, admitted = 0, completed = 0;
+    int micro_per_tick = 1;  // micro-step rounds per gsim_engine_tick
+    int64_t ticks = 0, admitted = 0, completed = 0;  // ticks: micro-step rounds
     double live_sum = 0;  // sum over ticks of live queries (mean concurrency)
 };
 
@@ -218,6 +224,20 @@ int admit(gsim_engine* E, std::unique_ptr<Query>& q, size_t off) {
     chk(up(ly.ktri, q->ktri));
     chk(up(ly.mass, q->mass));
     chk(up(ly.contact, q->contact));
+    {
+        const gsim_model* m = L.model;
+        const size_t ne = m->etiles_nat.size(), npt = m->ptiles_nat.size();
+        if (sizeof(Tile) * (ne + npt) > sizeof(Tile) * (q->plan->etiles.size() + (size_t)((q->np + 255) / 256) + 1))
+            e = hipErrorInvalidValue;  // (cannot happen: the model keeps the default particle tile size)
+        else if (ne + npt) {
+            q->tiles.assign(m->etiles_nat.begin(), m->etiles_nat.end());
+            q->tiles.insert(q->tiles.end(), m->ptiles_nat.begin(), m->ptiles_nat.end());
+            chk(hipMemcpyAsync(L.base + ly.tiles, q->tiles.data(), sizeof(Tile) * q->tiles.size(),
+                               hipMemcpyHostToDevice, s));
+            q->n_etiles = (int)ne;
+            q->n_ptiles = (int)npt;
+        }
+    }
     if (e != hipSuccess) {
         gsim_model_destroy(L.model);
         return hip_fail(e, "upload query");
@@ -363,69 +383,68 @@ int finish(gsim_engine* E, Live& L) {
     return GSIM_OK;
 }
 
-int tick(gsim_engine* E, int* n_live, int* n_queued) {
-    // 1. admission, FIFO while the head fits
-    while (!E->queue.empty() && (int)E->live.size() < E->max_live) {
-        size_t off;
-        if (!E->pool.alloc(E->queue.front()->lay.total, off)) break;
-        std::unique_ptr<Query> q = std::move(E->queue.front());
-        E->queue.pop_front();
-        int rc = admit(E, q, off);
-        if (rc) {
-            E->pool.release(off, q ? q->lay.total : 0);
-            return rc;
-        }
-    }
+// One micro-step of every live query: plan each query's next operation, upload the
+// round's tables in one copy, run the singular launches (loss seeds, final
+// reductions), then one element launch and one particle launch over the forward and
+// the adjoint tiles of every query together; finally advance the queries and finish
+// the completed ones.
+int micro_round(gsim_engine* E) {
     const int n = (int)E->live.size();
-    if (n_live) *n_live = n;
-    if (n_queued) *n_queued = (int)E->queue.size();
-    if (n == 0) return GSIM_OK;
     E->ticks++;
     E->live_sum += n;
-
-    // 2. plan this tick: one micro-step per live query
     std::vector<int> ops(n);
     std::vector<StepDev<float>> sd(n);
     for (int i = 0; i < n; ++i) ops[i] = next_op(E->live[i], sd[i]);
-    std::vector<Tile> nat[4];  // elem fwd, part fwd, elem adj, part adj
+    // segment tables: each query with a forward or adjoint micro-step contributes its
+    // resident element tiles and particle tiles; the device expands them into the
+    // round's XCD-ordered lists
+    std::vector<TileSeg> seg[2];  // element pass, particle pass
+    int total[2] = {0, 0};
     for (int i = 0; i < n; ++i) {
-        const gsim_model* m = E->live[i].model;
         if (ops[i] != OP_FWD && ops[i] != OP_ADJ) continue;
-        const int k = ops[i] == OP_FWD ? 0 : 2;
-        for (Tile t : m->etiles_nat) {
-            t.model = i;
-            nat[k].push_back(t);
-        }
-        for (Tile t : m->ptiles_nat) {
-            t.model = i;
-            nat[k + 1].push_back(t);
+        const Live& L = E->live[i];
+        const Tile* t = reinterpret_cast<const Tile*>(L.base + L.q->lay.tiles);
+        const int32_t flags = ops[i] == OP_ADJ ? TILE_ADJ : 0;
+        const int cnt[2] = {L.q->n_etiles, L.q->n_ptiles};
+        for (int k = 0; k < 2; ++k) {
+            if (cnt[k] == 0) continue;
+            seg[k].push_back({k == 0 ? t : t + L.q->n_etiles, total[k], cnt[k], i, flags});
+            total[k] += cnt[k];
         }
     }
-    std::vector<Tile> ord[4];
-    int grid[4] = {0, 0, 0, 0};
-    const int dummy_row = E->live[0].model->n_ptile_rows;  // empty tiles reduce into model 0's spare row
-    for (int k = 0; k < 4; ++k) xcd_order(nat[k], (k & 1) ? TILE_PART : TILE_TET, dummy_row, ord[k], grid[k]);
-    // 3. one blob: [ModelDev x n][StepDev x n][tiles x 4 lists]
+    int grid[2];
+    for (int k = 0; k < 2; ++k)
+        grid[k] = total[k] < N_XCD ? total[k] : (total[k] + N_XCD - 1) / N_XCD * N_XCD;
+    if (grid[0] > E->max_tiles || grid[1] > E->max_tiles)
+        return fail(GSIM_E_WORKSPACE, "a round needs %d / %d tiles, the engine holds %lld", grid[0], grid[1],
+                    (long long)E->max_tiles);
+    // one upload: [ModelDev x n][StepDev x n][element segments][particle segments]; the
+    // round's expanded tile lists sit at fixed offsets of the same slot
     const size_t md_sz = sizeof(ModelDev<float>), sd_sz = sizeof(StepDev<float>);
-    size_t o_md = 0, o_sd = aup(md_sz * n), o_t[4];
-    size_t o = aup(o_sd + sd_sz * n);
-    for (int k = 0; k < 4; ++k) {
-        o_t[k] = o;
-        o = aup(o + sizeof(Tile) * ord[k].size());
-    }
-    if (o > E->blob_bytes) return fail(GSIM_E_WORKSPACE, "tick tables exceed the engine's table capacity");
+    const size_t o_md = 0, o_sd = aup(md_sz * n), o_s0 = aup(o_sd + sd_sz * n);
+    const size_t o_s1 = aup(o_s0 + sizeof(TileSeg) * seg[0].size());
+    const size_t o = aup(o_s1 + sizeof(TileSeg) * seg[1].size());
+    if (o > E->head_bytes) return fail(GSIM_E_WORKSPACE, "round tables exceed the engine's table capacity");
     const int r = E->ring;
     E->ring = (E->ring + 1) % RING;
     HIP_TRY(hipEventSynchronize(E->blob_evt[r]), "wait for table ring");
     char* h = E->blob_host[r];
     for (int i = 0; i < n; ++i) std::memcpy(h + o_md + i * md_sz, E->live[i].model->md_host.data(), md_sz);
     std::memcpy(h + o_sd, sd.data(), sd_sz * n);
-    for (int k = 0; k < 4; ++k) std::memcpy(h + o_t[k], ord[k].data(), sizeof(Tile) * ord[k].size());
+    std::memcpy(h + o_s0, seg[0].data(), sizeof(TileSeg) * seg[0].size());
+    std::memcpy(h + o_s1, seg[1].data(), sizeof(TileSeg) * seg[1].size());
     char* d = E->blob_dev[r];
     HIP_TRY(hipMemcpyAsync(d, h, o, hipMemcpyHostToDevice, E->stream), "upload tick tables");
     const ModelDev<float>* dmd = reinterpret_cast<const ModelDev<float>*>(d + o_md);
     const StepDev<float>* dsd = reinterpret_cast<const StepDev<float>*>(d + o_sd);
-    // 4. per-query singular launches (loss seed, contact reduction)
+    Tile* elist = reinterpret_cast<Tile*>(d + E->head_bytes);
+    Tile* plist = elist + E->max_tiles;
+    const int dummy_row = E->live[0].model->n_ptile_rows;  // empty tiles reduce into model 0's spare row
+    LAUNCH_TRY(launch_expand_tiles<float>(reinterpret_cast<const TileSeg*>(d + o_s0), (int)seg[0].size(), total[0],
+                                          grid[0], elist, reinterpret_cast<const TileSeg*>(d + o_s1),
+                                          (int)seg[1].size(), total[1], grid[1], plist, dummy_row, E->stream),
+               "round tile lists");
+    // per-query singular launches (loss seed, contact reduction)
     for (int i = 0; i < n; ++i) {
         gsim_model* m = E->live[i].model;
         const ModelDev<float>* own = reinterpret_cast<const ModelDev<float>*>(m->ws + m->L.model);
@@ -434,22 +453,19 @@ int tick(gsim_engine* E, int* n_live, int* n_queued) {
             LAUNCH_TRY(launch_loss<float>(own, dsd + i, own_pt, m->n_ptiles, m->pblock, m->pitems, 1, E->stream), "loss");
         if (ops[i] == OP_FIN) LAUNCH_TRY(launch_contact_reduce<float>(own, dsd + i, 1, E->stream), "contact reduce");
     }
-    // 5. batched passes over all queries' tiles (element-pass LDS: the largest tile
-    // among the queries in that pass)
+    // the element launch and the particle launch over every query's tiles (element LDS:
+    // the largest tile among the queries in this round, forward or adjoint)
     const int block = 256;
-    size_t lds_f = 0, lds_a = 0;
+    size_t lds = 0;
     for (int i = 0; i < n; ++i) {
         const gsim_model* m = E->live[i].model;
-        if (ops[i] == OP_FWD) lds_f = std::max(lds_f, (size_t)m->etile_words[0] * sizeof(float));
-        if (ops[i] == OP_ADJ) lds_a = std::max(lds_a, (size_t)m->etile_words[1] * sizeof(float));
+        if (ops[i] == OP_FWD) lds = std::max(lds, (size_t)m->etile_words[0] * sizeof(float));
+        if (ops[i] == OP_ADJ) lds = std::max(lds, (size_t)m->etile_words[1] * sizeof(float));
     }
-    auto T_ = [&](int k) { return reinterpret_cast<const Tile*>(d + o_t[k]); };
-    LAUNCH_TRY(launch_elem_fwd<float>(dmd, dsd, T_(0), grid[0], block, lds_f, false, E->stream), "element pass");
-    LAUNCH_TRY(launch_part_fwd<float>(dmd, dsd, T_(1), grid[1], block, 1, E->stream), "particle pass");
-    LAUNCH_TRY(launch_elem_adj<float>(dmd, dsd, T_(2), grid[2], block, lds_a, false, E->stream), "element adjoint");
-    LAUNCH_TRY(launch_part_adj<float>(dmd, dsd, T_(3), grid[3], block, 1, false, E->stream), "particle adjoint");
+    LAUNCH_TRY(launch_mixed<float>(dmd, dsd, elist, grid[0], plist, grid[1], block, lds, E->stream),
+               "element and particle passes");
     HIP_TRY(hipEventRecord(E->blob_evt[r], E->stream), "record tick");
-    // 6. advance; finish completed queries
+    // advance; finish completed queries
     std::vector<Live> keep;
     keep.reserve(n);
     for (int i = 0; i < n; ++i) {
@@ -463,6 +479,27 @@ int tick(gsim_engine* E, int* n_live, int* n_queued) {
         keep.push_back(std::move(L));
     }
     E->live.swap(keep);
+    return GSIM_OK;
+}
+
+int tick(gsim_engine* E, int* n_live, int* n_queued) {
+    // 1. admission, FIFO while the head fits
+    while (!E->queue.empty() && (int)E->live.size() < E->max_live) {
+        size_t off;
+        if (!E->pool.alloc(E->queue.front()->lay.total, off)) break;
+        std::unique_ptr<Query> q = std::move(E->queue.front());
+        E->queue.pop_front();
+        int rc = admit(E, q, off);
+        if (rc) {
+            E->pool.release(off, q ? q->lay.total : 0);
+            return rc;
+        }
+    }
+    // 2. micro-step rounds
+    for (int k = 0; k < E->micro_per_tick && !E->live.empty(); ++k)
+        if (int rc = micro_round(E)) return rc;
+    if (n_live) *n_live = (int)E->live.size();
+    if (n_queued) *n_queued = (int)E->queue.size();
     return GSIM_OK;
 }
 
@@ -480,15 +517,17 @@ int gsim_engine_create(void* d_pool, size_t pool_bytes, int max_live, int64_t ma
     E->max_live = max_live;
     E->max_tiles = max_tiles;
     E->stream = (hipStream_t)stream;
-    E->blob_bytes = aup((sizeof(ModelDev<float>) + sizeof(StepDev<float>)) * max_live + 4096) +
-                    aup(sizeof(Tile) * (size_t)max_tiles + 4 * 8 * sizeof(Tile)) + 5 * 256;
+    // a ring slot: the round's uploaded head (models, steps, segment tables), then the two
+    // tile lists the device expands
+    E->head_bytes = aup((sizeof(ModelDev<float>) + sizeof(StepDev<float>) + 2 * sizeof(TileSeg)) * max_live + 4 * 256);
+    E->blob_bytes = E->head_bytes + aup(2 * sizeof(Tile) * (size_t)max_tiles);
     if ((size_t)RING * E->blob_bytes >= pool_bytes) {
         delete E;
         return fail(GSIM_E_WORKSPACE, "pool too small for the engine's tables");
     }
     for (int r = 0; r < RING; ++r) {
         E->blob_dev[r] = E->pool_base + r * E->blob_bytes;
-        hipError_t e = hipHostMalloc((void**)&E->blob_host[r], E->blob_bytes, hipHostMallocDefault);
+        hipError_t e = hipHostMalloc((void**)&E->blob_host[r], E->head_bytes, hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&E->blob_evt[r], hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(E->blob_evt[r], E->stream);
         if (e != hipSuccess) {
@@ -626,6 +665,13 @@ int gsim_engine_poll(gsim_engine* E, gsim_result* out, int max, int* n) {
         ++k;
     }
     *n = k;
+    return GSIM_OK;
+}
+
+int gsim_engine_set_micro_steps(gsim_engine* E, int rounds) {
+    if (!E) return fail(GSIM_E_INVALID, "NULL engine");
+    if (rounds < 1 || rounds > 256) return fail(GSIM_E_INVALID, "micro-step rounds per tick must be in [1, 256]");
+    E->micro_per_tick = rounds;
     return GSIM_OK;
 }
 

@@ -27,6 +27,9 @@
 namespace gsim {
 
 enum TileKind : int32_t { TILE_TET = 0, TILE_TRI = 1, TILE_HINGE = 2, TILE_PART = 3 };
+// Serving's combined launches: the kind of an adjoint tile carries this bit.
+const int32_t TILE_ADJ = 0x100;
+
 
 // One workgroup's share of a pass: `count` consecutive items of one kind of one body.
 struct Tile {
@@ -38,6 +41,14 @@ struct Tile {
     int32_t id;     // particle tiles: row of the contact-gradient partial buffer;
                     // element tiles: first tile particle
     int32_t pad;    // element tiles: number of tile particles
+};
+
+// Serving: one query's share of a round's pass: its `count` tiles (resident on the
+// device since admission) become the round's tiles [begin, begin + count), with the
+// launch's model index `model` and `flags` (TILE_ADJ or 0) OR-ed into their kind.
+struct TileSeg {
+    const Tile* tiles;
+    int32_t begin, count, model, flags;
 };
 
 template <typename T>
@@ -176,6 +187,19 @@ int launch_part_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* til
                     bool air, void* stream);
 template <typename T>
 int launch_fill(T* p, int64_t n, T value, void* stream);
+// Serving: expands a round's segment tables into its element and particle tile lists,
+// each in the XCD order of xcd_order (tile t of the concatenation at (t % G) * N_XCD +
+// t / G, G = grid / N_XCD; grid = the total rounded up to N_XCD, the rest empty tiles of
+// `empty_kind` reducing into row dummy_id of model 0).  Lists of fewer than N_XCD tiles
+// keep their order.
+template <typename T>
+int launch_expand_tiles(const TileSeg* eseg, int n_eseg, int e_total, int e_grid, Tile* elist, const TileSeg* pseg,
+                        int n_pseg, int p_total, int p_grid, Tile* plist, int dummy_id, void* stream);
+// Serving: one launch over forward and adjoint element tiles (adjoint ones marked
+// TILE_ADJ), then one over forward and adjoint particle tiles; `lds` covers both kinds.
+template <typename T>
+int launch_mixed(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* etiles, int n_etiles, const Tile* ptiles,
+                 int n_ptiles, int block, size_t lds, void* stream);
 template <typename T>
 int launch_contact_reduce(const ModelDev<T>* md, const StepDev<T>* sd, int n_bodies, void* stream);
 template <typename T>

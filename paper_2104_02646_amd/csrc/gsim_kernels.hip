@@ -24,6 +24,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "gsim_device.h"
@@ -558,10 +559,8 @@ __device__ __forceinline__ gi4 ld_tp(const int32_t* tp, int64_t i) {
 // AIR: the variant launched for models with a lift/drag body (the other compiles
 // without any of that code).
 template <typename T, bool AIR>
-__global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
-                                                   const Tile* __restrict__ tiles) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const Tile tl = tiles[blockIdx.x];
+__device__ __forceinline__ void elem_fwd_tile(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd, const Tile tl,
+                                              unsigned char* smem) {
     const ModelDev<T>& M = md[tl.model];
     const StepDev<T>& S = sd[tl.model];
     const int64_t np = M.np;
@@ -644,10 +643,15 @@ __global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict_
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(512) k_part_fwd(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
+template <typename T, bool AIR>
+__global__ void __launch_bounds__(512) k_elem_fwd(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
                                                    const Tile* __restrict__ tiles) {
-    const Tile tl = tiles[blockIdx.x];
+    extern __shared__ __align__(16) unsigned char smem[];
+    elem_fwd_tile<T, AIR>(md, sd, tiles[blockIdx.x], smem);
+}
+
+template <typename T>
+__device__ __forceinline__ void part_fwd_tile(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd, const Tile tl) {
     const ModelDev<T>& M = md[tl.model];
     const StepDev<T>& S = sd[tl.model];
     const BodyDev<T>& B = M.bodies[tl.body];
@@ -689,6 +693,12 @@ __global__ void __launch_bounds__(512) k_part_fwd(const ModelDev<T>* __restrict_
     }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(512) k_part_fwd(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
+                                                   const Tile* __restrict__ tiles) {
+    part_fwd_tile<T>(md, sd, tiles[blockIdx.x]);
+}
+
 // Adjoint force of a particle: fbar = dt w (vbar+ + dt xbar+), with one explicit
 // fused multiply-add per component so that every kernel forming it from the same
 // adjoint state gets the same bits.
@@ -716,10 +726,8 @@ __device__ __forceinline__ V3<T> corner_fbar(const ModelDev<T>& M, const StepDev
 // body's other tiles write zero there, so every partial the particle pass reads
 // is written.
 template <typename T, bool AIR>
-__global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
-                                                   const Tile* __restrict__ tiles) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const Tile tl = tiles[blockIdx.x];
+__device__ __forceinline__ void elem_adj_tile(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd, const Tile tl,
+                                              unsigned char* smem) {
     const ModelDev<T>& M = md[tl.model];
     const StepDev<T>& S = sd[tl.model];
     const int64_t np = M.np;
@@ -844,9 +852,14 @@ __global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict_
 }
 
 template <typename T, bool AIR>
-__global__ void __launch_bounds__(512) k_part_adj(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
+__global__ void __launch_bounds__(512) k_elem_adj(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
                                                    const Tile* __restrict__ tiles) {
-    const Tile tl = tiles[blockIdx.x];
+    extern __shared__ __align__(16) unsigned char smem[];
+    elem_adj_tile<T, AIR>(md, sd, tiles[blockIdx.x], smem);
+}
+
+template <typename T, bool AIR>
+__device__ __forceinline__ void part_adj_tile(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd, const Tile tl) {
     const ModelDev<T>& M = md[tl.model];
     const StepDev<T>& S = sd[tl.model];
     const BodyDev<T>& B = M.bodies[tl.body];
@@ -907,6 +920,79 @@ __global__ void __launch_bounds__(512) k_part_adj(const ModelDev<T>* __restrict_
 #pragma unroll
             for (int k = 0; k < 4; ++k) M.cpart[4 * tl.id + k] += tot[k];
     }
+}
+
+template <typename T, bool AIR>
+__global__ void __launch_bounds__(512) k_part_adj(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd,
+                                                   const Tile* __restrict__ tiles) {
+    part_adj_tile<T, AIR>(md, sd, tiles[blockIdx.x]);
+}
+
+// Serving: the forward and the adjoint tiles of one micro-step run in one launch per
+// pass (TILE_ADJ marks an adjoint tile; a tile never mixes queries and the forward and
+// adjoint tiles of a launch belong to different queries), so the two kinds of work
+// overlap instead of following each other.  The branch is uniform per workgroup.
+template <typename T>
+__global__ void __launch_bounds__(512) k_elem_mixed(const ModelDev<T>* __restrict__ md,
+                                                     const StepDev<T>* __restrict__ sd, const Tile* __restrict__ tiles) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    Tile tl = tiles[blockIdx.x];
+    if (tl.kind & TILE_ADJ) {
+        tl.kind &= ~TILE_ADJ;
+        elem_adj_tile<T, false>(md, sd, tl, smem);
+    } else {
+        elem_fwd_tile<T, false>(md, sd, tl, smem);
+    }
+}
+template <typename T>
+__global__ void __launch_bounds__(512) k_part_mixed(const ModelDev<T>* __restrict__ md,
+                                                     const StepDev<T>* __restrict__ sd, const Tile* __restrict__ tiles) {
+    Tile tl = tiles[blockIdx.x];
+    if (tl.kind & TILE_ADJ) {
+        tl.kind &= ~TILE_ADJ;
+        part_adj_tile<T, false>(md, sd, tl);
+    } else {
+        part_fwd_tile<T>(md, sd, tl);
+    }
+}
+
+// Serving: builds a round's tile lists from the queries' resident tiles (one thread per
+// output position; blockIdx.y selects the element or the particle list).  A position
+// of the XCD order maps back to tile t = (pos % N_XCD) * G + pos / N_XCD of the
+// concatenation; t finds its segment by binary search over the segments' begins.
+__global__ void k_expand_tiles(const TileSeg* __restrict__ eseg, int n_eseg, int e_total, int e_grid,
+                               Tile* __restrict__ elist, const TileSeg* __restrict__ pseg, int n_pseg, int p_total,
+                               int p_grid, Tile* __restrict__ plist, int dummy_id) {
+    const bool part = blockIdx.y == 1;
+    const TileSeg* seg = part ? pseg : eseg;
+    const int nseg = part ? n_pseg : n_eseg, total = part ? p_total : e_total, grid = part ? p_grid : e_grid;
+    Tile* out = part ? plist : elist;
+    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= grid) return;
+    const int nx = 8;  // N_XCD
+    const int t = total < nx ? pos : (pos % nx) * (grid / nx) + pos / nx;
+    Tile tl;
+    if (t < total) {
+        int lo = 0, hi = nseg - 1;  // the last segment with begin <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (seg[mid].begin <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const TileSeg g = seg[lo];
+        tl = g.tiles[t - g.begin];
+        tl.model = g.model;
+        tl.kind |= g.flags;
+    } else {
+        tl.model = 0;
+        tl.body = 0;
+        tl.kind = part ? TILE_PART : TILE_TET;
+        tl.count = 0;
+        tl.begin = 0;
+        tl.id = dummy_id;
+        tl.pad = 0;
+    }
+    out[pos] = tl;
 }
 
 template <typename T>
@@ -1560,6 +1646,28 @@ int launch_part_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* til
     return check_launch();
 }
 template <typename T>
+int launch_expand_tiles(const TileSeg* eseg, int n_eseg, int e_total, int e_grid, Tile* elist, const TileSeg* pseg,
+                        int n_pseg, int p_total, int p_grid, Tile* plist, int dummy_id, void* stream) {
+    const int g = std::max(e_grid, p_grid);
+    if (g <= 0) return 0;
+    hipLaunchKernelGGL(k_expand_tiles, dim3((g + 255) / 256, 2), dim3(256), 0, (hipStream_t)stream, eseg, n_eseg,
+                       e_total, e_grid, elist, pseg, n_pseg, p_total, p_grid, plist, dummy_id);
+    return check_launch();
+}
+template <typename T>
+int launch_mixed(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* etiles, int n_etiles, const Tile* ptiles,
+                 int n_ptiles, int block, size_t lds, void* stream) {
+    static size_t allowed = 48 * 1024;
+    if (n_etiles > 0) {
+        allow_lds(reinterpret_cast<const void*>(&k_elem_mixed<T>), lds, allowed);
+        hipLaunchKernelGGL(k_elem_mixed<T>, dim3(n_etiles), dim3(block), lds, (hipStream_t)stream, md, sd, etiles);
+        if (int rc = check_launch()) return rc;
+    }
+    if (n_ptiles > 0)
+        hipLaunchKernelGGL(k_part_mixed<T>, dim3(n_ptiles), dim3(block), 0, (hipStream_t)stream, md, sd, ptiles);
+    return check_launch();
+}
+template <typename T>
 int launch_fill(T* p, int64_t n, T value, void* stream) {
     if (n <= 0) return 0;
     int64_t blocks = (n + 255) / 256;
@@ -1643,6 +1751,10 @@ int launch_fused_grads(const ModelDev<T>* md, const StepDev<T>* sd, void* stream
     template int launch_elem_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, size_t, bool, void*); \
     template int launch_part_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, bool, void*); \
     template int launch_fill<T>(T*, int64_t, T, void*);                                                             \
+    template int launch_expand_tiles<T>(const TileSeg*, int, int, int, Tile*, const TileSeg*, int, int, int, Tile*,  \
+                                        int, void*);                                                                \
+    template int launch_mixed<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, const Tile*, int, int,       \
+                                 size_t, void*);                                                                    \
     template int launch_contact_reduce<T>(const ModelDev<T>*, const StepDev<T>*, int, void*);                       \
     template int launch_loss<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, int, void*);     \
     template int launch_fused_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const int32_t*, int, size_t, void*);     \

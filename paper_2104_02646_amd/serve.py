@@ -46,6 +46,7 @@ def _load():
         lib.gsim_engine_submit.argtypes = [vp, C.POINTER(_Query), C.POINTER(C.c_int64)]
         lib.gsim_engine_tick.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         lib.gsim_engine_poll.argtypes = [vp, C.POINTER(_Result), C.c_int, C.POINTER(C.c_int)]
+        lib.gsim_engine_set_micro_steps.argtypes = [vp, C.c_int]
         lib.gsim_engine_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                           C.POINTER(C.c_double), C.POINTER(C.c_size_t)]
         _ready = True
@@ -103,7 +104,8 @@ class QueryBuffers:
 class Engine:
     """``gsim_engine_*`` over a torch-allocated device pool."""
 
-    def __init__(self, pool_bytes=4 << 30, max_live=64, max_tiles=1 << 17, device="cuda", stream=None):
+    def __init__(self, pool_bytes=4 << 30, max_live=64, max_tiles=1 << 17, device="cuda", stream=None,
+                 micro_steps=1):
         lib = _load()
         self.device = torch.device(device)
         self.pool = torch.empty(pool_bytes + 256, dtype=torch.uint8, device=self.device)
@@ -114,6 +116,8 @@ class Engine:
                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self._h = h
         self.pending = {}
+        if micro_steps != 1:
+            self.set_micro_steps(micro_steps)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -126,6 +130,10 @@ class Engine:
         _check(_load().gsim_engine_submit(self._h, C.byref(qb.q), C.byref(i)))
         self.pending[i.value] = qb
         return i.value
+
+    def set_micro_steps(self, rounds):
+        """Micro-step rounds per tick (gsim_engine_set_micro_steps)."""
+        _check(_load().gsim_engine_set_micro_steps(self._h, int(rounds)))
 
     def tick(self):
         nl, nq = C.c_int(), C.c_int()
@@ -235,10 +243,11 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=40)
     ap.add_argument("--ckpt-every", type=int, default=10)
     ap.add_argument("--saturate", action="store_true")
+    ap.add_argument("--micro-steps", type=int, default=4, help="micro-step rounds per engine tick")
     args = ap.parse_args(argv)
     trace = W.serving_trace(args.seed, args.queries + args.warmup)
     bodies = [W.query_body(q) for q in trace]
-    eng = Engine(pool_bytes=8 << 30, max_live=256, max_tiles=1 << 18)
+    eng = Engine(pool_bytes=8 << 30, max_live=256, max_tiles=1 << 18, micro_steps=args.micro_steps)
     lat, wall, _ = replay_trace(trace, bodies, eng, ckpt_every=args.ckpt_every,
                                 time_scale=0.0 if args.saturate else 1.0)
     st = eng.stats()

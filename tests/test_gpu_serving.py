@@ -36,9 +36,10 @@ def mixed_queries():
     return qs
 
 
-def test_alone_equals_in_mix_bitwise(sv):
+@pytest.mark.parametrize("rounds", [1, 3])
+def test_alone_equals_in_mix_bitwise(sv, rounds):
     qs = mixed_queries()
-    eng = sv.Engine(pool_bytes=1 << 30, max_live=16)
+    eng = sv.Engine(pool_bytes=1 << 30, max_live=16, micro_steps=rounds)
     qbs = [sv.QueryBuffers(b, T, K) for b, T, K in qs]
     # half now, the rest while the first half is in flight
     for qb in qbs[:4]:
@@ -107,3 +108,40 @@ def test_rejects_query_larger_than_pool(sv):
     with pytest.raises(gsim.GsimError) as ei:
         eng.submit(qb)
     assert ei.value.code == gsim.GSIM_E_WORKSPACE
+
+
+def test_served_answers_match_the_oracle(sv, oracle_lib):
+    """A tet query and a cloth query served together with two more queries in the mix:
+    each answer (loss, and the gradients w.r.t. its own parameters) against the FP64
+    oracle's discrete adjoint of the same rollout: loss within 1e-4, gradients within
+    1e-3 (norm-relative, R16; the largest element-wise error printed)."""
+    from helpers import maxrel, oracle_for, rel
+    T, K = 60, 10
+    tet = W.batch_body(50100, lo=1200, hi=1200).round_to(np.float32)
+    cloth = W.cloth(61, n=20, size=0.5).round_to(np.float32)
+    extra = [W.batch_body(50101, lo=3000, hi=3000).round_to(np.float32), W.cloth(62, n=12, size=0.5).round_to(np.float32)]
+    bodies = [tet, cloth] + extra
+    for i, b in enumerate(bodies):
+        b.target = W.synthetic_target(b, 80 + i).astype(np.float32).astype(np.float64)
+    eng = sv.Engine(pool_bytes=1 << 30, max_live=8)
+    qbs = [sv.QueryBuffers(b, T, K) for b in bodies]
+    for qb in qbs:
+        eng.submit(qb)
+    done = eng.run_until_idle()
+    assert len(done) == len(qbs) and eng.stats()["mean_live"] > 2
+    for qb, b in zip(qbs[:2], bodies[:2]):
+        assert qb.status == 0
+        want = ("mu", "lam", "mass") if b.ne else ("ktri", "mass")
+        L, g, xs, _ = oracle_for(oracle_lib, b).loss_and_grad(b.params(), b.x0, b.v0, T, b.target, want=want)
+        errs = {"loss": abs(qb.loss - L) / abs(L)}
+        for k in want:
+            errs[k] = rel(qb.out["k_tri" if k == "ktri" else k], g[k])
+            errs[k + " max"] = maxrel(qb.out["k_tri" if k == "ktri" else k], g[k])
+        if b.ground:
+            errs["contact"] = rel(qb.out["contact"], g["contact"])
+        print("served %s (%d elements): %s" % ("tet" if b.ne else "cloth", b.ne or b.nt,
+                                              {k: "%.2e" % v for k, v in errs.items()}))
+        assert errs["loss"] < 1e-4
+        for k, v in errs.items():
+            if k != "loss" and not k.endswith(" max"):
+                assert v < 1e-3, (k, v)
