@@ -490,46 +490,53 @@ def rigid_batch_bench(steps, n_bodies=1024, T=400):
     (one launch, every state stored), vertex loss, reverse pass (one launch) with
     mass, inertia, contact and initial-state gradients.  Each body's steps form one
     dependent chain inside one wavefront, so the launches are bound by that chain's
-    latency, not by HBM (a body-step moves 104 bytes of state)."""
+    latency, not by HBM (a body-step moves 104 bytes of state in FP32).  Run in FP64
+    (the parity-bearing line: over 400 steps of bouncing contact some of these bodies'
+    gradients are conditioned beyond FP32 state storage) and in FP32 beside it."""
     import torch
     from paper_2104_02646_amd import gsim, workloads as W
     bodies = [b.round_to(np.float32) for b in W.rigid_batch(80, n_bodies)]
-    stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        m = gsim.RigidModel(bodies, torch.float32)
-        p = m.params_from_bodies()
-        s0 = m.initial_state()
-        tgt = torch.as_tensor(np.concatenate([b.verts + b.s0[:3] + 0.2 for b in bodies]), dtype=torch.float32,
-                              device="cuda")
-        traj = m.new_trajectory(T)
-        g = m.zero_grads()
+    out = {}
+    for tdt, name in ((torch.float64, "f64"), (torch.float32, "f32")):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            m = gsim.RigidModel(bodies, tdt)
+            p = m.params_from_bodies()
+            s0 = m.initial_state()
+            tgt = torch.as_tensor(np.concatenate([b.verts + b.s0[:3] + 0.2 for b in bodies]), dtype=tdt,
+                                  device="cuda")
+            traj = m.new_trajectory(T)
+            g = m.zero_grads()
 
-        def one():
-            m.rollout(p, s0, T, traj=traj, stream=stream)
-            loss, sbar = m.loss(traj[-1], tgt, stream=stream)
-            for t in g.values():
-                t.zero_()
-            return m.rollout_backward(p, traj, T, sbar, g, stream=stream)
-        one()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
+            def one():
+                m.rollout(p, s0, T, traj=traj, stream=stream)
+                loss, sbar = m.loss(traj[-1], tgt, stream=stream)
+                for t in g.values():
+                    t.zero_()
+                return m.rollout_backward(p, traj, T, sbar, g, stream=stream)
             one()
-        torch.cuda.synchronize()
-        sec = (time.perf_counter() - t0) / steps
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        ev[0].record(stream)
-        m.rollout(p, s0, T, traj=traj, stream=stream)
-        ev[1].record(stream)
-        loss, sbar = m.loss(traj[-1], tgt, stream=stream)
-        m.rollout_backward(p, traj, T, sbar, g, stream=stream)
-        ev[2].record(stream)
-        ev[2].synchronize()
-    nv = sum(b.nv for b in bodies)
-    return {"workload": "%d rigid bodies (%d vertices in all), %d steps forward + vertex loss + reverse pass"
-                        % (n_bodies, nv, T),
-            "ms_per_step": sec * 1e3, "body_steps_per_s": n_bodies * T / sec, "vertex_steps_per_s": nv * T / sec,
-            "forward_launch_ms": ev[0].elapsed_time(ev[1]), "loss_and_adjoint_ms": ev[1].elapsed_time(ev[2])}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                one()
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t0) / steps
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record(stream)
+            m.rollout(p, s0, T, traj=traj, stream=stream)
+            ev[1].record(stream)
+            loss, sbar = m.loss(traj[-1], tgt, stream=stream)
+            m.rollout_backward(p, traj, T, sbar, g, stream=stream)
+            ev[2].record(stream)
+            ev[2].synchronize()
+        nv = sum(b.nv for b in bodies)
+        out[name] = {"ms_per_step": sec * 1e3, "body_steps_per_s": n_bodies * T / sec,
+                     "vertex_steps_per_s": nv * T / sec, "forward_launch_ms": ev[0].elapsed_time(ev[1]),
+                     "loss_and_adjoint_ms": ev[1].elapsed_time(ev[2])}
+    out["workload"] = ("%d rigid bodies (%d vertices in all), %d steps forward + vertex loss + reverse pass; "
+                       "f64 is the parity-bearing line" % (n_bodies, sum(b.nv for b in bodies), T))
+    out["f64_over_f32_time"] = out["f64"]["ms_per_step"] / out["f32"]["ms_per_step"]
+    return out
 
 
 def raster_bench(reps=20, H=256, W=256):
