@@ -15,7 +15,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gsim_oracle.cpp")
-_LIB = os.path.join(_HERE, "libgsim_oracle.so")
+# GSIM_ORACLE_LIB selects another build of the same source (the sanitizer build).
+_LIB = os.environ.get("GSIM_ORACLE_LIB") or os.path.join(_HERE, "libgsim_oracle.so")
 
 # FMA contraction off and no fast-math: every product and sum rounds once.
 CXXFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-shared", "-fPIC"]
@@ -32,6 +33,20 @@ def build(force: bool = True) -> str:
         subprocess.check_call(["g++", *CXXFLAGS, _SRC, "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+SAN_FLAGS = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized(out_dir: str) -> str:
+    """The same source under AddressSanitizer and UndefinedBehaviorSanitizer (g++,
+    aborting on the first report), written to out_dir; load it with
+    GSIM_ORACLE_LIB=<path> and g++'s libasan in LD_PRELOAD."""
+    os.makedirs(out_dir, exist_ok=True)
+    lib = os.path.join(out_dir, "libgsim_oracle.so")
+    flags = [f for f in CXXFLAGS if f != "-O2"] + SAN_FLAGS
+    subprocess.check_call(["g++", *flags, _SRC, "-o", lib])
+    return lib
 
 
 _dp = C.POINTER(C.c_double)

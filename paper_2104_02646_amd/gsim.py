@@ -19,7 +19,9 @@ import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgsim.so")
+# GSIM_LIB selects another build of the same library (the sanitizer build of the host
+# runtime, for instance); by default the in-tree libgsim.so.
+LIB_PATH = os.environ.get("GSIM_LIB") or os.path.join(HERE, "libgsim.so")
 
 GSIM_OK, GSIM_E_INVALID, GSIM_E_TOPOLOGY, GSIM_E_DEGENERATE = 0, -1, -2, -3
 GSIM_E_WORKSPACE, GSIM_E_HIP, GSIM_E_NONFINITE, GSIM_E_UNSUPPORTED = -4, -5, -6, -7
