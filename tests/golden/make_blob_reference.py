@@ -1,17 +1,21 @@
-"""Writes the FP64 oracle's 1000-step discrete-adjoint gradient of the large blob
-(App. A adjoint over App. A.2 semi-implicit Euler steps of the App. B.1 energy), so
-that the GPU test can compare its checkpointed 1000-step gradient element by element
-without running the oracle for half an hour.  Calls only oracle/ and the seeded input
-generators.
+"""Writes the FP64 oracle's discrete-adjoint gradient of the large blob's loss w.r.t.
+every element's mu (App. A adjoint over App. A.2 semi-implicit Euler steps of the App.
+B.1 energy) after 200 and after 1000 steps, so that the GPU tests compare their
+checkpointed gradients element by element without running the oracle for half an hour.
+For each horizon it also runs the oracle with its state stored the way the kernels
+store it (displacement from rest and velocity rounded to FP32 after every step) and
+records how many particle-steps take the other side of a contact or stick/slip kink
+than the FP64 run (reading R15) and how far that run's gradient lies from the FP64
+one.  Calls only oracle/ and the seeded input generators.
 
-    python tests/golden/make_blob_reference.py      (about 30 minutes on one core)
+    python tests/golden/make_blob_reference.py      (about 30 minutes, four threads)
 
-Writes tests/golden/blob_mu_1000.npy (float32 [n_tets]: d loss / d mu per element)
-and tests/golden/blob_mu_1000.json (loss, sizes and input checksums)."""
+Writes tests/golden/blob_mu_<T>.npy (float32 [n_tets]) and tests/golden/blob_mu_<T>.json."""
 import json
 import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -22,7 +26,7 @@ sys.path.insert(0, ROOT)
 import oracle.oracle as O  # noqa: E402
 from paper_2104_02646_amd import workloads as W  # noqa: E402
 
-T = 1000
+HORIZONS = (200, 1000)
 
 
 def blob():
@@ -36,20 +40,50 @@ def checksums(b):
             "target": float(b.target.sum()), "v0": float(b.v0.sum())}
 
 
+def run(b, T, stored32):
+    """(trajectory xs, vs, loss, mu gradient) of the oracle over T steps; stored32: round
+    the state after every step as the kernels store it."""
+    o = O.Oracle(b.X, tets=b.tets, pinned=b.pinned, gravity=b.gravity, ground=b.ground, plane=b.plane, dt=b.dt)
+    p = b.params()
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    xs, vs = [b.x0], [b.v0]
+    for _ in range(T):
+        x1, v1 = o.step(p, xs[-1], vs[-1])
+        if stored32:
+            x1, v1 = b.X + f32(x1 - b.X), f32(v1)
+        xs.append(x1)
+        vs.append(v1)
+    L, xb = o.loss(xs[-1], b.target, with_grad=True)
+    _, _, g = o.backward(p, np.array(xs), np.array(vs), xb, None, want=("mu",))
+    codes = [o.contact_branches(p, xs[t], vs[t]) for t in range(T)]
+    return L, g["mu"], codes, xs[-1]
+
+
 def main():
     O.build(force=False)
     b = blob()
     t0 = time.time()
-    o = O.Oracle(b.X, tets=b.tets, pinned=b.pinned, gravity=b.gravity, ground=b.ground, plane=b.plane, dt=b.dt)
-    L, g, xs, _ = o.loss_and_grad(b.params(), b.x0, b.v0, T, b.target, want=("mu",))
-    np.save(os.path.join(HERE, "blob_mu_1000.npy"), g["mu"].astype(np.float32))
-    meta = {"steps": T, "n_tets": int(b.ne), "n_particles": int(b.np), "loss": float(L),
-            "mu_grad_norm": float(np.linalg.norm(g["mu"])), "checksums": checksums(b),
-            "oracle_seconds": time.time() - t0,
-            "source": "tests/golden/make_blob_reference.py (FP64 oracle, seed 30 blob, target seed 31)"}
-    with open(os.path.join(HERE, "blob_mu_1000.json"), "w") as f:
-        json.dump(meta, f, indent=1)
-    print(meta)
+    jobs = [(T, s) for T in HORIZONS for s in (False, True)]
+    with ThreadPoolExecutor(len(jobs)) as pool:
+        res = dict(zip(jobs, pool.map(lambda j: run(b, j[0], j[1]), jobs)))
+    for T in HORIZONS:
+        L, mu, ca, xT = res[(T, False)]
+        Lq, muq, cb, xq = res[(T, True)]
+        flips = [int((a != c).sum()) for a, c in zip(ca, cb)]
+        np.save(os.path.join(HERE, "blob_mu_%d.npy" % T), mu.astype(np.float32))
+        meta = {"steps": T, "n_tets": int(b.ne), "n_particles": int(b.np), "loss": float(L),
+                "mu_grad_norm": float(np.linalg.norm(mu)), "checksums": checksums(b),
+                "fp32_stored_run": {
+                    "flipped_particle_steps": int(sum(flips)),
+                    "first_flip_step": next((t for t, f in enumerate(flips) if f), None),
+                    "mu_rel_change": float(np.linalg.norm(muq - mu) / np.linalg.norm(mu)),
+                    "x_rel_change": float(np.linalg.norm(xq - xT) / np.linalg.norm(xT)),
+                    "loss": float(Lq)},
+                "oracle_seconds": time.time() - t0,
+                "source": "tests/golden/make_blob_reference.py (FP64 oracle, seed 30 blob, target seed 31)"}
+        with open(os.path.join(HERE, "blob_mu_%d.json" % T), "w") as f:
+            json.dump(meta, f, indent=1)
+        print(meta)
 
 
 if __name__ == "__main__":
