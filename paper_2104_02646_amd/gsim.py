@@ -166,6 +166,35 @@ def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
 
 
+def _device(device):
+    d = torch.device(device)
+    if d.type == "cuda" and d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
+    return d
+
+
+def _arg(t, name, dtype, device, numel, shape=None):
+    """Device pointer of a caller tensor after checking what the library will assume of
+    it: the model's dtype and device, contiguous storage, and at least ``numel``
+    elements (exactly ``shape`` when given).  The library reads and writes through raw
+    pointers, so a tensor of another dtype or size would be read past its end."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: dtype {t.dtype}, the model computes in {dtype}")
+    if t.device != device:
+        raise ValueError(f"{name}: on {t.device}, the model is on {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.numel() < numel:
+        raise ValueError(f"{name}: {t.numel()} elements, at least {numel} needed")
+    return C.c_void_p(t.data_ptr())
+
+
 def _stream(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return C.c_void_p(s.cuda_stream)
@@ -203,8 +232,8 @@ def controller_forward(W, omega, dt, n_steps, t0=0, scale=1.0, out=None, stream=
     c, dt_code = _ctrl_args(W, omega, dt, scale)
     n = W.shape[1]
     act = torch.empty(int(n_steps), n, dtype=W.dtype, device=W.device) if out is None else out
-    if act.shape != (int(n_steps), n) or act.dtype != W.dtype or not act.is_contiguous():
-        raise ValueError("out must be a contiguous [n_steps, n] tensor of W's dtype")
+    if act.shape != (int(n_steps), n) or act.dtype != W.dtype or not act.is_contiguous() or act.device != W.device:
+        raise ValueError("out must be a contiguous [n_steps, n] tensor of W's dtype on W's device")
     _check(load().gsim_controller_forward(dt_code, C.byref(c), _ptr(W), n, int(t0), int(n_steps), _ptr(act),
                                           _stream(stream)))
     return act
@@ -214,11 +243,12 @@ def controller_backward(W, act_grad, omega, dt, t0=0, scale=1.0, W_grad=None, st
     """W_grad[n_signals, n] += d<act_grad, act>/dW (a new zeroed tensor if None)."""
     c, dt_code = _ctrl_args(W, omega, dt, scale)
     n = W.shape[1]
-    if act_grad.dim() != 2 or act_grad.shape[1] != n or act_grad.dtype != W.dtype or not act_grad.is_contiguous():
-        raise ValueError("act_grad must be a contiguous [n_steps, n] tensor of W's dtype")
+    if (act_grad.dim() != 2 or act_grad.shape[1] != n or act_grad.dtype != W.dtype or not act_grad.is_contiguous()
+            or act_grad.device != W.device):
+        raise ValueError("act_grad must be a contiguous [n_steps, n] tensor of W's dtype on W's device")
     gW = torch.zeros_like(W) if W_grad is None else W_grad
-    if gW.shape != W.shape or gW.dtype != W.dtype or not gW.is_contiguous():
-        raise ValueError("W_grad must be a contiguous tensor shaped like W")
+    if gW.shape != W.shape or gW.dtype != W.dtype or not gW.is_contiguous() or gW.device != W.device:
+        raise ValueError("W_grad must be a contiguous tensor shaped like W, on W's device")
     _check(load().gsim_controller_backward(dt_code, C.byref(c), _ptr(W), _ptr(act_grad), n, int(t0),
                                            act_grad.shape[0], _ptr(gW), _stream(stream)))
     return gW
@@ -359,7 +389,7 @@ class Model:
                  tile_elems=0):
         self.plan = Plan(bodies, dtype, tile_elems)
         self.dtype = dtype
-        self.device = torch.device(device)
+        self.device = _device(device)
         self.max_steps, self.ckpt_every = int(max_steps), int(ckpt_every)
         ws, ck, seg = self.plan.sizes(max_steps, ckpt_every)
         self.bytes = {"workspace": ws, "ckpt": ck, "segment": seg}
@@ -481,6 +511,8 @@ class Model:
         if a is None:
             return None, 0
         n = self.ne if key == "act" else self.nh
+        if not isinstance(a, torch.Tensor) or a.dtype != self.dtype or a.device != self.device:
+            raise TypeError(f"{key}: expected a {self.dtype} tensor on {self.device}")
         if a.dim() == 1:
             if a.shape[0] != n or a.stride(0) != 1:
                 raise ValueError(f"{key}: expected a contiguous [{n}] tensor")
@@ -491,41 +523,53 @@ class Model:
             raise ValueError(f"{key}: {a.shape[0]} rows for {n_steps} steps")
         return _ptr(a), a.stride(0)
 
+    def _a(self, t, name, numel, shape=None):
+        return _arg(t, name, self.dtype, self.device, numel, shape)
+
+    def _sizes(self):
+        return {"mu": self.ne, "lam": self.ne, "ktri": self.nt, "mass": self.np, "contact": 4 * self.nb,
+                "air": 2 * self.nb}
+
     def _params(self, p, n_steps=1):
         s = _Params()
-        s.mu, s.lam = _ptr(p.get("mu")), _ptr(p.get("lam"))
-        s.k_tri, s.mass, s.contact = _ptr(p.get("ktri")), _ptr(p.get("mass")), _ptr(p.get("contact"))
+        n = self._sizes()
+        a = lambda k: self._a(p.get(k), "params[%r]" % k, n[k])
+        s.mu, s.lam, s.k_tri, s.mass, s.contact = a("mu"), a("lam"), a("ktri"), a("mass"), a("contact")
         s.act, s.act_stride = self._actuation(p, "act", n_steps)
         s.hact, s.hact_stride = self._actuation(p, "hact", n_steps)
-        s.air = _ptr(p.get("air"))
+        s.air = a("air")
         return s
 
     def _grads(self, g, n_steps=1):
         s = _Grads()
         if g:
-            s.mu, s.lam, s.k_tri = _ptr(g.get("mu")), _ptr(g.get("lam")), _ptr(g.get("ktri"))
-            s.mass, s.contact = _ptr(g.get("mass")), _ptr(g.get("contact"))
+            n = self._sizes()
+            a = lambda k: self._a(g.get(k), "grads[%r]" % k, n[k])
+            s.mu, s.lam, s.k_tri, s.mass, s.contact = a("mu"), a("lam"), a("ktri"), a("mass"), a("contact")
             s.act, s.act_stride = self._actuation(g, "act", n_steps)
             s.hact, s.hact_stride = self._actuation(g, "hact", n_steps)
         return s
 
-    @staticmethod
-    def _state(x, v):
+    def _state(self, x, v, names=("x", "v")):
         s = _State()
-        s.x, s.v = _ptr(x), _ptr(v)
+        s.x = self._a(x, names[0], 3 * self.np, (3, self.np))
+        s.v = self._a(v, names[1], 3 * self.np, (3, self.np))
         return s
+
+    def _ck(self, ck):
+        return self._a(ck, "ckpt", self.ckpt.numel())
 
     # -- entry points -------------------------------------------------------------
     def step(self, params, x, v, n_steps=1, out=None, stream=None):
         xo, vo = self.empty_state() if out is None else out
-        _check(load().gsim_step(self._h, C.byref(self._params(params, n_steps)), self._state(x, v), self._state(xo, vo),
-                                int(n_steps), _stream(stream)))
+        _check(load().gsim_step(self._h, C.byref(self._params(params, n_steps)), self._state(x, v),
+                                self._state(xo, vo, ("x_out", "v_out")), int(n_steps), _stream(stream)))
         return xo, vo
 
     def step_backward(self, params, x, v, xb_plus, vb_plus, grads=None, stream=None):
         xbm, vbm = self.empty_state()
         _check(load().gsim_step_backward(self._h, C.byref(self._params(params)), self._state(x, v),
-                                         self._state(xb_plus, vb_plus), self._state(xbm, vbm),
+                                         self._state(xb_plus, vb_plus, ("xb_plus", "vb_plus")), self._state(xbm, vbm),
                                          C.byref(self._grads(grads)), _stream(stream)))
         return xbm, vbm
 
@@ -536,23 +580,24 @@ class Model:
     def rollout(self, params, x0, v0, n_steps, checkpoint=True, out=None, stream=None, ckpt=None):
         xo, vo = self.empty_state() if out is None else out
         ck = (self.ckpt if ckpt is None else ckpt) if checkpoint else None
-        _check(load().gsim_rollout(self._h, C.byref(self._params(params, n_steps)), self._state(x0, v0), int(n_steps),
-                                   _ptr(ck), self._state(xo, vo), _stream(stream)))
+        _check(load().gsim_rollout(self._h, C.byref(self._params(params, n_steps)), self._state(x0, v0, ("x0", "v0")),
+                                   int(n_steps), self._ck(ck), self._state(xo, vo, ("x_out", "v_out")), _stream(stream)))
         return xo, vo
 
     def rollout_backward(self, params, n_steps, xb_final, vb_final, grads=None, out=None, stream=None, ckpt=None):
         xbi, vbi = self.empty_state() if out is None else out
         ck = self.ckpt if ckpt is None else ckpt
-        _check(load().gsim_rollout_backward(self._h, C.byref(self._params(params, n_steps)), _ptr(ck), int(n_steps),
-                                            _ptr(self.segment), self._state(xb_final, vb_final), self._state(xbi, vbi),
+        _check(load().gsim_rollout_backward(self._h, C.byref(self._params(params, n_steps)), self._ck(ck), int(n_steps),
+                                            _ptr(self.segment), self._state(xb_final, vb_final, ("xb_final", "vb_final")),
+                                            self._state(xbi, vbi, ("xb_out", "vb_out")),
                                             C.byref(self._grads(grads, n_steps)), _stream(stream)))
         return xbi, vbi
 
     def loss_mse(self, x, target, seed=True, stream=None):
         loss = torch.empty(self.nb, dtype=self.dtype, device=self.device)
         xb, vb = self.empty_state() if seed else (None, None)
-        _check(load().gsim_loss_mse(self._h, self._state(x, None), _ptr(target), _ptr(loss), self._state(xb, vb),
-                                    _stream(stream)))
+        _check(load().gsim_loss_mse(self._h, self._state(x, None), self._a(target, "target", 3 * self.np, (3, self.np)),
+                                    _ptr(loss), self._state(xb, vb, ("xb", "vb")), _stream(stream)))
         return loss, xb, vb
 
 
@@ -569,7 +614,7 @@ class RigidModel:
     def __init__(self, bodies, dtype=torch.float32, device="cuda"):
         lib = load()
         self.bodies = list(bodies)
-        self.dtype, self.device = dtype, torch.device(device)
+        self.dtype, self.device = dtype, _device(device)
         self.nb = len(self.bodies)
         self.vert_off = np.zeros(self.nb + 1, np.int64)
         for i, b in enumerate(self.bodies):
@@ -616,11 +661,20 @@ class RigidModel:
                 "inertia": torch.zeros(self.nb, 6, dtype=self.dtype, device=self.device),
                 "contact": torch.zeros(self.nb, 4, dtype=self.dtype, device=self.device)}
 
-    @staticmethod
-    def _params(p):
+    def _a(self, t, name, numel, shape=None):
+        return _arg(t, name, self.dtype, self.device, numel, shape)
+
+    def _params(self, p):
         s = _RigidParams()
-        s.mass, s.inertia, s.contact = _ptr(p["mass"]), _ptr(p["inertia"]), _ptr(p["contact"])
+        s.mass = self._a(p["mass"], "mass", self.nb)
+        s.inertia = self._a(p["inertia"], "inertia", 6 * self.nb)
+        s.contact = self._a(p["contact"], "contact", 4 * self.nb)
         return s
+
+    def _traj(self, traj, n_steps):
+        if traj is None or traj.dim() != 3 or traj.shape[0] < int(n_steps) + 1 or tuple(traj.shape[1:]) != (self.nb, 13):
+            raise ValueError("traj must be a contiguous [n_steps + 1, n_bodies, 13] tensor")
+        return self._a(traj, "traj", (int(n_steps) + 1) * self.nb * 13)
 
     def new_trajectory(self, n_steps):
         return torch.empty(int(n_steps) + 1, self.nb, 13, dtype=self.dtype, device=self.device)
@@ -629,16 +683,18 @@ class RigidModel:
         traj = self.new_trajectory(n_steps) if traj is None else traj
         if traj.shape != (int(n_steps) + 1, self.nb, 13) or not traj.is_contiguous():
             raise ValueError("traj must be a contiguous [n_steps + 1, n_bodies, 13] tensor")
-        _check(load().gsim_rigid_rollout(self._h, C.byref(self._params(params)), _ptr(s0.contiguous()), int(n_steps),
-                                         _ptr(traj), _stream(stream)))
+        _check(load().gsim_rigid_rollout(self._h, C.byref(self._params(params)),
+                                         self._a(s0.contiguous(), "s0", 13 * self.nb, (self.nb, 13)), int(n_steps),
+                                         self._traj(traj, n_steps), _stream(stream)))
         return traj
 
     def loss(self, state, target, stream=None):
         """(loss [nb], d loss / d state [nb, 13]) for world target vertices [n_verts, 3]."""
         loss = torch.empty(self.nb, dtype=self.dtype, device=self.device)
         sbar = torch.empty(self.nb, 13, dtype=self.dtype, device=self.device)
-        _check(load().gsim_rigid_loss(self._h, _ptr(state.contiguous()), _ptr(target.contiguous()), _ptr(loss),
-                                      _ptr(sbar), _stream(stream)))
+        _check(load().gsim_rigid_loss(self._h, self._a(state.contiguous(), "state", 13 * self.nb, (self.nb, 13)),
+                                      self._a(target.contiguous(), "target", 3 * self.n_verts, (self.n_verts, 3)),
+                                      _ptr(loss), _ptr(sbar), _stream(stream)))
         return loss, sbar
 
     def rollout_backward(self, params, traj, n_steps, sbar_final, grads=None, stream=None):
@@ -646,9 +702,13 @@ class RigidModel:
         out = torch.empty(self.nb, 13, dtype=self.dtype, device=self.device)
         g = _RigidGrads()
         if grads:
-            g.mass, g.inertia, g.contact = _ptr(grads.get("mass")), _ptr(grads.get("inertia")), _ptr(grads.get("contact"))
-        _check(load().gsim_rigid_rollout_backward(self._h, C.byref(self._params(params)), _ptr(traj), int(n_steps),
-                                                  _ptr(sbar_final.contiguous()), _ptr(out), C.byref(g),
+            g.mass = self._a(grads.get("mass"), "grads['mass']", self.nb)
+            g.inertia = self._a(grads.get("inertia"), "grads['inertia']", 6 * self.nb)
+            g.contact = self._a(grads.get("contact"), "grads['contact']", 4 * self.nb)
+        _check(load().gsim_rigid_rollout_backward(self._h, C.byref(self._params(params)), self._traj(traj, n_steps),
+                                                  int(n_steps),
+                                                  self._a(sbar_final.contiguous(), "sbar_final", 13 * self.nb,
+                                                          (self.nb, 13)), _ptr(out), C.byref(g),
                                                   _stream(stream)))
         return out
 
@@ -667,7 +727,7 @@ class Renderer:
         self.tris = np.ascontiguousarray(np.asarray(tris, np.int32).reshape(-1, 3))
         self.nv, self.nt = int(n_verts), len(self.tris)
         self.H, self.W = int(height), int(width)
-        self.dtype, self.device = dtype, torch.device(device)
+        self.dtype, self.device = dtype, _device(device)
         code = GSIM_F64 if dtype == torch.float64 else GSIM_F32
         nbytes = C.c_size_t()
         _check(lib.gsim_raster_sizes(code, self.nv, self.nt, self.H, self.W, C.byref(nbytes)))
@@ -685,6 +745,9 @@ class Renderer:
             _lib.gsim_raster_destroy(h)
             self._h = None
 
+    def _x(self, x):
+        return _arg(x.contiguous(), "x", self.dtype, self.device, 3 * self.nv, (3, self.nv))
+
     @staticmethod
     def camera(P, sigma):
         c = _Camera()
@@ -695,14 +758,17 @@ class Renderer:
 
     def forward(self, x, P, sigma, stream=None):
         img = torch.empty(self.H, self.W, dtype=self.dtype, device=self.device)
-        _check(load().gsim_raster_forward(self._h, C.byref(self.camera(P, sigma)), _ptr(x.contiguous()), _ptr(img),
+        _check(load().gsim_raster_forward(self._h, C.byref(self.camera(P, sigma)), self._x(x), _ptr(img),
                                           _stream(stream)))
         return img
 
     def backward(self, x, P, sigma, image_bar, x_bar=None, stream=None):
         xb = torch.zeros(3, self.nv, dtype=self.dtype, device=self.device) if x_bar is None else x_bar
-        _check(load().gsim_raster_backward(self._h, C.byref(self.camera(P, sigma)), _ptr(x.contiguous()),
-                                           _ptr(image_bar.contiguous()), _ptr(xb), _stream(stream)))
+        _check(load().gsim_raster_backward(self._h, C.byref(self.camera(P, sigma)), self._x(x),
+                                           _arg(image_bar.contiguous(), "image_bar", self.dtype, self.device,
+                                                self.H * self.W, (self.H, self.W)),
+                                           _arg(xb, "x_bar", self.dtype, self.device, 3 * self.nv, (3, self.nv)),
+                                           _stream(stream)))
         return xb
 
 
@@ -714,8 +780,13 @@ def raster_forward_noalloc(tris, n_verts, height, width, x, P, sigma, out, strea
     library's static device array (no renderer object, no workspace, nothing
     allocated).  tris: device int32 [nt, 3]; x: device SoA [3, n_verts]; out: device
     [height, width] of x's dtype (written)."""
+    if x.dtype not in (torch.float32, torch.float64):
+        raise TypeError("x must be float32 or float64")
     code = GSIM_F64 if x.dtype == torch.float64 else GSIM_F32
-    _check(load().gsim_raster_forward_noalloc(code, int(n_verts), int(tris.shape[0]), _ptr(tris), int(height),
-                                              int(width), C.byref(Renderer.camera(P, sigma)), _ptr(x), _ptr(out),
-                                              _stream(stream)))
+    nv, H, W = int(n_verts), int(height), int(width)
+    tp = _arg(tris, "tris", torch.int32, x.device, 3 * tris.shape[0], (tris.shape[0], 3))
+    xp = _arg(x, "x", x.dtype, x.device, 3 * nv, (3, nv))
+    op = _arg(out, "out", x.dtype, x.device, H * W, (H, W))
+    _check(load().gsim_raster_forward_noalloc(code, nv, int(tris.shape[0]), tp, H, W,
+                                              C.byref(Renderer.camera(P, sigma)), xp, op, _stream(stream)))
     return out

@@ -132,3 +132,40 @@ def test_engine_fails_a_diverging_query_alone(gs):
         assert np.float32(loss) == np.float32(qbs[i].loss)
         for k in ("mu", "lam", "mass", "contact"):
             assert np.array_equal(g[k], qbs[i].out[k]), (i, k)
+
+
+def test_binding_rejects_mismatched_tensors(gs):
+    """The binding checks every caller tensor against what the library will assume (dtype,
+    device, contiguity, size) before any launch: a float32 state handed to an FP64 model
+    would otherwise be read as doubles past its end."""
+    b = W.tiny_cube(0)
+    m = gs.Model([b], torch.float64, max_steps=4, ckpt_every=2)
+    p = m.params_from_bodies()
+    x64, v64 = gs.soa(b.x0, torch.float64), gs.soa(b.v0, torch.float64)
+    with pytest.raises(TypeError):
+        m.rollout(p, gs.soa(b.x0), v64, 4)
+    with pytest.raises(ValueError):
+        m.rollout(p, x64[:, :-1].contiguous(), v64, 4)
+    with pytest.raises(ValueError):
+        m.rollout(p, x64.t().contiguous().t(), v64, 4)
+    with pytest.raises(TypeError):
+        m.rollout(dict(p, mu=p["mu"].float()), x64, v64, 4)
+    with pytest.raises(ValueError):
+        m.rollout(dict(p, mass=p["mass"][:-1]), x64, v64, 4)
+    with pytest.raises(TypeError):
+        m.loss_mse(x64, gs.soa(b.x0))
+    g = m.zero_grads(("mu",))
+    xT, vT = m.rollout(p, x64, v64, 4)
+    loss, xb, vb = m.loss_mse(xT, x64)
+    with pytest.raises(TypeError):
+        m.rollout_backward(p, 4, xb, vb, {"mu": g["mu"].float()})
+    m.rollout_backward(p, 4, xb, vb, g)  # the matching call still runs
+    torch.cuda.synchronize()
+    assert torch.isfinite(g["mu"]).all()
+    rb = [W.rigid_body(700, "box")]
+    rm = gs.RigidModel(rb, torch.float64)
+    with pytest.raises(TypeError):
+        rm.rollout(rm.params_from_bodies(), rm.initial_state().float(), 3)
+    r = gs.Renderer(np.array([[0, 1, 2]], np.int32), 3, 8, 8, torch.float32)
+    with pytest.raises(ValueError):
+        r.forward(torch.zeros(3, 2, device="cuda"), np.eye(3, 4), 1e-3)

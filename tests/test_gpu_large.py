@@ -33,11 +33,11 @@ def blob():
     return b
 
 
-def _grad(gs, b, T, K, want=("mu",)):
-    m = gs.Model([b], torch.float32, max_steps=T, ckpt_every=K)
+def _grad(gs, b, T, K, want=("mu",), dtype=torch.float32):
+    m = gs.Model([b], dtype, max_steps=T, ckpt_every=K)
     p = m.params_from_bodies()
-    xT, vT = m.rollout(p, gs.soa(b.x0), gs.soa(b.v0), T)
-    loss, xb, vb = m.loss_mse(xT, gs.soa(b.target))
+    xT, vT = m.rollout(p, gs.soa(b.x0, dtype), gs.soa(b.v0, dtype), T)
+    loss, xb, vb = m.loss_mse(xT, gs.soa(b.target, dtype))
     g = m.zero_grads(want)
     m.rollout_backward(p, T, xb, vb, g)
     torch.cuda.synchronize()
@@ -158,6 +158,21 @@ def test_blob_1000_steps_checkpointed(gs, blob):
                                       fl["mu_rel_change"]))
     assert abs(L50 - meta["loss"]) < 1e-4 * abs(meta["loss"])
     assert np.isfinite(g50["mu"]).all() and np.abs(g50["mu"]).max() > 0
+
+
+def test_blob_1000_steps_fp64(gs, blob):
+    """The same 1000-step checkpointed gradient with the kernels in FP64, every element's
+    mu gradient against the FP64 oracle's at the plain 1e-3 bar (the stored reference is
+    rounded to FP32, so agreement bottoms out near 1e-7)."""
+    b = blob
+    T = 1000
+    meta, ref = _stored_reference(b, T)
+    _, L, g = _grad(gs, b, T, 50, dtype=torch.float64)
+    e, em = rel(g["mu"], ref), maxrel(g["mu"], ref)
+    print("blob 1000-step mu gradient, FP64 kernels: rel err %.2e (max element %.2e); loss %.10e vs %.10e"
+          % (e, em, L, meta["loss"]))
+    assert abs(L - meta["loss"]) < 1e-10 * abs(meta["loss"])
+    assert e < 1e-3 and em < 1e-3
 
 
 def proxy_body():

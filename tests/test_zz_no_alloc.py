@@ -58,10 +58,12 @@ def test_noalloc_limits_and_bad_indices():
     out = torch.zeros(40, 48, device="cuda")
     tris = torch.as_tensor(np.ascontiguousarray(b.tris, np.int32), device="cuda")
     # an image whose transmittance alone exceeds the scratch: refused, nothing launched
-    big = torch.zeros(1, device="cuda")
+    big = torch.zeros(4096, 4096, device="cuda")
     with pytest.raises(gsim.GsimError) as e:
         gsim.raster_forward_noalloc(tris, b.np, 4096, 4096, x, P, 1.5, big)
     assert e.value.code == gsim.GSIM_E_WORKSPACE
+    with pytest.raises(ValueError):  # an output smaller than the image: refused by the binding
+        gsim.raster_forward_noalloc(tris, b.np, 4096, 4096, x, P, 1.5, out)
     # the last triangle with a corner index just past the vertices (it stays inside the
     # scratch even if it were read): the image equals the mesh without that triangle
     bad = b.tris.copy()
