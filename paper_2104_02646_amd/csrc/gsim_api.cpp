@@ -127,6 +127,7 @@ void colour_elements(gsim_plan* P) {
     P->cbase.assign(3 * nb, 0);
     P->ncol.assign(3 * nb, 0);
     P->fused_ok = true;
+    P->coloured = true;
     std::vector<uint64_t> used_lo, used_hi;
     for (int b = 0; b < nb; ++b) {
         const int64_t p0 = P->poff[b], npb = P->poff[b + 1] - p0;
@@ -228,7 +229,22 @@ int build_tiles(gsim_plan* P) {
                     }
                     ++e;
                 }
-                std::sort(parts.begin(), parts.end());
+                // increasing index order: a scan of the marks over the tile's index range
+                // when that range is narrow (tiles are spatially local), else a sort
+                {
+                    int32_t lo = INT32_MAX, hi = -1;
+                    for (int32_t p : parts) {
+                        lo = std::min(lo, p);
+                        hi = std::max(hi, p);
+                    }
+                    if (!parts.empty() && (int64_t)hi - lo < 8 * (int64_t)parts.size()) {
+                        size_t k = 0;
+                        for (int32_t p = lo; p <= hi; ++p)
+                            if (mark[p] == tile) parts[k++] = p;
+                    } else {
+                        std::sort(parts.begin(), parts.end());
+                    }
+                }
                 const int m = (int)parts.size();
                 for (int j = 0; j < m; ++j) loc[parts[j]] = j;
                 cnt.assign(m, 0);
@@ -296,7 +312,7 @@ bool distinct(const int32_t* id, int n) {
     return true;
 }
 
-int build_plan(const gsim_model_desc* d, gsim_plan* P) {
+int build_plan(const gsim_model_desc* d, gsim_plan* P, bool fused) {
     if (!d) return fail(GSIM_E_INVALID, "NULL description");
     if (d->dtype != GSIM_F32 && d->dtype != GSIM_F64) return fail(GSIM_E_INVALID, "dtype must be 32 or 64");
     if (d->n_bodies < 1) return fail(GSIM_E_INVALID, "n_bodies must be >= 1");
@@ -461,7 +477,13 @@ int build_plan(const gsim_model_desc* d, gsim_plan* P) {
         }
 
     if (int rc = build_tiles(P)) return rc;
-    colour_elements(P);
+    if (fused) {
+        colour_elements(P);
+    } else {
+        P->fused_ok = P->coloured = false;
+        P->cbase.assign(3 * nb, 0);
+        P->ncol.assign(3 * nb, 0);
+    }
     return GSIM_OK;
 }
 
@@ -569,7 +591,7 @@ void natural_tiles(const gsim_model* m, bool particles, int tile, std::vector<Ti
 }
 
 template <typename T>
-int upload_tiles(gsim_model* m, void* stream) {
+int upload_tiles(gsim_model* m, void* stream, UploadSink* sink = nullptr) {
     std::vector<Tile> et, pt;
     int rows_e = 0;
     natural_tiles(m, false, 0, m->etiles_nat, rows_e);
@@ -619,8 +641,12 @@ int upload_tiles(gsim_model* m, void* stream) {
     m->n_etiles = m->lane_e[m->lanes];
     m->n_ptiles = m->lane_p[m->lanes];
     hipStream_t s = (hipStream_t)stream;
-    if (!et.empty()) HIP_TRY(hipMemcpyAsync(m->ws + m->L.etiles, et.data(), et.size() * sizeof(Tile), hipMemcpyHostToDevice, s), "upload tiles");
-    if (!pt.empty()) HIP_TRY(hipMemcpyAsync(m->ws + m->L.ptiles, pt.data(), pt.size() * sizeof(Tile), hipMemcpyHostToDevice, s), "upload tiles");
+    auto up = [&](void* dst, const void* src, size_t n) -> hipError_t {
+        if (n == 0) return hipSuccess;
+        return sink ? sink->copy(dst, src, n) : hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, s);
+    };
+    HIP_TRY(up(m->ws + m->L.etiles, et.data(), et.size() * sizeof(Tile)), "upload tiles");
+    HIP_TRY(up(m->ws + m->L.ptiles, pt.data(), pt.size() * sizeof(Tile)), "upload tiles");
     // body particle-tile ranges (contact / loss partial rows) depend on the tile size
     BodyDev<T>* bodies = reinterpret_cast<BodyDev<T>*>(m->bodies_host.data());
     int row = 0;
@@ -630,8 +656,8 @@ int upload_tiles(gsim_model* m, void* stream) {
         row += (int)((m->poff[b + 1] - m->poff[b] + tile - 1) / tile);
         bodies[b].pt1 = row;
     }
-    HIP_TRY(hipMemcpyAsync(m->ws + m->L.bodies, bodies, sizeof(BodyDev<T>) * m->nb, hipMemcpyHostToDevice, s), "upload bodies");
-    HIP_TRY(hipStreamSynchronize(s), "sync");
+    HIP_TRY(up(m->ws + m->L.bodies, bodies, sizeof(BodyDev<T>) * m->nb), "upload bodies");
+    if (!sink) HIP_TRY(hipStreamSynchronize(s), "sync");
     for (auto& g : m->graphs)
         if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
     m->graphs.clear();
@@ -1241,7 +1267,8 @@ int guarded(F f) {
 namespace gsim {
 
 template <typename T>
-int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t bytes, void* stream, gsim_model** out) {
+int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t bytes, void* stream, gsim_model** out,
+               UploadSink* sink) {
     Layout L = make_layout<T>(P, max_steps);
     if (bytes < L.total) return fail(GSIM_E_WORKSPACE, "workspace has %zu bytes, needs %zu", bytes, L.total);
     if (((uintptr_t)d_ws & 255) != 0) return fail(GSIM_E_INVALID, "workspace must be 256-byte aligned");
@@ -1265,7 +1292,7 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     char* ws = m->ws;
     auto up = [&](size_t off, const void* src, size_t n) -> hipError_t {
         if (n == 0) return hipSuccess;
-        return hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, s);
+        return sink ? sink->copy(ws + off, src, n) : hipMemcpyAsync(ws + off, src, n, hipMemcpyHostToDevice, s);
     };
     auto cvt = [](const std::vector<double>& v) { return std::vector<T>(v.begin(), v.end()); };
     std::vector<T> tet_dinv = cvt(P->tet_dinv), tet_vol = cvt(P->tet_vol), tri_dinv = cvt(P->tri_dinv),
@@ -1302,42 +1329,44 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
         }
     chk(up(L.rest, rest.data(), rest.size() * sizeof(T)));
     chk(up(L.rgap, rgap.data(), rgap.size() * sizeof(T)));
-    chk(hipMemsetAsync(ws + L.bflag, 0, 2 * (size_t)P->nb * 4, s));  // (set-up, never inside a captured sequence)
-    // colour-ordered copies of the element records (fused path)
-    // corner indices become body-local (the fused kernels address the body's particles in LDS)
-    auto perm_i = [P](const std::vector<int32_t>& a, const std::vector<int32_t>& ord, int rows, int64_t n,
-                      const std::vector<int64_t>& off) {
-        std::vector<int32_t> out(a.size());
-        for (int b = 0; b < P->nb; ++b)
+    // (set-up, never inside a captured sequence)
+    chk(sink ? sink->zero(ws + L.bflag, 2 * (size_t)P->nb * 4) : hipMemsetAsync(ws + L.bflag, 0, 2 * (size_t)P->nb * 4, s));
+    if (P->coloured) {  // colour-ordered copies of the element records (fused path)
+        // corner indices become body-local (the fused kernels address the body's particles in LDS)
+        auto perm_i = [P](const std::vector<int32_t>& a, const std::vector<int32_t>& ord, int rows, int64_t n,
+                          const std::vector<int64_t>& off) {
+            std::vector<int32_t> out(a.size());
+            for (int b = 0; b < P->nb; ++b)
+                for (int r = 0; r < rows; ++r)
+                    for (int64_t e = off[b]; e < off[b + 1]; ++e)
+                        out[r * n + e] = (int32_t)(a[r * n + ord[e]] - P->poff[b]);
+            return out;
+        };
+        auto perm_t = [](const std::vector<T>& a, const std::vector<int32_t>& ord, int rows, int64_t n) {
+            std::vector<T> out(a.size());
             for (int r = 0; r < rows; ++r)
-                for (int64_t e = off[b]; e < off[b + 1]; ++e)
-                    out[r * n + e] = (int32_t)(a[r * n + ord[e]] - P->poff[b]);
-        return out;
-    };
-    auto perm_t = [](const std::vector<T>& a, const std::vector<int32_t>& ord, int rows, int64_t n) {
-        std::vector<T> out(a.size());
-        for (int r = 0; r < rows; ++r)
-            for (int64_t e = 0; e < n; ++e) out[r * n + e] = a[r * n + ord[e]];
-        return out;
-    };
-    std::vector<int32_t> f_tet_idx = perm_i(P->tet_idx, P->ftet, 4, P->ne, P->eoff),
-                         f_tri_idx = perm_i(P->tri_idx, P->ftri, 3, P->nt, P->toff),
-                         f_hin_idx = perm_i(P->hin_idx, P->fhin, 4, P->nh, P->hoff);
-    std::vector<T> f_tet_dinv = perm_t(tet_dinv, P->ftet, 9, P->ne), f_tet_vol = perm_t(tet_vol, P->ftet, 1, P->ne),
-                   f_tri_dinv = perm_t(tri_dinv, P->ftri, 4, P->nt), f_tri_area = perm_t(tri_area, P->ftri, 1, P->nt),
-                   f_hin_phi0 = perm_t(hin_phi0, P->fhin, 1, P->nh);
-    chk(up(L.f_tet_idx, f_tet_idx.data(), f_tet_idx.size() * 4));
-    chk(up(L.f_tet_dinv, f_tet_dinv.data(), f_tet_dinv.size() * sizeof(T)));
-    chk(up(L.f_tet_vol, f_tet_vol.data(), f_tet_vol.size() * sizeof(T)));
-    chk(up(L.f_tet_orig, P->ftet.data(), P->ftet.size() * 4));
-    chk(up(L.f_tri_idx, f_tri_idx.data(), f_tri_idx.size() * 4));
-    chk(up(L.f_tri_dinv, f_tri_dinv.data(), f_tri_dinv.size() * sizeof(T)));
-    chk(up(L.f_tri_area, f_tri_area.data(), f_tri_area.size() * sizeof(T)));
-    chk(up(L.f_tri_orig, P->ftri.data(), P->ftri.size() * 4));
-    chk(up(L.f_hin_idx, f_hin_idx.data(), f_hin_idx.size() * 4));
-    chk(up(L.f_hin_phi0, f_hin_phi0.data(), f_hin_phi0.size() * sizeof(T)));
-    chk(up(L.f_hin_orig, P->fhin.data(), P->fhin.size() * 4));
-    chk(up(L.coff, P->coff.data(), P->coff.size() * 4));
+                for (int64_t e = 0; e < n; ++e) out[r * n + e] = a[r * n + ord[e]];
+            return out;
+        };
+        std::vector<int32_t> f_tet_idx = perm_i(P->tet_idx, P->ftet, 4, P->ne, P->eoff),
+                             f_tri_idx = perm_i(P->tri_idx, P->ftri, 3, P->nt, P->toff),
+                             f_hin_idx = perm_i(P->hin_idx, P->fhin, 4, P->nh, P->hoff);
+        std::vector<T> f_tet_dinv = perm_t(tet_dinv, P->ftet, 9, P->ne), f_tet_vol = perm_t(tet_vol, P->ftet, 1, P->ne),
+                       f_tri_dinv = perm_t(tri_dinv, P->ftri, 4, P->nt), f_tri_area = perm_t(tri_area, P->ftri, 1, P->nt),
+                       f_hin_phi0 = perm_t(hin_phi0, P->fhin, 1, P->nh);
+        chk(up(L.f_tet_idx, f_tet_idx.data(), f_tet_idx.size() * 4));
+        chk(up(L.f_tet_dinv, f_tet_dinv.data(), f_tet_dinv.size() * sizeof(T)));
+        chk(up(L.f_tet_vol, f_tet_vol.data(), f_tet_vol.size() * sizeof(T)));
+        chk(up(L.f_tet_orig, P->ftet.data(), P->ftet.size() * 4));
+        chk(up(L.f_tri_idx, f_tri_idx.data(), f_tri_idx.size() * 4));
+        chk(up(L.f_tri_dinv, f_tri_dinv.data(), f_tri_dinv.size() * sizeof(T)));
+        chk(up(L.f_tri_area, f_tri_area.data(), f_tri_area.size() * sizeof(T)));
+        chk(up(L.f_tri_orig, P->ftri.data(), P->ftri.size() * 4));
+        chk(up(L.f_hin_idx, f_hin_idx.data(), f_hin_idx.size() * 4));
+        chk(up(L.f_hin_phi0, f_hin_phi0.data(), f_hin_phi0.size() * sizeof(T)));
+        chk(up(L.f_hin_orig, P->fhin.data(), P->fhin.size() * 4));
+        chk(up(L.coff, P->coff.data(), P->coff.size() * 4));
+    }
     // fused launch order: largest bodies first (they bound the makespan)
     std::vector<int32_t> border(P->nb);
     for (int b = 0; b < P->nb; ++b) border[b] = b;
@@ -1450,7 +1479,7 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
         delete m;
         return hip_fail(e, "upload model");
     }
-    int rc = upload_tiles<T>(m, stream);
+    int rc = upload_tiles<T>(m, stream, sink);
     if (rc) {
         gsim_model_destroy(m);
         return rc;
@@ -1459,8 +1488,8 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     return GSIM_OK;
 }
 
-template int model_init<float>(const gsim_plan*, int, int, void*, size_t, void*, gsim_model**);
-template int model_init<double>(const gsim_plan*, int, int, void*, size_t, void*, gsim_model**);
+template int model_init<float>(const gsim_plan*, int, int, void*, size_t, void*, gsim_model**, UploadSink*);
+template int model_init<double>(const gsim_plan*, int, int, void*, size_t, void*, gsim_model**, UploadSink*);
 
 }  // namespace gsim
 
@@ -1475,12 +1504,16 @@ int gsim_version(int* major, int* minor) {
     return GSIM_OK;
 }
 
-int gsim_plan_create(const gsim_model_desc* desc, gsim_plan** out) {
+int gsim_plan_create(const gsim_model_desc* desc, gsim_plan** out) { return plan_create(desc, out, true); }
+
+}  // extern "C"
+
+int gsim::plan_create(const gsim_model_desc* desc, gsim_plan** out, bool fused) {
     if (!out) return fail(GSIM_E_INVALID, "NULL output");
     *out = nullptr;
     return guarded<double>([&]() {
         gsim_plan* P = new gsim_plan();
-        int rc = build_plan(desc, P);
+        int rc = build_plan(desc, P, fused);
         if (rc) {
             delete P;
             return rc;
@@ -1489,6 +1522,8 @@ int gsim_plan_create(const gsim_model_desc* desc, gsim_plan** out) {
         return (int)GSIM_OK;
     });
 }
+
+extern "C" {
 
 int gsim_plan_destroy(gsim_plan* plan) {
     delete plan;

@@ -176,6 +176,125 @@ struct Pool {
 };
 
 const int RING = 4;  // tick tables in flight
+const size_t STAGE_CHUNK_BYTES = 8 << 20;  // per staging chunk (host and device), 4 chunks
+const size_t RESULT_RING_BYTES = 32 << 20;  // pinned ring of results on their way out
+
+// Staging of the queries' set-up copies: a ring of chunks, each a pinned host buffer
+// and its device mirror.  copy() packs the bytes into the current chunk (16-byte
+// aligned) and records the pieces; flush() appends the piece table, moves the chunk to
+// its mirror with one copy and scatters it with one k_stage_copy launch, then moves to
+// the next chunk once the launch that last read it has completed.  A copy larger than
+// a chunk goes directly (and waits for the stream, since its source is the caller's).
+struct Stager final : UploadSink {
+    static const int N = 4;
+    size_t cap = 0;
+    char* host[N] = {};
+    char* dev[N] = {};
+    hipEvent_t evt[N] = {};
+    hipStream_t stream = nullptr;
+    int cur = 0;
+    size_t fill = 0;
+    std::vector<StageSeg> segs;
+    int64_t flushes = 0, direct = 0;
+
+    static size_t pieces(size_t n) { return (n + STAGE_PIECE - 1) / STAGE_PIECE; }
+    size_t table_end(size_t data, size_t more) const {
+        return (data + 15) / 16 * 16 + (segs.size() + more) * sizeof(StageSeg);
+    }
+    void add(const char* src, char* dst, size_t n) {
+        for (size_t o = 0; o < n; o += (size_t)STAGE_PIECE)
+            segs.push_back({src ? src + o : nullptr, dst + o, (int64_t)std::min((size_t)STAGE_PIECE, n - o)});
+    }
+    hipError_t copy(void* dst, const void* src, size_t n) override {
+        if (n == 0) return hipSuccess;
+        const size_t need = (n + 15) / 16 * 16;
+        if (need + (pieces(n) + 1) * sizeof(StageSeg) > cap) {
+            ++direct;
+            hipError_t e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, stream);
+            return e == hipSuccess ? hipStreamSynchronize(stream) : e;
+        }
+        if (table_end(fill + need, pieces(n)) > cap)
+            if (hipError_t e = flush()) return e;
+        std::memcpy(host[cur] + fill, src, n);
+        add(dev[cur] + fill, (char*)dst, n);
+        fill += need;
+        return hipSuccess;
+    }
+    hipError_t zero(void* dst, size_t n) override {
+        if (n == 0) return hipSuccess;
+        if ((pieces(n) + 1) * sizeof(StageSeg) > cap) {
+            ++direct;
+            return hipMemsetAsync(dst, 0, n, stream);  // (the engine's stream is never captured)
+        }
+        if (table_end(fill, pieces(n)) > cap)
+            if (hipError_t e = flush()) return e;
+        add(nullptr, (char*)dst, n);
+        return hipSuccess;
+    }
+    hipError_t flush() {
+        if (segs.empty()) return hipSuccess;
+        const size_t t0 = (fill + 15) / 16 * 16;
+        std::memcpy(host[cur] + t0, segs.data(), segs.size() * sizeof(StageSeg));
+        hipError_t e = hipMemcpyAsync(dev[cur], host[cur], table_end(fill, 0), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = (hipError_t)launch_stage_copy(reinterpret_cast<const StageSeg*>(dev[cur] + t0), (int)segs.size(), stream);
+        if (e == hipSuccess) e = hipEventRecord(evt[cur], stream);
+        cur = (cur + 1) % N;
+        fill = 0;
+        segs.clear();
+        ++flushes;
+        if (e == hipSuccess) e = hipEventSynchronize(evt[cur]);  // the chunk's last reader has finished
+        return e;
+    }
+};
+
+// A finished query whose results are on their way to a pinned ring: its gradient
+// block [g_mu, loss] and status words land at [off, off + bytes) of the ring; `evt`
+// (recorded after the copies of the round that finished it) says when.
+struct Pending {
+    std::unique_ptr<Query> q;
+    size_t off = 0, bytes = 0, flags_at = 0;
+    double t_admit = 0;
+    hipEvent_t evt = nullptr;
+};
+
+// The pinned result ring: allocations in FIFO order, freed from the front.
+struct ResultRing {
+    char* host = nullptr;
+    size_t cap = 0;
+    size_t head = 0;
+    std::deque<Pending> q;
+    std::vector<hipEvent_t> free_events;
+
+    bool place(size_t n, size_t& off) {
+        if (n > cap) return false;
+        if (q.empty()) {
+            off = 0;
+            head = n;
+            return true;
+        }
+        const size_t tail = q.front().off;
+        if (head > tail) {  // live entries [tail, head): free space after head and before tail
+            if (head + n <= cap) {
+                off = head;
+                head += n;
+                return true;
+            }
+            if (n < tail) {
+                off = 0;
+                head = n;
+                return true;
+            }
+            return false;
+        }
+        if (head + n < tail) {  // wrapped: live [tail, cap) and [0, head), free [head, tail)
+            off = head;
+            head += n;
+            return true;
+        }
+        return false;
+    }
+};
 
 }  // namespace
 
@@ -198,6 +317,9 @@ struct gsim_engine {
     int micro_per_tick = 1;  // micro-step rounds per gsim_engine_tick
     int64_t ticks = 0, admitted = 0, completed = 0;  // ticks: micro-step rounds
     double live_sum = 0;  // sum over ticks of live queries (mean concurrency)
+    Stager stage;         // the queries' set-up copies
+    ResultRing results;   // finished queries' results on their way to the host
+    bool round_finished = false;  // the current round issued result copies
 };
 
 namespace {
@@ -208,12 +330,12 @@ int admit(gsim_engine* E, std::unique_ptr<Query>& q, size_t off) {
     L.off = off;
     L.base = E->pool_base + off;
     const QLayout& ly = q->lay;
-    int rc = model_init<float>(q->plan.get(), q->T, q->K, L.base + ly.ws, ly.ws_bytes, E->stream, &L.model);
+    Stager& st = E->stage;
+    int rc = model_init<float>(q->plan.get(), q->T, q->K, L.base + ly.ws, ly.ws_bytes, E->stream, &L.model, &st);
     if (rc) return rc;
-    hipStream_t s = E->stream;
     auto up = [&](size_t o, const std::vector<float>& v) -> hipError_t {
         if (v.empty()) return hipSuccess;
-        return hipMemcpyAsync(L.base + o, v.data(), v.size() * 4, hipMemcpyHostToDevice, s);
+        return st.copy(L.base + o, v.data(), v.size() * 4);
     };
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t r) { if (e == hipSuccess) e = r; };
@@ -232,8 +354,7 @@ int admit(gsim_engine* E, std::unique_ptr<Query>& q, size_t off) {
         else if (ne + npt) {
             q->tiles.assign(m->etiles_nat.begin(), m->etiles_nat.end());
             q->tiles.insert(q->tiles.end(), m->ptiles_nat.begin(), m->ptiles_nat.end());
-            chk(hipMemcpyAsync(L.base + ly.tiles, q->tiles.data(), sizeof(Tile) * q->tiles.size(),
-                               hipMemcpyHostToDevice, s));
+            chk(st.copy(L.base + ly.tiles, q->tiles.data(), sizeof(Tile) * q->tiles.size()));
             q->n_etiles = (int)ne;
             q->n_ptiles = (int)npt;
         }
@@ -242,14 +363,22 @@ int admit(gsim_engine* E, std::unique_ptr<Query>& q, size_t off) {
         gsim_model_destroy(L.model);
         return hip_fail(e, "upload query");
     }
-    // zero gradients and contact partial rows (fill kernels)
+    // zero gradients and contact partial rows
     const ModelDev<float>* md = reinterpret_cast<const ModelDev<float>*>(L.model->md_host.data());
-    LAUNCH_TRY(launch_fill<float>(L.F(ly.g_mu), q->ne, 0.f, s), "clear");
-    LAUNCH_TRY(launch_fill<float>(L.F(ly.g_lam), q->ne, 0.f, s), "clear");
-    LAUNCH_TRY(launch_fill<float>(L.F(ly.g_ktri), q->nt, 0.f, s), "clear");
-    LAUNCH_TRY(launch_fill<float>(L.F(ly.g_mass), q->np, 0.f, s), "clear");
-    LAUNCH_TRY(launch_fill<float>(L.F(ly.g_contact), 4, 0.f, s), "clear");
-    LAUNCH_TRY(launch_fill<float>(md->cpart, 4 * (int64_t)(L.model->n_ptile_rows + 1), 0.f, s), "clear");
+    chk(st.zero(L.F(ly.g_mu), 4 * (size_t)q->ne));
+    chk(st.zero(L.F(ly.g_lam), 4 * (size_t)q->ne));
+    chk(st.zero(L.F(ly.g_ktri), 4 * (size_t)q->nt));
+    chk(st.zero(L.F(ly.g_mass), 4 * (size_t)q->np));
+    chk(st.zero(L.F(ly.g_contact), 16));
+    chk(st.zero(md->cpart, 16 * (size_t)(L.model->n_ptile_rows + 1)));
+    if (e != hipSuccess) {
+        gsim_model_destroy(L.model);
+        return hip_fail(e, "clear query");
+    }
+    // the host copies of the inputs are no longer needed
+    for (std::vector<float>* v : {&q->mu, &q->lam, &q->ktri, &q->mass, &q->contact, &q->x0v0, &q->target})
+        std::vector<float>().swap(*v);
+    std::vector<Tile>().swap(q->tiles);
     L.q = std::move(q);
     L.t_admit = now_s();
     E->live.push_back(std::move(L));
@@ -357,10 +486,85 @@ void advance(Live& L, int op) {
     }
 }
 
+// Hands a retired query's results from the ring to the caller's buffers.
+void deliver(gsim_engine* E, Pending& P) {
+    const Query& q = *P.q;
+    const QLayout& ly = q.lay;
+    const char* r = E->results.host + P.off;
+    auto out = [&](float* dst, size_t o, int64_t n) {
+        if (dst && n) std::memcpy(dst, r + (o - ly.g_mu), (size_t)n * 4);
+    };
+    out(q.o_mu, ly.g_mu, q.ne);
+    out(q.o_lam, ly.g_lam, q.ne);
+    out(q.o_ktri, ly.g_ktri, q.nt);
+    out(q.o_mass, ly.g_mass, q.np);
+    out(q.o_contact, ly.g_contact, 4);
+    float loss;
+    int32_t flags[2];
+    std::memcpy(&loss, r + (ly.loss - ly.g_mu), 4);
+    std::memcpy(flags, E->results.host + P.flags_at, sizeof flags);
+    E->done.push_back({q.id, loss, q.t_submit, P.t_admit, now_s(), flags[0] ? GSIM_E_NONFINITE : GSIM_OK});
+    E->completed++;
+}
+
+// Delivers the finished queries whose copies have completed (all of them, waiting,
+// when `wait`), oldest first.
+int retire(gsim_engine* E, bool wait) {
+    ResultRing& R = E->results;
+    while (!R.q.empty()) {
+        Pending& P = R.q.front();
+        if (!P.evt) break;  // its round has not recorded its event yet
+        if (wait) {
+            HIP_TRY(hipEventSynchronize(P.evt), "wait for results");
+        } else {
+            const hipError_t e = hipEventQuery(P.evt);
+            if (e == hipErrorNotReady) break;
+            if (e != hipSuccess) return hip_fail(e, "query results");
+        }
+        deliver(E, P);
+        hipEvent_t ev = P.evt;
+        R.q.pop_front();
+        if (R.q.empty() || R.q.front().evt != ev) R.free_events.push_back(ev);
+    }
+    return GSIM_OK;
+}
+
 int finish(gsim_engine* E, Live& L) {
     Query& q = *L.q;
     const QLayout& ly = q.lay;
     hipStream_t s = E->stream;
+    // asynchronous: the gradient block and the status words go to the pinned ring and
+    // reach the caller when the round's event has completed
+    const size_t span = ly.loss + 4 - ly.g_mu, need = (span + 15) / 16 * 16 + 16;
+    ResultRing& R = E->results;
+    size_t off = 0;
+    bool placed = R.place(need, off);
+    while (!placed && !R.q.empty() && R.q.front().evt) {  // make room: wait for the oldest
+        Pending& P = R.q.front();
+        HIP_TRY(hipEventSynchronize(P.evt), "wait for results");
+        deliver(E, P);
+        hipEvent_t ev = P.evt;
+        R.q.pop_front();
+        if (R.q.empty() || R.q.front().evt != ev) R.free_events.push_back(ev);
+        placed = R.place(need, off);
+    }
+    if (placed) {
+        Pending P;
+        P.off = off;
+        P.bytes = need;
+        P.flags_at = off + (span + 15) / 16 * 16;
+        P.t_admit = L.t_admit;
+        HIP_TRY(hipMemcpyAsync(R.host + off, L.base + ly.g_mu, span, hipMemcpyDeviceToHost, s), "copy out");
+        HIP_TRY(hipMemcpyAsync(R.host + P.flags_at, L.model->ws + L.model->L.bflag, 8, hipMemcpyDeviceToHost, s),
+                "copy out");
+        P.q = std::move(L.q);
+        R.q.push_back(std::move(P));
+        E->round_finished = true;
+        gsim_model_destroy(L.model);
+        E->pool.release(L.off, R.q.back().q->lay.total);  // later users of the region come after the copies
+        return GSIM_OK;
+    }
+    // (results larger than the ring, or the ring held by this round alone: copy and wait)
     float loss = 0.f;
     int32_t flags[2] = {0, 0};
     auto down = [&](float* dst, size_t o, int64_t n) -> hipError_t {
@@ -468,6 +672,7 @@ int micro_round(gsim_engine* E) {
     // advance; finish completed queries
     std::vector<Live> keep;
     keep.reserve(n);
+    E->round_finished = false;
     for (int i = 0; i < n; ++i) {
         Live& L = E->live[i];
         if (ops[i] == OP_FIN) {
@@ -479,11 +684,25 @@ int micro_round(gsim_engine* E) {
         keep.push_back(std::move(L));
     }
     E->live.swap(keep);
+    if (E->round_finished) {  // one event for the result copies of this round
+        ResultRing& R = E->results;
+        hipEvent_t ev = nullptr;
+        if (!R.free_events.empty()) {
+            ev = R.free_events.back();
+            R.free_events.pop_back();
+        } else {
+            HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "result event");
+        }
+        HIP_TRY(hipEventRecord(ev, E->stream), "record results");
+        for (auto it = R.q.rbegin(); it != R.q.rend() && !it->evt; ++it) it->evt = ev;
+    }
     return GSIM_OK;
 }
 
 int tick(gsim_engine* E, int* n_live, int* n_queued) {
-    // 1. admission, FIFO while the head fits
+    if (int rc = retire(E, false)) return rc;
+    // 1. admission, FIFO while the head fits; the admitted queries' set-up copies move
+    // in one staged batch
     while (!E->queue.empty() && (int)E->live.size() < E->max_live) {
         size_t off;
         if (!E->pool.alloc(E->queue.front()->lay.total, off)) break;
@@ -491,13 +710,18 @@ int tick(gsim_engine* E, int* n_live, int* n_queued) {
         E->queue.pop_front();
         int rc = admit(E, q, off);
         if (rc) {
+            (void)E->stage.flush();  // what was staged for the region lands before it is reused
             E->pool.release(off, q ? q->lay.total : 0);
             return rc;
         }
     }
+    HIP_TRY(E->stage.flush(), "stage queries");
     // 2. micro-step rounds
     for (int k = 0; k < E->micro_per_tick && !E->live.empty(); ++k)
         if (int rc = micro_round(E)) return rc;
+    // 3. results: those ready now; all of them once nothing is live or queued, so that
+    // an idle engine has delivered every answer
+    if (int rc = retire(E, E->live.empty() && E->queue.empty())) return rc;
     if (n_live) *n_live = (int)E->live.size();
     if (n_queued) *n_queued = (int)E->queue.size();
     return GSIM_OK;
@@ -535,7 +759,31 @@ int gsim_engine_create(void* d_pool, size_t pool_bytes, int max_live, int64_t ma
             return hip_fail(e, "engine tables");
         }
     }
-    const size_t used = RING * E->blob_bytes;
+    // staging chunks (device mirrors after the table ring) and the pinned result ring
+    Stager& st = E->stage;
+    st.cap = STAGE_CHUNK_BYTES;
+    st.stream = E->stream;
+    size_t used = RING * E->blob_bytes;
+    if (used + Stager::N * st.cap >= pool_bytes) {
+        gsim_engine_destroy(E);
+        return fail(GSIM_E_WORKSPACE, "pool too small for the engine's tables and staging");
+    }
+    for (int c = 0; c < Stager::N; ++c) {
+        st.dev[c] = E->pool_base + used + c * st.cap;
+        hipError_t e = hipHostMalloc((void**)&st.host[c], st.cap, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&st.evt[c], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(st.evt[c], E->stream);
+        if (e != hipSuccess) {
+            gsim_engine_destroy(E);
+            return hip_fail(e, "engine staging");
+        }
+    }
+    used += Stager::N * st.cap;
+    E->results.cap = RESULT_RING_BYTES;
+    if (hipError_t e = hipHostMalloc((void**)&E->results.host, E->results.cap, hipHostMallocDefault)) {
+        gsim_engine_destroy(E);
+        return hip_fail(e, "engine result ring");
+    }
     E->pool.init(pool_bytes - used);
     E->pool_base += used;
     *out = E;
@@ -550,6 +798,17 @@ int gsim_engine_destroy(gsim_engine* E) {
         if (E->blob_evt[r]) (void)hipEventDestroy(E->blob_evt[r]);
         if (E->blob_host[r]) (void)hipHostFree(E->blob_host[r]);
     }
+    for (int c = 0; c < Stager::N; ++c) {
+        if (E->stage.evt[c]) (void)hipEventDestroy(E->stage.evt[c]);
+        if (E->stage.host[c]) (void)hipHostFree(E->stage.host[c]);
+    }
+    std::vector<hipEvent_t> evs = E->results.free_events;
+    for (const Pending& P : E->results.q)
+        if (P.evt && (evs.empty() || evs.back() != P.evt)) evs.push_back(P.evt);
+    std::sort(evs.begin(), evs.end());
+    evs.erase(std::unique(evs.begin(), evs.end()), evs.end());
+    for (hipEvent_t ev : evs) (void)hipEventDestroy(ev);
+    if (E->results.host) (void)hipHostFree(E->results.host);
     delete E;
     return GSIM_OK;
 }
@@ -557,7 +816,7 @@ int gsim_engine_destroy(gsim_engine* E) {
 int gsim_engine_query_bytes(const gsim_query* q, size_t* bytes) {
     if (!q || !q->desc || !bytes) return fail(GSIM_E_INVALID, "NULL argument");
     gsim_plan* P = nullptr;
-    int rc = gsim_plan_create(q->desc, &P);
+    int rc = plan_create(q->desc, &P, false);  // queries run the two-pass path only
     if (rc) return rc;
     *bytes = qlayout(P, q->n_steps, q->ckpt_every).total;
     gsim_plan_destroy(P);
@@ -603,7 +862,7 @@ int gsim_engine_submit(gsim_engine* E, const gsim_query* in, int64_t* id) {
     try {
         std::unique_ptr<Query> q(new Query());
         gsim_plan* P = nullptr;
-        int rc = gsim_plan_create(d, &P);
+        int rc = plan_create(d, &P, false);
         if (rc) return rc;
         q->plan.reset(P);
         q->T = in->n_steps;

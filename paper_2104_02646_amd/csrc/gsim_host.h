@@ -35,6 +35,7 @@ struct gsim_plan {
     // colour-ordered element copies for the fused path: within each body and kind,
     // elements sorted by (colour, index); no two elements of a colour share a particle
     bool fused_ok = false;                         // every kind of every body coloured with <= 128 colours
+    bool coloured = false;                         // the fused path's colouring was made (not for serving queries)
     std::vector<int32_t> ftet, ftri, fhin;         // fused position -> element index
     std::vector<int32_t> coff;                     // colour boundaries (fused element positions)
     std::vector<int32_t> cbase, ncol;              // [nb][3] first entry in coff, number of colours
@@ -84,8 +85,25 @@ int hip_fail(hipError_t e, const char* what);
 // particles, hence L2 lines) land on the same XCD; pads with empty tiles.
 void xcd_order(const std::vector<Tile>& nat, int empty_kind, int dummy_id, std::vector<Tile>& out, int& grid);
 
+// Where the host-to-device copies of a model's set-up go.  Without one, each copy is a
+// hipMemcpyAsync on the set-up stream and the set-up ends with a synchronisation of
+// that stream (the host arrays are temporaries).  The serving engine passes its
+// staging area instead: copy() takes the bytes at once (the source may be freed on
+// return) and zero() records a zero fill; both land on the device, in stream order,
+// before any later launch on that stream reads them.
+struct UploadSink {
+    virtual ~UploadSink() = default;
+    virtual hipError_t copy(void* dst, const void* src, size_t n) = 0;
+    virtual hipError_t zero(void* dst, size_t n) = 0;
+};
+
 template <typename T>
-int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t bytes, void* stream, gsim_model** out);
+int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t bytes, void* stream, gsim_model** out,
+               UploadSink* sink = nullptr);
+
+// gsim_plan_create, optionally without the fused path's colouring (a model of such a
+// plan runs the two-pass path only; its colour-ordered records are not made).
+int plan_create(const gsim_model_desc* desc, gsim_plan** out, bool fused);
 
 }  // namespace gsim
 

@@ -51,6 +51,15 @@ struct TileSeg {
     int32_t begin, count, model, flags;
 };
 
+// One piece of a batched device copy: n bytes from src to dst, or zeros when src is
+// null; the host splits each copy into pieces of at most STAGE_PIECE bytes.
+struct StageSeg {
+    const char* src;
+    char* dst;
+    int64_t n;
+};
+const int64_t STAGE_PIECE = 64 << 10;
+
 template <typename T>
 struct BodyDev {
     int64_t p0, np;      // particle range
@@ -195,6 +204,9 @@ int launch_fill(T* p, int64_t n, T value, void* stream);
 template <typename T>
 int launch_expand_tiles(const TileSeg* eseg, int n_eseg, int e_total, int e_grid, Tile* elist, const TileSeg* pseg,
                         int n_pseg, int p_total, int p_grid, Tile* plist, int dummy_id, void* stream);
+// One workgroup per piece: the pieces' copies and zero fills in one launch (the serving
+// engine's query set-up, staged through one host-to-device copy).
+int launch_stage_copy(const StageSeg* segs, int n_segs, void* stream);
 // Serving: one launch over forward and adjoint element tiles (adjoint ones marked
 // TILE_ADJ), then one over forward and adjoint particle tiles; `lds` covers both kinds.
 template <typename T>

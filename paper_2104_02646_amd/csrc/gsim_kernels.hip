@@ -995,6 +995,25 @@ __global__ void k_expand_tiles(const TileSeg* __restrict__ eseg, int n_eseg, int
     out[pos] = tl;
 }
 
+// Batched copy: workgroup b moves piece b, 16 bytes per lane and load when both
+// addresses are 16-byte aligned (the staging area and every workspace region are),
+// bytes otherwise.
+__global__ void __launch_bounds__(256) k_stage_copy(const StageSeg* __restrict__ segs) {
+    const StageSeg g = segs[blockIdx.x];
+    const char* src = g.src;
+    char* dst = g.dst;
+    const int64_t n = g.n;
+    int64_t done = 0;
+    if (((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0) {
+        const int64_t nv = n >> 4;
+        uint4* d4 = reinterpret_cast<uint4*>(dst);
+        const uint4* s4 = reinterpret_cast<const uint4*>(src);
+        for (int64_t i = threadIdx.x; i < nv; i += blockDim.x) d4[i] = src ? s4[i] : make_uint4(0u, 0u, 0u, 0u);
+        done = nv << 4;
+    }
+    for (int64_t i = done + threadIdx.x; i < n; i += blockDim.x) dst[i] = src ? src[i] : (char)0;
+}
+
 template <typename T>
 __global__ void k_contact_reduce(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ sd) {
     const ModelDev<T>& M = md[0];
@@ -1652,6 +1671,11 @@ int launch_expand_tiles(const TileSeg* eseg, int n_eseg, int e_total, int e_grid
     if (g <= 0) return 0;
     hipLaunchKernelGGL(k_expand_tiles, dim3((g + 255) / 256, 2), dim3(256), 0, (hipStream_t)stream, eseg, n_eseg,
                        e_total, e_grid, elist, pseg, n_pseg, p_total, p_grid, plist, dummy_id);
+    return check_launch();
+}
+int launch_stage_copy(const StageSeg* segs, int n_segs, void* stream) {
+    if (n_segs <= 0) return 0;
+    hipLaunchKernelGGL(k_stage_copy, dim3(n_segs), dim3(256), 0, (hipStream_t)stream, segs);
     return check_launch();
 }
 template <typename T>
