@@ -528,8 +528,17 @@ typedef struct {
 int gsim_engine_create(void* d_pool, size_t pool_bytes, int max_live, int64_t max_tiles, void* stream,
                        gsim_engine** out);
 int gsim_engine_destroy(gsim_engine* engine);
-/* Exact device bytes a query occupies while live (its admission footprint). */
+/* Exact device bytes a query occupies while live with its own checkpoint interval
+ * (its admission footprint; a query the engine runs with every state stored, see
+ * gsim_engine_set_store_limit, occupies the bytes of interval 1). */
 int gsim_engine_query_bytes(const gsim_query* query, size_t* bytes);
+/* Queries whose footprint with every state stored (checkpoint interval 1) is at most
+ * `bytes` run that way: the reverse pass reads each state instead of recomputing the
+ * checkpoint segments, one forward micro-step fewer per step of the rollout but the
+ * first of each segment.  Results are bitwise those of the query's own interval (the
+ * recomputed states are the stored ones).  Default: pool_bytes / 64; 0 keeps every
+ * query's own interval.  Applies to queries submitted afterwards. */
+int gsim_engine_set_store_limit(gsim_engine* engine, size_t bytes);
 /* Validates and plans the query (host), copies its inputs, queues it.  Refused before
  * it takes a slot: a non-finite mass, mu, lambda, k_tri, contact coefficient, start
  * state or target (GSIM_E_NONFINITE); mass, mu, lambda or k_tri not > 0, a negative
@@ -537,10 +546,14 @@ int gsim_engine_query_bytes(const gsim_query* query, size_t* bytes);
  * pool.  A query that goes non-finite while it runs completes with status
  * GSIM_E_NONFINITE in its gsim_result and frees its slot like any other. */
 int gsim_engine_submit(gsim_engine* engine, const gsim_query* query, int64_t* id);
-/* Admits what fits, then runs the set number of micro-step rounds: in each, one
- * micro-step of every live query, the forward and adjoint micro-steps of all queries
- * in one element launch and one particle launch.  Completed queries have their
- * outputs copied (the call waits for that copy).  n_live / n_queued: after the rounds. */
+/* Admits what fits (the admitted queries' set-up copies move as one staged batch),
+ * then runs the set number of micro-step rounds: in each, one micro-step of every live
+ * query, the forward and adjoint micro-steps of all queries in one element launch and
+ * one particle launch.  A completed query's results are copied out asynchronously and
+ * written to its output buffers by a later call once the copy has landed; when no
+ * query is live or queued the call waits for every outstanding copy, so an engine
+ * whose tick reports n_live = n_queued = 0 has delivered every answer (gsim_engine_poll
+ * lists them).  n_live / n_queued: after the rounds. */
 int gsim_engine_tick(gsim_engine* engine, int* n_live, int* n_queued);
 /* Micro-step rounds per gsim_engine_tick (1..256, default 1): admission happens once
  * per tick, then every live query advances by that many micro-steps.  More rounds per

@@ -315,6 +315,7 @@ struct gsim_engine {
     std::vector<Live> live;
     std::vector<Done> done;
     int micro_per_tick = 1;  // micro-step rounds per gsim_engine_tick
+    size_t store_limit = 0;  // queries whose every-state footprint fits store every state
     int64_t ticks = 0, admitted = 0, completed = 0;  // ticks: micro-step rounds
     double live_sum = 0;  // sum over ticks of live queries (mean concurrency)
     Stager stage;         // the queries' set-up copies
@@ -786,6 +787,7 @@ int gsim_engine_create(void* d_pool, size_t pool_bytes, int max_live, int64_t ma
     }
     E->pool.init(pool_bytes - used);
     E->pool_base += used;
+    E->store_limit = E->pool.size / 64;
     *out = E;
     return GSIM_OK;
 }
@@ -870,6 +872,10 @@ int gsim_engine_submit(gsim_engine* E, const gsim_query* in, int64_t* id) {
         q->np = P->np;
         q->ne = P->ne;
         q->nt = P->nt;
+        if (q->K > 1 && E->store_limit > 0) {  // every state stored when it fits the limit
+            const QLayout all = qlayout(P, q->T, 1);
+            if (all.total <= E->store_limit) q->K = 1;
+        }
         q->lay = qlayout(P, q->T, q->K);
         if (q->lay.total > E->pool.size)
             return fail(GSIM_E_WORKSPACE, "query needs %zu bytes, the pool has %zu", q->lay.total, E->pool.size);
@@ -931,6 +937,12 @@ int gsim_engine_set_micro_steps(gsim_engine* E, int rounds) {
     if (!E) return fail(GSIM_E_INVALID, "NULL engine");
     if (rounds < 1 || rounds > 256) return fail(GSIM_E_INVALID, "micro-step rounds per tick must be in [1, 256]");
     E->micro_per_tick = rounds;
+    return GSIM_OK;
+}
+
+int gsim_engine_set_store_limit(gsim_engine* E, size_t bytes) {
+    if (!E) return fail(GSIM_E_INVALID, "NULL engine");
+    E->store_limit = bytes;
     return GSIM_OK;
 }
 

@@ -42,7 +42,8 @@ ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan
                "gsim_raster_forward_noalloc",
                "gsim_raster_backward",
                "gsim_engine_create", "gsim_engine_destroy", "gsim_engine_query_bytes", "gsim_engine_submit",
-               "gsim_engine_tick", "gsim_engine_poll", "gsim_engine_stats", "gsim_engine_set_micro_steps")
+               "gsim_engine_tick", "gsim_engine_poll", "gsim_engine_stats", "gsim_engine_set_micro_steps",
+               "gsim_engine_set_store_limit")
 GSIM_F32, GSIM_F64 = 32, 64
 KERNELS = ("element_fwd", "particle_fwd", "element_adj", "particle_adj", "fused_fwd", "fused_adj")
 

@@ -47,6 +47,7 @@ def _load():
         lib.gsim_engine_tick.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         lib.gsim_engine_poll.argtypes = [vp, C.POINTER(_Result), C.c_int, C.POINTER(C.c_int)]
         lib.gsim_engine_set_micro_steps.argtypes = [vp, C.c_int]
+        lib.gsim_engine_set_store_limit.argtypes = [vp, C.c_size_t]
         lib.gsim_engine_stats.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                           C.POINTER(C.c_double), C.POINTER(C.c_size_t)]
         _ready = True
@@ -130,6 +131,11 @@ class Engine:
         _check(_load().gsim_engine_submit(self._h, C.byref(qb.q), C.byref(i)))
         self.pending[i.value] = qb
         return i.value
+
+    def set_store_limit(self, nbytes):
+        """Queries whose every-state footprint is at most nbytes store every state
+        (gsim_engine_set_store_limit; 0: every query keeps its own interval)."""
+        _check(_load().gsim_engine_set_store_limit(self._h, int(nbytes)))
 
     def set_micro_steps(self, rounds):
         """Micro-step rounds per tick (gsim_engine_set_micro_steps)."""

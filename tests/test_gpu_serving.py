@@ -145,3 +145,26 @@ def test_served_answers_match_the_oracle(sv, oracle_lib):
         for k, v in errs.items():
             if k != "loss" and not k.endswith(" max"):
                 assert v < 1e-3, (k, v)
+
+
+def test_store_every_state_is_bitwise_the_checkpointed_answer(sv):
+    """The same queries with their own checkpoint intervals (store limit 0) and with
+    every state stored (a limit above every footprint): bitwise the same losses and
+    gradients, in fewer micro-step rounds (no recomputed segments)."""
+    qs = mixed_queries()
+    runs = []
+    for limit in (0, 1 << 40):
+        qbs = [sv.QueryBuffers(b, T, K) for b, T, K in qs]
+        eng = sv.Engine(pool_bytes=1 << 30, max_live=16)
+        eng.set_store_limit(limit)
+        for qb in qbs:
+            eng.submit(qb)
+        eng.run_until_idle()
+        runs.append((qbs, eng.stats()["ticks"]))
+    (a, ticks_a), (b, ticks_b) = runs
+    for qa, qb in zip(a, b):
+        assert qa.status == 0 and qb.status == 0
+        assert np.float32(qa.loss) == np.float32(qb.loss)
+        for k in qa.out:
+            assert np.array_equal(qa.out[k], qb.out[k]), k
+    assert ticks_b < ticks_a
