@@ -104,9 +104,9 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
 # (of gsim_kernels.hip followed by gsim_device.h) and 512-element tiles only; for any other
 # source or tile size the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "source_sha1": "0d1d1e632825bb186887573d7fab86b9885cb962",
+    "source_sha1": "908e3b1d58256465d433549210c89afe3235c7fa",
     "workload": (256, 100, 10, 512),  # bodies, steps, checkpoint interval, elements per tile
-    "per_launch": {"element_fwd": 108.48e6, "particle_fwd": 29.74e6, "element_adj": 134.23e6,
+    "per_launch": {"element_fwd": 108.49e6, "particle_fwd": 29.74e6, "element_adj": 134.26e6,
                    "particle_adj": 42.81e6},
 }
 
@@ -222,7 +222,7 @@ def host_info():
     return {"cpu_model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
 
 
-def gradient_line(bodies, dtype, T, K, exec_mode, lanes=1, reps=3, timing=False, targets=None):
+def gradient_line(bodies, dtype, T, K, exec_mode, lanes=1, reps=3, timing=False, targets=None, tile=0):
     """One model of `bodies`: median ms of a checkpointed gradient (rollout, loss, zeroed
     gradients, adjoint) and of a forward rollout, HIP events on the launch stream; with
     `timing`, also one gradient in plain execution with per-kernel events and the
@@ -234,7 +234,7 @@ def gradient_line(bodies, dtype, T, K, exec_mode, lanes=1, reps=3, timing=False,
     nel = sum(b.ne + b.nt + b.nh for b in bodies)
     np_ = sum(b.np for b in bodies)
     with torch.cuda.stream(stream):
-        m = gsim.Model(bodies, dtype, max_steps=T, ckpt_every=K)
+        m = gsim.Model(bodies, dtype, max_steps=T, ckpt_every=K, tile_elems=tile)
         m.set_exec(exec_mode)
         m.set_lanes(min(lanes, len(bodies)))
         p = m.params_from_bodies()
@@ -318,15 +318,30 @@ def config_lines(W, log):
         c1[en] = try_line(cl, torch.float32, 400, 20, ex)
     out["cloth"] = c1
     log("configs: cloth done")
+    from paper_2104_02646_amd import autotune
+
+    def tuned(bodies, T, K, tiles, lanes, fused):
+        """The autotuner's choice for this workload (set-up, outside every timing)."""
+        t0 = time.perf_counter()
+        m, rep = autotune.tune_model(bodies, torch.float32, T, K, reps=2, use_cache=False, tiles=tiles, lanes=lanes,
+                                     fused=fused)
+        del m
+        torch.cuda.synchronize()
+        return dict(rep["choice"], candidates_ms=rep["candidates_ms"], tune_s=time.perf_counter() - t0)
     blob = W.large_blob(30).round_to(np.float32)
     c3 = {"workload": "large blob: %d tets, %d particles, 1000 steps, checkpoints every 50" % (blob.ne, blob.np),
           "unit": "element-steps/s"}
-    c3["graph"] = gradient_line([blob], torch.float32, 1000, 50, gsim.EXEC_GRAPH, timing=True)
-    c3["plain"] = gradient_line([blob], torch.float32, 1000, 50, gsim.EXEC_PLAIN)
+    ch = tuned([blob], 1000, 50, (64, 128, 256, 512), (1,), False)
+    c3["autotuned"] = ch
+    c3["graph"] = gradient_line([blob], torch.float32, 1000, 50, gsim.EXEC_GRAPH, timing=True, tile=ch["tile_elems"])
+    c3["plain"] = gradient_line([blob], torch.float32, 1000, 50, gsim.EXEC_PLAIN, tile=ch["tile_elems"])
     out["large_blob"] = c3
     log("configs: large blob done")
     big = [b.round_to(np.float32) for b in W.batch_bodies(20, 2048)]
-    out["batch_2048"] = dict(gradient_line(big, torch.float32, 100, 10, gsim.EXEC_GRAPH, lanes=3, timing=True),
+    ch = tuned(big, 100, 10, (512,), (2, 3, 4), False)
+    out["batch_2048"] = dict(gradient_line(big, torch.float32, 100, 10, gsim.EXEC_GRAPH, lanes=ch["lanes"], timing=True,
+                                           tile=ch["tile_elems"]),
+                             autotuned=ch,
                              workload="batch of 2048 tet bodies (%d tets, %d particles), 100 steps, checkpoints "
                                       "every 10: working set beyond the 256 MB last-level cache"
                                       % (sum(b.ne for b in big), sum(b.np for b in big)),
@@ -364,14 +379,20 @@ def serving(n_measured, n_warm, ckpt_every, log):
     # engine's slots stay full; throughput against the queries' algorithmic bytes
     n_sat = min(400, len(trace))
     eng = serve.Engine(pool_bytes=8 << 30, max_live=256, max_tiles=1 << 18)
+    # the engine stores every state of a query whose whole trajectory fits 1/64 of its
+    # pool (no recomputed segments): the algorithmic bytes count the passes it runs
+    limit = eng.stats()["pool_free"] // 64
+    k_run = [1 if serve.QueryBuffers(b, q.steps, 1).bytes() <= limit else ckpt_every
+             for q, b in zip(trace[:n_sat], bodies[:n_sat])]
     slat, swall, _ = serve.replay_trace(trace[:n_sat], bodies[:n_sat], eng, ckpt_every=ckpt_every, time_scale=0.0)
     sst = eng.stats()
     del eng
     torch.cuda.synchronize()
     log("serving: saturation done (%.1f s)" % swall)
-    sbytes = sum(gradient_bytes(b.ne, b.np, q.steps, ckpt_every, b.nt, b.nh)[0] for q, b in zip(trace[:n_sat],
-                                                                                              bodies[:n_sat]))
+    sbytes = sum(gradient_bytes(b.ne, b.np, q.steps, k, b.nt, b.nh)[0]
+                 for q, b, k in zip(trace[:n_sat], bodies[:n_sat], k_run))
     sat = {"queries": n_sat, "wall_s": swall, "req_per_s": n_sat / swall,
+           "queries_storing_every_state": int(sum(k == 1 for k in k_run)),
            "element_steps_per_s": float(work[:n_sat].sum() / swall), "mean_live": sst["mean_live"],
            "ticks": sst["ticks"], "ms_per_tick": swall * 1e3 / max(sst["ticks"], 1),
            "algorithmic_GBps": sbytes / swall / 1e9, "frac_of_hbm_peak": sbytes / swall / 1e9 / HBM_PEAK_GBS}

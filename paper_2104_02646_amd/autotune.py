@@ -154,13 +154,13 @@ def _gradient_ms(m, bodies, T, reps, stream):
 
 
 def tune_model(bodies, dtype=torch.float32, max_steps=100, ckpt_every=10, reps=3, use_cache=True, device="cuda",
-               stream=None, tiles=TILE_CANDIDATES, lanes=LANE_CANDIDATES):
-    """Builds the batch with every candidate (tile size, lanes, graph) and the fused path,
-    times a gradient of max_steps steps for each, and returns (model, report) for the
-    fastest; the model is left in that configuration."""
+               stream=None, tiles=TILE_CANDIDATES, lanes=LANE_CANDIDATES, fused=True):
+    """Builds the batch with every candidate (tile size, lanes, graph) and, with `fused`,
+    the fused path, times a gradient of max_steps steps for each, and returns (model,
+    report) for the fastest; the model is left in that configuration."""
     stream = stream or torch.cuda.Stream(device)
     T, K = int(max_steps), int(ckpt_every)
-    key = model_key(bodies, dtype, T, K, device)
+    key = model_key(bodies, dtype, T, K, device) + ("" if fused else "/two-pass")
     cache = _load_cache() if use_cache else {}
 
     def build(tile, n_lanes, exec_mode):
@@ -181,12 +181,13 @@ def tune_model(bodies, dtype=torch.float32, max_steps=100, ckpt_every=10, reps=3
             m.set_lanes(n_lanes)
             results["tile%d/lanes%d/graph" % (tile, n_lanes)] = _gradient_ms(m, bodies, T, reps, stream)
         del m
-    try:
-        m = build(0, 1, gsim.EXEC_FUSED)
-        results["fused"] = _gradient_ms(m, bodies, T, reps, stream)
-        del m
-    except gsim.GsimError:
-        pass  # a body does not fit one workgroup's LDS
+    if fused:
+        try:
+            m = build(0, 1, gsim.EXEC_FUSED)
+            results["fused"] = _gradient_ms(m, bodies, T, reps, stream)
+            del m
+        except gsim.GsimError:
+            pass  # a body does not fit one workgroup's LDS
     torch.cuda.synchronize()
     best = min(results, key=results.get)
     if best == "fused":
