@@ -523,8 +523,9 @@ typedef struct {
 } gsim_result;
 
 /* d_pool: caller-owned device memory (256-byte aligned); max_live: live query
- * slots; max_tiles: capacity of one tick's tile lists (sum over live queries of
- * their planned element tiles and their particle tiles of 256 particles). */
+ * slots; max_tiles: the most tiles one round's element or particle launch may hold
+ * (sum over live queries of their planned element tiles, or of their particle tiles
+ * of 256 particles; a round beyond it fails with GSIM_E_WORKSPACE). */
 int gsim_engine_create(void* d_pool, size_t pool_bytes, int max_live, int64_t max_tiles, void* stream,
                        gsim_engine** out);
 int gsim_engine_destroy(gsim_engine* engine);

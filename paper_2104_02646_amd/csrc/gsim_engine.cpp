@@ -601,8 +601,8 @@ int micro_round(gsim_engine* E) {
     std::vector<StepDev<float>> sd(n);
     for (int i = 0; i < n; ++i) ops[i] = next_op(E->live[i], sd[i]);
     // segment tables: each query with a forward or adjoint micro-step contributes its
-    // resident element tiles and particle tiles; the device expands them into the
-    // round's XCD-ordered lists
+    // resident element tiles and particle tiles; each workgroup of the round's two
+    // launches finds its tile in them (XCD order over the concatenation)
     std::vector<TileSeg> seg[2];  // element pass, particle pass
     int total[2] = {0, 0};
     for (int i = 0; i < n; ++i) {
@@ -623,8 +623,7 @@ int micro_round(gsim_engine* E) {
     if (grid[0] > E->max_tiles || grid[1] > E->max_tiles)
         return fail(GSIM_E_WORKSPACE, "a round needs %d / %d tiles, the engine holds %lld", grid[0], grid[1],
                     (long long)E->max_tiles);
-    // one upload: [ModelDev x n][StepDev x n][element segments][particle segments]; the
-    // round's expanded tile lists sit at fixed offsets of the same slot
+    // one upload: [ModelDev x n][StepDev x n][element segments][particle segments]
     const size_t md_sz = sizeof(ModelDev<float>), sd_sz = sizeof(StepDev<float>);
     const size_t o_md = 0, o_sd = aup(md_sz * n), o_s0 = aup(o_sd + sd_sz * n);
     const size_t o_s1 = aup(o_s0 + sizeof(TileSeg) * seg[0].size());
@@ -642,13 +641,7 @@ int micro_round(gsim_engine* E) {
     HIP_TRY(hipMemcpyAsync(d, h, o, hipMemcpyHostToDevice, E->stream), "upload tick tables");
     const ModelDev<float>* dmd = reinterpret_cast<const ModelDev<float>*>(d + o_md);
     const StepDev<float>* dsd = reinterpret_cast<const StepDev<float>*>(d + o_sd);
-    Tile* elist = reinterpret_cast<Tile*>(d + E->head_bytes);
-    Tile* plist = elist + E->max_tiles;
     const int dummy_row = E->live[0].model->n_ptile_rows;  // empty tiles reduce into model 0's spare row
-    LAUNCH_TRY(launch_expand_tiles<float>(reinterpret_cast<const TileSeg*>(d + o_s0), (int)seg[0].size(), total[0],
-                                          grid[0], elist, reinterpret_cast<const TileSeg*>(d + o_s1),
-                                          (int)seg[1].size(), total[1], grid[1], plist, dummy_row, E->stream),
-               "round tile lists");
     // per-query singular launches (loss seed, contact reduction)
     for (int i = 0; i < n; ++i) {
         gsim_model* m = E->live[i].model;
@@ -667,7 +660,9 @@ int micro_round(gsim_engine* E) {
         if (ops[i] == OP_FWD) lds = std::max(lds, (size_t)m->etile_words[0] * sizeof(float));
         if (ops[i] == OP_ADJ) lds = std::max(lds, (size_t)m->etile_words[1] * sizeof(float));
     }
-    LAUNCH_TRY(launch_mixed<float>(dmd, dsd, elist, grid[0], plist, grid[1], block, lds, E->stream),
+    LAUNCH_TRY(launch_mixed<float>(dmd, dsd, reinterpret_cast<const TileSeg*>(d + o_s0), (int)seg[0].size(), total[0],
+                                   grid[0], reinterpret_cast<const TileSeg*>(d + o_s1), (int)seg[1].size(), total[1],
+                                   grid[1], dummy_row, block, lds, E->stream),
                "element and particle passes");
     HIP_TRY(hipEventRecord(E->blob_evt[r], E->stream), "record tick");
     // advance; finish completed queries
@@ -742,10 +737,9 @@ int gsim_engine_create(void* d_pool, size_t pool_bytes, int max_live, int64_t ma
     E->max_live = max_live;
     E->max_tiles = max_tiles;
     E->stream = (hipStream_t)stream;
-    // a ring slot: the round's uploaded head (models, steps, segment tables), then the two
-    // tile lists the device expands
+    // a ring slot: the round's uploaded tables (models, steps, segment tables)
     E->head_bytes = aup((sizeof(ModelDev<float>) + sizeof(StepDev<float>) + 2 * sizeof(TileSeg)) * max_live + 4 * 256);
-    E->blob_bytes = E->head_bytes + aup(2 * sizeof(Tile) * (size_t)max_tiles);
+    E->blob_bytes = E->head_bytes;
     if ((size_t)RING * E->blob_bytes >= pool_bytes) {
         delete E;
         return fail(GSIM_E_WORKSPACE, "pool too small for the engine's tables");

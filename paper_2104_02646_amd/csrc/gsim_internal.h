@@ -196,22 +196,19 @@ int launch_part_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* til
                     bool air, void* stream);
 template <typename T>
 int launch_fill(T* p, int64_t n, T value, void* stream);
-// Serving: expands a round's segment tables into its element and particle tile lists,
-// each in the XCD order of xcd_order (tile t of the concatenation at (t % G) * N_XCD +
-// t / G, G = grid / N_XCD; grid = the total rounded up to N_XCD, the rest empty tiles of
-// `empty_kind` reducing into row dummy_id of model 0).  Lists of fewer than N_XCD tiles
-// keep their order.
-template <typename T>
-int launch_expand_tiles(const TileSeg* eseg, int n_eseg, int e_total, int e_grid, Tile* elist, const TileSeg* pseg,
-                        int n_pseg, int p_total, int p_grid, Tile* plist, int dummy_id, void* stream);
 // One workgroup per piece: the pieces' copies and zero fills in one launch (the serving
 // engine's query set-up, staged through one host-to-device copy).
 int launch_stage_copy(const StageSeg* segs, int n_segs, void* stream);
-// Serving: one launch over forward and adjoint element tiles (adjoint ones marked
-// TILE_ADJ), then one over forward and adjoint particle tiles; `lds` covers both kinds.
+// Serving: one launch over a round's forward and adjoint element tiles (adjoint ones
+// marked TILE_ADJ), then one over its particle tiles; each workgroup finds its tile from
+// the round's segment tables (position pos of the XCD order of the concatenation: tile
+// t = (pos % N_XCD) * G + pos / N_XCD, G = grid / N_XCD, grid = the total rounded up to
+// N_XCD; fewer than N_XCD tiles keep their order; positions past the total are empty
+// tiles reducing into row dummy_id of model 0).  `lds` covers both element kinds.
 template <typename T>
-int launch_mixed(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* etiles, int n_etiles, const Tile* ptiles,
-                 int n_ptiles, int block, size_t lds, void* stream);
+int launch_mixed(const ModelDev<T>* md, const StepDev<T>* sd, const TileSeg* eseg, int n_eseg, int e_total, int e_grid,
+                 const TileSeg* pseg, int n_pseg, int p_total, int p_grid, int dummy_id, int block, size_t lds,
+                 void* stream);
 template <typename T>
 int launch_contact_reduce(const ModelDev<T>* md, const StepDev<T>* sd, int n_bodies, void* stream);
 template <typename T>

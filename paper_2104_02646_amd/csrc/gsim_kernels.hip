@@ -928,15 +928,68 @@ __global__ void __launch_bounds__(512) k_part_adj(const ModelDev<T>* __restrict_
     part_adj_tile<T, AIR>(md, sd, tiles[blockIdx.x]);
 }
 
-// Serving: the forward and the adjoint tiles of one micro-step run in one launch per
-// pass (TILE_ADJ marks an adjoint tile; a tile never mixes queries and the forward and
-// adjoint tiles of a launch belong to different queries), so the two kinds of work
-// overlap instead of following each other.  The branch is uniform per workgroup.
+// Serving: the tile at launch position `pos` of a round's element or particle launch.
+// The round's tiles are the concatenation of its segments (each query's resident tiles,
+// segments in increasing order of their first position `begin`) laid out in XCD order:
+// position pos holds tile t = (pos % N_XCD) * G + pos / N_XCD of the concatenation
+// (G = grid / N_XCD; fewer than N_XCD tiles keep their order), and positions past the
+// total are empty tiles of `empty_kind` reducing into row dummy_id of model 0.  Each
+// wavefront finds t's segment from the segments' begins by ballots (see below), then
+// loads that segment and the tile: three dependent loads for up to 256 segments.
+__device__ __forceinline__ Tile round_tile(const TileSeg* __restrict__ seg, int nseg, int total, int grid, int pos,
+                                           int empty_kind, int dummy_id) {
+    Tile tl;
+    const int nx = 8;  // N_XCD
+    const int t = total < nx ? pos : (pos % nx) * (grid / nx) + pos / nx;
+    if (t >= total) {
+        tl.model = 0;
+        tl.body = 0;
+        tl.kind = empty_kind;
+        tl.count = 0;
+        tl.begin = 0;
+        tl.id = dummy_id;
+        tl.pad = 0;
+        return tl;
+    }
+    // the first SEG_LOOKUP_CHUNKS * 64 begins in one round of independent loads; the
+    // segments with begin <= t form a prefix whose length, summed over the ballots,
+    // names the segment (a longer table continues chunk by chunk)
+    constexpr int SEG_LOOKUP_CHUNKS = 4;
+    const int lane = threadIdx.x & 63;
+    int bg[SEG_LOOKUP_CHUNKS];
+#pragma unroll
+    for (int k = 0; k < SEG_LOOKUP_CHUNKS; ++k) {
+        const int i = 64 * k + lane;
+        bg[k] = i < nseg ? seg[i].begin : INT32_MAX;
+    }
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < SEG_LOOKUP_CHUNKS; ++k) c += __popcll(__ballot(bg[k] <= t));
+    for (int b = 64 * SEG_LOOKUP_CHUNKS; b < nseg && c == b; b += 64) {  // uniform trip count
+        const int i = b + lane;
+        c += __popcll(__ballot(i < nseg && seg[i].begin <= t));
+    }
+    const TileSeg g = seg[c - 1];  // the same address in every lane
+    const Tile* tiles = g.tiles;
+    const int sbegin = g.begin, smodel = g.model, sflags = g.flags;
+    tl = tiles[t - sbegin];
+    tl.model = smodel;
+    tl.kind |= sflags;
+    return tl;
+}
+
+// Serving: one launch over the forward and adjoint element tiles of a round (the
+// adjoint ones marked TILE_ADJ), and one over its particle tiles.  Each workgroup runs
+// the same element or particle code as the two-pass kernels, for its query's launch
+// records; forward and adjoint tiles of a launch belong to different queries, so the
+// two kinds of work overlap instead of following each other.  The branch is uniform
+// per workgroup.
 template <typename T>
 __global__ void __launch_bounds__(512) k_elem_mixed(const ModelDev<T>* __restrict__ md,
-                                                     const StepDev<T>* __restrict__ sd, const Tile* __restrict__ tiles) {
+                                                     const StepDev<T>* __restrict__ sd, const TileSeg* __restrict__ seg,
+                                                     int nseg, int total, int grid, int dummy_id) {
     extern __shared__ __align__(16) unsigned char smem[];
-    Tile tl = tiles[blockIdx.x];
+    Tile tl = round_tile(seg, nseg, total, grid, blockIdx.x, TILE_TET, dummy_id);
     if (tl.kind & TILE_ADJ) {
         tl.kind &= ~TILE_ADJ;
         elem_adj_tile<T, false>(md, sd, tl, smem);
@@ -946,53 +999,15 @@ __global__ void __launch_bounds__(512) k_elem_mixed(const ModelDev<T>* __restric
 }
 template <typename T>
 __global__ void __launch_bounds__(512) k_part_mixed(const ModelDev<T>* __restrict__ md,
-                                                     const StepDev<T>* __restrict__ sd, const Tile* __restrict__ tiles) {
-    Tile tl = tiles[blockIdx.x];
+                                                     const StepDev<T>* __restrict__ sd, const TileSeg* __restrict__ seg,
+                                                     int nseg, int total, int grid, int dummy_id) {
+    Tile tl = round_tile(seg, nseg, total, grid, blockIdx.x, TILE_PART, dummy_id);
     if (tl.kind & TILE_ADJ) {
         tl.kind &= ~TILE_ADJ;
         part_adj_tile<T, false>(md, sd, tl);
     } else {
         part_fwd_tile<T>(md, sd, tl);
     }
-}
-
-// Serving: builds a round's tile lists from the queries' resident tiles (one thread per
-// output position; blockIdx.y selects the element or the particle list).  A position
-// of the XCD order maps back to tile t = (pos % N_XCD) * G + pos / N_XCD of the
-// concatenation; t finds its segment by binary search over the segments' begins.
-__global__ void k_expand_tiles(const TileSeg* __restrict__ eseg, int n_eseg, int e_total, int e_grid,
-                               Tile* __restrict__ elist, const TileSeg* __restrict__ pseg, int n_pseg, int p_total,
-                               int p_grid, Tile* __restrict__ plist, int dummy_id) {
-    const bool part = blockIdx.y == 1;
-    const TileSeg* seg = part ? pseg : eseg;
-    const int nseg = part ? n_pseg : n_eseg, total = part ? p_total : e_total, grid = part ? p_grid : e_grid;
-    Tile* out = part ? plist : elist;
-    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pos >= grid) return;
-    const int nx = 8;  // N_XCD
-    const int t = total < nx ? pos : (pos % nx) * (grid / nx) + pos / nx;
-    Tile tl;
-    if (t < total) {
-        int lo = 0, hi = nseg - 1;  // the last segment with begin <= t
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (seg[mid].begin <= t) lo = mid;
-            else hi = mid - 1;
-        }
-        const TileSeg g = seg[lo];
-        tl = g.tiles[t - g.begin];
-        tl.model = g.model;
-        tl.kind |= g.flags;
-    } else {
-        tl.model = 0;
-        tl.body = 0;
-        tl.kind = part ? TILE_PART : TILE_TET;
-        tl.count = 0;
-        tl.begin = 0;
-        tl.id = dummy_id;
-        tl.pad = 0;
-    }
-    out[pos] = tl;
 }
 
 // Batched copy: workgroup b moves piece b, 16 bytes per lane and load when both
@@ -1664,31 +1679,25 @@ int launch_part_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* til
         launch_timed(k_part_adj<T, false>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
     return check_launch();
 }
-template <typename T>
-int launch_expand_tiles(const TileSeg* eseg, int n_eseg, int e_total, int e_grid, Tile* elist, const TileSeg* pseg,
-                        int n_pseg, int p_total, int p_grid, Tile* plist, int dummy_id, void* stream) {
-    const int g = std::max(e_grid, p_grid);
-    if (g <= 0) return 0;
-    hipLaunchKernelGGL(k_expand_tiles, dim3((g + 255) / 256, 2), dim3(256), 0, (hipStream_t)stream, eseg, n_eseg,
-                       e_total, e_grid, elist, pseg, n_pseg, p_total, p_grid, plist, dummy_id);
-    return check_launch();
-}
 int launch_stage_copy(const StageSeg* segs, int n_segs, void* stream) {
     if (n_segs <= 0) return 0;
     hipLaunchKernelGGL(k_stage_copy, dim3(n_segs), dim3(256), 0, (hipStream_t)stream, segs);
     return check_launch();
 }
 template <typename T>
-int launch_mixed(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* etiles, int n_etiles, const Tile* ptiles,
-                 int n_ptiles, int block, size_t lds, void* stream) {
+int launch_mixed(const ModelDev<T>* md, const StepDev<T>* sd, const TileSeg* eseg, int n_eseg, int e_total, int e_grid,
+                 const TileSeg* pseg, int n_pseg, int p_total, int p_grid, int dummy_id, int block, size_t lds,
+                 void* stream) {
     static size_t allowed = 48 * 1024;
-    if (n_etiles > 0) {
+    if (e_grid > 0) {
         allow_lds(reinterpret_cast<const void*>(&k_elem_mixed<T>), lds, allowed);
-        hipLaunchKernelGGL(k_elem_mixed<T>, dim3(n_etiles), dim3(block), lds, (hipStream_t)stream, md, sd, etiles);
+        hipLaunchKernelGGL(k_elem_mixed<T>, dim3(e_grid), dim3(block), lds, (hipStream_t)stream, md, sd, eseg, n_eseg,
+                           e_total, e_grid, dummy_id);
         if (int rc = check_launch()) return rc;
     }
-    if (n_ptiles > 0)
-        hipLaunchKernelGGL(k_part_mixed<T>, dim3(n_ptiles), dim3(block), 0, (hipStream_t)stream, md, sd, ptiles);
+    if (p_grid > 0)
+        hipLaunchKernelGGL(k_part_mixed<T>, dim3(p_grid), dim3(block), 0, (hipStream_t)stream, md, sd, pseg, n_pseg,
+                           p_total, p_grid, dummy_id);
     return check_launch();
 }
 template <typename T>
@@ -1775,10 +1784,8 @@ int launch_fused_grads(const ModelDev<T>* md, const StepDev<T>* sd, void* stream
     template int launch_elem_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, size_t, bool, void*); \
     template int launch_part_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, bool, void*); \
     template int launch_fill<T>(T*, int64_t, T, void*);                                                             \
-    template int launch_expand_tiles<T>(const TileSeg*, int, int, int, Tile*, const TileSeg*, int, int, int, Tile*,  \
-                                        int, void*);                                                                \
-    template int launch_mixed<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, const Tile*, int, int,       \
-                                 size_t, void*);                                                                    \
+    template int launch_mixed<T>(const ModelDev<T>*, const StepDev<T>*, const TileSeg*, int, int, int, const TileSeg*, \
+                                 int, int, int, int, int, size_t, void*);                                           \
     template int launch_contact_reduce<T>(const ModelDev<T>*, const StepDev<T>*, int, void*);                       \
     template int launch_loss<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, int, void*);     \
     template int launch_fused_fwd<T>(const ModelDev<T>*, const StepDev<T>*, const int32_t*, int, size_t, void*);     \
