@@ -443,6 +443,11 @@ int next_op(const Live& L, StepDev<float>& r) {
         r.vb = r.xb + 3 * np;
         r.xbo = L.F(L.qa & 1 ? ly.aB : ly.aA);
         r.vbo = r.xbo + 3 * np;
+        // adjoint-force hand-off (as in the rollout backward): this step's particle pass
+        // stores step t-1's adjoint force, the element pass of the next one reads it
+        float* fbar = reinterpret_cast<float*>(L.model->ws + L.model->L.fbar);
+        if (t > 0) r.fbo = fbar + (int64_t)(L.qa & 1) * 3 * np;
+        if (L.qa > 0) r.fb = fbar + (int64_t)((L.qa - 1) & 1) * 3 * np;
         r.g_mu = q.ne ? L.F(ly.g_mu) : nullptr;
         r.g_lam = q.ne ? L.F(ly.g_lam) : nullptr;
         r.g_ktri = q.nt ? L.F(ly.g_ktri) : nullptr;
