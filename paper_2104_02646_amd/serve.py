@@ -146,18 +146,21 @@ class Engine:
         _check(_load().gsim_engine_tick(self._h, C.byref(nl), C.byref(nq)))
         return nl.value, nq.value
 
-    def poll(self, max_n=256):
-        res = (_Result * max_n)()
+    def poll(self, batch=256):
+        """Every completed query not yet reported (gsim_engine_poll, `batch` at a time)."""
+        res = (_Result * batch)()
         n = C.c_int()
-        _check(_load().gsim_engine_poll(self._h, res, max_n, C.byref(n)))
         out = []
-        for k in range(n.value):
-            r = res[k]
-            qb = self.pending.pop(r.id)
-            qb.loss = r.loss
-            qb.status = r.status
-            out.append((r.id, qb, r.t_submit, r.t_admit, r.t_done))
-        return out
+        while True:
+            _check(_load().gsim_engine_poll(self._h, res, batch, C.byref(n)))
+            for k in range(n.value):
+                r = res[k]
+                qb = self.pending.pop(r.id)
+                qb.loss = r.loss
+                qb.status = r.status
+                out.append((r.id, qb, r.t_submit, r.t_admit, r.t_done))
+            if n.value < batch:
+                return out
 
     def stats(self):
         t, a, c = C.c_int64(), C.c_int64(), C.c_int64()

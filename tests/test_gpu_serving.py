@@ -168,3 +168,29 @@ def test_store_every_state_is_bitwise_the_checkpointed_answer(sv):
         for k in qa.out:
             assert np.array_equal(qa.out[k], qb.out[k]), k
     assert ticks_b < ticks_a
+
+
+def test_more_segments_than_one_lookup_holds(sv):
+    """300 small queries live at once: every round's launches hold 300 segments, beyond
+    one wavefront's 64 and beyond the 256 begins each workgroup loads at once, so the
+    tile lookup takes its chunked path; every answer is bitwise that of the query alone
+    (sampled) and the first rounds run all 300 together."""
+    qs = []
+    for s in range(300):
+        b = W.tiny_cube(s)
+        b.target = W.synthetic_target(b, 1000 + s)
+        qs.append(b)
+    qbs = [sv.QueryBuffers(b, 12, 4) for b in qs]
+    eng = sv.Engine(pool_bytes=1 << 30, max_live=300, max_tiles=1 << 12)
+    for qb in qbs:
+        eng.submit(qb)
+    nl, nq = eng.tick()
+    assert nl == 300 and nq == 0
+    done = eng.poll() + eng.run_until_idle()
+    assert len(done) == 300
+    for qb in qbs[::23] + [qbs[-1]]:
+        assert qb.status == 0
+        loss, g = sv.solve_alone(qb)
+        assert np.float32(loss) == np.float32(qb.loss)
+        for k in ("mu", "lam", "mass", "contact"):
+            assert np.array_equal(g[k], qb.out[k]), k
