@@ -104,10 +104,10 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
 # (of gsim_kernels.hip followed by gsim_device.h) and 512-element tiles only; for any other
 # source or tile size the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "source_sha1": "908e3b1d58256465d433549210c89afe3235c7fa",
+    "source_sha1": "16001fdb306fab4f93e55090558fe2e2319d6802",
     "workload": (256, 100, 10, 512),  # bodies, steps, checkpoint interval, elements per tile
-    "per_launch": {"element_fwd": 108.49e6, "particle_fwd": 29.74e6, "element_adj": 134.26e6,
-                   "particle_adj": 42.81e6},
+    "per_launch": {"element_fwd": 108.46e6, "particle_fwd": 29.75e6, "element_adj": 134.25e6,
+                   "particle_adj": 42.83e6},
 }
 
 
