@@ -299,7 +299,8 @@ def config_lines(W, log):
     """The other workloads: tiny cube (FP32 and FP64), 64 x 64 cloth, large blob, and
     the batch at 2048 bodies (working set beyond the 256 MB last-level cache), each as
     the two-pass graph path beside the plain one-launch-per-pass path (and the fused
-    path where every body fits one workgroup's LDS)."""
+    path where every body fits one workgroup's LDS; the tiny cube also with persistent
+    execution, FP32)."""
     import torch
     from paper_2104_02646_amd import gsim
     out = {}
@@ -307,7 +308,8 @@ def config_lines(W, log):
     tc = {"workload": "tiny cube: 162 tets, 64 particles, 100 steps, checkpoints every 10", "unit": "us per step "
           "(fwd + checkpointed adjoint of one gradient, divided by its steps)"}
     for dt, name in ((torch.float32, "f32"), (torch.float64, "f64")):
-        for ex, en in ((gsim.EXEC_GRAPH, "graph"), (gsim.EXEC_FUSED, "fused"), (gsim.EXEC_PLAIN, "plain")):
+        for ex, en in ((gsim.EXEC_GRAPH, "graph"), (gsim.EXEC_PERSIST, "persist"), (gsim.EXEC_FUSED, "fused"),
+                       (gsim.EXEC_PLAIN, "plain")):
             tc["%s_%s" % (name, en)] = try_line(cube, dt, 100, 10, ex)
     out["tiny_cube"] = tc
     log("configs: tiny cube done")

@@ -70,10 +70,16 @@ enum {
     GSIM_EXEC_PLAIN = 0,   /* two kernel launches per step (element pass, particle pass) */
     GSIM_EXEC_GRAPH = 1,   /* the same launches captured once into a hipGraph and replayed
                               (needs a non-default stream) */
-    GSIM_EXEC_FUSED = 2    /* one workgroup per body keeps the body in LDS and runs a whole
+    GSIM_EXEC_FUSED = 2,   /* one workgroup per body keeps the body in LDS and runs a whole
                               checkpoint segment of steps per launch (forward rollout: one
                               launch; backward: two launches per segment).  Needs every
                               body's particles to fit in LDS (36 B each for FP32) */
+    GSIM_EXEC_PERSIST = 3  /* one workgroup per body runs every step of a call's run of
+                              steps (a rollout: one launch; a backward: one launch) through
+                              the two-pass path's element and particle tiles, with workgroup
+                              barriers in place of launch boundaries: bitwise the two-pass
+                              results; for bodies of few tiles, whose steps are bound by
+                              launch latency.  FP32 models without lift/drag */
 };
 
 const char* gsim_last_error(void);

@@ -2,10 +2,11 @@
 
 ``tune_model`` chooses how a batch is planned and launched: the element-tile size of
 the two-pass path (elements per tile), the number of concurrent launch lanes, and the
-execution (two-pass launches replayed from a captured graph, or the fused path with
-one workgroup per body), by timing whole checkpointed gradient evaluations (rollout,
-loss, adjoint) of every candidate with HIP events on the launch stream; it returns
-the model built with the fastest configuration.
+execution (two-pass launches replayed from a captured graph, the fused path with one
+workgroup per LDS-resident body, or persistent execution of the two-pass tiles with one
+workgroup per body), by timing whole checkpointed gradient evaluations (rollout, loss,
+adjoint) of every candidate with HIP events on the launch stream; it returns the model
+built with the fastest configuration.
 
 ``tune`` chooses, for a given model, the launch shape of each pass: threads per
 workgroup (element passes: per planned element tile) and, for the particle passes,
@@ -188,10 +189,17 @@ def tune_model(bodies, dtype=torch.float32, max_steps=100, ckpt_every=10, reps=3
             del m
         except gsim.GsimError:
             pass  # a body does not fit one workgroup's LDS
+        try:
+            m = build(0, 1, gsim.EXEC_PERSIST)
+            results["persist"] = _gradient_ms(m, bodies, T, reps, stream)
+            del m
+        except gsim.GsimError:
+            pass  # FP64, or a body with lift/drag
     torch.cuda.synchronize()
     best = min(results, key=results.get)
-    if best == "fused":
-        choice = {"tile_elems": gsim.TILE_DEFAULT, "lanes": 1, "exec": gsim.EXEC_FUSED}
+    if best in ("fused", "persist"):
+        choice = {"tile_elems": gsim.TILE_DEFAULT, "lanes": 1,
+                  "exec": gsim.EXEC_FUSED if best == "fused" else gsim.EXEC_PERSIST}
     else:
         t, l, _ = best.split("/")
         choice = {"tile_elems": int(t[4:]), "lanes": int(l[5:]), "exec": gsim.EXEC_GRAPH}

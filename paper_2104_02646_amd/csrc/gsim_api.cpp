@@ -556,6 +556,8 @@ Layout make_layout(const gsim_plan* P, int max_steps) {
     L.f_gk = take(nt * sizeof(T));
     L.f_hpar = take(nh * sizeof(T));
     L.f_gh = take(nh * sizeof(T));
+    L.ntiles = take(sizeof(Tile) * (cap_e + cap_p));  // natural-order tiles (persistent execution)
+    L.toff = take(2 * (P->nb + 1) * 4);
     L.table_cap = 4 * (int64_t)max_steps + 8;
     L.table = take(sizeof(StepDev<T>) * L.table_cap);
     L.total = align_up(o, 256);
@@ -647,6 +649,22 @@ int upload_tiles(gsim_model* m, void* stream, UploadSink* sink = nullptr) {
     };
     HIP_TRY(up(m->ws + m->L.etiles, et.data(), et.size() * sizeof(Tile)), "upload tiles");
     HIP_TRY(up(m->ws + m->L.ptiles, pt.data(), pt.size() * sizeof(Tile)), "upload tiles");
+    // persistent execution: the natural-order tiles (element, then particle) and each
+    // body's ranges in them
+    {
+        std::vector<Tile> nat(m->etiles_nat);
+        nat.insert(nat.end(), m->ptiles_nat.begin(), m->ptiles_nat.end());
+        std::vector<int32_t> toff(2 * (m->nb + 1), 0);
+        for (const Tile& t : m->etiles_nat) toff[t.body + 1]++;
+        for (const Tile& t : m->ptiles_nat) toff[m->nb + 1 + t.body + 1]++;
+        for (int b = 0; b < m->nb; ++b) {
+            toff[b + 1] += toff[b];
+            toff[m->nb + 1 + b + 1] += toff[m->nb + 1 + b];
+        }
+        m->n_etiles_nat = (int)m->etiles_nat.size();
+        HIP_TRY(up(m->ws + m->L.ntiles, nat.data(), nat.size() * sizeof(Tile)), "upload tiles");
+        HIP_TRY(up(m->ws + m->L.toff, toff.data(), toff.size() * 4), "upload tiles");
+    }
     // body particle-tile ranges (contact / loss partial rows) depend on the tile size
     BodyDev<T>* bodies = reinterpret_cast<BodyDev<T>*>(m->bodies_host.data());
     int row = 0;
@@ -798,8 +816,27 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
                 return rc;
         return GSIM_OK;
     };
-    for (const Launch& l : seq) {
+    for (size_t li = 0; li < seq.size(); ++li) {
+        const Launch& l = seq[li];
         const StepDev<T>* sd = c.table + l.row;
+        if (m->exec == GSIM_EXEC_PERSIST && (l.op == OP_FWD || l.op == OP_ADJ)) {
+            // the run of forward / adjoint steps on consecutive rows: one launch
+            size_t lj = li + 1;
+            while (lj < seq.size() && (seq[lj].op == OP_FWD || seq[lj].op == OP_ADJ) &&
+                   seq[lj].row == seq[lj - 1].row + 1)
+                ++lj;
+            const Tile* nt = reinterpret_cast<const Tile*>(m->ws + m->L.ntiles);
+            const size_t lds = std::max(m->etile_words[0], m->etile_words[1]) * sizeof(T);
+            // the particle passes' block size, so each thread sums the same particles into
+            // the contact-gradient reduction as in the two-pass launches (element results do
+            // not depend on the block size)
+            LAUNCH_TRY(launch_persist<T>(md, sd, (int)(lj - li), nt, nt + m->n_etiles_nat,
+                                         reinterpret_cast<const int32_t*>(m->ws + m->L.toff), m->nb, m->pblock, lds,
+                                         stream),
+                       "persistent steps");
+            li = lj - 1;
+            continue;
+        }
         if (l.op == OP_FWD || l.op == OP_ADJ) {
             const bool adjoint = l.op == OP_ADJ;
             if (nl == 1) {
@@ -1102,6 +1139,7 @@ int do_step_backward(gsim_model* m, const gsim_params* p, gsim_state s, gsim_sta
     r.vbo = (T*)am.v;
     r.nsteps = 1;
     r.ckpt_every = m->K;
+    r.adj = 1;
     const int64_t r0 = region_misc(m);
     if ((rc = upload_rows<T>(m, r0, rows, stream))) return rc;
     if (m->exec == GSIM_EXEC_FUSED) {
@@ -1224,6 +1262,7 @@ int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, i
                 r.fbo = fbar + (q & 1) * 3 * np;  // this step hands step t-1 its adjoint force
             }
             if (q > 0) r.fb = fbar + ((q - 1) & 1) * 3 * np;
+            r.adj = 1;
             rows.push_back(r);
             seq.push_back({OP_ADJ, r0 + (int64_t)rows.size() - 1});
         }
@@ -1681,8 +1720,12 @@ int gsim_model_get_launch(const gsim_model* m, int pass, int* block, int* items)
 
 int gsim_model_set_exec(gsim_model* m, int exec, int block, int items) {
     if (!m) return fail(GSIM_E_INVALID, "NULL model");
-    if (exec != GSIM_EXEC_PLAIN && exec != GSIM_EXEC_GRAPH && exec != GSIM_EXEC_FUSED)
+    if (exec != GSIM_EXEC_PLAIN && exec != GSIM_EXEC_GRAPH && exec != GSIM_EXEC_FUSED && exec != GSIM_EXEC_PERSIST)
         return fail(GSIM_E_INVALID, "unknown exec %d", exec);
+    if (exec == GSIM_EXEC_PERSIST && m->any_air)
+        return fail(GSIM_E_UNSUPPORTED, "persistent execution does not model lift/drag (a body has air_on)");
+    if (exec == GSIM_EXEC_PERSIST && m->dtype != GSIM_F32)
+        return fail(GSIM_E_UNSUPPORTED, "persistent execution is FP32 only");
     if (exec == GSIM_EXEC_FUSED) {
         if (!m->fused_ok) return fail(GSIM_E_UNSUPPORTED, "fused execution: an element kind needs more than 128 colours");
         if (m->any_air) return fail(GSIM_E_UNSUPPORTED, "fused execution does not model lift/drag (a body has air_on)");
@@ -1723,6 +1766,7 @@ int gsim_model_get_exec(const gsim_model* m, int* exec, int* block, int* items) 
 int gsim_model_set_timing(gsim_model* m, int mask) {
     if (!m) return fail(GSIM_E_INVALID, "NULL model");
     if (mask < 0 || mask > 63) return fail(GSIM_E_INVALID, "timing mask must be in [0, 63]");
+    if (mask && m->exec == GSIM_EXEC_PERSIST) return fail(GSIM_E_UNSUPPORTED, "kernel timing needs plain execution");
     m->timing_mask = mask;
     return GSIM_OK;
 }

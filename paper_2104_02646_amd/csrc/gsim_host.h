@@ -67,6 +67,7 @@ struct Layout {
     // fused path: colour-ordered element records, colour bounds, body launch order
     size_t f_tet_idx, f_tet_dinv, f_tet_vol, f_tet_orig, f_tri_idx, f_tri_dinv, f_tri_area, f_tri_orig;
     size_t f_hin_idx, f_hin_phi0, f_hin_orig, coff, border, f_par, f_ktri, f_g, f_gk, f_hpar, f_gh;
+    size_t ntiles, toff;  // persistent execution: natural-order tiles, per-body ranges [2][nb + 1]
     size_t table;
     int64_t table_cap;
     size_t total;
@@ -119,6 +120,7 @@ struct gsim_model {
     int block = 256, items = 1;    // element passes: threads per element tile (items: unused, tiles are planned)
     int pblock = 256, pitems = 1;  // particle passes
     int n_etiles = 0, n_ptiles = 0;   // launched grid sizes (including XCD padding)
+    int n_etiles_nat = 0;             // natural-order element tiles (persistent execution)
     // launch lanes: with L > 1, the bodies are split into L groups of about equal
     // work whose passes run on L streams (the caller's and lane_stream[1 .. L-1])
     // between a fork and a join; lane l's tiles are [lane_e[l], lane_e[l + 1]) of

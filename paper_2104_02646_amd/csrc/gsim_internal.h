@@ -167,7 +167,7 @@ struct StepDev {
     int32_t ckpt_every;
     int32_t x_abs;     // x holds absolute positions (the caller's state), not displacements
     int32_t xo_abs;    // forward: write absolute positions to xo (the caller's state)
-    int32_t pad;
+    int32_t adj;       // the row is an adjoint step (read by persistent execution)
 };
 
 // Kernel timing: when a pair of events is armed, the next launch of the element and
@@ -196,6 +196,13 @@ int launch_part_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* til
                     bool air, void* stream);
 template <typename T>
 int launch_fill(T* p, int64_t n, T value, void* stream);
+// Persistent execution of steps rows[0 .. n_rows): workgroup b runs body b's element
+// tiles etiles[toff[b] .. toff[b + 1]) one after another, then its particle tiles
+// ptiles[toff[nb + 1 + b] .. toff[nb + 2 + b]), for every row in turn (forward, or
+// adjoint where row.adj is set); `lds` covers the largest element tile of either kind.
+template <typename T>
+int launch_persist(const ModelDev<T>* md, const StepDev<T>* rows, int n_rows, const Tile* etiles, const Tile* ptiles,
+                   const int32_t* toff, int n_bodies, int block, size_t lds, void* stream);
 // One workgroup per piece: the pieces' copies and zero fills in one launch (the serving
 // engine's query set-up, staged through one host-to-device copy).
 int launch_stage_copy(const StageSeg* segs, int n_segs, void* stream);

@@ -928,6 +928,38 @@ __global__ void __launch_bounds__(512) k_part_adj(const ModelDev<T>* __restrict_
     part_adj_tile<T, AIR>(md, sd, tiles[blockIdx.x]);
 }
 
+// Persistent execution: workgroup b runs body b through a run of steps.  Each step is
+// the body's element tiles one after another, then its particle tiles, where the
+// two-pass path has its launch boundaries there are device-scope fences and workgroup
+// barriers (the partials and states a pass writes are read by other threads of the
+// workgroup in the next).  The tiles, their partial slots and their contact rows are
+// those of the two-pass launches, so every result is bitwise the same; only the order
+// in which tiles run changes, and no result depends on it.
+template <typename T>
+__global__ void __launch_bounds__(512) k_persist(const ModelDev<T>* __restrict__ md, const StepDev<T>* __restrict__ rows,
+                                                  int n_rows, const Tile* __restrict__ etiles,
+                                                  const Tile* __restrict__ ptiles, const int32_t* __restrict__ toff) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int b = blockIdx.x, nb = gridDim.x;
+    const int e0 = toff[b], e1 = toff[b + 1], p0 = toff[nb + 1 + b], p1 = toff[nb + 2 + b];
+    for (int r = 0; r < n_rows; ++r) {
+        const StepDev<T>* sd = rows + r;  // tiles carry model 0: their record is sd[0]
+        const bool adj = sd->adj != 0;
+        for (int k = e0; k < e1; ++k) {
+            if (adj) elem_adj_tile<T, false>(md, sd, etiles[k], smem);
+            else elem_fwd_tile<T, false>(md, sd, etiles[k], smem);
+            __syncthreads();  // the next tile reuses the LDS
+        }
+        __syncthreads();  // (workgroup-scope release and acquire of global memory)
+        for (int k = p0; k < p1; ++k) {
+            if (adj) part_adj_tile<T, false>(md, sd, ptiles[k]);
+            else part_fwd_tile<T>(md, sd, ptiles[k]);
+            __syncthreads();  // the contact reduction's LDS
+        }
+        __syncthreads();  // (workgroup-scope release and acquire of global memory)
+    }
+}
+
 // Serving: the tile at launch position `pos` of a round's element or particle launch.
 // The round's tiles are the concatenation of its segments (each query's resident tiles,
 // segments in increasing order of their first position `begin`) laid out in XCD order:
@@ -1679,6 +1711,21 @@ int launch_part_adj(const ModelDev<T>* md, const StepDev<T>* sd, const Tile* til
         launch_timed(k_part_adj<T, false>, dim3(ntiles), dim3(block), 0, (hipStream_t)stream, md, sd, tiles);
     return check_launch();
 }
+template <typename T>
+int launch_persist(const ModelDev<T>* md, const StepDev<T>* rows, int n_rows, const Tile* etiles, const Tile* ptiles,
+                   const int32_t* toff, int n_bodies, int block, size_t lds, void* stream) {
+    if constexpr (std::is_same<T, double>::value) {
+        // FP32 only: with all four tile passes in one kernel the FP64 build spills
+        return (int)hipErrorNotSupported;
+    } else {
+        static size_t allowed = 48 * 1024;
+        if (n_rows <= 0 || n_bodies <= 0) return 0;
+        allow_lds(reinterpret_cast<const void*>(&k_persist<T>), lds, allowed);
+        hipLaunchKernelGGL(k_persist<T>, dim3(n_bodies), dim3(block), lds, (hipStream_t)stream, md, rows, n_rows,
+                           etiles, ptiles, toff);
+        return check_launch();
+    }
+}
 int launch_stage_copy(const StageSeg* segs, int n_segs, void* stream) {
     if (n_segs <= 0) return 0;
     hipLaunchKernelGGL(k_stage_copy, dim3(n_segs), dim3(256), 0, (hipStream_t)stream, segs);
@@ -1784,6 +1831,8 @@ int launch_fused_grads(const ModelDev<T>* md, const StepDev<T>* sd, void* stream
     template int launch_elem_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, size_t, bool, void*); \
     template int launch_part_adj<T>(const ModelDev<T>*, const StepDev<T>*, const Tile*, int, int, int, bool, void*); \
     template int launch_fill<T>(T*, int64_t, T, void*);                                                             \
+    template int launch_persist<T>(const ModelDev<T>*, const StepDev<T>*, int, const Tile*, const Tile*, const int32_t*, \
+                                   int, int, size_t, void*);                                                        \
     template int launch_mixed<T>(const ModelDev<T>*, const StepDev<T>*, const TileSeg*, int, int, int, const TileSeg*, \
                                  int, int, int, int, int, size_t, void*);                                           \
     template int launch_contact_reduce<T>(const ModelDev<T>*, const StepDev<T>*, int, void*);                       \

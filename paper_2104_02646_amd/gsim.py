@@ -25,7 +25,7 @@ LIB_PATH = os.environ.get("GSIM_LIB") or os.path.join(HERE, "libgsim.so")
 
 GSIM_OK, GSIM_E_INVALID, GSIM_E_TOPOLOGY, GSIM_E_DEGENERATE = 0, -1, -2, -3
 GSIM_E_WORKSPACE, GSIM_E_HIP, GSIM_E_NONFINITE, GSIM_E_UNSUPPORTED = -4, -5, -6, -7
-EXEC_PLAIN, EXEC_GRAPH, EXEC_FUSED = 0, 1, 2
+EXEC_PLAIN, EXEC_GRAPH, EXEC_FUSED, EXEC_PERSIST = 0, 1, 2, 3
 FLAG_NONFINITE, FLAG_INVERTED = 1, 2
 TILE_DEFAULT = 256
 
