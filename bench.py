@@ -104,10 +104,10 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
 # (of gsim_kernels.hip followed by gsim_device.h) and 512-element tiles only; for any other
 # source or tile size the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "source_sha1": "16001fdb306fab4f93e55090558fe2e2319d6802",
+    "source_sha1": "33fa957de4ea536f4215e7bcebf7e392c2e8fe40",
     "workload": (256, 100, 10, 512),  # bodies, steps, checkpoint interval, elements per tile
-    "per_launch": {"element_fwd": 108.46e6, "particle_fwd": 29.75e6, "element_adj": 134.25e6,
-                   "particle_adj": 42.83e6},
+    "per_launch": {"element_fwd": 108.49e6, "particle_fwd": 29.74e6, "element_adj": 134.26e6,
+                   "particle_adj": 42.81e6},
 }
 
 
@@ -603,8 +603,8 @@ def raster_bench(reps=20, H=256, W=256):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--bodies", type=int, default=256)
     ap.add_argument("--sim-steps", type=int, default=100)
     ap.add_argument("--ckpt-every", type=int, default=10)
