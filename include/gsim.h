@@ -553,6 +553,19 @@ int gsim_engine_set_store_limit(gsim_engine* engine, size_t bytes);
  * pool.  A query that goes non-finite while it runs completes with status
  * GSIM_E_NONFINITE in its gsim_result and frees its slot like any other. */
 int gsim_engine_submit(gsim_engine* engine, const gsim_query* query, int64_t* id);
+/* gsim_engine_submit in two parts, so that the host work of a query (validation as
+ * above, planning, copying its inputs: about a millisecond for 10^4 elements) can run
+ * off the thread that drives the engine.  gsim_engine_prepare touches no engine state
+ * and may run on several threads at once; it returns an owned handle (its submit time
+ * is the call's start).  gsim_engine_submit_prepared takes ownership of the handle in
+ * every case, decides the query's checkpointing (gsim_engine_set_store_limit), checks
+ * that it can fit the pool (GSIM_E_WORKSPACE) and queues it.  The engine's own calls
+ * (submit, submit_prepared, tick, poll, the setters, stats, destroy) are made from one
+ * thread at a time.  gsim_prepared_destroy frees a handle that is not submitted. */
+typedef struct gsim_prepared gsim_prepared;
+int gsim_engine_prepare(const gsim_query* query, gsim_prepared** out);
+int gsim_engine_submit_prepared(gsim_engine* engine, gsim_prepared* prepared, int64_t* id);
+int gsim_prepared_destroy(gsim_prepared* prepared);
 /* Admits what fits (the admitted queries' set-up copies move as one staged batch),
  * then runs the set number of micro-step rounds: in each, one micro-step of every live
  * query, the forward and adjoint micro-steps of all queries in one element launch and

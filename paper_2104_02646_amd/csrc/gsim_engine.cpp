@@ -824,8 +824,10 @@ int gsim_engine_query_bytes(const gsim_query* q, size_t* bytes) {
     return GSIM_OK;
 }
 
-int gsim_engine_submit(gsim_engine* E, const gsim_query* in, int64_t* id) {
-    if (!E || !in || !in->desc) return fail(GSIM_E_INVALID, "NULL argument");
+int gsim_engine_prepare(const gsim_query* in, gsim_prepared** out) {
+    if (!in || !in->desc || !out) return fail(GSIM_E_INVALID, "NULL argument");
+    *out = nullptr;
+    const double t_arrive = now_s();
     const gsim_model_desc* d = in->desc;
     if (d->dtype != GSIM_F32 || d->n_bodies != 1) return fail(GSIM_E_UNSUPPORTED, "queries are single FP32 bodies");
     if (d->air_on && d->air_on[0]) return fail(GSIM_E_UNSUPPORTED, "queries do not model lift/drag");
@@ -871,13 +873,7 @@ int gsim_engine_submit(gsim_engine* E, const gsim_query* in, int64_t* id) {
         q->np = P->np;
         q->ne = P->ne;
         q->nt = P->nt;
-        if (q->K > 1 && E->store_limit > 0) {  // every state stored when it fits the limit
-            const QLayout all = qlayout(P, q->T, 1);
-            if (all.total <= E->store_limit) q->K = 1;
-        }
         q->lay = qlayout(P, q->T, q->K);
-        if (q->lay.total > E->pool.size)
-            return fail(GSIM_E_WORKSPACE, "query needs %zu bytes, the pool has %zu", q->lay.total, E->pool.size);
         auto cp = [](std::vector<float>& v, const float* src, int64_t n) { v.assign(src, src + n); };
         if (q->ne) {
             cp(q->mu, in->mu, q->ne);
@@ -895,14 +891,46 @@ int gsim_engine_submit(gsim_engine* E, const gsim_query* in, int64_t* id) {
         q->o_ktri = in->out_k_tri;
         q->o_mass = in->out_mass;
         q->o_contact = in->out_contact;
+        q->t_submit = t_arrive;
+        *out = reinterpret_cast<gsim_prepared*>(q.release());
+    } catch (const std::bad_alloc&) {
+        return fail(GSIM_E_INVALID, "out of host memory");
+    }
+    return GSIM_OK;
+}
+
+int gsim_engine_submit_prepared(gsim_engine* E, gsim_prepared* prep, int64_t* id) {
+    if (!E || !prep) return fail(GSIM_E_INVALID, "NULL argument");
+    std::unique_ptr<Query> q(reinterpret_cast<Query*>(prep));  // owned from here on, queued or not
+    try {
+        if (q->K > 1 && E->store_limit > 0) {  // every state stored when it fits the limit
+            const QLayout all = qlayout(q->plan.get(), q->T, 1);
+            if (all.total <= E->store_limit) {
+                q->K = 1;
+                q->lay = all;
+            }
+        }
+        if (q->lay.total > E->pool.size)
+            return fail(GSIM_E_WORKSPACE, "query needs %zu bytes, the pool has %zu", q->lay.total, E->pool.size);
         q->id = E->next_id++;
-        q->t_submit = now_s();
         if (id) *id = q->id;
         E->queue.push_back(std::move(q));
     } catch (const std::bad_alloc&) {
         return fail(GSIM_E_INVALID, "out of host memory");
     }
     return GSIM_OK;
+}
+
+int gsim_prepared_destroy(gsim_prepared* prep) {
+    delete reinterpret_cast<Query*>(prep);
+    return GSIM_OK;
+}
+
+int gsim_engine_submit(gsim_engine* E, const gsim_query* in, int64_t* id) {
+    if (!E) return fail(GSIM_E_INVALID, "NULL engine");
+    gsim_prepared* prep = nullptr;
+    if (int rc = gsim_engine_prepare(in, &prep)) return rc;
+    return gsim_engine_submit_prepared(E, prep, id);
 }
 
 int gsim_engine_tick(gsim_engine* E, int* n_live, int* n_queued) {

@@ -43,7 +43,8 @@ ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan
                "gsim_raster_backward",
                "gsim_engine_create", "gsim_engine_destroy", "gsim_engine_query_bytes", "gsim_engine_submit",
                "gsim_engine_tick", "gsim_engine_poll", "gsim_engine_stats", "gsim_engine_set_micro_steps",
-               "gsim_engine_set_store_limit")
+               "gsim_engine_set_store_limit", "gsim_engine_prepare", "gsim_engine_submit_prepared",
+               "gsim_prepared_destroy")
 GSIM_F32, GSIM_F64 = 32, 64
 KERNELS = ("element_fwd", "particle_fwd", "element_adj", "particle_adj", "fused_fwd", "fused_adj")
 

@@ -44,6 +44,9 @@ def _load():
         lib.gsim_engine_destroy.argtypes = [vp]
         lib.gsim_engine_query_bytes.argtypes = [C.POINTER(_Query), C.POINTER(C.c_size_t)]
         lib.gsim_engine_submit.argtypes = [vp, C.POINTER(_Query), C.POINTER(C.c_int64)]
+        lib.gsim_engine_prepare.argtypes = [C.POINTER(_Query), C.POINTER(vp)]
+        lib.gsim_engine_submit_prepared.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+        lib.gsim_prepared_destroy.argtypes = [vp]
         lib.gsim_engine_tick.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         lib.gsim_engine_poll.argtypes = [vp, C.POINTER(_Result), C.c_int, C.POINTER(C.c_int)]
         lib.gsim_engine_set_micro_steps.argtypes = [vp, C.c_int]
@@ -132,6 +135,20 @@ class Engine:
         self.pending[i.value] = qb
         return i.value
 
+    @staticmethod
+    def prepare(qb: QueryBuffers):
+        """gsim_engine_prepare: the query's host work, on any thread (ctypes releases the
+        GIL for the call); returns the handle for submit_prepared."""
+        h = C.c_void_p()
+        _check(_load().gsim_engine_prepare(C.byref(qb.q), C.byref(h)))
+        return h
+
+    def submit_prepared(self, qb: QueryBuffers, handle) -> int:
+        i = C.c_int64()
+        _check(_load().gsim_engine_submit_prepared(self._h, handle, C.byref(i)))
+        self.pending[i.value] = qb
+        return i.value
+
     def set_store_limit(self, nbytes):
         """Queries whose every-state footprint is at most nbytes store every state
         (gsim_engine_set_store_limit; 0: every query keeps its own interval)."""
@@ -194,12 +211,19 @@ def solve_alone(qb: QueryBuffers, block=256, device="cuda"):
     return float(loss[0]), {k: v.detach().cpu().numpy().reshape(-1) for k, v in g.items()}
 
 
-def replay_trace(trace, bodies, engine: Engine, ckpt_every=10, time_scale=1.0, log=None):
-    """Real-time replay: query i is submitted at its arrival time (seconds from the
-    start, scaled); the engine ticks continuously.  Returns per-query latency
-    (completion - arrival) and the engine's statistics."""
+def replay_trace(trace, bodies, engine: Engine, ckpt_every=10, time_scale=1.0, log=None, prep_workers=4):
+    """Real-time replay: query i arrives at its arrival time (seconds from the start,
+    scaled); the engine ticks continuously on this thread.  With prep_workers > 0 an
+    arrived query's host work (gsim_engine_prepare) runs on a pool of that many worker
+    threads while the engine keeps ticking, and prepared queries are submitted in
+    arrival order; with 0 each is submitted whole on this thread.  Returns per-query
+    latency (completion - arrival), the wall time and the query buffers."""
+    import collections
+    from concurrent.futures import ThreadPoolExecutor
     qbs = [QueryBuffers(b, q.steps, ckpt_every) for q, b in zip(trace, bodies)]
     arrivals = np.array([q.arrival for q in trace]) * time_scale
+    pool = ThreadPoolExecutor(prep_workers) if prep_workers > 0 else None
+    preparing = collections.deque()  # (index, future) in arrival order
     t0 = time.perf_counter()
     nxt = 0
     lat = {}
@@ -209,18 +233,26 @@ def replay_trace(trace, bodies, engine: Engine, ckpt_every=10, time_scale=1.0, l
     while len(lat) < n:
         now = time.perf_counter() - t0
         while nxt < n and arrivals[nxt] <= now:
-            id2idx[engine.submit(qbs[nxt])] = nxt
+            if pool is None:
+                id2idx[engine.submit(qbs[nxt])] = nxt
+            else:
+                preparing.append((nxt, pool.submit(Engine.prepare, qbs[nxt])))
             nxt += 1
+        while preparing and preparing[0][1].done():
+            i, fut = preparing.popleft()
+            id2idx[engine.submit_prepared(qbs[i], fut.result())] = i
         nl, nq = engine.tick()
         for qid, qb, ts, ta, td in engine.poll():
             i = id2idx[qid]
             lat[i] = (time.perf_counter() - t0) - arrivals[i]
-        if nl == 0 and nq == 0 and nxt < n:
+        if nl == 0 and nq == 0 and nxt < n and not preparing:
             time.sleep(max(0.0, min(0.001, arrivals[nxt] - (time.perf_counter() - t0))))
         if log and len(lat) >= logged + 200:
             logged = len(lat)
             log("served %d/%d" % (len(lat), n))
     wall = time.perf_counter() - t0
+    if pool is not None:
+        pool.shutdown()
     return np.array([lat[i] for i in range(n)]), wall, qbs
 
 

@@ -194,3 +194,40 @@ def test_more_segments_than_one_lookup_holds(sv):
         assert np.float32(loss) == np.float32(qb.loss)
         for k in ("mu", "lam", "mass", "contact"):
             assert np.array_equal(g[k], qb.out[k]), k
+
+
+def test_prepared_on_threads_equals_submit(sv):
+    """Queries prepared concurrently on worker threads (gsim_engine_prepare) and then
+    submitted in order: bitwise the answers of plain submission; a handle that is not
+    submitted is freed; a query that cannot fit is refused at submission (the handle is
+    consumed either way)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2104_02646_amd import gsim
+    qs = mixed_queries()
+    ref = [sv.QueryBuffers(b, T, K) for b, T, K in qs]
+    eng = sv.Engine(pool_bytes=1 << 30, max_live=16)
+    for qb in ref:
+        eng.submit(qb)
+    eng.run_until_idle()
+    qbs = [sv.QueryBuffers(b, T, K) for b, T, K in qs]
+    with ThreadPoolExecutor(4) as pool:
+        handles = list(pool.map(sv.Engine.prepare, qbs))
+    eng2 = sv.Engine(pool_bytes=1 << 30, max_live=16)
+    for qb, h in zip(qbs, handles):
+        eng2.submit_prepared(qb, h)
+    eng2.run_until_idle()
+    for a, b in zip(ref, qbs):
+        assert a.status == 0 and b.status == 0
+        assert np.float32(a.loss) == np.float32(b.loss)
+        for k in a.out:
+            assert np.array_equal(a.out[k], b.out[k]), k
+    spare = sv.Engine.prepare(qbs[0])
+    sv._load().gsim_prepared_destroy(spare)
+    big = W.batch_body(52000, lo=4000, hi=4000)
+    big.target = W.synthetic_target(big, 1)
+    qb = sv.QueryBuffers(big, 100, 10)
+    small = sv.Engine(pool_bytes=qb.bytes() // 2 + _table_bytes(sv, 4, 1 << 14), max_live=4, max_tiles=1 << 14)
+    small.set_store_limit(0)
+    with pytest.raises(gsim.GsimError) as ei:
+        small.submit_prepared(qb, sv.Engine.prepare(qb))
+    assert ei.value.code == gsim.GSIM_E_WORKSPACE
