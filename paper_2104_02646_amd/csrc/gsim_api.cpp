@@ -531,6 +531,7 @@ Layout make_layout(const gsim_plan* P, int max_steps) {
     L.rgap = take(np * sizeof(T));
     L.bflag = take(2 * (size_t)P->nb * 4);
     L.slots = take(4 * std::max<int64_t>(P->nslot, 1) * sizeof(T));
+    L.fslots = take(3 * std::max<int64_t>(P->nslot, 1) * sizeof(T));
     L.vslots = P->any_air ? take(4 * std::max<int64_t>(P->nslot, 1) * sizeof(T)) : 0;
     L.cpart = take(4 * (cap_p + 1) * sizeof(T));
     L.lpart = take((cap_p + 1) * sizeof(T));
@@ -1475,6 +1476,7 @@ int model_init(const gsim_plan* P, int max_steps, int K, void* d_ws, size_t byte
     M.bflag = (int32_t*)(ws + L.bflag);
     M.bodies = (const BodyDev<T>*)(ws + L.bodies);
     M.slots = (T*)(ws + L.slots);
+    M.fslots = (T*)(ws + L.fslots);
     M.vslots = P->any_air ? (T*)(ws + L.vslots) : nullptr;
     M.cpart = (T*)(ws + L.cpart);
     M.lpart = (T*)(ws + L.lpart);

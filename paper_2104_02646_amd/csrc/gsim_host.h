@@ -59,7 +59,7 @@ struct Layout {
     size_t tri_code, tri_dinv, tri_area;
     size_t hin_code, hin_phi0;
     size_t tp;
-    size_t gbase, pdeg, pinned, slots, vslots, cpart, lpart;  // vslots: only when a body has air
+    size_t gbase, pdeg, pinned, slots, fslots, vslots, cpart, lpart;  // vslots: only when a body has air
     size_t rest, rgap;  // rest positions [3][np], rest ground gaps [np]
     size_t bflag;       // [nb][2] int32 body status words
     size_t fbuf, abuf;  // forward / adjoint internal ping-pong states

@@ -100,7 +100,8 @@ struct ModelDev {
     const BodyDev<T>* bodies;
     int32_t* bflag;  // [n_bodies][2] status words, set to 1 by the kernels: [0] a state or
                      // adjoint value stopped being finite, [1] a tet inverted (J <= 0)
-    T* slots;   // [nslot][4] per-(tile, particle) partial sums
+    T* slots;   // [nslot][4] per-(tile, particle) partial sums of the adjoint passes
+    T* fslots;  // [nslot][3] per-(tile, particle) forces of the forward passes
     T* vslots;  // [nslot][4] velocity-adjoint partials of air tiles (null when no body has air)
     T* cpart;   // [n_ptiles][4] contact-gradient partial sums
     T* lpart;   // [n_ptiles] loss partial sums

@@ -17,8 +17,8 @@
 // lambda, k) are accumulated by their element's thread; per-body contact
 // gradients go through a per-tile partial buffer reduced in fixed order.
 //
-// All state arrays are SoA [3][n]; element records SoA over elements; slots AoS
-// [nslot][4] so one corner is one 16-byte (FP32) access.  The kernels are
+// All state arrays are SoA [3][n]; element records SoA over elements; partial slots
+// AoS: forward [nslot][3] (12 bytes), adjoint [nslot][4] (one 16-byte FP32 access).  The kernels are
 // templated on the scalar type: float for production, double for checking the
 // algorithm against the FP64 oracle independently of FP32 rounding.
 #include <hip/hip_ext.h>
@@ -55,6 +55,26 @@ __device__ __forceinline__ void ld_slot(const double* s, int64_t k, double& a, d
     const __attribute__((address_space(1))) gd2* p = (const __attribute__((address_space(1))) gd2*)(s + 4 * k);
     const gd2 q0 = p[0], q1 = p[1];
     a = q0.x; b = q0.y; c = q1.x; d = q1.y;
+}
+
+// Forward partials are 3-vectors, 12 (FP32) or 24 (FP64) bytes a slot (the adjoint's
+// carry a fourth value and keep 4-vector slots of their own).
+__device__ __forceinline__ void st_fslot(float* s, int64_t k, float a, float b, float c) {
+    __attribute__((address_space(1))) float* p = (__attribute__((address_space(1))) float*)(s + 3 * k);
+    p[0] = a;
+    p[1] = b;
+    p[2] = c;
+}
+__device__ __forceinline__ void st_fslot(double* s, int64_t k, double a, double b, double c) {
+    __attribute__((address_space(1))) double* p = (__attribute__((address_space(1))) double*)(s + 3 * k);
+    p[0] = a;
+    p[1] = b;
+    p[2] = c;
+}
+template <typename T>
+__device__ __forceinline__ V3<T> ld_fslot(const T* s, int64_t k) {
+    const __attribute__((address_space(1))) T* p = (const __attribute__((address_space(1))) T*)(s + 3 * k);
+    return mk3(p[0], p[1], p[2]);
 }
 
 // w = 1/m, 0 for pinned particles.  The mass is loaded whether or not the particle
@@ -122,6 +142,20 @@ __device__ __forceinline__ void sum_slots(const T* slots, int64_t base, int32_t 
         f += mk3(a, b, c);
         d += e;
     }
+}
+
+// Sum, in slot order, of a particle's deg forward partials at base, base + 64, ...
+// (the first SLOT_BATCH fetched before any is used, as in sum_slots).
+template <typename T>
+__device__ __forceinline__ void sum_fslots(const T* slots, int64_t base, int32_t deg, V3<T>& f) {
+    V3<T> q[SLOT_BATCH];
+#pragma unroll
+    for (int k = 0; k < SLOT_BATCH; ++k)
+        if (k < deg) q[k] = ld_fslot(slots, base + 64 * k);
+#pragma unroll
+    for (int k = 0; k < SLOT_BATCH; ++k)
+        if (k < deg) f += q[k];
+    for (int32_t k = SLOT_BATCH; k < deg; ++k) f += ld_fslot(slots, base + 64 * k);
 }
 
 // ---------------------------------------------------------- tet (NH) ---
@@ -639,7 +673,7 @@ __device__ __forceinline__ void elem_fwd_tile(const ModelDev<T>* __restrict__ md
         const int r0 = r.y & 0xffff, rn = r.y >> 16;
         V3<T> f = zero3<T>();
         for (int k = 0; k < rn; ++k) f += v3(cs[r0 + k]);
-        st_slot(M.slots, r.z, f.x, f.y, f.z, T(0));
+        st_fslot(M.fslots, r.z, f.x, f.y, f.z);
     }
 }
 
@@ -677,8 +711,7 @@ __device__ __forceinline__ void part_fwd_tile(const ModelDev<T>* __restrict__ md
         const T rg = contact ? gld(M.rgap, i) : T(0);
         const T w = inv_mass(M, S, i);
         V3<T> f = zero3<T>();
-        T unused = T(0);
-        sum_slots(M.slots, gb + (li & 63), deg, f, unused);
+        sum_fslots(M.fslots, gb + (li & 63), deg, f);
         if (S.ckx) {
             st3(S.ckx, np, i, u);
             st3(S.ckv, np, i, v);
