@@ -66,17 +66,17 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
       element pass, per tet: corner codes 16, D_m^-1 36, volume 4, mu + lambda 8
         (adjoint: + mu-bar, lambda-bar read-modify-write 16); per tile particle:
         record (index, run, partial slot) 12, positions 12 (adjoint: + the adjoint force
-        12), partial write 16;
+        12), partial write 12 (adjoint: 16);
       particle pass, per particle: partial count 4, x, v 24, mass 4, pinned 1, writes
         24 (adjoint: xbar+, vbar+ 24, x, v 24, mass 4, pinned 1, partial count 4,
-        writes 24, mass-bar read-modify-write 8); per partial: 16; checkpoint stores
-        24 per particle per segment."""
+        writes 24, mass-bar read-modify-write 8); per partial: 12 (adjoint: 16);
+        checkpoint stores 24 per particle per segment."""
     nseg = -(-T // K)
     fwd_passes = T + (T - nseg)  # rollout + segment recompute
     if kernel == "element_fwd":
-        return fwd_passes * (64 * ne + 40 * ntp)
+        return fwd_passes * (64 * ne + 36 * ntp)
     if kernel == "particle_fwd":
-        return fwd_passes * (57 * np_ + 16 * ntp) + nseg * 24 * np_
+        return fwd_passes * (57 * np_ + 12 * ntp) + nseg * 24 * np_
     if kernel == "element_adj":
         # adjoint force handed over by the previous particle adjoint: x and fbar (24)
         # per tile particle, except for the first adjoint step (x, xbar+, vbar+, mass,

@@ -1,7 +1,7 @@
 """Host-side checks of bench.py's accounting (no GPU).
 
 The compulsory bytes per launch follow the per-unit figures of the kernels (64 B per
-tet and 40 B per tile particle in the forward element pass, ...), recomputed here by
+tet and 36 B per tile particle in the forward element pass, ...), recomputed here by
 hand for the 256-body batch; measured HBM traffic is reported only for the kernel
 source it was taken with; more than one GPU is refused with a message.
 """
@@ -21,7 +21,7 @@ NE, NP, NTP = 1367346, 307196, 676018  # the 256-body batch: tets, particles, ti
 def test_kernel_bytes_per_unit():
     # one pass over one tet / one particle / one tile particle (T = K = 1: one forward pass)
     assert bench.kernel_bytes("element_fwd", 1, 0, 0, 1, 1) == 64
-    assert bench.kernel_bytes("element_fwd", 0, 0, 1, 1, 1) == 40
+    assert bench.kernel_bytes("element_fwd", 0, 0, 1, 1, 1) == 36
     assert bench.kernel_bytes("element_adj", 1, 0, 0, 1, 1) == 80
     assert bench.kernel_bytes("element_adj", 0, 0, 1, 1, 1) == 69
     assert bench.kernel_bytes("particle_adj", 0, 1, 0, 1, 1) == 89
@@ -34,7 +34,7 @@ def test_batch_bytes_per_launch():
     fwd_launches = T + (T - T // K)  # rollout + recompute of 9 of every 10 steps
     assert fwd_launches == 190
     per = bench.kernel_bytes("element_fwd", NE, NP, NTP, T, K) / fwd_launches
-    assert per == 64 * NE + 40 * NTP == 114550864
+    assert per == 64 * NE + 36 * NTP == 111846792
     # the first adjoint step stages the adjoint state (41 B per tile particle), the others
     # the adjoint force the previous particle adjoint stored (24 B)
     per_adj = bench.kernel_bytes("element_adj", NE, NP, NTP, T, K)
