@@ -484,11 +484,15 @@ int gsim_raster_forward_noalloc(int dtype, int64_t n_verts, int64_t n_tris, cons
 /* ------------------------------------------------------------------------ */
 /* SERVING ENGINE: continuous batching of rollout-gradient queries           */
 /* ------------------------------------------------------------------------ */
-/* A query is one FP32 body (n_bodies == 1) with parameters, start state and
- * target; its answer is the loss of its final positions (gsim_loss_mse) and
- * the gradients of that loss, exactly as gsim_rollout + gsim_loss_mse +
- * gsim_rollout_backward would compute them on a model of its own (bit for bit:
- * a query's arithmetic does not depend on the other queries in flight).
+/* A query is one gradient evaluation of the physical-parameter estimation task
+ * (Sec. 5.1 "Physical parameter estimation": a loss on the simulated trajectory,
+ * minimised over the body's physical parameters by gradient descent through the
+ * simulator): one FP32 body
+ * (n_bodies == 1) with parameters, start state and target; its answer is the loss
+ * of its final positions (gsim_loss_mse) and the gradients of that loss, exactly
+ * as gsim_rollout + gsim_loss_mse + gsim_rollout_backward would compute them on a
+ * model of its own (bit for bit: a query's arithmetic does not depend on the other
+ * queries in flight).
  *
  * The engine carves every admitted query's device buffers out of one
  * caller-owned pool (first fit), admits queued queries in FIFO order as pool
