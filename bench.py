@@ -610,7 +610,7 @@ def main():
     ap.add_argument("--ckpt-every", type=int, default=10)
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (tile size, lanes, execution, pass shapes) and use the flags below")
-    ap.add_argument("--exec", choices=("fused", "graph", "plain"), default="graph")
+    ap.add_argument("--exec", choices=("fused", "graph", "plain", "persist"), default="graph")
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--items", type=int, default=1)
     ap.add_argument("--lanes", type=int, default=3, help="concurrent launch lanes of the two-pass path (1..4)")
@@ -666,7 +666,8 @@ def main():
     with torch.cuda.stream(stream):
         if args.no_tune:
             model = gsim.Model(bodies, torch.float32, max_steps=T, ckpt_every=K, device=dev, tile_elems=args.tile)
-            exec_mode = {"fused": gsim.EXEC_FUSED, "graph": gsim.EXEC_GRAPH, "plain": gsim.EXEC_PLAIN}[args.exec]
+            exec_mode = {"fused": gsim.EXEC_FUSED, "graph": gsim.EXEC_GRAPH, "plain": gsim.EXEC_PLAIN,
+                         "persist": gsim.EXEC_PERSIST}[args.exec]
             model.set_exec(exec_mode, args.block, args.items)
             model.set_lanes(args.lanes)
         else:
@@ -687,7 +688,8 @@ def main():
     stream.synchronize()
     t_plan = time.perf_counter() - t_plan - t_tune
     exec_mode, block, items = model.get_exec()
-    args.exec = {gsim.EXEC_FUSED: "fused", gsim.EXEC_GRAPH: "graph", gsim.EXEC_PLAIN: "plain"}[exec_mode]
+    args.exec = {gsim.EXEC_FUSED: "fused", gsim.EXEC_GRAPH: "graph", gsim.EXEC_PLAIN: "plain",
+                 gsim.EXEC_PERSIST: "persist"}[exec_mode]
     args.block, args.items, args.lanes = block, items, model.get_lanes()
     tile_elems = model.plan.tile_elems or gsim.TILE_DEFAULT
     ntp = len(gsim.Plan(bodies, tile_elems=tile_elems).tiles()[1])  # tile particles of the element tiles
