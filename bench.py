@@ -104,10 +104,10 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
 # (of gsim_kernels.hip followed by gsim_device.h) and 512-element tiles only; for any other
 # source or tile size the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "source_sha1": "f862480b6f68ca2c11534af75dc94a8a3f965396",
+    "source_sha1": "c43f820ec3c699ab52d932e5a1fbc45776d38872",
     "workload": (256, 100, 10, 512),  # bodies, steps, checkpoint interval, elements per tile
-    "per_launch": {"element_fwd": 106.19e6, "particle_fwd": 27.37e6, "element_adj": 134.26e6,
-                   "particle_adj": 42.82e6},
+    "per_launch": {"element_fwd": 106.20e6, "particle_fwd": 27.54e6, "element_adj": 134.23e6,
+                   "particle_adj": 42.76e6},
 }
 
 

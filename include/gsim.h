@@ -206,6 +206,19 @@ int gsim_model_get_launch(const gsim_model* model, int pass, int* block, int* it
 int gsim_model_set_lanes(gsim_model* model, int lanes);
 int gsim_model_get_lanes(const gsim_model* model, int* lanes);
 
+/* Overlapped recompute in gsim_rollout_backward (the checkpointed reverse pass of
+ * App. A.2: every segment's states are recomputed from its checkpoint before its
+ * adjoint steps).  The recompute of segment s - 1 needs only its own checkpoint,
+ * so it can run beside the adjoint steps of segment s: with a second segment buffer
+ * d_segment2 of at least max(ckpt_every - 1, 1) states (6 n_particles values each,
+ * caller-owned device memory that must outlive its use), the two passes share each
+ * element launch and each particle launch, and consecutive segments alternate
+ * between the two buffers.  Applies under GSIM_EXEC_PLAIN and GSIM_EXEC_GRAPH, with
+ * kernel timing off, for models without lift/drag; otherwise, and with d_segment2 =
+ * NULL (the default), the passes run one after another.  Results are bitwise the same
+ * either way.  GSIM_E_WORKSPACE when `bytes` is too small. */
+int gsim_model_set_overlap(gsim_model* model, void* d_segment2, size_t bytes);
+
 /* Kernel timing for measurement: with bit k of `mask` set, every launch of
  * kernel k is bracketed by HIP events on its stream (k: 0 element pass,
  * 1 particle pass, 2 element adjoint pass, 3 particle adjoint pass, 4 fused

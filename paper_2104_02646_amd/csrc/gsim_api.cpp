@@ -722,7 +722,8 @@ enum Op : int {
     OP_FUSED_ADJ = 6,    // whole segment of adjoint steps, one workgroup per body
     OP_FUSED_PARAMS = 7, // parameters into colour order (and colour-ordered gradient clear)
     OP_FUSED_GRADS = 8,  // colour-ordered gradients back to element order
-    OP_FUSED_ADJ_ACT = 9 // OP_FUSED_ADJ that also accumulates actuation gradients
+    OP_FUSED_ADJ_ACT = 9, // OP_FUSED_ADJ that also accumulates actuation gradients
+    OP_DUAL = 10          // adjoint pass of `row` and forward pass of `row2` in the same launches
 };
 
 template <typename T>
@@ -732,6 +733,7 @@ size_t fused_lds(const gsim_model* m, bool adjoint) {
 struct Launch {
     int op;
     int64_t row;
+    int64_t row2 = 0;  // OP_DUAL: the forward pass's row
 };
 
 hipError_t take_event(gsim_model* m, hipEvent_t* e) {
@@ -817,9 +819,37 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
                 return rc;
         return GSIM_OK;
     };
+    // adjoint pass of row sd_a and forward pass of row sd_f, element launch then particle
+    // launch, over lane l's tiles (l < 0: every tile, one pair of launches); models
+    // without lift/drag only
+    auto dual = [&](int l, const StepDev<T>* sd_a, const StepDev<T>* sd_f) -> int {
+        const int e0 = l < 0 ? 0 : m->lane_e[l], e1 = l < 0 ? m->n_etiles : m->lane_e[l + 1];
+        const int p0 = l < 0 ? 0 : m->lane_p[l], p1 = l < 0 ? m->n_ptiles : m->lane_p[l + 1];
+        void* st = l > 0 ? (void*)m->lane_stream[l] : stream;
+        const size_t lds = std::max(m->etile_words[0], m->etile_words[1]) * sizeof(T);
+        LAUNCH_TRY(launch_dual<T>(md, sd_a, sd_f, c.et + e0, e1 - e0, c.pt + p0, p1 - p0, m->block, m->pblock, lds,
+                                  false, st), "overlapped element passes");
+        LAUNCH_TRY(launch_dual<T>(md, sd_a, sd_f, c.et + e0, e1 - e0, c.pt + p0, p1 - p0, m->block, m->pblock, lds,
+                                  true, st), "overlapped particle passes");
+        return GSIM_OK;
+    };
     for (size_t li = 0; li < seq.size(); ++li) {
         const Launch& l = seq[li];
         const StepDev<T>* sd = c.table + l.row;
+        if (l.op == OP_DUAL) {
+            if (nl == 1) {
+                if (int rc = dual(-1, sd, c.table + l.row2)) return rc;
+                continue;
+            }
+            if (!forked) {
+                HIP_TRY(hipEventRecord(m->ev_fork, s0), "fork lanes");
+                for (int k = 1; k < nl; ++k) HIP_TRY(hipStreamWaitEvent(m->lane_stream[k], m->ev_fork, 0), "fork lanes");
+                forked = true;
+            }
+            for (int k = 0; k < nl; ++k)
+                if (int rc = dual(k, sd, c.table + l.row2)) return rc;
+            continue;
+        }
         if (m->exec == GSIM_EXEC_PERSIST && (l.op == OP_FWD || l.op == OP_ADJ)) {
             // the run of forward / adjoint steps on consecutive rows: one launch
             size_t lj = li + 1;
@@ -1224,12 +1254,19 @@ int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, i
         rows.push_back(base);
         seq.push_back({OP_FILL_CPART, r0});
     }
-    T* segT = (T*)seg;
     const T* ck = (const T*)ckpt;
     T* fbar = (T*)(m->ws + m->L.fbar);
+    // Overlapped recompute: segment s's states live in buffer s % 2 (the caller's
+    // segment buffer, or the second one given to gsim_model_set_overlap), and the
+    // recompute of segment s - 1 runs in the same launches as segment s's adjoint steps.
+    const bool overlap = m->seg2 && nseg > 1 && m->timing_mask == 0 && !m->any_air &&
+                         (m->exec == GSIM_EXEC_PLAIN || m->exec == GSIM_EXEC_GRAPH);
+    auto segbuf = [&](int s) -> T* { return overlap && (s & 1) ? (T*)m->seg2 : (T*)seg; };
+    std::vector<std::vector<int64_t>> rec(nseg), adj(nseg);  // table rows of each segment's passes
     int q = 0;  // adjoint steps done
     for (int s = nseg - 1; s >= 0; --s) {
         const int t0 = s * K, t1 = std::min(n, t0 + K), L = t1 - t0;
+        T* segT = segbuf(s);
         // recompute states t0+1 .. t1-1 into seg[0 .. L-2]
         for (int j = 0; j + 1 < L; ++j) {
             StepDev<T> r = base;
@@ -1240,7 +1277,7 @@ int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, i
             r.xo = segT + j * S;
             r.vo = r.xo + 3 * np;
             rows.push_back(r);
-            seq.push_back({OP_FWD, r0 + (int64_t)rows.size() - 1});
+            rec[s].push_back(r0 + (int64_t)rows.size() - 1);
         }
         for (int t = t1 - 1; t >= t0; --t, ++q) {
             StepDev<T> r = base;
@@ -1265,12 +1302,32 @@ int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, i
             if (q > 0) r.fb = fbar + ((q - 1) & 1) * 3 * np;
             r.adj = 1;
             rows.push_back(r);
-            seq.push_back({OP_ADJ, r0 + (int64_t)rows.size() - 1});
+            adj[s].push_back(r0 + (int64_t)rows.size() - 1);
+        }
+    }
+    if (!overlap) {
+        for (int s = nseg - 1; s >= 0; --s) {
+            for (int64_t row : rec[s]) seq.push_back({OP_FWD, row});
+            for (int64_t row : adj[s]) seq.push_back({OP_ADJ, row});
+        }
+    } else {
+        // the last segment's recompute alone, then each segment's adjoint steps paired
+        // with the previous segment's recompute steps (two independent chains)
+        for (int64_t row : rec[nseg - 1]) seq.push_back({OP_FWD, row});
+        for (int s = nseg - 1; s >= 0; --s) {
+            const std::vector<int64_t>& A = adj[s];
+            static const std::vector<int64_t> none;
+            const std::vector<int64_t>& R = s > 0 ? rec[s - 1] : none;
+            const size_t k = std::min(A.size(), R.size());
+            for (size_t i = 0; i < k; ++i) seq.push_back({OP_DUAL, A[i], R[i]});
+            for (size_t i = k; i < A.size(); ++i) seq.push_back({OP_ADJ, A[i]});
+            for (size_t i = k; i < R.size(); ++i) seq.push_back({OP_FWD, R[i]});
         }
     }
     if (want_contact) seq.push_back({OP_CONTACT_REDUCE, r0});
     if ((rc = upload_rows<T>(m, r0, rows, stream))) return rc;
-    return execute<T>(m, (4LL << 40) | ((long long)n << 1) | (want_contact ? 1 : 0), seq, stream);
+    return execute<T>(m, (4LL << 40) | (overlap ? 1LL << 39 : 0) | ((long long)n << 1) | (want_contact ? 1 : 0), seq,
+                      stream);
 }
 
 template <typename T>
@@ -1704,6 +1761,20 @@ int gsim_model_set_lanes(gsim_model* m, int lanes) {
     HIP_TRY(hipDeviceSynchronize(), "synchronize before retiling");
     m->lanes = lanes;
     return guarded<double>([&]() { return m->dtype == GSIM_F64 ? upload_tiles<double>(m, nullptr) : upload_tiles<float>(m, nullptr); });
+}
+
+int gsim_model_set_overlap(gsim_model* m, void* d_segment2, size_t bytes) {
+    if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    if (!d_segment2) {
+        m->seg2 = nullptr;
+        m->seg2_bytes = 0;
+        return GSIM_OK;
+    }
+    const size_t need = (size_t)std::max(m->K - 1, 1) * 6 * (size_t)m->np * (m->dtype == GSIM_F64 ? 8 : 4);
+    if (bytes < need) return fail(GSIM_E_WORKSPACE, "second segment buffer: %zu bytes, need %zu", bytes, need);
+    m->seg2 = d_segment2;
+    m->seg2_bytes = bytes;
+    return GSIM_OK;
 }
 
 int gsim_model_get_lanes(const gsim_model* m, int* lanes) {

@@ -134,6 +134,9 @@ struct gsim_model {
     hipStream_t lane_stream[gsim::MAX_LANES] = {};
     hipEvent_t ev_fork = nullptr, ev_join[gsim::MAX_LANES] = {};
     int n_ptile_rows = 0;             // real particle tiles (contact / loss partial rows)
+    // overlapped recompute (gsim_model_set_overlap): the caller's second segment buffer
+    void* seg2 = nullptr;
+    size_t seg2_bytes = 0;
     std::vector<char> bodies_host;    // BodyDev<T>[nb] as last uploaded
     char* stage = nullptr;            // pinned copy of the launch table as last uploaded
     hipEvent_t stage_evt = nullptr;   // completes when the last table upload has read `stage`

@@ -962,10 +962,10 @@ __global__ void __launch_bounds__(512) k_part_adj(const ModelDev<T>* __restrict_
 }
 
 // Persistent execution: workgroup b runs body b through a run of steps.  Each step is
-// the body's element tiles one after another, then its particle tiles, where the
-// two-pass path has its launch boundaries there are device-scope fences and workgroup
-// barriers (the partials and states a pass writes are read by other threads of the
-// workgroup in the next).  The tiles, their partial slots and their contact rows are
+// the body's element tiles one after another, then its particle tiles; where the
+// two-pass path has its launch boundaries there are workgroup barriers (the partials
+// and states a pass writes are read by other threads of the workgroup in the next,
+// all on one CU).  The tiles, their partial slots and their contact rows are
 // those of the two-pass launches, so every result is bitwise the same; only the order
 // in which tiles run changes, and no result depends on it.
 template <typename T>
@@ -991,6 +991,33 @@ __global__ void __launch_bounds__(512) k_persist(const ModelDev<T>* __restrict__
         }
         __syncthreads();  // (workgroup-scope release and acquire of global memory)
     }
+}
+
+// Overlapped recompute: one launch runs an adjoint pass (row sd_adj) over the tiles
+// adj[0, n_adj) and a forward pass (row sd_fwd) over fwd[0, n_fwd), the forward
+// tiles starting at workgroup adj_span (n_adj rounded up to a multiple of the 8 XCDs, so
+// each list keeps its XCD placement; the workgroups in between return at once).
+// The two passes belong to independent chains of the checkpointed backward (the
+// adjoint steps of one segment, the recompute of the previous segment's states) and
+// touch disjoint buffers, so each tile's result is the one its own launch would give.
+template <typename T>
+__global__ void __launch_bounds__(512) k_elem_dual(const ModelDev<T>* __restrict__ md,
+                                                    const StepDev<T>* __restrict__ sd_adj, const Tile* __restrict__ adj,
+                                                    int n_adj, int adj_span, const StepDev<T>* __restrict__ sd_fwd,
+                                                    const Tile* __restrict__ fwd) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int b = blockIdx.x;
+    if (b >= adj_span) elem_fwd_tile<T, false>(md, sd_fwd, fwd[b - adj_span], smem);
+    else if (b < n_adj) elem_adj_tile<T, false>(md, sd_adj, adj[b], smem);
+}
+template <typename T>
+__global__ void __launch_bounds__(512) k_part_dual(const ModelDev<T>* __restrict__ md,
+                                                    const StepDev<T>* __restrict__ sd_adj, const Tile* __restrict__ adj,
+                                                    int n_adj, int adj_span, const StepDev<T>* __restrict__ sd_fwd,
+                                                    const Tile* __restrict__ fwd) {
+    const int b = blockIdx.x;
+    if (b >= adj_span) part_fwd_tile<T>(md, sd_fwd, fwd[b - adj_span]);
+    else if (b < n_adj) part_adj_tile<T, false>(md, sd_adj, adj[b]);
 }
 
 // Serving: the tile at launch position `pos` of a round's element or particle launch.
@@ -1759,6 +1786,25 @@ int launch_persist(const ModelDev<T>* md, const StepDev<T>* rows, int n_rows, co
         return check_launch();
     }
 }
+template <typename T>
+int launch_dual(const ModelDev<T>* md, const StepDev<T>* sd_adj, const StepDev<T>* sd_fwd, const Tile* etiles,
+                int n_etiles, const Tile* ptiles, int n_ptiles, int block, int pblock, size_t lds, bool particles,
+                void* stream) {
+    static size_t allowed = 48 * 1024;
+    const int nx = 8;  // XCDs: workgroup b runs on XCD b % 8
+    const int espan = (n_etiles + nx - 1) / nx * nx, pspan = (n_ptiles + nx - 1) / nx * nx;
+    if (!particles) {
+        if (n_etiles <= 0) return 0;
+        allow_lds(reinterpret_cast<const void*>(&k_elem_dual<T>), lds, allowed);
+        hipLaunchKernelGGL(k_elem_dual<T>, dim3(espan + n_etiles), dim3(block), lds, (hipStream_t)stream, md, sd_adj,
+                           etiles, n_etiles, espan, sd_fwd, etiles);
+        return check_launch();
+    }
+    if (n_ptiles <= 0) return 0;
+    hipLaunchKernelGGL(k_part_dual<T>, dim3(pspan + n_ptiles), dim3(pblock), 0, (hipStream_t)stream, md, sd_adj,
+                       ptiles, n_ptiles, pspan, sd_fwd, ptiles);
+    return check_launch();
+}
 int launch_stage_copy(const StageSeg* segs, int n_segs, void* stream) {
     if (n_segs <= 0) return 0;
     hipLaunchKernelGGL(k_stage_copy, dim3(n_segs), dim3(256), 0, (hipStream_t)stream, segs);
@@ -1866,6 +1912,8 @@ int launch_fused_grads(const ModelDev<T>* md, const StepDev<T>* sd, void* stream
     template int launch_fill<T>(T*, int64_t, T, void*);                                                             \
     template int launch_persist<T>(const ModelDev<T>*, const StepDev<T>*, int, const Tile*, const Tile*, const int32_t*, \
                                    int, int, size_t, void*);                                                        \
+    template int launch_dual<T>(const ModelDev<T>*, const StepDev<T>*, const StepDev<T>*, const Tile*, int, const Tile*, \
+                                int, int, int, size_t, bool, void*);                                              \
     template int launch_mixed<T>(const ModelDev<T>*, const StepDev<T>*, const TileSeg*, int, int, int, const TileSeg*, \
                                  int, int, int, int, int, size_t, void*);                                           \
     template int launch_contact_reduce<T>(const ModelDev<T>*, const StepDev<T>*, int, void*);                       \

@@ -33,6 +33,7 @@ ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan
                "gsim_plan_counts", "gsim_plan_colouring", "gsim_plan_tiles", "gsim_plan_codes", "gsim_plan_partials",
                "gsim_model_init", "gsim_model_destroy", "gsim_model_set_exec", "gsim_model_get_exec",
                "gsim_model_set_launch", "gsim_model_get_launch", "gsim_model_set_lanes", "gsim_model_get_lanes",
+               "gsim_model_set_overlap",
                "gsim_step", "gsim_step_backward", "gsim_rollout", "gsim_rollout_backward",
                "gsim_loss_mse", "gsim_model_set_timing", "gsim_model_read_timing", "gsim_model_check",
                "gsim_controller_forward", "gsim_controller_backward",
@@ -131,6 +132,7 @@ def load():
         lib.gsim_model_get_launch.argtypes = [vp, ip, C.POINTER(ip), C.POINTER(ip)]
         lib.gsim_model_set_lanes.argtypes = [vp, ip]
         lib.gsim_model_get_lanes.argtypes = [vp, C.POINTER(ip)]
+        lib.gsim_model_set_overlap.argtypes = [vp, vp, C.c_size_t]
         lib.gsim_step.argtypes = [vp, C.POINTER(_Params), _State, _State, ip, vp]
         lib.gsim_step_backward.argtypes = [vp, C.POINTER(_Params), _State, _State, _State, C.POINTER(_Grads), vp]
         lib.gsim_rollout.argtypes = [vp, C.POINTER(_Params), _State, ip, vp, _State, vp]
@@ -388,7 +390,7 @@ class Model:
     """``gsim_model_init`` over torch-allocated buffers, plus the per-call entry points."""
 
     def __init__(self, bodies, dtype=torch.float32, max_steps=100, ckpt_every=10, device="cuda", stream=None,
-                 tile_elems=0):
+                 tile_elems=0, overlap=True):
         self.plan = Plan(bodies, dtype, tile_elems)
         self.dtype = dtype
         self.device = _device(device)
@@ -407,6 +409,8 @@ class Model:
         self._h = h
         p = self.plan
         self.np, self.ne, self.nt, self.nh, self.nb = p.np, p.ne, p.nt, p.nh, p.nb
+        self.segment2 = None
+        self.set_overlap(overlap)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -437,6 +441,19 @@ class Model:
         n = C.c_int()
         _check(load().gsim_model_get_lanes(self._h, C.byref(n)))
         return n.value
+
+    def set_overlap(self, on=True):
+        """Overlapped recompute in rollout_backward: a second segment buffer of
+        max(ckpt_every - 1, 1) states lets the recompute of one checkpoint segment share
+        launches with the adjoint steps of the next (results bitwise unchanged)."""
+        if on:
+            if self.segment2 is None:
+                n = max(self.ckpt_every - 1, 1) * 6 * self.np
+                self.segment2 = torch.empty(max(n, 1), dtype=self.dtype, device=self.device)
+            t = self.segment2
+            _check(load().gsim_model_set_overlap(self._h, C.c_void_p(t.data_ptr()), t.numel() * t.element_size()))
+        else:  # the buffer is kept: launches already queued may still use it
+            _check(load().gsim_model_set_overlap(self._h, None, 0))
 
     def get_exec(self):
         e, b, i = C.c_int(), C.c_int(), C.c_int()
