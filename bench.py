@@ -717,13 +717,15 @@ def main():
         t_total = time.perf_counter() - t0
         step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
         sec = float(np.median(step_ms)) * 1e-3
-        # forward-only rate (rollout with checkpoints)
+        # forward-only rate (rollout with checkpoints): median of per-rollout HIP events
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
+        evf = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        evf[0].record(stream)
+        for k in range(args.steps):
             model.rollout(p, x0, v0, T, out=(xT, vT), stream=stream)
+            evf[k + 1].record(stream)
         torch.cuda.synchronize()
-        sec_fwd = (time.perf_counter() - t0) / args.steps
+        sec_fwd = float(np.median([evf[k].elapsed_time(evf[k + 1]) for k in range(args.steps)])) * 1e-3
         control = None if args.no_control else control_step(model, p, x0, v0, tgt, T, args.steps, stream, ne)
         # per-kernel durations: one more bench step with HIP events around every launch
         # (graph replay cannot carry them: the two-pass path is timed with plain launches)
