@@ -56,7 +56,24 @@ def algorithmic_bytes(kernel, ne, np_, K):
         return 64 * ne + 16 * ne / K + 40 * np_
     if kernel == "particle_adj":
         return 84 * np_
+    if kernel in ("element_dual", "particle_dual"):  # a shared launch: one pass of each
+        return (algorithmic_bytes(kernel.replace("dual", "fwd"), ne, np_, K)
+                + algorithmic_bytes(kernel.replace("dual", "adj"), ne, np_, K))
     return None
+
+
+def compulsory_per_launch(kernel, ne, np_, ntp, T, K, launches):
+    """Compulsory bytes of one launch: a two-pass kernel's bytes per pass (its
+    kernel_bytes over the passes of that kind in one gradient, whether they run on their
+    own or in shared launches), a shared launch the sum of its two passes', a fused
+    kernel's total over its launches."""
+    nseg = -(-T // K)
+    passes = {"element_fwd": T + (T - nseg), "particle_fwd": T + (T - nseg), "element_adj": T, "particle_adj": T}
+    if kernel in passes:
+        return kernel_bytes(kernel, ne, np_, ntp, T, K) / passes[kernel]
+    if kernel in ("element_dual", "particle_dual"):
+        return sum(compulsory_per_launch(kernel.replace("dual", x), ne, np_, ntp, T, K, None) for x in ("fwd", "adj"))
+    return kernel_bytes(kernel, ne, np_, ntp, T, K) / launches
 
 
 def kernel_bytes(kernel, ne, np_, ntp, T, K):
@@ -107,7 +124,7 @@ MEASURED_TRAFFIC = {
     "source_sha1": "c43f820ec3c699ab52d932e5a1fbc45776d38872",
     "workload": (256, 100, 10, 512),  # bodies, steps, checkpoint interval, elements per tile
     "per_launch": {"element_fwd": 106.20e6, "particle_fwd": 27.54e6, "element_adj": 134.23e6,
-                   "particle_adj": 42.76e6},
+                   "particle_adj": 42.76e6, "element_dual": 240.40e6, "particle_dual": 68.47e6},
 }
 
 
@@ -150,7 +167,7 @@ def kernel_table(timing, ne, np_, ntp, T, K):
         if n:
             avg = ms / n
             alg = algorithmic_bytes(k, ne, np_, K)
-            comp = kernel_bytes(k, ne, np_, ntp, T, K) / n
+            comp = compulsory_per_launch(k, ne, np_, ntp, T, K, n)
             kern[k] = {"launches": n, "avg_us": avg * 1e3, "total_ms": ms, "compulsory_bytes_per_launch": comp,
                        "compulsory_GBps": comp / (avg * 1e-3) / 1e9}
             if alg is not None:

@@ -213,8 +213,8 @@ int gsim_model_get_lanes(const gsim_model* model, int* lanes);
  * d_segment2 of at least max(ckpt_every - 1, 1) states (6 n_particles values each,
  * caller-owned device memory that must outlive its use), the two passes share each
  * element launch and each particle launch, and consecutive segments alternate
- * between the two buffers.  Applies under GSIM_EXEC_PLAIN and GSIM_EXEC_GRAPH, with
- * kernel timing off, for models without lift/drag; otherwise, and with d_segment2 =
+ * between the two buffers.  Applies under GSIM_EXEC_PLAIN and GSIM_EXEC_GRAPH, for
+ * models without lift/drag; otherwise, and with d_segment2 =
  * NULL (the default), the passes run one after another.  Results are bitwise the same
  * either way.  GSIM_E_WORKSPACE when `bytes` is too small. */
 int gsim_model_set_overlap(gsim_model* model, void* d_segment2, size_t bytes);
@@ -222,7 +222,9 @@ int gsim_model_set_overlap(gsim_model* model, void* d_segment2, size_t bytes);
 /* Kernel timing for measurement: with bit k of `mask` set, every launch of
  * kernel k is bracketed by HIP events on its stream (k: 0 element pass,
  * 1 particle pass, 2 element adjoint pass, 3 particle adjoint pass, 4 fused
- * forward segment, 5 fused adjoint segment).  Plain
+ * forward segment, 5 fused adjoint segment, 6 shared adjoint + recompute element
+ * launch, 7 shared adjoint + recompute particle launch of gsim_model_set_overlap).
+ * With timing on, each pass is one launch over every lane's tiles.  Plain
  * execution only (GSIM_E_UNSUPPORTED under GSIM_EXEC_GRAPH).
  * gsim_model_read_timing waits for the recorded events and returns (then
  * clears) kernel k's launch count and summed duration in milliseconds. */

@@ -827,10 +827,14 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
         const int p0 = l < 0 ? 0 : m->lane_p[l], p1 = l < 0 ? m->n_ptiles : m->lane_p[l + 1];
         void* st = l > 0 ? (void*)m->lane_stream[l] : stream;
         const size_t lds = std::max(m->etile_words[0], m->etile_words[1]) * sizeof(T);
-        LAUNCH_TRY(launch_dual<T>(md, sd_a, sd_f, c.et + e0, e1 - e0, c.pt + p0, p1 - p0, m->block, m->pblock, lds,
-                                  false, st), "overlapped element passes");
-        LAUNCH_TRY(launch_dual<T>(md, sd_a, sd_f, c.et + e0, e1 - e0, c.pt + p0, p1 - p0, m->block, m->pblock, lds,
-                                  true, st), "overlapped particle passes");
+        LAUNCH_TRY(timed(m, 6, st, [&] {
+            return launch_dual<T>(md, sd_a, sd_f, c.et + e0, e1 - e0, c.pt + p0, p1 - p0, m->block, m->pblock, lds,
+                                  false, st);
+        }), "overlapped element passes");
+        LAUNCH_TRY(timed(m, 7, st, [&] {
+            return launch_dual<T>(md, sd_a, sd_f, c.et + e0, e1 - e0, c.pt + p0, p1 - p0, m->block, m->pblock, lds,
+                                  true, st);
+        }), "overlapped particle passes");
         return GSIM_OK;
     };
     for (size_t li = 0; li < seq.size(); ++li) {
@@ -1259,8 +1263,7 @@ int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, i
     // Overlapped recompute: segment s's states live in buffer s % 2 (the caller's
     // segment buffer, or the second one given to gsim_model_set_overlap), and the
     // recompute of segment s - 1 runs in the same launches as segment s's adjoint steps.
-    const bool overlap = m->seg2 && nseg > 1 && m->timing_mask == 0 && !m->any_air &&
-                         (m->exec == GSIM_EXEC_PLAIN || m->exec == GSIM_EXEC_GRAPH);
+    const bool overlap = m->seg2 && nseg > 1 && !m->any_air && (m->exec == GSIM_EXEC_PLAIN || m->exec == GSIM_EXEC_GRAPH);
     auto segbuf = [&](int s) -> T* { return overlap && (s & 1) ? (T*)m->seg2 : (T*)seg; };
     std::vector<std::vector<int64_t>> rec(nseg), adj(nseg);  // table rows of each segment's passes
     int q = 0;  // adjoint steps done
@@ -1838,7 +1841,7 @@ int gsim_model_get_exec(const gsim_model* m, int* exec, int* block, int* items) 
 
 int gsim_model_set_timing(gsim_model* m, int mask) {
     if (!m) return fail(GSIM_E_INVALID, "NULL model");
-    if (mask < 0 || mask > 63) return fail(GSIM_E_INVALID, "timing mask must be in [0, 63]");
+    if (mask < 0 || mask > 255) return fail(GSIM_E_INVALID, "timing mask must be in [0, 255]");
     if (mask && m->exec == GSIM_EXEC_PERSIST) return fail(GSIM_E_UNSUPPORTED, "kernel timing needs plain execution");
     m->timing_mask = mask;
     return GSIM_OK;
@@ -1846,7 +1849,7 @@ int gsim_model_set_timing(gsim_model* m, int mask) {
 
 int gsim_model_read_timing(gsim_model* m, int kernel, int64_t* launches, double* total_ms) {
     if (!m) return fail(GSIM_E_INVALID, "NULL model");
-    if (kernel < 0 || kernel > 5) return fail(GSIM_E_INVALID, "kernel must be in [0, 5]");
+    if (kernel < 0 || kernel > 7) return fail(GSIM_E_INVALID, "kernel must be in [0, 7]");
     for (auto& p : m->pending) {
         HIP_TRY(hipEventSynchronize(p.b), "timing sync");
         float ms = 0.f;

@@ -153,8 +153,8 @@ struct gsim_model {
         hipEvent_t a, b;
     };
     std::vector<Pending> pending;
-    double timing_ms[6] = {0, 0, 0, 0, 0, 0};
-    int64_t timing_n[6] = {0, 0, 0, 0, 0, 0};
+    double timing_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t timing_n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     // fused path
     bool fused_ok = false;   // colouring succeeded for every body and kind
     bool any_air = false;    // some body has lift/drag (not modelled by the fused path)

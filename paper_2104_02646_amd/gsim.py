@@ -47,7 +47,8 @@ ABI_SYMBOLS = ("gsim_last_error", "gsim_version", "gsim_plan_create", "gsim_plan
                "gsim_engine_set_store_limit", "gsim_engine_prepare", "gsim_engine_submit_prepared",
                "gsim_prepared_destroy")
 GSIM_F32, GSIM_F64 = 32, 64
-KERNELS = ("element_fwd", "particle_fwd", "element_adj", "particle_adj", "fused_fwd", "fused_adj")
+KERNELS = ("element_fwd", "particle_fwd", "element_adj", "particle_adj", "fused_fwd", "fused_adj", "element_dual",
+           "particle_dual")
 
 
 class GsimError(RuntimeError):

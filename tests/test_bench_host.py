@@ -41,6 +41,21 @@ def test_batch_bytes_per_launch():
     assert per_adj == T * (80 * NE + 52 * NTP) + 17 * NTP
 
 
+def test_shared_launch_bytes():
+    """A shared launch (one adjoint and one recompute pass of the overlapped backward)
+    counts both passes' bytes; a pass's compulsory bytes do not depend on how many of
+    its passes run on their own."""
+    T, K = 100, 10
+    for kind in ("element", "particle"):
+        assert bench.algorithmic_bytes(kind + "_dual", NE, NP, K) == (bench.algorithmic_bytes(kind + "_fwd", NE, NP, K)
+                                                                      + bench.algorithmic_bytes(kind + "_adj", NE, NP, K))
+    fwd = bench.compulsory_per_launch("element_fwd", NE, NP, NTP, T, K, 109)
+    assert fwd == 64 * NE + 36 * NTP
+    adj = bench.compulsory_per_launch("element_adj", NE, NP, NTP, T, K, 10)
+    assert adj == (T * (80 * NE + 52 * NTP) + 17 * NTP) / T
+    assert bench.compulsory_per_launch("element_dual", NE, NP, NTP, T, K, 90) == fwd + adj
+
+
 def test_algorithmic_bytes():
     """The scope table's accounting: per launch, and for a whole checkpointed gradient
     (190 forward passes: 100 in the rollout, 90 recomputed)."""
