@@ -121,10 +121,10 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
 # (of gsim_kernels.hip followed by gsim_device.h) and 512-element tiles only; for any other
 # source or tile size the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "source_sha1": "c43f820ec3c699ab52d932e5a1fbc45776d38872",
+    "source_sha1": "e440ec09770c43d476002f1664d11c5fd6fafb17",
     "workload": (256, 100, 10, 512),  # bodies, steps, checkpoint interval, elements per tile
-    "per_launch": {"element_fwd": 106.20e6, "particle_fwd": 27.54e6, "element_adj": 134.23e6,
-                   "particle_adj": 42.76e6, "element_dual": 240.40e6, "particle_dual": 68.47e6},
+    "per_launch": {"element_fwd": 106.20e6, "particle_fwd": 27.63e6, "element_adj": 134.20e6,
+                   "particle_adj": 42.66e6, "element_dual": 240.41e6, "particle_dual": 68.66e6},
 }
 
 

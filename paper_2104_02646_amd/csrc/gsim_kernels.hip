@@ -1796,13 +1796,13 @@ int launch_dual(const ModelDev<T>* md, const StepDev<T>* sd_adj, const StepDev<T
     if (!particles) {
         if (n_etiles <= 0) return 0;
         allow_lds(reinterpret_cast<const void*>(&k_elem_dual<T>), lds, allowed);
-        hipLaunchKernelGGL(k_elem_dual<T>, dim3(espan + n_etiles), dim3(block), lds, (hipStream_t)stream, md, sd_adj,
-                           etiles, n_etiles, espan, sd_fwd, etiles);
+        launch_timed(k_elem_dual<T>, dim3(espan + n_etiles), dim3(block), lds, (hipStream_t)stream, md, sd_adj, etiles,
+                     n_etiles, espan, sd_fwd, etiles);
         return check_launch();
     }
     if (n_ptiles <= 0) return 0;
-    hipLaunchKernelGGL(k_part_dual<T>, dim3(pspan + n_ptiles), dim3(pblock), 0, (hipStream_t)stream, md, sd_adj,
-                       ptiles, n_ptiles, pspan, sd_fwd, ptiles);
+    launch_timed(k_part_dual<T>, dim3(pspan + n_ptiles), dim3(pblock), 0, (hipStream_t)stream, md, sd_adj, ptiles,
+                 n_ptiles, pspan, sd_fwd, ptiles);
     return check_launch();
 }
 int launch_stage_copy(const StageSeg* segs, int n_segs, void* stream) {
