@@ -150,12 +150,14 @@ def step_algorithmic_bytes(ne, np_, K, nt=0, nh=0):
     return bf, ba
 
 
-def gradient_bytes(ne, np_, T, K, nt=0, nh=0):
+def gradient_bytes(ne, np_, T, K, nt=0, nh=0, kept=False):
     """Algorithmic bytes of one checkpointed gradient: the forward passes that run (T
     in the rollout, T - ceil(T/K) recomputed: the first state of each segment is its
-    checkpoint) times B_f, plus T adjoint steps times B_a."""
+    checkpoint; with `kept`, the last segment's states come from the rollout and its
+    recompute does not run) times B_f, plus T adjoint steps times B_a."""
     bf, ba = step_algorithmic_bytes(ne, np_, K, nt, nh)
-    fwd_passes = T + (T - -(-T // K))
+    nseg = -(-T // K)
+    fwd_passes = T + (T - nseg) - ((T - (nseg - 1) * K - 1) if kept else 0)
     return fwd_passes * bf + T * ba, fwd_passes
 
 
@@ -283,6 +285,7 @@ def gradient_line(bodies, dtype, T, K, exec_mode, lanes=1, reps=3, timing=False,
             ev[-1].synchronize()
             return float(np.median([ev[k].elapsed_time(ev[k + 1]) for k in range(reps)]))
         gms, fms = median_ms(grad), median_ms(fwd)
+        kept = m.keeps_last_segment()
         out = {"ms_per_gradient": gms, "us_per_sim_step": gms * 1e3 / T, "fwd_us_per_sim_step": fms * 1e3 / T,
                "value": nel * T / (gms * 1e-3), "forward_value": nel * T / (fms * 1e-3)}
         if timing:
@@ -297,8 +300,9 @@ def gradient_line(bodies, dtype, T, K, exec_mode, lanes=1, reps=3, timing=False,
             dom = max((k for k in kern if "algorithmic_bytes_per_launch" in kern[k]), key=lambda k: kern[k]["total_ms"])
             out["kernels"] = kern
             out["roofline"] = roofline(kern[dom], dom, None)
-            gb, _ = gradient_bytes(ne, np_, T, K)
-            out["step_algorithmic"] = {"GBps": gb / (gms * 1e-3) / 1e9, "frac": gb / (gms * 1e-3) / 1e12 / 8.0}
+            gb, passes = gradient_bytes(ne, np_, T, K, kept=kept)
+            out["step_algorithmic"] = {"GBps": gb / (gms * 1e-3) / 1e9, "frac": gb / (gms * 1e-3) / 1e12 / 8.0,
+                                       "forward_passes": passes}
     del m
     torch.cuda.synchronize()
     return out
@@ -708,6 +712,7 @@ def main():
     args.exec = {gsim.EXEC_FUSED: "fused", gsim.EXEC_GRAPH: "graph", gsim.EXEC_PLAIN: "plain",
                  gsim.EXEC_PERSIST: "persist"}[exec_mode]
     args.block, args.items, args.lanes = block, items, model.get_lanes()
+    kept = model.keeps_last_segment()  # the timed steps' backward takes the rollout's last segment
     tile_elems = model.plan.tile_elems or gsim.TILE_DEFAULT
     ntp = len(gsim.Plan(bodies, tile_elems=tile_elems).tiles()[1])  # tile particles of the element tiles
 
@@ -773,7 +778,7 @@ def main():
     kern = kernel_table(timing, ne, np_, ntp, T, K)
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     d = kern[dom]
-    gbytes, fwd_passes = gradient_bytes(ne, np_, T, K)
+    gbytes, fwd_passes = gradient_bytes(ne, np_, T, K, kept=kept)
     step_bw = gbytes / sec / 1e9
     traffic = measured_traffic(dom, len(bodies), T, K, tile_elems)
 

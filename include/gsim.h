@@ -213,10 +213,14 @@ int gsim_model_get_lanes(const gsim_model* model, int* lanes);
  * d_segment2 of at least max(ckpt_every - 1, 1) states (6 n_particles values each,
  * caller-owned device memory that must outlive its use), the two passes share each
  * element launch and each particle launch, and consecutive segments alternate
- * between the two buffers.  Applies under GSIM_EXEC_PLAIN and GSIM_EXEC_GRAPH, for
- * models without lift/drag; otherwise, and with d_segment2 =
- * NULL (the default), the passes run one after another.  Results are bitwise the same
- * either way.  GSIM_E_WORKSPACE when `bytes` is too small. */
+ * between the two buffers.  A checkpointed gsim_rollout also leaves the states of its
+ * last segment in d_segment2, and the next gsim_rollout_backward with the same d_ckpt
+ * and n_steps skips that segment's recompute; any other checkpointed rollout, any
+ * backward and any call of this function in between discard them (forward-only
+ * rollouts, single steps and losses do not touch them).  Applies under
+ * GSIM_EXEC_PLAIN and GSIM_EXEC_GRAPH, for models without lift/drag; otherwise, and
+ * with d_segment2 = NULL (the default), the passes run one after another.  Results
+ * are bitwise the same either way.  GSIM_E_WORKSPACE when `bytes` is too small. */
 int gsim_model_set_overlap(gsim_model* model, void* d_segment2, size_t bytes);
 
 /* Kernel timing for measurement: with bit k of `mask` set, every launch of

@@ -1023,6 +1023,12 @@ int check_params(const gsim_model* m, const gsim_params* p, const gsim_grads* g 
     return GSIM_OK;
 }
 
+// The second segment buffer is in use (overlapped recompute, kept last segment): plain
+// and graph execution of models without lift/drag.
+bool uses_seg2(const gsim_model* m) {
+    return m->seg2 && !m->any_air && (m->exec == GSIM_EXEC_PLAIN || m->exec == GSIM_EXEC_GRAPH);
+}
+
 // table regions
 int64_t region_rollout(const gsim_model*) { return 0; }
 int64_t region_backward(const gsim_model* m) { return m->max_steps + 2; }
@@ -1195,11 +1201,20 @@ int do_rollout(gsim_model* m, const gsim_params* p, gsim_state s0, int n, void* 
     if (!s0.x || !s0.v || !sf.x || !sf.v) return fail(GSIM_E_INVALID, "NULL state");
     int rc = check_params(m, p);
     if (rc) return rc;
+    if (ckpt) m->tail_ckpt = nullptr;  // new checkpoints: any kept segment is stale
     if (m->exec == GSIM_EXEC_FUSED)
         return do_fused_forward<T>(m, p, (const T*)s0.x, (const T*)s0.v, (T*)sf.x, (T*)sf.v, (T*)ckpt, n,
                                    region_rollout(m), (6LL << 40) | ((long long)n << 1) | (ckpt ? 1 : 0), stream);
     Ctx<T> c = ctx<T>(m);
     const int64_t S = 6 * c.np;
+    // With the second segment buffer, the states of the last checkpoint segment (steps
+    // tl0 + 1 .. n - 1) go there instead of the ping-pong buffers: the backward that
+    // follows finds them in place of its first recompute (same steps, same inputs).
+    const bool tail = ckpt && uses_seg2(m);
+    const int tl0 = (n - 1) / m->K * m->K;
+    auto state = [&](int t) -> T* {  // where step t - 1 leaves state t (0 < t < n)
+        return tail && t > tl0 ? (T*)m->seg2 + (int64_t)(t - tl0 - 1) * S : c.fbuf + ((t - 1) & 1) * S;
+    };
     std::vector<StepDev<T>> rows(n);
     std::vector<Launch> seq;
     for (int t = 0; t < n; ++t) {
@@ -1212,7 +1227,7 @@ int do_rollout(gsim_model* m, const gsim_params* p, gsim_state s0, int n, void* 
             r.v = (const T*)s0.v;
             r.x_abs = 1;
         } else {
-            r.x = c.fbuf + ((t - 1) & 1) * S;
+            r.x = state(t);
             r.v = r.x + 3 * c.np;
         }
         if (t == n - 1) {
@@ -1220,7 +1235,7 @@ int do_rollout(gsim_model* m, const gsim_params* p, gsim_state s0, int n, void* 
             r.vo = (T*)sf.v;
             r.xo_abs = 1;
         } else {
-            r.xo = c.fbuf + (t & 1) * S;
+            r.xo = state(t + 1);
             r.vo = r.xo + 3 * c.np;
         }
         if (ckpt && t % m->K == 0) {
@@ -1230,7 +1245,13 @@ int do_rollout(gsim_model* m, const gsim_params* p, gsim_state s0, int n, void* 
         seq.push_back({OP_FWD, region_rollout(m) + t});
     }
     if ((rc = upload_rows<T>(m, region_rollout(m), rows, stream))) return rc;
-    return execute<T>(m, (3LL << 40) | ((long long)n << 1) | (ckpt ? 1 : 0), seq, stream);
+    if ((rc = execute<T>(m, (3LL << 40) | ((long long)n << 1) | (ckpt ? 1 : 0), seq, stream))) return rc;
+    if (tail) {
+        m->tail_ckpt = ckpt;
+        m->tail_seg2 = m->seg2;
+        m->tail_n = n;
+    }
+    return GSIM_OK;
 }
 
 template <typename T>
@@ -1260,18 +1281,22 @@ int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, i
     }
     const T* ck = (const T*)ckpt;
     T* fbar = (T*)(m->ws + m->L.fbar);
-    // Overlapped recompute: segment s's states live in buffer s % 2 (the caller's
-    // segment buffer, or the second one given to gsim_model_set_overlap), and the
-    // recompute of segment s - 1 runs in the same launches as segment s's adjoint steps.
-    const bool overlap = m->seg2 && nseg > 1 && !m->any_air && (m->exec == GSIM_EXEC_PLAIN || m->exec == GSIM_EXEC_GRAPH);
-    auto segbuf = [&](int s) -> T* { return overlap && (s & 1) ? (T*)m->seg2 : (T*)seg; };
+    // Overlapped recompute: with the second segment buffer (gsim_model_set_overlap), the
+    // last segment's states live there and the others alternate between the caller's
+    // buffer and it, and the recompute of segment s - 1 runs in the same launches as
+    // segment s's adjoint steps.  When the rollout of these checkpoints left the last
+    // segment's states in that buffer, that segment is not recomputed.
+    const bool two = uses_seg2(m), overlap = two && nseg > 1;
+    const bool kept = two && m->tail_ckpt == ckpt && m->tail_seg2 == m->seg2 && m->tail_n == n;
+    m->tail_ckpt = nullptr;  // this call overwrites the second buffer
+    auto segbuf = [&](int s) -> T* { return two && ((nseg - 1 - s) & 1) == 0 ? (T*)m->seg2 : (T*)seg; };
     std::vector<std::vector<int64_t>> rec(nseg), adj(nseg);  // table rows of each segment's passes
     int q = 0;  // adjoint steps done
     for (int s = nseg - 1; s >= 0; --s) {
         const int t0 = s * K, t1 = std::min(n, t0 + K), L = t1 - t0;
         T* segT = segbuf(s);
         // recompute states t0+1 .. t1-1 into seg[0 .. L-2]
-        for (int j = 0; j + 1 < L; ++j) {
+        for (int j = 0; j + 1 < L && !(kept && s == nseg - 1); ++j) {
             StepDev<T> r = base;
             r.g_mu = r.g_lam = r.g_ktri = r.g_mass = r.g_contact = r.g_act = r.g_hact = nullptr;
             at_step<T>(r, p, nullptr, t0 + j);
@@ -1329,8 +1354,9 @@ int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, i
     }
     if (want_contact) seq.push_back({OP_CONTACT_REDUCE, r0});
     if ((rc = upload_rows<T>(m, r0, rows, stream))) return rc;
-    return execute<T>(m, (4LL << 40) | (overlap ? 1LL << 39 : 0) | ((long long)n << 1) | (want_contact ? 1 : 0), seq,
-                      stream);
+    return execute<T>(m, (4LL << 40) | (overlap ? 1LL << 39 : 0) | (kept ? 1LL << 38 : 0) | (two ? 1LL << 37 : 0) |
+                             ((long long)n << 1) | (want_contact ? 1 : 0),
+                      seq, stream);
 }
 
 template <typename T>
@@ -1768,6 +1794,7 @@ int gsim_model_set_lanes(gsim_model* m, int lanes) {
 
 int gsim_model_set_overlap(gsim_model* m, void* d_segment2, size_t bytes) {
     if (!m) return fail(GSIM_E_INVALID, "NULL model");
+    m->tail_ckpt = nullptr;
     if (!d_segment2) {
         m->seg2 = nullptr;
         m->seg2_bytes = 0;

@@ -134,9 +134,13 @@ struct gsim_model {
     hipStream_t lane_stream[gsim::MAX_LANES] = {};
     hipEvent_t ev_fork = nullptr, ev_join[gsim::MAX_LANES] = {};
     int n_ptile_rows = 0;             // real particle tiles (contact / loss partial rows)
-    // overlapped recompute (gsim_model_set_overlap): the caller's second segment buffer
+    // overlapped recompute (gsim_model_set_overlap): the caller's second segment buffer;
+    // tail_*: the checkpointed rollout whose last segment's states seg2 holds (none: null)
     void* seg2 = nullptr;
     size_t seg2_bytes = 0;
+    const void* tail_ckpt = nullptr;
+    const void* tail_seg2 = nullptr;
+    int tail_n = 0;
     std::vector<char> bodies_host;    // BodyDev<T>[nb] as last uploaded
     char* stage = nullptr;            // pinned copy of the launch table as last uploaded
     hipEvent_t stage_evt = nullptr;   // completes when the last table upload has read `stage`

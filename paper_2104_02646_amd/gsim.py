@@ -336,6 +336,7 @@ class Plan:
         _check(lib.gsim_plan_create(C.byref(d), C.byref(h)))
         self._h = h
         self.np, self.ne, self.nt, self.nh, self.nb = d.n_particles, d.n_tets, d.n_tris, d.n_hinges, d.n_bodies
+        self.any_air = bool(pk.air_on.any())
 
     def colouring(self, kind):
         """(order, bounds) of the colour-ordered element list of one kind (0 tet, 1 tri, 2 hinge)."""
@@ -411,6 +412,7 @@ class Model:
         p = self.plan
         self.np, self.ne, self.nt, self.nh, self.nb = p.np, p.ne, p.nt, p.nh, p.nb
         self.segment2 = None
+        self._overlap = False
         self.set_overlap(overlap)
 
     def __del__(self):
@@ -443,6 +445,12 @@ class Model:
         _check(load().gsim_model_get_lanes(self._h, C.byref(n)))
         return n.value
 
+    def keeps_last_segment(self):
+        """Whether the second segment buffer is in use (the library's rule: overlap on,
+        plain or graph execution, no body with lift/drag), so that a checkpointed rollout
+        leaves its last segment for the backward and that segment is not recomputed."""
+        return self._overlap and not self.plan.any_air and self.get_exec()[0] in (EXEC_PLAIN, EXEC_GRAPH)
+
     def set_overlap(self, on=True):
         """Overlapped recompute in rollout_backward: a second segment buffer of
         max(ckpt_every - 1, 1) states lets the recompute of one checkpoint segment share
@@ -455,6 +463,7 @@ class Model:
             _check(load().gsim_model_set_overlap(self._h, C.c_void_p(t.data_ptr()), t.numel() * t.element_size()))
         else:  # the buffer is kept: launches already queued may still use it
             _check(load().gsim_model_set_overlap(self._h, None, 0))
+        self._overlap = bool(on)
 
     def get_exec(self):
         e, b, i = C.c_int(), C.c_int(), C.c_int()

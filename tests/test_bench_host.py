@@ -69,6 +69,12 @@ def test_algorithmic_bytes():
     assert 74 < bf / NE < 77 and 80 < ba / NE < 86  # the batch's ~75 B and ~84 B per element-step
     total, passes = bench.gradient_bytes(NE, NP, T, K)
     assert passes == 190 and total == 190 * bf + 100 * ba
+    # the rollout's last segment kept for the backward: its 9 recompute passes do not run
+    total, passes = bench.gradient_bytes(NE, NP, T, K, kept=True)
+    assert passes == 181 and total == 181 * bf + 100 * ba
+    assert bench.gradient_bytes(NE, NP, 1000, 50, kept=True)[1] == 1000 + 980 - 49
+    assert bench.gradient_bytes(NE, NP, 40, 7, kept=True)[1] == 40 + 34 - 4  # ragged last segment of 5
+    assert bench.gradient_bytes(NE, NP, 9, 10, kept=True)[1] == 9  # one segment: nothing recomputed
     # cloth: triangle 36 B, hinge 20 B per pass, stiffness gradient once per segment
     bf, ba = bench.step_algorithmic_bytes(0, 4096, 20, nt=7938, nh=11781)
     assert bf == 36 * 7938 + 20 * 11781 + 52 * 4096 and ba == bf + 32 * 4096 + 8 * 7938 / 20

@@ -84,6 +84,49 @@ def test_overlap_with_lift_drag_keeps_the_sequential_backward(gs):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("T,K", [(40, 7), (9, 10)])
+def test_kept_last_segment_follows_its_checkpoints(gs, T, K):
+    """A checkpointed rollout leaves its last segment's states for the next backward with
+    the same checkpoints: that backward equals, bitwise, one without the second buffer, also
+    when a forward-only rollout from another state ran in between; a checkpointed rollout
+    into other checkpoints in between, or a toggle of the buffer, makes the backward
+    recompute the segment and it still equals the reference."""
+    bodies = [W.tiny_cube(6).round_to(np.float32), mixed_body(7).round_to(np.float32)]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        m = gs.Model(bodies, torch.float32, max_steps=T, ckpt_every=K)
+        m.set_exec(gs.EXEC_GRAPH)
+        p = m.params_from_bodies()
+        x0 = gs.soa(np.concatenate([b.x0 for b in bodies]))
+        v0 = gs.soa(np.concatenate([b.v0 for b in bodies]))
+        x0b, v0b = x0 + 0.003, v0 * 0.5
+        tg = gs.soa(np.concatenate([W.synthetic_target(b, 60 + i) for i, b in enumerate(bodies)]))
+        ck_other = m.new_checkpoints()
+
+        def grad(between=None, overlap=True):
+            m.set_overlap(overlap)
+            xT, _ = m.rollout(p, x0, v0, T, stream=stream)
+            loss, xb, vb = m.loss_mse(xT, tg, stream=stream)
+            if between:
+                between()
+            g = m.zero_grads(("mu", "lam", "ktri", "mass", "contact"))
+            xb0, vb0 = m.rollout_backward(p, T, xb, vb, g, stream=stream)
+            stream.synchronize()
+            return [t.cpu().numpy().copy() for t in list(g.values()) + [xb0, vb0]]
+
+        ref = grad(overlap=False)
+        cases = {
+            "kept": grad(),
+            "forward-only rollout between": grad(lambda: m.rollout(p, x0b, v0b, T, checkpoint=False, stream=stream)),
+            "checkpointed rollout into other checkpoints between":
+                grad(lambda: m.rollout(p, x0b, v0b, T, ckpt=ck_other, stream=stream)),
+            "buffer toggled between": grad(lambda: (m.set_overlap(False), m.set_overlap(True))),
+        }
+    for name, out in cases.items():
+        for a, b in zip(ref, out):
+            assert np.array_equal(a, b), name
+
+
 def test_overlap_needs_a_large_enough_buffer(gs):
     m = gs.Model([W.tiny_cube(0)], torch.float32, max_steps=20, ckpt_every=5, overlap=False)
     small = torch.empty(4 * 6 * m.np - 1, dtype=torch.float32, device="cuda")  # K - 1 = 4 states, one value short
