@@ -217,10 +217,11 @@ int gsim_model_get_lanes(const gsim_model* model, int* lanes);
  * last segment in d_segment2, and the next gsim_rollout_backward with the same d_ckpt
  * and n_steps skips that segment's recompute; any other checkpointed rollout, any
  * backward and any call of this function in between discard them (forward-only
- * rollouts, single steps and losses do not touch them).  Applies under
- * GSIM_EXEC_PLAIN and GSIM_EXEC_GRAPH, for models without lift/drag; otherwise, and
- * with d_segment2 = NULL (the default), the passes run one after another.  Results
- * are bitwise the same either way.  GSIM_E_WORKSPACE when `bytes` is too small. */
+ * rollouts, single steps and losses do not touch them).  The shared launches apply
+ * under GSIM_EXEC_PLAIN and GSIM_EXEC_GRAPH, the kept segment also under
+ * GSIM_EXEC_PERSIST, both for models without lift/drag; otherwise, and with
+ * d_segment2 = NULL (the default), the passes run one after another.  Results are
+ * bitwise the same either way.  GSIM_E_WORKSPACE when `bytes` is too small. */
 int gsim_model_set_overlap(gsim_model* model, void* d_segment2, size_t bytes);
 
 /* Kernel timing for measurement: with bit k of `mask` set, every launch of

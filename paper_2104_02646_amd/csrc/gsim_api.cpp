@@ -1023,10 +1023,11 @@ int check_params(const gsim_model* m, const gsim_params* p, const gsim_grads* g 
     return GSIM_OK;
 }
 
-// The second segment buffer is in use (overlapped recompute, kept last segment): plain
-// and graph execution of models without lift/drag.
+// The second segment buffer is in use (kept last segment; overlapped recompute under
+// plain and graph execution): models without lift/drag, two-pass or persistent execution.
 bool uses_seg2(const gsim_model* m) {
-    return m->seg2 && !m->any_air && (m->exec == GSIM_EXEC_PLAIN || m->exec == GSIM_EXEC_GRAPH);
+    return m->seg2 && !m->any_air &&
+           (m->exec == GSIM_EXEC_PLAIN || m->exec == GSIM_EXEC_GRAPH || m->exec == GSIM_EXEC_PERSIST);
 }
 
 // table regions
@@ -1286,7 +1287,7 @@ int do_rollout_backward(gsim_model* m, const gsim_params* p, const void* ckpt, i
     // buffer and it, and the recompute of segment s - 1 runs in the same launches as
     // segment s's adjoint steps.  When the rollout of these checkpoints left the last
     // segment's states in that buffer, that segment is not recomputed.
-    const bool two = uses_seg2(m), overlap = two && nseg > 1;
+    const bool two = uses_seg2(m), overlap = two && nseg > 1 && m->exec != GSIM_EXEC_PERSIST;
     const bool kept = two && m->tail_ckpt == ckpt && m->tail_seg2 == m->seg2 && m->tail_n == n;
     m->tail_ckpt = nullptr;  // this call overwrites the second buffer
     auto segbuf = [&](int s) -> T* { return two && ((nseg - 1 - s) & 1) == 0 ? (T*)m->seg2 : (T*)seg; };

@@ -447,9 +447,11 @@ class Model:
 
     def keeps_last_segment(self):
         """Whether the second segment buffer is in use (the library's rule: overlap on,
-        plain or graph execution, no body with lift/drag), so that a checkpointed rollout
-        leaves its last segment for the backward and that segment is not recomputed."""
-        return self._overlap and not self.plan.any_air and self.get_exec()[0] in (EXEC_PLAIN, EXEC_GRAPH)
+        plain, graph or persistent execution, no body with lift/drag), so that a
+        checkpointed rollout leaves its last segment for the backward and that segment is
+        not recomputed."""
+        return self._overlap and not self.plan.any_air and self.get_exec()[0] in (EXEC_PLAIN, EXEC_GRAPH,
+                                                                                   EXEC_PERSIST)
 
     def set_overlap(self, on=True):
         """Overlapped recompute in rollout_backward: a second segment buffer of

@@ -84,10 +84,11 @@ def test_overlap_with_lift_drag_keeps_the_sequential_backward(gs):
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("exec_name", ["graph", "persist"])
 @pytest.mark.parametrize("T,K", [(40, 7), (9, 10)])
-def test_kept_last_segment_follows_its_checkpoints(gs, T, K):
-    """A checkpointed rollout leaves its last segment's states for the next backward with
-    the same checkpoints: that backward equals, bitwise, one without the second buffer, also
+def test_kept_last_segment_follows_its_checkpoints(gs, T, K, exec_name):
+    """A checkpointed rollout (graph or persistent execution) leaves its last segment's
+    states for the next backward with the same checkpoints: that backward equals, bitwise, one without the second buffer, also
     when a forward-only rollout from another state ran in between; a checkpointed rollout
     into other checkpoints in between, or a toggle of the buffer, makes the backward
     recompute the segment and it still equals the reference."""
@@ -95,7 +96,7 @@ def test_kept_last_segment_follows_its_checkpoints(gs, T, K):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         m = gs.Model(bodies, torch.float32, max_steps=T, ckpt_every=K)
-        m.set_exec(gs.EXEC_GRAPH)
+        m.set_exec({"graph": gs.EXEC_GRAPH, "persist": gs.EXEC_PERSIST}[exec_name])
         p = m.params_from_bodies()
         x0 = gs.soa(np.concatenate([b.x0 for b in bodies]))
         v0 = gs.soa(np.concatenate([b.v0 for b in bodies]))
