@@ -65,14 +65,16 @@ def algorithmic_bytes(kernel, ne, np_, K):
 def compulsory_per_launch(kernel, ne, np_, ntp, T, K, launches):
     """Compulsory bytes of one launch: a two-pass kernel's bytes per pass (its
     kernel_bytes over the passes of that kind in one gradient, whether they run on their
-    own or in shared launches), a shared launch the sum of its two passes', a fused
-    kernel's total over its launches."""
+    own or in shared launches), a shared launch the sum of its two passes' (the shared
+    element launch less one read of the element records, 64 B per tet: its workgroups
+    run both passes of a tile), a fused kernel's total over its launches."""
     nseg = -(-T // K)
     passes = {"element_fwd": T + (T - nseg), "particle_fwd": T + (T - nseg), "element_adj": T, "particle_adj": T}
     if kernel in passes:
         return kernel_bytes(kernel, ne, np_, ntp, T, K) / passes[kernel]
     if kernel in ("element_dual", "particle_dual"):
-        return sum(compulsory_per_launch(kernel.replace("dual", x), ne, np_, ntp, T, K, None) for x in ("fwd", "adj"))
+        both = sum(compulsory_per_launch(kernel.replace("dual", x), ne, np_, ntp, T, K, None) for x in ("fwd", "adj"))
+        return both - (64 * ne if kernel == "element_dual" else 0)
     return kernel_bytes(kernel, ne, np_, ntp, T, K) / launches
 
 
@@ -121,10 +123,10 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
 # (of gsim_kernels.hip followed by gsim_device.h) and 512-element tiles only; for any other
 # source or tile size the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "source_sha1": "e440ec09770c43d476002f1664d11c5fd6fafb17",
+    "source_sha1": "8b516e51cbf8221927829476c8c45aaf160b11a8",
     "workload": (256, 100, 10, 512),  # bodies, steps, checkpoint interval, elements per tile
-    "per_launch": {"element_fwd": 106.20e6, "particle_fwd": 27.63e6, "element_adj": 134.20e6,
-                   "particle_adj": 42.66e6, "element_dual": 240.41e6, "particle_dual": 68.66e6},
+    "per_launch": {"element_fwd": 106.20e6, "particle_fwd": 27.68e6, "element_adj": 134.20e6,
+                   "particle_adj": 42.67e6, "element_dual": 206.25e6, "particle_dual": 68.50e6},
 }
 
 

@@ -993,22 +993,26 @@ __global__ void __launch_bounds__(512) k_persist(const ModelDev<T>* __restrict__
     }
 }
 
-// Overlapped recompute: one launch runs an adjoint pass (row sd_adj) over the tiles
-// adj[0, n_adj) and a forward pass (row sd_fwd) over fwd[0, n_fwd), the forward
-// tiles starting at workgroup adj_span (n_adj rounded up to a multiple of the 8 XCDs, so
-// each list keeps its XCD placement; the workgroups in between return at once).
-// The two passes belong to independent chains of the checkpointed backward (the
-// adjoint steps of one segment, the recompute of the previous segment's states) and
-// touch disjoint buffers, so each tile's result is the one its own launch would give.
+// Overlapped recompute: one launch runs an adjoint pass (row sd_adj) and a forward pass
+// (row sd_fwd).  The two passes belong to independent chains of the checkpointed
+// backward (the adjoint steps of one segment, the recompute of the previous segment's
+// states) and touch disjoint buffers, so each tile's result is the one its own launch
+// would give.  Element launch: workgroup b runs tile b's adjoint pass and then its
+// forward pass, so the second pass finds the tile's element records (corner codes,
+// Dm^-1, volume, mu, lambda) in cache.  Particle launch: the adjoint tiles in the first
+// workgroups, the forward tiles from workgroup adj_span on (n_adj rounded up to a
+// multiple of the 8 XCDs, so each list keeps its XCD placement; the workgroups in
+// between return at once).
 template <typename T>
 __global__ void __launch_bounds__(512) k_elem_dual(const ModelDev<T>* __restrict__ md,
-                                                    const StepDev<T>* __restrict__ sd_adj, const Tile* __restrict__ adj,
-                                                    int n_adj, int adj_span, const StepDev<T>* __restrict__ sd_fwd,
-                                                    const Tile* __restrict__ fwd) {
+                                                    const StepDev<T>* __restrict__ sd_adj,
+                                                    const StepDev<T>* __restrict__ sd_fwd,
+                                                    const Tile* __restrict__ tiles) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int b = blockIdx.x;
-    if (b >= adj_span) elem_fwd_tile<T, false>(md, sd_fwd, fwd[b - adj_span], smem);
-    else if (b < n_adj) elem_adj_tile<T, false>(md, sd_adj, adj[b], smem);
+    const Tile tl = tiles[blockIdx.x];
+    elem_adj_tile<T, false>(md, sd_adj, tl, smem);
+    __syncthreads();  // the forward pass reuses the LDS
+    elem_fwd_tile<T, false>(md, sd_fwd, tl, smem);
 }
 template <typename T>
 __global__ void __launch_bounds__(512) k_part_dual(const ModelDev<T>* __restrict__ md,
@@ -1792,12 +1796,11 @@ int launch_dual(const ModelDev<T>* md, const StepDev<T>* sd_adj, const StepDev<T
                 void* stream) {
     static size_t allowed = 48 * 1024;
     const int nx = 8;  // XCDs: workgroup b runs on XCD b % 8
-    const int espan = (n_etiles + nx - 1) / nx * nx, pspan = (n_ptiles + nx - 1) / nx * nx;
+    const int pspan = (n_ptiles + nx - 1) / nx * nx;
     if (!particles) {
         if (n_etiles <= 0) return 0;
         allow_lds(reinterpret_cast<const void*>(&k_elem_dual<T>), lds, allowed);
-        launch_timed(k_elem_dual<T>, dim3(espan + n_etiles), dim3(block), lds, (hipStream_t)stream, md, sd_adj, etiles,
-                     n_etiles, espan, sd_fwd, etiles);
+        launch_timed(k_elem_dual<T>, dim3(n_etiles), dim3(block), lds, (hipStream_t)stream, md, sd_adj, sd_fwd, etiles);
         return check_launch();
     }
     if (n_ptiles <= 0) return 0;

@@ -43,8 +43,9 @@ def test_batch_bytes_per_launch():
 
 def test_shared_launch_bytes():
     """A shared launch (one adjoint and one recompute pass of the overlapped backward)
-    counts both passes' bytes; a pass's compulsory bytes do not depend on how many of
-    its passes run on their own."""
+    counts both passes' algorithmic bytes; its compulsory bytes are both passes' less, for
+    the element launch, the second read of the element records; a pass's compulsory bytes
+    do not depend on how many of its passes run on their own."""
     T, K = 100, 10
     for kind in ("element", "particle"):
         assert bench.algorithmic_bytes(kind + "_dual", NE, NP, K) == (bench.algorithmic_bytes(kind + "_fwd", NE, NP, K)
@@ -53,7 +54,11 @@ def test_shared_launch_bytes():
     assert fwd == 64 * NE + 36 * NTP
     adj = bench.compulsory_per_launch("element_adj", NE, NP, NTP, T, K, 10)
     assert adj == (T * (80 * NE + 52 * NTP) + 17 * NTP) / T
-    assert bench.compulsory_per_launch("element_dual", NE, NP, NTP, T, K, 90) == fwd + adj
+    # one workgroup runs both passes of a tile: the element records are read once
+    assert bench.compulsory_per_launch("element_dual", NE, NP, NTP, T, K, 90) == fwd + adj - 64 * NE
+    pf = bench.compulsory_per_launch("particle_fwd", NE, NP, NTP, T, K, 100)
+    pa = bench.compulsory_per_launch("particle_adj", NE, NP, NTP, T, K, 19)
+    assert bench.compulsory_per_launch("particle_dual", NE, NP, NTP, T, K, 81) == pf + pa
 
 
 def test_algorithmic_bytes():
