@@ -123,10 +123,10 @@ def kernel_bytes(kernel, ne, np_, ntp, T, K):
 # (of gsim_kernels.hip followed by gsim_device.h) and 512-element tiles only; for any other
 # source or tile size the traffic is reported as null.
 MEASURED_TRAFFIC = {
-    "source_sha1": "8b516e51cbf8221927829476c8c45aaf160b11a8",
+    "source_sha1": "3d05ef10ad73b646266638641f7adf5421e2a62a",
     "workload": (256, 100, 10, 512),  # bodies, steps, checkpoint interval, elements per tile
-    "per_launch": {"element_fwd": 106.20e6, "particle_fwd": 27.68e6, "element_adj": 134.20e6,
-                   "particle_adj": 42.67e6, "element_dual": 206.25e6, "particle_dual": 68.50e6},
+    "per_launch": {"element_fwd": 106.21e6, "particle_fwd": 27.68e6, "element_adj": 134.20e6,
+                   "particle_adj": 42.67e6, "element_dual": 206.37e6, "particle_dual": 68.50e6},
 }
 
 

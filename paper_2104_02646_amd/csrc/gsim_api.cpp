@@ -711,6 +711,12 @@ Ctx<T> ctx(gsim_model* m) {
     return c;
 }
 
+// Shared adjoint + recompute element launches pair each tile's two passes in one
+// workgroup when the model has at least this many element tiles (8 per CU): measured,
+// the paired layout is faster for the 256- and 2048-body batches (2,794 and ~21,000
+// tiles) and slower for the 200k-tet blob (800 tiles), the tiny cube and the cloth.
+const int DUAL_PAIR_MIN_TILES = 2048;
+
 // One launch of the sequence a call replays: pass kind and its table row.
 enum Op : int {
     OP_FWD = 0,
@@ -827,13 +833,16 @@ int run_sequence(gsim_model* m, const std::vector<Launch>& seq, void* stream) {
         const int p0 = l < 0 ? 0 : m->lane_p[l], p1 = l < 0 ? m->n_ptiles : m->lane_p[l + 1];
         void* st = l > 0 ? (void*)m->lane_stream[l] : stream;
         const size_t lds = std::max(m->etile_words[0], m->etile_words[1]) * sizeof(T);
+        // a model with many element tiles pairs each tile's two passes in one workgroup
+        // (its records read once); with few, both passes of a tile run side by side
+        const bool paired = m->n_etiles >= DUAL_PAIR_MIN_TILES;
         LAUNCH_TRY(timed(m, 6, st, [&] {
             return launch_dual<T>(md, sd_a, sd_f, c.et + e0, e1 - e0, c.pt + p0, p1 - p0, m->block, m->pblock, lds,
-                                  false, st);
+                                  false, paired, st);
         }), "overlapped element passes");
         LAUNCH_TRY(timed(m, 7, st, [&] {
             return launch_dual<T>(md, sd_a, sd_f, c.et + e0, e1 - e0, c.pt + p0, p1 - p0, m->block, m->pblock, lds,
-                                  true, st);
+                                  true, false, st);
         }), "overlapped particle passes");
         return GSIM_OK;
     };

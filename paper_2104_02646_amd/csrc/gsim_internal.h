@@ -206,14 +206,14 @@ int launch_persist(const ModelDev<T>* md, const StepDev<T>* rows, int n_rows, co
                    const int32_t* toff, int n_bodies, int block, size_t lds, void* stream);
 // Overlapped recompute: one element launch (particles = false) or one particle launch
 // (true) running the adjoint pass of row sd_adj and the forward pass of row sd_fwd
-// over the same tile list (models without lift/drag).  Element launch: one workgroup
-// per tile runs both passes of its tile, adjoint first; particle launch: the forward
-// tiles start at the adjoint count rounded up to a multiple of 8, so both keep their
-// XCD placement.  `lds` covers both element passes.
+// over the same tile list (models without lift/drag).  Split layout: the forward tiles
+// start at the adjoint count rounded up to a multiple of 8, so both keep their XCD
+// placement; paired layout (element launch with `paired`): one workgroup per tile runs
+// both passes of its tile, adjoint first.  `lds` covers both element passes.
 template <typename T>
 int launch_dual(const ModelDev<T>* md, const StepDev<T>* sd_adj, const StepDev<T>* sd_fwd, const Tile* etiles,
                 int n_etiles, const Tile* ptiles, int n_ptiles, int block, int pblock, size_t lds, bool particles,
-                void* stream);
+                bool paired, void* stream);
 // One workgroup per piece: the pieces' copies and zero fills in one launch (the serving
 // engine's query set-up, staged through one host-to-device copy).
 int launch_stage_copy(const StageSeg* segs, int n_segs, void* stream);

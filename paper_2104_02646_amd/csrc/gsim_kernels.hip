@@ -997,22 +997,30 @@ __global__ void __launch_bounds__(512) k_persist(const ModelDev<T>* __restrict__
 // (row sd_fwd).  The two passes belong to independent chains of the checkpointed
 // backward (the adjoint steps of one segment, the recompute of the previous segment's
 // states) and touch disjoint buffers, so each tile's result is the one its own launch
-// would give.  Element launch: workgroup b runs tile b's adjoint pass and then its
-// forward pass, so the second pass finds the tile's element records (corner codes,
-// Dm^-1, volume, mu, lambda) in cache.  Particle launch: the adjoint tiles in the first
-// workgroups, the forward tiles from workgroup adj_span on (n_adj rounded up to a
-// multiple of the 8 XCDs, so each list keeps its XCD placement; the workgroups in
-// between return at once).
+// would give.  Split layout (particle launches, and element launches of models with few
+// tiles): the adjoint tiles in the first workgroups, the forward tiles from workgroup
+// span on (the tile count rounded up to a multiple of the 8 XCDs, so each list keeps
+// its XCD placement; the workgroups in between return at once).  Paired layout
+// (element launches of models with many tiles): workgroup b runs tile b's adjoint pass
+// and then its forward pass, so the second pass finds the tile's element records
+// (corner codes, Dm^-1, volume, mu, lambda) in cache.
 template <typename T>
 __global__ void __launch_bounds__(512) k_elem_dual(const ModelDev<T>* __restrict__ md,
                                                     const StepDev<T>* __restrict__ sd_adj,
                                                     const StepDev<T>* __restrict__ sd_fwd,
-                                                    const Tile* __restrict__ tiles) {
+                                                    const Tile* __restrict__ tiles, int n, int span, int paired) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const Tile tl = tiles[blockIdx.x];
-    elem_adj_tile<T, false>(md, sd_adj, tl, smem);
-    __syncthreads();  // the forward pass reuses the LDS
-    elem_fwd_tile<T, false>(md, sd_fwd, tl, smem);
+    const int b = blockIdx.x;
+    if (paired) {
+        const Tile tl = tiles[b];
+        elem_adj_tile<T, false>(md, sd_adj, tl, smem);
+        __syncthreads();  // the forward pass reuses the LDS
+        elem_fwd_tile<T, false>(md, sd_fwd, tl, smem);
+    } else if (b >= span) {
+        elem_fwd_tile<T, false>(md, sd_fwd, tiles[b - span], smem);
+    } else if (b < n) {
+        elem_adj_tile<T, false>(md, sd_adj, tiles[b], smem);
+    }
 }
 template <typename T>
 __global__ void __launch_bounds__(512) k_part_dual(const ModelDev<T>* __restrict__ md,
@@ -1793,14 +1801,15 @@ int launch_persist(const ModelDev<T>* md, const StepDev<T>* rows, int n_rows, co
 template <typename T>
 int launch_dual(const ModelDev<T>* md, const StepDev<T>* sd_adj, const StepDev<T>* sd_fwd, const Tile* etiles,
                 int n_etiles, const Tile* ptiles, int n_ptiles, int block, int pblock, size_t lds, bool particles,
-                void* stream) {
+                bool paired, void* stream) {
     static size_t allowed = 48 * 1024;
     const int nx = 8;  // XCDs: workgroup b runs on XCD b % 8
-    const int pspan = (n_ptiles + nx - 1) / nx * nx;
+    const int espan = (n_etiles + nx - 1) / nx * nx, pspan = (n_ptiles + nx - 1) / nx * nx;
     if (!particles) {
         if (n_etiles <= 0) return 0;
         allow_lds(reinterpret_cast<const void*>(&k_elem_dual<T>), lds, allowed);
-        launch_timed(k_elem_dual<T>, dim3(n_etiles), dim3(block), lds, (hipStream_t)stream, md, sd_adj, sd_fwd, etiles);
+        launch_timed(k_elem_dual<T>, dim3(paired ? n_etiles : espan + n_etiles), dim3(block), lds, (hipStream_t)stream,
+                     md, sd_adj, sd_fwd, etiles, n_etiles, espan, paired ? 1 : 0);
         return check_launch();
     }
     if (n_ptiles <= 0) return 0;
@@ -1916,7 +1925,7 @@ int launch_fused_grads(const ModelDev<T>* md, const StepDev<T>* sd, void* stream
     template int launch_persist<T>(const ModelDev<T>*, const StepDev<T>*, int, const Tile*, const Tile*, const int32_t*, \
                                    int, int, size_t, void*);                                                        \
     template int launch_dual<T>(const ModelDev<T>*, const StepDev<T>*, const StepDev<T>*, const Tile*, int, const Tile*, \
-                                int, int, int, size_t, bool, void*);                                              \
+                                int, int, int, size_t, bool, bool, void*);                                        \
     template int launch_mixed<T>(const ModelDev<T>*, const StepDev<T>*, const TileSeg*, int, int, int, const TileSeg*, \
                                  int, int, int, int, int, size_t, void*);                                           \
     template int launch_contact_reduce<T>(const ModelDev<T>*, const StepDev<T>*, int, void*);                       \

@@ -76,6 +76,39 @@ def test_overlap_bitwise_equals_sequential(gs, case, dtype):
                 assert np.array_equal(a[k], b[k]), (k, exec_mode, lanes)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_paired_layout_bitwise_equals_sequential(gs, dtype):
+    """A model with at least 2048 element tiles (here 32-element tiles over ~70k tets)
+    runs each shared element launch in the paired layout (one workgroup per tile, adjoint
+    pass then forward pass): bitwise the sequential backward, on 1 and 4 lanes."""
+    dt = torch.float32 if dtype == "f32" else torch.float64
+    bodies = [W.batch_body(62000 + i, lo=2000, hi=5000) for i in range(20)]
+    if dt == torch.float32:
+        bodies = [b.round_to(np.float32) for b in bodies]
+    from paper_2104_02646_amd import gsim
+    assert len(gsim.Plan(bodies, tile_elems=32).tiles()[0]) >= 2048
+    for lanes in (1, 4):
+        outs = []
+        for overlap in (False, True):
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                m = gs.Model(bodies, dt, max_steps=12, ckpt_every=4, overlap=overlap, tile_elems=32)
+                m.set_exec(gs.EXEC_GRAPH)
+                m.set_lanes(lanes)
+                p = m.params_from_bodies()
+                x0 = gs.soa(np.concatenate([b.x0 for b in bodies]), dtype=dt)
+                v0 = gs.soa(np.concatenate([b.v0 for b in bodies]), dtype=dt)
+                tg = gs.soa(np.concatenate([W.synthetic_target(b, 80 + i) for i, b in enumerate(bodies)]), dtype=dt)
+                xT, _ = m.rollout(p, x0, v0, 12, stream=stream)
+                loss, xb, vb = m.loss_mse(xT, tg, stream=stream)
+                g = m.zero_grads(("mu", "lam", "mass", "contact"))
+                xb0, vb0 = m.rollout_backward(p, 12, xb, vb, g, stream=stream)
+                stream.synchronize()
+                outs.append([t.cpu().numpy().copy() for t in list(g.values()) + [xb0, vb0]])
+        for a, b in zip(*outs):
+            assert np.array_equal(a, b), lanes
+
+
 def test_overlap_with_lift_drag_keeps_the_sequential_backward(gs):
     bodies = [W.control_cloth(5, n=12), W.tiny_cube(2)]
     a = gradient(gs, bodies, torch.float64, 30, 7, False, gs.EXEC_GRAPH, 2)
