@@ -62,19 +62,23 @@ def algorithmic_bytes(kernel, ne, np_, K):
     return None
 
 
-def compulsory_per_launch(kernel, ne, np_, ntp, T, K, launches):
+DUAL_PAIR_MIN_TILES = 2048  # the library pairs a tile's two passes from this many element tiles on
+
+
+def compulsory_per_launch(kernel, ne, np_, ntp, T, K, launches, paired=True):
     """Compulsory bytes of one launch: a two-pass kernel's bytes per pass (its
     kernel_bytes over the passes of that kind in one gradient, whether they run on their
     own or in shared launches), a shared launch the sum of its two passes' (the shared
-    element launch less one read of the element records, 64 B per tet: its workgroups
-    run both passes of a tile), a fused kernel's total over its launches."""
+    element launch in the paired layout less one read of the element records, 64 B per
+    tet: its workgroups run both passes of a tile), a fused kernel's total over its
+    launches."""
     nseg = -(-T // K)
     passes = {"element_fwd": T + (T - nseg), "particle_fwd": T + (T - nseg), "element_adj": T, "particle_adj": T}
     if kernel in passes:
         return kernel_bytes(kernel, ne, np_, ntp, T, K) / passes[kernel]
     if kernel in ("element_dual", "particle_dual"):
         both = sum(compulsory_per_launch(kernel.replace("dual", x), ne, np_, ntp, T, K, None) for x in ("fwd", "adj"))
-        return both - (64 * ne if kernel == "element_dual" else 0)
+        return both - (64 * ne if kernel == "element_dual" and paired else 0)
     return kernel_bytes(kernel, ne, np_, ntp, T, K) / launches
 
 
@@ -163,7 +167,7 @@ def gradient_bytes(ne, np_, T, K, nt=0, nh=0, kept=False):
     return fwd_passes * bf + T * ba, fwd_passes
 
 
-def kernel_table(timing, ne, np_, ntp, T, K):
+def kernel_table(timing, ne, np_, ntp, T, K, paired=True):
     """Per-kernel averages from the HIP-event timing of one gradient, with the
     algorithmic and the design's compulsory bytes per launch."""
     kern = {}
@@ -171,7 +175,7 @@ def kernel_table(timing, ne, np_, ntp, T, K):
         if n:
             avg = ms / n
             alg = algorithmic_bytes(k, ne, np_, K)
-            comp = compulsory_per_launch(k, ne, np_, ntp, T, K, n)
+            comp = compulsory_per_launch(k, ne, np_, ntp, T, K, n, paired)
             kern[k] = {"launches": n, "avg_us": avg * 1e3, "total_ms": ms, "compulsory_bytes_per_launch": comp,
                        "compulsory_GBps": comp / (avg * 1e-3) / 1e9}
             if alg is not None:
@@ -297,8 +301,8 @@ def gradient_line(bodies, dtype, T, K, exec_mode, lanes=1, reps=3, timing=False,
             torch.cuda.synchronize()
             t = m.read_timing()
             m.set_timing(())
-            ntp = len(m.plan.tiles()[1])
-            kern = kernel_table(t, ne, np_, ntp, T, K)
+            etiles, tps = m.plan.tiles()[:2]
+            kern = kernel_table(t, ne, np_, len(tps), T, K, len(etiles) >= DUAL_PAIR_MIN_TILES)
             dom = max((k for k in kern if "algorithmic_bytes_per_launch" in kern[k]), key=lambda k: kern[k]["total_ms"])
             out["kernels"] = kern
             out["roofline"] = roofline(kern[dom], dom, None)
@@ -716,7 +720,9 @@ def main():
     args.block, args.items, args.lanes = block, items, model.get_lanes()
     kept = model.keeps_last_segment()  # the timed steps' backward takes the rollout's last segment
     tile_elems = model.plan.tile_elems or gsim.TILE_DEFAULT
-    ntp = len(gsim.Plan(bodies, tile_elems=tile_elems).tiles()[1])  # tile particles of the element tiles
+    etiles_, tps_ = gsim.Plan(bodies, tile_elems=tile_elems).tiles()[:2]
+    ntp = len(tps_)  # tile particles of the element tiles
+    paired = len(etiles_) >= DUAL_PAIR_MIN_TILES
 
     def bench_step():
         model.rollout(p, x0, v0, T, out=(xT, vT), stream=stream)
@@ -777,7 +783,7 @@ def main():
             alt = str(e)
 
     value = ne * T / sec
-    kern = kernel_table(timing, ne, np_, ntp, T, K)
+    kern = kernel_table(timing, ne, np_, ntp, T, K, paired)
     dom = max(kern, key=lambda k: kern[k]["total_ms"])
     d = kern[dom]
     gbytes, fwd_passes = gradient_bytes(ne, np_, T, K, kept=kept)

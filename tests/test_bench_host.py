@@ -56,6 +56,8 @@ def test_shared_launch_bytes():
     assert adj == (T * (80 * NE + 52 * NTP) + 17 * NTP) / T
     # one workgroup runs both passes of a tile: the element records are read once
     assert bench.compulsory_per_launch("element_dual", NE, NP, NTP, T, K, 90) == fwd + adj - 64 * NE
+    # side by side (models with fewer tiles): each pass reads the records
+    assert bench.compulsory_per_launch("element_dual", NE, NP, NTP, T, K, 90, paired=False) == fwd + adj
     pf = bench.compulsory_per_launch("particle_fwd", NE, NP, NTP, T, K, 100)
     pa = bench.compulsory_per_launch("particle_adj", NE, NP, NTP, T, K, 19)
     assert bench.compulsory_per_launch("particle_dual", NE, NP, NTP, T, K, 81) == pf + pa
