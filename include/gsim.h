@@ -229,7 +229,8 @@ int gsim_model_set_overlap(gsim_model* model, void* d_segment2, size_t bytes);
  * 1 particle pass, 2 element adjoint pass, 3 particle adjoint pass, 4 fused
  * forward segment, 5 fused adjoint segment, 6 shared adjoint + recompute element
  * launch, 7 shared adjoint + recompute particle launch of gsim_model_set_overlap).
- * With timing on, each pass is one launch over every lane's tiles.  Plain
+ * With timing on, each pass (or shared pair of passes) is one launch over every
+ * lane's tiles.  Plain
  * execution only (GSIM_E_UNSUPPORTED under GSIM_EXEC_GRAPH).
  * gsim_model_read_timing waits for the recorded events and returns (then
  * clears) kernel k's launch count and summed duration in milliseconds. */
